@@ -1,0 +1,1447 @@
+/*
+ * ctu_oracle.c -- plain FP64 CPU oracle for the single-patch CTU-GLM step.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only tests/, __graft_entry__.smoke() and the
+ * cpu_baseline leg of bench.py may load this library.  It shares no code,
+ * header, table or helper with the HIP library under paper_1110_0740_amd/.
+ *
+ * It follows Mignone et al., "The PLUTO code for adaptive mesh computations
+ * in astrophysical fluid dynamics" (ApJS 2012):
+ *   Sec. 2.1  ideal / non-ideal MHD equations (Eq. mhd, visc_tens, tc_flux)
+ *   Sec. 2.2  relativistic MHD (Eq. rmhd, gammaEos)
+ *   Sec. 3    GLM cleaning (Eq. glm2x2)
+ *   Sec. 3.1  unsplit CTU update (Eq. update, incrementop_hyp/par, ctu_flux,
+ *             transv, Ca, dt_cool)
+ *   Sec. 3.2  characteristic normal predictors (Eq. char_var, wnorm_predp/m,
+ *             ppm1, MClim, minmod, ppm_parabolic_lim, WENO3, WENO3a, Linear,
+ *             harmonic_lim, vanalbada_lim)
+ *   Sec. 3.3  MUSCL-Hancock primitive predictor (Eq. MUSCL-Hancock)
+ *   App. A    saturated conduction flux (Eq. sat_eq, sat_flux)
+ * and, where the paper defers to published methods, their textbook form:
+ *   HLLD (Miyoshi & Kusano 2005), HLL (Harten, Lax & van Leer 1983),
+ *   normalized MHD eigenvectors (Roe & Balsara 1996), GLM Riemann subsystem
+ *   (Dedner et al. 2002).
+ *
+ * Plain scalar loops, one box at a time, full-size temporaries, no tiling and
+ * no fusion.  Left eigenvectors are obtained by numerically inverting the
+ * right-eigenvector matrix; the relativistic conserved-to-primitive map is
+ * solved by bracketing bisection.  Both are slow and obviously correct.
+ *
+ * Array layout: every cell field is SoA  q[v][k][j][i]  over the ghosted box
+ * (i fastest), extents NX=nx+2g, NY=ny+2g, NZ=nz+2g (NZ=1 when dim==2).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define NVAR 9
+enum { RHO = 0, MX1 = 1, MX2 = 2, MX3 = 3, ENG = 4, BX1 = 5, BX2 = 6, BX3 = 7, PSI = 8 };
+#define PRS ENG /* primitive pressure sits where the conserved energy sits */
+
+enum { PHYS_MHD = 0, PHYS_RMHD = 1 };
+enum { REC_LIN_MC = 0, REC_LIN_MINMOD = 1, REC_LIN_VANLEER = 2, REC_LIN_VANALBADA = 3,
+       REC_PPM = 4, REC_WENO3 = 5 };
+enum { PRED_CHAR = 0, PRED_MH = 1 };
+enum { WREF_FACE = 0, WREF_CELL = 1, WREF_CW84 = 2 };
+enum { RS_HLLD = 0, RS_HLL = 1 };
+enum { FAIL_RHO = 0, FAIL_PRS = 1, FAIL_NEWTON = 2, FAIL_VEL = 3, FAIL_NAN = 4, NFAIL = 5 };
+
+#define PARAB_VISC 1u
+#define PARAB_RES 2u
+#define PARAB_TC 4u
+
+typedef struct {
+    int dim, physics, recon, predictor, wref, riemann;
+    double gamma;
+    double dx[3];
+    int glm;
+    double glm_alpha;
+    unsigned parabolic_mask;
+    double nu, eta, kappa_par, kappa_perp, tc_phi;
+    int cooling;
+    double cool_beta, T_floor;
+    int hyperbolic_off;
+} orc_opts;
+
+/* ------------------------------------------------------------------------ */
+/* small helpers                                                             */
+/* ------------------------------------------------------------------------ */
+
+static double sgn0(double a) { return (a > 0.0) - (a < 0.0); } /* sign(0) = 0 */
+static double sgn1(double a) { return a < 0.0 ? -1.0 : 1.0; }  /* sign(0) = +1 */
+
+/* Component indices of (normal, transverse, binormal) for direction d; the
+ * cyclic order keeps the triad right-handed. */
+static void dir_axes(int d, int *n, int *t, int *b)
+{
+    *n = d;
+    *t = (d + 1) % 3;
+    *b = (d + 2) % 3;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Ideal MHD: Eq. mhd with the ideal-gas closure (Sec. 2.1)                  */
+/* ------------------------------------------------------------------------ */
+
+static void mhd_prim2cons(const orc_opts *o, const double *V, double *U)
+{
+    double v2 = V[MX1] * V[MX1] + V[MX2] * V[MX2] + V[MX3] * V[MX3];
+    double b2 = V[BX1] * V[BX1] + V[BX2] * V[BX2] + V[BX3] * V[BX3];
+    U[RHO] = V[RHO];
+    U[MX1] = V[RHO] * V[MX1];
+    U[MX2] = V[RHO] * V[MX2];
+    U[MX3] = V[RHO] * V[MX3];
+    U[ENG] = V[PRS] / (o->gamma - 1.0) + 0.5 * V[RHO] * v2 + 0.5 * b2;
+    U[BX1] = V[BX1];
+    U[BX2] = V[BX2];
+    U[BX3] = V[BX3];
+    U[PSI] = V[PSI];
+}
+
+static void mhd_cons2prim(const orc_opts *o, const double *U, double *V, int *fails)
+{
+    double rho = U[RHO];
+    V[RHO] = rho;
+    V[MX1] = U[MX1] / rho;
+    V[MX2] = U[MX2] / rho;
+    V[MX3] = U[MX3] / rho;
+    V[BX1] = U[BX1];
+    V[BX2] = U[BX2];
+    V[BX3] = U[BX3];
+    V[PSI] = U[PSI];
+    double v2 = V[MX1] * V[MX1] + V[MX2] * V[MX2] + V[MX3] * V[MX3];
+    double b2 = V[BX1] * V[BX1] + V[BX2] * V[BX2] + V[BX3] * V[BX3];
+    V[PRS] = (o->gamma - 1.0) * (U[ENG] - 0.5 * rho * v2 - 0.5 * b2);
+    if (fails) {
+        if (!(rho > 0.0)) fails[FAIL_RHO]++;
+        if (!(V[PRS] > 0.0)) fails[FAIL_PRS]++;
+        for (int v = 0; v < NVAR; v++)
+            if (isnan(V[v])) { fails[FAIL_NAN]++; break; }
+    }
+}
+
+/* Fast magnetosonic speed along direction d. */
+static double mhd_fast_speed(const orc_opts *o, const double *V, int d)
+{
+    double a2 = o->gamma * V[PRS] / V[RHO];
+    double b2 = (V[BX1] * V[BX1] + V[BX2] * V[BX2] + V[BX3] * V[BX3]) / V[RHO];
+    double bn2 = V[BX1 + d] * V[BX1 + d] / V[RHO];
+    double s = a2 + b2;
+    double disc = s * s - 4.0 * a2 * bn2;
+    if (disc < 0.0) disc = 0.0;
+    return sqrt(0.5 * (s + sqrt(disc)));
+}
+
+/* Hyperbolic flux along d (rows of Eq. mhd) without the GLM rows; the GLM
+ * rows (B_n, psi) are filled by the caller. */
+static void mhd_flux(const orc_opts *o, const double *V, const double *U, int d, double *F)
+{
+    int n, t, b;
+    dir_axes(d, &n, &t, &b);
+    double vn = V[MX1 + n];
+    double Bn = V[BX1 + n];
+    double b2 = V[BX1] * V[BX1] + V[BX2] * V[BX2] + V[BX3] * V[BX3];
+    double vB = V[MX1] * V[BX1] + V[MX2] * V[BX2] + V[MX3] * V[BX3];
+    double pt = V[PRS] + 0.5 * b2;
+    F[RHO] = U[RHO] * vn;
+    F[MX1 + n] = U[MX1 + n] * vn - Bn * Bn + pt;
+    F[MX1 + t] = U[MX1 + t] * vn - Bn * V[BX1 + t];
+    F[MX1 + b] = U[MX1 + b] * vn - Bn * V[BX1 + b];
+    F[ENG] = (U[ENG] + pt) * vn - vB * Bn;
+    F[BX1 + n] = 0.0;
+    F[BX1 + t] = vn * V[BX1 + t] - Bn * V[MX1 + t];
+    F[BX1 + b] = vn * V[BX1 + b] - Bn * V[MX1 + b];
+    F[PSI] = 0.0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Relativistic MHD: Eq. rmhd with the ideal EOS Eq. gammaEos (Sec. 2.2)     */
+/* ------------------------------------------------------------------------ */
+
+static void rmhd_prim2cons(const orc_opts *o, const double *V, double *U)
+{
+    double G = o->gamma;
+    double v2 = V[MX1] * V[MX1] + V[MX2] * V[MX2] + V[MX3] * V[MX3];
+    double B2 = V[BX1] * V[BX1] + V[BX2] * V[BX2] + V[BX3] * V[BX3];
+    double vB = V[MX1] * V[BX1] + V[MX2] * V[BX2] + V[MX3] * V[BX3];
+    double lor2 = 1.0 / (1.0 - v2);
+    double lor = sqrt(lor2);
+    double w = V[RHO] + G * V[PRS] / (G - 1.0);
+    double E2 = B2 * v2 - vB * vB; /* |v x B|^2 */
+    U[RHO] = V[RHO] * lor;
+    /* m = w gamma^2 v + E x B, with E = -v x B  =>  E x B = B^2 v - (v.B) B */
+    for (int c = 0; c < 3; c++) U[MX1 + c] = (w * lor2 + B2) * V[MX1 + c] - vB * V[BX1 + c];
+    U[ENG] = w * lor2 - V[PRS] + 0.5 * (B2 + E2) - U[RHO];
+    U[BX1] = V[BX1];
+    U[BX2] = V[BX2];
+    U[BX3] = V[BX3];
+    U[PSI] = V[PSI];
+}
+
+/* Velocity squared and pressure as functions of W = w gamma^2 for fixed
+ * conserved variables (the map that the inversion must undo). */
+typedef struct {
+    double D, E, m2, S, B2, G;
+} rmhd_inv;
+
+static double rmhd_v2_of_W(const rmhd_inv *q, double W)
+{
+    double sw = q->S / W;
+    double num = q->m2 + sw * sw * (2.0 * W + q->B2);
+    double den = (W + q->B2) * (W + q->B2);
+    return num / den;
+}
+
+/* Residual of the energy definition: f(W) = W - p + B^2/2 + (v^2 B^2 - S^2/W^2)/2 - D - E. */
+static double rmhd_resid(const rmhd_inv *q, double W, double *p_out, double *v2_out)
+{
+    double v2 = rmhd_v2_of_W(q, W);
+    double sq = sqrt(1.0 - v2);
+    double p = (q->G - 1.0) / q->G * (W * (1.0 - v2) - q->D * sq);
+    if (p_out) *p_out = p;
+    if (v2_out) *v2_out = v2;
+    double sw = q->S / W;
+    return W - p + 0.5 * q->B2 + 0.5 * (v2 * q->B2 - sw * sw) - q->D - q->E;
+}
+
+/* Conserved -> primitive for RMHD by bisection on W.  v^2(W) decreases
+ * monotonically, so the physical branch is W > W*, with v^2(W*) = 1; the
+ * root of f is bracketed on (W*, W_hi] and bisected to machine precision. */
+static int rmhd_cons2prim(const orc_opts *o, const double *U, double *V, int *fails)
+{
+    rmhd_inv q;
+    q.G = o->gamma;
+    q.D = U[RHO];
+    q.E = U[ENG];
+    q.m2 = U[MX1] * U[MX1] + U[MX2] * U[MX2] + U[MX3] * U[MX3];
+    q.S = U[MX1] * U[BX1] + U[MX2] * U[BX2] + U[MX3] * U[BX3];
+    q.B2 = U[BX1] * U[BX1] + U[BX2] * U[BX2] + U[BX3] * U[BX3];
+    V[BX1] = U[BX1];
+    V[BX2] = U[BX2];
+    V[BX3] = U[BX3];
+    V[PSI] = U[PSI];
+    int ok = 1;
+    if (!(q.D > 0.0)) ok = 0;
+    /* lower end: largest W with v^2 >= 1 */
+    double lo = 0.0, hi = 1.0;
+    double scale = q.D + q.E + sqrt(q.m2) + q.B2 + 1e-300;
+    hi = scale;
+    while (rmhd_v2_of_W(&q, hi) >= 1.0 && hi < 1e300) hi *= 2.0;
+    if (rmhd_v2_of_W(&q, 1e-300) < 1.0) {
+        lo = 0.0; /* v^2 < 1 everywhere */
+    } else {
+        double a = 0.0, c = hi;
+        for (int it = 0; it < 2000 && c - a > 0.0; it++) {
+            double mid = 0.5 * (a + c);
+            if (mid <= a || mid >= c) break;
+            if (rmhd_v2_of_W(&q, mid) >= 1.0) a = mid; else c = mid;
+        }
+        lo = c; /* first W with v^2 < 1 */
+    }
+    /* upper end: grow until f > 0 */
+    double whi = (lo > 0.0 ? 2.0 * lo : scale);
+    if (whi < scale) whi = scale;
+    int grow = 0;
+    while (rmhd_resid(&q, whi, NULL, NULL) <= 0.0 && grow < 4000) { whi *= 2.0; grow++; }
+    double flo = rmhd_resid(&q, lo > 0.0 ? lo : 1e-300, NULL, NULL);
+    if (!(flo < 0.0)) ok = 0;
+    double a = (lo > 0.0 ? lo : 1e-300), c = whi;
+    for (int it = 0; it < 5000; it++) {
+        double mid = 0.5 * (a + c);
+        if (mid <= a || mid >= c) break;
+        if (rmhd_resid(&q, mid, NULL, NULL) > 0.0) c = mid; else a = mid;
+    }
+    double W = 0.5 * (a + c);
+    double p, v2;
+    rmhd_resid(&q, W, &p, &v2);
+    double lor = 1.0 / sqrt(1.0 - v2);
+    V[RHO] = q.D / lor;
+    V[PRS] = p;
+    for (int c3 = 0; c3 < 3; c3++)
+        V[MX1 + c3] = (U[MX1 + c3] + q.S / W * U[BX1 + c3]) / (W + q.B2);
+    if (fails) {
+        if (!ok) fails[FAIL_NEWTON]++;
+        if (!(V[RHO] > 0.0)) fails[FAIL_RHO]++;
+        if (!(p > 0.0)) fails[FAIL_PRS]++;
+        if (!(v2 < 1.0)) fails[FAIL_VEL]++;
+        for (int v = 0; v < NVAR; v++)
+            if (isnan(V[v])) { fails[FAIL_NAN]++; break; }
+    }
+    return ok;
+}
+
+static void rmhd_flux(const orc_opts *o, const double *V, const double *U, int d, double *F)
+{
+    int n, t, b;
+    dir_axes(d, &n, &t, &b);
+    double G = o->gamma;
+    double v2 = V[MX1] * V[MX1] + V[MX2] * V[MX2] + V[MX3] * V[MX3];
+    double B2 = V[BX1] * V[BX1] + V[BX2] * V[BX2] + V[BX3] * V[BX3];
+    double vB = V[MX1] * V[BX1] + V[MX2] * V[BX2] + V[MX3] * V[BX3];
+    double lor2 = 1.0 / (1.0 - v2);
+    double w = V[RHO] + G * V[PRS] / (G - 1.0);
+    double E[3];
+    /* E = -v x B */
+    E[0] = -(V[MX2] * V[BX3] - V[MX3] * V[BX2]);
+    E[1] = -(V[MX3] * V[BX1] - V[MX1] * V[BX3]);
+    E[2] = -(V[MX1] * V[BX2] - V[MX2] * V[BX1]);
+    double E2 = E[0] * E[0] + E[1] * E[1] + E[2] * E[2];
+    double pt = V[PRS] + 0.5 * (B2 + E2);
+    double vn = V[MX1 + n];
+    (void)vB;
+    F[RHO] = U[RHO] * vn;
+    for (int c = 0; c < 3; c++)
+        F[MX1 + c] = w * lor2 * vn * V[MX1 + c] - V[BX1 + n] * V[BX1 + c] - E[n] * E[c] + (c == n ? pt : 0.0);
+    F[ENG] = U[MX1 + n] - U[RHO] * vn;
+    F[BX1 + n] = 0.0;
+    F[BX1 + t] = vn * V[BX1 + t] - V[BX1 + n] * V[MX1 + t];
+    F[BX1 + b] = vn * V[BX1 + b] - V[BX1 + n] * V[MX1 + b];
+    F[PSI] = 0.0;
+}
+
+/* Outer signal speeds along d: the isotropic upper bound on the fast
+ * magnetosonic speeds built from a^2 = cs^2 + ca^2 - cs^2 ca^2 and the
+ * relativistic velocity addition along d. */
+static void rmhd_speeds(const orc_opts *o, const double *V, int d, double *lmin, double *lmax)
+{
+    double G = o->gamma;
+    double v2 = V[MX1] * V[MX1] + V[MX2] * V[MX2] + V[MX3] * V[MX3];
+    double B2 = V[BX1] * V[BX1] + V[BX2] * V[BX2] + V[BX3] * V[BX3];
+    double vB = V[MX1] * V[BX1] + V[MX2] * V[BX2] + V[MX3] * V[BX3];
+    double w = V[RHO] + G * V[PRS] / (G - 1.0);
+    double cs2 = G * V[PRS] / w;
+    double bb2 = B2 * (1.0 - v2) + vB * vB; /* b^2 = B^2/gamma^2 + (v.B)^2 */
+    double ca2 = bb2 / (w + bb2);
+    double a2 = cs2 + ca2 - cs2 * ca2;
+    double vn = V[MX1 + d];
+    double den = 1.0 - v2 * a2;
+    double disc = (1.0 - v2) * (1.0 - v2 * a2 - vn * vn * (1.0 - a2));
+    if (disc < 0.0) disc = 0.0;
+    double root = sqrt(a2) * sqrt(disc);
+    *lmin = (vn * (1.0 - a2) - root) / den;
+    *lmax = (vn * (1.0 - a2) + root) / den;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Physics dispatch                                                          */
+/* ------------------------------------------------------------------------ */
+
+static void prim2cons(const orc_opts *o, const double *V, double *U)
+{
+    if (o->physics == PHYS_MHD) mhd_prim2cons(o, V, U); else rmhd_prim2cons(o, V, U);
+}
+
+static void cons2prim(const orc_opts *o, const double *U, double *V, int *fails)
+{
+    if (o->physics == PHYS_MHD) mhd_cons2prim(o, U, V, fails); else rmhd_cons2prim(o, U, V, fails);
+}
+
+/* Physical flux along d including the GLM rows (Eq. glm2x2): F_{B_n} = psi,
+ * F_psi = c_h^2 B_n. */
+static void phys_flux(const orc_opts *o, const double *V, int d, double ch, double *F)
+{
+    double U[NVAR];
+    prim2cons(o, V, U);
+    if (o->physics == PHYS_MHD) mhd_flux(o, V, U, d, F); else rmhd_flux(o, V, U, d, F);
+    if (o->glm) {
+        F[BX1 + d] = V[PSI];
+        F[PSI] = ch * ch * V[BX1 + d];
+    }
+}
+
+static void signal_speeds(const orc_opts *o, const double *V, int d, double *lmin, double *lmax)
+{
+    if (o->physics == PHYS_MHD) {
+        double cf = mhd_fast_speed(o, V, d);
+        *lmin = V[MX1 + d] - cf;
+        *lmax = V[MX1 + d] + cf;
+    } else {
+        rmhd_speeds(o, V, d, lmin, lmax);
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Riemann solvers                                                           */
+/* ------------------------------------------------------------------------ */
+
+/* HLL: single intermediate state between the outer signal speeds. */
+static void riemann_hll(const orc_opts *o, const double *VL, const double *VR, int d, double ch,
+                        double *F, double *smax)
+{
+    double lminL, lmaxL, lminR, lmaxR;
+    signal_speeds(o, VL, d, &lminL, &lmaxL);
+    signal_speeds(o, VR, d, &lminR, &lmaxR);
+    double SL = fmin(lminL, lminR);
+    double SR = fmax(lmaxL, lmaxR);
+    *smax = fmax(fabs(SL), fabs(SR));
+    double FL[NVAR], FR[NVAR], UL[NVAR], UR[NVAR];
+    phys_flux(o, VL, d, ch, FL);
+    phys_flux(o, VR, d, ch, FR);
+    prim2cons(o, VL, UL);
+    prim2cons(o, VR, UR);
+    if (SL >= 0.0) {
+        memcpy(F, FL, sizeof(FL));
+    } else if (SR <= 0.0) {
+        memcpy(F, FR, sizeof(FR));
+    } else {
+        for (int v = 0; v < NVAR; v++)
+            F[v] = (SR * FL[v] - SL * FR[v] + SL * SR * (UR[v] - UL[v])) / (SR - SL);
+    }
+}
+
+/* HLLD for ideal MHD (Miyoshi & Kusano 2005), for states sharing B_n. */
+static void riemann_hlld(const orc_opts *o, const double *VL, const double *VR, int d, double ch,
+                         double *F, double *smax)
+{
+    int n, t, b;
+    dir_axes(d, &n, &t, &b);
+    double cfL = mhd_fast_speed(o, VL, d), cfR = mhd_fast_speed(o, VR, d);
+    double uL = VL[MX1 + n], uR = VR[MX1 + n];
+    double SL = fmin(uL - cfL, uR - cfR);
+    double SR = fmax(uL + cfL, uR + cfR);
+    *smax = fmax(fabs(SL), fabs(SR));
+
+    double UL[NVAR], UR[NVAR], FL[NVAR], FR[NVAR];
+    prim2cons(o, VL, UL);
+    prim2cons(o, VR, UR);
+    phys_flux(o, VL, d, ch, FL);
+    phys_flux(o, VR, d, ch, FR);
+    if (SL >= 0.0) { memcpy(F, FL, sizeof(FL)); return; }
+    if (SR <= 0.0) { memcpy(F, FR, sizeof(FR)); return; }
+
+    double Bn = VL[BX1 + n]; /* equal to VR[BX1+n] by construction */
+    double B2L = VL[BX1] * VL[BX1] + VL[BX2] * VL[BX2] + VL[BX3] * VL[BX3];
+    double B2R = VR[BX1] * VR[BX1] + VR[BX2] * VR[BX2] + VR[BX3] * VR[BX3];
+    double ptL = VL[PRS] + 0.5 * B2L, ptR = VR[PRS] + 0.5 * B2R;
+    double rhoL = VL[RHO], rhoR = VR[RHO];
+    double aL = (SL - uL) * rhoL, aR = (SR - uR) * rhoR;
+    double SM = (aR * uR - aL * uL - ptR + ptL) / (aR - aL);
+    double pts = (aR * ptL - aL * ptR + aL * aR * (uR - uL)) / (aR - aL);
+
+    /* single-star states */
+    double Us[2][NVAR], vs[2][3], Bs[2][3], sqr[2];
+    const double *Vk[2] = { VL, VR };
+    const double *Uk[2] = { UL, UR };
+    double Sk[2] = { SL, SR };
+    for (int s = 0; s < 2; s++) {
+        const double *V = Vk[s];
+        double S = Sk[s], u = V[MX1 + n], rho = V[RHO];
+        double rhos = rho * (S - u) / (S - SM);
+        double den = rho * (S - u) * (S - SM) - Bn * Bn;
+        double scale = rho * fabs(S - u) * fabs(S - SM) + Bn * Bn;
+        vs[s][n] = SM;
+        Bs[s][n] = Bn;
+        if (fabs(den) <= 1e-12 * scale) {
+            /* degenerate: transverse velocity and field are continuous */
+            vs[s][t] = V[MX1 + t];
+            vs[s][b] = V[MX1 + b];
+            Bs[s][t] = V[BX1 + t];
+            Bs[s][b] = V[BX1 + b];
+        } else {
+            double fv = Bn * (SM - u) / den;
+            double fB = (rho * (S - u) * (S - u) - Bn * Bn) / den;
+            vs[s][t] = V[MX1 + t] - V[BX1 + t] * fv;
+            vs[s][b] = V[MX1 + b] - V[BX1 + b] * fv;
+            Bs[s][t] = V[BX1 + t] * fB;
+            Bs[s][b] = V[BX1 + b] * fB;
+        }
+        double vB = V[MX1] * V[BX1] + V[MX2] * V[BX2] + V[MX3] * V[BX3];
+        double vBs = vs[s][0] * Bs[s][0] + vs[s][1] * Bs[s][1] + vs[s][2] * Bs[s][2];
+        double pt = (s == 0 ? ptL : ptR);
+        double Es = ((S - u) * Uk[s][ENG] - pt * u + pts * SM + Bn * (vB - vBs)) / (S - SM);
+        Us[s][RHO] = rhos;
+        for (int c = 0; c < 3; c++) {
+            Us[s][MX1 + c] = rhos * vs[s][c];
+            Us[s][BX1 + c] = Bs[s][c];
+        }
+        Us[s][ENG] = Es;
+        Us[s][PSI] = V[PSI];
+        sqr[s] = sqrt(rhos);
+    }
+    double SLs = SM - fabs(Bn) / sqr[0];
+    double SRs = SM + fabs(Bn) / sqr[1];
+
+    if (SLs >= 0.0) {
+        for (int v = 0; v < NVAR; v++) F[v] = FL[v] + SL * (Us[0][v] - UL[v]);
+    } else if (SRs <= 0.0) {
+        for (int v = 0; v < NVAR; v++) F[v] = FR[v] + SR * (Us[1][v] - UR[v]);
+    } else {
+        /* double-star states */
+        double sB = sgn1(Bn);
+        double den = sqr[0] + sqr[1];
+        double vss[3], Bss[3];
+        vss[n] = SM;
+        Bss[n] = Bn;
+        vss[t] = (sqr[0] * vs[0][t] + sqr[1] * vs[1][t] + (Bs[1][t] - Bs[0][t]) * sB) / den;
+        vss[b] = (sqr[0] * vs[0][b] + sqr[1] * vs[1][b] + (Bs[1][b] - Bs[0][b]) * sB) / den;
+        Bss[t] = (sqr[0] * Bs[1][t] + sqr[1] * Bs[0][t] + sqr[0] * sqr[1] * (vs[1][t] - vs[0][t]) * sB) / den;
+        Bss[b] = (sqr[0] * Bs[1][b] + sqr[1] * Bs[0][b] + sqr[0] * sqr[1] * (vs[1][b] - vs[0][b]) * sB) / den;
+        double vBss = vss[0] * Bss[0] + vss[1] * Bss[1] + vss[2] * Bss[2];
+        double Uss[2][NVAR];
+        for (int s = 0; s < 2; s++) {
+            double vBs = vs[s][0] * Bs[s][0] + vs[s][1] * Bs[s][1] + vs[s][2] * Bs[s][2];
+            double sgn = (s == 0 ? -1.0 : 1.0);
+            Uss[s][RHO] = Us[s][RHO];
+            for (int c = 0; c < 3; c++) {
+                Uss[s][MX1 + c] = Us[s][RHO] * vss[c];
+                Uss[s][BX1 + c] = Bss[c];
+            }
+            Uss[s][ENG] = Us[s][ENG] + sgn * sqr[s] * (vBs - vBss) * sB;
+            Uss[s][PSI] = Us[s][PSI];
+        }
+        if (SM >= 0.0) {
+            for (int v = 0; v < NVAR; v++)
+                F[v] = FL[v] + SLs * Uss[0][v] - (SLs - SL) * Us[0][v] - SL * UL[v];
+        } else {
+            for (int v = 0; v < NVAR; v++)
+                F[v] = FR[v] + SRs * Uss[1][v] - (SRs - SR) * Us[1][v] - SR * UR[v];
+        }
+    }
+}
+
+/* Full interface solve along d: the linear (B_n, psi) subsystem of Eq.
+ * glm2x2 is solved exactly (characteristics psi +- c_h B_n), its interface
+ * value of B_n is imposed on both states, then HLLD or HLL gives the other
+ * seven fluxes.  Without GLM the two normal fields are averaged. */
+static void riemann(const orc_opts *o, const double *VLin, const double *VRin, int d, double ch,
+                    double *F, double *smax)
+{
+    double VL[NVAR], VR[NVAR];
+    memcpy(VL, VLin, sizeof(VL));
+    memcpy(VR, VRin, sizeof(VR));
+    double Bm, psim;
+    if (o->glm) {
+        Bm = 0.5 * (VL[BX1 + d] + VR[BX1 + d]) - (VR[PSI] - VL[PSI]) / (2.0 * ch);
+        psim = 0.5 * (VL[PSI] + VR[PSI]) - 0.5 * ch * (VR[BX1 + d] - VL[BX1 + d]);
+    } else {
+        Bm = 0.5 * (VL[BX1 + d] + VR[BX1 + d]);
+        psim = 0.0;
+    }
+    VL[BX1 + d] = VR[BX1 + d] = Bm;
+    if (o->riemann == RS_HLLD && o->physics == PHYS_MHD)
+        riemann_hlld(o, VL, VR, d, ch, F, smax);
+    else
+        riemann_hll(o, VL, VR, d, ch, F, smax);
+    if (o->glm) {
+        F[BX1 + d] = psim;
+        F[PSI] = ch * ch * Bm;
+    } else {
+        F[BX1 + d] = 0.0;
+        F[PSI] = 0.0;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Limiters and reconstruction (Sec. 3.2)                                    */
+/* ------------------------------------------------------------------------ */
+
+static double minmod(double a, double b) /* Eq. minmod */
+{
+    return 0.5 * (sgn0(a) + sgn0(b)) * fmin(fabs(a), fabs(b));
+}
+
+static double lim_mc(double dp, double dm) /* Eq. MClim */
+{
+    return minmod(0.5 * (dp + dm), 2.0 * minmod(dm, dp));
+}
+
+static double lim_vanleer(double dp, double dm) /* Eq. harmonic_lim */
+{
+    return (dp * dm > 0.0) ? 2.0 * dp * dm / (dp + dm) : 0.0;
+}
+
+static double lim_vanalbada(double dp, double dm) /* Eq. vanalbada_lim */
+{
+    return (dp * dm > 0.0) ? dp * dm * (dp + dm) / (dp * dp + dm * dm) : 0.0;
+}
+
+static double limited_slope(int recon, double dp, double dm)
+{
+    switch (recon) {
+    case REC_LIN_MINMOD: return minmod(dp, dm);
+    case REC_LIN_VANLEER: return lim_vanleer(dp, dm);
+    case REC_LIN_VANALBADA: return lim_vanalbada(dp, dm);
+    default: return lim_mc(dp, dm);
+    }
+}
+
+/* Interface values w_{-}, w_{+} of cell 0 from the stencil w[l+2], l=-2..2
+ * (linear and WENO3 use l=-1..1 only). */
+static void reconstruct(int recon, const double *w, double dx, double *wm, double *wp)
+{
+    double w0 = w[2];
+    double dp = w[3] - w[2]; /* Delta w_{+1/2} */
+    double dm = w[2] - w[1]; /* Delta w_{-1/2} */
+    if (recon == REC_PPM) {
+        double s0 = lim_mc(dp, dm);
+        double sp = lim_mc(w[4] - w[3], w[3] - w[2]);
+        double sm = lim_mc(w[1] - w[0], w[2] - w[1]);
+        double wP = 0.5 * (w0 + w[3]) - (sp - s0) / 6.0; /* Eq. ppm1 */
+        double wM = 0.5 * (w0 + w[1]) + (sm - s0) / 6.0;
+        double dP = wP - w0, dM = wM - w0;
+        double nP, nM;
+        if (dP * dM > 0.0) { /* Eq. ppm_parabolic_lim: local extremum */
+            nP = 0.0;
+            nM = 0.0;
+        } else {
+            nP = (fabs(dP) >= 2.0 * fabs(dM)) ? -2.0 * dM : dP;
+            nM = (fabs(dM) >= 2.0 * fabs(dP)) ? -2.0 * dP : dM;
+        }
+        *wp = w0 + nP;
+        *wm = w0 + nM;
+    } else if (recon == REC_WENO3) {
+        double d2 = (dp - dm) * (dp - dm);
+        double ap = 1.0 + d2 / (dx * dx + dp * dp); /* Eq. WENO3a */
+        double am = 1.0 + d2 / (dx * dx + dm * dm);
+        *wp = w0 + (ap * dp + 0.5 * am * dm) / (2.0 * ap + am); /* Eq. WENO3 */
+        *wm = w0 - (am * dm + 0.5 * ap * dp) / (2.0 * am + ap);
+    } else {
+        double s = limited_slope(recon, dp, dm); /* Eq. Linear */
+        *wp = w0 + 0.5 * s;
+        *wm = w0 - 0.5 * s;
+    }
+}
+
+/* Upwind tracing of one characteristic field to the half step (Eq.
+ * wnorm_predp / wnorm_predm).  nu = lambda dt / dx. */
+static void trace_wave(int wref, double w0, double wm, double wp, double nu, double numax, double numin,
+                       double *wsm, double *wsp)
+{
+    double dw = wp - wm;
+    double d2w = wp - 2.0 * w0 + wm;
+    double bp = 0.5 * (1.0 + sgn0(nu));
+    double bm = 0.5 * (1.0 - sgn0(nu));
+    double tp = wp - 0.5 * nu * (dw + d2w * (3.0 - 2.0 * nu));
+    double tm = wm - 0.5 * nu * (dw - d2w * (3.0 + 2.0 * nu));
+    double rp, rm;
+    if (wref == WREF_CELL) {
+        rp = w0;
+        rm = w0;
+    } else if (wref == WREF_CW84) {
+        rp = wp - 0.5 * numax * (dw + d2w * (3.0 - 2.0 * numax));
+        rm = wm - 0.5 * numin * (dw - d2w * (3.0 + 2.0 * numin));
+    } else {
+        rp = wp;
+        rm = wm;
+    }
+    *wsp = rp + bp * (tp - rp);
+    *wsm = rm + bm * (tm - rm);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Eigenvectors of the primitive MHD system (normalized after Roe & Balsara)  */
+/* ------------------------------------------------------------------------ */
+
+/* Rotated 7-component primitive vector (rho, v_n, v_t, v_b, B_t, B_b, p). */
+static void rot7(const double *V, int d, double *q)
+{
+    int n, t, b;
+    dir_axes(d, &n, &t, &b);
+    q[0] = V[RHO];
+    q[1] = V[MX1 + n];
+    q[2] = V[MX1 + t];
+    q[3] = V[MX1 + b];
+    q[4] = V[BX1 + t];
+    q[5] = V[BX1 + b];
+    q[6] = V[PRS];
+}
+
+static void unrot7(const double *q, int d, double *V)
+{
+    int n, t, b;
+    dir_axes(d, &n, &t, &b);
+    V[RHO] = q[0];
+    V[MX1 + n] = q[1];
+    V[MX1 + t] = q[2];
+    V[MX1 + b] = q[3];
+    V[BX1 + t] = q[4];
+    V[BX1 + b] = q[5];
+    V[PRS] = q[6];
+}
+
+/* Right eigenvectors R[m][k] (component m of wave k) and eigenvalues of the
+ * 7-wave primitive system along d, with B_n held as a parameter.  Waves in
+ * order: v-cf, v-ca, v-cs, v, v+cs, v+ca, v+cf. */
+static void mhd_right_eigen(const orc_opts *o, const double *V, int d, double R[7][7], double lam[7])
+{
+    int n, t, b;
+    dir_axes(d, &n, &t, &b);
+    double rho = V[RHO], p = V[PRS];
+    double Bn = V[BX1 + n], Bt = V[BX1 + t], Bb = V[BX1 + b];
+    double a2 = o->gamma * p / rho;
+    double a = sqrt(a2);
+    double srho = sqrt(rho);
+    double bn2 = Bn * Bn / rho;
+    double bt2 = (Bt * Bt + Bb * Bb) / rho;
+    double b2 = bn2 + bt2;
+    /* c_f^2 - c_s^2 = sqrt((a^2 + b^2)^2 - 4 a^2 b_n^2), written as
+     * sqrt((a^2 - b^2)^2 + 4 a^2 b_t^2) so that it is exact when b_t = 0;
+     * a^2 - c_s^2 and c_f^2 - a^2 then follow without cancellation. */
+    double dab = a2 - b2;
+    double sq = sqrt(dab * dab + 4.0 * a2 * bt2);
+    double cf2 = 0.5 * (a2 + b2 + sq);
+    double cs2 = a2 * bn2 / cf2; /* c_f^2 c_s^2 = a^2 c_a^2 */
+    double cf = sqrt(cf2), cs = sqrt(cs2), ca = sqrt(bn2);
+    double af, as;
+    if (sq <= 0.0) {
+        af = 1.0; /* triple degeneracy a = c_a, b_t = 0 */
+        as = 0.0;
+    } else {
+        af = sqrt(fmax(0.5 * (sq + dab) / sq, 0.0)); /* (a^2 - c_s^2)/(c_f^2 - c_s^2) */
+        as = sqrt(fmax(0.5 * (sq - dab) / sq, 0.0)); /* (c_f^2 - a^2)/(c_f^2 - c_s^2) */
+    }
+    double Btn2 = Bt * Bt + Bb * Bb;
+    double B2 = Btn2 + Bn * Bn;
+    double by, bz;
+    if (Btn2 <= 1e-12 * B2) {
+        by = 1.0 / sqrt(2.0);
+        bz = 1.0 / sqrt(2.0);
+    } else {
+        double bt = sqrt(Btn2);
+        by = Bt / bt;
+        bz = Bb / bt;
+    }
+    double sB = sgn1(Bn);
+    double vn = V[MX1 + n];
+    lam[0] = vn - cf; lam[1] = vn - ca; lam[2] = vn - cs; lam[3] = vn;
+    lam[4] = vn + cs; lam[5] = vn + ca; lam[6] = vn + cf;
+    memset(R, 0, sizeof(double) * 49);
+    /* fast waves */
+    for (int k = 0; k < 7; k += 6) {
+        double e = (k == 0 ? -1.0 : 1.0);
+        R[0][k] = rho * af;
+        R[1][k] = e * af * cf;
+        R[2][k] = -e * sB * as * cs * by;
+        R[3][k] = -e * sB * as * cs * bz;
+        R[4][k] = as * a * srho * by;
+        R[5][k] = as * a * srho * bz;
+        R[6][k] = rho * a2 * af;
+    }
+    /* slow waves */
+    for (int k = 2; k <= 4; k += 2) {
+        double e = (k == 2 ? -1.0 : 1.0);
+        R[0][k] = rho * as;
+        R[1][k] = e * as * cs;
+        R[2][k] = e * sB * af * cf * by;
+        R[3][k] = e * sB * af * cf * bz;
+        R[4][k] = -af * a * srho * by;
+        R[5][k] = -af * a * srho * bz;
+        R[6][k] = rho * a2 * as;
+    }
+    /* Alfven waves */
+    for (int k = 1; k <= 5; k += 4) {
+        double e = (k == 1 ? 1.0 : -1.0);
+        R[2][k] = -bz;
+        R[3][k] = by;
+        R[4][k] = -e * sB * srho * bz;
+        R[5][k] = e * sB * srho * by;
+    }
+    /* entropy wave */
+    R[0][3] = 1.0;
+}
+
+/* Matrix inverse by Gauss-Jordan elimination with partial pivoting. */
+static int invert7(double A[7][7], double Ainv[7][7])
+{
+    double M[7][14];
+    for (int i = 0; i < 7; i++) {
+        for (int j = 0; j < 7; j++) {
+            M[i][j] = A[i][j];
+            M[i][7 + j] = (i == j) ? 1.0 : 0.0;
+        }
+    }
+    for (int c = 0; c < 7; c++) {
+        int piv = c;
+        for (int r = c + 1; r < 7; r++)
+            if (fabs(M[r][c]) > fabs(M[piv][c])) piv = r;
+        if (M[piv][c] == 0.0) return 0;
+        if (piv != c)
+            for (int j = 0; j < 14; j++) { double tmp = M[c][j]; M[c][j] = M[piv][j]; M[piv][j] = tmp; }
+        double inv = 1.0 / M[c][c];
+        for (int j = 0; j < 14; j++) M[c][j] *= inv;
+        for (int r = 0; r < 7; r++) {
+            if (r == c) continue;
+            double f = M[r][c];
+            if (f != 0.0)
+                for (int j = 0; j < 14; j++) M[r][j] -= f * M[c][j];
+        }
+    }
+    for (int i = 0; i < 7; i++)
+        for (int j = 0; j < 7; j++) Ainv[i][j] = M[i][7 + j];
+    return 1;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Normal predictors                                                         */
+/* ------------------------------------------------------------------------ */
+
+/* Characteristic normal predictor (Sec. 3.2) for cell 0 of the stencil
+ * Vs[l+2], l=-2..2 (primitive), along d.  Output: V*_{-}, V*_{+}. */
+static void predict_char(const orc_opts *o, const double Vs[5][NVAR], int d, double dt, double ch,
+                         double *Vm, double *Vp)
+{
+    double dx = o->dx[d];
+    const double *V0 = Vs[2];
+    double R[7][7], L[7][7], lam[7];
+    mhd_right_eigen(o, V0, d, R, lam);
+    invert7(R, L);
+
+    /* Eq. char_var: project the stencil on the left eigenvectors of cell 0 */
+    double q[5][7], w[7][5];
+    for (int l = 0; l < 5; l++) rot7(Vs[l], d, q[l]);
+    for (int k = 0; k < 7; k++)
+        for (int l = 0; l < 5; l++) {
+            double acc = 0.0;
+            for (int m = 0; m < 7; m++) acc += L[k][m] * q[l][m];
+            w[k][l] = acc;
+        }
+    /* GLM pair (B_n, psi) of Eq. glm2x2: speeds -c_h, +c_h with right
+     * eigenvectors (1, -+c_h) and left eigenvectors (c_h, -+1)/(2 c_h) */
+    double wh[2][5], lamh[2] = { -ch, ch };
+    int use_glm = o->glm && ch > 0.0;
+    if (use_glm) {
+        for (int l = 0; l < 5; l++) {
+            wh[0][l] = (ch * Vs[l][BX1 + d] - Vs[l][PSI]) / (2.0 * ch);
+            wh[1][l] = (ch * Vs[l][BX1 + d] + Vs[l][PSI]) / (2.0 * ch);
+        }
+    }
+
+    double nu[9], numax = 0.0, numin = 0.0;
+    for (int k = 0; k < 7; k++) nu[k] = lam[k] * dt / dx;
+    int nw = 7;
+    if (use_glm) { nu[7] = lamh[0] * dt / dx; nu[8] = lamh[1] * dt / dx; nw = 9; }
+    for (int k = 0; k < nw; k++) { numax = fmax(numax, nu[k]); numin = fmin(numin, nu[k]); }
+
+    double wsm[7], wsp[7];
+    for (int k = 0; k < 7; k++) {
+        double wm, wp;
+        reconstruct(o->recon, w[k], dx, &wm, &wp);
+        trace_wave(o->wref, w[k][2], wm, wp, nu[k], numax, numin, &wsm[k], &wsp[k]);
+    }
+    double Bnm, Bnp, psim, psip, dBn, dpsi;
+    if (use_glm) {
+        double hm[2], hp[2], hsm[2], hsp[2];
+        for (int k = 0; k < 2; k++) {
+            reconstruct(o->recon, wh[k], dx, &hm[k], &hp[k]);
+            trace_wave(o->wref, wh[k][2], hm[k], hp[k], nu[7 + k], numax, numin, &hsm[k], &hsp[k]);
+        }
+        /* r_{-} = (1, -c_h), r_{+} = (1, +c_h) in (B_n, psi) */
+        dBn = (hp[0] + hp[1]) - (hm[0] + hm[1]);
+        dpsi = ch * ((hp[1] - hp[0]) - (hm[1] - hm[0]));
+        Bnm = hsm[0] + hsm[1];
+        Bnp = hsp[0] + hsp[1];
+        psim = ch * (hsm[1] - hsm[0]);
+        psip = ch * (hsp[1] - hsp[0]);
+    } else {
+        double bn[5], bm, bp;
+        for (int l = 0; l < 5; l++) bn[l] = Vs[l][BX1 + d];
+        reconstruct(o->recon, bn, dx, &bm, &bp);
+        dBn = bp - bm;
+        dpsi = 0.0;
+        Bnm = bm;
+        Bnp = bp;
+        psim = psip = V0[PSI];
+    }
+
+    /* right-eigenvector recombination */
+    double qm[7], qp[7];
+    for (int m = 0; m < 7; m++) {
+        double am = 0.0, ap = 0.0;
+        for (int k = 0; k < 7; k++) { am += R[m][k] * wsm[k]; ap += R[m][k] * wsp[k]; }
+        qm[m] = am;
+        qp[m] = ap;
+    }
+    unrot7(qm, d, Vm);
+    unrot7(qp, d, Vp);
+    Vm[BX1 + d] = Bnm;
+    Vp[BX1 + d] = Bnp;
+    Vm[PSI] = psim;
+    Vp[PSI] = psip;
+
+    /* Multidimensional terms: the 1D conservative system differs from the
+     * 7-wave primitive one by d(B_n)/dn (0, B/rho, v_t, v_b, (1-G) v.B) and
+     * d(psi)/dn in the pressure row ((G-1) B_n). */
+    double rho = V0[RHO];
+    double vB = V0[MX1] * V0[BX1] + V0[MX2] * V0[BX2] + V0[MX3] * V0[BX3];
+    double SB[NVAR] = { 0 }, Spsi[NVAR] = { 0 };
+    int n, t, b;
+    dir_axes(d, &n, &t, &b);
+    SB[MX1 + n] = V0[BX1 + n] / rho;
+    SB[MX1 + t] = V0[BX1 + t] / rho;
+    SB[MX1 + b] = V0[BX1 + b] / rho;
+    SB[BX1 + t] = V0[MX1 + t];
+    SB[BX1 + b] = V0[MX1 + b];
+    SB[PRS] = (1.0 - o->gamma) * vB;
+    Spsi[PRS] = (o->gamma - 1.0) * V0[BX1 + n];
+    for (int v = 0; v < NVAR; v++) {
+        double src = 0.5 * dt * (SB[v] * dBn / dx + Spsi[v] * dpsi / dx);
+        Vm[v] += src;
+        Vp[v] += src;
+    }
+}
+
+/* MUSCL-Hancock primitive predictor (Sec. 3.3) with beta = 1. */
+static void predict_mh(const orc_opts *o, const double Vs[5][NVAR], const double *U0, int d, double dt,
+                       double ch, double *Vm, double *Vp, int *fails)
+{
+    double dx = o->dx[d];
+    double dV[NVAR], Vlo[NVAR], Vhi[NVAR];
+    for (int v = 0; v < NVAR; v++) {
+        dV[v] = limited_slope(o->recon, Vs[3][v] - Vs[2][v], Vs[2][v] - Vs[1][v]);
+        Vlo[v] = Vs[2][v] - 0.5 * dV[v];
+        Vhi[v] = Vs[2][v] + 0.5 * dV[v];
+    }
+    if (o->physics == PHYS_RMHD) {
+        double v2lo = Vlo[MX1] * Vlo[MX1] + Vlo[MX2] * Vlo[MX2] + Vlo[MX3] * Vlo[MX3];
+        double v2hi = Vhi[MX1] * Vhi[MX1] + Vhi[MX2] * Vhi[MX2] + Vhi[MX3] * Vhi[MX3];
+        if (!(v2lo < 1.0) || !(v2hi < 1.0)) {
+            /* superluminal reconstruction: first order in this cell */
+            if (fails) fails[FAIL_VEL]++;
+            for (int v = 0; v < NVAR; v++) { dV[v] = 0.0; Vlo[v] = Vhi[v] = Vs[2][v]; }
+        }
+    }
+    double Flo[NVAR], Fhi[NVAR], Us[NVAR], Vh[NVAR];
+    phys_flux(o, Vlo, d, ch, Flo);
+    phys_flux(o, Vhi, d, ch, Fhi);
+    for (int v = 0; v < NVAR; v++) Us[v] = U0[v] - 0.5 * dt / dx * (Fhi[v] - Flo[v]);
+    int fl[NFAIL] = { 0 };
+    cons2prim(o, Us, Vh, fl);
+    int bad = 0;
+    for (int k = 0; k < NFAIL; k++) bad |= fl[k];
+    if (bad) {
+        if (fails) for (int k = 0; k < NFAIL; k++) fails[k] += fl[k];
+        memcpy(Vh, Vs[2], sizeof(Vh));
+    }
+    for (int v = 0; v < NVAR; v++) {
+        Vm[v] = Vh[v] - 0.5 * dV[v];
+        Vp[v] = Vh[v] + 0.5 * dV[v];
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Parabolic fluxes (Sec. 2.1.1, Sec. 3.1, App. A)                            */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    int NX, NY, NZ;
+    long NC;
+} grid_t;
+
+static long cidx(const grid_t *g, int i, int j, int k) { return ((long)k * g->NY + j) * g->NX + i; }
+
+/* Parabolic face flux Pi (9 components) on the d-face between cell A = c - e_d
+ * and cell B = c.  Vc: primitive point values; Uc: conserved values (face
+ * coefficients use g((U_A + U_B)/2)).  pL, pR, rL, rR: pressures and
+ * densities of the Riemann input states used by the saturated flux. */
+static void parab_flux(const orc_opts *o, const grid_t *g, const double *Vc, const double *Uc, int i, int j,
+                       int k, int d, double pL, double pR, double rL, double rR, double *Pi)
+{
+    int n, t, b;
+    dir_axes(d, &n, &t, &b);
+    int off[3][3] = { { 1, 0, 0 }, { 0, 1, 0 }, { 0, 0, 1 } };
+    long NC = g->NC;
+    long cB = cidx(g, i, j, k);
+    long cA = cidx(g, i - off[d][0], j - off[d][1], k - off[d][2]);
+    /* face averages of conserved variables */
+    double rhof = 0.5 * (Uc[RHO * NC + cA] + Uc[RHO * NC + cB]);
+    double vf[3], Bf[3];
+    for (int c = 0; c < 3; c++) {
+        vf[c] = (Uc[(MX1 + c) * NC + cA] + Uc[(MX1 + c) * NC + cB]) / (Uc[RHO * NC + cA] + Uc[RHO * NC + cB]);
+        Bf[c] = 0.5 * (Uc[(BX1 + c) * NC + cA] + Uc[(BX1 + c) * NC + cB]);
+    }
+    /* gradients of f = (v_x, v_y, v_z, B_x, B_y, B_z, T) at the face */
+    double grad[7][3];
+    for (int f = 0; f < 7; f++) {
+        for (int e = 0; e < 3; e++) {
+            if (e >= o->dim) { grad[f][e] = 0.0; continue; }
+#define FVAL(ii, jj, kk)                                                                            \
+    (f < 3 ? Vc[(MX1 + f) * NC + cidx(g, ii, jj, kk)]                                              \
+           : (f < 6 ? Vc[(BX1 + f - 3) * NC + cidx(g, ii, jj, kk)]                                 \
+                    : Vc[PRS * NC + cidx(g, ii, jj, kk)] / Vc[RHO * NC + cidx(g, ii, jj, kk)]))
+            if (e == d) {
+                grad[f][e] = (FVAL(i, j, k) - FVAL(i - off[d][0], j - off[d][1], k - off[d][2])) / o->dx[d];
+            } else {
+                int ai = i - off[d][0], aj = j - off[d][1], ak = k - off[d][2];
+                int ei = off[e][0], ej = off[e][1], ek = off[e][2];
+                double up = FVAL(i + ei, j + ej, k + ek) + FVAL(ai + ei, aj + ej, ak + ek);
+                double dn = FVAL(i - ei, j - ej, k - ek) + FVAL(ai - ei, aj - ej, ak - ek);
+                grad[f][e] = (up - dn) / (4.0 * o->dx[e]);
+            }
+#undef FVAL
+        }
+    }
+    for (int v = 0; v < NVAR; v++) Pi[v] = 0.0;
+    double G = o->gamma;
+    if (o->parabolic_mask & PARAB_VISC) {
+        /* Eq. visc_tens, row n */
+        double divv = grad[0][0] + grad[1][1] + grad[2][2];
+        double tau[3];
+        for (int c = 0; c < 3; c++) {
+            tau[c] = rhof * o->nu * (grad[c][n] + grad[n][c] - (c == n ? 2.0 / 3.0 * divv : 0.0));
+            Pi[MX1 + c] += tau[c];
+        }
+        Pi[ENG] += vf[0] * tau[0] + vf[1] * tau[1] + vf[2] * tau[2];
+    }
+    if (o->parabolic_mask & PARAB_RES) {
+        /* J = curl B;  d B/dt = -curl(eta J)  =>  flux of B_t is eta J_b, of B_b is -eta J_t */
+        double J[3];
+        J[0] = grad[5][1] - grad[4][2];
+        J[1] = grad[3][2] - grad[5][0];
+        J[2] = grad[4][0] - grad[3][1];
+        Pi[BX1 + t] += o->eta * J[b];
+        Pi[BX1 + b] += -o->eta * J[t];
+        /* energy: -(eta J x B)_n */
+        double JxB_n = J[t] * Bf[b] - J[b] * Bf[t];
+        Pi[ENG] += -o->eta * JxB_n;
+    }
+    if (o->parabolic_mask & PARAB_TC) {
+        double B2 = Bf[0] * Bf[0] + Bf[1] * Bf[1] + Bf[2] * Bf[2];
+        double bh[3] = { 0.0, 0.0, 0.0 };
+        if (B2 > 0.0) {
+            double Bm = sqrt(B2);
+            for (int c = 0; c < 3; c++) bh[c] = Bf[c] / Bm;
+        }
+        double bgT = bh[0] * grad[6][0] + bh[1] * grad[6][1] + bh[2] * grad[6][2];
+        double Fcl[3];
+        for (int c = 0; c < 3; c++)
+            Fcl[c] = o->kappa_par * bh[c] * bgT + o->kappa_perp * (grad[6][c] - bh[c] * bgT);
+        double Fmag = sqrt(Fcl[0] * Fcl[0] + Fcl[1] * Fcl[1] + Fcl[2] * Fcl[2]);
+        double Fc = Fcl[n];
+        if (o->tc_phi > 0.0 && Fmag > 0.0) {
+            /* Eq. sat_flux: upwinded saturated flux, then the harmonic blend */
+            double tx = Fcl[n] / Fmag;
+            double rh = 0.5 * (rL + rR);
+            double pu = (tx < 0.0) ? pL : pR;
+            double q = 5.0 * o->tc_phi * pu * sqrt(pu) / sqrt(rh);
+            Fc = q / (Fmag + q) * Fcl[n];
+        }
+        Pi[ENG] += Fc;
+    }
+    (void)G;
+}
+
+/* Largest diffusion coefficient at a cell, entering Eq. Ca. */
+static double diff_coeff(const orc_opts *o, const double *V)
+{
+    double D = 0.0;
+    if (o->parabolic_mask & PARAB_VISC) D = fmax(D, o->nu);
+    if (o->parabolic_mask & PARAB_RES) D = fmax(D, o->eta);
+    if (o->parabolic_mask & PARAB_TC)
+        D = fmax(D, (o->gamma - 1.0) * fmax(o->kappa_par, o->kappa_perp) / V[RHO]);
+    return D;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Public helpers for the tests                                              */
+/* ------------------------------------------------------------------------ */
+
+void orc_prim2cons(const orc_opts *o, long ncell, const double *V, double *U)
+{
+    /* V, U are [9][ncell] */
+    for (long c = 0; c < ncell; c++) {
+        double v[NVAR], u[NVAR];
+        for (int q = 0; q < NVAR; q++) v[q] = V[q * ncell + c];
+        prim2cons(o, v, u);
+        for (int q = 0; q < NVAR; q++) U[q * ncell + c] = u[q];
+    }
+}
+
+void orc_cons2prim(const orc_opts *o, long ncell, const double *U, double *V, int *fails)
+{
+    for (long c = 0; c < ncell; c++) {
+        double v[NVAR], u[NVAR];
+        for (int q = 0; q < NVAR; q++) u[q] = U[q * ncell + c];
+        cons2prim(o, u, v, fails);
+        for (int q = 0; q < NVAR; q++) V[q * ncell + c] = v[q];
+    }
+}
+
+void orc_flux(const orc_opts *o, const double *V, int d, double ch, double *F) { phys_flux(o, V, d, ch, F); }
+
+void orc_riemann(const orc_opts *o, const double *VL, const double *VR, int d, double ch, double *F,
+                 double *smax)
+{
+    riemann(o, VL, VR, d, ch, F, smax);
+}
+
+void orc_speeds(const orc_opts *o, const double *V, int d, double *lmin, double *lmax)
+{
+    signal_speeds(o, V, d, lmin, lmax);
+}
+
+void orc_eigen(const orc_opts *o, const double *V, int d, double *R, double *L, double *lam)
+{
+    double Rm[7][7], Lm[7][7];
+    mhd_right_eigen(o, V, d, Rm, lam);
+    invert7(Rm, Lm);
+    memcpy(R, Rm, sizeof(Rm));
+    memcpy(L, Lm, sizeof(Lm));
+}
+
+void orc_reconstruct(int recon, const double *w, double dx, double *wm, double *wp)
+{
+    reconstruct(recon, w, dx, wm, wp);
+}
+
+void orc_trace(int wref, double w0, double wm, double wp, double nu, double numax, double numin, double *wsm,
+               double *wsp)
+{
+    trace_wave(wref, w0, wm, wp, nu, numax, numin, wsm, wsp);
+}
+
+void orc_predict(const orc_opts *o, const double *Vs /*[5][9]*/, const double *U0, int d, double dt, double ch,
+                 double *Vm, double *Vp, int *fails)
+{
+    double S[5][NVAR];
+    memcpy(S, Vs, sizeof(S));
+    if (o->predictor == PRED_CHAR) predict_char(o, S, d, dt, ch, Vm, Vp);
+    else predict_mh(o, S, U0, d, dt, ch, Vm, Vp, fails);
+}
+
+/* ------------------------------------------------------------------------ */
+/* The CTU step on one ghosted box (Sec. 3.1)                                */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * orc_step: advance the interior of one ghosted box by dt.
+ *   nx, ny, nz : interior extents (nz == 1 when dim == 2)
+ *   ng         : ghost zones per side in active directions
+ *   U_in       : [9][NZ][NY][NX] conserved, ghosts filled by the caller
+ *   L0         : per-cell cooling coefficient on the same ghosted layout, or NULL
+ *   U_out      : receives U^{n+1} in the interior (ghosts copied from U_in)
+ *   face_flux  : optional [dim][9][NZ][NY][NX]; entry at cell c in direction d
+ *                is dt*(F - Pi) on the face between c-e_d and c, interior
+ *                faces only (others zero)
+ *   out_scalars: [0] = CFL rate (Eq. Ca), [1] = max |dp/p| of the cooling step
+ *   fails      : [5] counters
+ * Returns 0 on success, <0 on unsupported options.
+ */
+int orc_step(const orc_opts *o, int nx, int ny, int nz, int ng, const double *U_in, const double *L0, double dt,
+             double ch, double *U_out, double *face_flux, double *out_scalars, int *fails)
+{
+    if (o->dim != 2 && o->dim != 3) return -1;
+    if (o->dim == 2 && nz != 1) return -1;
+    if (o->predictor == PRED_CHAR && o->physics != PHYS_MHD) return -2;
+    if (o->predictor == PRED_MH && (o->recon == REC_PPM || o->recon == REC_WENO3)) return -3;
+    if (o->physics == PHYS_RMHD && (o->parabolic_mask || o->cooling)) return -4;
+    if (o->glm && !(ch > 0.0)) return -5;
+    int need = (o->recon == REC_PPM ? 3 : 2) + (o->parabolic_mask ? 1 : 0);
+    if (ng < need) return -6;
+
+    grid_t g;
+    int gz = (o->dim == 3) ? ng : 0;
+    g.NX = nx + 2 * ng;
+    g.NY = ny + 2 * ng;
+    g.NZ = nz + 2 * gz;
+    g.NC = (long)g.NX * g.NY * g.NZ;
+    long NC = g.NC;
+    int N[3] = { g.NX, g.NY, g.NZ };
+    int lo[3] = { ng, ng, gz };
+    int hi[3] = { ng + nx, ng + ny, gz + nz }; /* exclusive */
+    int offs[3][3] = { { 1, 0, 0 }, { 0, 1, 0 }, { 0, 0, 1 } };
+    int dim = o->dim;
+    int par = (o->parabolic_mask != 0);
+    int hyp = !o->hyperbolic_off;
+
+    double *V = calloc(NVAR * NC, sizeof(double));
+    double *Fn = calloc(3 * NVAR * NC, sizeof(double)); /* t^n Godunov fluxes */
+    double *Pn = calloc(3 * NVAR * NC, sizeof(double)); /* t^n parabolic fluxes */
+    double *Ln = calloc(3 * NVAR * NC, sizeof(double)); /* -dF/dx per direction */
+    double *LPn = calloc(3 * NVAR * NC, sizeof(double)); /* +dPi/dx per direction */
+    double *Uhm = calloc(3 * NVAR * NC, sizeof(double)); /* corner-coupled states, minus side */
+    double *Uhp = calloc(3 * NVAR * NC, sizeof(double)); /* plus side */
+    double *Fh = calloc(3 * NVAR * NC, sizeof(double));  /* F^{n+1/2} */
+    double *Ph = calloc(3 * NVAR * NC, sizeof(double));  /* Pi^{n+1/2} */
+    double *lamf = calloc(3 * NC, sizeof(double));       /* |S|max per face */
+    double *pfL = calloc(3 * NC, sizeof(double));        /* Riemann input p, rho per face */
+    double *pfR = calloc(3 * NC, sizeof(double));
+    double *rfL = calloc(3 * NC, sizeof(double));
+    double *rfR = calloc(3 * NC, sizeof(double));
+    double *Uhalf = par ? calloc(NVAR * NC, sizeof(double)) : NULL;
+    double *Vhalf = par ? calloc(NVAR * NC, sizeof(double)) : NULL;
+    int lf[NFAIL] = { 0 };
+
+    /* 1. primitive recovery on every cell */
+    for (long c = 0; c < NC; c++) {
+        double u[NVAR], v[NVAR];
+        for (int q = 0; q < NVAR; q++) u[q] = U_in[q * NC + c];
+        cons2prim(o, u, v, lf);
+        for (int q = 0; q < NVAR; q++) V[q * NC + c] = v[q];
+    }
+
+    /* 2-3. first-order Godunov fluxes and parabolic fluxes at t^n, on every
+     * face whose stencil lies inside the ghosted box */
+    for (int d = 0; d < dim; d++) {
+        for (int k = 0; k < g.NZ; k++)
+            for (int j = 0; j < g.NY; j++)
+                for (int i = 0; i < g.NX; i++) {
+                    int ci[3] = { i, j, k };
+                    if (ci[d] < 1) continue;
+                    long cB = cidx(&g, i, j, k);
+                    long cA = cidx(&g, i - offs[d][0], j - offs[d][1], k - offs[d][2]);
+                    double VL[NVAR], VR[NVAR], F[NVAR], sm;
+                    for (int q = 0; q < NVAR; q++) { VL[q] = V[q * NC + cA]; VR[q] = V[q * NC + cB]; }
+                    if (hyp) {
+                        riemann(o, VL, VR, d, ch, F, &sm);
+                        for (int q = 0; q < NVAR; q++) Fn[(d * NVAR + q) * NC + cB] = F[q];
+                    }
+                    if (par) {
+                        int ok = 1;
+                        for (int e = 0; e < dim; e++)
+                            if (e != d && (ci[e] < 1 || ci[e] > N[e] - 2)) ok = 0;
+                        if (ok) {
+                            double Pi[NVAR];
+                            parab_flux(o, &g, V, U_in, i, j, k, d, VL[PRS], VR[PRS], VL[RHO], VR[RHO], Pi);
+                            for (int q = 0; q < NVAR; q++) Pn[(d * NVAR + q) * NC + cB] = Pi[q];
+                        }
+                    }
+                }
+        /* increment operators per cell (Eq. incrementop_hyp / incrementop_par) */
+        for (int k = 0; k < g.NZ; k++)
+            for (int j = 0; j < g.NY; j++)
+                for (int i = 0; i < g.NX; i++) {
+                    int ci[3] = { i, j, k };
+                    if (ci[d] < 1 || ci[d] > N[d] - 2) continue;
+                    long c = cidx(&g, i, j, k);
+                    long cp = cidx(&g, i + offs[d][0], j + offs[d][1], k + offs[d][2]);
+                    for (int q = 0; q < NVAR; q++) {
+                        Ln[(d * NVAR + q) * NC + c] = -(Fn[(d * NVAR + q) * NC + cp] - Fn[(d * NVAR + q) * NC + c]) / o->dx[d];
+                        LPn[(d * NVAR + q) * NC + c] = (Pn[(d * NVAR + q) * NC + cp] - Pn[(d * NVAR + q) * NC + c]) / o->dx[d];
+                    }
+                }
+    }
+
+    /* 4. normal predictors and corner coupling (Eq. transv) on cells one
+     * zone beyond the interior along d, interior across d */
+    for (int d = 0; d < dim; d++) {
+        int rlo[3], rhi[3];
+        for (int e = 0; e < 3; e++) { rlo[e] = lo[e]; rhi[e] = hi[e]; }
+        rlo[d] = lo[d] - 1;
+        rhi[d] = hi[d] + 1;
+        for (int k = rlo[2]; k < rhi[2]; k++)
+            for (int j = rlo[1]; j < rhi[1]; j++)
+                for (int i = rlo[0]; i < rhi[0]; i++) {
+                    long c = cidx(&g, i, j, k);
+                    double Vm[NVAR], Vp[NVAR];
+                    if (hyp) {
+                        double Vs[5][NVAR], U0[NVAR];
+                        for (int l = -2; l <= 2; l++) {
+                            int ii = i + l * offs[d][0], jj = j + l * offs[d][1], kk = k + l * offs[d][2];
+                            int inside = ii >= 0 && ii < g.NX && jj >= 0 && jj < g.NY && kk >= 0 && kk < g.NZ;
+                            long cl = inside ? cidx(&g, ii, jj, kk) : c;
+                            for (int q = 0; q < NVAR; q++) Vs[l + 2][q] = V[q * NC + cl];
+                        }
+                        for (int q = 0; q < NVAR; q++) U0[q] = U_in[q * NC + c];
+                        if (o->predictor == PRED_CHAR) predict_char(o, Vs, d, dt, ch, Vm, Vp);
+                        else predict_mh(o, Vs, U0, d, dt, ch, Vm, Vp, lf);
+                    } else {
+                        for (int q = 0; q < NVAR; q++) Vm[q] = Vp[q] = V[q * NC + c];
+                    }
+                    double Um[NVAR], Up[NVAR];
+                    prim2cons(o, Vm, Um);
+                    prim2cons(o, Vp, Up);
+                    for (int q = 0; q < NVAR; q++) {
+                        double tr = 0.0;
+                        for (int e = 0; e < dim; e++) {
+                            if (e != d) tr += Ln[(e * NVAR + q) * NC + c];
+                            tr += LPn[(e * NVAR + q) * NC + c];
+                        }
+                        Uhm[(d * NVAR + q) * NC + c] = Um[q] + 0.5 * dt * tr;
+                        Uhp[(d * NVAR + q) * NC + c] = Up[q] + 0.5 * dt * tr;
+                    }
+                }
+    }
+
+    /* 5. time-centred Riemann fluxes (Eq. ctu_flux) on interior-adjacent faces */
+    for (int d = 0; d < dim; d++) {
+        int rlo[3], rhi[3];
+        for (int e = 0; e < 3; e++) { rlo[e] = lo[e]; rhi[e] = hi[e]; }
+        rhi[d] = hi[d] + 1;
+        for (int k = rlo[2]; k < rhi[2]; k++)
+            for (int j = rlo[1]; j < rhi[1]; j++)
+                for (int i = rlo[0]; i < rhi[0]; i++) {
+                    long cB = cidx(&g, i, j, k);
+                    long cA = cidx(&g, i - offs[d][0], j - offs[d][1], k - offs[d][2]);
+                    double UL[NVAR], UR[NVAR], VL[NVAR], VR[NVAR], F[NVAR], sm = 0.0;
+                    for (int q = 0; q < NVAR; q++) {
+                        UL[q] = Uhp[(d * NVAR + q) * NC + cA];
+                        UR[q] = Uhm[(d * NVAR + q) * NC + cB];
+                    }
+                    /* an unphysical corner-coupled state falls back to the
+                     * cell-centred primitive state of its cell (first order) */
+                    int zl[NFAIL] = { 0 }, zr[NFAIL] = { 0 }, bl = 0, br = 0;
+                    cons2prim(o, UL, VL, zl);
+                    cons2prim(o, UR, VR, zr);
+                    for (int q = 0; q < NFAIL; q++) {
+                        lf[q] += zl[q] + zr[q];
+                        bl |= zl[q];
+                        br |= zr[q];
+                    }
+                    if (bl) for (int q = 0; q < NVAR; q++) VL[q] = V[q * NC + cA];
+                    if (br) for (int q = 0; q < NVAR; q++) VR[q] = V[q * NC + cB];
+                    if (hyp) {
+                        riemann(o, VL, VR, d, ch, F, &sm);
+                    } else {
+                        for (int q = 0; q < NVAR; q++) F[q] = 0.0;
+                    }
+                    for (int q = 0; q < NVAR; q++) Fh[(d * NVAR + q) * NC + cB] = F[q];
+                    lamf[d * NC + cB] = sm;
+                    pfL[d * NC + cB] = VL[PRS];
+                    pfR[d * NC + cB] = VR[PRS];
+                    rfL[d * NC + cB] = VL[RHO];
+                    rfR[d * NC + cB] = VR[RHO];
+                }
+    }
+
+    /* 6. parabolic fluxes at the half step from the cell-centred U^{n+1/2} */
+    if (par) {
+        memcpy(Uhalf, U_in, sizeof(double) * NVAR * NC);
+        int rlo[3], rhi[3];
+        for (int e = 0; e < 3; e++) {
+            rlo[e] = lo[e] - (e < dim ? 1 : 0);
+            rhi[e] = hi[e] + (e < dim ? 1 : 0);
+        }
+        for (int k = rlo[2]; k < rhi[2]; k++)
+            for (int j = rlo[1]; j < rhi[1]; j++)
+                for (int i = rlo[0]; i < rhi[0]; i++) {
+                    long c = cidx(&g, i, j, k);
+                    for (int q = 0; q < NVAR; q++) {
+                        double s = 0.0;
+                        for (int e = 0; e < dim; e++) s += Ln[(e * NVAR + q) * NC + c] + LPn[(e * NVAR + q) * NC + c];
+                        Uhalf[q * NC + c] = U_in[q * NC + c] + 0.5 * dt * s;
+                    }
+                }
+        for (long c = 0; c < NC; c++) {
+            double u[NVAR], v[NVAR];
+            for (int q = 0; q < NVAR; q++) u[q] = Uhalf[q * NC + c];
+            cons2prim(o, u, v, NULL);
+            for (int q = 0; q < NVAR; q++) Vhalf[q * NC + c] = v[q];
+        }
+        for (int d = 0; d < dim; d++) {
+            int flo[3], fhi[3];
+            for (int e = 0; e < 3; e++) { flo[e] = lo[e]; fhi[e] = hi[e]; }
+            fhi[d] = hi[d] + 1;
+            for (int k = flo[2]; k < fhi[2]; k++)
+                for (int j = flo[1]; j < fhi[1]; j++)
+                    for (int i = flo[0]; i < fhi[0]; i++) {
+                        long cB = cidx(&g, i, j, k);
+                        double Pi[NVAR];
+                        parab_flux(o, &g, Vhalf, Uhalf, i, j, k, d, pfL[d * NC + cB], pfR[d * NC + cB],
+                                   rfL[d * NC + cB], rfR[d * NC + cB], Pi);
+                        for (int q = 0; q < NVAR; q++) Ph[(d * NVAR + q) * NC + cB] = Pi[q];
+                    }
+        }
+    }
+
+    /* 7. conservative update (Eq. update), directions summed in order */
+    memcpy(U_out, U_in, sizeof(double) * NVAR * NC);
+    double rate = 0.0, dpp = 0.0;
+    double dxmin = o->dx[0];
+    for (int e = 1; e < dim; e++) dxmin = fmin(dxmin, o->dx[e]);
+    for (int k = lo[2]; k < hi[2]; k++)
+        for (int j = lo[1]; j < hi[1]; j++)
+            for (int i = lo[0]; i < hi[0]; i++) {
+                long c = cidx(&g, i, j, k);
+                double u[NVAR];
+                for (int q = 0; q < NVAR; q++) {
+                    double s = 0.0;
+                    for (int d = 0; d < dim; d++) {
+                        long cp = cidx(&g, i + offs[d][0], j + offs[d][1], k + offs[d][2]);
+                        double dF = Fh[(d * NVAR + q) * NC + cp] - Fh[(d * NVAR + q) * NC + c];
+                        double dP = Ph[(d * NVAR + q) * NC + cp] - Ph[(d * NVAR + q) * NC + c];
+                        s += (dF - dP) / o->dx[d];
+                    }
+                    u[q] = U_in[q * NC + c] - dt * s;
+                }
+                /* 8. operator-split point-local sources */
+                if (o->glm) u[PSI] *= exp(-o->glm_alpha * ch * dt / dxmin);
+                if (o->cooling && L0) {
+                    double v[NVAR];
+                    cons2prim(o, u, v, NULL);
+                    double T = v[PRS] / v[RHO];
+                    double beta = o->cool_beta;
+                    if (T > o->T_floor) {
+                        double x = pow(T, 1.0 - beta) - (1.0 - beta) * (o->gamma - 1.0) * v[RHO] * L0[c] * dt;
+                        double xf = pow(o->T_floor, 1.0 - beta);
+                        if (x < xf) x = xf;
+                        double Tn = pow(x, 1.0 / (1.0 - beta));
+                        double pn = v[RHO] * Tn;
+                        u[ENG] += (pn - v[PRS]) / (o->gamma - 1.0);
+                        dpp = fmax(dpp, fabs(pn - v[PRS]) / v[PRS]);
+                    }
+                }
+                for (int q = 0; q < NVAR; q++) U_out[q * NC + c] = u[q];
+
+                /* 9. CFL rate (Eq. Ca) */
+                double lmax = 0.0;
+                for (int d = 0; d < dim; d++) {
+                    long cp = cidx(&g, i + offs[d][0], j + offs[d][1], k + offs[d][2]);
+                    double lc = fmax(lamf[d * NC + c], lamf[d * NC + cp]);
+                    lmax = fmax(lmax, lc / o->dx[d]);
+                }
+                double r = lmax;
+                if (par) {
+                    double vh[NVAR];
+                    for (int q = 0; q < NVAR; q++) vh[q] = Vhalf[q * NC + c];
+                    double D = diff_coeff(o, vh);
+                    for (int d = 0; d < dim; d++) r += 2.0 * D / (o->dx[d] * o->dx[d]);
+                }
+                rate = fmax(rate, r);
+            }
+
+    if (face_flux) {
+        memset(face_flux, 0, sizeof(double) * dim * NVAR * NC);
+        for (int d = 0; d < dim; d++) {
+            int rlo[3], rhi[3];
+            for (int e = 0; e < 3; e++) { rlo[e] = lo[e]; rhi[e] = hi[e]; }
+            rhi[d] = hi[d] + 1;
+            for (int k = rlo[2]; k < rhi[2]; k++)
+                for (int j = rlo[1]; j < rhi[1]; j++)
+                    for (int i = rlo[0]; i < rhi[0]; i++) {
+                        long c = cidx(&g, i, j, k);
+                        for (int q = 0; q < NVAR; q++)
+                            face_flux[(d * NVAR + q) * NC + c] =
+                                dt * (Fh[(d * NVAR + q) * NC + c] - Ph[(d * NVAR + q) * NC + c]);
+                    }
+        }
+    }
+    if (out_scalars) { out_scalars[0] = rate; out_scalars[1] = dpp; }
+    if (fails) for (int k = 0; k < NFAIL; k++) fails[k] += lf[k];
+
+    free(V); free(Fn); free(Pn); free(Ln); free(LPn); free(Uhm); free(Uhp); free(Fh); free(Ph);
+    free(lamf); free(pfL); free(pfR); free(rfL); free(rfR); free(Uhalf); free(Vhalf);
+    return 0;
+}
+
+/* CFL rate from cell-centred states: max over cells of max_d (|v_d| + c_f)/dx_d
+ * for MHD, max_d max(|lambda_-|, |lambda_+|)/dx_d for RMHD, plus the
+ * diffusion term of Eq. Ca.  Interior cells only. */
+double orc_cfl_rate(const orc_opts *o, int nx, int ny, int nz, int ng, const double *U)
+{
+    int gz = (o->dim == 3) ? ng : 0;
+    grid_t g;
+    g.NX = nx + 2 * ng;
+    g.NY = ny + 2 * ng;
+    g.NZ = nz + 2 * gz;
+    g.NC = (long)g.NX * g.NY * g.NZ;
+    double rate = 0.0;
+    for (int k = gz; k < gz + nz; k++)
+        for (int j = ng; j < ng + ny; j++)
+            for (int i = ng; i < ng + nx; i++) {
+                long c = cidx(&g, i, j, k);
+                double u[NVAR], v[NVAR];
+                for (int q = 0; q < NVAR; q++) u[q] = U[q * g.NC + c];
+                cons2prim(o, u, v, NULL);
+                double r = 0.0;
+                for (int d = 0; d < o->dim; d++) {
+                    double lm, lp;
+                    signal_speeds(o, v, d, &lm, &lp);
+                    r = fmax(r, fmax(fabs(lm), fabs(lp)) / o->dx[d]);
+                }
+                double D = diff_coeff(o, v);
+                for (int d = 0; d < o->dim; d++) r += 2.0 * D / (o->dx[d] * o->dx[d]);
+                rate = fmax(rate, r);
+            }
+    return rate;
+}

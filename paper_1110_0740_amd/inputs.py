@@ -1,0 +1,352 @@
+"""Seeded synthetic inputs shared by the oracle tests, the GPU tests and the bench.
+
+This module holds no arithmetic of the method itself: it draws random mode
+parameters with a counter-free SplitMix64 stream, evaluates smooth periodic
+fields (sums of Fourier modes, analytic curls, compact blob profiles) at cell
+centres, and copies ghost zones by index wrapping.  Primitive fields come out
+as float64 arrays ``V[9, NZ, NY, NX]`` over the ghosted box, in the order
+(rho, v_x, v_y, v_z, p, B_x, B_y, B_z, psi); each side converts them to
+conserved variables with its own routines.
+
+Workload recipes (Sec. 5 / Sec. 6 style smooth MHD and RMHD states):
+  * 2D ideal MHD, 128^2, Gamma = 5/3  -> :func:`mhd2d_fields`
+  * 3D ideal MHD, 256^3 (beta ~ 1, Mach ~ 1) -> :func:`mhd3d_fields`
+  * 3D relativistic MHD jets/blobs, Gamma = 4/3 -> :func:`rmhd3d_fields`
+  * 3D non-ideal MHD with per-cell cooling times -> :func:`mhd3d_fields` +
+    :func:`cooling_time_field`
+  * 3D AMR patch hierarchy around density blobs -> :func:`amr_hierarchy`
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+MASK64 = (1 << 64) - 1
+NVAR = 9
+RHO, VX1, VX2, VX3, PRS, BX1, BX2, BX3, PSI = range(9)
+
+
+class SplitMix64:
+    """SplitMix64 (Steele, Lea & Flood 2014): state += golden gamma, then a
+    two-round xor-shift-multiply finaliser."""
+
+    def __init__(self, seed: int):
+        self.state = seed & MASK64
+
+    def next_u64(self) -> int:
+        self.state = (self.state + 0x9E3779B97F4A7C15) & MASK64
+        z = self.state
+        z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & MASK64
+        z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & MASK64
+        return z ^ (z >> 31)
+
+    def uniform(self) -> float:
+        """Uniform on [0, 1) with 53 random bits."""
+        return (self.next_u64() >> 11) * (1.0 / (1 << 53))
+
+    def randint(self, lo: int, hi: int) -> int:
+        """Uniform integer in [lo, hi]."""
+        return lo + int(self.uniform() * (hi - lo + 1))
+
+    def normal(self) -> float:
+        u1 = max(self.uniform(), 1e-300)
+        u2 = self.uniform()
+        return math.sqrt(-2.0 * math.log(u1)) * math.cos(2.0 * math.pi * u2)
+
+
+@dataclass
+class Modes:
+    """A sum of ``len(k)`` cosine modes with weights ``amp``:
+    S(x) = sum_m amp_m cos(2 pi k_m . x + phi_m)."""
+
+    k: np.ndarray  # (M, 3) integers
+    phi: np.ndarray  # (M,)
+    amp: np.ndarray  # (M,)
+
+    def rms(self) -> float:
+        return float(math.sqrt(0.5 * float(np.sum(self.amp ** 2))))
+
+
+def draw_modes(rng: SplitMix64, dim: int, nmodes: int = 8, kmax: float = 4.0) -> Modes:
+    """Integer wave vectors with 0 < |k| <= kmax (k_z = 0 in 2D), uniform
+    phases, equal weights 1/nmodes so that |S| <= 1."""
+    ks, phis = [], []
+    kr = int(math.floor(kmax))
+    while len(ks) < nmodes:
+        k = [rng.randint(-kr, kr), rng.randint(-kr, kr), rng.randint(-kr, kr) if dim == 3 else 0]
+        n2 = k[0] ** 2 + k[1] ** 2 + k[2] ** 2
+        if n2 == 0 or n2 > kmax * kmax:
+            continue
+        ks.append(k)
+        phis.append(2.0 * math.pi * rng.uniform())
+    return Modes(np.array(ks, dtype=np.int64), np.array(phis), np.full(nmodes, 1.0 / nmodes))
+
+
+def mode_sum(m: Modes, X, Y, Z):
+    out = np.zeros(np.broadcast(X, Y, Z).shape)
+    for k, ph, a in zip(m.k, m.phi, m.amp):
+        out += a * np.cos(2.0 * math.pi * (k[0] * X + k[1] * Y + k[2] * Z) + ph)
+    return out
+
+
+def mode_grad(m: Modes, X, Y, Z):
+    """Analytic gradient (dS/dx, dS/dy, dS/dz)."""
+    shape = np.broadcast(X, Y, Z).shape
+    g = [np.zeros(shape), np.zeros(shape), np.zeros(shape)]
+    for k, ph, a in zip(m.k, m.phi, m.amp):
+        s = np.sin(2.0 * math.pi * (k[0] * X + k[1] * Y + k[2] * Z) + ph)
+        for c in range(3):
+            g[c] -= a * 2.0 * math.pi * k[c] * s
+    return g
+
+
+def curl_rms(A: list[Modes]) -> float:
+    """Analytic rms of curl(A) for A = (Ax, Ay, Az) mode sums, counting each
+    mode's mean square independently."""
+    tot = 0.0
+    for c, m in enumerate(A):
+        if m is None:
+            continue
+        for k, a in zip(m.k, m.amp):
+            kk = (2.0 * math.pi) ** 2 * (float(np.dot(k, k)) - float(k[c]) ** 2)
+            tot += 0.5 * a * a * kk
+    return math.sqrt(tot)
+
+
+@dataclass
+class Box:
+    """Interior index box on one level: lo (global cell index), n (extent)."""
+
+    lo: tuple
+    n: tuple
+    level: int = 0
+
+
+def cell_centres(box: Box, ng: int, dx: tuple, dim: int):
+    """Cell-centre coordinates of the ghosted box (periodic unit domain,
+    cell i covers [i dx, (i+1) dx))."""
+    gz = ng if dim == 3 else 0
+    ax = []
+    for d in range(3):
+        g = ng if d < dim else gz
+        if d >= dim:
+            ax.append(np.array([0.5 * dx[d]]))
+            continue
+        idx = np.arange(box.lo[d] - g, box.lo[d] + box.n[d] + g)
+        ax.append((idx + 0.5) * dx[d])
+    Z, Y, X = np.meshgrid(ax[2], ax[1], ax[0], indexing="ij")
+    return X, Y, Z
+
+
+# --------------------------------------------------------------------------
+# Workload recipes
+# --------------------------------------------------------------------------
+
+
+def mhd2d_fields(n: int = 128, ng: int = 4, seed: int = 1000, box: Box | None = None):
+    """2D ideal MHD, Gamma = 5/3, periodic unit square: rho = 1 + 0.2 S,
+    p = 1 + 0.2 S', each velocity component 0.5 S, B_z = 0.5 S, and
+    (B_x, B_y) = 0.5 curl(A_z z) / bound, where bound majorises |curl A_z|."""
+    rng = SplitMix64(seed)
+    dim = 2
+    m = {name: draw_modes(rng, dim) for name in ("rho", "p", "vx", "vy", "vz", "Az", "Bz")}
+    if box is None:
+        box = Box((0, 0, 0), (n, n, 1))
+    dx = (1.0 / n, 1.0 / n, 1.0)
+    X, Y, Z = cell_centres(box, ng, dx, dim)
+    V = np.zeros((NVAR,) + X.shape)
+    V[RHO] = 1.0 + 0.2 * mode_sum(m["rho"], X, Y, Z)
+    V[PRS] = 1.0 + 0.2 * mode_sum(m["p"], X, Y, Z)
+    V[VX1] = 0.5 * mode_sum(m["vx"], X, Y, Z)
+    V[VX2] = 0.5 * mode_sum(m["vy"], X, Y, Z)
+    V[VX3] = 0.5 * mode_sum(m["vz"], X, Y, Z)
+    gAx, gAy, _ = mode_grad(m["Az"], X, Y, Z)
+    bound = sum(a * 2.0 * math.pi * math.sqrt(float(np.dot(k, k))) for k, a in zip(m["Az"].k, m["Az"].amp))
+    V[BX1] = 0.5 * gAy / bound
+    V[BX2] = -0.5 * gAx / bound
+    V[BX3] = 0.5 * mode_sum(m["Bz"], X, Y, Z)
+    return V, dict(dim=2, gamma=5.0 / 3.0, dx=dx, box=box, ng=ng)
+
+
+def mhd3d_fields(n: int = 256, ng: int = 4, seed: int = 2000, box: Box | None = None, level_n: int | None = None,
+                 v_rms: float = 1.0, b_rms: float | None = None):
+    """3D ideal MHD, Gamma = 5/3, periodic unit cube: rho = 1 + 0.5 S in
+    [0.5, 1.5], p = 0.6 (1 + 0.2 S'), velocity components scaled to a total
+    rms of v_rms (Mach ~ 1 for v_rms = 1, c_s ~ 1), B = curl A scaled to
+    rms sqrt(2 * 0.6) (plasma beta ~ 1)."""
+    rng = SplitMix64(seed)
+    dim = 3
+    m = {name: draw_modes(rng, dim) for name in ("rho", "p", "vx", "vy", "vz", "Ax", "Ay", "Az")}
+    N = level_n if level_n is not None else n
+    if box is None:
+        box = Box((0, 0, 0), (n, n, n))
+    dx = (1.0 / N, 1.0 / N, 1.0 / N)
+    X, Y, Z = cell_centres(box, ng, dx, dim)
+    V = np.zeros((NVAR,) + X.shape)
+    V[RHO] = 1.0 + 0.5 * mode_sum(m["rho"], X, Y, Z)
+    V[PRS] = 0.6 * (1.0 + 0.2 * mode_sum(m["p"], X, Y, Z))
+    for c, name in enumerate(("vx", "vy", "vz")):
+        V[VX1 + c] = (v_rms / math.sqrt(3.0)) / m[name].rms() * mode_sum(m[name], X, Y, Z)
+    A = [m["Ax"], m["Ay"], m["Az"]]
+    if b_rms is None:
+        b_rms = math.sqrt(2.0 * 0.6)
+    scale = b_rms / curl_rms(A)
+    g = [mode_grad(a, X, Y, Z) for a in A]
+    V[BX1] = scale * (g[2][1] - g[1][2])
+    V[BX2] = scale * (g[0][2] - g[2][0])
+    V[BX3] = scale * (g[1][0] - g[0][1])
+    return V, dict(dim=3, gamma=5.0 / 3.0, dx=dx, box=box, ng=ng)
+
+
+def cooling_time_field(seed: int, X, Y, Z, dt0: float, dim: int = 3):
+    """Per-cell cooling time t_c = dt0 * 10^(3 S_c) (t_c / dt0 in [1e-3, 1e3])."""
+    rng = SplitMix64(seed)
+    m = draw_modes(rng, dim)
+    return dt0 * 10.0 ** (3.0 * mode_sum(m, X, Y, Z))
+
+
+def nonideal_coeffs(seed: int):
+    """nu, eta, kappa_par, kappa_perp ~ log-uniform on [1e-4, 1e-2], with
+    kappa_perp <= kappa_par."""
+    rng = SplitMix64(seed)
+    draw = lambda: 10.0 ** (-4.0 + 2.0 * rng.uniform())
+    nu, eta, k1, k2 = draw(), draw(), draw(), draw()
+    return dict(nu=nu, eta=eta, kappa_par=max(k1, k2), kappa_perp=min(k1, k2))
+
+
+def rmhd3d_fields(n: int = 192, ng: int = 4, seed: int = 4000, box: Box | None = None, gmax_cap: float = 10.0):
+    """3D relativistic MHD, Gamma = 4/3, periodic unit cube.  Background
+    rho = 1, p = 0.1.  Two periodic cylindrical jets along seeded axes and six
+    spherical blobs, each with the C^1 profile P = (1 - (r/R)^2)^2, radius
+    R in [0.05, 0.12], central density in [0.1, 1] and central Lorentz
+    factor g_max in [2, 10] (the first equal to the cap): log(rho) and the
+    spatial 4-velocity sqrt(g_max^2 - 1) P d (d the object's direction) add
+    over overlapping objects.  B = uniform + mode sum, scaled so that max b^2/w = 1 would hold
+    at the background state."""
+    rng = SplitMix64(seed)
+    dim = 3
+    if box is None:
+        box = Box((0, 0, 0), (n, n, n))
+    dx = (1.0 / n, 1.0 / n, 1.0 / n)
+    X, Y, Z = cell_centres(box, ng, dx, dim)
+    shape = X.shape
+    prs = np.full(shape, 0.1)
+    objs = []
+    for j in range(8):
+        kind = "jet" if j < 2 else "blob"
+        c = np.array([rng.uniform(), rng.uniform(), rng.uniform()])
+        R = 0.05 + 0.07 * rng.uniform()
+        dens = 0.1 + 0.9 * rng.uniform()
+        gmax = gmax_cap if j == 0 else 2.0 + (gmax_cap - 2.0) * rng.uniform()
+        axis = rng.randint(0, 2)
+        # direction of motion: along the jet axis, random for blobs
+        if kind == "jet":
+            dvec = np.zeros(3)
+            dvec[axis] = 1.0 if rng.uniform() < 0.5 else -1.0
+        else:
+            dvec = np.array([rng.normal(), rng.normal(), rng.normal()])
+            dvec /= np.linalg.norm(dvec)
+        objs.append((kind, c, R, dens, gmax, axis, dvec))
+    # smooth superposition: log-density and spatial 4-velocity u = gamma v
+    # add up the objects' profiles, so the fields stay C^1 where they overlap
+    logrho = np.zeros(shape)
+    u = np.zeros((3,) + shape)
+    for kind, c, R, dens, gmax, axis, dvec in objs:
+        d = []
+        for q, Q in enumerate((X, Y, Z)):
+            t = Q - c[q]
+            t = t - np.round(t)  # periodic minimum image
+            d.append(t)
+        if kind == "jet":
+            r2 = sum(d[q] ** 2 for q in range(3) if q != axis)
+        else:
+            r2 = d[0] ** 2 + d[1] ** 2 + d[2] ** 2
+        x = np.clip(r2 / (R * R), 0.0, 1.0)
+        prof = (1.0 - x) ** 2
+        logrho += math.log(dens) * prof
+        umax = math.sqrt(gmax * gmax - 1.0)
+        for q in range(3):
+            u[q] += umax * prof * dvec[q]
+    umag = np.sqrt(u[0] ** 2 + u[1] ** 2 + u[2] ** 2)
+    ucap = math.sqrt(gmax_cap * gmax_cap - 1.0)
+    fac = np.where(umag > ucap, ucap / np.maximum(umag, 1e-300), 1.0)
+    u *= fac
+    lor = np.sqrt(1.0 + u[0] ** 2 + u[1] ** 2 + u[2] ** 2)
+    rho = np.exp(logrho)
+    vel = u / lor
+    V = np.zeros((NVAR,) + shape)
+    V[RHO] = rho
+    V[PRS] = prs
+    V[VX1:VX1 + 3] = vel
+    # magnetic field: uniform part + divergence-free mode sum, magnetization <= 1
+    G = 4.0 / 3.0
+    w_bg = 1.0 + G * 0.1 / (G - 1.0)
+    b0 = math.sqrt(0.5 * w_bg)
+    th = math.acos(2.0 * rng.uniform() - 1.0)
+    ph = 2.0 * math.pi * rng.uniform()
+    B0 = b0 * np.array([math.sin(th) * math.cos(ph), math.sin(th) * math.sin(ph), math.cos(th)])
+    A = [draw_modes(rng, dim) for _ in range(3)]
+    scale = 0.5 * b0 / curl_rms(A)
+    g = [mode_grad(a, X, Y, Z) for a in A]
+    V[BX1] = B0[0] + scale * (g[2][1] - g[1][2])
+    V[BX2] = B0[1] + scale * (g[0][2] - g[2][0])
+    V[BX3] = B0[2] + scale * (g[1][0] - g[0][1])
+    return V, dict(dim=3, gamma=G, dx=dx, box=box, ng=ng)
+
+
+# --------------------------------------------------------------------------
+# Ghost zones (pure index copies)
+# --------------------------------------------------------------------------
+
+
+def fill_periodic(U: np.ndarray, ng: int, dim: int) -> None:
+    """Copy periodic images into the ghost zones of one ghosted box in place
+    (arrays shaped [..., NZ, NY, NX])."""
+    axes = [-1, -2, -3][:dim]
+    for ax in axes:
+        n = U.shape[ax] - 2 * ng
+        sl = [slice(None)] * U.ndim
+        src = [slice(None)] * U.ndim
+        sl[ax] = slice(0, ng)
+        src[ax] = slice(n, n + ng)
+        U[tuple(sl)] = U[tuple(src)]
+        sl[ax] = slice(n + ng, n + 2 * ng)
+        src[ax] = slice(ng, 2 * ng)
+        U[tuple(sl)] = U[tuple(src)]
+
+
+def fill_outflow(U: np.ndarray, ng: int, dim: int) -> None:
+    """Zero-gradient ghost zones (copy of the nearest interior cell)."""
+    axes = [-1, -2, -3][:dim]
+    for ax in axes:
+        n = U.shape[ax] - 2 * ng
+        for g in range(ng):
+            sl = [slice(None)] * U.ndim
+            src = [slice(None)] * U.ndim
+            sl[ax] = slice(g, g + 1)
+            src[ax] = slice(ng, ng + 1)
+            U[tuple(sl)] = U[tuple(src)]
+            sl[ax] = slice(n + ng + g, n + ng + g + 1)
+            src[ax] = slice(n + ng - 1, n + ng)
+            U[tuple(sl)] = U[tuple(src)]
+
+
+def interior(a: np.ndarray, ng: int, dim: int) -> np.ndarray:
+    sl = [slice(None)] * a.ndim
+    for q, ax in enumerate([-1, -2, -3]):
+        if q < dim:
+            sl[ax] = slice(ng, a.shape[ax] - ng)
+    return a[tuple(sl)]
+
+
+def sub_box(a: np.ndarray, lo: tuple, n: tuple, ng: int, dim: int) -> np.ndarray:
+    """Extract the ghosted sub-box whose interior starts at interior index lo
+    (relative to the big box's interior) with extent n, from a ghosted array."""
+    sl = [slice(None)] * a.ndim
+    for q, ax in enumerate([-1, -2, -3]):
+        if q < dim:
+            s = lo[q]
+            sl[ax] = slice(s, s + n[q] + 2 * ng)
+    return np.ascontiguousarray(a[tuple(sl)])
