@@ -1,0 +1,217 @@
+/*
+ * ctu.h -- C ABI of the MI355X (gfx950) CTU-GLM step library (libctu.so).
+ *
+ * One call advances every patch of a batch by one dimensionally unsplit
+ * Corner Transport Upwind step with GLM divergence cleaning, as defined in
+ * Mignone et al. (ApJS 2012), Sec. 3.1 (Eq. update, ctu_flux, transv, Ca):
+ * a conserved state U on ghosted boxes, dt, the EOS and the solver options
+ * go in; the updated interior U, fine/coarse flux-register increments and the
+ * maximum signal rate of Eq. Ca come out.  Ghost zones are filled by the
+ * caller (Sec. 4: physical boundaries, same-level exchange, coarse
+ * interpolation).
+ *
+ * Conventions shared by every entry point
+ *  - All pointers named *_dev are device pointers (hipMalloc / torch CUDA
+ *    tensors) owned by the caller; the library never frees them.
+ *  - Host pointers (options, box and register tables) are read during the
+ *    call only.
+ *  - Calls are asynchronous on the given HIP stream (NULL = default
+ *    stream); results are valid after the stream is synchronised.
+ *  - Every function returns a ctu_status: 0 on success, < 0 on a
+ *    synchronous error (bad argument, unsupported option combination, HIP
+ *    launch or allocation failure).  ctu_last_error() then returns a
+ *    message (thread-local).  Physical failures inside kernels never abort:
+ *    they are counted (see ctu_step).
+ *  - A plan is used by one stream at a time: calls that overlap on two
+ *    streams with the same plan race on its workspace.
+ *
+ * Variables (9 per cell, SoA):
+ *   conserved   (rho | D, m_x, m_y, m_z, E, B_x, B_y, B_z, psi)
+ *   primitive   (rho, v_x, v_y, v_z, p, B_x, B_y, B_z, psi)
+ * MHD (Sec. 2.1): E = p/(Gamma-1) + rho v^2/2 + B^2/2.
+ * RMHD (Sec. 2.2): D = rho gamma, m = w gamma^2 v + E x B,
+ *   E = w gamma^2 - p + (B^2 + E_field^2)/2 - D, w = rho + Gamma p/(Gamma-1).
+ *
+ * State layout: box b occupies elements [offset_b, offset_b + 9*NX*NY*NZ)
+ * of the state array as q[v][k][j][i] (i fastest) over its ghosted extent
+ * NX = n_x + 2g, NY = n_y + 2g, NZ = n_z + 2g (NZ = n_z = 1 in 2D).  The
+ * element type is double for CTU_FP64 and float for CTU_FP32.
+ */
+#ifndef CTU_H
+#define CTU_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t ctu_status;
+enum {
+    CTU_OK = 0,
+    CTU_ERR_ARG = -1,         /* invalid argument or table entry */
+    CTU_ERR_UNSUPPORTED = -2, /* option combination not implemented */
+    CTU_ERR_HIP = -3,         /* HIP runtime error (launch, copy) */
+    CTU_ERR_NOMEM = -4        /* device allocation failed */
+};
+
+typedef enum { CTU_MHD = 0, CTU_RMHD = 1 } ctu_physics;
+/* FP32: state, reconstruction, Riemann solves and update in float; the RMHD
+ * conserved-to-primitive inversion, the CFL maximum and the flux registers
+ * stay in double.  FP64: everything in double. */
+typedef enum { CTU_FP64 = 0, CTU_FP32 = 1 } ctu_precision;
+/* Sec. 3.2: linear with the MC (Eq. MClim), MinMod (Eq. minmod), harmonic
+ * (Eq. harmonic_lim) or van Albada (Eq. vanalbada_lim) limiter; PPM (Eq.
+ * ppm1 + Eq. ppm_parabolic_lim); improved WENO3 (Eq. WENO3, WENO3a). */
+typedef enum {
+    CTU_LIN_MC = 0, CTU_LIN_MINMOD = 1, CTU_LIN_VANLEER = 2, CTU_LIN_VANALBADA = 3,
+    CTU_PPM = 4, CTU_WENO3 = 5
+} ctu_recon;
+/* Sec. 3.2 characteristic tracing (MHD only) or Sec. 3.3 MUSCL-Hancock
+ * (linear reconstructions only; the RMHD predictor). */
+typedef enum { CTU_PRED_CHAR = 0, CTU_PRED_MUSCL_HANCOCK = 1 } ctu_predictor;
+/* Reference state of Eq. wnorm_predp/m: w_ref = w_{i,+-} (FACE, default),
+ * w_{i,0} (CELL) or the nu_max / nu_min form (CW84). */
+typedef enum { CTU_WREF_FACE = 0, CTU_WREF_CELL = 1, CTU_WREF_CW84 = 2 } ctu_wref;
+/* Sec. 3.1: HLLD (MHD) or HLL (MHD, RMHD). */
+typedef enum { CTU_HLLD = 0, CTU_HLL = 1 } ctu_riemann;
+
+#define CTU_PARAB_VISC 1u /* Eq. visc_tens */
+#define CTU_PARAB_RES 2u  /* resistive term -curl(eta J) */
+#define CTU_PARAB_TC 4u   /* Eq. tc_flux with the App. A saturated flux */
+
+#define CTU_NFAIL 5 /* failure counters: rho<=0, p<=0, RMHD inversion, |v|>=1, NaN */
+
+typedef struct {
+    int32_t dim;           /* 2 or 3 (vectors always have 3 components) */
+    int32_t physics;       /* ctu_physics */
+    int32_t precision;     /* ctu_precision */
+    int32_t recon;         /* ctu_recon */
+    int32_t predictor;     /* ctu_predictor */
+    int32_t wref;          /* ctu_wref */
+    int32_t riemann;       /* ctu_riemann */
+    int32_t glm;           /* 1: GLM cleaning (Eq. glm2x2); 0: B_n averaged at faces */
+    double gamma;          /* specific heat ratio of the ideal EOS */
+    double dx[3];          /* level-0 cell size; a box on level l uses dx / 2^l */
+    double glm_alpha;      /* psi damping: psi *= exp(-alpha c_h dt / min dx) */
+    uint32_t parabolic_mask; /* CTU_PARAB_* bits; 0 = no parabolic terms */
+    int32_t cooling;       /* 1: optically thin cooling source (needs cool_L0) */
+    double nu, eta;        /* kinematic viscosity, scalar resistivity */
+    double kappa_par, kappa_perp; /* conduction coefficients along / across B */
+    double tc_phi;         /* saturation parameter phi; <= 0: classical flux */
+    double cool_beta;      /* Lambda = L0 rho^2 T^beta for T > T_floor, T = p/rho */
+    double T_floor;
+    int32_t hyperbolic_off; /* 1: skip hyperbolic fluxes (isolates Pi / sources) */
+    int32_t pad;
+} ctu_opts;
+
+/* One ghosted box: interior cells [lo, lo+n) in level-global indices. */
+typedef struct {
+    int32_t lo[3];
+    int32_t n[3];   /* n[2] = 1 in 2D */
+    int32_t level;  /* refinement level (cell size dx / 2^level) */
+    int32_t pad;
+    int64_t offset; /* element offset of the box's block in the state arrays */
+} ctu_box;
+
+/* A rectangle of faces of one box whose dt*A*(F - Pi) is accumulated into
+ * the FP64 register array (Sec. 4, Eq. fluxcorr): the faces normal to
+ * direction dir at level-global face index `face` (the face between cells
+ * face-1 and face), covering transverse cells [tlo, tlo+tn) in the two other
+ * directions (ordered by increasing direction index; in 2D tn[1] = 1).
+ * Face (t0, t1) owns the 9 doubles at reg[9 * (slot + t1*tn[0] + t0) + v]. */
+typedef struct {
+    int32_t box, dir, face, pad;
+    int32_t tlo[2], tn[2];
+    int64_t slot;
+} ctu_regface;
+
+/* One coarse cell that receives a flux correction (Eq. addreflux):
+ * U_coarse[cell] += -side * (sum of fine register slots - coarse slot) / V,
+ * with V the coarse cell volume (so A/V = 1/dx_dir on the coarse level).
+ * side = +1 when the refined region lies on the cell's high face along the
+ * correction direction, -1 on its low face.  Several entries may name the
+ * same cell; they are applied by one thread per cell in table order. */
+typedef struct {
+    int32_t box;        /* coarse box */
+    int32_t i, j, k;    /* ghosted-local cell index inside that box */
+    int32_t dir;        /* direction normal to the corrected face */
+    int32_t side;       /* +1 / -1 */
+    int32_t nfine;      /* number of fine slots (r^(dim-1), at most 4) */
+    int32_t pad;
+    int64_t coarse_slot;
+    int64_t fine_slot[4];
+} ctu_refluxface;
+
+typedef struct ctu_plan ctu_plan;
+
+/* Create a plan for a batch of boxes (Sec. 3.1 applied to each patch of a
+ * level, Sec. 4).  Validates the options, uploads the box and register
+ * tables, builds the work decomposition and allocates the device workspace
+ * (the only allocating call).  nghost must be >= 3 (PPM needs 3, parabolic
+ * terms one more); box blocks must not overlap.  Returns CTU_ERR_UNSUPPORTED
+ * for PPM/WENO3 with MUSCL-Hancock, characteristic tracing with RMHD, or
+ * parabolic/cooling terms with RMHD. */
+ctu_status ctu_plan_create(const ctu_opts *opts, const ctu_box *boxes, int32_t nbox, int32_t nghost,
+                           const ctu_regface *regfaces, int32_t nreg, ctu_plan **plan_out);
+void ctu_plan_destroy(ctu_plan *plan);
+
+/* Number of state elements the plan addresses: max over boxes of
+ * offset + 9*NX*NY*NZ.  Device workspace bytes held by the plan. */
+int64_t ctu_plan_state_elems(const ctu_plan *plan);
+int64_t ctu_plan_workspace_bytes(const ctu_plan *plan);
+
+/* One CTU step (Sec. 3.1) of every box of the plan.
+ *  U_in_dev   : state at t^n with ghosts filled (read only)
+ *  U_out_dev  : receives U^{n+1} in every interior cell; ghost cells are left
+ *               untouched; must not alias U_in_dev
+ *  params_dev : device doubles {dt, c_h}; read by the kernels at run time, so
+ *               a captured graph can be replayed with new values
+ *  cool_L0_dev: per-cell cooling coefficient on the state layout (one
+ *               element per cell, no variable index; same element type as
+ *               the state), required when opts.cooling, else may be NULL
+ *  reg_dev    : FP64 register array, accumulated (+=), NULL if nreg == 0
+ *  rate_dev   : one double, set to the maximum over interior cells of
+ *               max_d(lambda_d/dx_d) + sum_d 2 D/dx_d^2 (Eq. Ca); the next
+ *               step is dt = C_a / rate
+ *  dpp_dev    : one double, max |dp/p| of the cooling step (Eq. dt_cool), or NULL
+ *  fails_dev  : CTU_NFAIL int32 counters, zeroed then incremented per failing
+ *               conversion, or NULL */
+ctu_status ctu_step(ctu_plan *plan, const void *U_in_dev, void *U_out_dev, const double *params_dev,
+                    const void *cool_L0_dev, double *reg_dev, double *rate_dev, double *dpp_dev,
+                    int32_t *fails_dev, void *stream);
+
+/* Capture ctu_step with the given arguments into a HIP graph owned by the
+ * plan (replacing a previous one), and replay it.  The graph holds no
+ * memset nodes; buffers are re-zeroed by kernels on every replay. */
+ctu_status ctu_step_graph_capture(ctu_plan *plan, const void *U_in_dev, void *U_out_dev,
+                                  const double *params_dev, const void *cool_L0_dev, double *reg_dev,
+                                  double *rate_dev, double *dpp_dev, int32_t *fails_dev, void *stream);
+ctu_status ctu_step_graph_launch(ctu_plan *plan, void *stream);
+
+/* Signal rate of Eq. Ca from cell-centred states (for the first dt):
+ * max over interior cells of max_d(|lambda_d|max / dx_d) + diffusion term. */
+ctu_status ctu_cfl_rate(ctu_plan *plan, const void *U_dev, double *rate_dev, void *stream);
+
+/* Elementwise maps over every ghosted cell of every box: primitive ->
+ * conserved and conserved -> primitive (Sec. 2; RMHD inversion in FP64). */
+ctu_status ctu_prim_to_cons(ctu_plan *plan, const void *V_dev, void *U_dev, void *stream);
+ctu_status ctu_cons_to_prim(ctu_plan *plan, const void *U_dev, void *V_dev, int32_t *fails_dev, void *stream);
+
+/* Refluxing at level synchronisation (Eq. fluxcorr, Eq. addreflux).
+ * ctu_plan_set_reflux uploads (and groups per coarse cell) a table of
+ * corrections for the boxes of this (coarse) plan, replacing any previous
+ * table; it allocates device memory.  ctu_reflux applies them to the coarse
+ * state in FP64 arithmetic; reg_dev holds both the coarse slots (dt*A*F of
+ * the coarse step) and the fine slots (dt*A*F summed over the fine
+ * substeps) that the table names. */
+ctu_status ctu_plan_set_reflux(ctu_plan *coarse_plan, const ctu_refluxface *faces, int32_t nfaces);
+ctu_status ctu_reflux(ctu_plan *coarse_plan, void *U_dev, const double *reg_dev, void *stream);
+
+const char *ctu_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CTU_H */

@@ -1,0 +1,807 @@
+// ctu_device.hpp -- device building blocks of the CTU-GLM step for gfx950.
+//
+// Everything here is a __device__ inline function templated on the working
+// precision R (float or double) and, where the cost matters, on the sweep
+// direction D so that every vector component is addressed with a compile-time
+// index (no scratch-memory indexing).  References are to Mignone et al.
+// (ApJS 2012) and to the published methods it relies on.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ctu {
+
+enum { RHO = 0, MX1 = 1, MX2 = 2, MX3 = 3, ENG = 4, BX1 = 5, BX2 = 6, BX3 = 7, PSI = 8, NV = 9 };
+enum { PRS = 4 };
+enum { PHYS_MHD = 0, PHYS_RMHD = 1 };
+enum { RK_LIN = 0, RK_PPM = 1, RK_WENO = 2 };            // reconstruction kinds
+enum { LIM_MC = 0, LIM_MINMOD = 1, LIM_VANLEER = 2, LIM_VANALBADA = 3 };
+enum { PRED_CHAR = 0, PRED_MH = 1 };
+enum { WREF_FACE = 0, WREF_CELL = 1, WREF_CW84 = 2 };
+enum { RS_HLLD = 0, RS_HLL = 1 };
+enum { F_RHO = 1, F_PRS = 2, F_INV = 4, F_VEL = 8, F_NAN = 16 };  // failure bits
+enum { PB_VISC = 1, PB_RES = 2, PB_TC = 4 };
+
+// Options as seen by the kernels (by value in every launch).
+struct KOpts {
+    int dim, limiter, wref, glm, parab, cooling, hyp_off, pad;
+    double gamma, glm_alpha, nu, eta, kpar, kperp, phi, cool_beta, T_floor;
+};
+
+// (normal, transverse, binormal) component indices of direction D.
+template <int D> struct Ax {
+    static constexpr int n = D, t = (D + 1) % 3, b = (D + 2) % 3;
+};
+
+template <typename R> __device__ __forceinline__ R sq(R x) { return x * x; }
+template <typename R> __device__ __forceinline__ R sgn0(R a) { return R((a > R(0)) - (a < R(0))); }
+template <typename R> __device__ __forceinline__ R sgn1(R a) { return a < R(0) ? R(-1) : R(1); }
+
+// ---------------------------------------------------------------------------
+// Ideal MHD (Sec. 2.1, Eq. mhd, ideal-gas closure)
+// ---------------------------------------------------------------------------
+
+template <typename R> __device__ __forceinline__ void p2c_mhd(const R *V, R *U, R gm1)
+{
+    R kin = V[RHO] * (sq(V[MX1]) + sq(V[MX2]) + sq(V[MX3]));
+    R mag = sq(V[BX1]) + sq(V[BX2]) + sq(V[BX3]);
+    U[RHO] = V[RHO];
+    U[MX1] = V[RHO] * V[MX1];
+    U[MX2] = V[RHO] * V[MX2];
+    U[MX3] = V[RHO] * V[MX3];
+    U[ENG] = V[PRS] / gm1 + R(0.5) * (kin + mag);
+    U[BX1] = V[BX1];
+    U[BX2] = V[BX2];
+    U[BX3] = V[BX3];
+    U[PSI] = V[PSI];
+}
+
+template <typename R> __device__ __forceinline__ int c2p_mhd(const R *U, R *V, R gm1)
+{
+    R rho = U[RHO];
+    R ir = R(1) / rho;
+    V[RHO] = rho;
+    V[MX1] = U[MX1] * ir;
+    V[MX2] = U[MX2] * ir;
+    V[MX3] = U[MX3] * ir;
+    V[BX1] = U[BX1];
+    V[BX2] = U[BX2];
+    V[BX3] = U[BX3];
+    V[PSI] = U[PSI];
+    R kin = U[MX1] * V[MX1] + U[MX2] * V[MX2] + U[MX3] * V[MX3];
+    R mag = sq(U[BX1]) + sq(U[BX2]) + sq(U[BX3]);
+    V[PRS] = gm1 * (U[ENG] - R(0.5) * (kin + mag));
+    int f = 0;
+    if (!(rho > R(0))) f |= F_RHO;
+    if (!(V[PRS] > R(0))) f |= F_PRS;
+    if (isnan(V[PRS]) || isnan(V[MX1] + V[MX2] + V[MX3])) f |= F_NAN;
+    return f;
+}
+
+// fast magnetosonic speed along D
+template <int D, typename R> __device__ __forceinline__ R cfast_mhd(const R *V, R gam)
+{
+    R ir = R(1) / V[RHO];
+    R a2 = gam * V[PRS] * ir;
+    R b2 = (sq(V[BX1]) + sq(V[BX2]) + sq(V[BX3])) * ir;
+    R bn2 = sq(V[BX1 + D]) * ir;
+    R s = a2 + b2;
+    R disc = s * s - R(4) * a2 * bn2;
+    disc = disc > R(0) ? disc : R(0);
+    return sqrt(R(0.5) * (s + sqrt(disc)));
+}
+
+// conserved state and hyperbolic flux along D (GLM rows left to the caller)
+template <int D, typename R> __device__ __forceinline__ void flux_mhd(const R *V, const R *U, R *F)
+{
+    constexpr int n = Ax<D>::n, t = Ax<D>::t, b = Ax<D>::b;
+    R vn = V[MX1 + n], Bn = V[BX1 + n];
+    R pt = V[PRS] + R(0.5) * (sq(V[BX1]) + sq(V[BX2]) + sq(V[BX3]));
+    R vB = V[MX1] * V[BX1] + V[MX2] * V[BX2] + V[MX3] * V[BX3];
+    F[RHO] = U[MX1 + n];
+    F[MX1 + n] = U[MX1 + n] * vn - Bn * Bn + pt;
+    F[MX1 + t] = U[MX1 + t] * vn - Bn * V[BX1 + t];
+    F[MX1 + b] = U[MX1 + b] * vn - Bn * V[BX1 + b];
+    F[ENG] = (U[ENG] + pt) * vn - vB * Bn;
+    F[BX1 + n] = R(0);
+    F[BX1 + t] = vn * V[BX1 + t] - Bn * V[MX1 + t];
+    F[BX1 + b] = vn * V[BX1 + b] - Bn * V[MX1 + b];
+    F[PSI] = R(0);
+}
+
+// ---------------------------------------------------------------------------
+// Relativistic MHD (Sec. 2.2, Eq. rmhd, Eq. gammaEos) -- always FP64 for the
+// inversion; fluxes in the working precision.
+// ---------------------------------------------------------------------------
+
+template <typename R> __device__ __forceinline__ void p2c_rmhd(const R *V, R *U, R gam)
+{
+    R v2 = sq(V[MX1]) + sq(V[MX2]) + sq(V[MX3]);
+    R B2 = sq(V[BX1]) + sq(V[BX2]) + sq(V[BX3]);
+    R vB = V[MX1] * V[BX1] + V[MX2] * V[BX2] + V[MX3] * V[BX3];
+    R lor2 = R(1) / (R(1) - v2);
+    R lor = sqrt(lor2);
+    R w = V[RHO] + gam * V[PRS] / (gam - R(1));
+    R wl2 = w * lor2;
+    U[RHO] = V[RHO] * lor;
+    U[MX1] = (wl2 + B2) * V[MX1] - vB * V[BX1];
+    U[MX2] = (wl2 + B2) * V[MX2] - vB * V[BX2];
+    U[MX3] = (wl2 + B2) * V[MX3] - vB * V[BX3];
+    U[ENG] = wl2 - V[PRS] + R(0.5) * (B2 + B2 * v2 - vB * vB) - U[RHO];
+    U[BX1] = V[BX1];
+    U[BX2] = V[BX2];
+    U[BX3] = V[BX3];
+    U[PSI] = V[PSI];
+}
+
+// Conserved -> primitive for RMHD: Newton-Raphson on W = w gamma^2 for the
+// energy residual f(W) = W - p(W) + B^2/2 + (v^2(W) B^2 - S^2/W^2)/2 - D - E,
+// with S = m.B and v^2(W) = (m^2 + S^2 (2W + B^2)/W^2)/(W + B^2)^2, kept
+// inside a bracket [lo, hi] (bisection when a step leaves it).  The upper
+// end Gamma (E + D) has f >= 0 for the Gamma-law EOS.  Converged when
+// |dW| <= 1e-14 W.
+__device__ __forceinline__ int c2p_rmhd(const double *U, double *V, double gam, double Wguess)
+{
+    const double D = U[RHO], E = U[ENG];
+    const double m2 = U[MX1] * U[MX1] + U[MX2] * U[MX2] + U[MX3] * U[MX3];
+    const double S = U[MX1] * U[BX1] + U[MX2] * U[BX2] + U[MX3] * U[BX3];
+    const double B2 = U[BX1] * U[BX1] + U[BX2] * U[BX2] + U[BX3] * U[BX3];
+    const double gfac = (gam - 1.0) / gam;
+    V[BX1] = U[BX1];
+    V[BX2] = U[BX2];
+    V[BX3] = U[BX3];
+    V[PSI] = U[PSI];
+    int fl = 0;
+    if (!(D > 0.0)) fl |= F_RHO;
+    double hi = gam * (E + D);
+    double lo = 0.0;
+    double W = (Wguess > 0.0 && Wguess < hi) ? Wguess : hi;
+    bool conv = false;
+    double v2 = 0.0;
+    for (int it = 0; it < 60; ++it) {
+        double sw = S / W;
+        double WB = W + B2;
+        double iWB = 1.0 / WB;
+        v2 = (m2 + sw * sw * (2.0 * W + B2)) * iWB * iWB;
+        double f, df;
+        if (!(v2 < 1.0)) {
+            // unphysical (superluminal) trial: the root lies above
+            lo = W;
+            f = -1.0;
+            df = 0.0;
+        } else {
+            double sq1 = sqrt(1.0 - v2);
+            double p = gfac * (W * (1.0 - v2) - D * sq1);
+            f = W - p + 0.5 * B2 + 0.5 * (v2 * B2 - sw * sw) - D - E;
+            double dv2 = -2.0 * sw * sw / (W * WB) - 2.0 * v2 * iWB;
+            double dp = gfac * ((1.0 - v2) + dv2 * (-W + 0.5 * D / sq1));
+            df = 1.0 - dp + 0.5 * B2 * dv2 + sw * sw / W;
+            if (f > 0.0) hi = W; else lo = W;
+        }
+        double Wn = (df > 0.0) ? W - f / df : 0.5 * (lo + hi);
+        if (!(Wn > lo && Wn < hi)) Wn = 0.5 * (lo + hi);
+        if (fabs(Wn - W) <= 1e-14 * W) { W = Wn; conv = true; break; }
+        W = Wn;
+    }
+    double sw = S / W;
+    v2 = (m2 + sw * sw * (2.0 * W + B2)) / ((W + B2) * (W + B2));
+    double sq1 = sqrt(1.0 - v2);
+    V[RHO] = D * sq1;
+    V[PRS] = gfac * (W * (1.0 - v2) - D * sq1);
+    double iWB = 1.0 / (W + B2);
+    V[MX1] = (U[MX1] + sw * U[BX1]) * iWB;
+    V[MX2] = (U[MX2] + sw * U[BX2]) * iWB;
+    V[MX3] = (U[MX3] + sw * U[BX3]) * iWB;
+    if (!conv) fl |= F_INV;
+    if (!(V[RHO] > 0.0)) fl |= F_RHO;
+    if (!(V[PRS] > 0.0)) fl |= F_PRS;
+    if (!(v2 < 1.0)) fl |= F_VEL;
+    if (isnan(V[PRS]) || isnan(V[RHO]) || isnan(V[MX1] + V[MX2] + V[MX3])) fl |= F_NAN;
+    return fl;
+}
+
+template <int D, typename R> __device__ __forceinline__ void flux_rmhd(const R *V, const R *U, R *F, R gam)
+{
+    constexpr int n = Ax<D>::n, t = Ax<D>::t, b = Ax<D>::b;
+    R v2 = sq(V[MX1]) + sq(V[MX2]) + sq(V[MX3]);
+    R B2 = sq(V[BX1]) + sq(V[BX2]) + sq(V[BX3]);
+    R vB = V[MX1] * V[BX1] + V[MX2] * V[BX2] + V[MX3] * V[BX3];
+    R wl2 = (V[RHO] + gam * V[PRS] / (gam - R(1))) / (R(1) - v2);
+    // E = -v x B; E_n E_c terms and |E|^2 = v^2 B^2 - (v.B)^2
+    R E0 = V[MX3] * V[BX2] - V[MX2] * V[BX3];
+    R E1 = V[MX1] * V[BX3] - V[MX3] * V[BX1];
+    R E2 = V[MX2] * V[BX1] - V[MX1] * V[BX2];
+    R Ev[3] = { E0, E1, E2 };
+    R pt = V[PRS] + R(0.5) * (B2 + B2 * v2 - vB * vB);
+    R vn = V[MX1 + n];
+    F[RHO] = U[RHO] * vn;
+    F[MX1 + n] = wl2 * vn * vn - V[BX1 + n] * V[BX1 + n] - Ev[n] * Ev[n] + pt;
+    F[MX1 + t] = wl2 * vn * V[MX1 + t] - V[BX1 + n] * V[BX1 + t] - Ev[n] * Ev[t];
+    F[MX1 + b] = wl2 * vn * V[MX1 + b] - V[BX1 + n] * V[BX1 + b] - Ev[n] * Ev[b];
+    F[ENG] = U[MX1 + n] - U[RHO] * vn;
+    F[BX1 + n] = R(0);
+    F[BX1 + t] = vn * V[BX1 + t] - V[BX1 + n] * V[MX1 + t];
+    F[BX1 + b] = vn * V[BX1 + b] - V[BX1 + n] * V[MX1 + b];
+    F[PSI] = R(0);
+}
+
+// outer characteristic speeds along D from the isotropic bound
+// a^2 = cs^2 + ca^2 - cs^2 ca^2 combined with v_n by relativistic addition
+template <int D, typename R> __device__ __forceinline__ void speeds_rmhd(const R *V, R gam, R &lmin, R &lmax)
+{
+    R v2 = sq(V[MX1]) + sq(V[MX2]) + sq(V[MX3]);
+    R B2 = sq(V[BX1]) + sq(V[BX2]) + sq(V[BX3]);
+    R vB = V[MX1] * V[BX1] + V[MX2] * V[BX2] + V[MX3] * V[BX3];
+    R w = V[RHO] + gam * V[PRS] / (gam - R(1));
+    R cs2 = gam * V[PRS] / w;
+    R bb2 = B2 * (R(1) - v2) + vB * vB;
+    R ca2 = bb2 / (w + bb2);
+    R a2 = cs2 + ca2 - cs2 * ca2;
+    R vn = V[MX1 + D];
+    R den = R(1) / (R(1) - v2 * a2);
+    R disc = (R(1) - v2) * (R(1) - v2 * a2 - vn * vn * (R(1) - a2));
+    disc = disc > R(0) ? disc : R(0);
+    R root = sqrt(a2 * disc);
+    lmin = (vn * (R(1) - a2) - root) * den;
+    lmax = (vn * (R(1) - a2) + root) * den;
+}
+
+// ---------------------------------------------------------------------------
+// Physics dispatch
+// ---------------------------------------------------------------------------
+
+template <int PHYS, typename R> __device__ __forceinline__ void p2c(const R *V, R *U, R gam)
+{
+    if constexpr (PHYS == PHYS_MHD) p2c_mhd(V, U, gam - R(1));
+    else p2c_rmhd(V, U, gam);
+}
+
+// conserved -> primitive; RMHD always inverts in FP64
+template <int PHYS, typename R> __device__ __forceinline__ int c2p(const R *U, R *V, R gam, double Wguess = 0.0)
+{
+    if constexpr (PHYS == PHYS_MHD) {
+        return c2p_mhd(U, V, gam - R(1));
+    } else {
+        double u[NV], v[NV];
+#pragma unroll
+        for (int q = 0; q < NV; q++) u[q] = (double)U[q];
+        int f = c2p_rmhd(u, v, (double)gam, Wguess);
+#pragma unroll
+        for (int q = 0; q < NV; q++) V[q] = (R)v[q];
+        return f;
+    }
+}
+
+// physical flux with the GLM rows: F_{B_n} = psi, F_psi = c_h^2 B_n
+template <int D, int PHYS, typename R>
+__device__ __forceinline__ void phys_flux(const R *V, R *U, R *F, R gam, R ch, int glm)
+{
+    p2c<PHYS>(V, U, gam);
+    if constexpr (PHYS == PHYS_MHD) flux_mhd<D>(V, U, F);
+    else flux_rmhd<D>(V, U, F, gam);
+    if (glm) {
+        F[BX1 + D] = V[PSI];
+        F[PSI] = ch * ch * V[BX1 + D];
+    }
+}
+
+template <int D, int PHYS, typename R> __device__ __forceinline__ void wave_speeds(const R *V, R gam, R &lm, R &lp)
+{
+    if constexpr (PHYS == PHYS_MHD) {
+        R cf = cfast_mhd<D>(V, gam);
+        lm = V[MX1 + D] - cf;
+        lp = V[MX1 + D] + cf;
+    } else {
+        speeds_rmhd<D>(V, gam, lm, lp);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Riemann solvers (Sec. 3.1: HLL, HLLD) with the GLM interface subsystem
+// ---------------------------------------------------------------------------
+
+template <int D, int PHYS, typename R>
+__device__ __forceinline__ void hll(const R *VL, const R *VR, R *F, R &smax, R gam, R ch, int glm)
+{
+    R lmL, lpL, lmR, lpR;
+    wave_speeds<D, PHYS>(VL, gam, lmL, lpL);
+    wave_speeds<D, PHYS>(VR, gam, lmR, lpR);
+    R SL = fmin(lmL, lmR), SR = fmax(lpL, lpR);
+    smax = fmax(fabs(SL), fabs(SR));
+    R UL[NV], UR[NV], FL[NV], FR[NV];
+    phys_flux<D, PHYS>(VL, UL, FL, gam, ch, glm);
+    phys_flux<D, PHYS>(VR, UR, FR, gam, ch, glm);
+    if (SL >= R(0)) {
+#pragma unroll
+        for (int q = 0; q < NV; q++) F[q] = FL[q];
+    } else if (SR <= R(0)) {
+#pragma unroll
+        for (int q = 0; q < NV; q++) F[q] = FR[q];
+    } else {
+        R id = R(1) / (SR - SL);
+#pragma unroll
+        for (int q = 0; q < NV; q++) F[q] = (SR * FL[q] - SL * FR[q] + SL * SR * (UR[q] - UL[q])) * id;
+    }
+}
+
+// HLLD (Miyoshi & Kusano 2005) for states sharing the normal field.
+template <int D, typename R>
+__device__ __forceinline__ void hlld(const R *VL, const R *VR, R *F, R &smax, R gam, R ch, int glm)
+{
+    constexpr int n = Ax<D>::n, t = Ax<D>::t, b = Ax<D>::b;
+    R cfL = cfast_mhd<D>(VL, gam), cfR = cfast_mhd<D>(VR, gam);
+    R uL = VL[MX1 + n], uR = VR[MX1 + n];
+    R SL = fmin(uL - cfL, uR - cfR);
+    R SR = fmax(uL + cfL, uR + cfR);
+    smax = fmax(fabs(SL), fabs(SR));
+    R UL[NV], UR[NV], FL[NV], FR[NV];
+    phys_flux<D, PHYS_MHD>(VL, UL, FL, gam, ch, glm);
+    phys_flux<D, PHYS_MHD>(VR, UR, FR, gam, ch, glm);
+    if (SL >= R(0)) {
+#pragma unroll
+        for (int q = 0; q < NV; q++) F[q] = FL[q];
+        return;
+    }
+    if (SR <= R(0)) {
+#pragma unroll
+        for (int q = 0; q < NV; q++) F[q] = FR[q];
+        return;
+    }
+    const R Bn = VL[BX1 + n];
+    const R Bn2 = Bn * Bn;
+    R ptL = VL[PRS] + R(0.5) * (sq(VL[BX1]) + sq(VL[BX2]) + sq(VL[BX3]));
+    R ptR = VR[PRS] + R(0.5) * (sq(VR[BX1]) + sq(VR[BX2]) + sq(VR[BX3]));
+    R aL = (SL - uL) * VL[RHO], aR = (SR - uR) * VR[RHO];
+    R iden = R(1) / (aR - aL);
+    R SM = (aR * uR - aL * uL - ptR + ptL) * iden;
+    R pts = (aR * ptL - aL * ptR + aL * aR * (uR - uL)) * iden;
+
+    // single-star states; index 0 = left, 1 = right
+    R rs[2], vt[2], vb[2], Bt[2], Bb[2], Es[2], sr[2];
+#pragma unroll
+    for (int s = 0; s < 2; s++) {
+        const R *V = s ? VR : VL;
+        const R *U = s ? UR : UL;
+        R S = s ? SR : SL;
+        R pt = s ? ptR : ptL;
+        R u = V[MX1 + n], rho = V[RHO];
+        R Su = S - u, SSM = S - SM;
+        rs[s] = rho * Su / SSM;
+        R den = rho * Su * SSM - Bn2;
+        R scale = rho * fabs(Su) * fabs(SSM) + Bn2;
+        if (fabs(den) <= R(sizeof(R) == 8 ? 1e-12 : 1e-6) * scale) {
+            vt[s] = V[MX1 + t];
+            vb[s] = V[MX1 + b];
+            Bt[s] = V[BX1 + t];
+            Bb[s] = V[BX1 + b];
+        } else {
+            R iden2 = R(1) / den;
+            R fv = Bn * (SM - u) * iden2;
+            R fB = (rho * Su * Su - Bn2) * iden2;
+            vt[s] = V[MX1 + t] - V[BX1 + t] * fv;
+            vb[s] = V[MX1 + b] - V[BX1 + b] * fv;
+            Bt[s] = V[BX1 + t] * fB;
+            Bb[s] = V[BX1 + b] * fB;
+        }
+        R vB = V[MX1] * V[BX1] + V[MX2] * V[BX2] + V[MX3] * V[BX3];
+        R vBs = SM * Bn + vt[s] * Bt[s] + vb[s] * Bb[s];
+        Es[s] = (Su * U[ENG] - pt * u + pts * SM + Bn * (vB - vBs)) / SSM;
+        sr[s] = sqrt(rs[s]);
+    }
+    R SLs = SM - fabs(Bn) / sr[0];
+    R SRs = SM + fabs(Bn) / sr[1];
+
+    auto star = [&](int s, R *Us) {
+        Us[RHO] = rs[s];
+        Us[MX1 + n] = rs[s] * SM;
+        Us[MX1 + t] = rs[s] * vt[s];
+        Us[MX1 + b] = rs[s] * vb[s];
+        Us[ENG] = Es[s];
+        Us[BX1 + n] = Bn;
+        Us[BX1 + t] = Bt[s];
+        Us[BX1 + b] = Bb[s];
+        Us[PSI] = s ? VR[PSI] : VL[PSI];
+    };
+    if (SLs >= R(0)) {
+        R Us[NV];
+        star(0, Us);
+#pragma unroll
+        for (int q = 0; q < NV; q++) F[q] = FL[q] + SL * (Us[q] - UL[q]);
+        return;
+    }
+    if (SRs <= R(0)) {
+        R Us[NV];
+        star(1, Us);
+#pragma unroll
+        for (int q = 0; q < NV; q++) F[q] = FR[q] + SR * (Us[q] - UR[q]);
+        return;
+    }
+    // double-star states
+    R sB = sgn1(Bn);
+    R idn = R(1) / (sr[0] + sr[1]);
+    R vtt = (sr[0] * vt[0] + sr[1] * vt[1] + (Bt[1] - Bt[0]) * sB) * idn;
+    R vbb = (sr[0] * vb[0] + sr[1] * vb[1] + (Bb[1] - Bb[0]) * sB) * idn;
+    R Btt = (sr[0] * Bt[1] + sr[1] * Bt[0] + sr[0] * sr[1] * (vt[1] - vt[0]) * sB) * idn;
+    R Bbb = (sr[0] * Bb[1] + sr[1] * Bb[0] + sr[0] * sr[1] * (vb[1] - vb[0]) * sB) * idn;
+    R vBss = SM * Bn + vtt * Btt + vbb * Bbb;
+    int s = (SM >= R(0)) ? 0 : 1;
+    R Us[NV], Uss[NV];
+    star(s, Us);
+    R vBs = SM * Bn + vt[s] * Bt[s] + vb[s] * Bb[s];
+    Uss[RHO] = rs[s];
+    Uss[MX1 + n] = rs[s] * SM;
+    Uss[MX1 + t] = rs[s] * vtt;
+    Uss[MX1 + b] = rs[s] * vbb;
+    Uss[ENG] = Es[s] + (s ? R(1) : R(-1)) * sr[s] * (vBs - vBss) * sB;
+    Uss[BX1 + n] = Bn;
+    Uss[BX1 + t] = Btt;
+    Uss[BX1 + b] = Bbb;
+    Uss[PSI] = Us[PSI];
+    R Sk = s ? SR : SL;
+    R Sks = s ? SRs : SLs;
+    const R *Fk = s ? FR : FL;
+    const R *Uk = s ? UR : UL;
+#pragma unroll
+    for (int q = 0; q < NV; q++) F[q] = Fk[q] + Sks * Uss[q] - (Sks - Sk) * Us[q] - Sk * Uk[q];
+}
+
+// Interface solve: exact solution of the linear (B_n, psi) subsystem of
+// Eq. glm2x2 (psi + c_h B_n carried from the left, psi - c_h B_n from the
+// right), then HLLD / HLL on the states with the common B_n.  VL, VR are
+// modified in place (their B_n is replaced).
+template <int D, int PHYS, int RS, typename R>
+__device__ __forceinline__ void riemann(R *VL, R *VR, R *F, R &smax, R gam, R ch, int glm)
+{
+    R Bm, psim;
+    if (glm) {
+        Bm = R(0.5) * (VL[BX1 + D] + VR[BX1 + D]) - (VR[PSI] - VL[PSI]) / (R(2) * ch);
+        psim = R(0.5) * (VL[PSI] + VR[PSI]) - R(0.5) * ch * (VR[BX1 + D] - VL[BX1 + D]);
+    } else {
+        Bm = R(0.5) * (VL[BX1 + D] + VR[BX1 + D]);
+        psim = R(0);
+    }
+    VL[BX1 + D] = Bm;
+    VR[BX1 + D] = Bm;
+    if constexpr (RS == RS_HLLD && PHYS == PHYS_MHD) hlld<D>(VL, VR, F, smax, gam, ch, glm);
+    else hll<D, PHYS>(VL, VR, F, smax, gam, ch, glm);
+    F[BX1 + D] = glm ? psim : R(0);
+    F[PSI] = glm ? ch * ch * Bm : R(0);
+}
+
+// ---------------------------------------------------------------------------
+// Limiters and reconstruction (Sec. 3.2), on undivided differences.
+// ---------------------------------------------------------------------------
+
+template <typename R> __device__ __forceinline__ R minmod(R a, R b)
+{
+    return R(0.5) * (sgn0(a) + sgn0(b)) * fmin(fabs(a), fabs(b));
+}
+
+template <typename R> __device__ __forceinline__ R lim_mc(R dp, R dm) { return minmod(R(0.5) * (dp + dm), R(2) * minmod(dm, dp)); }
+
+template <typename R> __device__ __forceinline__ R limiter(int lim, R dp, R dm)
+{
+    R pr = dp * dm;
+    switch (lim) {
+    case LIM_MINMOD: return minmod(dp, dm);
+    case LIM_VANLEER: return pr > R(0) ? R(2) * pr / (dp + dm) : R(0);
+    case LIM_VANALBADA: return pr > R(0) ? pr * (dp + dm) / (dp * dp + dm * dm) : R(0);
+    default: return lim_mc(dp, dm);
+    }
+}
+
+// Interface offsets dm = w_- - w_0, dp = w_+ - w_0 from the differences
+// d[l] = w_{l+1} - w_l, l = -2..1 stored at d[0..3] (linear / WENO3 use d[1],
+// d[2] only).
+template <int RK, typename R>
+__device__ __forceinline__ void recon_offsets(const R *d, int lim, R dxr, R &dm, R &dp)
+{
+    if constexpr (RK == RK_LIN) {
+        R s = limiter(lim, d[2], d[1]);
+        dp = R(0.5) * s;
+        dm = -dp;
+    } else if constexpr (RK == RK_PPM) {
+        R s0 = lim_mc(d[2], d[1]);
+        R sp = lim_mc(d[3], d[2]);
+        R sm = lim_mc(d[1], d[0]);
+        R P = R(0.5) * d[2] - (sp - s0) * R(1.0 / 6.0);   // Eq. ppm1, w_+ - w_0
+        R M = -R(0.5) * d[1] + (sm - s0) * R(1.0 / 6.0);  // w_- - w_0
+        if (P * M > R(0)) {                               // Eq. ppm_parabolic_lim
+            dp = R(0);
+            dm = R(0);
+        } else {
+            dp = (fabs(P) >= R(2) * fabs(M)) ? R(-2) * M : P;
+            dm = (fabs(M) >= R(2) * fabs(P)) ? R(-2) * P : M;
+        }
+    } else {
+        R a = d[2], c = d[1];                              // Delta w_{+1/2}, Delta w_{-1/2}
+        R num = sq(a - c);
+        R ap = R(1) + num / (dxr * dxr + a * a);            // Eq. WENO3a
+        R am = R(1) + num / (dxr * dxr + c * c);
+        dp = (ap * a + R(0.5) * am * c) / (R(2) * ap + am); // Eq. WENO3
+        dm = -(am * c + R(0.5) * ap * a) / (R(2) * am + ap);
+    }
+}
+
+// Upwind tracing of one wave (Eq. wnorm_predp/m) in offset form: returns
+// w*_{+-} - w_0.
+template <typename R>
+__device__ __forceinline__ void trace(int wref, R dm, R dp, R nu, R numax, R numin, R &sm, R &sp)
+{
+    R dw = dp - dm, d2 = dp + dm;
+    R bp = R(0.5) * (R(1) + sgn0(nu));
+    R bm = R(0.5) * (R(1) - sgn0(nu));
+    R tp = dp - R(0.5) * nu * (dw + d2 * (R(3) - R(2) * nu));
+    R tm = dm - R(0.5) * nu * (dw - d2 * (R(3) + R(2) * nu));
+    R rp, rm;
+    if (wref == WREF_CELL) {
+        rp = R(0);
+        rm = R(0);
+    } else if (wref == WREF_CW84) {
+        rp = dp - R(0.5) * numax * (dw + d2 * (R(3) - R(2) * numax));
+        rm = dm - R(0.5) * numin * (dw - d2 * (R(3) + R(2) * numin));
+    } else {
+        rp = dp;
+        rm = dm;
+    }
+    sp = rp + bp * (tp - rp);
+    sm = rm + bm * (tm - rm);
+}
+
+// ---------------------------------------------------------------------------
+// Characteristic normal predictor (Sec. 3.2) with closed-form eigenvectors
+// of the 7-wave primitive MHD system normalised after Roe & Balsara (1996).
+// ---------------------------------------------------------------------------
+
+template <typename R> struct Eigen {
+    R rho, srho, a, a2, cf, cs, ca, af, as, by, bz, s;
+    R X, Y, Z;  // 1/(2N), 1/(2 a sqrt(rho)), 1/(2 rho a^2), N = af^2 cf^2 + as^2 cs^2
+};
+
+template <int D, typename R> __device__ __forceinline__ void eigen_setup(const R *V, R gam, Eigen<R> &e)
+{
+    constexpr int n = Ax<D>::n, t = Ax<D>::t, b = Ax<D>::b;
+    R rho = V[RHO];
+    R ir = R(1) / rho;
+    R Bn = V[BX1 + n], Bt = V[BX1 + t], Bb = V[BX1 + b];
+    R a2 = gam * V[PRS] * ir;
+    R bn2 = Bn * Bn * ir;
+    R Bt2 = Bt * Bt + Bb * Bb;
+    R bt2 = Bt2 * ir;
+    R b2 = bn2 + bt2;
+    R dab = a2 - b2;
+    R root = sqrt(dab * dab + R(4) * a2 * bt2);  // c_f^2 - c_s^2, exact for b_t = 0
+    R cf2 = R(0.5) * (a2 + b2 + root);
+    R cs2 = a2 * bn2 / cf2;                      // c_f^2 c_s^2 = a^2 c_a^2
+    e.rho = rho;
+    e.srho = sqrt(rho);
+    e.a2 = a2;
+    e.a = sqrt(a2);
+    e.cf = sqrt(cf2);
+    e.cs = sqrt(cs2);
+    e.ca = sqrt(bn2);
+    if (root > R(0)) {
+        R ir2 = R(0.5) / root;
+        R af2 = (root + dab) * ir2, as2 = (root - dab) * ir2;
+        e.af = sqrt(af2 > R(0) ? af2 : R(0));
+        e.as = sqrt(as2 > R(0) ? as2 : R(0));
+    } else {
+        e.af = R(1);
+        e.as = R(0);
+    }
+    if (Bt2 <= R(1e-12) * (Bt2 + Bn * Bn)) {
+        e.by = R(0.70710678118654752440);
+        e.bz = R(0.70710678118654752440);
+    } else {
+        R ib = R(1) / sqrt(Bt2);
+        e.by = Bt * ib;
+        e.bz = Bb * ib;
+    }
+    e.s = sgn1(Bn);
+    R N = e.af * e.af * cf2 + e.as * e.as * cs2;
+    e.X = R(0.5) / N;
+    e.Y = R(0.5) / (e.a * e.srho);
+    e.Z = R(0.5) / (rho * a2);
+}
+
+// project a primitive difference dq onto the 7 left eigenvectors
+template <int D, typename R> __device__ __forceinline__ void project(const Eigen<R> &e, const R *dq, R *w)
+{
+    constexpr int n = Ax<D>::n, t = Ax<D>::t, b = Ax<D>::b;
+    R u = dq[MX1 + n];
+    R vpa = e.by * dq[MX1 + t] + e.bz * dq[MX1 + b];
+    R vpe = -e.bz * dq[MX1 + t] + e.by * dq[MX1 + b];
+    R Bpa = e.by * dq[BX1 + t] + e.bz * dq[BX1 + b];
+    R Bpe = -e.bz * dq[BX1 + t] + e.by * dq[BX1 + b];
+    R dp = dq[PRS];
+    R fu = e.X * e.af * e.cf * u, su = e.X * e.as * e.cs * u;
+    R fv = e.X * e.s * e.as * e.cs * vpa, sv = e.X * e.s * e.af * e.cf * vpa;
+    R fB = e.Y * e.as * Bpa, sB = e.Y * e.af * Bpa;
+    R fp = e.Z * e.af * dp, sp = e.Z * e.as * dp;
+    w[0] = -fu + fv + fB + fp;  // v - c_f
+    w[6] = fu - fv + fB + fp;   // v + c_f
+    w[2] = -su - sv - sB + sp;  // v - c_s
+    w[4] = su + sv - sB + sp;   // v + c_s
+    R hv = R(0.5) * vpe, hB = R(0.5) * e.s * Bpe / e.srho;
+    w[1] = hv + hB;             // v - c_a
+    w[5] = hv - hB;             // v + c_a
+    w[3] = dq[RHO] - dp / e.a2; // entropy
+}
+
+// dV = sum_k c_k r_k (right eigenvectors), added to V
+template <int D, typename R> __device__ __forceinline__ void recombine(const Eigen<R> &e, const R *c, R *V)
+{
+    constexpr int n = Ax<D>::n, t = Ax<D>::t, b = Ax<D>::b;
+    R f = c[0] + c[6], sl = c[2] + c[4];
+    V[RHO] += e.rho * (e.af * f + e.as * sl) + c[3];
+    V[MX1 + n] += e.af * e.cf * (c[6] - c[0]) + e.as * e.cs * (c[4] - c[2]);
+    R vpa = e.s * (e.as * e.cs * (c[0] - c[6]) + e.af * e.cf * (c[4] - c[2]));
+    R vpe = c[1] + c[5];
+    R asr = e.a * e.srho;
+    R Bpa = asr * (e.as * f - e.af * sl);
+    R Bpe = e.s * e.srho * (c[1] - c[5]);
+    V[MX1 + t] += e.by * vpa - e.bz * vpe;
+    V[MX1 + b] += e.bz * vpa + e.by * vpe;
+    V[BX1 + t] += e.by * Bpa - e.bz * Bpe;
+    V[BX1 + b] += e.bz * Bpa + e.by * Bpe;
+    V[PRS] += e.rho * e.a2 * (e.af * f + e.as * sl);
+}
+
+// Characteristic predictor for cell 0 of the primitive stencil Vs[l+2]
+// (l = -2..2; linear and WENO3 read l = -1..1).  Outputs V*_- and V*_+.
+template <int D, int RK, typename R>
+__device__ __forceinline__ void predict_char(const R (*Vs)[NV], const KOpts &o, R gam, R dtdx, R dxr, R ch, R *Vm,
+                                             R *Vp)
+{
+    const R *V0 = Vs[2];
+    Eigen<R> e;
+    eigen_setup<D>(V0, gam, e);
+    constexpr int L0 = (RK == RK_PPM) ? 0 : 1;
+    constexpr int L1 = (RK == RK_PPM) ? 4 : 3;
+    // characteristic differences d[k][l] = l_k . (V_{l+1} - V_l)
+    R d[7][4];
+    R dh[2][4];
+#pragma unroll
+    for (int l = L0; l < L1; l++) {
+        R dq[NV];
+#pragma unroll
+        for (int q = 0; q < NV; q++) dq[q] = Vs[l + 1][q] - Vs[l][q];
+        R w[7];
+        project<D>(e, dq, w);
+#pragma unroll
+        for (int k = 0; k < 7; k++) d[k][l] = w[k];
+        if (o.glm) {
+            R ih = R(0.5) / ch;
+            dh[0][l] = (ch * dq[BX1 + D] - dq[PSI]) * ih;
+            dh[1][l] = (ch * dq[BX1 + D] + dq[PSI]) * ih;
+        } else {
+            dh[0][l] = dq[BX1 + D];
+            dh[1][l] = R(0);
+        }
+    }
+    R vn = V0[MX1 + D];
+    R nu[7] = { (vn - e.cf) * dtdx, (vn - e.ca) * dtdx, (vn - e.cs) * dtdx, vn * dtdx,
+                (vn + e.cs) * dtdx, (vn + e.ca) * dtdx, (vn + e.cf) * dtdx };
+    R nuh = ch * dtdx;
+    R numax = R(0), numin = R(0);
+    if (o.wref == WREF_CW84) {
+#pragma unroll
+        for (int k = 0; k < 7; k++) {
+            numax = fmax(numax, nu[k]);
+            numin = fmin(numin, nu[k]);
+        }
+        if (o.glm) {
+            numax = fmax(numax, nuh);
+            numin = fmin(numin, -nuh);
+        }
+    }
+    R cm[7], cp[7];
+#pragma unroll
+    for (int k = 0; k < 7; k++) {
+        R dm, dp;
+        recon_offsets<RK>(d[k], o.limiter, dxr, dm, dp);
+        trace(o.wref, dm, dp, nu[k], numax, numin, cm[k], cp[k]);
+    }
+#pragma unroll
+    for (int q = 0; q < NV; q++) {
+        Vm[q] = V0[q];
+        Vp[q] = V0[q];
+    }
+    recombine<D>(e, cm, Vm);
+    recombine<D>(e, cp, Vp);
+
+    // (B_n, psi): GLM pair with speeds -+c_h, or plain reconstruction of B_n
+    R dBn, dpsi;
+    if (o.glm) {
+        R hm[2], hp[2], tm[2], tp[2];
+#pragma unroll
+        for (int k = 0; k < 2; k++) {
+            recon_offsets<RK>(dh[k], o.limiter, dxr, hm[k], hp[k]);
+            trace(o.wref, hm[k], hp[k], k ? nuh : -nuh, numax, numin, tm[k], tp[k]);
+        }
+        dBn = (hp[0] + hp[1]) - (hm[0] + hm[1]);
+        dpsi = ch * ((hp[1] - hp[0]) - (hm[1] - hm[0]));
+        Vm[BX1 + D] += tm[0] + tm[1];
+        Vp[BX1 + D] += tp[0] + tp[1];
+        Vm[PSI] += ch * (tm[1] - tm[0]);
+        Vp[PSI] += ch * (tp[1] - tp[0]);
+    } else {
+        R bm, bp;
+        recon_offsets<RK>(dh[0], o.limiter, dxr, bm, bp);
+        dBn = bp - bm;
+        dpsi = R(0);
+        Vm[BX1 + D] += bm;
+        Vp[BX1 + D] += bp;
+    }
+    // terms that the 7-wave primitive system omits: d(B_n)/dn and d(psi)/dn
+    constexpr int t = Ax<D>::t, b = Ax<D>::b;
+    R h = R(0.5) * dtdx;
+    R gB = h * dBn, gP = h * dpsi;
+    R ir = R(1) / V0[RHO];
+    R vB = V0[MX1] * V0[BX1] + V0[MX2] * V0[BX2] + V0[MX3] * V0[BX3];
+    R src[NV] = { R(0) };
+    src[MX1 + D] = gB * V0[BX1 + D] * ir;
+    src[MX1 + t] = gB * V0[BX1 + t] * ir;
+    src[MX1 + b] = gB * V0[BX1 + b] * ir;
+    src[BX1 + t] = gB * V0[MX1 + t];
+    src[BX1 + b] = gB * V0[MX1 + b];
+    src[PRS] = gB * (R(1) - gam) * vB + gP * (gam - R(1)) * V0[BX1 + D];
+#pragma unroll
+    for (int q = 0; q < NV; q++) {
+        Vm[q] += src[q];
+        Vp[q] += src[q];
+    }
+}
+
+// MUSCL-Hancock primitive predictor (Sec. 3.3, Eq. MUSCL-Hancock, beta = 1):
+// limited slopes of the primitive variables, a conservative half step of
+// the cell with the physical fluxes of its two interface values, and
+// V*_{+-} = V(U*) +- dV/2.  A superluminal reconstruction (RMHD) drops the
+// slopes of the cell; a failed V(U*) falls back to V_i.  Returns failure bits.
+template <int D, int PHYS, typename R>
+__device__ __forceinline__ int predict_mh(const R (*Vs)[NV], const R *U0, const KOpts &o, R gam, R dtdx, R ch, R *Vm,
+                                          R *Vp)
+{
+    int fl = 0;
+    R dV[NV], Vlo[NV], Vhi[NV];
+#pragma unroll
+    for (int q = 0; q < NV; q++) {
+        dV[q] = limiter(o.limiter, Vs[3][q] - Vs[2][q], Vs[2][q] - Vs[1][q]);
+        Vlo[q] = Vs[2][q] - R(0.5) * dV[q];
+        Vhi[q] = Vs[2][q] + R(0.5) * dV[q];
+    }
+    if constexpr (PHYS == PHYS_RMHD) {
+        R v2l = sq(Vlo[MX1]) + sq(Vlo[MX2]) + sq(Vlo[MX3]);
+        R v2h = sq(Vhi[MX1]) + sq(Vhi[MX2]) + sq(Vhi[MX3]);
+        if (!(v2l < R(1)) || !(v2h < R(1))) {
+            fl |= F_VEL;
+#pragma unroll
+            for (int q = 0; q < NV; q++) {
+                dV[q] = R(0);
+                Vlo[q] = Vs[2][q];
+                Vhi[q] = Vs[2][q];
+            }
+        }
+    }
+    R Ut[NV], Flo[NV], Fhi[NV], Us[NV], Vh[NV];
+    phys_flux<D, PHYS>(Vlo, Ut, Flo, gam, ch, o.glm);
+    phys_flux<D, PHYS>(Vhi, Ut, Fhi, gam, ch, o.glm);
+#pragma unroll
+    for (int q = 0; q < NV; q++) Us[q] = U0[q] - R(0.5) * dtdx * (Fhi[q] - Flo[q]);
+    double Wg = 0.0;
+    if constexpr (PHYS == PHYS_RMHD) Wg = (double)(U0[ENG] + U0[RHO]);
+    int f2 = c2p<PHYS>(Us, Vh, gam, Wg);
+    if (f2) {
+        fl |= f2;
+#pragma unroll
+        for (int q = 0; q < NV; q++) Vh[q] = Vs[2][q];
+    }
+#pragma unroll
+    for (int q = 0; q < NV; q++) {
+        Vm[q] = Vh[q] - R(0.5) * dV[q];
+        Vp[q] = Vh[q] + R(0.5) * dV[q];
+    }
+    return fl;
+}
+
+}  // namespace ctu

@@ -1,0 +1,103 @@
+// ctu_dispatch.hpp -- selection of the kernel instantiation for an option set.
+//
+// The sweep and Godunov kernels are templates over the direction, the
+// physics, the predictor, the reconstruction kind and the Riemann solver, so
+// that each supported combination compiles to straight-line code.  The
+// instantiations are spread over one translation unit per precision.
+#pragma once
+#include "ctu_kernels.hpp"
+
+namespace ctu {
+
+struct Combo {
+    int phys, pred, rk, rs;
+};
+
+// supported (physics, predictor, reconstruction, solver) combinations
+__host__ inline bool combo_supported(const Combo &c)
+{
+    if (c.phys == PHYS_MHD) {
+        if (c.pred == PRED_CHAR) return true;
+        return c.rk == RK_LIN;
+    }
+    return c.pred == PRED_MH && c.rk == RK_LIN && c.rs == RS_HLL;
+}
+
+hipError_t launch_sweep_f32(int D, const Combo &c, int nblocks, const SweepArgs<float> &a, hipStream_t s);
+hipError_t launch_sweep_f64(int D, const Combo &c, int nblocks, const SweepArgs<double> &a, hipStream_t s);
+hipError_t launch_godunov_f32(int D, const Combo &c, int nblocks, const KBox *b, const KTile *t, const float *V,
+                              float *Fn, float *Pn, const double *params, const KOpts &o, hipStream_t s);
+hipError_t launch_godunov_f64(int D, const Combo &c, int nblocks, const KBox *b, const KTile *t, const double *V,
+                              double *Fn, double *Pn, const double *params, const KOpts &o, hipStream_t s);
+
+template <typename R> inline hipError_t launch_sweep(int D, const Combo &c, int nb, const SweepArgs<R> &a, hipStream_t s);
+template <> inline hipError_t launch_sweep<float>(int D, const Combo &c, int nb, const SweepArgs<float> &a, hipStream_t s)
+{
+    return launch_sweep_f32(D, c, nb, a, s);
+}
+template <> inline hipError_t launch_sweep<double>(int D, const Combo &c, int nb, const SweepArgs<double> &a, hipStream_t s)
+{
+    return launch_sweep_f64(D, c, nb, a, s);
+}
+
+}  // namespace ctu
+
+// Body of one precision's dispatch translation unit.
+#define CTU_DEFINE_DISPATCH(R, SUFFIX)                                                                            \
+    namespace ctu {                                                                                              \
+    template <int D, int PHYS, int PRED, int RK, int RS>                                                         \
+    static hipError_t sweep_one(int nb, const SweepArgs<R> &a, hipStream_t s)                                   \
+    {                                                                                                            \
+        hipLaunchKernelGGL((k_sweep<D, PHYS, PRED, RK, RS, R>), dim3(nb), dim3(NT), 0, s, a);                  \
+        return hipGetLastError();                                                                                \
+    }                                                                                                            \
+    template <int D>                                                                                             \
+    static hipError_t sweep_dir(const Combo &c, int nb, const SweepArgs<R> &a, hipStream_t s)                   \
+    {                                                                                                            \
+        if (c.phys == PHYS_RMHD) return sweep_one<D, PHYS_RMHD, PRED_MH, RK_LIN, RS_HLL>(nb, a, s);            \
+        if (c.pred == PRED_MH) {                                                                                 \
+            if (c.rs == RS_HLLD) return sweep_one<D, PHYS_MHD, PRED_MH, RK_LIN, RS_HLLD>(nb, a, s);            \
+            return sweep_one<D, PHYS_MHD, PRED_MH, RK_LIN, RS_HLL>(nb, a, s);                                  \
+        }                                                                                                        \
+        if (c.rk == RK_PPM) {                                                                                    \
+            if (c.rs == RS_HLLD) return sweep_one<D, PHYS_MHD, PRED_CHAR, RK_PPM, RS_HLLD>(nb, a, s);          \
+            return sweep_one<D, PHYS_MHD, PRED_CHAR, RK_PPM, RS_HLL>(nb, a, s);                                \
+        }                                                                                                        \
+        if (c.rk == RK_WENO) {                                                                                   \
+            if (c.rs == RS_HLLD) return sweep_one<D, PHYS_MHD, PRED_CHAR, RK_WENO, RS_HLLD>(nb, a, s);         \
+            return sweep_one<D, PHYS_MHD, PRED_CHAR, RK_WENO, RS_HLL>(nb, a, s);                               \
+        }                                                                                                        \
+        if (c.rs == RS_HLLD) return sweep_one<D, PHYS_MHD, PRED_CHAR, RK_LIN, RS_HLLD>(nb, a, s);              \
+        return sweep_one<D, PHYS_MHD, PRED_CHAR, RK_LIN, RS_HLL>(nb, a, s);                                    \
+    }                                                                                                            \
+    hipError_t launch_sweep_##SUFFIX(int D, const Combo &c, int nb, const SweepArgs<R> &a, hipStream_t s)      \
+    {                                                                                                            \
+        if (nb <= 0) return hipSuccess;                                                                          \
+        if (D == 0) return sweep_dir<0>(c, nb, a, s);                                                            \
+        if (D == 1) return sweep_dir<1>(c, nb, a, s);                                                            \
+        return sweep_dir<2>(c, nb, a, s);                                                                        \
+    }                                                                                                            \
+    template <int D>                                                                                             \
+    static hipError_t god_dir(const Combo &c, int nb, const KBox *b, const KTile *t, const R *V, R *Fn, R *Pn,  \
+                              const double *p, const KOpts &o, hipStream_t s)                                   \
+    {                                                                                                            \
+        if (c.phys == PHYS_RMHD)                                                                                 \
+            hipLaunchKernelGGL((k_godunov<D, PHYS_RMHD, RS_HLL, R>), dim3(nb), dim3(NT), 0, s, b, t, V, Fn, Pn, \
+                               p, o);                                                                            \
+        else if (c.rs == RS_HLLD)                                                                                \
+            hipLaunchKernelGGL((k_godunov<D, PHYS_MHD, RS_HLLD, R>), dim3(nb), dim3(NT), 0, s, b, t, V, Fn, Pn, \
+                               p, o);                                                                            \
+        else                                                                                                     \
+            hipLaunchKernelGGL((k_godunov<D, PHYS_MHD, RS_HLL, R>), dim3(nb), dim3(NT), 0, s, b, t, V, Fn, Pn,  \
+                               p, o);                                                                            \
+        return hipGetLastError();                                                                                \
+    }                                                                                                            \
+    hipError_t launch_godunov_##SUFFIX(int D, const Combo &c, int nb, const KBox *b, const KTile *t,           \
+                                       const R *V, R *Fn, R *Pn, const double *p, const KOpts &o, hipStream_t s) \
+    {                                                                                                            \
+        if (nb <= 0) return hipSuccess;                                                                          \
+        if (D == 0) return god_dir<0>(c, nb, b, t, V, Fn, Pn, p, o, s);                                          \
+        if (D == 1) return god_dir<1>(c, nb, b, t, V, Fn, Pn, p, o, s);                                          \
+        return god_dir<2>(c, nb, b, t, V, Fn, Pn, p, o, s);                                                      \
+    }                                                                                                            \
+    }

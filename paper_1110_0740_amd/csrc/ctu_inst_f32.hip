@@ -1,0 +1,3 @@
+// Kernel instantiations for the FP32 working precision.
+#include "ctu_dispatch.hpp"
+CTU_DEFINE_DISPATCH(float, f32)

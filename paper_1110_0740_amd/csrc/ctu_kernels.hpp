@@ -1,0 +1,737 @@
+// ctu_kernels.hpp -- HIP kernels of the CTU-GLM step (Sec. 3.1) for gfx950.
+//
+// One step of a batch of ghosted boxes is a short chain of launches:
+//   k_reset      zero the rate / dpp / failure outputs (graph-safe, no memset)
+//   k_prim       V = V(U) on every ghosted cell                       (a1)
+//   k_godunov<D> first-order fluxes R(V_j, V_{j+1}) at t^n, and the
+//                parabolic fluxes Pi^n, on the faces the corner coupling
+//                and the half step need                                (a2, a3)
+//   k_halfstep   cell-centred V^{n+1/2} for Pi^{n+1/2} (parabolic only) (a7)
+//   k_sweep<D>   for direction D: normal predictor, corner coupling
+//                (Eq. transv), final Riemann solve (Eq. ctu_flux), flux
+//                registers, and the conservative update of U^{n+1}; the
+//                last sweep also applies the split sources and reduces the
+//                CFL rate of Eq. Ca                                    (a4-a10)
+// Work is described by tables of tiles (box, range) so that boxes of any
+// size and level run in one launch per kernel.
+#pragma once
+#include "ctu_device.hpp"
+
+namespace ctu {
+
+constexpr int NT = 256;  // threads per block
+
+struct KBox {
+    int N[3];      // ghosted extents (N[2] = 1 in 2D)
+    int n[3];      // interior extents
+    int g[3];      // ghost widths (g[2] = 0 in 2D)
+    int lo[3];     // level-global index of the first interior cell
+    long long uoff;  // element offset of the box block in caller arrays
+    long long woff;  // element offset of the box block in workspace arrays
+    long long cells; // N0*N1*N2
+    double dx[3];
+    int reg0, reg1;  // register entries [reg0, reg1)
+};
+
+struct KTile {
+    int box, a, b, c;
+};
+
+struct KReg {
+    int dir, face, tlo0, tlo1, tn0, tn1, pad0, pad1;
+    long long slot;
+};
+
+__device__ __forceinline__ long long cidx(const KBox &bx, int i, int j, int k)
+{
+    return ((long long)k * bx.N[1] + j) * bx.N[0] + i;
+}
+
+template <int D> __device__ __forceinline__ void unit(int &di, int &dj, int &dk)
+{
+    di = (D == 0);
+    dj = (D == 1);
+    dk = (D == 2);
+}
+
+__device__ __forceinline__ void count_fails(int f, int *fails)
+{
+    if (f && fails) {
+        if (f & F_RHO) atomicAdd(&fails[0], 1);
+        if (f & F_PRS) atomicAdd(&fails[1], 1);
+        if (f & F_INV) atomicAdd(&fails[2], 1);
+        if (f & F_VEL) atomicAdd(&fails[3], 1);
+        if (f & F_NAN) atomicAdd(&fails[4], 1);
+    }
+}
+
+// non-negative doubles order like their bit patterns
+__device__ __forceinline__ void atomic_max_pos(double *addr, double v)
+{
+    atomicMax((unsigned long long *)addr, (unsigned long long)__double_as_longlong(v));
+}
+
+__device__ __forceinline__ double block_max(double v, double *red)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+    int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) red[w] = v;
+    __syncthreads();
+    double r = red[0];
+#pragma unroll
+    for (int q = 1; q < NT / 64; q++) r = fmax(r, red[q]);
+    __syncthreads();
+    return r;
+}
+
+template <int Z = 0> __global__ void k_reset(double *rate, double *dpp, int *fails)
+{
+    int t = threadIdx.x;
+    if (t == 0 && rate) rate[0] = 0.0;
+    if (t == 1 && dpp) dpp[0] = 0.0;
+    if (t >= 2 && t < 2 + 5 && fails) fails[t - 2] = 0;
+}
+
+// ---------------------------------------------------------------------------
+// elementwise maps: tile = (box, first cell); one cell per thread
+// ---------------------------------------------------------------------------
+
+template <int PHYS, typename R>
+__global__ __launch_bounds__(NT) void k_cons2prim(const KBox *boxes, const KTile *tiles, const R *U, R *V,
+                                                  int *fails, R gam, int out_ws)
+{
+    KTile tl = tiles[blockIdx.x];
+    const KBox &bx = boxes[tl.box];
+    long long c = tl.a + threadIdx.x;
+    if (c >= bx.cells) return;
+    R u[NV], v[NV];
+#pragma unroll
+    for (int q = 0; q < NV; q++) u[q] = U[bx.uoff + q * bx.cells + c];
+    int f = c2p<PHYS>(u, v, gam);
+    count_fails(f, fails);
+    long long o = out_ws ? bx.woff : bx.uoff;
+#pragma unroll
+    for (int q = 0; q < NV; q++) V[o + q * bx.cells + c] = v[q];
+}
+
+template <int PHYS, typename R>
+__global__ __launch_bounds__(NT) void k_prim2cons(const KBox *boxes, const KTile *tiles, const R *V, R *U, R gam)
+{
+    KTile tl = tiles[blockIdx.x];
+    const KBox &bx = boxes[tl.box];
+    long long c = tl.a + threadIdx.x;
+    if (c >= bx.cells) return;
+    R u[NV], v[NV];
+#pragma unroll
+    for (int q = 0; q < NV; q++) v[q] = V[bx.uoff + q * bx.cells + c];
+    p2c<PHYS>(v, u, gam);
+#pragma unroll
+    for (int q = 0; q < NV; q++) U[bx.uoff + q * bx.cells + c] = u[q];
+}
+
+// ---------------------------------------------------------------------------
+// Parabolic face flux (Sec. 2.1.1, Sec. 3.1, App. A) on the D-face between
+// cells A = c - e_D and B = c, from primitive point values Vf of the box.
+// Face coefficients use the average of the conserved variables of A and B;
+// transverse derivatives use the four-point average.
+// ---------------------------------------------------------------------------
+
+template <int D, typename R>
+__device__ __forceinline__ void parab_flux(const R *Vf, const KBox &bx, int i, int j, int k, const KOpts &o, R pL,
+                                           R pR, R rL, R rR, R *Pi)
+{
+    constexpr int n = Ax<D>::n, t = Ax<D>::t, b = Ax<D>::b;
+    int di, dj, dk;
+    unit<D>(di, dj, dk);
+    const long long cs = bx.cells;
+    const long long cB = cidx(bx, i, j, k);
+    const long long cA = cidx(bx, i - di, j - dj, k - dk);
+    auto fv = [&](int f, long long c) -> R {
+        if (f < 3) return Vf[(MX1 + f) * cs + c];
+        if (f < 6) return Vf[(BX1 + f - 3) * cs + c];
+        return Vf[PRS * cs + c] / Vf[RHO * cs + c];
+    };
+    R rA = Vf[RHO * cs + cA], rB = Vf[RHO * cs + cB];
+    R irs = R(1) / (rA + rB);
+    R rhof = R(0.5) * (rA + rB);
+    R vf[3], Bf[3];
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        vf[c] = (rA * Vf[(MX1 + c) * cs + cA] + rB * Vf[(MX1 + c) * cs + cB]) * irs;
+        Bf[c] = R(0.5) * (Vf[(BX1 + c) * cs + cA] + Vf[(BX1 + c) * cs + cB]);
+    }
+    // gradients of (v_x, v_y, v_z, B_x, B_y, B_z, T) at the face
+    R g[7][3];
+#pragma unroll
+    for (int f = 0; f < 7; f++) {
+        g[f][D] = (fv(f, cB) - fv(f, cA)) / R(bx.dx[D]);
+#pragma unroll
+        for (int e = 0; e < 3; e++) {
+            if (e == D) continue;
+            if (e >= o.dim) {
+                g[f][e] = R(0);
+                continue;
+            }
+            int ei = (e == 0), ej = (e == 1), ek = (e == 2);
+            R up = fv(f, cidx(bx, i + ei, j + ej, k + ek)) + fv(f, cidx(bx, i - di + ei, j - dj + ej, k - dk + ek));
+            R dn = fv(f, cidx(bx, i - ei, j - ej, k - ek)) + fv(f, cidx(bx, i - di - ei, j - dj - ej, k - dk - ek));
+            g[f][e] = (up - dn) / (R(4) * R(bx.dx[e]));
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < NV; q++) Pi[q] = R(0);
+    if (o.parab & PB_VISC) {
+        R divv = g[0][0] + g[1][1] + g[2][2];
+        R mu = rhof * R(o.nu);
+        R tau[3];
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+            tau[c] = mu * (g[c][n] + g[n][c] - (c == n ? R(2.0 / 3.0) * divv : R(0)));
+            Pi[MX1 + c] += tau[c];
+        }
+        Pi[ENG] += vf[0] * tau[0] + vf[1] * tau[1] + vf[2] * tau[2];
+    }
+    if (o.parab & PB_RES) {
+        R J[3];
+        J[0] = g[5][1] - g[4][2];
+        J[1] = g[3][2] - g[5][0];
+        J[2] = g[4][0] - g[3][1];
+        R eta = R(o.eta);
+        Pi[BX1 + t] += eta * J[b];
+        Pi[BX1 + b] -= eta * J[t];
+        Pi[ENG] -= eta * (J[t] * Bf[b] - J[b] * Bf[t]);
+    }
+    if (o.parab & PB_TC) {
+        R B2 = Bf[0] * Bf[0] + Bf[1] * Bf[1] + Bf[2] * Bf[2];
+        R bh[3] = { R(0), R(0), R(0) };
+        if (B2 > R(0)) {
+            R ib = R(1) / sqrt(B2);
+#pragma unroll
+            for (int c = 0; c < 3; c++) bh[c] = Bf[c] * ib;
+        }
+        R bg = bh[0] * g[6][0] + bh[1] * g[6][1] + bh[2] * g[6][2];
+        R Fc[3];
+#pragma unroll
+        for (int c = 0; c < 3; c++) Fc[c] = R(o.kpar) * bh[c] * bg + R(o.kperp) * (g[6][c] - bh[c] * bg);
+        R Fm = sqrt(Fc[0] * Fc[0] + Fc[1] * Fc[1] + Fc[2] * Fc[2]);
+        R Fn = Fc[n];
+        if (o.phi > 0.0 && Fm > R(0)) {
+            R pu = (Fc[n] < R(0)) ? pL : pR;  // Eq. sat_flux: upwind by sign of t_n
+            R q = R(5.0 * o.phi) * pu * sqrt(pu) / sqrt(R(0.5) * (rL + rR));
+            Fn = q / (Fm + q) * Fc[n];
+        }
+        Pi[ENG] += Fn;
+    }
+}
+
+template <typename R> __device__ __forceinline__ R diff_coeff(const KOpts &o, R rho, R gam)
+{
+    R D = R(0);
+    if (o.parab & PB_VISC) D = fmax(D, R(o.nu));
+    if (o.parab & PB_RES) D = fmax(D, R(o.eta));
+    if (o.parab & PB_TC) D = fmax(D, (gam - R(1)) * R(fmax(o.kpar, o.kperp)) / rho);
+    return D;
+}
+
+// ---------------------------------------------------------------------------
+// k_godunov<D>: faces between c - e_D and c (stored at c).  Region: along D
+// the faces of the interior (one more on each side with parabolic terms),
+// across D one halo cell on each side.
+// ---------------------------------------------------------------------------
+
+template <int D, int PHYS, int RS, typename R>
+__global__ __launch_bounds__(NT) void k_godunov(const KBox *boxes, const KTile *tiles, const R *V, R *Fn, R *Pn,
+                                                const double *params, KOpts o)
+{
+    KTile tl = tiles[blockIdx.x];
+    const KBox &bx = boxes[tl.box];
+    int e = o.parab ? 1 : 0;
+    int ext[3], org[3];
+#pragma unroll
+    for (int q = 0; q < 3; q++) {
+        if (q >= o.dim) {
+            ext[q] = 1;
+            org[q] = 0;
+        } else if (q == D) {
+            ext[q] = bx.n[q] + 1 + 2 * e;
+            org[q] = bx.g[q] - e;
+        } else {
+            ext[q] = bx.n[q] + 2;
+            org[q] = bx.g[q] - 1;
+        }
+    }
+    long long it = (long long)tl.a + threadIdx.x;
+    long long tot = (long long)ext[0] * ext[1] * ext[2];
+    if (it >= tot) return;
+    int i = org[0] + (int)(it % ext[0]);
+    int j = org[1] + (int)((it / ext[0]) % ext[1]);
+    int k = org[2] + (int)(it / ((long long)ext[0] * ext[1]));
+    int di, dj, dk;
+    unit<D>(di, dj, dk);
+    const long long cs = bx.cells;
+    const R *Vb = V + bx.woff;
+    long long cB = cidx(bx, i, j, k), cA = cidx(bx, i - di, j - dj, k - dk);
+    R VL[NV], VR[NV], F[NV];
+#pragma unroll
+    for (int q = 0; q < NV; q++) {
+        VL[q] = Vb[q * cs + cA];
+        VR[q] = Vb[q * cs + cB];
+    }
+    R gam = R(o.gamma), ch = R(params[1]);
+    R pL = VL[PRS], pR = VR[PRS], rL = VL[RHO], rR = VR[RHO];
+    if (!o.hyp_off) {
+        R sm;
+        riemann<D, PHYS, RS>(VL, VR, F, sm, gam, ch, o.glm);
+    } else {
+#pragma unroll
+        for (int q = 0; q < NV; q++) F[q] = R(0);
+    }
+    R *Fb = Fn + bx.woff;
+#pragma unroll
+    for (int q = 0; q < NV; q++) Fb[q * cs + cB] = F[q];
+    if (o.parab) {
+        // the four-point transverse stencil needs one more cell across D
+        bool inside = true;
+#pragma unroll
+        for (int q = 0; q < 3; q++) {
+            if (q == D || q >= o.dim) continue;
+            int c = (q == 0) ? i : (q == 1 ? j : k);
+            if (c < 1 || c > bx.N[q] - 2) inside = false;
+        }
+        R Pi[NV];
+        if (inside) parab_flux<D>(Vb, bx, i, j, k, o, pL, pR, rL, rR, Pi);
+        else
+#pragma unroll
+            for (int q = 0; q < NV; q++) Pi[q] = R(0);
+        R *Pb = Pn + bx.woff;
+#pragma unroll
+        for (int q = 0; q < NV; q++) Pb[q * cs + cB] = Pi[q];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_halfstep: U^{n+1/2} = U^n + dt/2 sum_d (L_H,d^n + L_P,d^n) on the
+// interior plus one halo cell, converted to V^{n+1/2} (MHD).
+// ---------------------------------------------------------------------------
+
+template <typename R>
+__global__ __launch_bounds__(NT) void k_halfstep(const KBox *boxes, const KTile *tiles, const R *U, const R *Fx,
+                                                 const R *Fy, const R *Fz, const R *Px, const R *Py, const R *Pz,
+                                                 R *Vh, const double *params, KOpts o)
+{
+    KTile tl = tiles[blockIdx.x];
+    const KBox &bx = boxes[tl.box];
+    int ext[3], org[3];
+#pragma unroll
+    for (int q = 0; q < 3; q++) {
+        ext[q] = (q < o.dim) ? bx.n[q] + 2 : 1;
+        org[q] = (q < o.dim) ? bx.g[q] - 1 : 0;
+    }
+    long long it = (long long)tl.a + threadIdx.x;
+    long long tot = (long long)ext[0] * ext[1] * ext[2];
+    if (it >= tot) return;
+    int i = org[0] + (int)(it % ext[0]);
+    int j = org[1] + (int)((it / ext[0]) % ext[1]);
+    int k = org[2] + (int)(it / ((long long)ext[0] * ext[1]));
+    const long long cs = bx.cells;
+    long long c = cidx(bx, i, j, k);
+    const R *F[3] = { Fx + bx.woff, Fy + bx.woff, Fz ? Fz + bx.woff : nullptr };
+    const R *P[3] = { Px + bx.woff, Py + bx.woff, Pz ? Pz + bx.woff : nullptr };
+    long long cp[3] = { cidx(bx, i + 1, j, k), cidx(bx, i, j + 1, k), cidx(bx, i, j, k + 1) };
+    R hdt = R(0.5 * params[0]);
+    R u[NV], v[NV];
+#pragma unroll
+    for (int q = 0; q < NV; q++) {
+        R s = R(0);
+#pragma unroll
+        for (int d = 0; d < 3; d++) {
+            if (d >= o.dim) continue;
+            R idx = R(1.0 / bx.dx[d]);
+            s += (-(F[d][q * cs + cp[d]] - F[d][q * cs + c]) + (P[d][q * cs + cp[d]] - P[d][q * cs + c])) * idx;
+        }
+        u[q] = U[bx.uoff + q * cs + c] + hdt * s;
+    }
+    c2p<PHYS_MHD>(u, v, R(o.gamma));
+#pragma unroll
+    for (int q = 0; q < NV; q++) Vh[bx.woff + q * cs + c] = v[q];
+}
+
+// ---------------------------------------------------------------------------
+// k_sweep<D>: one direction of the corner-coupled update.
+//
+// A block owns a column of transverse positions and marches along D over
+// the cells lo-1 .. lo+n (n+2 positions s = 0 .. n+1).  Items are processed
+// in rounds of NT: each item computes its cell's normal predictor and
+// corner-coupled states; the left state of the face below the item comes
+// from the item DEL places earlier (in LDS, or carried over from the
+// previous round); the update of a cell waits for the round holding the
+// face above it.  DEL = 1 along x (pencils laid end to end), 64 across
+// (64 transverse positions per row, x fastest for coalescing).
+// ---------------------------------------------------------------------------
+
+template <typename R> struct SweepArgs {
+    const KBox *boxes;
+    const KTile *tiles;
+    const KReg *regs;
+    const R *U;       // U^n (caller layout)
+    R *Uout;          // U^{n+1} (caller layout)
+    const R *V;       // V^n (workspace)
+    const R *Fn[3];   // Godunov fluxes at t^n (workspace)
+    const R *Pn[3];   // parabolic fluxes at t^n (workspace) or null
+    const R *Vh;      // V^{n+1/2} (workspace) or null
+    R *lam;           // per-cell rate accumulator (workspace, parabolic only)
+    const R *L0;      // cooling coefficient (caller layout / 9) or null
+    double *reg;      // flux registers or null
+    const double *params;
+    double *rate;
+    double *dpp;
+    int *fails;
+    KOpts o;
+    int first, last;  // first / last sweep of the step
+};
+
+template <int D, int PHYS, int PRED, int RK, int RS, typename R>
+__global__ __launch_bounds__(NT, 2) void k_sweep(SweepArgs<R> a)
+{
+    constexpr int DEL = (D == 0) ? 1 : 64;
+    __shared__ R sP[NV][NT];
+    __shared__ R sF[NV][NT];
+    __shared__ R sL[NT];
+    __shared__ R cP[NV][DEL];
+    __shared__ R cF[NV][DEL];
+    __shared__ R cL[DEL];
+    __shared__ double red[NT / 64];
+
+    const int tid = threadIdx.x;
+    const KTile tl = a.tiles[blockIdx.x];
+    const KBox bx = a.boxes[tl.box];
+    const KOpts &o = a.o;
+    const int dim = o.dim;
+    const long long cs = bx.cells;
+    const int nD = bx.n[D];
+    const int Lc = nD + 2;
+    // transverse axes of D (t0 < t1 by direction index)
+    constexpr int T0 = (D == 0) ? 1 : 0;
+    constexpr int T1 = (D == 2) ? 1 : 2;
+    const int nT0 = bx.n[T0], nT1 = (T1 < dim) ? bx.n[T1] : 1;
+    const int npos_tot = nT0 * nT1;
+    const int pos0 = tl.a;
+    int items;
+    int P = 0;
+    if (D == 0) {
+        P = min(tl.b, npos_tot - pos0);
+        items = P * Lc;
+    } else {
+        items = Lc * DEL;
+    }
+    const R gam = R(o.gamma);
+    const R dt = R(a.params[0]);
+    const R ch = R(a.params[1]);
+    const R dxD = R(bx.dx[D]);
+    const R dtdx = dt / dxD;
+    const R hdt = R(0.5) * dt;
+    int di, dj, dk;
+    unit<D>(di, dj, dk);
+    const R *Vb = a.V + bx.woff;
+    double rate_loc = 0.0, dpp_loc = 0.0;
+
+    for (int base = 0; base < items; base += NT) {
+        const int kit = base + tid;
+        bool valid = kit < items;
+        int s = 0, pos = 0;
+        if (D == 0) {
+            s = kit % Lc;
+            pos = pos0 + kit / Lc;
+        } else {
+            s = kit / DEL;
+            pos = pos0 + kit % DEL;
+            valid = valid && pos < npos_tot;
+        }
+        // ghosted coordinates of the item's cell
+        int tc0 = pos % nT0, tc1 = pos / nT0;
+        int cD = bx.g[D] - 1 + s;
+        int ci = 0, cj = 0, ck = 0;
+        if (D == 0) { ci = cD; cj = bx.g[1] + tc0; ck = bx.g[2] + tc1; }
+        if (D == 1) { ci = bx.g[0] + tc0; cj = cD; ck = bx.g[2] + tc1; }
+        if (D == 2) { ci = bx.g[0] + tc0; cj = bx.g[1] + tc1; ck = cD; }
+        const long long c = valid ? cidx(bx, ci, cj, ck) : 0;
+        const long long sD = (D == 0) ? 1 : (D == 1 ? (long long)bx.N[0] : (long long)bx.N[0] * bx.N[1]);
+
+        R Um[NV], Vc[NV], Vl[NV];
+        int fl = 0;
+        if (valid) {
+            // ---- normal predictor (Sec. 3.2 / 3.3) ----
+            R Vs[5][NV];
+            constexpr int l0 = (RK == RK_PPM) ? 0 : 1, l1 = (RK == RK_PPM) ? 5 : 4;
+#pragma unroll
+            for (int l = l0; l < l1; l++)
+#pragma unroll
+                for (int q = 0; q < NV; q++) Vs[l][q] = Vb[q * cs + c + (l - 2) * sD];
+#pragma unroll
+            for (int q = 0; q < NV; q++) {
+                Vc[q] = Vs[2][q];
+                Vl[q] = Vs[1][q];
+            }
+            R Vm[NV], Vp[NV];
+            if (o.hyp_off) {
+#pragma unroll
+                for (int q = 0; q < NV; q++) Vm[q] = Vp[q] = Vs[2][q];
+            } else if constexpr (PRED == PRED_CHAR) {
+                predict_char<D, RK>(Vs, o, gam, dtdx, dxD, ch, Vm, Vp);
+            } else {
+                R U0[NV];
+#pragma unroll
+                for (int q = 0; q < NV; q++) U0[q] = a.U[bx.uoff + q * cs + c];
+                fl |= predict_mh<D, PHYS>(Vs, U0, o, gam, dtdx, ch, Vm, Vp);
+            }
+            R Up[NV];
+            p2c<PHYS>(Vm, Um, gam);
+            p2c<PHYS>(Vp, Up, gam);
+            // ---- corner coupling (Eq. transv) ----
+#pragma unroll
+            for (int e = 0; e < 3; e++) {
+                if (e >= dim) continue;
+                const long long se = (e == 0) ? 1 : (e == 1 ? (long long)bx.N[0] : (long long)bx.N[0] * bx.N[1]);
+                const R ie = R(1.0 / bx.dx[e]);
+                if (e != D) {
+                    const R *Fe = a.Fn[e] + bx.woff;
+#pragma unroll
+                    for (int q = 0; q < NV; q++) {
+                        R tr = -(Fe[q * cs + c + se] - Fe[q * cs + c]) * ie * hdt;
+                        Um[q] += tr;
+                        Up[q] += tr;
+                    }
+                }
+                if (o.parab) {
+                    const R *Pe = a.Pn[e] + bx.woff;
+#pragma unroll
+                    for (int q = 0; q < NV; q++) {
+                        R tr = (Pe[q * cs + c + se] - Pe[q * cs + c]) * ie * hdt;
+                        Um[q] += tr;
+                        Up[q] += tr;
+                    }
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < NV; q++) sP[q][tid] = Up[q];
+        }
+        __syncthreads();
+
+        // ---- time-centred Riemann solve on the face below the item ----
+        if (valid && s >= 1) {
+            R UL[NV], VL[NV], VR[NV], F[NV];
+#pragma unroll
+            for (int q = 0; q < NV; q++) UL[q] = (tid >= DEL) ? sP[q][tid - DEL] : cP[q][tid];
+            double Wg = 0.0;
+            int fL = c2p<PHYS>(UL, VL, gam, Wg);
+            int fR = c2p<PHYS>(Um, VR, gam, Wg);
+            fl |= fL | fR;
+            if (fL) {
+#pragma unroll
+                for (int q = 0; q < NV; q++) VL[q] = Vl[q];
+            }
+            if (fR) {
+#pragma unroll
+                for (int q = 0; q < NV; q++) VR[q] = Vc[q];
+            }
+            R pL = VL[PRS], pR = VR[PRS], rL = VL[RHO], rR = VR[RHO];
+            R smax = R(0);
+            if (!o.hyp_off) {
+                riemann<D, PHYS, RS>(VL, VR, F, smax, gam, ch, o.glm);
+            } else {
+#pragma unroll
+                for (int q = 0; q < NV; q++) F[q] = R(0);
+            }
+            if (o.parab) {
+                R Pi[NV];
+                parab_flux<D>(a.Vh + bx.woff, bx, ci, cj, ck, o, pL, pR, rL, rR, Pi);
+#pragma unroll
+                for (int q = 0; q < NV; q++) F[q] -= Pi[q];
+            }
+            // ---- flux registers: dt * A * (F - Pi) on listed faces ----
+            if (a.reg && bx.reg1 > bx.reg0) {
+                int gface = bx.lo[D] + (s - 1);
+                int gt0 = bx.lo[T0] + tc0, gt1 = (T1 < dim) ? bx.lo[T1] + tc1 : 0;
+                for (int r = bx.reg0; r < bx.reg1; r++) {
+                    KReg rg = a.regs[r];
+                    if (rg.dir != D || rg.face != gface) continue;
+                    int u0 = gt0 - rg.tlo0, u1 = gt1 - rg.tlo1;
+                    if (u0 < 0 || u0 >= rg.tn0 || u1 < 0 || u1 >= rg.tn1) continue;
+                    double area = 1.0;
+#pragma unroll
+                    for (int e = 0; e < 3; e++)
+                        if (e != D && e < dim) area *= bx.dx[e];
+                    double *rp = a.reg + 9 * (rg.slot + (long long)u1 * rg.tn0 + u0);
+                    double fac = (double)dt * area;
+#pragma unroll
+                    for (int q = 0; q < NV; q++) rp[q] += fac * (double)F[q];
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < NV; q++) sF[q][tid] = F[q];
+            sL[tid] = smax;
+        }
+        __syncthreads();
+
+        // ---- conservative update (Eq. update) of the cell below the item ----
+        if (valid && s >= 2) {
+            const long long cu = c - sD;
+            R lamc = fmax(sL[tid], (tid >= DEL) ? sL[tid - DEL] : cL[tid]) / dxD;
+            R u[NV];
+            const R *Ub = a.first ? a.U : a.Uout;
+#pragma unroll
+            for (int q = 0; q < NV; q++) {
+                R Flo = (tid >= DEL) ? sF[q][tid - DEL] : cF[q][tid];
+                u[q] = Ub[bx.uoff + q * cs + cu] - dtdx * (sF[q][tid] - Flo);
+            }
+            R lamt = lamc;
+            if (o.parab) {
+                R *lp = a.lam + bx.woff / NV + cu;
+                if (!a.first) lamt = fmax(lamt, *lp);
+                if (!a.last) *lp = lamt;
+            }
+            if (a.last) {
+                // ---- split point-local sources (Sec. 3.1) ----
+                if (o.glm) {
+                    R dxm = R(bx.dx[0]);
+                    for (int e = 1; e < dim; e++) dxm = fmin(dxm, R(bx.dx[e]));
+                    u[PSI] *= exp(-R(o.glm_alpha) * ch * dt / dxm);
+                }
+                if (o.cooling && a.L0) {
+                    R v[NV];
+                    c2p<PHYS_MHD>(u, v, gam);
+                    R T = v[PRS] / v[RHO];
+                    if (T > R(o.T_floor)) {
+                        R om = R(1) - R(o.cool_beta);
+                        R x = pow(T, om) - om * (gam - R(1)) * v[RHO] * a.L0[bx.uoff / NV + cu] * dt;
+                        R xf = pow(R(o.T_floor), om);
+                        x = fmax(x, xf);
+                        R pn = v[RHO] * pow(x, R(1) / om);
+                        u[ENG] += (pn - v[PRS]) / (gam - R(1));
+                        dpp_loc = fmax(dpp_loc, (double)(fabs(pn - v[PRS]) / v[PRS]));
+                    }
+                }
+                double r = (double)lamt;
+                if (o.parab) {
+                    R rho_h = a.Vh[bx.woff + RHO * cs + cu];
+                    R Dc = diff_coeff(o, rho_h, gam);
+                    for (int e = 0; e < dim; e++) r += 2.0 * (double)Dc / (bx.dx[e] * bx.dx[e]);
+                }
+                rate_loc = fmax(rate_loc, r);
+            } else if (!o.parab) {
+                rate_loc = fmax(rate_loc, (double)lamt);
+            }
+#pragma unroll
+            for (int q = 0; q < NV; q++) a.Uout[bx.uoff + q * cs + cu] = u[q];
+        }
+        count_fails(fl, a.fails);
+        __syncthreads();
+        // ---- carry the last DEL items into the next round ----
+        if (tid >= NT - DEL) {
+            int ct = tid - (NT - DEL);
+#pragma unroll
+            for (int q = 0; q < NV; q++) {
+                cP[q][ct] = sP[q][tid];
+                cF[q][ct] = sF[q][tid];
+            }
+            cL[ct] = sL[tid];
+        }
+        __syncthreads();
+    }
+    double rb = block_max(rate_loc, red);
+    if (tid == 0 && a.rate) atomic_max_pos(a.rate, rb);
+    if (a.last && a.dpp && o.cooling) {
+        double db = block_max(dpp_loc, red);
+        if (tid == 0) atomic_max_pos(a.dpp, db);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_cfl: rate of Eq. Ca from cell-centred states (interior cells)
+// ---------------------------------------------------------------------------
+
+template <int PHYS, typename R>
+__global__ __launch_bounds__(NT) void k_cfl(const KBox *boxes, const KTile *tiles, const R *U, double *rate, KOpts o)
+{
+    __shared__ double red[NT / 64];
+    KTile tl = tiles[blockIdx.x];
+    const KBox &bx = boxes[tl.box];
+    long long it = (long long)tl.a + threadIdx.x;
+    long long tot = (long long)bx.n[0] * bx.n[1] * bx.n[2];
+    double r = 0.0;
+    if (it < tot) {
+        int i = bx.g[0] + (int)(it % bx.n[0]);
+        int j = bx.g[1] + (int)((it / bx.n[0]) % bx.n[1]);
+        int k = bx.g[2] + (int)(it / ((long long)bx.n[0] * bx.n[1]));
+        long long c = cidx(bx, i, j, k);
+        R u[NV], v[NV];
+#pragma unroll
+        for (int q = 0; q < NV; q++) u[q] = U[bx.uoff + q * bx.cells + c];
+        R gam = R(o.gamma);
+        c2p<PHYS>(u, v, gam);
+        R lm, lp;
+        wave_speeds<0, PHYS>(v, gam, lm, lp);
+        r = fmax(r, (double)fmax(fabs(lm), fabs(lp)) / bx.dx[0]);
+        wave_speeds<1, PHYS>(v, gam, lm, lp);
+        r = fmax(r, (double)fmax(fabs(lm), fabs(lp)) / bx.dx[1]);
+        if (o.dim == 3) {
+            wave_speeds<2, PHYS>(v, gam, lm, lp);
+            r = fmax(r, (double)fmax(fabs(lm), fabs(lp)) / bx.dx[2]);
+        }
+        if (o.parab) {
+            R Dc = diff_coeff(o, v[RHO], gam);
+            for (int e = 0; e < o.dim; e++) r += 2.0 * (double)Dc / (bx.dx[e] * bx.dx[e]);
+        }
+    }
+    double rb = block_max(r, red);
+    if (threadIdx.x == 0) atomic_max_pos(rate, rb);
+}
+
+// ---------------------------------------------------------------------------
+// k_reflux: Eq. fluxcorr / Eq. addreflux, one thread per corrected coarse
+// cell, entries of the cell applied in table order, FP64 arithmetic.
+// ---------------------------------------------------------------------------
+
+struct KRefl {
+    int box, i, j, k, dir, side, nfine, pad;
+    long long cslot;
+    long long fslot[4];
+};
+
+template <typename R>
+__global__ __launch_bounds__(NT) void k_reflux(const KBox *boxes, const KRefl *ent, const int *cell_start, int ncell,
+                                               R *U, const double *reg)
+{
+    int cidx_ = blockIdx.x * NT + threadIdx.x;
+    if (cidx_ >= ncell) return;
+    int e0 = cell_start[cidx_], e1 = cell_start[cidx_ + 1];
+    KRefl first = ent[e0];
+    const KBox &bx = boxes[first.box];
+    long long c = cidx(bx, first.i, first.j, first.k);
+    double du[NV];
+#pragma unroll
+    for (int q = 0; q < NV; q++) du[q] = 0.0;
+    for (int e = e0; e < e1; e++) {
+        KRefl en = ent[e];
+        double idx = 1.0 / bx.dx[en.dir];
+#pragma unroll
+        for (int q = 0; q < NV; q++) {
+            double fine = 0.0;
+            for (int f = 0; f < en.nfine; f++) fine += reg[9 * en.fslot[f] + q];
+            double delta = fine - reg[9 * en.cslot + q];
+            // reg holds dt*A*F; A/V = 1/dx on a Cartesian level
+            double area = 1.0;
+            for (int d = 0; d < 3; d++)
+                if (d != en.dir && bx.n[d] > 0 && !(d == 2 && bx.N[2] == 1)) area *= bx.dx[d];
+            du[q] += -(double)en.side * delta / area * idx;
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < NV; q++) {
+        R *p = &U[bx.uoff + q * bx.cells + c];
+        *p = R((double)(*p) + du[q]);
+    }
+}
+
+}  // namespace ctu

@@ -1,0 +1,611 @@
+// ctu_lib.hip -- host side of libctu: plans, work tables, launches, graphs.
+//
+// Implements the C ABI declared in include/ctu.h.  A plan owns the uploaded
+// box / register / reflux tables, the tile tables of every kernel and the
+// device workspace (V^n, the t^n face fluxes, V^{n+1/2}, the per-cell rate
+// accumulator).  ctu_step enqueues the launch chain described in
+// ctu_kernels.hpp on the caller's stream; nothing in it allocates.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/ctu.h"
+#include "ctu_dispatch.hpp"
+
+using namespace ctu;
+
+namespace {
+
+thread_local std::string g_err;
+
+ctu_status fail(ctu_status code, const std::string &msg)
+{
+    g_err = msg;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                                  \
+    do {                                                                                               \
+        hipError_t e_ = (expr);                                                                        \
+        if (e_ != hipSuccess) return fail(CTU_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+template <typename T> ctu_status upload(const std::vector<T> &h, T **d)
+{
+    *d = nullptr;
+    if (h.empty()) return CTU_OK;
+    if (hipMalloc((void **)d, h.size() * sizeof(T)) != hipSuccess) return fail(CTU_ERR_NOMEM, "hipMalloc of a table failed");
+    HIP_TRY(hipMemcpy(*d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
+    return CTU_OK;
+}
+
+struct TileSet {
+    std::vector<KTile> h;
+    KTile *d = nullptr;
+    int n() const { return (int)h.size(); }
+};
+
+}  // namespace
+
+struct ctu_plan {
+    ctu_opts opts;
+    KOpts ko;
+    Combo combo;
+    int nghost = 0;
+    int esize = 8;
+    std::vector<KBox> hboxes;
+    KBox *dboxes = nullptr;
+    std::vector<KReg> hregs;
+    KReg *dregs = nullptr;
+    int64_t state_elems = 0;
+    int64_t ws_cells = 0;  // sum of ghosted cells
+    TileSet t_cells, t_god[3], t_half, t_sweep[3], t_cfl;
+    // workspace fields
+    void *wsV = nullptr, *wsF[3] = { nullptr, nullptr, nullptr }, *wsP[3] = { nullptr, nullptr, nullptr };
+    void *wsVh = nullptr, *wsLam = nullptr;
+    int64_t ws_bytes = 0;
+    // reflux
+    KRefl *drefl = nullptr;
+    int *dcell_start = nullptr;
+    int nrefl_cells = 0;
+    // graph
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+};
+
+namespace {
+
+void free_plan(ctu_plan *p)
+{
+    if (!p) return;
+    if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    void *ptrs[] = { p->dboxes, p->dregs, p->t_cells.d, p->t_god[0].d, p->t_god[1].d, p->t_god[2].d, p->t_half.d,
+                     p->t_sweep[0].d, p->t_sweep[1].d, p->t_sweep[2].d, p->t_cfl.d, p->wsV, p->wsF[0], p->wsF[1],
+                     p->wsF[2], p->wsP[0], p->wsP[1], p->wsP[2], p->wsVh, p->wsLam, p->drefl, p->dcell_start };
+    for (void *q : ptrs)
+        if (q) (void)hipFree(q);
+    delete p;
+}
+
+// pencils per block along x: the P that keeps P*(n+2) closest to a multiple
+// of the block size (fewest idle lanes in the last round)
+int pencils_per_block(int L, int npos)
+{
+    int best = 1;
+    double best_eff = 0.0;
+    for (int P = 1; P <= 64; P++) {
+        if (P > npos && P > 1) break;
+        long long items = (long long)P * L;
+        long long rounds = (items + NT - 1) / NT;
+        double eff = (double)items / (double)(rounds * NT);
+        if (eff > best_eff + 1e-9 || (eff > best_eff - 1e-9 && P * L <= 16 * NT)) {
+            if (eff >= best_eff - 1e-9) {
+                best_eff = std::max(best_eff, eff);
+                best = P;
+            }
+        }
+    }
+    return best;
+}
+
+void add_linear_tiles(TileSet &ts, int box, long long count)
+{
+    for (long long s = 0; s < count; s += NT) ts.h.push_back(KTile{ box, (int)s, 0, 0 });
+}
+
+ctu_status build_tables(ctu_plan *p)
+{
+    const int dim = p->opts.dim;
+    const int par = p->opts.parabolic_mask ? 1 : 0;
+    for (int b = 0; b < (int)p->hboxes.size(); b++) {
+        const KBox &bx = p->hboxes[b];
+        add_linear_tiles(p->t_cells, b, bx.cells);
+        for (int D = 0; D < dim; D++) {
+            long long ext = 1;
+            for (int q = 0; q < dim; q++) ext *= (q == D) ? (bx.n[q] + 1 + 2 * par) : (bx.n[q] + 2);
+            add_linear_tiles(p->t_god[D], b, ext);
+        }
+        if (par) {
+            long long ext = 1;
+            for (int q = 0; q < dim; q++) ext *= bx.n[q] + 2;
+            add_linear_tiles(p->t_half, b, ext);
+        }
+        long long interior = (long long)bx.n[0] * bx.n[1] * bx.n[2];
+        add_linear_tiles(p->t_cfl, b, interior);
+        for (int D = 0; D < dim; D++) {
+            int T0 = (D == 0) ? 1 : 0, T1 = (D == 2) ? 1 : 2;
+            int npos = bx.n[T0] * ((T1 < dim) ? bx.n[T1] : 1);
+            if (D == 0) {
+                int P = pencils_per_block(bx.n[0] + 2, npos);
+                for (int s = 0; s < npos; s += P) p->t_sweep[0].h.push_back(KTile{ b, s, P, 0 });
+            } else {
+                for (int s = 0; s < npos; s += 64) p->t_sweep[D].h.push_back(KTile{ b, s, 64, 0 });
+            }
+        }
+    }
+    ctu_status st;
+    TileSet *all[] = { &p->t_cells, &p->t_god[0], &p->t_god[1], &p->t_god[2], &p->t_half,
+                       &p->t_sweep[0], &p->t_sweep[1], &p->t_sweep[2], &p->t_cfl };
+    for (TileSet *ts : all)
+        if ((st = upload(ts->h, &ts->d)) != CTU_OK) return st;
+    return CTU_OK;
+}
+
+ctu_status alloc_ws(ctu_plan *p, void **ptr, int64_t elems)
+{
+    int64_t bytes = elems * p->esize;
+    if (hipMalloc(ptr, bytes) != hipSuccess) return fail(CTU_ERR_NOMEM, "hipMalloc of the workspace failed");
+    p->ws_bytes += bytes;
+    return CTU_OK;
+}
+
+template <typename R>
+ctu_status enqueue_step(ctu_plan *p, const void *U_in, void *U_out, const double *params, const void *L0, double *reg,
+                        double *rate, double *dpp, int32_t *fails, hipStream_t s)
+{
+    const int dim = p->opts.dim;
+    const bool par = p->opts.parabolic_mask != 0;
+    hipLaunchKernelGGL(k_reset<0>, dim3(1), dim3(64), 0, s, rate, dpp, (int *)fails);
+    HIP_TRY(hipGetLastError());
+    const R gam = (R)p->opts.gamma;
+    if (p->combo.phys == PHYS_MHD)
+        hipLaunchKernelGGL((k_cons2prim<PHYS_MHD, R>), dim3(p->t_cells.n()), dim3(NT), 0, s, p->dboxes, p->t_cells.d,
+                           (const R *)U_in, (R *)p->wsV, (int *)fails, gam, 1);
+    else
+        hipLaunchKernelGGL((k_cons2prim<PHYS_RMHD, R>), dim3(p->t_cells.n()), dim3(NT), 0, s, p->dboxes,
+                           p->t_cells.d, (const R *)U_in, (R *)p->wsV, (int *)fails, gam, 1);
+    HIP_TRY(hipGetLastError());
+    for (int D = 0; D < dim; D++) {
+        hipError_t e;
+        if (sizeof(R) == 4)
+            e = launch_godunov_f32(D, p->combo, p->t_god[D].n(), p->dboxes, p->t_god[D].d, (const float *)p->wsV,
+                                   (float *)p->wsF[D], (float *)p->wsP[D], params, p->ko, s);
+        else
+            e = launch_godunov_f64(D, p->combo, p->t_god[D].n(), p->dboxes, p->t_god[D].d, (const double *)p->wsV,
+                                   (double *)p->wsF[D], (double *)p->wsP[D], params, p->ko, s);
+        if (e != hipSuccess) return fail(CTU_ERR_HIP, std::string("godunov launch: ") + hipGetErrorString(e));
+    }
+    if (par) {
+        hipLaunchKernelGGL((k_halfstep<R>), dim3(p->t_half.n()), dim3(NT), 0, s, p->dboxes, p->t_half.d,
+                           (const R *)U_in, (const R *)p->wsF[0], (const R *)p->wsF[1], (const R *)p->wsF[2],
+                           (const R *)p->wsP[0], (const R *)p->wsP[1], (const R *)p->wsP[2], (R *)p->wsVh, params,
+                           p->ko);
+        HIP_TRY(hipGetLastError());
+    }
+    SweepArgs<R> a;
+    a.boxes = p->dboxes;
+    a.regs = p->dregs;
+    a.U = (const R *)U_in;
+    a.Uout = (R *)U_out;
+    a.V = (const R *)p->wsV;
+    for (int d = 0; d < 3; d++) {
+        a.Fn[d] = (const R *)p->wsF[d];
+        a.Pn[d] = (const R *)p->wsP[d];
+    }
+    a.Vh = (const R *)p->wsVh;
+    a.lam = (R *)p->wsLam;
+    a.L0 = (const R *)L0;
+    a.reg = p->hregs.empty() ? nullptr : reg;
+    a.params = params;
+    a.rate = rate;
+    a.dpp = dpp;
+    a.fails = (int *)fails;
+    a.o = p->ko;
+    for (int D = 0; D < dim; D++) {
+        a.tiles = p->t_sweep[D].d;
+        a.first = (D == 0);
+        a.last = (D == dim - 1);
+        hipError_t e = launch_sweep<R>(D, p->combo, p->t_sweep[D].n(), a, s);
+        if (e != hipSuccess) return fail(CTU_ERR_HIP, std::string("sweep launch: ") + hipGetErrorString(e));
+    }
+    return CTU_OK;
+}
+
+ctu_status check_step_args(ctu_plan *p, const void *U_in, void *U_out, const double *params, const void *L0,
+                           double *reg, double *rate)
+{
+    if (!p) return fail(CTU_ERR_ARG, "null plan");
+    if (!U_in || !U_out || !params || !rate) return fail(CTU_ERR_ARG, "U_in, U_out, params and rate are required");
+    if (U_in == U_out) return fail(CTU_ERR_ARG, "U_out must not alias U_in");
+    if (p->opts.cooling && !L0) return fail(CTU_ERR_ARG, "cooling needs cool_L0");
+    if (!p->hregs.empty() && !reg) return fail(CTU_ERR_ARG, "the plan has register faces: reg is required");
+    return CTU_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *ctu_last_error(void) { return g_err.c_str(); }
+
+ctu_status ctu_plan_create(const ctu_opts *opts, const ctu_box *boxes, int32_t nbox, int32_t nghost,
+                           const ctu_regface *regfaces, int32_t nreg, ctu_plan **plan_out)
+{
+    if (!plan_out) return fail(CTU_ERR_ARG, "plan_out is null");
+    *plan_out = nullptr;
+    if (!opts || !boxes || nbox <= 0) return fail(CTU_ERR_ARG, "options and at least one box are required");
+    const ctu_opts &o = *opts;
+    if (o.dim != 2 && o.dim != 3) return fail(CTU_ERR_ARG, "dim must be 2 or 3");
+    if (o.physics != CTU_MHD && o.physics != CTU_RMHD) return fail(CTU_ERR_ARG, "bad physics");
+    if (o.precision != CTU_FP64 && o.precision != CTU_FP32) return fail(CTU_ERR_ARG, "bad precision");
+    if (o.recon < CTU_LIN_MC || o.recon > CTU_WENO3) return fail(CTU_ERR_ARG, "bad recon");
+    if (o.predictor != CTU_PRED_CHAR && o.predictor != CTU_PRED_MUSCL_HANCOCK) return fail(CTU_ERR_ARG, "bad predictor");
+    if (o.wref < CTU_WREF_FACE || o.wref > CTU_WREF_CW84) return fail(CTU_ERR_ARG, "bad wref");
+    if (o.riemann != CTU_HLLD && o.riemann != CTU_HLL) return fail(CTU_ERR_ARG, "bad riemann");
+    if (!(o.gamma > 1.0)) return fail(CTU_ERR_ARG, "gamma must exceed 1");
+    for (int d = 0; d < o.dim; d++)
+        if (!(o.dx[d] > 0.0)) return fail(CTU_ERR_ARG, "dx must be positive");
+    if (o.parabolic_mask & ~7u) return fail(CTU_ERR_ARG, "unknown parabolic bits");
+    Combo c;
+    c.phys = o.physics;
+    c.pred = o.predictor;
+    c.rk = (o.recon == CTU_PPM) ? RK_PPM : (o.recon == CTU_WENO3 ? RK_WENO : RK_LIN);
+    c.rs = o.riemann;
+    if (o.physics == CTU_RMHD && o.riemann == CTU_HLLD) c.rs = RS_HLL;
+    if (o.physics == CTU_RMHD && o.riemann == CTU_HLLD)
+        return fail(CTU_ERR_UNSUPPORTED, "RMHD supports the HLL solver only");
+    if (!combo_supported(c))
+        return fail(CTU_ERR_UNSUPPORTED, "unsupported combination (characteristic tracing is MHD only; "
+                                         "MUSCL-Hancock needs a linear reconstruction)");
+    if (o.physics == CTU_RMHD && (o.parabolic_mask || o.cooling))
+        return fail(CTU_ERR_UNSUPPORTED, "parabolic terms and cooling are MHD only");
+    int need = (o.recon == CTU_PPM ? 3 : 2) + (o.parabolic_mask ? 1 : 0);
+    if (nghost < 3 || nghost < need) return fail(CTU_ERR_ARG, "nghost too small for the stencil");
+    if (nreg > 0 && !regfaces) return fail(CTU_ERR_ARG, "regfaces is null");
+
+    ctu_plan *p = new ctu_plan();
+    p->opts = o;
+    p->combo = c;
+    p->nghost = nghost;
+    p->esize = (o.precision == CTU_FP32) ? 4 : 8;
+    KOpts &k = p->ko;
+    k.dim = o.dim;
+    k.limiter = (o.recon <= CTU_LIN_VANALBADA) ? o.recon : LIM_MC;
+    k.wref = o.wref;
+    k.glm = o.glm ? 1 : 0;
+    k.parab = (int)o.parabolic_mask;
+    k.cooling = o.cooling ? 1 : 0;
+    k.hyp_off = o.hyperbolic_off ? 1 : 0;
+    k.pad = 0;
+    k.gamma = o.gamma;
+    k.glm_alpha = o.glm_alpha;
+    k.nu = o.nu;
+    k.eta = o.eta;
+    k.kpar = o.kappa_par;
+    k.kperp = o.kappa_perp;
+    k.phi = o.tc_phi;
+    k.cool_beta = o.cool_beta;
+    k.T_floor = o.T_floor;
+
+    // boxes: validate, workspace offsets
+    int64_t woff = 0;
+    std::vector<std::pair<int64_t, int64_t>> spans;
+    for (int b = 0; b < nbox; b++) {
+        const ctu_box &B = boxes[b];
+        KBox kb;
+        std::memset(&kb, 0, sizeof(kb));
+        for (int d = 0; d < 3; d++) {
+            bool act = d < o.dim;
+            kb.n[d] = act ? B.n[d] : 1;
+            kb.g[d] = act ? nghost : 0;
+            kb.N[d] = kb.n[d] + 2 * kb.g[d];
+            kb.lo[d] = act ? B.lo[d] : 0;
+            kb.dx[d] = act ? o.dx[d] / (double)(1LL << B.level) : 1.0;
+            if (act && B.n[d] < 1) {
+                free_plan(p);
+                return fail(CTU_ERR_ARG, "box extents must be positive");
+            }
+        }
+        if (o.dim == 2 && B.n[2] != 1) {
+            free_plan(p);
+            return fail(CTU_ERR_ARG, "2D boxes must have n[2] == 1");
+        }
+        if (B.level < 0 || B.level > 30 || B.offset < 0 || (B.offset % NV) != 0) {
+            free_plan(p);
+            return fail(CTU_ERR_ARG, "bad box level or offset (offsets are multiples of 9)");
+        }
+        kb.cells = (long long)kb.N[0] * kb.N[1] * kb.N[2];
+        kb.uoff = B.offset;
+        kb.woff = woff;
+        woff += NV * kb.cells;
+        spans.push_back({ B.offset, B.offset + NV * kb.cells });
+        p->state_elems = std::max<int64_t>(p->state_elems, B.offset + NV * kb.cells);
+        p->ws_cells += kb.cells;
+        kb.reg0 = kb.reg1 = 0;
+        p->hboxes.push_back(kb);
+    }
+    std::sort(spans.begin(), spans.end());
+    for (size_t q = 1; q < spans.size(); q++)
+        if (spans[q].first < spans[q - 1].second) {
+            free_plan(p);
+            return fail(CTU_ERR_ARG, "box blocks overlap in the state array");
+        }
+
+    // register faces grouped per box
+    std::vector<std::vector<KReg>> per(nbox);
+    for (int r = 0; r < nreg; r++) {
+        const ctu_regface &R = regfaces[r];
+        if (R.box < 0 || R.box >= nbox || R.dir < 0 || R.dir >= o.dim || R.tn[0] < 1 || R.tn[1] < 1 || R.slot < 0 ||
+            (o.dim == 2 && R.tn[1] != 1)) {
+            free_plan(p);
+            return fail(CTU_ERR_ARG, "bad register face entry");
+        }
+        KReg kr;
+        kr.dir = R.dir;
+        kr.face = R.face;
+        kr.tlo0 = R.tlo[0];
+        kr.tlo1 = (o.dim == 2) ? 0 : R.tlo[1];
+        kr.tn0 = R.tn[0];
+        kr.tn1 = R.tn[1];
+        kr.pad0 = kr.pad1 = 0;
+        kr.slot = R.slot;
+        per[R.box].push_back(kr);
+    }
+    for (int b = 0; b < nbox; b++) {
+        p->hboxes[b].reg0 = (int)p->hregs.size();
+        for (auto &r : per[b]) p->hregs.push_back(r);
+        p->hboxes[b].reg1 = (int)p->hregs.size();
+    }
+
+    ctu_status st;
+    if ((st = upload(p->hboxes, &p->dboxes)) != CTU_OK || (st = upload(p->hregs, &p->dregs)) != CTU_OK ||
+        (st = build_tables(p)) != CTU_OK) {
+        free_plan(p);
+        return st;
+    }
+    const int64_t f9 = NV * p->ws_cells;
+    if ((st = alloc_ws(p, &p->wsV, f9)) != CTU_OK) {
+        free_plan(p);
+        return st;
+    }
+    for (int d = 0; d < o.dim; d++)
+        if ((st = alloc_ws(p, &p->wsF[d], f9)) != CTU_OK) {
+            free_plan(p);
+            return st;
+        }
+    if (o.parabolic_mask) {
+        for (int d = 0; d < o.dim; d++)
+            if ((st = alloc_ws(p, &p->wsP[d], f9)) != CTU_OK) {
+                free_plan(p);
+                return st;
+            }
+        if ((st = alloc_ws(p, &p->wsVh, f9)) != CTU_OK || (st = alloc_ws(p, &p->wsLam, p->ws_cells)) != CTU_OK) {
+            free_plan(p);
+            return st;
+        }
+    }
+    *plan_out = p;
+    return CTU_OK;
+}
+
+void ctu_plan_destroy(ctu_plan *plan) { free_plan(plan); }
+
+int64_t ctu_plan_state_elems(const ctu_plan *plan) { return plan ? plan->state_elems : 0; }
+int64_t ctu_plan_workspace_bytes(const ctu_plan *plan) { return plan ? plan->ws_bytes : 0; }
+
+ctu_status ctu_step(ctu_plan *plan, const void *U_in_dev, void *U_out_dev, const double *params_dev,
+                    const void *cool_L0_dev, double *reg_dev, double *rate_dev, double *dpp_dev, int32_t *fails_dev,
+                    void *stream)
+{
+    ctu_status st = check_step_args(plan, U_in_dev, U_out_dev, params_dev, cool_L0_dev, reg_dev, rate_dev);
+    if (st != CTU_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    if (plan->esize == 4)
+        return enqueue_step<float>(plan, U_in_dev, U_out_dev, params_dev, cool_L0_dev, reg_dev, rate_dev, dpp_dev,
+                                   fails_dev, s);
+    return enqueue_step<double>(plan, U_in_dev, U_out_dev, params_dev, cool_L0_dev, reg_dev, rate_dev, dpp_dev,
+                                fails_dev, s);
+}
+
+ctu_status ctu_step_graph_capture(ctu_plan *plan, const void *U_in_dev, void *U_out_dev, const double *params_dev,
+                                  const void *cool_L0_dev, double *reg_dev, double *rate_dev, double *dpp_dev,
+                                  int32_t *fails_dev, void *stream)
+{
+    ctu_status st = check_step_args(plan, U_in_dev, U_out_dev, params_dev, cool_L0_dev, reg_dev, rate_dev);
+    if (st != CTU_OK) return st;
+    if (!stream) return fail(CTU_ERR_ARG, "graph capture needs a non-default stream");
+    hipStream_t s = (hipStream_t)stream;
+    if (plan->gexec) {
+        HIP_TRY(hipGraphExecDestroy(plan->gexec));
+        plan->gexec = nullptr;
+    }
+    if (plan->graph) {
+        HIP_TRY(hipGraphDestroy(plan->graph));
+        plan->graph = nullptr;
+    }
+    HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    ctu_status st2 = (plan->esize == 4)
+                         ? enqueue_step<float>(plan, U_in_dev, U_out_dev, params_dev, cool_L0_dev, reg_dev, rate_dev,
+                                               dpp_dev, fails_dev, s)
+                         : enqueue_step<double>(plan, U_in_dev, U_out_dev, params_dev, cool_L0_dev, reg_dev, rate_dev,
+                                                dpp_dev, fails_dev, s);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(s, &g);
+    if (st2 != CTU_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return st2;
+    }
+    if (e != hipSuccess) return fail(CTU_ERR_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    plan->graph = g;
+    HIP_TRY(hipGraphInstantiate(&plan->gexec, g, nullptr, nullptr, 0));
+    HIP_TRY(hipGraphLaunch(plan->gexec, s));
+    return CTU_OK;
+}
+
+ctu_status ctu_step_graph_launch(ctu_plan *plan, void *stream)
+{
+    if (!plan || !plan->gexec) return fail(CTU_ERR_ARG, "no captured graph");
+    HIP_TRY(hipGraphLaunch(plan->gexec, (hipStream_t)stream));
+    return CTU_OK;
+}
+
+ctu_status ctu_cfl_rate(ctu_plan *plan, const void *U_dev, double *rate_dev, void *stream)
+{
+    if (!plan || !U_dev || !rate_dev) return fail(CTU_ERR_ARG, "plan, U and rate are required");
+    hipStream_t s = (hipStream_t)stream;
+    hipLaunchKernelGGL(k_reset<0>, dim3(1), dim3(64), 0, s, rate_dev, (double *)nullptr, (int *)nullptr);
+    HIP_TRY(hipGetLastError());
+    int nb = plan->t_cfl.n();
+    if (plan->esize == 4) {
+        if (plan->combo.phys == PHYS_MHD)
+            hipLaunchKernelGGL((k_cfl<PHYS_MHD, float>), dim3(nb), dim3(NT), 0, s, plan->dboxes, plan->t_cfl.d,
+                               (const float *)U_dev, rate_dev, plan->ko);
+        else
+            hipLaunchKernelGGL((k_cfl<PHYS_RMHD, float>), dim3(nb), dim3(NT), 0, s, plan->dboxes, plan->t_cfl.d,
+                               (const float *)U_dev, rate_dev, plan->ko);
+    } else {
+        if (plan->combo.phys == PHYS_MHD)
+            hipLaunchKernelGGL((k_cfl<PHYS_MHD, double>), dim3(nb), dim3(NT), 0, s, plan->dboxes, plan->t_cfl.d,
+                               (const double *)U_dev, rate_dev, plan->ko);
+        else
+            hipLaunchKernelGGL((k_cfl<PHYS_RMHD, double>), dim3(nb), dim3(NT), 0, s, plan->dboxes, plan->t_cfl.d,
+                               (const double *)U_dev, rate_dev, plan->ko);
+    }
+    HIP_TRY(hipGetLastError());
+    return CTU_OK;
+}
+
+ctu_status ctu_prim_to_cons(ctu_plan *plan, const void *V_dev, void *U_dev, void *stream)
+{
+    if (!plan || !V_dev || !U_dev) return fail(CTU_ERR_ARG, "plan, V and U are required");
+    hipStream_t s = (hipStream_t)stream;
+    int nb = plan->t_cells.n();
+    bool f32 = plan->esize == 4, mhd = plan->combo.phys == PHYS_MHD;
+    if (f32 && mhd)
+        hipLaunchKernelGGL((k_prim2cons<PHYS_MHD, float>), dim3(nb), dim3(NT), 0, s, plan->dboxes, plan->t_cells.d,
+                           (const float *)V_dev, (float *)U_dev, (float)plan->opts.gamma);
+    else if (f32)
+        hipLaunchKernelGGL((k_prim2cons<PHYS_RMHD, float>), dim3(nb), dim3(NT), 0, s, plan->dboxes, plan->t_cells.d,
+                           (const float *)V_dev, (float *)U_dev, (float)plan->opts.gamma);
+    else if (mhd)
+        hipLaunchKernelGGL((k_prim2cons<PHYS_MHD, double>), dim3(nb), dim3(NT), 0, s, plan->dboxes, plan->t_cells.d,
+                           (const double *)V_dev, (double *)U_dev, plan->opts.gamma);
+    else
+        hipLaunchKernelGGL((k_prim2cons<PHYS_RMHD, double>), dim3(nb), dim3(NT), 0, s, plan->dboxes,
+                           plan->t_cells.d, (const double *)V_dev, (double *)U_dev, plan->opts.gamma);
+    HIP_TRY(hipGetLastError());
+    return CTU_OK;
+}
+
+ctu_status ctu_cons_to_prim(ctu_plan *plan, const void *U_dev, void *V_dev, int32_t *fails_dev, void *stream)
+{
+    if (!plan || !V_dev || !U_dev) return fail(CTU_ERR_ARG, "plan, U and V are required");
+    hipStream_t s = (hipStream_t)stream;
+    if (fails_dev) {
+        hipLaunchKernelGGL(k_reset<0>, dim3(1), dim3(64), 0, s, (double *)nullptr, (double *)nullptr, (int *)fails_dev);
+        HIP_TRY(hipGetLastError());
+    }
+    int nb = plan->t_cells.n();
+    bool f32 = plan->esize == 4, mhd = plan->combo.phys == PHYS_MHD;
+    if (f32 && mhd)
+        hipLaunchKernelGGL((k_cons2prim<PHYS_MHD, float>), dim3(nb), dim3(NT), 0, s, plan->dboxes, plan->t_cells.d,
+                           (const float *)U_dev, (float *)V_dev, (int *)fails_dev, (float)plan->opts.gamma, 0);
+    else if (f32)
+        hipLaunchKernelGGL((k_cons2prim<PHYS_RMHD, float>), dim3(nb), dim3(NT), 0, s, plan->dboxes, plan->t_cells.d,
+                           (const float *)U_dev, (float *)V_dev, (int *)fails_dev, (float)plan->opts.gamma, 0);
+    else if (mhd)
+        hipLaunchKernelGGL((k_cons2prim<PHYS_MHD, double>), dim3(nb), dim3(NT), 0, s, plan->dboxes, plan->t_cells.d,
+                           (const double *)U_dev, (double *)V_dev, (int *)fails_dev, plan->opts.gamma, 0);
+    else
+        hipLaunchKernelGGL((k_cons2prim<PHYS_RMHD, double>), dim3(nb), dim3(NT), 0, s, plan->dboxes,
+                           plan->t_cells.d, (const double *)U_dev, (double *)V_dev, (int *)fails_dev,
+                           plan->opts.gamma, 0);
+    HIP_TRY(hipGetLastError());
+    return CTU_OK;
+}
+
+ctu_status ctu_plan_set_reflux(ctu_plan *plan, const ctu_refluxface *faces, int32_t nfaces)
+{
+    if (!plan) return fail(CTU_ERR_ARG, "null plan");
+    if (nfaces > 0 && !faces) return fail(CTU_ERR_ARG, "faces is null");
+    // group the entries per coarse cell, keeping table order inside a cell
+    std::map<std::pair<int, long long>, std::vector<int>> groups;
+    std::vector<std::pair<int, long long>> order;
+    for (int e = 0; e < nfaces; e++) {
+        const ctu_refluxface &f = faces[e];
+        if (f.box < 0 || f.box >= (int)plan->hboxes.size() || (f.side != 1 && f.side != -1) || f.nfine < 1 ||
+            f.nfine > 4 || f.dir < 0 || f.dir >= plan->opts.dim || f.coarse_slot < 0)
+            return fail(CTU_ERR_ARG, "bad reflux entry");
+        const KBox &bx = plan->hboxes[f.box];
+        if (f.i < 0 || f.i >= bx.N[0] || f.j < 0 || f.j >= bx.N[1] || f.k < 0 || f.k >= bx.N[2])
+            return fail(CTU_ERR_ARG, "reflux cell outside its box");
+        long long c = ((long long)f.k * bx.N[1] + f.j) * bx.N[0] + f.i;
+        auto key = std::make_pair(f.box, c);
+        if (!groups.count(key)) order.push_back(key);
+        groups[key].push_back(e);
+    }
+    std::vector<KRefl> ents;
+    std::vector<int> starts;
+    for (auto &key : order) {
+        starts.push_back((int)ents.size());
+        for (int e : groups[key]) {
+            const ctu_refluxface &f = faces[e];
+            KRefl r;
+            r.box = f.box;
+            r.i = f.i;
+            r.j = f.j;
+            r.k = f.k;
+            r.dir = f.dir;
+            r.side = f.side;
+            r.nfine = f.nfine;
+            r.pad = 0;
+            r.cslot = f.coarse_slot;
+            for (int q = 0; q < 4; q++) r.fslot[q] = (q < f.nfine) ? f.fine_slot[q] : 0;
+            ents.push_back(r);
+        }
+    }
+    starts.push_back((int)ents.size());
+    if (plan->drefl) (void)hipFree(plan->drefl);
+    if (plan->dcell_start) (void)hipFree(plan->dcell_start);
+    plan->drefl = nullptr;
+    plan->dcell_start = nullptr;
+    plan->nrefl_cells = (int)order.size();
+    ctu_status st;
+    if ((st = upload(ents, &plan->drefl)) != CTU_OK) return st;
+    if ((st = upload(starts, &plan->dcell_start)) != CTU_OK) return st;
+    return CTU_OK;
+}
+
+ctu_status ctu_reflux(ctu_plan *plan, void *U_dev, const double *reg_dev, void *stream)
+{
+    if (!plan || !U_dev || !reg_dev) return fail(CTU_ERR_ARG, "plan, U and reg are required");
+    if (plan->nrefl_cells == 0) return CTU_OK;
+    int nb = (plan->nrefl_cells + NT - 1) / NT;
+    hipStream_t s = (hipStream_t)stream;
+    if (plan->esize == 4)
+        hipLaunchKernelGGL((k_reflux<float>), dim3(nb), dim3(NT), 0, s, plan->dboxes, plan->drefl, plan->dcell_start,
+                           plan->nrefl_cells, (float *)U_dev, reg_dev);
+    else
+        hipLaunchKernelGGL((k_reflux<double>), dim3(nb), dim3(NT), 0, s, plan->dboxes, plan->drefl,
+                           plan->dcell_start, plan->nrefl_cells, (double *)U_dev, reg_dev);
+    HIP_TRY(hipGetLastError());
+    return CTU_OK;
+}
+
+}  // extern "C"

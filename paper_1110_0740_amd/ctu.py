@@ -1,0 +1,222 @@
+"""Thin ctypes binding of libctu.so (argument marshalling only).
+
+Every entry point mirrors a function of ``include/ctu.h`` and takes torch
+CUDA tensors for device buffers; the computation runs entirely in the HIP
+kernels of the library.  Loading fails loudly when the shared object is
+missing: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libctu.so")
+
+MHD, RMHD = 0, 1
+FP64, FP32 = 0, 1
+RECON = {"lin_mc": 0, "lin_minmod": 1, "lin_vanleer": 2, "lin_vanalbada": 3, "ppm": 4, "weno3": 5}
+PRED = {"char": 0, "mh": 1}
+WREF = {"face": 0, "cell": 1, "cw84": 2}
+RIEMANN = {"hlld": 0, "hll": 1}
+PARAB_VISC, PARAB_RES, PARAB_TC = 1, 2, 4
+NFAIL = 5
+
+# exported C symbols (kept in step with include/ctu.h)
+SYMBOLS = [
+    "ctu_plan_create", "ctu_plan_destroy", "ctu_plan_state_elems", "ctu_plan_workspace_bytes", "ctu_step",
+    "ctu_step_graph_capture", "ctu_step_graph_launch", "ctu_cfl_rate", "ctu_prim_to_cons", "ctu_cons_to_prim",
+    "ctu_plan_set_reflux", "ctu_reflux", "ctu_last_error",
+]
+
+
+class CtuOpts(C.Structure):
+    _fields_ = [
+        ("dim", C.c_int32), ("physics", C.c_int32), ("precision", C.c_int32), ("recon", C.c_int32),
+        ("predictor", C.c_int32), ("wref", C.c_int32), ("riemann", C.c_int32), ("glm", C.c_int32),
+        ("gamma", C.c_double), ("dx", C.c_double * 3), ("glm_alpha", C.c_double),
+        ("parabolic_mask", C.c_uint32), ("cooling", C.c_int32),
+        ("nu", C.c_double), ("eta", C.c_double), ("kappa_par", C.c_double), ("kappa_perp", C.c_double),
+        ("tc_phi", C.c_double), ("cool_beta", C.c_double), ("T_floor", C.c_double),
+        ("hyperbolic_off", C.c_int32), ("pad", C.c_int32),
+    ]
+
+
+class CtuBox(C.Structure):
+    _fields_ = [("lo", C.c_int32 * 3), ("n", C.c_int32 * 3), ("level", C.c_int32), ("pad", C.c_int32),
+                ("offset", C.c_int64)]
+
+
+class CtuRegFace(C.Structure):
+    _fields_ = [("box", C.c_int32), ("dir", C.c_int32), ("face", C.c_int32), ("pad", C.c_int32),
+                ("tlo", C.c_int32 * 2), ("tn", C.c_int32 * 2), ("slot", C.c_int64)]
+
+
+class CtuRefluxFace(C.Structure):
+    _fields_ = [("box", C.c_int32), ("i", C.c_int32), ("j", C.c_int32), ("k", C.c_int32), ("dir", C.c_int32),
+                ("side", C.c_int32), ("nfine", C.c_int32), ("pad", C.c_int32), ("coarse_slot", C.c_int64),
+                ("fine_slot", C.c_int64 * 4)]
+
+
+_lib = None
+_vp = C.c_void_p
+
+
+def lib() -> C.CDLL:
+    """Load libctu.so (built in-tree by __graft_entry__.build())."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'`")
+        L = C.CDLL(LIB_PATH)
+        L.ctu_plan_create.restype = C.c_int32
+        L.ctu_plan_create.argtypes = [C.POINTER(CtuOpts), C.POINTER(CtuBox), C.c_int32, C.c_int32,
+                                      C.POINTER(CtuRegFace), C.c_int32, C.POINTER(_vp)]
+        L.ctu_plan_destroy.argtypes = [_vp]
+        L.ctu_plan_state_elems.restype = C.c_int64
+        L.ctu_plan_state_elems.argtypes = [_vp]
+        L.ctu_plan_workspace_bytes.restype = C.c_int64
+        L.ctu_plan_workspace_bytes.argtypes = [_vp]
+        L.ctu_step.restype = C.c_int32
+        L.ctu_step.argtypes = [_vp] + [_vp] * 8 + [_vp]
+        L.ctu_step_graph_capture.restype = C.c_int32
+        L.ctu_step_graph_capture.argtypes = [_vp] + [_vp] * 8 + [_vp]
+        L.ctu_step_graph_launch.restype = C.c_int32
+        L.ctu_step_graph_launch.argtypes = [_vp, _vp]
+        L.ctu_cfl_rate.restype = C.c_int32
+        L.ctu_cfl_rate.argtypes = [_vp, _vp, _vp, _vp]
+        L.ctu_prim_to_cons.restype = C.c_int32
+        L.ctu_prim_to_cons.argtypes = [_vp, _vp, _vp, _vp]
+        L.ctu_cons_to_prim.restype = C.c_int32
+        L.ctu_cons_to_prim.argtypes = [_vp, _vp, _vp, _vp, _vp]
+        L.ctu_plan_set_reflux.restype = C.c_int32
+        L.ctu_plan_set_reflux.argtypes = [_vp, C.POINTER(CtuRefluxFace), C.c_int32]
+        L.ctu_reflux.restype = C.c_int32
+        L.ctu_reflux.argtypes = [_vp, _vp, _vp, _vp]
+        L.ctu_last_error.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+class CtuError(RuntimeError):
+    pass
+
+
+def _check(rc: int):
+    if rc != 0:
+        raise CtuError(f"libctu error {rc}: {lib().ctu_last_error().decode()}")
+
+
+def make_opts(dim=3, physics="mhd", precision="fp64", recon="ppm", predictor="char", wref="face", riemann="hlld",
+              glm=True, gamma=5.0 / 3.0, dx=(1.0, 1.0, 1.0), glm_alpha=0.1, parabolic_mask=0, cooling=False,
+              nu=0.0, eta=0.0, kappa_par=0.0, kappa_perp=0.0, tc_phi=0.0, cool_beta=0.5, T_floor=0.0,
+              hyperbolic_off=False) -> CtuOpts:
+    o = CtuOpts()
+    o.dim = dim
+    o.physics = {"mhd": MHD, "rmhd": RMHD}[physics]
+    o.precision = {"fp64": FP64, "fp32": FP32}[precision]
+    o.recon = RECON[recon]
+    o.predictor = PRED[predictor]
+    o.wref = WREF[wref]
+    o.riemann = RIEMANN[riemann]
+    o.glm = int(bool(glm))
+    o.gamma = gamma
+    for q in range(3):
+        o.dx[q] = dx[q]
+    o.glm_alpha = glm_alpha
+    o.parabolic_mask = parabolic_mask
+    o.cooling = int(bool(cooling))
+    o.nu, o.eta, o.kappa_par, o.kappa_perp, o.tc_phi = nu, eta, kappa_par, kappa_perp, tc_phi
+    o.cool_beta, o.T_floor = cool_beta, T_floor
+    o.hyperbolic_off = int(bool(hyperbolic_off))
+    return o
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        return None
+    if hasattr(stream, "cuda_stream"):
+        return C.c_void_p(stream.cuda_stream)
+    return C.c_void_p(int(stream))
+
+
+class Plan:
+    """A ctu_plan: boxes (lo, n, level, offset), ghosts, register faces."""
+
+    def __init__(self, opts: CtuOpts, boxes, nghost: int, regfaces=None):
+        L = lib()
+        nb = len(boxes)
+        arr = (CtuBox * nb)()
+        for q, b in enumerate(boxes):
+            lo, n, level, offset = b
+            for d in range(3):
+                arr[q].lo[d] = lo[d]
+                arr[q].n[d] = n[d]
+            arr[q].level = level
+            arr[q].offset = offset
+        regs = regfaces or []
+        rarr = (CtuRegFace * max(1, len(regs)))()
+        for q, r in enumerate(regs):
+            box, d, face, tlo, tn, slot = r
+            rarr[q].box, rarr[q].dir, rarr[q].face = box, d, face
+            rarr[q].tlo[0], rarr[q].tlo[1] = tlo
+            rarr[q].tn[0], rarr[q].tn[1] = tn
+            rarr[q].slot = slot
+        self.opts = opts
+        self._h = C.c_void_p()
+        _check(L.ctu_plan_create(C.byref(opts), arr, nb, nghost, rarr if regs else None, len(regs),
+                                 C.byref(self._h)))
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.ctu_plan_destroy(h)
+            self._h = None
+
+    @property
+    def state_elems(self) -> int:
+        return int(lib().ctu_plan_state_elems(self._h))
+
+    @property
+    def workspace_bytes(self) -> int:
+        return int(lib().ctu_plan_workspace_bytes(self._h))
+
+    def step(self, U_in, U_out, params, rate, L0=None, reg=None, dpp=None, fails=None, stream=None):
+        _check(lib().ctu_step(self._h, _ptr(U_in), _ptr(U_out), _ptr(params), _ptr(L0), _ptr(reg), _ptr(rate),
+                              _ptr(dpp), _ptr(fails), _stream(stream)))
+
+    def graph_capture(self, U_in, U_out, params, rate, L0=None, reg=None, dpp=None, fails=None, stream=None):
+        _check(lib().ctu_step_graph_capture(self._h, _ptr(U_in), _ptr(U_out), _ptr(params), _ptr(L0), _ptr(reg),
+                                            _ptr(rate), _ptr(dpp), _ptr(fails), _stream(stream)))
+
+    def graph_launch(self, stream=None):
+        _check(lib().ctu_step_graph_launch(self._h, _stream(stream)))
+
+    def cfl_rate(self, U, rate, stream=None):
+        _check(lib().ctu_cfl_rate(self._h, _ptr(U), _ptr(rate), _stream(stream)))
+
+    def prim_to_cons(self, V, U, stream=None):
+        _check(lib().ctu_prim_to_cons(self._h, _ptr(V), _ptr(U), _stream(stream)))
+
+    def cons_to_prim(self, U, V, fails=None, stream=None):
+        _check(lib().ctu_cons_to_prim(self._h, _ptr(U), _ptr(V), _ptr(fails), _stream(stream)))
+
+    def set_reflux(self, entries):
+        n = len(entries)
+        arr = (CtuRefluxFace * max(1, n))()
+        for q, e in enumerate(entries):
+            box, (i, j, k), d, side, cslot, fslots = e
+            a = arr[q]
+            a.box, a.i, a.j, a.k, a.dir, a.side = box, i, j, k, d, side
+            a.nfine = len(fslots)
+            a.coarse_slot = cslot
+            for f, s in enumerate(fslots):
+                a.fine_slot[f] = s
+        _check(lib().ctu_plan_set_reflux(self._h, arr, n))
+
+    def reflux(self, U, reg, stream=None):
+        _check(lib().ctu_reflux(self._h, _ptr(U), _ptr(reg), _stream(stream)))

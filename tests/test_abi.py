@@ -1,0 +1,59 @@
+"""Host-side checks of the C ABI: libctu.so loads, exports every function
+that include/ctu.h declares, and the ctypes structures match the C layout."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_1110_0740_amd import ctu
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ctu.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:ctu_status|void|int64_t|const char \*)\s*\*?\s*(ctu_\w+)\s*\(", text,
+                                 flags=re.M)))
+
+
+def test_header_declares_the_binding_symbols():
+    assert declared_functions() == sorted(ctu.SYMBOLS)
+
+
+def test_library_exports_every_declared_symbol():
+    L = ctu.lib()
+    for name in declared_functions():
+        assert hasattr(L, name), name
+
+
+def test_struct_layouts_match_c(tmp_path):
+    src = tmp_path / "layout.c"
+    src.write_text(
+        '#include <stdio.h>\n#include <stddef.h>\n#include "ctu.h"\n'
+        "int main(void){\n"
+        'printf("%zu %zu %zu %zu\\n", sizeof(ctu_opts), sizeof(ctu_box), sizeof(ctu_regface), sizeof(ctu_refluxface));\n'
+        'printf("%zu %zu %zu %zu\\n", offsetof(ctu_opts, gamma), offsetof(ctu_opts, parabolic_mask), '
+        "offsetof(ctu_opts, T_floor), offsetof(ctu_refluxface, fine_slot));\n"
+        "return 0;}\n")
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    out = subprocess.check_output([str(exe)]).decode().split()
+    sizes = [int(x) for x in out]
+    assert sizes[:4] == [ctypes.sizeof(ctu.CtuOpts), ctypes.sizeof(ctu.CtuBox), ctypes.sizeof(ctu.CtuRegFace),
+                         ctypes.sizeof(ctu.CtuRefluxFace)]
+    assert sizes[4:] == [ctu.CtuOpts.gamma.offset, ctu.CtuOpts.parabolic_mask.offset, ctu.CtuOpts.T_floor.offset,
+                         ctu.CtuRefluxFace.fine_slot.offset]
+
+
+def test_plan_creation_validates_options_without_gpu():
+    """Argument checks run on the host before any device call."""
+    with pytest.raises(ctu.CtuError, match="dim"):
+        ctu.Plan(ctu.make_opts(dim=4), [((0, 0, 0), (8, 8, 8), 0, 0)], 4)
+    with pytest.raises(ctu.CtuError, match="MHD"):
+        ctu.Plan(ctu.make_opts(dim=3, physics="rmhd", predictor="char", recon="lin_mc", riemann="hll"),
+                 [((0, 0, 0), (8, 8, 8), 0, 0)], 4)
+    with pytest.raises(ctu.CtuError, match="nghost"):
+        ctu.Plan(ctu.make_opts(dim=3, recon="ppm"), [((0, 0, 0), (8, 8, 8), 0, 0)], 2)
