@@ -1,0 +1,253 @@
+"""Benchmark: zone-updates/s of one CTU-GLM step on the 3D ideal-MHD workload
+(256^3 periodic, PPM characteristic tracing + HLLD + GLM, Gamma = 5/3,
+CFL 0.4), FP32 batched (HIP-graph replay) vs FP64 plain (eager launches),
+on one MI355X.  Prints one JSON line.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 256] [--no-cpu]
+
+A step is one pass of the whole hot path (primitive recovery, t^n Godunov
+fluxes, predictors, corner coupling, final Riemann solves, update, split
+sources, FP64 CFL reduction) over the resident 256^3 state.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "zone-updates/sec per CTU step (FP32 batched vs FP64 plain) + achieved HBM GB/s"
+
+# Issued VALU floating-point operations per interior zone of the dominant
+# kernel (the x sweep, FP32), from the rocprofv3 counter pass recorded in
+# profiles/sweep_x_fp32_256cube_counters.md (64 lanes x (ADD + MUL + TRANS +
+# 2 FMA) per wave instruction / interior zones).  None until measured.
+SWEEP_FLOPS_PER_ZONE = {"sweep_x": 2114.0, "sweep_y": 2113.0, "sweep_z": 2123.0}
+# HBM bytes per launch from FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (KiB x 1024):
+# a plain 1 GiB copy (bench.py --copy-calibration) reads 0.50 GiB of
+# FETCH_SIZE and 1.00 GiB of WRITE_SIZE, hence the factors; recorded in
+# profiles/sweep_fp32_256cube_counters.md.  Set to None when the kernels
+# change after the counter runs.
+SWEEP_TRAFFIC_BYTES = {"sweep_x": (2292071 * 2 + 652225) * 1024, "sweep_y": (3029403 * 2 + 690208) * 1024,
+                       "sweep_z": (3067881 * 2 + 690208) * 1024}
+# Algorithmic HBM bytes per zone of a whole step (read U^n on the ghosted box,
+# write U^{n+1}): 36 B x (264/256)^3 + 36 B in FP32, twice that in FP64.
+PEAK_HBM_GBS = 8000.0
+PEAK_FP32_TFLOPS = 157.3
+PEAK_FP64_TFLOPS = 78.6
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=256)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle cpu_baseline leg")
+    ap.add_argument("--precision", default="both", choices=["both", "fp32", "fp64"])
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy (HBM counter calibration) and exit")
+    return ap.parse_args()
+
+
+def copy_calibration():
+    """A plain device-to-device copy of 1 GiB: under rocprofv3 --pmc its
+    FETCH_SIZE / WRITE_SIZE give the scale of the HBM byte counters."""
+    import torch
+
+    x = torch.ones(256 * 1024 * 1024, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": x.numel() * 4, "copy_bytes_written": y.numel() * 4}))
+
+
+def cpu_baseline(Vfull, ng, dx, gamma, sub=96, nsub=3):
+    """The FP64 oracle, single-threaded, on `nsub` sub-boxes of sub^3 cut from
+    the same input (ghosts included), one step each."""
+    import numpy as np
+
+    import oracle as O
+    from paper_1110_0740_amd import inputs as I
+
+    oo = O.make_opts(dim=3, recon="ppm", riemann="hlld", gamma=gamma, dx=dx)
+    n = Vfull.shape[-1] - 2 * ng
+    origins = [(0, 0, 0), (n - sub, n // 2 - sub // 2, 17), (n // 3, n - sub, n - sub)][:nsub]
+    zones = 0
+    elapsed = 0.0
+    for lo in origins:
+        Vs = I.sub_box(Vfull, lo, (sub, sub, sub), ng, 3)
+        U = O.prim2cons(oo, Vs)
+        rate = O.cfl_rate(oo, U, ng)
+        dt = 0.4 / rate
+        ch = 0.4 * dx[0] / dt
+        t0 = time.perf_counter()
+        O.step(oo, U, ng, dt, ch)
+        elapsed += time.perf_counter() - t0
+        zones += sub ** 3
+    return {"value": zones / elapsed, "unit": "zone-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"{nsub} sub-boxes of {sub}^3 (+4 ghosts) of the {n}^3 input, one FP64 step each, "
+                      f"{elapsed:.1f} s single-threaded"}
+
+
+def main():
+    args = parse()
+    if args.copy_calibration:
+        copy_calibration()
+        return
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU decomposition is "
+              f"described in DESIGN.md but not built.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1110_0740_amd import ctu, inputs as I
+
+    dev = torch.device("cuda:0")
+    n, ng = args.n, 4
+    K, W = args.steps, args.warmup
+    print(f"[bench] generating {n}^3 inputs on the GPU", file=sys.stderr, flush=True)
+    V64, meta = I.mhd3d_fields_torch(n=n, ng=ng, seed=2000, device=dev)
+    dx, gamma = meta["dx"], meta["gamma"]
+    N = n + 2 * ng
+    zones = n ** 3
+    box = [((0, 0, 0), (n, n, n), 0, 0)]
+    s = torch.cuda.Stream()
+
+    o64 = ctu.make_opts(dim=3, recon="ppm", riemann="hlld", gamma=gamma, dx=dx, precision="fp64")
+    p64 = ctu.Plan(o64, box, ng)
+    U64 = torch.empty(9 * N ** 3, dtype=torch.float64, device=dev)
+    p64.prim_to_cons(V64.reshape(-1), U64)
+    rate = torch.zeros(1, dtype=torch.float64, device=dev)
+    p64.cfl_rate(U64, rate)
+    torch.cuda.synchronize()
+    dt = 0.4 / rate.item()
+    ch = 0.4 * dx[0] / dt
+    params = torch.tensor([dt, ch], dtype=torch.float64, device=dev)
+    fails = torch.zeros(5, dtype=torch.int32, device=dev)
+    Vhost = None
+    if not args.no_cpu:
+        Vhost = V64.cpu().numpy()
+    del V64
+
+    result = {}
+
+    def run_fp64():
+        Uo = torch.empty_like(U64)
+        with torch.cuda.stream(s):
+            for _ in range(W):
+                p64.step(U64, Uo, params, rate, fails=fails, stream=s)
+        s.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        with torch.cuda.stream(s):
+            e0.record(s)
+            for _ in range(K):
+                p64.step(U64, Uo, params, rate, fails=fails, stream=s)
+            e1.record(s)
+        s.synchronize()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / K
+        assert fails.sum().item() == 0, fails
+        result["fp64_plain"] = {"ms_per_step": ms, "zone_updates_per_s": zones / (ms * 1e-3)}
+        del Uo
+
+    def run_fp32():
+        o32 = ctu.make_opts(dim=3, recon="ppm", riemann="hlld", gamma=gamma, dx=dx, precision="fp32")
+        p32 = ctu.Plan(o32, box, ng)
+        U32 = U64.to(torch.float32)
+        Uo = torch.empty_like(U32)
+        torch.cuda.synchronize()
+        with torch.cuda.stream(s):
+            p32.graph_capture(U32, Uo, params, rate, fails=fails, stream=s)
+            for _ in range(W):
+                p32.graph_launch(stream=s)
+        s.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        with torch.cuda.stream(s):
+            e0.record(s)
+            for _ in range(K):
+                p32.graph_launch(stream=s)
+            e1.record(s)
+        s.synchronize()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / K
+        assert fails.sum().item() == 0, fails
+        # per-kernel durations: the same K steps launched eagerly with HIP
+        # events around every kernel, on the same stream
+        p32.enable_timing(True)
+        with torch.cuda.stream(s):
+            for _ in range(K):
+                p32.step(U32, Uo, params, rate, fails=fails, stream=s)
+        s.synchronize()
+        stage_ms, nrec = p32.read_timing()
+        p32.enable_timing(False)
+        result["fp32_batched"] = {"ms_per_step": ms, "zone_updates_per_s": zones / (ms * 1e-3),
+                                  "stage_ms": {k: v / max(nrec, 1) for k, v in stage_ms.items() if v > 0}}
+        del Uo, U32, p32
+
+    print(f"[bench] timing {K} steps after {W} warm-up steps", file=sys.stderr, flush=True)
+    if args.precision in ("both", "fp32"):
+        run_fp32()
+    if args.precision in ("both", "fp64"):
+        run_fp64()
+
+    main_key = "fp32_batched" if "fp32_batched" in result else "fp64_plain"
+    res = result[main_key]
+    esize = 4 if main_key == "fp32_batched" else 8
+    alg_bytes_zone = 9 * esize * ((n + 2 * ng) / n) ** 3 + 9 * esize
+    hbm_gbs = alg_bytes_zone * zones / (res["ms_per_step"] * 1e-3) / 1e9
+    roofline = None
+    if "stage_ms" in res:
+        dom = max(res["stage_ms"], key=res["stage_ms"].get)
+        dom_ms = res["stage_ms"][dom]
+        fpz = SWEEP_FLOPS_PER_ZONE.get(dom)
+        if fpz is not None:
+            achieved = fpz * zones / (dom_ms * 1e-3) / 1e12
+            roofline = {"bound": "alu", "kernel": dom, "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
+                        "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
+                        "traffic": SWEEP_TRAFFIC_BYTES.get(dom), "avg_ms": dom_ms}
+        else:
+            roofline = {"bound": "alu", "kernel": dom, "achieved": None, "peak": PEAK_FP32_TFLOPS,
+                        "unit": "TFLOP/s", "frac": None, "traffic": None, "avg_ms": dom_ms}
+    line = {
+        "metric": METRIC,
+        "value": res["zone_updates_per_s"],
+        "unit": "zone-updates/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": res["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if main_key == "fp32_batched" else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"3D ideal MHD {n}^3 periodic, PPM characteristic tracing + HLLD + GLM, "
+                               f"Gamma 5/3, CFL 0.4, seeded smooth random modes (beta~1, Mach~1)",
+                   "zones": zones, "nghost": ng, "path": main_key},
+        "hbm_step": {"bound": "hbm", "achieved": hbm_gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": hbm_gbs / PEAK_HBM_GBS, "alg_bytes_per_zone": alg_bytes_zone},
+        "roofline": roofline,
+        "paths": result,
+    }
+    if "fp64_plain" in result and "fp32_batched" in result:
+        line["fp32_over_fp64"] = result["fp32_batched"]["zone_updates_per_s"] / result["fp64_plain"][
+            "zone_updates_per_s"]
+    if not args.no_cpu:
+        print("[bench] oracle cpu_baseline", file=sys.stderr, flush=True)
+        line["cpu_baseline"] = cpu_baseline(Vhost, ng, dx, gamma)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

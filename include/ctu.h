@@ -209,6 +209,17 @@ ctu_status ctu_cons_to_prim(ctu_plan *plan, const void *U_dev, void *V_dev, int3
 ctu_status ctu_plan_set_reflux(ctu_plan *coarse_plan, const ctu_refluxface *faces, int32_t nfaces);
 ctu_status ctu_reflux(ctu_plan *coarse_plan, void *U_dev, const double *reg_dev, void *stream);
 
+/* Per-stage kernel timing with HIP events recorded on the launch stream
+ * around each kernel of ctu_step (eager launches only, not inside captured
+ * graphs).  Enabling (re)starts the accumulation; up to 256 steps are
+ * recorded.  ctu_plan_read_timing synchronises on the recorded events and
+ * writes the total milliseconds per stage into ms_out[CTU_NSTAGE] and the
+ * number of recorded steps into nsteps_out.  Stages: 0 primitive recovery,
+ * 1-3 Godunov fluxes x/y/z, 4 half step, 5-7 direction sweeps x/y/z. */
+#define CTU_NSTAGE 8
+ctu_status ctu_plan_enable_timing(ctu_plan *plan, int32_t enable);
+ctu_status ctu_plan_read_timing(ctu_plan *plan, double *ms_out, int32_t *nsteps_out);
+
 const char *ctu_last_error(void);
 
 #ifdef __cplusplus

@@ -76,13 +76,22 @@ struct ctu_plan {
     // graph
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
+    // per-stage event timing
+    bool timing = false;
+    int tsteps = 0;
+    std::vector<hipEvent_t> tev;  // [step][stage][2]
+    std::vector<char> tused;      // [step][stage]
 };
+
+static constexpr int kMaxTimedSteps = 256;
 
 namespace {
 
 void free_plan(ctu_plan *p)
 {
     if (!p) return;
+    for (hipEvent_t e : p->tev)
+        if (e) (void)hipEventDestroy(e);
     if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
     if (p->graph) (void)hipGraphDestroy(p->graph);
     void *ptrs[] = { p->dboxes, p->dregs, p->t_cells.d, p->t_god[0].d, p->t_god[1].d, p->t_god[2].d, p->t_half.d,
@@ -165,6 +174,28 @@ ctu_status alloc_ws(ctu_plan *p, void **ptr, int64_t elems)
     return CTU_OK;
 }
 
+// event pair of (current step, stage) or null when timing is off / full
+hipEvent_t *timer(ctu_plan *p, int stage)
+{
+    if (!p->timing || p->tsteps >= kMaxTimedSteps) return nullptr;
+    size_t idx = (size_t)p->tsteps * CTU_NSTAGE + stage;
+    p->tused[idx] = 1;
+    return &p->tev[2 * idx];
+}
+
+struct StageTimer {
+    hipEvent_t *ev;
+    hipStream_t s;
+    StageTimer(ctu_plan *p, int stage, hipStream_t st) : ev(timer(p, stage)), s(st)
+    {
+        if (ev) (void)hipEventRecord(ev[0], s);
+    }
+    ~StageTimer()
+    {
+        if (ev) (void)hipEventRecord(ev[1], s);
+    }
+};
+
 template <typename R>
 ctu_status enqueue_step(ctu_plan *p, const void *U_in, void *U_out, const double *params, const void *L0, double *reg,
                         double *rate, double *dpp, int32_t *fails, hipStream_t s)
@@ -174,14 +205,18 @@ ctu_status enqueue_step(ctu_plan *p, const void *U_in, void *U_out, const double
     hipLaunchKernelGGL(k_reset<0>, dim3(1), dim3(64), 0, s, rate, dpp, (int *)fails);
     HIP_TRY(hipGetLastError());
     const R gam = (R)p->opts.gamma;
-    if (p->combo.phys == PHYS_MHD)
-        hipLaunchKernelGGL((k_cons2prim<PHYS_MHD, R>), dim3(p->t_cells.n()), dim3(NT), 0, s, p->dboxes, p->t_cells.d,
-                           (const R *)U_in, (R *)p->wsV, (int *)fails, gam, 1);
-    else
-        hipLaunchKernelGGL((k_cons2prim<PHYS_RMHD, R>), dim3(p->t_cells.n()), dim3(NT), 0, s, p->dboxes,
-                           p->t_cells.d, (const R *)U_in, (R *)p->wsV, (int *)fails, gam, 1);
+    {
+        StageTimer tm(p, 0, s);
+        if (p->combo.phys == PHYS_MHD)
+            hipLaunchKernelGGL((k_cons2prim<PHYS_MHD, R>), dim3(p->t_cells.n()), dim3(NT), 0, s, p->dboxes,
+                               p->t_cells.d, (const R *)U_in, (R *)p->wsV, (int *)fails, gam, 1);
+        else
+            hipLaunchKernelGGL((k_cons2prim<PHYS_RMHD, R>), dim3(p->t_cells.n()), dim3(NT), 0, s, p->dboxes,
+                               p->t_cells.d, (const R *)U_in, (R *)p->wsV, (int *)fails, gam, 1);
+    }
     HIP_TRY(hipGetLastError());
     for (int D = 0; D < dim; D++) {
+        StageTimer tm(p, 1 + D, s);
         hipError_t e;
         if (sizeof(R) == 4)
             e = launch_godunov_f32(D, p->combo, p->t_god[D].n(), p->dboxes, p->t_god[D].d, (const float *)p->wsV,
@@ -192,6 +227,7 @@ ctu_status enqueue_step(ctu_plan *p, const void *U_in, void *U_out, const double
         if (e != hipSuccess) return fail(CTU_ERR_HIP, std::string("godunov launch: ") + hipGetErrorString(e));
     }
     if (par) {
+        StageTimer tm(p, 4, s);
         hipLaunchKernelGGL((k_halfstep<R>), dim3(p->t_half.n()), dim3(NT), 0, s, p->dboxes, p->t_half.d,
                            (const R *)U_in, (const R *)p->wsF[0], (const R *)p->wsF[1], (const R *)p->wsF[2],
                            (const R *)p->wsP[0], (const R *)p->wsP[1], (const R *)p->wsP[2], (R *)p->wsVh, params,
@@ -221,9 +257,14 @@ ctu_status enqueue_step(ctu_plan *p, const void *U_in, void *U_out, const double
         a.tiles = p->t_sweep[D].d;
         a.first = (D == 0);
         a.last = (D == dim - 1);
-        hipError_t e = launch_sweep<R>(D, p->combo, p->t_sweep[D].n(), a, s);
+        hipError_t e;
+        {
+            StageTimer tm(p, 5 + D, s);
+            e = launch_sweep<R>(D, p->combo, p->t_sweep[D].n(), a, s);
+        }
         if (e != hipSuccess) return fail(CTU_ERR_HIP, std::string("sweep launch: ") + hipGetErrorString(e));
     }
+    if (p->timing && p->tsteps < kMaxTimedSteps) p->tsteps++;
     return CTU_OK;
 }
 
@@ -439,6 +480,8 @@ ctu_status ctu_step_graph_capture(ctu_plan *plan, const void *U_in_dev, void *U_
         HIP_TRY(hipGraphDestroy(plan->graph));
         plan->graph = nullptr;
     }
+    bool was_timing = plan->timing;
+    plan->timing = false;
     HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
     ctu_status st2 = (plan->esize == 4)
                          ? enqueue_step<float>(plan, U_in_dev, U_out_dev, params_dev, cool_L0_dev, reg_dev, rate_dev,
@@ -447,6 +490,7 @@ ctu_status ctu_step_graph_capture(ctu_plan *plan, const void *U_in_dev, void *U_
                                                 dpp_dev, fails_dev, s);
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(s, &g);
+    plan->timing = was_timing;
     if (st2 != CTU_OK) {
         if (g) (void)hipGraphDestroy(g);
         return st2;
@@ -462,6 +506,36 @@ ctu_status ctu_step_graph_launch(ctu_plan *plan, void *stream)
 {
     if (!plan || !plan->gexec) return fail(CTU_ERR_ARG, "no captured graph");
     HIP_TRY(hipGraphLaunch(plan->gexec, (hipStream_t)stream));
+    return CTU_OK;
+}
+
+ctu_status ctu_plan_enable_timing(ctu_plan *plan, int32_t enable)
+{
+    if (!plan) return fail(CTU_ERR_ARG, "null plan");
+    if (enable && plan->tev.empty()) {
+        plan->tev.assign(2 * (size_t)kMaxTimedSteps * CTU_NSTAGE, nullptr);
+        for (auto &e : plan->tev) HIP_TRY(hipEventCreate(&e));
+    }
+    plan->tused.assign((size_t)kMaxTimedSteps * CTU_NSTAGE, 0);
+    plan->tsteps = 0;
+    plan->timing = enable != 0;
+    return CTU_OK;
+}
+
+ctu_status ctu_plan_read_timing(ctu_plan *plan, double *ms_out, int32_t *nsteps_out)
+{
+    if (!plan || !ms_out) return fail(CTU_ERR_ARG, "plan and ms_out are required");
+    for (int st = 0; st < CTU_NSTAGE; st++) ms_out[st] = 0.0;
+    for (int step = 0; step < plan->tsteps; step++)
+        for (int st = 0; st < CTU_NSTAGE; st++) {
+            size_t idx = (size_t)step * CTU_NSTAGE + st;
+            if (idx >= plan->tused.size() || !plan->tused[idx]) continue;
+            HIP_TRY(hipEventSynchronize(plan->tev[2 * idx + 1]));
+            float ms = 0.f;
+            HIP_TRY(hipEventElapsedTime(&ms, plan->tev[2 * idx], plan->tev[2 * idx + 1]));
+            ms_out[st] += ms;
+        }
+    if (nsteps_out) *nsteps_out = plan->tsteps;
     return CTU_OK;
 }
 

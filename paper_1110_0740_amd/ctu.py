@@ -26,8 +26,10 @@ NFAIL = 5
 SYMBOLS = [
     "ctu_plan_create", "ctu_plan_destroy", "ctu_plan_state_elems", "ctu_plan_workspace_bytes", "ctu_step",
     "ctu_step_graph_capture", "ctu_step_graph_launch", "ctu_cfl_rate", "ctu_prim_to_cons", "ctu_cons_to_prim",
-    "ctu_plan_set_reflux", "ctu_reflux", "ctu_last_error",
+    "ctu_plan_set_reflux", "ctu_reflux", "ctu_plan_enable_timing", "ctu_plan_read_timing", "ctu_last_error",
 ]
+NSTAGE = 8
+STAGES = ["prim", "godunov_x", "godunov_y", "godunov_z", "halfstep", "sweep_x", "sweep_y", "sweep_z"]
 
 
 class CtuOpts(C.Structure):
@@ -93,6 +95,10 @@ def lib() -> C.CDLL:
         L.ctu_plan_set_reflux.argtypes = [_vp, C.POINTER(CtuRefluxFace), C.c_int32]
         L.ctu_reflux.restype = C.c_int32
         L.ctu_reflux.argtypes = [_vp, _vp, _vp, _vp]
+        L.ctu_plan_enable_timing.restype = C.c_int32
+        L.ctu_plan_enable_timing.argtypes = [_vp, C.c_int32]
+        L.ctu_plan_read_timing.restype = C.c_int32
+        L.ctu_plan_read_timing.argtypes = [_vp, C.POINTER(C.c_double), C.POINTER(C.c_int32)]
         L.ctu_last_error.restype = C.c_char_p
         _lib = L
     return _lib
@@ -217,6 +223,16 @@ class Plan:
             for f, s in enumerate(fslots):
                 a.fine_slot[f] = s
         _check(lib().ctu_plan_set_reflux(self._h, arr, n))
+
+    def enable_timing(self, on: bool = True):
+        _check(lib().ctu_plan_enable_timing(self._h, int(on)))
+
+    def read_timing(self):
+        """(total ms per stage as a dict, number of recorded steps)."""
+        ms = (C.c_double * NSTAGE)()
+        n = C.c_int32()
+        _check(lib().ctu_plan_read_timing(self._h, ms, C.byref(n)))
+        return dict(zip(STAGES, list(ms))), n.value
 
     def reflux(self, U, reg, stream=None):
         _check(lib().ctu_reflux(self._h, _ptr(U), _ptr(reg), _stream(stream)))

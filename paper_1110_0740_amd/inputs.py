@@ -350,3 +350,82 @@ def sub_box(a: np.ndarray, lo: tuple, n: tuple, ng: int, dim: int) -> np.ndarray
             s = lo[q]
             sl[ax] = slice(s, s + n[q] + 2 * ng)
     return np.ascontiguousarray(a[tuple(sl)])
+
+
+# --------------------------------------------------------------------------
+# Device-side evaluation of the same recipes (torch), for full-size runs
+# --------------------------------------------------------------------------
+
+
+def _axis_phases(torch, box: Box, ng: int, dx: tuple, dim: int, device):
+    """exp(2 pi i x) factors per axis at ghosted cell centres, as a list of
+    functions k -> complex 1D tensor (separable form of cos(2 pi k.x + phi))."""
+    cache = []
+    for d in range(3):
+        if d >= dim:
+            x = torch.tensor([0.5 * dx[d]], dtype=torch.float64, device=device)
+        else:
+            idx = torch.arange(box.lo[d] - ng, box.lo[d] + box.n[d] + ng, dtype=torch.float64, device=device)
+            x = (idx + 0.5) * dx[d]
+        cache.append(x)
+    return cache
+
+
+def _mode_terms(torch, m: Modes, axes):
+    """Complex field sum_m a_m exp(i (2 pi k_m . x + phi_m)) as [NZ, NY, NX]."""
+    x, y, z = axes
+    out = None
+    for k, ph, a in zip(m.k, m.phi, m.amp):
+        ex = torch.exp(2j * math.pi * float(k[0]) * x.to(torch.complex128))
+        ey = torch.exp(2j * math.pi * float(k[1]) * y.to(torch.complex128))
+        ez = torch.exp(2j * math.pi * float(k[2]) * z.to(torch.complex128)) * complex(math.cos(ph), math.sin(ph))
+        term = (a * ez)[:, None, None] * ey[None, :, None] * ex[None, None, :]
+        out = term if out is None else out + term
+    return out
+
+
+def _mode_sum_t(torch, m, axes):
+    return _mode_terms(torch, m, axes).real
+
+
+def _mode_grad_t(torch, m, axes):
+    """Analytic gradient of the mode sum: d/dx_c cos(theta) = Re(2 pi i k_c e^{i theta})."""
+    x, y, z = axes
+    g = [None, None, None]
+    for k, ph, a in zip(m.k, m.phi, m.amp):
+        ex = torch.exp(2j * math.pi * float(k[0]) * x.to(torch.complex128))
+        ey = torch.exp(2j * math.pi * float(k[1]) * y.to(torch.complex128))
+        ez = torch.exp(2j * math.pi * float(k[2]) * z.to(torch.complex128)) * complex(math.cos(ph), math.sin(ph))
+        base = (a * ez)[:, None, None] * ey[None, :, None] * ex[None, None, :]
+        for c in range(3):
+            t = (2j * math.pi * float(k[c]) * base).real
+            g[c] = t if g[c] is None else g[c] + t
+    return g
+
+
+def mhd3d_fields_torch(n: int = 256, ng: int = 4, seed: int = 2000, device="cuda", v_rms: float = 1.0):
+    """:func:`mhd3d_fields` evaluated with torch on `device` (float64,
+    ghosted [9, NZ, NY, NX]); same modes, same recipe."""
+    import torch
+
+    rng = SplitMix64(seed)
+    dim = 3
+    m = {name: draw_modes(rng, dim) for name in ("rho", "p", "vx", "vy", "vz", "Ax", "Ay", "Az")}
+    box = Box((0, 0, 0), (n, n, n))
+    dx = (1.0 / n, 1.0 / n, 1.0 / n)
+    axes = _axis_phases(torch, box, ng, dx, dim, device)
+    N = n + 2 * ng
+    V = torch.zeros((NVAR, N, N, N), dtype=torch.float64, device=device)
+    V[RHO] = 1.0 + 0.5 * _mode_sum_t(torch, m["rho"], axes)
+    V[PRS] = 0.6 * (1.0 + 0.2 * _mode_sum_t(torch, m["p"], axes))
+    for c, name in enumerate(("vx", "vy", "vz")):
+        V[VX1 + c] = (v_rms / math.sqrt(3.0)) / m[name].rms() * _mode_sum_t(torch, m[name], axes)
+    A = [m["Ax"], m["Ay"], m["Az"]]
+    scale = math.sqrt(2.0 * 0.6) / curl_rms(A)
+    g0 = _mode_grad_t(torch, A[0], axes)
+    g1 = _mode_grad_t(torch, A[1], axes)
+    g2 = _mode_grad_t(torch, A[2], axes)
+    V[BX1] = scale * (g2[1] - g1[2])
+    V[BX2] = scale * (g0[2] - g2[0])
+    V[BX3] = scale * (g1[0] - g0[1])
+    return V, dict(dim=3, gamma=5.0 / 3.0, dx=dx, box=box, ng=ng)
