@@ -50,6 +50,7 @@ def parse():
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle cpu_baseline leg")
     ap.add_argument("--precision", default="both", choices=["both", "fp32", "fp64"])
+    ap.add_argument("--no-amr", action="store_true", help="skip the AMR batch leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (HBM counter calibration) and exit")
     return ap.parse_args()
@@ -94,6 +95,120 @@ def cpu_baseline(Vfull, ng, dx, gamma, sub=96, nsub=3):
     return {"value": zones / elapsed, "unit": "zone-updates/s", "cores": 1, "kind": "oracle",
             "sample": f"{nsub} sub-boxes of {sub}^3 (+4 ghosts) of the {n}^3 input, one FP64 step each, "
                       f"{elapsed:.1f} s single-threaded"}
+
+
+def amr_leg(K, W, dev, s):
+    """AMR batch: 3 levels, ratio 2, ~1500 patches of 16^3-32^3 around density
+    blobs (4 ghosts, fields evaluated at each level's resolution).  One AMR
+    step = one CTU step of every patch of every level plus the two reflux
+    launches.  FP32 batched: one plan and one captured graph per level.
+    FP64 plain: one plan per patch, eager launches, no graph."""
+    import numpy as np
+    import torch
+
+    from paper_1110_0740_amd import amr, ctu, inputs as I
+
+    ng = 4
+    h = I.amr_hierarchy()
+    tables, nslots = amr.build_tables(h.levels, h.base, ng)
+    zones = int(sum(int(np.prod(B.n)) for L in h.levels for B in L))
+    npatch = sum(len(L) for L in h.levels)
+    dt0 = 1e-4
+    ch = 0.4 * h.dx(0)[0] / dt0
+    reg = torch.zeros(9 * nslots, dtype=torch.float64, device=dev)
+    rate = torch.zeros(1, dtype=torch.float64, device=dev)
+    fails = torch.zeros(5, dtype=torch.int32, device=dev)
+    # conserved states per level, FP64, packed in box order
+    U64, offs = [], []
+    for lev, L in enumerate(h.levels):
+        o, off = 0, []
+        for B in L:
+            off.append(o)
+            o += 9 * int(np.prod([n + 2 * ng for n in B.n]))
+        U = torch.empty(o, dtype=torch.float64, device=dev)
+        go = ctu.make_opts(dim=3, recon="ppm", riemann="hlld", gamma=5.0 / 3.0, dx=h.dx(0), precision="fp64")
+        boxes = [(B.lo, B.n, lev, ob) for B, ob in zip(L, off)]
+        tmp = ctu.Plan(go, boxes, ng)
+        for B, ob in zip(L, off):
+            V = I.amr_fields_torch(h, B, ng, device=dev).reshape(-1)
+            U[ob:ob + V.numel()] = V
+        Uc = torch.empty_like(U)
+        tmp.prim_to_cons(U, Uc)
+        U64.append(Uc)
+        offs.append(off)
+        del tmp, U
+    torch.cuda.synchronize()
+    params = [torch.tensor([dt0 / (1 << lev), ch], dtype=torch.float64, device=dev) for lev in range(len(h.levels))]
+    out = {"patches": npatch, "zones": zones, "levels": [len(L) for L in h.levels], "register_slots": nslots}
+
+    # FP32 batched
+    plans, Uin, Uout = [], [], []
+    for lev, L in enumerate(h.levels):
+        go = ctu.make_opts(dim=3, recon="ppm", riemann="hlld", gamma=5.0 / 3.0, dx=h.dx(0), precision="fp32")
+        p = ctu.Plan(go, [(B.lo, B.n, lev, ob) for B, ob in zip(L, offs[lev])], ng, regfaces=tables[lev].regfaces)
+        if tables[lev].reflux:
+            p.set_reflux(tables[lev].reflux)
+        plans.append(p)
+        Uin.append(U64[lev].to(torch.float32))
+        Uout.append(torch.empty_like(Uin[-1]))
+    torch.cuda.synchronize()
+    with torch.cuda.stream(s):
+        for lev, p in enumerate(plans):
+            p.graph_capture(Uin[lev], Uout[lev], params[lev], rate, reg=reg, fails=fails, stream=s)
+
+    def amr_step32():
+        for p in plans:
+            p.graph_launch(stream=s)
+        for lev in range(len(plans) - 1):
+            plans[lev].reflux(Uout[lev], reg, stream=s)
+
+    with torch.cuda.stream(s):
+        for _ in range(W):
+            amr_step32()
+    s.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    with torch.cuda.stream(s):
+        e0.record(s)
+        for _ in range(K):
+            amr_step32()
+        e1.record(s)
+    s.synchronize()
+    ms32 = e0.elapsed_time(e1) / K
+    assert fails.sum().item() == 0, fails
+    out["fp32_batched"] = {"ms_per_step": ms32, "zone_updates_per_s": zones / (ms32 * 1e-3),
+                           "launches_per_step": len(plans) + len(plans) - 1}
+    del plans, Uin, Uout
+    torch.cuda.synchronize()
+
+    # FP64 plain, one plan per patch
+    pplans = []
+    for lev, L in enumerate(h.levels):
+        go = ctu.make_opts(dim=3, recon="ppm", riemann="hlld", gamma=5.0 / 3.0, dx=h.dx(0), precision="fp64")
+        for B, ob in zip(L, offs[lev]):
+            pplans.append((lev, ctu.Plan(go, [(B.lo, B.n, lev, ob)], ng)))
+    Uo64 = [torch.empty_like(u) for u in U64]
+    torch.cuda.synchronize()
+
+    def amr_step64():
+        for lev, p in pplans:
+            p.step(U64[lev], Uo64[lev], params[lev], rate, fails=fails, stream=s)
+
+    with torch.cuda.stream(s):
+        for _ in range(W):
+            amr_step64()
+    s.synchronize()
+    with torch.cuda.stream(s):
+        e0.record(s)
+        for _ in range(K):
+            amr_step64()
+        e1.record(s)
+    s.synchronize()
+    ms64 = e0.elapsed_time(e1) / K
+    assert fails.sum().item() == 0, fails
+    out["fp64_plain_per_patch"] = {"ms_per_step": ms64, "zone_updates_per_s": zones / (ms64 * 1e-3),
+                                   "launches_per_step": 6 * npatch}
+    out["batched_fp32_over_plain_fp64"] = ms64 / ms32
+    return out
 
 
 def main():
@@ -243,6 +358,11 @@ def main():
     if "fp64_plain" in result and "fp32_batched" in result:
         line["fp32_over_fp64"] = result["fp32_batched"]["zone_updates_per_s"] / result["fp64_plain"][
             "zone_updates_per_s"]
+    if not args.no_amr:
+        print("[bench] AMR batch leg", file=sys.stderr, flush=True)
+        del U64
+        torch.cuda.empty_cache()
+        line["amr"] = amr_leg(max(3, K // 2), min(W, 2), dev, s)
     if not args.no_cpu:
         print("[bench] oracle cpu_baseline", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(Vhost, ng, dx, gamma)

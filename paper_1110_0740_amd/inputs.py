@@ -429,3 +429,172 @@ def mhd3d_fields_torch(n: int = 256, ng: int = 4, seed: int = 2000, device="cuda
     V[BX2] = scale * (g0[2] - g2[0])
     V[BX3] = scale * (g1[0] - g0[1])
     return V, dict(dim=3, gamma=5.0 / 3.0, dx=dx, box=box, ng=ng)
+
+
+# --------------------------------------------------------------------------
+# AMR hierarchy around density blobs (3 levels, refinement ratio 2)
+# --------------------------------------------------------------------------
+
+
+@dataclass
+class Hierarchy:
+    base: int                      # level-0 cells per side of the periodic unit cube
+    levels: list                   # levels[l] = list of Box (level-l global indices)
+    blobs: list                    # (centre (3,), radius)
+    seed: int
+    modes: dict = field(default_factory=dict)
+
+    def dx(self, level: int):
+        h = 1.0 / (self.base * (1 << level))
+        return (h, h, h)
+
+
+def _blob_bump(blobs, x, widen=1.0):
+    v = 0.0
+    for c, r in blobs:
+        d = np.asarray(x) - c
+        d = d - np.round(d)
+        v = max(v, math.exp(-float(np.dot(d, d)) / (widen * r) ** 2))
+    return v
+
+
+def amr_hierarchy(seed: int = 3000, base: int = 128, base_box: int = 32, lattice: int = 32,
+                  size_range=(16, 32), nblobs: int = 8, p1=(0.75, 1.0), p2=(0.35, 1.2)) -> Hierarchy:
+    """Level 0 tiles the base^3 domain with base_box^3 boxes.  Level 1 (2x)
+    places at most one box per lattice^3 cell of a jittered lattice, with
+    probability p1[0] + p1[1] * bump, bump = max_b exp(-|x - c_b|^2/(3 r_b)^2)
+    at the lattice-cell centre; sizes are even and uniform in size_range per
+    axis, origins even, one level-1 cell of margin from the domain boundary.
+    Level 2 (4x) refines a level-1 box with probability p2[0] + p2[1] * bump
+    (width 2 r_b) into 1 or 2 children per axis inside the parent shrunk by
+    one level-1 cell (2 level-2 cells), sizes even in size_range.  Boxes are
+    therefore disjoint per level and properly nested by construction."""
+    rng = SplitMix64(seed)
+    blobs = []
+    for _ in range(nblobs):
+        c = np.array([0.15 + 0.7 * rng.uniform() for _ in range(3)])
+        r = 0.03 + 0.05 * rng.uniform()
+        blobs.append((c, r))
+    levels = [[Box((i, j, k), (base_box,) * 3, 0) for k in range(0, base, base_box)
+               for j in range(0, base, base_box) for i in range(0, base, base_box)]]
+    lo_s, hi_s = size_range
+    # level 1
+    N1 = base * 2
+    L1 = []
+    for k in range(0, N1, lattice):
+        for j in range(0, N1, lattice):
+            for i in range(0, N1, lattice):
+                org = (i, j, k)
+                ctr = np.array([(org[q] + 0.5 * lattice) / N1 for q in range(3)])
+                prob = p1[0] + p1[1] * _blob_bump(blobs, ctr, 3.0)
+                if rng.uniform() >= prob:
+                    continue
+                lo, n = [], []
+                for q in range(3):
+                    a0 = max(org[q], 2)
+                    a1 = min(org[q] + lattice, N1 - 2)
+                    span = a1 - a0
+                    nq = min(2 * rng.randint(lo_s // 2, hi_s // 2), span - span % 2)
+                    off = 2 * rng.randint(0, (span - nq) // 2)
+                    lo.append(a0 + off)
+                    n.append(nq)
+                L1.append(Box(tuple(lo), tuple(n), 1))
+    levels.append(L1)
+    # level 2
+    L2 = []
+    for P in L1:
+        ctr = np.array([(P.lo[q] + 0.5 * P.n[q]) / N1 for q in range(3)])
+        prob = p2[0] + p2[1] * _blob_bump(blobs, ctr, 2.0)
+        if rng.uniform() >= prob:
+            continue
+        segs = []
+        for q in range(3):
+            u0 = 2 * P.lo[q] + 2
+            u1 = 2 * (P.lo[q] + P.n[q]) - 2
+            usable = u1 - u0
+            parts = 2 if (usable >= 2 * lo_s and rng.uniform() < 0.75) else 1
+            width = usable // parts
+            axis = []
+            for pidx in range(parts):
+                s0 = u0 + pidx * width
+                nq = min(2 * rng.randint(lo_s // 2, hi_s // 2), width - width % 2)
+                off = 2 * rng.randint(0, (width - nq) // 2)
+                axis.append((s0 + off, nq))
+            segs.append(axis)
+        for (x0, nx) in segs[0]:
+            for (y0, ny) in segs[1]:
+                for (z0, nz) in segs[2]:
+                    L2.append(Box((x0, y0, z0), (nx, ny, nz), 2))
+    levels.append(L2)
+    return Hierarchy(base=base, levels=levels, blobs=blobs, seed=seed)
+
+
+def amr_fields(h: Hierarchy, box: Box, ng: int = 4, v_rms: float = 0.5, b_rms: float = 0.5):
+    """Primitive fields of the AMR workload on one ghosted box at its level:
+    rho = 1 + 9 max_b exp(-|x - c_b|^2 / r_b^2) (periodic minimum image,
+    contrast 10), p = 0.6, velocity and B as the 3D MHD recipe with rms
+    v_rms and b_rms; Gamma = 5/3."""
+    if not h.modes:
+        rng = SplitMix64(h.seed + 17)
+        h.modes = {name: draw_modes(rng, 3) for name in ("vx", "vy", "vz", "Ax", "Ay", "Az")}
+    m = h.modes
+    dx = h.dx(box.level)
+    X, Y, Z = cell_centres(box, ng, dx, 3)
+    V = np.zeros((NVAR,) + X.shape)
+    bump = np.zeros(X.shape)
+    for c, r in h.blobs:
+        d2 = np.zeros(X.shape)
+        for q, Q in enumerate((X, Y, Z)):
+            t = Q - c[q]
+            t = t - np.round(t)
+            d2 += t * t
+        bump = np.maximum(bump, np.exp(-d2 / (r * r)))
+    V[RHO] = 1.0 + 9.0 * bump
+    V[PRS] = 0.6
+    for c, name in enumerate(("vx", "vy", "vz")):
+        V[VX1 + c] = (v_rms / math.sqrt(3.0)) / m[name].rms() * mode_sum(m[name], X, Y, Z)
+    A = [m["Ax"], m["Ay"], m["Az"]]
+    scale = b_rms / curl_rms(A)
+    g = [mode_grad(a, X, Y, Z) for a in A]
+    V[BX1] = scale * (g[2][1] - g[1][2])
+    V[BX2] = scale * (g[0][2] - g[2][0])
+    V[BX3] = scale * (g[1][0] - g[0][1])
+    return V
+
+
+def amr_fields_torch(h: Hierarchy, box: Box, ng: int = 4, device="cuda", v_rms: float = 0.5, b_rms: float = 0.5):
+    """:func:`amr_fields` evaluated with torch on `device` (float64)."""
+    import torch
+
+    if not h.modes:
+        rng = SplitMix64(h.seed + 17)
+        h.modes = {name: draw_modes(rng, 3) for name in ("vx", "vy", "vz", "Ax", "Ay", "Az")}
+    m = h.modes
+    dx = h.dx(box.level)
+    axes = _axis_phases(torch, box, ng, dx, 3, device)
+    x, y, z = axes
+    shape = (z.numel(), y.numel(), x.numel())
+    V = torch.zeros((NVAR,) + shape, dtype=torch.float64, device=device)
+    bump = torch.zeros(shape, dtype=torch.float64, device=device)
+    for c, r in h.blobs:
+        tx = x - c[0]
+        tx = tx - torch.round(tx)
+        ty = y - c[1]
+        ty = ty - torch.round(ty)
+        tz = z - c[2]
+        tz = tz - torch.round(tz)
+        d2 = tz[:, None, None] ** 2 + ty[None, :, None] ** 2 + tx[None, None, :] ** 2
+        bump = torch.maximum(bump, torch.exp(-d2 / (r * r)))
+    V[RHO] = 1.0 + 9.0 * bump
+    V[PRS] = 0.6
+    for c, name in enumerate(("vx", "vy", "vz")):
+        V[VX1 + c] = (v_rms / math.sqrt(3.0)) / m[name].rms() * _mode_sum_t(torch, m[name], axes)
+    A = [m["Ax"], m["Ay"], m["Az"]]
+    scale = b_rms / curl_rms(A)
+    g0 = _mode_grad_t(torch, A[0], axes)
+    g1 = _mode_grad_t(torch, A[1], axes)
+    g2 = _mode_grad_t(torch, A[2], axes)
+    V[BX1] = scale * (g2[1] - g1[2])
+    V[BX2] = scale * (g0[2] - g2[0])
+    V[BX3] = scale * (g1[0] - g0[1])
+    return V

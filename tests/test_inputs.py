@@ -37,3 +37,14 @@ def test_periodic_ghosts_equal_images():
     W = V.copy()
     I.fill_periodic(W, 4, 3)
     assert np.max(np.abs(W - V)) < 1e-12
+
+
+def test_amr_fields_torch_matches_numpy():
+    h = I.amr_hierarchy(seed=3001, base=32, base_box=16, lattice=16, size_range=(8, 16))
+    for lev in (0, 1, 2):
+        if not h.levels[lev]:
+            continue
+        B = h.levels[lev][0]
+        Vn = I.amr_fields(h, B, 4)
+        Vt = I.amr_fields_torch(h, B, 4, device="cpu")
+        assert np.max(np.abs(Vt.numpy() - Vn)) < 1e-12
