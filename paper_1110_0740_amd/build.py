@@ -29,31 +29,39 @@ FLAGS = [
 ]
 
 
-def _compile(unit: str, extra: list[str]) -> str:
+# FP32 translation unit: divide and square root as the hardware's
+# approximate reciprocal / root (a few ulp) instead of the correctly rounded
+# expansions; FP64 keeps the correctly rounded forms.
+UNIT_FLAGS = {"ctu_inst_f32.hip": ["-fno-hip-fp32-correctly-rounded-divide-sqrt"]}
+
+
+def _compile(unit: str, extra: list[str], build_dir: str = BUILD) -> str:
     src = os.path.join(CSRC, unit)
-    obj = os.path.join(BUILD, unit.replace(".hip", ".o"))
-    cmd = [HIPCC, *FLAGS, *extra, "-c", src, "-o", obj]
+    obj = os.path.join(build_dir, unit.replace(".hip", ".o"))
+    cmd = [HIPCC, *FLAGS, *UNIT_FLAGS.get(unit, []), *extra, "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {unit}:\n{r.stderr[-8000:]}")
     return obj
 
 
-def build(extra: list[str] | None = None, verbose: bool = False) -> str:
-    """Compile every HIP source and link libctu.so; always rebuilds."""
+def build(extra: list[str] | None = None, verbose: bool = False, out: str = OUT) -> str:
+    """Compile every HIP source and link the library (default: the in-tree
+    libctu.so); always rebuilds."""
     extra = list(extra or [])
-    os.makedirs(BUILD, exist_ok=True)
+    build_dir = BUILD if out == OUT else out + ".objs"
+    os.makedirs(build_dir, exist_ok=True)
     with ThreadPoolExecutor(max_workers=len(UNITS)) as ex:
-        objs = list(ex.map(lambda u: _compile(u, extra), UNITS))
-    tmp = OUT + ".tmp"
+        objs = list(ex.map(lambda u: _compile(u, extra, build_dir), UNITS))
+    tmp = out + ".tmp"
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr[-4000:]}")
-    os.replace(tmp, OUT)
+    os.replace(tmp, out)
     if verbose:
-        print(f"built {OUT}")
-    return OUT
+        print(f"built {out}")
+    return out
 
 
 if __name__ == "__main__":

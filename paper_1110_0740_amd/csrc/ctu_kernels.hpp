@@ -42,9 +42,11 @@ struct KReg {
     long long slot;
 };
 
-__device__ __forceinline__ long long cidx(const KBox &bx, int i, int j, int k)
+// cell offset inside one box block (a box holds fewer than 2^31 / 9 cells,
+// checked at plan creation, so 32-bit offsets address every variable)
+__device__ __forceinline__ int cidx(const KBox &bx, int i, int j, int k)
 {
-    return ((long long)k * bx.N[1] + j) * bx.N[0] + i;
+    return (k * bx.N[1] + j) * bx.N[0] + i;
 }
 
 template <int D> __device__ __forceinline__ void unit(int &di, int &dj, int &dk)
@@ -144,10 +146,10 @@ __device__ __forceinline__ void parab_flux(const R *Vf, const KBox &bx, int i, i
     constexpr int n = Ax<D>::n, t = Ax<D>::t, b = Ax<D>::b;
     int di, dj, dk;
     unit<D>(di, dj, dk);
-    const long long cs = bx.cells;
-    const long long cB = cidx(bx, i, j, k);
-    const long long cA = cidx(bx, i - di, j - dj, k - dk);
-    auto fv = [&](int f, long long c) -> R {
+    const int cs = (int)bx.cells;
+    const int cB = cidx(bx, i, j, k);
+    const int cA = cidx(bx, i - di, j - dj, k - dk);
+    auto fv = [&](int f, int c) -> R {
         if (f < 3) return Vf[(MX1 + f) * cs + c];
         if (f < 6) return Vf[(BX1 + f - 3) * cs + c];
         return Vf[PRS * cs + c] / Vf[RHO * cs + c];
@@ -261,17 +263,17 @@ __global__ __launch_bounds__(NT) void k_godunov(const KBox *boxes, const KTile *
             org[q] = bx.g[q] - 1;
         }
     }
-    long long it = (long long)tl.a + threadIdx.x;
-    long long tot = (long long)ext[0] * ext[1] * ext[2];
+    const int it = tl.a + (int)threadIdx.x;
+    const int tot = ext[0] * ext[1] * ext[2];
     if (it >= tot) return;
-    int i = org[0] + (int)(it % ext[0]);
-    int j = org[1] + (int)((it / ext[0]) % ext[1]);
-    int k = org[2] + (int)(it / ((long long)ext[0] * ext[1]));
+    const int i = org[0] + it % ext[0];
+    const int j = org[1] + (it / ext[0]) % ext[1];
+    const int k = org[2] + it / (ext[0] * ext[1]);
     int di, dj, dk;
     unit<D>(di, dj, dk);
-    const long long cs = bx.cells;
+    const int cs = (int)bx.cells;
     const R *Vb = V + bx.woff;
-    long long cB = cidx(bx, i, j, k), cA = cidx(bx, i - di, j - dj, k - dk);
+    const int cB = cidx(bx, i, j, k), cA = cidx(bx, i - di, j - dj, k - dk);
     R VL[NV], VR[NV], F[NV];
 #pragma unroll
     for (int q = 0; q < NV; q++) {
@@ -328,17 +330,17 @@ __global__ __launch_bounds__(NT) void k_halfstep(const KBox *boxes, const KTile 
         ext[q] = (q < o.dim) ? bx.n[q] + 2 : 1;
         org[q] = (q < o.dim) ? bx.g[q] - 1 : 0;
     }
-    long long it = (long long)tl.a + threadIdx.x;
-    long long tot = (long long)ext[0] * ext[1] * ext[2];
+    const int it = tl.a + (int)threadIdx.x;
+    const int tot = ext[0] * ext[1] * ext[2];
     if (it >= tot) return;
-    int i = org[0] + (int)(it % ext[0]);
-    int j = org[1] + (int)((it / ext[0]) % ext[1]);
-    int k = org[2] + (int)(it / ((long long)ext[0] * ext[1]));
-    const long long cs = bx.cells;
-    long long c = cidx(bx, i, j, k);
+    const int i = org[0] + it % ext[0];
+    const int j = org[1] + (it / ext[0]) % ext[1];
+    const int k = org[2] + it / (ext[0] * ext[1]);
+    const int cs = (int)bx.cells;
+    const int c = cidx(bx, i, j, k);
     const R *F[3] = { Fx + bx.woff, Fy + bx.woff, Fz ? Fz + bx.woff : nullptr };
     const R *P[3] = { Px + bx.woff, Py + bx.woff, Pz ? Pz + bx.woff : nullptr };
-    long long cp[3] = { cidx(bx, i + 1, j, k), cidx(bx, i, j + 1, k), cidx(bx, i, j, k + 1) };
+    const int cp[3] = { cidx(bx, i + 1, j, k), cidx(bx, i, j + 1, k), cidx(bx, i, j, k + 1) };
     R hdt = R(0.5 * params[0]);
     R u[NV], v[NV];
 #pragma unroll
@@ -391,8 +393,20 @@ template <typename R> struct SweepArgs {
     int first, last;  // first / last sweep of the step
 };
 
+// Waves per SIMD the sweep is compiled for: the register budget is 512 /
+// waves VGPRs.  FP32 fits two waves without spills; FP64 spills some of its
+// doubled state at two waves, which measures faster on MI355X than one
+// spill-free wave (13.5 vs 17.1 ms for a 256^3 step).
+#ifndef CTU_SWEEP_WAVES_F32
+#define CTU_SWEEP_WAVES_F32 2
+#endif
+#ifndef CTU_SWEEP_WAVES_F64
+#define CTU_SWEEP_WAVES_F64 2
+#endif
+
 template <int D, int PHYS, int PRED, int RK, int RS, typename R>
-__global__ __launch_bounds__(NT, 2) void k_sweep(SweepArgs<R> a)
+__global__ __launch_bounds__(NT, (sizeof(R) == 4 ? CTU_SWEEP_WAVES_F32 : CTU_SWEEP_WAVES_F64)) void k_sweep(
+    SweepArgs<R> a)
 {
     constexpr int DEL = (D == 0) ? 1 : 64;
     __shared__ R sP[NV][NT];
@@ -408,7 +422,7 @@ __global__ __launch_bounds__(NT, 2) void k_sweep(SweepArgs<R> a)
     const KBox bx = a.boxes[tl.box];
     const KOpts &o = a.o;
     const int dim = o.dim;
-    const long long cs = bx.cells;
+    const int cs = (int)bx.cells;
     const int nD = bx.n[D];
     const int Lc = nD + 2;
     // transverse axes of D (t0 < t1 by direction index)
@@ -434,6 +448,12 @@ __global__ __launch_bounds__(NT, 2) void k_sweep(SweepArgs<R> a)
     int di, dj, dk;
     unit<D>(di, dj, dk);
     const R *Vb = a.V + bx.woff;
+    const R *Ub = a.U + bx.uoff;
+    R *Uob = a.Uout + bx.uoff;
+    const R *Fb[3] = { a.Fn[0] ? a.Fn[0] + bx.woff : nullptr, a.Fn[1] ? a.Fn[1] + bx.woff : nullptr,
+                       a.Fn[2] ? a.Fn[2] + bx.woff : nullptr };
+    const R *Pb[3] = { a.Pn[0] ? a.Pn[0] + bx.woff : nullptr, a.Pn[1] ? a.Pn[1] + bx.woff : nullptr,
+                       a.Pn[2] ? a.Pn[2] + bx.woff : nullptr };
     double rate_loc = 0.0, dpp_loc = 0.0;
 
     for (int base = 0; base < items; base += NT) {
@@ -455,10 +475,10 @@ __global__ __launch_bounds__(NT, 2) void k_sweep(SweepArgs<R> a)
         if (D == 0) { ci = cD; cj = bx.g[1] + tc0; ck = bx.g[2] + tc1; }
         if (D == 1) { ci = bx.g[0] + tc0; cj = cD; ck = bx.g[2] + tc1; }
         if (D == 2) { ci = bx.g[0] + tc0; cj = bx.g[1] + tc1; ck = cD; }
-        const long long c = valid ? cidx(bx, ci, cj, ck) : 0;
-        const long long sD = (D == 0) ? 1 : (D == 1 ? (long long)bx.N[0] : (long long)bx.N[0] * bx.N[1]);
+        const int c = valid ? cidx(bx, ci, cj, ck) : 0;
+        const int sD = (D == 0) ? 1 : (D == 1 ? bx.N[0] : bx.N[0] * bx.N[1]);
 
-        R Um[NV], Vc[NV], Vl[NV];
+        R Um[NV];
         int fl = 0;
         if (valid) {
             // ---- normal predictor (Sec. 3.2 / 3.3) ----
@@ -468,11 +488,6 @@ __global__ __launch_bounds__(NT, 2) void k_sweep(SweepArgs<R> a)
             for (int l = l0; l < l1; l++)
 #pragma unroll
                 for (int q = 0; q < NV; q++) Vs[l][q] = Vb[q * cs + c + (l - 2) * sD];
-#pragma unroll
-            for (int q = 0; q < NV; q++) {
-                Vc[q] = Vs[2][q];
-                Vl[q] = Vs[1][q];
-            }
             R Vm[NV], Vp[NV];
             if (o.hyp_off) {
 #pragma unroll
@@ -482,7 +497,7 @@ __global__ __launch_bounds__(NT, 2) void k_sweep(SweepArgs<R> a)
             } else {
                 R U0[NV];
 #pragma unroll
-                for (int q = 0; q < NV; q++) U0[q] = a.U[bx.uoff + q * cs + c];
+                for (int q = 0; q < NV; q++) U0[q] = Ub[q * cs + c];
                 fl |= predict_mh<D, PHYS>(Vs, U0, o, gam, dtdx, ch, Vm, Vp);
             }
             R Up[NV];
@@ -492,10 +507,10 @@ __global__ __launch_bounds__(NT, 2) void k_sweep(SweepArgs<R> a)
 #pragma unroll
             for (int e = 0; e < 3; e++) {
                 if (e >= dim) continue;
-                const long long se = (e == 0) ? 1 : (e == 1 ? (long long)bx.N[0] : (long long)bx.N[0] * bx.N[1]);
+                const int se = (e == 0) ? 1 : (e == 1 ? bx.N[0] : bx.N[0] * bx.N[1]);
                 const R ie = R(1.0 / bx.dx[e]);
                 if (e != D) {
-                    const R *Fe = a.Fn[e] + bx.woff;
+                    const R *Fe = Fb[e];
 #pragma unroll
                     for (int q = 0; q < NV; q++) {
                         R tr = -(Fe[q * cs + c + se] - Fe[q * cs + c]) * ie * hdt;
@@ -504,7 +519,7 @@ __global__ __launch_bounds__(NT, 2) void k_sweep(SweepArgs<R> a)
                     }
                 }
                 if (o.parab) {
-                    const R *Pe = a.Pn[e] + bx.woff;
+                    const R *Pe = Pb[e];
 #pragma unroll
                     for (int q = 0; q < NV; q++) {
                         R tr = (Pe[q * cs + c + se] - Pe[q * cs + c]) * ie * hdt;
@@ -527,13 +542,14 @@ __global__ __launch_bounds__(NT, 2) void k_sweep(SweepArgs<R> a)
             int fL = c2p<PHYS>(UL, VL, gam, Wg);
             int fR = c2p<PHYS>(Um, VR, gam, Wg);
             fl |= fL | fR;
+            // rare fallback to the cell-centred states: reloaded, not kept live
             if (fL) {
 #pragma unroll
-                for (int q = 0; q < NV; q++) VL[q] = Vl[q];
+                for (int q = 0; q < NV; q++) VL[q] = Vb[q * cs + c - sD];
             }
             if (fR) {
 #pragma unroll
-                for (int q = 0; q < NV; q++) VR[q] = Vc[q];
+                for (int q = 0; q < NV; q++) VR[q] = Vb[q * cs + c];
             }
             R pL = VL[PRS], pR = VR[PRS], rL = VL[RHO], rR = VR[RHO];
             R smax = R(0);
@@ -576,14 +592,14 @@ __global__ __launch_bounds__(NT, 2) void k_sweep(SweepArgs<R> a)
 
         // ---- conservative update (Eq. update) of the cell below the item ----
         if (valid && s >= 2) {
-            const long long cu = c - sD;
+            const int cu = c - sD;
             R lamc = fmax(sL[tid], (tid >= DEL) ? sL[tid - DEL] : cL[tid]) / dxD;
             R u[NV];
-            const R *Ub = a.first ? a.U : a.Uout;
+            const R *Ubase = a.first ? Ub : Uob;
 #pragma unroll
             for (int q = 0; q < NV; q++) {
                 R Flo = (tid >= DEL) ? sF[q][tid - DEL] : cF[q][tid];
-                u[q] = Ub[bx.uoff + q * cs + cu] - dtdx * (sF[q][tid] - Flo);
+                u[q] = Ubase[q * cs + cu] - dtdx * (sF[q][tid] - Flo);
             }
             R lamt = lamc;
             if (o.parab) {
@@ -595,7 +611,9 @@ __global__ __launch_bounds__(NT, 2) void k_sweep(SweepArgs<R> a)
                 // ---- split point-local sources (Sec. 3.1) ----
                 if (o.glm) {
                     R dxm = R(bx.dx[0]);
-                    for (int e = 1; e < dim; e++) dxm = fmin(dxm, R(bx.dx[e]));
+#pragma unroll
+                    for (int e = 1; e < 3; e++)
+                        if (e < dim) dxm = fmin(dxm, R(bx.dx[e]));
                     u[PSI] *= exp(-R(o.glm_alpha) * ch * dt / dxm);
                 }
                 if (o.cooling && a.L0) {
@@ -616,14 +634,16 @@ __global__ __launch_bounds__(NT, 2) void k_sweep(SweepArgs<R> a)
                 if (o.parab) {
                     R rho_h = a.Vh[bx.woff + RHO * cs + cu];
                     R Dc = diff_coeff(o, rho_h, gam);
-                    for (int e = 0; e < dim; e++) r += 2.0 * (double)Dc / (bx.dx[e] * bx.dx[e]);
+#pragma unroll
+                    for (int e = 0; e < 3; e++)
+                        if (e < dim) r += 2.0 * (double)Dc / (bx.dx[e] * bx.dx[e]);
                 }
                 rate_loc = fmax(rate_loc, r);
             } else if (!o.parab) {
                 rate_loc = fmax(rate_loc, (double)lamt);
             }
 #pragma unroll
-            for (int q = 0; q < NV; q++) a.Uout[bx.uoff + q * cs + cu] = u[q];
+            for (int q = 0; q < NV; q++) Uob[q * cs + cu] = u[q];
         }
         count_fails(fl, a.fails);
         __syncthreads();
@@ -657,14 +677,14 @@ __global__ __launch_bounds__(NT) void k_cfl(const KBox *boxes, const KTile *tile
     __shared__ double red[NT / 64];
     KTile tl = tiles[blockIdx.x];
     const KBox &bx = boxes[tl.box];
-    long long it = (long long)tl.a + threadIdx.x;
-    long long tot = (long long)bx.n[0] * bx.n[1] * bx.n[2];
+    const int it = tl.a + (int)threadIdx.x;
+    const int tot = bx.n[0] * bx.n[1] * bx.n[2];
     double r = 0.0;
     if (it < tot) {
-        int i = bx.g[0] + (int)(it % bx.n[0]);
-        int j = bx.g[1] + (int)((it / bx.n[0]) % bx.n[1]);
-        int k = bx.g[2] + (int)(it / ((long long)bx.n[0] * bx.n[1]));
-        long long c = cidx(bx, i, j, k);
+        int i = bx.g[0] + it % bx.n[0];
+        int j = bx.g[1] + (it / bx.n[0]) % bx.n[1];
+        int k = bx.g[2] + it / (bx.n[0] * bx.n[1]);
+        int c = cidx(bx, i, j, k);
         R u[NV], v[NV];
 #pragma unroll
         for (int q = 0; q < NV; q++) u[q] = U[bx.uoff + q * bx.cells + c];
@@ -681,7 +701,9 @@ __global__ __launch_bounds__(NT) void k_cfl(const KBox *boxes, const KTile *tile
         }
         if (o.parab) {
             R Dc = diff_coeff(o, v[RHO], gam);
-            for (int e = 0; e < o.dim; e++) r += 2.0 * (double)Dc / (bx.dx[e] * bx.dx[e]);
+#pragma unroll
+            for (int e = 0; e < 3; e++)
+                if (e < o.dim) r += 2.0 * (double)Dc / (bx.dx[e] * bx.dx[e]);
         }
     }
     double rb = block_max(r, red);
@@ -708,7 +730,7 @@ __global__ __launch_bounds__(NT) void k_reflux(const KBox *boxes, const KRefl *e
     int e0 = cell_start[cidx_], e1 = cell_start[cidx_ + 1];
     KRefl first = ent[e0];
     const KBox &bx = boxes[first.box];
-    long long c = cidx(bx, first.i, first.j, first.k);
+    int c = cidx(bx, first.i, first.j, first.k);
     double du[NV];
 #pragma unroll
     for (int q = 0; q < NV; q++) du[q] = 0.0;

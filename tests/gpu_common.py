@@ -9,15 +9,28 @@ from paper_1110_0740_amd import ctu, inputs as I
 DEV = torch.device("cuda:0")
 
 
-def l1rel(got, ref, ng, dim, ch=1.0):
-    """Per-variable relative L1 over interior cells, sum|got-ref| / sum|ref|.
-    psi is measured against c_h * sum|B| (its natural scale), since it starts
-    at zero and stays small."""
+def l1rel(got, ref, ng, dim, ch=1.0, physics="mhd"):
+    """Per-variable relative L1 over interior cells, sum|got - ref| / S_q.
+
+    S_q = sum|ref_q|, except for variables that can vanish identically over a
+    region, which are measured against their natural scale instead:
+    momentum components against sum sqrt(2 rho E) (MHD, |m|^2 <= 2 rho E) or
+    sum (E + D) (RMHD, |m| <= E + D); each B component against sum|B|/3;
+    psi against c_h sum|B|/3."""
     g = I.interior(got, ng, dim).reshape(9, -1).astype(np.float64)
     r = I.interior(ref, ng, dim).reshape(9, -1)
     num = np.abs(g - r).sum(axis=1)
     den = np.abs(r).sum(axis=1)
-    den[8] = max(den[8], ch * np.abs(r[5:8]).sum() / 3.0)
+    if physics == "rmhd":
+        mscale = (np.abs(r[4]) + np.abs(r[0])).sum()
+    else:
+        mscale = np.sqrt(2.0 * np.abs(r[0]) * np.abs(r[4])).sum()
+    bscale = np.sqrt((r[5:8] ** 2).sum(axis=0)).sum() / 3.0
+    for q in (1, 2, 3):
+        den[q] = max(den[q], mscale)
+    for q in (5, 6, 7):
+        den[q] = max(den[q], bscale)
+    den[8] = max(den[8], ch * bscale)
     return num / np.maximum(den, 1e-300)
 
 

@@ -1,0 +1,103 @@
+"""Full-size parity: the whole 256^3 (3D MHD, non-ideal MHD) and 192^3
+(RMHD) steps run on the GPU in the launch configuration the bench times;
+the oracle recomputes sampled 8^3 sub-boxes (corners, edges and interior
+positions) exactly from the same input, and the two are compared there."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_1110_0740_amd import ctu, inputs as I
+from tests.gpu_common import DEV, l1rel
+
+pytestmark = pytest.mark.gpu
+
+NG = 4
+SUB = 8
+
+
+def sample_origins(n, rng):
+    pts = [(0, 0, 0), (n - SUB, n - SUB, n - SUB), (n - SUB, 0, n // 2), (n // 2 - 3, n // 3 + 1, 0)]
+    for _ in range(4):
+        pts.append(tuple(int(rng.integers(0, n - SUB + 1)) for _ in range(3)))
+    return pts
+
+
+def run_fullsize(V, n, gamma, dx, precision, cfl, okw, L0=None, chmax=None, seed=0):
+    physics = okw.get("physics", "mhd")
+    oo = O.make_opts(dim=3, gamma=gamma, dx=dx, **okw)
+    U = O.prim2cons(oo, V)
+    rate0 = O.cfl_rate(oo, U, NG)
+    dt = cfl / rate0
+    ch = cfl * dx[0] / dt
+    if chmax is not None:
+        ch = min(ch, chmax)
+    go = ctu.make_opts(dim=3, gamma=gamma, dx=dx, precision=precision, **okw)
+    plan = ctu.Plan(go, [((0, 0, 0), (n, n, n), 0, 0)], NG)
+    tdt = torch.float32 if precision == "fp32" else torch.float64
+    Ud = torch.from_numpy(U.reshape(-1)).to(tdt).to(DEV)
+    Uo = Ud.clone()
+    L0d = torch.from_numpy(L0.reshape(-1)).to(tdt).to(DEV) if L0 is not None else None
+    params = torch.tensor([dt, ch], dtype=torch.float64, device=DEV)
+    rate = torch.zeros(1, dtype=torch.float64, device=DEV)
+    fails = torch.zeros(5, dtype=torch.int32, device=DEV)
+    plan.step(Ud, Uo, params, rate, L0=L0d, fails=fails)
+    torch.cuda.synchronize()
+    got = Uo.cpu().numpy().astype(np.float64).reshape(U.shape)
+    del Ud, Uo
+    rng = np.random.default_rng(seed)
+    worst = np.zeros(9)
+    for lo in sample_origins(n, rng):
+        Us = I.sub_box(U, lo, (SUB,) * 3, NG, 3)
+        L0s = I.sub_box(L0[None], lo, (SUB,) * 3, NG, 3)[0] if L0 is not None else None
+        ref, _, _, _ = O.step(oo, Us, NG, dt, ch, L0=L0s)
+        gs = I.sub_box(got, lo, (SUB,) * 3, NG, 3)
+        worst = np.maximum(worst, l1rel(gs, ref, NG, 3, ch, physics))
+    return worst, fails.cpu().tolist(), rate.item(), rate0
+
+
+@pytest.mark.parametrize("precision,tol", [("fp32", 2e-6), ("fp64", 1e-12)])
+def test_mhd3d_256_fullsize_sampled(precision, tol):
+    n = 256
+    Vt, meta = I.mhd3d_fields_torch(n=n, ng=NG, seed=2000, device=DEV)
+    V = Vt.cpu().numpy()
+    del Vt
+    worst, fails, rate, rate0 = run_fullsize(V, n, meta["gamma"], meta["dx"], precision, 0.4,
+                                             dict(recon="ppm", riemann="hlld"), seed=1)
+    assert fails == [0] * 5
+    assert worst.max() <= tol, worst
+    assert 0.5 * rate0 < rate < 2.0 * rate0
+
+
+@pytest.mark.parametrize("precision,tol", [("fp32", 2e-6), ("fp64", 1e-12)])
+def test_rmhd_192_fullsize_sampled(precision, tol):
+    n = 192
+    V, meta = I.rmhd3d_fields(n=n, ng=NG, seed=4000)
+    worst, fails, rate, rate0 = run_fullsize(V, n, meta["gamma"], meta["dx"], precision, 0.3,
+                                             dict(physics="rmhd", recon="lin_mc", predictor="mh", riemann="hll"),
+                                             chmax=1.0, seed=2)
+    assert worst.max() <= tol, (worst, fails)
+
+
+@pytest.mark.parametrize("precision,tol", [("fp32", 2e-6), ("fp64", 1e-12)])
+def test_nonideal_256_fullsize_sampled(precision, tol):
+    n = 256
+    Vt, meta = I.mhd3d_fields_torch(n=n, ng=NG, seed=5000, device=DEV)
+    V = Vt.cpu().numpy()
+    del Vt
+    G = meta["gamma"]
+    coef = I.nonideal_coeffs(5001)
+    oo = O.make_opts(dim=3, gamma=G, dx=meta["dx"], recon="ppm", riemann="hlld")
+    X, Y, Z = I.cell_centres(meta["box"], NG, meta["dx"], 3)
+    T = V[4] / V[0]
+    # cooling times t_c = dt0 10^{3 S}, with dt0 the hyperbolic CFL step of U^0
+    dt0 = 0.4 / O.cfl_rate(oo, O.prim2cons(oo, V), NG)
+    tc = I.cooling_time_field(5002, X, Y, Z, dt0)
+    L0 = V[4] / ((G - 1) * V[0] ** 2 * np.sqrt(T) * tc)
+    if precision == "fp32":
+        L0 = L0.astype(np.float32).astype(np.float64)
+    okw = dict(recon="ppm", riemann="hlld", parabolic_mask=7, tc_phi=0.3, cooling=True, cool_beta=0.5,
+               T_floor=0.1 * float(T.min()), **coef)
+    worst, fails, rate, rate0 = run_fullsize(V, n, G, meta["dx"], precision, 0.4, okw, L0=L0, seed=3)
+    assert fails == [0] * 5
+    assert worst.max() <= tol, worst

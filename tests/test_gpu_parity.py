@@ -45,7 +45,7 @@ def _compare_one_step(V, meta, precision, tol, n_int, **kw):
     st = GpuStepper(single_box_plan(go, n_int, ng), U.shape, precision)
     Ug = U.astype(np.float32).astype(np.float64) if precision == "fp32" else U
     out, rate, dpp, fails = st.step(Ug, dt, ch, L0=L0)
-    e = l1rel(out, Uref, ng, dim, ch)
+    e = l1rel(out, Uref, ng, dim, ch, kw.get("physics", "mhd"))
     assert fails == [0] * 5 and fref == [0] * 5, (fails, fref)
     assert e.max() <= tol, e
     assert abs(rate - rref) <= max(tol, 1e-7 if precision == "fp32" else 1e-13) * rref * 10, (rate, rref)
