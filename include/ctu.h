@@ -215,7 +215,8 @@ ctu_status ctu_reflux(ctu_plan *coarse_plan, void *U_dev, const double *reg_dev,
  * recorded.  ctu_plan_read_timing synchronises on the recorded events and
  * writes the total milliseconds per stage into ms_out[CTU_NSTAGE] and the
  * number of recorded steps into nsteps_out.  Stages: 0 primitive recovery,
- * 1-3 Godunov fluxes x/y/z, 4 half step, 5-7 direction sweeps x/y/z. */
+ * 1 the t^n fluxes and transverse increments (with the half step), 2-4
+ * unused, 5-7 direction sweeps x/y/z. */
 #define CTU_NSTAGE 8
 ctu_status ctu_plan_enable_timing(ctu_plan *plan, int32_t enable);
 ctu_status ctu_plan_read_timing(ctu_plan *plan, double *ms_out, int32_t *nsteps_out);

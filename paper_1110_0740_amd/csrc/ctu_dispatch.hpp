@@ -25,10 +25,8 @@ __host__ inline bool combo_supported(const Combo &c)
 
 hipError_t launch_sweep_f32(int D, const Combo &c, int nblocks, const SweepArgs<float> &a, hipStream_t s);
 hipError_t launch_sweep_f64(int D, const Combo &c, int nblocks, const SweepArgs<double> &a, hipStream_t s);
-hipError_t launch_godunov_f32(int D, const Combo &c, int nblocks, const KBox *b, const KTile *t, const float *V,
-                              float *Fn, float *Pn, const double *params, const KOpts &o, hipStream_t s);
-hipError_t launch_godunov_f64(int D, const Combo &c, int nblocks, const KBox *b, const KTile *t, const double *V,
-                              double *Fn, double *Pn, const double *params, const KOpts &o, hipStream_t s);
+hipError_t launch_tcouple_f32(int dim, int par, const Combo &c, int nblocks, const TArgs<float> &a, hipStream_t s);
+hipError_t launch_tcouple_f64(int dim, int par, const Combo &c, int nblocks, const TArgs<double> &a, hipStream_t s);
 
 template <typename R> inline hipError_t launch_sweep(int D, const Combo &c, int nb, const SweepArgs<R> &a, hipStream_t s);
 template <> inline hipError_t launch_sweep<float>(int D, const Combo &c, int nb, const SweepArgs<float> &a, hipStream_t s)
@@ -77,27 +75,22 @@ template <> inline hipError_t launch_sweep<double>(int D, const Combo &c, int nb
         if (D == 1) return sweep_dir<1>(c, nb, a, s);                                                            \
         return sweep_dir<2>(c, nb, a, s);                                                                        \
     }                                                                                                            \
-    template <int D>                                                                                             \
-    static hipError_t god_dir(const Combo &c, int nb, const KBox *b, const KTile *t, const R *V, R *Fn, R *Pn,  \
-                              const double *p, const KOpts &o, hipStream_t s)                                   \
+    template <int DIM, int PAR>                                                                                  \
+    static hipError_t tc_one(const Combo &c, int nb, const TArgs<R> &a, hipStream_t s)                          \
     {                                                                                                            \
         if (c.phys == PHYS_RMHD)                                                                                 \
-            hipLaunchKernelGGL((k_godunov<D, PHYS_RMHD, RS_HLL, R>), dim3(nb), dim3(NT), 0, s, b, t, V, Fn, Pn, \
-                               p, o);                                                                            \
+            hipLaunchKernelGGL((k_tcouple<DIM, PHYS_RMHD, RS_HLL, 0, R>), dim3(nb), dim3(NT), 0, s, a);         \
         else if (c.rs == RS_HLLD)                                                                                \
-            hipLaunchKernelGGL((k_godunov<D, PHYS_MHD, RS_HLLD, R>), dim3(nb), dim3(NT), 0, s, b, t, V, Fn, Pn, \
-                               p, o);                                                                            \
+            hipLaunchKernelGGL((k_tcouple<DIM, PHYS_MHD, RS_HLLD, PAR, R>), dim3(nb), dim3(NT), 0, s, a);       \
         else                                                                                                     \
-            hipLaunchKernelGGL((k_godunov<D, PHYS_MHD, RS_HLL, R>), dim3(nb), dim3(NT), 0, s, b, t, V, Fn, Pn,  \
-                               p, o);                                                                            \
+            hipLaunchKernelGGL((k_tcouple<DIM, PHYS_MHD, RS_HLL, PAR, R>), dim3(nb), dim3(NT), 0, s, a);        \
         return hipGetLastError();                                                                                \
     }                                                                                                            \
-    hipError_t launch_godunov_##SUFFIX(int D, const Combo &c, int nb, const KBox *b, const KTile *t,           \
-                                       const R *V, R *Fn, R *Pn, const double *p, const KOpts &o, hipStream_t s) \
+    hipError_t launch_tcouple_##SUFFIX(int dim, int par, const Combo &c, int nb, const TArgs<R> &a,            \
+                                       hipStream_t s)                                                            \
     {                                                                                                            \
         if (nb <= 0) return hipSuccess;                                                                          \
-        if (D == 0) return god_dir<0>(c, nb, b, t, V, Fn, Pn, p, o, s);                                          \
-        if (D == 1) return god_dir<1>(c, nb, b, t, V, Fn, Pn, p, o, s);                                          \
-        return god_dir<2>(c, nb, b, t, V, Fn, Pn, p, o, s);                                                      \
+        if (dim == 2) return par ? tc_one<2, 1>(c, nb, a, s) : tc_one<2, 0>(c, nb, a, s);                        \
+        return par ? tc_one<3, 1>(c, nb, a, s) : tc_one<3, 0>(c, nb, a, s);                                      \
     }                                                                                                            \
     }

@@ -237,126 +237,209 @@ template <typename R> __device__ __forceinline__ R diff_coeff(const KOpts &o, R 
 }
 
 // ---------------------------------------------------------------------------
-// k_godunov<D>: faces between c - e_D and c (stored at c).  Region: along D
-// the faces of the interior (one more on each side with parabolic terms),
-// across D one halo cell on each side.
+// k_tcouple: the t^n part of the step in one marching kernel.
+//
+// A block owns an in-plane tile of TX x TY cells (x, y in 3D; x in 2D) of the
+// region [g-1, g+n] and marches along the last axis over the same range.
+// For each plane it solves the first-order Riemann problems R(V_j, V_{j+1})
+// (and, with parabolic terms, evaluates Pi^n) on the low faces of its cells
+// plus the tile's high faces, hands them over through LDS, and forms per
+// cell the increments L_d = -(G_{d,+} - G_{d,-})/dx_d of G = F - Pi and
+// Lp_d = (Pi_{d,+} - Pi_{d,-})/dx_d.  The marching-axis faces of one plane
+// are the high faces of the previous one, so each cell is finished one plane
+// later.  Outputs, per cell:
+//   T_d = sum_{d' != d} L_{d'} + Lp_d     (the Eq. transv increment of sweep d)
+//   V^{n+1/2} = V(U^n + dt/2 sum_d L_d)   (parabolic runs only)
 // ---------------------------------------------------------------------------
 
-template <int D, int PHYS, int RS, typename R>
-__global__ __launch_bounds__(NT) void k_godunov(const KBox *boxes, const KTile *tiles, const R *V, R *Fn, R *Pn,
-                                                const double *params, KOpts o)
+template <int DIM> struct TTile {
+    static constexpr int TX = (DIM == 3) ? 32 : NT;
+    static constexpr int TY = (DIM == 3) ? 8 : 1;
+    static constexpr int LM = 16;  // planes per block along the marching axis
+};
+
+template <typename R> struct TArgs {
+    const KBox *boxes;
+    const KTile *tiles;
+    const R *U;       // U^n (caller layout)
+    const R *V;       // V^n (workspace)
+    R *T[3];          // transverse increments (workspace)
+    R *Vh;            // V^{n+1/2} (workspace) or null
+    const double *params;
+    KOpts o;
+};
+
+// one face: G = F - Pi (and Pi separately) on the D-face below cell (i,j,k)
+template <int D, int PHYS, int RS, int PAR, typename R>
+__device__ __forceinline__ void tface(const R *Vb, const KBox &bx, int i, int j, int k, const KOpts &o, R gam, R ch,
+                                      R *G, R *Pi)
 {
-    KTile tl = tiles[blockIdx.x];
-    const KBox &bx = boxes[tl.box];
-    int e = o.parab ? 1 : 0;
-    int ext[3], org[3];
-#pragma unroll
-    for (int q = 0; q < 3; q++) {
-        if (q >= o.dim) {
-            ext[q] = 1;
-            org[q] = 0;
-        } else if (q == D) {
-            ext[q] = bx.n[q] + 1 + 2 * e;
-            org[q] = bx.g[q] - e;
-        } else {
-            ext[q] = bx.n[q] + 2;
-            org[q] = bx.g[q] - 1;
-        }
-    }
-    const int it = tl.a + (int)threadIdx.x;
-    const int tot = ext[0] * ext[1] * ext[2];
-    if (it >= tot) return;
-    const int i = org[0] + it % ext[0];
-    const int j = org[1] + (it / ext[0]) % ext[1];
-    const int k = org[2] + it / (ext[0] * ext[1]);
     int di, dj, dk;
     unit<D>(di, dj, dk);
     const int cs = (int)bx.cells;
-    const R *Vb = V + bx.woff;
     const int cB = cidx(bx, i, j, k), cA = cidx(bx, i - di, j - dj, k - dk);
-    R VL[NV], VR[NV], F[NV];
+    R VL[NV], VR[NV];
 #pragma unroll
     for (int q = 0; q < NV; q++) {
         VL[q] = Vb[q * cs + cA];
         VR[q] = Vb[q * cs + cB];
     }
-    R gam = R(o.gamma), ch = R(params[1]);
     R pL = VL[PRS], pR = VR[PRS], rL = VL[RHO], rR = VR[RHO];
     if (!o.hyp_off) {
         R sm;
-        riemann<D, PHYS, RS>(VL, VR, F, sm, gam, ch, o.glm);
+        riemann<D, PHYS, RS>(VL, VR, G, sm, gam, ch, o.glm);
     } else {
 #pragma unroll
-        for (int q = 0; q < NV; q++) F[q] = R(0);
+        for (int q = 0; q < NV; q++) G[q] = R(0);
     }
-    R *Fb = Fn + bx.woff;
+    if constexpr (PAR) {
+        parab_flux<D>(Vb, bx, i, j, k, o, pL, pR, rL, rR, Pi);
 #pragma unroll
-    for (int q = 0; q < NV; q++) Fb[q * cs + cB] = F[q];
-    if (o.parab) {
-        // the four-point transverse stencil needs one more cell across D
-        bool inside = true;
-#pragma unroll
-        for (int q = 0; q < 3; q++) {
-            if (q == D || q >= o.dim) continue;
-            int c = (q == 0) ? i : (q == 1 ? j : k);
-            if (c < 1 || c > bx.N[q] - 2) inside = false;
-        }
-        R Pi[NV];
-        if (inside) parab_flux<D>(Vb, bx, i, j, k, o, pL, pR, rL, rR, Pi);
-        else
-#pragma unroll
-            for (int q = 0; q < NV; q++) Pi[q] = R(0);
-        R *Pb = Pn + bx.woff;
-#pragma unroll
-        for (int q = 0; q < NV; q++) Pb[q * cs + cB] = Pi[q];
+        for (int q = 0; q < NV; q++) G[q] -= Pi[q];
     }
 }
 
-// ---------------------------------------------------------------------------
-// k_halfstep: U^{n+1/2} = U^n + dt/2 sum_d (L_H,d^n + L_P,d^n) on the
-// interior plus one halo cell, converted to V^{n+1/2} (MHD).
-// ---------------------------------------------------------------------------
-
-template <typename R>
-__global__ __launch_bounds__(NT) void k_halfstep(const KBox *boxes, const KTile *tiles, const R *U, const R *Fx,
-                                                 const R *Fy, const R *Fz, const R *Px, const R *Py, const R *Pz,
-                                                 R *Vh, const double *params, KOpts o)
+template <int DIM, int PHYS, int RS, int PAR, typename R>
+__global__ __launch_bounds__(NT) void k_tcouple(TArgs<R> a)
 {
-    KTile tl = tiles[blockIdx.x];
-    const KBox &bx = boxes[tl.box];
-    int ext[3], org[3];
-#pragma unroll
-    for (int q = 0; q < 3; q++) {
-        ext[q] = (q < o.dim) ? bx.n[q] + 2 : 1;
-        org[q] = (q < o.dim) ? bx.g[q] - 1 : 0;
-    }
-    const int it = tl.a + (int)threadIdx.x;
-    const int tot = ext[0] * ext[1] * ext[2];
-    if (it >= tot) return;
-    const int i = org[0] + it % ext[0];
-    const int j = org[1] + (it / ext[0]) % ext[1];
-    const int k = org[2] + it / (ext[0] * ext[1]);
+    constexpr int TX = TTile<DIM>::TX, TY = TTile<DIM>::TY;
+    constexpr int AM = DIM - 1;                 // marching axis
+    constexpr int NPX = PAR ? NV : 1;           // Pi planes kept only with parabolic terms
+    __shared__ R Gx[NV][TY][TX + 1];
+    __shared__ R Px[NPX][TY][TX + 1];
+    __shared__ R Gy[(DIM == 3) ? NV : 1][TY + 1][TX];
+    __shared__ R Py[(DIM == 3) ? NPX : 1][TY + 1][TX];
+
+    const int tid = threadIdx.x;
+    const int tx = tid % TX, ty = tid / TX;
+    const KTile tl = a.tiles[blockIdx.x];
+    const KBox bx = a.boxes[tl.box];
+    const KOpts &o = a.o;
+    const R gam = R(o.gamma), ch = R(a.params[1]);
+    const R hdt = R(0.5 * a.params[0]);
     const int cs = (int)bx.cells;
-    const int c = cidx(bx, i, j, k);
-    const R *F[3] = { Fx + bx.woff, Fy + bx.woff, Fz ? Fz + bx.woff : nullptr };
-    const R *P[3] = { Px + bx.woff, Py + bx.woff, Pz ? Pz + bx.woff : nullptr };
-    const int cp[3] = { cidx(bx, i + 1, j, k), cidx(bx, i, j + 1, k), cidx(bx, i, j, k + 1) };
-    R hdt = R(0.5 * params[0]);
-    R u[NV], v[NV];
+    const R *Vb = a.V + bx.woff;
+    const R ix = R(1.0 / bx.dx[0]), iy = R(1.0 / bx.dx[1]), iz = R(1.0 / bx.dx[2]);
+    // in-plane cell of this thread (ghosted coordinates) and region bounds
+    const int i = bx.g[0] - 1 + tl.a + tx;
+    const int j = (DIM == 3) ? bx.g[1] - 1 + tl.b + ty : 0;
+    const int hi0 = bx.g[0] + bx.n[0];                       // last region cell along x
+    const int hi1 = (DIM == 3) ? bx.g[1] + bx.n[1] : 0;
+    const bool inplane = (i <= hi0) && (DIM == 2 || j <= hi1);
+    // this block's chunk of the region [g-1, g+n] along the marching axis;
+    // its first marching faces are recomputed, not shared with the chunk below
+    const int m0 = bx.g[AM] - 1 + tl.c;
+    const int m1 = min(m0 + TTile<DIM>::LM - 1, bx.g[AM] + bx.n[AM]);
+
+    R Gm_prev[NV], Pm_prev[NV], Lx_prev[NV], Ly_prev[NV], Px_prev[NV], Py_prev[NV];
+    for (int m = m0; m <= m1 + 1; m++) {
+        const int ci = i, cj = (DIM == 3) ? j : m, ck = (DIM == 3) ? m : 0;
+        // ---- faces of this plane: the marching face below each region cell,
+        // and the in-plane low faces of every cell whose face borders the
+        // region (one cell past it along x / y computes only that face) ----
+        R Gm[NV], Pm[NV];
+        if (inplane) tface<AM, PHYS, RS, PAR>(Vb, bx, ci, cj, ck, o, gam, ch, Gm, Pm);
+        if (m <= m1) {
+            R G[NV], P[NV];
+            if (i <= hi0 + 1 && (DIM == 2 || j <= hi1)) {
+                tface<0, PHYS, RS, PAR>(Vb, bx, ci, cj, ck, o, gam, ch, G, P);
 #pragma unroll
-    for (int q = 0; q < NV; q++) {
-        R s = R(0);
+                for (int q = 0; q < NV; q++) {
+                    Gx[q][ty][tx] = G[q];
+                    if (PAR) Px[q][ty][tx] = P[q];
+                }
+            }
+            if constexpr (DIM == 3) {
+                if (i <= hi0 && j <= hi1 + 1) {
+                    tface<1, PHYS, RS, PAR>(Vb, bx, ci, cj, ck, o, gam, ch, G, P);
 #pragma unroll
-        for (int d = 0; d < 3; d++) {
-            if (d >= o.dim) continue;
-            R idx = R(1.0 / bx.dx[d]);
-            s += (-(F[d][q * cs + cp[d]] - F[d][q * cs + c]) + (P[d][q * cs + cp[d]] - P[d][q * cs + c])) * idx;
+                    for (int q = 0; q < NV; q++) {
+                        Gy[q][ty][tx] = G[q];
+                        if (PAR) Py[q][ty][tx] = P[q];
+                    }
+                }
+            }
         }
-        u[q] = U[bx.uoff + q * cs + c] + hdt * s;
-    }
-    c2p<PHYS_MHD>(u, v, R(o.gamma));
+        // the tile's high in-plane faces (TY along x, TX along y)
+        if (m <= m1) {
+            if (tid < TY) {
+                const int ei = bx.g[0] - 1 + tl.a + TX, ej = (DIM == 3) ? bx.g[1] - 1 + tl.b + tid : m;
+                const int ek = (DIM == 3) ? m : 0;
+                if (ei <= hi0 + 1 && (DIM == 2 || ej <= hi1)) {
+                    R G[NV], P[NV];
+                    tface<0, PHYS, RS, PAR>(Vb, bx, ei, ej, ek, o, gam, ch, G, P);
 #pragma unroll
-    for (int q = 0; q < NV; q++) Vh[bx.woff + q * cs + c] = v[q];
+                    for (int q = 0; q < NV; q++) {
+                        Gx[q][tid][TX] = G[q];
+                        if (PAR) Px[q][tid][TX] = P[q];
+                    }
+                }
+            } else if (DIM == 3 && tid < TY + TX) {
+                const int c = tid - TY;
+                const int ei = bx.g[0] - 1 + tl.a + c, ej = bx.g[1] - 1 + tl.b + TY;
+                if (ei <= hi0 && ej <= hi1 + 1) {
+                    R G[NV], P[NV];
+                    tface<(DIM == 3 ? 1 : 0), PHYS, RS, PAR>(Vb, bx, ei, ej, m, o, gam, ch, G, P);
+#pragma unroll
+                    for (int q = 0; q < NV; q++) {
+                        Gy[q][TY][c] = G[q];
+                        if (PAR) Py[q][TY][c] = P[q];
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        if (inplane) {
+            // ---- finish the previous plane (its high marching face is Gm) ----
+            if (m > m0) {
+                const int pj = (DIM == 3) ? j : m - 1, pk = (DIM == 3) ? m - 1 : 0;
+                const int c = cidx(bx, i, pj, pk);
+                const R im = (DIM == 3) ? iz : iy;
+                R Lm[NV], S[NV];
+#pragma unroll
+                for (int q = 0; q < NV; q++) {
+                    Lm[q] = -(Gm[q] - Gm_prev[q]) * im;
+                    R Lpm = PAR ? (Pm[q] - Pm_prev[q]) * im : R(0);
+                    if constexpr (DIM == 3) {
+                        a.T[0][bx.woff + q * cs + c] = Ly_prev[q] + Lm[q] + (PAR ? Px_prev[q] : R(0));
+                        a.T[1][bx.woff + q * cs + c] = Lx_prev[q] + Lm[q] + (PAR ? Py_prev[q] : R(0));
+                        a.T[2][bx.woff + q * cs + c] = Lx_prev[q] + Ly_prev[q] + Lpm;
+                        S[q] = Lx_prev[q] + Ly_prev[q] + Lm[q];
+                    } else {
+                        a.T[0][bx.woff + q * cs + c] = Lm[q] + (PAR ? Px_prev[q] : R(0));
+                        a.T[1][bx.woff + q * cs + c] = Lx_prev[q] + Lpm;
+                        S[q] = Lx_prev[q] + Lm[q];
+                    }
+                }
+                if constexpr (PAR) {
+                    R u[NV], v[NV];
+#pragma unroll
+                    for (int q = 0; q < NV; q++) u[q] = a.U[bx.uoff + q * cs + c] + hdt * S[q];
+                    c2p<PHYS_MHD>(u, v, gam);
+#pragma unroll
+                    for (int q = 0; q < NV; q++) a.Vh[bx.woff + q * cs + c] = v[q];
+                }
+            }
+            // ---- in-plane increments of this plane, kept for one plane ----
+            if (m <= m1) {
+#pragma unroll
+                for (int q = 0; q < NV; q++) {
+                    Lx_prev[q] = -(Gx[q][ty][tx + 1] - Gx[q][ty][tx]) * ix;
+                    if (PAR) Px_prev[q] = (Px[q][ty][tx + 1] - Px[q][ty][tx]) * ix;
+                    if constexpr (DIM == 3) {
+                        Ly_prev[q] = -(Gy[q][ty + 1][tx] - Gy[q][ty][tx]) * iy;
+                        if (PAR) Py_prev[q] = (Py[q][ty + 1][tx] - Py[q][ty][tx]) * iy;
+                    }
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < NV; q++) {
+                Gm_prev[q] = Gm[q];
+                if (PAR) Pm_prev[q] = Pm[q];
+            }
+        }
+        __syncthreads();
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -379,8 +462,7 @@ template <typename R> struct SweepArgs {
     const R *U;       // U^n (caller layout)
     R *Uout;          // U^{n+1} (caller layout)
     const R *V;       // V^n (workspace)
-    const R *Fn[3];   // Godunov fluxes at t^n (workspace)
-    const R *Pn[3];   // parabolic fluxes at t^n (workspace) or null
+    const R *T[3];    // transverse increments of Eq. transv (workspace)
     const R *Vh;      // V^{n+1/2} (workspace) or null
     R *lam;           // per-cell rate accumulator (workspace, parabolic only)
     const R *L0;      // cooling coefficient (caller layout / 9) or null
@@ -450,10 +532,7 @@ __global__ __launch_bounds__(NT, (sizeof(R) == 4 ? CTU_SWEEP_WAVES_F32 : CTU_SWE
     const R *Vb = a.V + bx.woff;
     const R *Ub = a.U + bx.uoff;
     R *Uob = a.Uout + bx.uoff;
-    const R *Fb[3] = { a.Fn[0] ? a.Fn[0] + bx.woff : nullptr, a.Fn[1] ? a.Fn[1] + bx.woff : nullptr,
-                       a.Fn[2] ? a.Fn[2] + bx.woff : nullptr };
-    const R *Pb[3] = { a.Pn[0] ? a.Pn[0] + bx.woff : nullptr, a.Pn[1] ? a.Pn[1] + bx.woff : nullptr,
-                       a.Pn[2] ? a.Pn[2] + bx.woff : nullptr };
+    const R *Tb = a.T[D] + bx.woff;
     double rate_loc = 0.0, dpp_loc = 0.0;
 
     for (int base = 0; base < items; base += NT) {
@@ -505,28 +584,10 @@ __global__ __launch_bounds__(NT, (sizeof(R) == 4 ? CTU_SWEEP_WAVES_F32 : CTU_SWE
             p2c<PHYS>(Vp, Up, gam);
             // ---- corner coupling (Eq. transv) ----
 #pragma unroll
-            for (int e = 0; e < 3; e++) {
-                if (e >= dim) continue;
-                const int se = (e == 0) ? 1 : (e == 1 ? bx.N[0] : bx.N[0] * bx.N[1]);
-                const R ie = R(1.0 / bx.dx[e]);
-                if (e != D) {
-                    const R *Fe = Fb[e];
-#pragma unroll
-                    for (int q = 0; q < NV; q++) {
-                        R tr = -(Fe[q * cs + c + se] - Fe[q * cs + c]) * ie * hdt;
-                        Um[q] += tr;
-                        Up[q] += tr;
-                    }
-                }
-                if (o.parab) {
-                    const R *Pe = Pb[e];
-#pragma unroll
-                    for (int q = 0; q < NV; q++) {
-                        R tr = (Pe[q * cs + c + se] - Pe[q * cs + c]) * ie * hdt;
-                        Um[q] += tr;
-                        Up[q] += tr;
-                    }
-                }
+            for (int q = 0; q < NV; q++) {
+                R tr = hdt * Tb[q * cs + c];
+                Um[q] += tr;
+                Up[q] += tr;
             }
 #pragma unroll
             for (int q = 0; q < NV; q++) sP[q][tid] = Up[q];

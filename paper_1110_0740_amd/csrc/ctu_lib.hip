@@ -64,9 +64,9 @@ struct ctu_plan {
     KReg *dregs = nullptr;
     int64_t state_elems = 0;
     int64_t ws_cells = 0;  // sum of ghosted cells
-    TileSet t_cells, t_god[3], t_half, t_sweep[3], t_cfl;
-    // workspace fields
-    void *wsV = nullptr, *wsF[3] = { nullptr, nullptr, nullptr }, *wsP[3] = { nullptr, nullptr, nullptr };
+    TileSet t_cells, t_tc, t_sweep[3], t_cfl;
+    // workspace fields: V^n, the transverse increments T_d, V^{n+1/2}, rate
+    void *wsV = nullptr, *wsT[3] = { nullptr, nullptr, nullptr };
     void *wsVh = nullptr, *wsLam = nullptr;
     int64_t ws_bytes = 0;
     // reflux
@@ -94,9 +94,9 @@ void free_plan(ctu_plan *p)
         if (e) (void)hipEventDestroy(e);
     if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
     if (p->graph) (void)hipGraphDestroy(p->graph);
-    void *ptrs[] = { p->dboxes, p->dregs, p->t_cells.d, p->t_god[0].d, p->t_god[1].d, p->t_god[2].d, p->t_half.d,
-                     p->t_sweep[0].d, p->t_sweep[1].d, p->t_sweep[2].d, p->t_cfl.d, p->wsV, p->wsF[0], p->wsF[1],
-                     p->wsF[2], p->wsP[0], p->wsP[1], p->wsP[2], p->wsVh, p->wsLam, p->drefl, p->dcell_start };
+    void *ptrs[] = { p->dboxes, p->dregs, p->t_cells.d, p->t_tc.d, p->t_sweep[0].d, p->t_sweep[1].d,
+                     p->t_sweep[2].d, p->t_cfl.d, p->wsV, p->wsT[0], p->wsT[1], p->wsT[2], p->wsVh, p->wsLam,
+                     p->drefl, p->dcell_start };
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
     delete p;
@@ -135,15 +135,16 @@ ctu_status build_tables(ctu_plan *p)
     for (int b = 0; b < (int)p->hboxes.size(); b++) {
         const KBox &bx = p->hboxes[b];
         add_linear_tiles(p->t_cells, b, bx.cells);
-        for (int D = 0; D < dim; D++) {
-            long long ext = 1;
-            for (int q = 0; q < dim; q++) ext *= (q == D) ? (bx.n[q] + 1 + 2 * par) : (bx.n[q] + 2);
-            add_linear_tiles(p->t_god[D], b, ext);
-        }
-        if (par) {
-            long long ext = 1;
-            for (int q = 0; q < dim; q++) ext *= bx.n[q] + 2;
-            add_linear_tiles(p->t_half, b, ext);
+        // t^n marching kernel: in-plane tiles of the region [g-1, g+n]
+        {
+            const int TX = (dim == 3) ? TTile<3>::TX : TTile<2>::TX;
+            const int TY = (dim == 3) ? TTile<3>::TY : TTile<2>::TY;
+            const int LM = TTile<3>::LM;
+            const int ex = bx.n[0] + 2, ey = (dim == 3) ? bx.n[1] + 2 : 1;
+            const int em = bx.n[dim - 1] + 2;
+            for (int m0 = 0; m0 < em; m0 += LM)
+                for (int y0 = 0; y0 < ey; y0 += TY)
+                    for (int x0 = 0; x0 < ex; x0 += TX) p->t_tc.h.push_back(KTile{ b, x0, y0, m0 });
         }
         long long interior = (long long)bx.n[0] * bx.n[1] * bx.n[2];
         add_linear_tiles(p->t_cfl, b, interior);
@@ -159,8 +160,7 @@ ctu_status build_tables(ctu_plan *p)
         }
     }
     ctu_status st;
-    TileSet *all[] = { &p->t_cells, &p->t_god[0], &p->t_god[1], &p->t_god[2], &p->t_half,
-                       &p->t_sweep[0], &p->t_sweep[1], &p->t_sweep[2], &p->t_cfl };
+    TileSet *all[] = { &p->t_cells, &p->t_tc, &p->t_sweep[0], &p->t_sweep[1], &p->t_sweep[2], &p->t_cfl };
     for (TileSet *ts : all)
         if ((st = upload(ts->h, &ts->d)) != CTU_OK) return st;
     return CTU_OK;
@@ -215,24 +215,23 @@ ctu_status enqueue_step(ctu_plan *p, const void *U_in, void *U_out, const double
                                p->t_cells.d, (const R *)U_in, (R *)p->wsV, (int *)fails, gam, 1);
     }
     HIP_TRY(hipGetLastError());
-    for (int D = 0; D < dim; D++) {
-        StageTimer tm(p, 1 + D, s);
+    {
+        StageTimer tm(p, 1, s);
+        TArgs<R> ta;
+        ta.boxes = p->dboxes;
+        ta.tiles = p->t_tc.d;
+        ta.U = (const R *)U_in;
+        ta.V = (const R *)p->wsV;
+        for (int d = 0; d < 3; d++) ta.T[d] = (R *)p->wsT[d];
+        ta.Vh = (R *)p->wsVh;
+        ta.params = params;
+        ta.o = p->ko;
         hipError_t e;
-        if (sizeof(R) == 4)
-            e = launch_godunov_f32(D, p->combo, p->t_god[D].n(), p->dboxes, p->t_god[D].d, (const float *)p->wsV,
-                                   (float *)p->wsF[D], (float *)p->wsP[D], params, p->ko, s);
+        if constexpr (sizeof(R) == 4)
+            e = launch_tcouple_f32(dim, par ? 1 : 0, p->combo, p->t_tc.n(), ta, s);
         else
-            e = launch_godunov_f64(D, p->combo, p->t_god[D].n(), p->dboxes, p->t_god[D].d, (const double *)p->wsV,
-                                   (double *)p->wsF[D], (double *)p->wsP[D], params, p->ko, s);
-        if (e != hipSuccess) return fail(CTU_ERR_HIP, std::string("godunov launch: ") + hipGetErrorString(e));
-    }
-    if (par) {
-        StageTimer tm(p, 4, s);
-        hipLaunchKernelGGL((k_halfstep<R>), dim3(p->t_half.n()), dim3(NT), 0, s, p->dboxes, p->t_half.d,
-                           (const R *)U_in, (const R *)p->wsF[0], (const R *)p->wsF[1], (const R *)p->wsF[2],
-                           (const R *)p->wsP[0], (const R *)p->wsP[1], (const R *)p->wsP[2], (R *)p->wsVh, params,
-                           p->ko);
-        HIP_TRY(hipGetLastError());
+            e = launch_tcouple_f64(dim, par ? 1 : 0, p->combo, p->t_tc.n(), ta, s);
+        if (e != hipSuccess) return fail(CTU_ERR_HIP, std::string("t^n kernel launch: ") + hipGetErrorString(e));
     }
     SweepArgs<R> a;
     a.boxes = p->dboxes;
@@ -240,10 +239,7 @@ ctu_status enqueue_step(ctu_plan *p, const void *U_in, void *U_out, const double
     a.U = (const R *)U_in;
     a.Uout = (R *)U_out;
     a.V = (const R *)p->wsV;
-    for (int d = 0; d < 3; d++) {
-        a.Fn[d] = (const R *)p->wsF[d];
-        a.Pn[d] = (const R *)p->wsP[d];
-    }
+    for (int d = 0; d < 3; d++) a.T[d] = (const R *)p->wsT[d];
     a.Vh = (const R *)p->wsVh;
     a.lam = (R *)p->wsLam;
     a.L0 = (const R *)L0;
@@ -430,16 +426,11 @@ ctu_status ctu_plan_create(const ctu_opts *opts, const ctu_box *boxes, int32_t n
         return st;
     }
     for (int d = 0; d < o.dim; d++)
-        if ((st = alloc_ws(p, &p->wsF[d], f9)) != CTU_OK) {
+        if ((st = alloc_ws(p, &p->wsT[d], f9)) != CTU_OK) {
             free_plan(p);
             return st;
         }
     if (o.parabolic_mask) {
-        for (int d = 0; d < o.dim; d++)
-            if ((st = alloc_ws(p, &p->wsP[d], f9)) != CTU_OK) {
-                free_plan(p);
-                return st;
-            }
         if ((st = alloc_ws(p, &p->wsVh, f9)) != CTU_OK || (st = alloc_ws(p, &p->wsLam, p->ws_cells)) != CTU_OK) {
             free_plan(p);
             return st;

@@ -29,7 +29,7 @@ SYMBOLS = [
     "ctu_plan_set_reflux", "ctu_reflux", "ctu_plan_enable_timing", "ctu_plan_read_timing", "ctu_last_error",
 ]
 NSTAGE = 8
-STAGES = ["prim", "godunov_x", "godunov_y", "godunov_z", "halfstep", "sweep_x", "sweep_y", "sweep_z"]
+STAGES = ["prim", "tcouple", "unused2", "unused3", "unused4", "sweep_x", "sweep_y", "sweep_z"]
 
 
 class CtuOpts(C.Structure):
