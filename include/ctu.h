@@ -106,7 +106,10 @@ typedef struct {
     int32_t pad;
 } ctu_opts;
 
-/* One ghosted box: interior cells [lo, lo+n) in level-global indices. */
+/* One ghosted box: interior cells [lo, lo+n) in level-global indices.
+ * Its block of nine ghosted planes must fit in 4 GiB (FP32: at most
+ * 119,304,647 ghosted cells, FP64: 59,652,323); larger grids are split
+ * into several boxes.  ctu_plan_create rejects a larger box (CTU_ERR_ARG). */
 typedef struct {
     int32_t lo[3];
     int32_t n[3];   /* n[2] = 1 in 2D */

@@ -31,8 +31,11 @@ FLAGS = [
 
 # FP32 translation unit: divide and square root as the hardware's
 # approximate reciprocal / root (a few ulp) instead of the correctly rounded
-# expansions; FP64 keeps the correctly rounded forms.
-UNIT_FLAGS = {"ctu_inst_f32.hip": ["-fno-hip-fp32-correctly-rounded-divide-sqrt"]}
+# expansions, and FP32 subnormals flushed to zero, which lets both map to
+# single instructions without range scaling (the state variables stay many
+# orders of magnitude above 1e-38); FP64 keeps the correctly rounded forms
+# and subnormals.
+UNIT_FLAGS = {"ctu_inst_f32.hip": ["-fno-hip-fp32-correctly-rounded-divide-sqrt", "-fgpu-flush-denormals-to-zero"]}
 
 
 def _compile(unit: str, extra: list[str], build_dir: str = BUILD) -> str:

@@ -34,7 +34,6 @@ template <int D> struct Ax {
 };
 
 template <typename R> __device__ __forceinline__ R sq(R x) { return x * x; }
-template <typename R> __device__ __forceinline__ R sgn0(R a) { return R((a > R(0)) - (a < R(0))); }
 template <typename R> __device__ __forceinline__ R sgn1(R a) { return a < R(0) ? R(-1) : R(1); }
 
 // ---------------------------------------------------------------------------
@@ -311,20 +310,21 @@ __device__ __forceinline__ void hll(const R *VL, const R *VR, R *F, R &smax, R g
     R UL[NV], UR[NV], FL[NV], FR[NV];
     phys_flux<D, PHYS>(VL, UL, FL, gam, ch, glm);
     phys_flux<D, PHYS>(VR, UR, FR, gam, ch, glm);
-    if (SL >= R(0)) {
+    // upwind or fan flux, selected per lane
+    R id = R(1) / (SR - SL);
 #pragma unroll
-        for (int q = 0; q < NV; q++) F[q] = FL[q];
-    } else if (SR <= R(0)) {
-#pragma unroll
-        for (int q = 0; q < NV; q++) F[q] = FR[q];
-    } else {
-        R id = R(1) / (SR - SL);
-#pragma unroll
-        for (int q = 0; q < NV; q++) F[q] = (SR * FL[q] - SL * FR[q] + SL * SR * (UR[q] - UL[q])) * id;
+    for (int q = 0; q < NV; q++) {
+        R Fh = (SR * FL[q] - SL * FR[q] + SL * SR * (UR[q] - UL[q])) * id;
+        F[q] = (SL >= R(0)) ? FL[q] : ((SR <= R(0)) ? FR[q] : Fh);
     }
 }
 
 // HLLD (Miyoshi & Kusano 2005) for states sharing the normal field.
+//
+// Evaluated without branches: all star states are formed and the flux of
+// the region holding the interface is selected, so that the lanes of a wave
+// never split over the five regions.  Quantities of regions not selected
+// may be non-finite; they enter only through selects.
 template <int D, typename R>
 __device__ __forceinline__ void hlld(const R *VL, const R *VR, R *F, R &smax, R gam, R ch, int glm)
 {
@@ -337,16 +337,6 @@ __device__ __forceinline__ void hlld(const R *VL, const R *VR, R *F, R &smax, R 
     R UL[NV], UR[NV], FL[NV], FR[NV];
     phys_flux<D, PHYS_MHD>(VL, UL, FL, gam, ch, glm);
     phys_flux<D, PHYS_MHD>(VR, UR, FR, gam, ch, glm);
-    if (SL >= R(0)) {
-#pragma unroll
-        for (int q = 0; q < NV; q++) F[q] = FL[q];
-        return;
-    }
-    if (SR <= R(0)) {
-#pragma unroll
-        for (int q = 0; q < NV; q++) F[q] = FR[q];
-        return;
-    }
     const R Bn = VL[BX1 + n];
     const R Bn2 = Bn * Bn;
     R ptL = VL[PRS] + R(0.5) * (sq(VL[BX1]) + sq(VL[BX2]) + sq(VL[BX3]));
@@ -366,56 +356,34 @@ __device__ __forceinline__ void hlld(const R *VL, const R *VR, R *F, R &smax, R 
         R pt = s ? ptR : ptL;
         R u = V[MX1 + n], rho = V[RHO];
         R Su = S - u, SSM = S - SM;
-        rs[s] = rho * Su / SSM;
+        R iSSM = R(1) / SSM;
+        rs[s] = rho * Su * iSSM;
         R den = rho * Su * SSM - Bn2;
         R scale = rho * fabs(Su) * fabs(SSM) + Bn2;
-        if (fabs(den) <= R(sizeof(R) == 8 ? 1e-12 : 1e-6) * scale) {
-            vt[s] = V[MX1 + t];
-            vb[s] = V[MX1 + b];
-            Bt[s] = V[BX1 + t];
-            Bb[s] = V[BX1 + b];
-        } else {
-            R iden2 = R(1) / den;
-            R fv = Bn * (SM - u) * iden2;
-            R fB = (rho * Su * Su - Bn2) * iden2;
-            vt[s] = V[MX1 + t] - V[BX1 + t] * fv;
-            vb[s] = V[MX1 + b] - V[BX1 + b] * fv;
-            Bt[s] = V[BX1 + t] * fB;
-            Bb[s] = V[BX1 + b] * fB;
-        }
+        // degenerate case (S -> S_M with B_t -> 0): transverse values kept
+        bool degen = fabs(den) <= R(sizeof(R) == 8 ? 1e-12 : 1e-6) * scale;
+        R iden2 = R(1) / den;
+        R fv = degen ? R(0) : Bn * (SM - u) * iden2;
+        R fB = degen ? R(1) : (rho * Su * Su - Bn2) * iden2;
+        vt[s] = V[MX1 + t] - V[BX1 + t] * fv;
+        vb[s] = V[MX1 + b] - V[BX1 + b] * fv;
+        Bt[s] = V[BX1 + t] * fB;
+        Bb[s] = V[BX1 + b] * fB;
         R vB = V[MX1] * V[BX1] + V[MX2] * V[BX2] + V[MX3] * V[BX3];
         R vBs = SM * Bn + vt[s] * Bt[s] + vb[s] * Bb[s];
-        Es[s] = (Su * U[ENG] - pt * u + pts * SM + Bn * (vB - vBs)) / SSM;
+        Es[s] = (Su * U[ENG] - pt * u + pts * SM + Bn * (vB - vBs)) * iSSM;
         sr[s] = sqrt(rs[s]);
     }
     R SLs = SM - fabs(Bn) / sr[0];
     R SRs = SM + fabs(Bn) / sr[1];
 
-    auto star = [&](int s, R *Us) {
-        Us[RHO] = rs[s];
-        Us[MX1 + n] = rs[s] * SM;
-        Us[MX1 + t] = rs[s] * vt[s];
-        Us[MX1 + b] = rs[s] * vb[s];
-        Us[ENG] = Es[s];
-        Us[BX1 + n] = Bn;
-        Us[BX1 + t] = Bt[s];
-        Us[BX1 + b] = Bb[s];
-        Us[PSI] = s ? VR[PSI] : VL[PSI];
-    };
-    if (SLs >= R(0)) {
-        R Us[NV];
-        star(0, Us);
-#pragma unroll
-        for (int q = 0; q < NV; q++) F[q] = FL[q] + SL * (Us[q] - UL[q]);
-        return;
-    }
-    if (SRs <= R(0)) {
-        R Us[NV];
-        star(1, Us);
-#pragma unroll
-        for (int q = 0; q < NV; q++) F[q] = FR[q] + SR * (Us[q] - UR[q]);
-        return;
-    }
+    // region: outer (F_L or F_R), single star (L* or R*) or double star on
+    // side k; k follows S_M inside the fan
+    const bool outerL = SL >= R(0), outerR = SR <= R(0);
+    const bool outer = outerL || outerR;
+    const bool single = (SLs >= R(0)) || (SRs <= R(0));
+    const bool k = outerL ? false : (outerR ? true : !(SM >= R(0)));
+
     // double-star states
     R sB = sgn1(Bn);
     R idn = R(1) / (sr[0] + sr[1]);
@@ -424,25 +392,41 @@ __device__ __forceinline__ void hlld(const R *VL, const R *VR, R *F, R &smax, R 
     R Btt = (sr[0] * Bt[1] + sr[1] * Bt[0] + sr[0] * sr[1] * (vt[1] - vt[0]) * sB) * idn;
     R Bbb = (sr[0] * Bb[1] + sr[1] * Bb[0] + sr[0] * sr[1] * (vb[1] - vb[0]) * sB) * idn;
     R vBss = SM * Bn + vtt * Btt + vbb * Bbb;
-    int s = (SM >= R(0)) ? 0 : 1;
+
+    // star and double-star states of side k
+    const R rk = k ? rs[1] : rs[0], vtk = k ? vt[1] : vt[0], vbk = k ? vb[1] : vb[0];
+    const R Btk = k ? Bt[1] : Bt[0], Bbk = k ? Bb[1] : Bb[0], Ek = k ? Es[1] : Es[0];
+    const R srk = k ? sr[1] : sr[0];
+    const R vBsk = SM * Bn + vtk * Btk + vbk * Bbk;
     R Us[NV], Uss[NV];
-    star(s, Us);
-    R vBs = SM * Bn + vt[s] * Bt[s] + vb[s] * Bb[s];
-    Uss[RHO] = rs[s];
-    Uss[MX1 + n] = rs[s] * SM;
-    Uss[MX1 + t] = rs[s] * vtt;
-    Uss[MX1 + b] = rs[s] * vbb;
-    Uss[ENG] = Es[s] + (s ? R(1) : R(-1)) * sr[s] * (vBs - vBss) * sB;
+    Us[RHO] = rk;
+    Us[MX1 + n] = rk * SM;
+    Us[MX1 + t] = rk * vtk;
+    Us[MX1 + b] = rk * vbk;
+    Us[ENG] = Ek;
+    Us[BX1 + n] = Bn;
+    Us[BX1 + t] = Btk;
+    Us[BX1 + b] = Bbk;
+    Us[PSI] = k ? VR[PSI] : VL[PSI];
+    Uss[RHO] = rk;
+    Uss[MX1 + n] = rk * SM;
+    Uss[MX1 + t] = rk * vtt;
+    Uss[MX1 + b] = rk * vbb;
+    Uss[ENG] = Ek + (k ? R(1) : R(-1)) * srk * (vBsk - vBss) * sB;
     Uss[BX1 + n] = Bn;
     Uss[BX1 + t] = Btt;
     Uss[BX1 + b] = Bbb;
     Uss[PSI] = Us[PSI];
-    R Sk = s ? SR : SL;
-    R Sks = s ? SRs : SLs;
-    const R *Fk = s ? FR : FL;
-    const R *Uk = s ? UR : UL;
+    const R Sk = k ? SR : SL;
+    const R Sks = k ? SRs : SLs;
 #pragma unroll
-    for (int q = 0; q < NV; q++) F[q] = Fk[q] + Sks * Uss[q] - (Sks - Sk) * Us[q] - Sk * Uk[q];
+    for (int q = 0; q < NV; q++) {
+        R Fk = k ? FR[q] : FL[q];
+        R Uk = k ? UR[q] : UL[q];
+        R f1 = Fk + Sk * (Us[q] - Uk);       // single-star flux
+        R f2 = f1 + Sks * (Uss[q] - Us[q]);  // double-star flux
+        F[q] = outer ? Fk : (single ? f1 : f2);
+    }
 }
 
 // Interface solve: exact solution of the linear (B_n, psi) subsystem of
@@ -472,12 +456,22 @@ __device__ __forceinline__ void riemann(R *VL, R *VR, R *F, R &smax, R gam, R ch
 // Limiters and reconstruction (Sec. 3.2), on undivided differences.
 // ---------------------------------------------------------------------------
 
+// minmod: the argument of smaller magnitude when both share a sign, else 0
+// (selects rather than sign arithmetic, same value)
 template <typename R> __device__ __forceinline__ R minmod(R a, R b)
 {
-    return R(0.5) * (sgn0(a) + sgn0(b)) * fmin(fabs(a), fabs(b));
+    R m = (fabs(a) < fabs(b)) ? a : b;
+    return (a * b > R(0)) ? m : R(0);
 }
 
-template <typename R> __device__ __forceinline__ R lim_mc(R dp, R dm) { return minmod(R(0.5) * (dp + dm), R(2) * minmod(dm, dp)); }
+// monotonised central limiter minmod((dp + dm)/2, 2 minmod(dp, dm)): for
+// differences of one sign, that sign times min(|dp + dm|/2, 2|dp|, 2|dm|)
+template <typename R> __device__ __forceinline__ R lim_mc(R dp, R dm)
+{
+    R c = R(0.5) * (dp + dm);
+    R m = fmin(fmin(fabs(c), R(2) * fabs(dp)), R(2) * fabs(dm));
+    return (dp * dm > R(0)) ? copysign(m, c) : R(0);
+}
 
 template <typename R> __device__ __forceinline__ R limiter(int lim, R dp, R dm)
 {
@@ -529,8 +523,9 @@ template <typename R>
 __device__ __forceinline__ void trace(int wref, R dm, R dp, R nu, R numax, R numin, R &sm, R &sp)
 {
     R dw = dp - dm, d2 = dp + dm;
-    R bp = R(0.5) * (R(1) + sgn0(nu));
-    R bm = R(0.5) * (R(1) - sgn0(nu));
+    // upwind weights (1 + sgn nu)/2 and (1 - sgn nu)/2
+    R bp = (nu > R(0)) ? R(1) : ((nu < R(0)) ? R(0) : R(0.5));
+    R bm = R(1) - bp;
     R tp = dp - R(0.5) * nu * (dw + d2 * (R(3) - R(2) * nu));
     R tm = dm - R(0.5) * nu * (dw - d2 * (R(3) + R(2) * nu));
     R rp, rm;

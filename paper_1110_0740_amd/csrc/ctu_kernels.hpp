@@ -42,12 +42,49 @@ struct KReg {
     long long slot;
 };
 
-// cell offset inside one box block (a box holds fewer than 2^31 / 9 cells,
+// cell offset inside one box block (a box block of nine planes is below 4 GiB,
 // checked at plan creation, so 32-bit offsets address every variable)
 __device__ __forceinline__ int cidx(const KBox &bx, int i, int j, int k)
 {
     return (k * bx.N[1] + j) * bx.N[0] + i;
 }
+
+// Raw-buffer view of one box's block of an array: NV variable planes of
+// `cells` elements each.  An access takes the plane start in a scalar
+// register and the cell's byte offset in a 32-bit vector register, so no
+// 64-bit address arithmetic is done per element.  The block's byte size
+// (below 4 GiB, checked at plan creation) is the hardware range limit:
+// loads past it read 0 and stores past it are dropped.
+template <typename R> struct Blk {
+    __amdgpu_buffer_rsrc_t rs;
+    uint32_t pb;  // bytes per variable plane
+
+    __device__ __forceinline__ Blk(const R *base, long long cells)
+        : rs(__builtin_amdgcn_make_buffer_rsrc((void *)base, (short)0, (int)(uint32_t)(NV * cells * sizeof(R)),
+                                               0x00020000)),
+          pb((uint32_t)(cells * sizeof(R)))
+    {
+    }
+    // element e >= 0 of variable plane q
+    __device__ __forceinline__ R ld(int q, int e) const
+    {
+        const int vo = (int)((uint32_t)e * (uint32_t)sizeof(R)), so = (int)((uint32_t)q * pb);
+        if constexpr (sizeof(R) == 4)
+            return __builtin_bit_cast(R, __builtin_amdgcn_raw_buffer_load_b32(rs, vo, so, 0));
+        else
+            return __builtin_bit_cast(R, __builtin_amdgcn_raw_buffer_load_b64(rs, vo, so, 0));
+    }
+    __device__ __forceinline__ void st(int q, int e, R v) const
+    {
+        const int vo = (int)((uint32_t)e * (uint32_t)sizeof(R)), so = (int)((uint32_t)q * pb);
+        if constexpr (sizeof(R) == 4) {
+            __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), rs, vo, so, 0);
+        } else {
+            using W = decltype(__builtin_amdgcn_raw_buffer_load_b64(rs, 0, 0, 0));
+            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(W, v), rs, vo, so, 0);
+        }
+    }
+};
 
 template <int D> __device__ __forceinline__ void unit(int &di, int &dj, int &dk)
 {
@@ -271,8 +308,8 @@ template <typename R> struct TArgs {
 
 // one face: G = F - Pi (and Pi separately) on the D-face below cell (i,j,k)
 template <int D, int PHYS, int RS, int PAR, typename R>
-__device__ __forceinline__ void tface(const R *Vb, const KBox &bx, int i, int j, int k, const KOpts &o, R gam, R ch,
-                                      R *G, R *Pi)
+__device__ __forceinline__ void tface(const Blk<R> &bV, const R *Vb, const KBox &bx, int i, int j, int k,
+                                      const KOpts &o, R gam, R ch, R *G, R *Pi)
 {
     int di, dj, dk;
     unit<D>(di, dj, dk);
@@ -281,8 +318,8 @@ __device__ __forceinline__ void tface(const R *Vb, const KBox &bx, int i, int j,
     R VL[NV], VR[NV];
 #pragma unroll
     for (int q = 0; q < NV; q++) {
-        VL[q] = Vb[q * cs + cA];
-        VR[q] = Vb[q * cs + cB];
+        VL[q] = bV.ld(q, cA);
+        VR[q] = bV.ld(q, cB);
     }
     R pL = VL[PRS], pR = VR[PRS], rL = VL[RHO], rR = VR[RHO];
     if (!o.hyp_off) {
@@ -319,6 +356,8 @@ __global__ __launch_bounds__(NT) void k_tcouple(TArgs<R> a)
     const R hdt = R(0.5 * a.params[0]);
     const int cs = (int)bx.cells;
     const R *Vb = a.V + bx.woff;
+    const Blk<R> bV(Vb, bx.cells);
+    const Blk<R> bT0(a.T[0] + bx.woff, bx.cells), bT1(a.T[1] + bx.woff, bx.cells), bT2(DIM == 3 ? a.T[2] + bx.woff : Vb, bx.cells);
     const R ix = R(1.0 / bx.dx[0]), iy = R(1.0 / bx.dx[1]), iz = R(1.0 / bx.dx[2]);
     // in-plane cell of this thread (ghosted coordinates) and region bounds
     const int i = bx.g[0] - 1 + tl.a + tx;
@@ -338,11 +377,11 @@ __global__ __launch_bounds__(NT) void k_tcouple(TArgs<R> a)
         // and the in-plane low faces of every cell whose face borders the
         // region (one cell past it along x / y computes only that face) ----
         R Gm[NV], Pm[NV];
-        if (inplane) tface<AM, PHYS, RS, PAR>(Vb, bx, ci, cj, ck, o, gam, ch, Gm, Pm);
+        if (inplane) tface<AM, PHYS, RS, PAR>(bV, Vb, bx, ci, cj, ck, o, gam, ch, Gm, Pm);
         if (m <= m1) {
             R G[NV], P[NV];
             if (i <= hi0 + 1 && (DIM == 2 || j <= hi1)) {
-                tface<0, PHYS, RS, PAR>(Vb, bx, ci, cj, ck, o, gam, ch, G, P);
+                tface<0, PHYS, RS, PAR>(bV, Vb, bx, ci, cj, ck, o, gam, ch, G, P);
 #pragma unroll
                 for (int q = 0; q < NV; q++) {
                     Gx[q][ty][tx] = G[q];
@@ -351,7 +390,7 @@ __global__ __launch_bounds__(NT) void k_tcouple(TArgs<R> a)
             }
             if constexpr (DIM == 3) {
                 if (i <= hi0 && j <= hi1 + 1) {
-                    tface<1, PHYS, RS, PAR>(Vb, bx, ci, cj, ck, o, gam, ch, G, P);
+                    tface<1, PHYS, RS, PAR>(bV, Vb, bx, ci, cj, ck, o, gam, ch, G, P);
 #pragma unroll
                     for (int q = 0; q < NV; q++) {
                         Gy[q][ty][tx] = G[q];
@@ -367,7 +406,7 @@ __global__ __launch_bounds__(NT) void k_tcouple(TArgs<R> a)
                 const int ek = (DIM == 3) ? m : 0;
                 if (ei <= hi0 + 1 && (DIM == 2 || ej <= hi1)) {
                     R G[NV], P[NV];
-                    tface<0, PHYS, RS, PAR>(Vb, bx, ei, ej, ek, o, gam, ch, G, P);
+                    tface<0, PHYS, RS, PAR>(bV, Vb, bx, ei, ej, ek, o, gam, ch, G, P);
 #pragma unroll
                     for (int q = 0; q < NV; q++) {
                         Gx[q][tid][TX] = G[q];
@@ -379,7 +418,7 @@ __global__ __launch_bounds__(NT) void k_tcouple(TArgs<R> a)
                 const int ei = bx.g[0] - 1 + tl.a + c, ej = bx.g[1] - 1 + tl.b + TY;
                 if (ei <= hi0 && ej <= hi1 + 1) {
                     R G[NV], P[NV];
-                    tface<(DIM == 3 ? 1 : 0), PHYS, RS, PAR>(Vb, bx, ei, ej, m, o, gam, ch, G, P);
+                    tface<(DIM == 3 ? 1 : 0), PHYS, RS, PAR>(bV, Vb, bx, ei, ej, m, o, gam, ch, G, P);
 #pragma unroll
                     for (int q = 0; q < NV; q++) {
                         Gy[q][TY][c] = G[q];
@@ -401,23 +440,23 @@ __global__ __launch_bounds__(NT) void k_tcouple(TArgs<R> a)
                     Lm[q] = -(Gm[q] - Gm_prev[q]) * im;
                     R Lpm = PAR ? (Pm[q] - Pm_prev[q]) * im : R(0);
                     if constexpr (DIM == 3) {
-                        a.T[0][bx.woff + q * cs + c] = Ly_prev[q] + Lm[q] + (PAR ? Px_prev[q] : R(0));
-                        a.T[1][bx.woff + q * cs + c] = Lx_prev[q] + Lm[q] + (PAR ? Py_prev[q] : R(0));
-                        a.T[2][bx.woff + q * cs + c] = Lx_prev[q] + Ly_prev[q] + Lpm;
+                        bT0.st(q, c, Ly_prev[q] + Lm[q] + (PAR ? Px_prev[q] : R(0)));
+                        bT1.st(q, c, Lx_prev[q] + Lm[q] + (PAR ? Py_prev[q] : R(0)));
+                        bT2.st(q, c, Lx_prev[q] + Ly_prev[q] + Lpm);
                         S[q] = Lx_prev[q] + Ly_prev[q] + Lm[q];
                     } else {
-                        a.T[0][bx.woff + q * cs + c] = Lm[q] + (PAR ? Px_prev[q] : R(0));
-                        a.T[1][bx.woff + q * cs + c] = Lx_prev[q] + Lpm;
+                        bT0.st(q, c, Lm[q] + (PAR ? Px_prev[q] : R(0)));
+                        bT1.st(q, c, Lx_prev[q] + Lpm);
                         S[q] = Lx_prev[q] + Lm[q];
                     }
                 }
                 if constexpr (PAR) {
                     R u[NV], v[NV];
 #pragma unroll
-                    for (int q = 0; q < NV; q++) u[q] = a.U[bx.uoff + q * cs + c] + hdt * S[q];
+                    for (int q = 0; q < NV; q++) u[q] = Blk<R>(a.U + bx.uoff, bx.cells).ld(q, c) + hdt * S[q];
                     c2p<PHYS_MHD>(u, v, gam);
 #pragma unroll
-                    for (int q = 0; q < NV; q++) a.Vh[bx.woff + q * cs + c] = v[q];
+                    for (int q = 0; q < NV; q++) Blk<R>(a.Vh + bx.woff, bx.cells).st(q, c, v[q]);
                 }
             }
             // ---- in-plane increments of this plane, kept for one plane ----
@@ -529,10 +568,8 @@ __global__ __launch_bounds__(NT, (sizeof(R) == 4 ? CTU_SWEEP_WAVES_F32 : CTU_SWE
     const R hdt = R(0.5) * dt;
     int di, dj, dk;
     unit<D>(di, dj, dk);
-    const R *Vb = a.V + bx.woff;
-    const R *Ub = a.U + bx.uoff;
-    R *Uob = a.Uout + bx.uoff;
-    const R *Tb = a.T[D] + bx.woff;
+    const Blk<R> bV(a.V + bx.woff, bx.cells), bU(a.U + bx.uoff, bx.cells), bUo(a.Uout + bx.uoff, bx.cells);
+    const Blk<R> bT(a.T[D] + bx.woff, bx.cells);
     double rate_loc = 0.0, dpp_loc = 0.0;
 
     for (int base = 0; base < items; base += NT) {
@@ -566,7 +603,7 @@ __global__ __launch_bounds__(NT, (sizeof(R) == 4 ? CTU_SWEEP_WAVES_F32 : CTU_SWE
 #pragma unroll
             for (int l = l0; l < l1; l++)
 #pragma unroll
-                for (int q = 0; q < NV; q++) Vs[l][q] = Vb[q * cs + c + (l - 2) * sD];
+                for (int q = 0; q < NV; q++) Vs[l][q] = bV.ld(q, c + (l - 2) * sD);
             R Vm[NV], Vp[NV];
             if (o.hyp_off) {
 #pragma unroll
@@ -576,7 +613,7 @@ __global__ __launch_bounds__(NT, (sizeof(R) == 4 ? CTU_SWEEP_WAVES_F32 : CTU_SWE
             } else {
                 R U0[NV];
 #pragma unroll
-                for (int q = 0; q < NV; q++) U0[q] = Ub[q * cs + c];
+                for (int q = 0; q < NV; q++) U0[q] = bU.ld(q, c);
                 fl |= predict_mh<D, PHYS>(Vs, U0, o, gam, dtdx, ch, Vm, Vp);
             }
             R Up[NV];
@@ -585,7 +622,7 @@ __global__ __launch_bounds__(NT, (sizeof(R) == 4 ? CTU_SWEEP_WAVES_F32 : CTU_SWE
             // ---- corner coupling (Eq. transv) ----
 #pragma unroll
             for (int q = 0; q < NV; q++) {
-                R tr = hdt * Tb[q * cs + c];
+                R tr = hdt * bT.ld(q, c);
                 Um[q] += tr;
                 Up[q] += tr;
             }
@@ -606,11 +643,11 @@ __global__ __launch_bounds__(NT, (sizeof(R) == 4 ? CTU_SWEEP_WAVES_F32 : CTU_SWE
             // rare fallback to the cell-centred states: reloaded, not kept live
             if (fL) {
 #pragma unroll
-                for (int q = 0; q < NV; q++) VL[q] = Vb[q * cs + c - sD];
+                for (int q = 0; q < NV; q++) VL[q] = bV.ld(q, c - sD);
             }
             if (fR) {
 #pragma unroll
-                for (int q = 0; q < NV; q++) VR[q] = Vb[q * cs + c];
+                for (int q = 0; q < NV; q++) VR[q] = bV.ld(q, c);
             }
             R pL = VL[PRS], pR = VR[PRS], rL = VL[RHO], rR = VR[RHO];
             R smax = R(0);
@@ -656,11 +693,11 @@ __global__ __launch_bounds__(NT, (sizeof(R) == 4 ? CTU_SWEEP_WAVES_F32 : CTU_SWE
             const int cu = c - sD;
             R lamc = fmax(sL[tid], (tid >= DEL) ? sL[tid - DEL] : cL[tid]) / dxD;
             R u[NV];
-            const R *Ubase = a.first ? Ub : Uob;
+            const Blk<R> bUb = a.first ? bU : bUo;
 #pragma unroll
             for (int q = 0; q < NV; q++) {
                 R Flo = (tid >= DEL) ? sF[q][tid - DEL] : cF[q][tid];
-                u[q] = Ubase[q * cs + cu] - dtdx * (sF[q][tid] - Flo);
+                u[q] = bUb.ld(q, cu) - dtdx * (sF[q][tid] - Flo);
             }
             R lamt = lamc;
             if (o.parab) {
@@ -704,7 +741,7 @@ __global__ __launch_bounds__(NT, (sizeof(R) == 4 ? CTU_SWEEP_WAVES_F32 : CTU_SWE
                 rate_loc = fmax(rate_loc, (double)lamt);
             }
 #pragma unroll
-            for (int q = 0; q < NV; q++) Uob[q * cs + cu] = u[q];
+            for (int q = 0; q < NV; q++) bUo.st(q, cu, u[q]);
         }
         count_fails(fl, a.fails);
         __syncthreads();

@@ -368,9 +368,11 @@ ctu_status ctu_plan_create(const ctu_opts *opts, const ctu_box *boxes, int32_t n
             return fail(CTU_ERR_ARG, "bad box level or offset (offsets are multiples of 9)");
         }
         kb.cells = (long long)kb.N[0] * kb.N[1] * kb.N[2];
-        if (NV * kb.cells >= (1LL << 31)) {
+        // the kernels address one box's nine planes with 32-bit byte offsets
+        if (NV * kb.cells * p->esize > 0xFFFFFFFFLL) {
             free_plan(p);
-            return fail(CTU_ERR_ARG, "a box must hold fewer than 2^31/9 ghosted cells (split larger grids into boxes)");
+            return fail(CTU_ERR_ARG,
+                        "a box's nine variable planes must fit in 4 GiB of ghosted cells (split larger grids into boxes)");
         }
         kb.uoff = B.offset;
         kb.woff = woff;
