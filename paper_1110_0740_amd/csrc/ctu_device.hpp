@@ -34,13 +34,22 @@ template <int D> struct Ax {
 };
 
 template <typename R> __device__ __forceinline__ R sq(R x) { return x * x; }
+// 1/sqrt(x): the hardware reciprocal root in FP32 (the FP32 unit runs with
+// approximate divide / sqrt and flushed subnormals), the correctly rounded
+// quotient in FP64
+template <typename R> __device__ __forceinline__ R rsq(R x)
+{
+    if constexpr (sizeof(R) == 4) return __builtin_amdgcn_rsqf(x);
+    else return R(1) / sqrt(x);
+}
 template <typename R> __device__ __forceinline__ R sgn1(R a) { return a < R(0) ? R(-1) : R(1); }
 
 // ---------------------------------------------------------------------------
 // Ideal MHD (Sec. 2.1, Eq. mhd, ideal-gas closure)
 // ---------------------------------------------------------------------------
 
-template <typename R> __device__ __forceinline__ void p2c_mhd(const R *V, R *U, R gm1)
+// igm1 = 1 / (Gamma - 1), formed once by the caller's hoisted division
+template <typename R> __device__ __forceinline__ void p2c_mhd(const R *V, R *U, R igm1)
 {
     R kin = V[RHO] * (sq(V[MX1]) + sq(V[MX2]) + sq(V[MX3]));
     R mag = sq(V[BX1]) + sq(V[BX2]) + sq(V[BX3]);
@@ -48,7 +57,7 @@ template <typename R> __device__ __forceinline__ void p2c_mhd(const R *V, R *U, 
     U[MX1] = V[RHO] * V[MX1];
     U[MX2] = V[RHO] * V[MX2];
     U[MX3] = V[RHO] * V[MX3];
-    U[ENG] = V[PRS] / gm1 + R(0.5) * (kin + mag);
+    U[ENG] = V[PRS] * igm1 + R(0.5) * (kin + mag);
     U[BX1] = V[BX1];
     U[BX2] = V[BX2];
     U[BX3] = V[BX3];
@@ -251,7 +260,7 @@ template <int D, typename R> __device__ __forceinline__ void speeds_rmhd(const R
 
 template <int PHYS, typename R> __device__ __forceinline__ void p2c(const R *V, R *U, R gam)
 {
-    if constexpr (PHYS == PHYS_MHD) p2c_mhd(V, U, gam - R(1));
+    if constexpr (PHYS == PHYS_MHD) p2c_mhd(V, U, R(1) / (gam - R(1)));
     else p2c_rmhd(V, U, gam);
 }
 
@@ -347,7 +356,7 @@ __device__ __forceinline__ void hlld(const R *VL, const R *VR, R *F, R &smax, R 
     R pts = (aR * ptL - aL * ptR + aL * aR * (uR - uL)) * iden;
 
     // single-star states; index 0 = left, 1 = right
-    R rs[2], vt[2], vb[2], Bt[2], Bb[2], Es[2], sr[2];
+    R rs[2], vt[2], vb[2], Bt[2], Bb[2], Es[2], sr[2], isr[2];
 #pragma unroll
     for (int s = 0; s < 2; s++) {
         const R *V = s ? VR : VL;
@@ -372,10 +381,11 @@ __device__ __forceinline__ void hlld(const R *VL, const R *VR, R *F, R &smax, R 
         R vB = V[MX1] * V[BX1] + V[MX2] * V[BX2] + V[MX3] * V[BX3];
         R vBs = SM * Bn + vt[s] * Bt[s] + vb[s] * Bb[s];
         Es[s] = (Su * U[ENG] - pt * u + pts * SM + Bn * (vB - vBs)) * iSSM;
-        sr[s] = sqrt(rs[s]);
+        isr[s] = rsq(rs[s]);
+        sr[s] = rs[s] * isr[s];
     }
-    R SLs = SM - fabs(Bn) / sr[0];
-    R SRs = SM + fabs(Bn) / sr[1];
+    R SLs = SM - fabs(Bn) * isr[0];
+    R SRs = SM + fabs(Bn) * isr[1];
 
     // region: outer (F_L or F_R), single star (L* or R*) or double star on
     // side k; k follows S_M inside the fan
@@ -438,7 +448,8 @@ __device__ __forceinline__ void riemann(R *VL, R *VR, R *F, R &smax, R gam, R ch
 {
     R Bm, psim;
     if (glm) {
-        Bm = R(0.5) * (VL[BX1 + D] + VR[BX1 + D]) - (VR[PSI] - VL[PSI]) / (R(2) * ch);
+        const R ih = R(0.5) / ch;  // loop-invariant, hoisted
+        Bm = R(0.5) * (VL[BX1 + D] + VR[BX1 + D]) - (VR[PSI] - VL[PSI]) * ih;
         psim = R(0.5) * (VL[PSI] + VR[PSI]) - R(0.5) * ch * (VR[BX1 + D] - VL[BX1 + D]);
     } else {
         Bm = R(0.5) * (VL[BX1 + D] + VR[BX1 + D]);
@@ -551,13 +562,16 @@ __device__ __forceinline__ void trace(int wref, R dm, R dp, R nu, R numax, R num
 template <typename R> struct Eigen {
     R rho, srho, a, a2, cf, cs, ca, af, as, by, bz, s;
     R X, Y, Z;  // 1/(2N), 1/(2 a sqrt(rho)), 1/(2 rho a^2), N = af^2 cf^2 + as^2 cs^2
+    R isrho, ia2;  // 1/sqrt(rho), 1/a^2
 };
 
 template <int D, typename R> __device__ __forceinline__ void eigen_setup(const R *V, R gam, Eigen<R> &e)
 {
     constexpr int n = Ax<D>::n, t = Ax<D>::t, b = Ax<D>::b;
+    // reciprocal roots carry the divisions: 1/sqrt(rho), 1/a, 1/c_f
     R rho = V[RHO];
-    R ir = R(1) / rho;
+    R isr = rsq(rho);
+    R ir = isr * isr;
     R Bn = V[BX1 + n], Bt = V[BX1 + t], Bb = V[BX1 + b];
     R a2 = gam * V[PRS] * ir;
     R bn2 = Bn * Bn * ir;
@@ -567,14 +581,17 @@ template <int D, typename R> __device__ __forceinline__ void eigen_setup(const R
     R dab = a2 - b2;
     R root = sqrt(dab * dab + R(4) * a2 * bt2);  // c_f^2 - c_s^2, exact for b_t = 0
     R cf2 = R(0.5) * (a2 + b2 + root);
-    R cs2 = a2 * bn2 / cf2;                      // c_f^2 c_s^2 = a^2 c_a^2
+    R ia = rsq(a2), icf = rsq(cf2);
     e.rho = rho;
-    e.srho = sqrt(rho);
+    e.srho = rho * isr;
+    e.isrho = isr;
     e.a2 = a2;
-    e.a = sqrt(a2);
-    e.cf = sqrt(cf2);
-    e.cs = sqrt(cs2);
-    e.ca = sqrt(bn2);
+    e.ia2 = ia * ia;
+    e.a = a2 * ia;
+    e.cf = cf2 * icf;
+    e.ca = fabs(Bn) * isr;
+    e.cs = e.a * e.ca * icf;                     // c_f c_s = a c_a
+    R cs2 = e.cs * e.cs;
     if (root > R(0)) {
         R ir2 = R(0.5) / root;
         R af2 = (root + dab) * ir2, as2 = (root - dab) * ir2;
@@ -588,15 +605,15 @@ template <int D, typename R> __device__ __forceinline__ void eigen_setup(const R
         e.by = R(0.70710678118654752440);
         e.bz = R(0.70710678118654752440);
     } else {
-        R ib = R(1) / sqrt(Bt2);
+        R ib = rsq(Bt2);
         e.by = Bt * ib;
         e.bz = Bb * ib;
     }
     e.s = sgn1(Bn);
     R N = e.af * e.af * cf2 + e.as * e.as * cs2;
     e.X = R(0.5) / N;
-    e.Y = R(0.5) / (e.a * e.srho);
-    e.Z = R(0.5) / (rho * a2);
+    e.Y = R(0.5) * ia * isr;
+    e.Z = R(0.5) * ir * e.ia2;
 }
 
 // project a primitive difference dq onto the 7 left eigenvectors
@@ -617,10 +634,10 @@ template <int D, typename R> __device__ __forceinline__ void project(const Eigen
     w[6] = fu - fv + fB + fp;   // v + c_f
     w[2] = -su - sv - sB + sp;  // v - c_s
     w[4] = su + sv - sB + sp;   // v + c_s
-    R hv = R(0.5) * vpe, hB = R(0.5) * e.s * Bpe / e.srho;
+    R hv = R(0.5) * vpe, hB = R(0.5) * e.s * Bpe * e.isrho;
     w[1] = hv + hB;             // v - c_a
     w[5] = hv - hB;             // v + c_a
-    w[3] = dq[RHO] - dp / e.a2; // entropy
+    w[3] = dq[RHO] - dp * e.ia2; // entropy
 }
 
 // dV = sum_k c_k r_k (right eigenvectors), added to V
@@ -732,7 +749,7 @@ __device__ __forceinline__ void predict_char(const R (*Vs)[NV], const KOpts &o, 
     constexpr int t = Ax<D>::t, b = Ax<D>::b;
     R h = R(0.5) * dtdx;
     R gB = h * dBn, gP = h * dpsi;
-    R ir = R(1) / V0[RHO];
+    R ir = e.isrho * e.isrho;
     R vB = V0[MX1] * V0[BX1] + V0[MX2] * V0[BX2] + V0[MX3] * V0[BX3];
     R src[NV] = { R(0) };
     src[MX1 + D] = gB * V0[BX1 + D] * ir;

@@ -565,6 +565,7 @@ __global__ __launch_bounds__(NT, (sizeof(R) == 4 ? CTU_SWEEP_WAVES_F32 : CTU_SWE
     const R ch = R(a.params[1]);
     const R dxD = R(bx.dx[D]);
     const R dtdx = dt / dxD;
+    const R idxD = R(1) / dxD;
     const R hdt = R(0.5) * dt;
     int di, dj, dk;
     unit<D>(di, dj, dk);
@@ -691,7 +692,7 @@ __global__ __launch_bounds__(NT, (sizeof(R) == 4 ? CTU_SWEEP_WAVES_F32 : CTU_SWE
         // ---- conservative update (Eq. update) of the cell below the item ----
         if (valid && s >= 2) {
             const int cu = c - sD;
-            R lamc = fmax(sL[tid], (tid >= DEL) ? sL[tid - DEL] : cL[tid]) / dxD;
+            R lamc = fmax(sL[tid], (tid >= DEL) ? sL[tid - DEL] : cL[tid]) * idxD;
             R u[NV];
             const Blk<R> bUb = a.first ? bU : bUo;
 #pragma unroll
