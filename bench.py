@@ -23,22 +23,27 @@ sys.path.insert(0, ROOT)
 
 METRIC = "zone-updates/sec per CTU step (FP32 batched vs FP64 plain) + achieved HBM GB/s"
 
-# Issued VALU floating-point operations per interior zone of the dominant
-# kernel (the x sweep, FP32), from the rocprofv3 counter pass recorded in
-# profiles/sweep_x_fp32_256cube_counters.md (64 lanes x (ADD + MUL + TRANS +
-# 2 FMA) per wave instruction / interior zones).  None until measured.
-SWEEP_FLOPS_PER_ZONE = {"sweep_x": 2114.0, "sweep_y": 2113.0, "sweep_z": 2123.0}
-# HBM bytes per launch from FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (KiB x 1024):
-# a plain 1 GiB copy (bench.py --copy-calibration) reads 0.50 GiB of
-# FETCH_SIZE and 1.00 GiB of WRITE_SIZE, hence the factors; recorded in
-# profiles/sweep_fp32_256cube_counters.md.  Set to None when the kernels
-# change after the counter runs.
-SWEEP_TRAFFIC_BYTES = {"sweep_x": (2292071 * 2 + 652225) * 1024, "sweep_y": (3029403 * 2 + 690208) * 1024,
-                       "sweep_z": (3067881 * 2 + 690208) * 1024}
+# FP32 floating-point operations per interior zone of each kernel of the
+# FP32 step (256^3, PPM + HLLD + GLM), counted by rocprofv3
+# (SQ_INSTS_VALU_FLOPS_FP32 x 64 lanes / 16,777,216 zones, which equals
+# 64 x (ADD + MUL + 2 FMA + TRANS) wave instructions); recorded with the
+# commands in profiles/ctu_step_fp32_256cube_counters.md.  They include
+# the ~1 % of items computed for the pencil ends.
+KERNEL_FLOPS_PER_ZONE = {"prim": 37.0, "tcouple": 1481.0, "sweep_x": 1397.0, "sweep_y": 1396.0,
+                         "sweep_z": 1399.0}
+# HBM bytes per launch, FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (KiB x 1024): a
+# plain 1 GiB device copy (bench.py --copy-calibration) reads back as
+# 524,308 KiB of FETCH_SIZE and 1,048,576 KiB of WRITE_SIZE, hence the
+# factors.  Same profile file; set an entry to None when its kernel changes
+# after the counter runs.
+KERNEL_TRAFFIC_BYTES = {"prim": (327952 * 2 + 646866) * 1024, "tcouple": (1626130 * 2 + 2304169) * 1024,
+                        "sweep_x": (918923 * 2 + 639105) * 1024, "sweep_y": (1447951 * 2 + 663584) * 1024,
+                        "sweep_z": (1446567 * 2 + 663584) * 1024}
 # Algorithmic HBM bytes per zone of a whole step (read U^n on the ghosted box,
 # write U^{n+1}): 36 B x (264/256)^3 + 36 B in FP32, twice that in FP64.
 PEAK_HBM_GBS = 8000.0
-PEAK_FP32_TFLOPS = 157.3
+PEAK_FP32_TFLOPS = 157.3           # published FP32 vector peak (packed FP32 issue)
+PEAK_FP32_UNPACKED_TFLOPS = 78.6   # one FP32 lane op per VALU lane per cycle (this build emits no packed FP32)
 PEAK_FP64_TFLOPS = 78.6
 
 
@@ -325,12 +330,14 @@ def main():
     if "stage_ms" in res:
         dom = max(res["stage_ms"], key=res["stage_ms"].get)
         dom_ms = res["stage_ms"][dom]
-        fpz = SWEEP_FLOPS_PER_ZONE.get(dom)
+        fpz = KERNEL_FLOPS_PER_ZONE.get(dom) if main_key == "fp32_batched" and n == 256 else None
         if fpz is not None:
             achieved = fpz * zones / (dom_ms * 1e-3) / 1e12
             roofline = {"bound": "alu", "kernel": dom, "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
                         "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
-                        "traffic": SWEEP_TRAFFIC_BYTES.get(dom), "avg_ms": dom_ms}
+                        "traffic": KERNEL_TRAFFIC_BYTES.get(dom), "avg_ms": dom_ms,
+                        "flop_per_zone": fpz, "peak_unpacked": PEAK_FP32_UNPACKED_TFLOPS,
+                        "frac_unpacked": achieved / PEAK_FP32_UNPACKED_TFLOPS}
         else:
             roofline = {"bound": "alu", "kernel": dom, "achieved": None, "peak": PEAK_FP32_TFLOPS,
                         "unit": "TFLOP/s", "frac": None, "traffic": None, "avg_ms": dom_ms}
