@@ -459,7 +459,7 @@ def _blob_bump(blobs, x, widen=1.0):
 
 
 def amr_hierarchy(seed: int = 3000, base: int = 128, base_box: int = 32, lattice: int = 32,
-                  size_range=(16, 32), nblobs: int = 8, p1=(0.75, 1.0), p2=(0.35, 1.2)) -> Hierarchy:
+                  size_range=(16, 32), nblobs: int = 8, p1=(0.75, 1.0), p2=(0.35, 1.2), nest: int = 1) -> Hierarchy:
     """Level 0 tiles the base^3 domain with base_box^3 boxes.  Level 1 (2x)
     places at most one box per lattice^3 cell of a jittered lattice, with
     probability p1[0] + p1[1] * bump, bump = max_b exp(-|x - c_b|^2/(3 r_b)^2)
@@ -467,8 +467,11 @@ def amr_hierarchy(seed: int = 3000, base: int = 128, base_box: int = 32, lattice
     axis, origins even, one level-1 cell of margin from the domain boundary.
     Level 2 (4x) refines a level-1 box with probability p2[0] + p2[1] * bump
     (width 2 r_b) into 1 or 2 children per axis inside the parent shrunk by
-    one level-1 cell (2 level-2 cells), sizes even in size_range.  Boxes are
-    therefore disjoint per level and properly nested by construction."""
+    `nest` level-1 cells (2 nest level-2 cells), sizes even in size_range.
+    Boxes are therefore disjoint per level and properly nested by
+    construction; nest = 3 keeps the coarse stencil of every level-2 ghost
+    cell (2 coarse cells deep, plus 1 for the slopes) inside the parent, as
+    the coarse-to-fine ghost fill needs."""
     rng = SplitMix64(seed)
     blobs = []
     for _ in range(nblobs):
@@ -509,8 +512,8 @@ def amr_hierarchy(seed: int = 3000, base: int = 128, base_box: int = 32, lattice
             continue
         segs = []
         for q in range(3):
-            u0 = 2 * P.lo[q] + 2
-            u1 = 2 * (P.lo[q] + P.n[q]) - 2
+            u0 = 2 * P.lo[q] + 2 * nest
+            u1 = 2 * (P.lo[q] + P.n[q]) - 2 * nest
             usable = u1 - u0
             parts = 2 if (usable >= 2 * lo_s and rng.uniform() < 0.75) else 1
             width = usable // parts
