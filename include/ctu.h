@@ -212,6 +212,64 @@ ctu_status ctu_cons_to_prim(ctu_plan *plan, const void *U_dev, void *V_dev, int3
 ctu_status ctu_plan_set_reflux(ctu_plan *coarse_plan, const ctu_refluxface *faces, int32_t nfaces);
 ctu_status ctu_reflux(ctu_plan *coarse_plan, void *U_dev, const double *reg_dev, void *stream);
 
+/* As ctu_reflux, then clears every register slot the table read (each slot
+ * belongs to one face, hence to one corrected cell), ready for the next
+ * accumulation; slots the table does not name are left as they are. */
+ctu_status ctu_reflux_consume(ctu_plan *coarse_plan, void *U_dev, double *reg_dev, void *stream);
+
+/* ---- AMR level cycle (Sec. 4) -------------------------------------------
+ *
+ * A hierarchy of boxes on a periodic cube of `base` level-0 cells per side
+ * with refinement ratio 2: level l has base * 2^l cells per side.
+ * level_nbox[l] boxes of level l follow each other in `boxes` (level-global
+ * indices, `level` = l, `offset` = element offset of the box block in that
+ * level's state array, the layout of ctu_plan_create).  3D only.  Checked at
+ * creation (CTU_ERR_ARG): boxes inside their level, 2-aligned (even lo and n)
+ * on levels >= 1, disjoint per level, level 0 covering the domain, every
+ * fine box inside the coarser level's interiors, each box block below 4 GiB.
+ * Host-side tables (candidate boxes per box for the lookups below) are
+ * uploaded once; creation is the only allocating call. */
+typedef struct ctu_hier ctu_hier;
+ctu_status ctu_hier_create(int32_t precision, int32_t base, int32_t nlev, const int32_t *level_nbox,
+                           const ctu_box *boxes, int32_t nghost, ctu_hier **out);
+void ctu_hier_destroy(ctu_hier *hier);
+
+/* Fill every ghost cell of every box of `level` in U_dev (that level's state
+ * array; interiors are read, ghosts written).  A ghost cell whose periodic
+ * image lies in a box interior of the same level is copied from it (level 0:
+ * always).  Otherwise it is prolonged (Eq. prolong, ratio 2: the parent
+ * value plus -+1/4 of the monotonised-central slope of the parent and its
+ * face neighbours per direction, Eq. MClim) from the coarse state
+ * (1 - alpha) Uc_old + alpha Uc_new (Eq. intalpha), read from coarse box
+ * interiors only; alpha in [0, 1], Uc_new may be null when alpha = 0.  A
+ * cell whose coarse stencil leaves the coarse interiors (insufficient
+ * nesting) is set to NaN and counted in *missing_dev (nullable). */
+ctu_status ctu_hier_fill_ghosts(ctu_hier *hier, int32_t level, void *U_dev, const void *Uc_old_dev,
+                                const void *Uc_new_dev, double alpha, int32_t *missing_dev, void *stream);
+
+/* Eq. avgdown (ratio 2, equal Cartesian volumes): every coarse cell under a
+ * box interior of `fine_level` becomes the mean of its 8 children. */
+ctu_status ctu_hier_average_down(ctu_hier *hier, int32_t fine_level, const void *U_fine_dev, void *U_coarse_dev,
+                                 void *stream);
+
+/* One level-0 step of the whole hierarchy with time subcycling (Sec. 4):
+ * level l is filled (level 0 periodically; level l >= 1 at alpha = 0 and
+ * 1/2 of its parent's step), advanced by ctu_step with plans[l], then level
+ * l+1 takes two substeps, is averaged down into level l, and level l is
+ * refluxed with ctu_reflux_consume.  plans[l] holds level l's boxes in the
+ * same order and offsets, with its register faces and reflux table (the
+ * caller builds both); params_dev[l] = {dt_l, c_h} on the device with
+ * dt_l = dt_0 / 2^l.  Each level has two state arrays U_a[l], U_b[l];
+ * cur[l] (host, 0 or 1) names the one holding the current state and is
+ * updated on return.  reg_dev (FP64 registers, zero on the first call) is
+ * left with every slot it read cleared.  rate_dev[l] receives the CFL rate
+ * of level l's last substep; fails_dev[5] (nullable) accumulates the
+ * failure counts of every step; missing_dev (nullable) as above.
+ * Asynchronous on `stream`; allocation-free. */
+ctu_status ctu_hier_advance(ctu_hier *hier, ctu_plan *const *plans, void *const *U_a, void *const *U_b,
+                            int32_t *cur, const double *const *params_dev, double *reg_dev, double *rate_dev,
+                            int32_t *fails_dev, int32_t *missing_dev, void *stream);
+
 /* Per-stage kernel timing with HIP events recorded on the launch stream
  * around each kernel of ctu_step (eager launches only, not inside captured
  * graphs).  Enabling (re)starts the accumulation; up to 256 steps are

@@ -1,0 +1,186 @@
+// ctu_hier.hpp -- device kernels of the AMR level cycle (Sec. 4): ghost
+// filling by same-level periodic copy or coarse-to-fine prolongation of
+// time-interpolated coarse data (Eq. prolong, Eq. intalpha), and restriction
+// (Eq. avgdown), for refinement ratio 2 in 3D.
+//
+// A level's state array holds one ghosted block per box, q[v][k][j][i] with
+// i fastest, at the box's element offset.  Every thread handles one cell.
+// Candidate lists, built on the host per box, name the boxes that can hold
+// a cell the thread looks up (same level: interiors meeting the box's
+// ghosted extent under the periodic shifts; coarse level: interiors meeting
+// the coarse stencil of its ghosts; for restriction: interiors meeting its
+// coarse footprint), so no search spans the whole level.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "ctu_device.hpp"
+
+namespace ctu {
+
+struct HBox {
+    int lo[3], n[3], N[3];  // interior origin (level-global) and extents; ghosted extents
+    int pad;
+    long long off;    // element offset of the box block in the level array
+    long long cells;  // ghosted cells
+};
+
+struct HTile {
+    int box, start;
+};
+
+__device__ __forceinline__ int wrapi(int a, int N)
+{
+    int r = a % N;
+    return r < 0 ? r + N : r;
+}
+
+__device__ __forceinline__ bool holds(const HBox &b, int gi, int gj, int gk)
+{
+    return gi >= b.lo[0] && gi < b.lo[0] + b.n[0] && gj >= b.lo[1] && gj < b.lo[1] + b.n[1] && gk >= b.lo[2] &&
+           gk < b.lo[2] + b.n[2];
+}
+
+// element index of interior cell (gi, gj, gk) of box b, variable 0
+__device__ __forceinline__ long long hidx(const HBox &b, int gi, int gj, int gk, int ng)
+{
+    return b.off + ((long long)(gk - b.lo[2] + ng) * b.N[1] + (gj - b.lo[1] + ng)) * b.N[0] + (gi - b.lo[0] + ng);
+}
+
+// Time-interpolated coarse state at the (wrapped) coarse cell (ci, cj, ck),
+// read from the interiors of the candidate coarse boxes; false if none holds it.
+template <typename R>
+__device__ __forceinline__ bool coarse_state(const HBox *cbox, const int *cand, int c0, int c1, int ci, int cj, int ck,
+                                             int ng, const R *Uo, const R *Un, R alpha, R *u)
+{
+    for (int e = c0; e < c1; e++) {
+        const HBox cb = cbox[cand[e]];
+        if (!holds(cb, ci, cj, ck)) continue;
+        const long long p = hidx(cb, ci, cj, ck, ng);
+        if (alpha == R(0)) {
+#pragma unroll
+            for (int q = 0; q < NV; q++) u[q] = Uo[p + q * cb.cells];
+        } else {
+#pragma unroll
+            for (int q = 0; q < NV; q++) u[q] = (R(1) - alpha) * Uo[p + q * cb.cells] + alpha * Un[p + q * cb.cells];
+        }
+        return true;
+    }
+    return false;
+}
+
+// monotonised central slope of the one-sided differences (same value as
+// minmod((dp + dm)/2, 2 minmod(dm, dp)))
+template <typename R> __device__ __forceinline__ R mc_slope(R dp, R dm)
+{
+    R c = R(0.5) * (dp + dm);
+    R m = fmin(fmin(fabs(c), R(2) * fabs(dp)), R(2) * fabs(dm));
+    return (dp * dm > R(0)) ? copysign(m, c) : R(0);
+}
+
+// Ghost cells of every box of one level.  cbox == nullptr on level 0, whose
+// boxes must cover the periodic domain.  A cell that neither a same-level
+// box nor the coarse interiors can supply is set to NaN and counted.
+template <typename R>
+__global__ __launch_bounds__(NT) void k_hfill(const HBox *box, const HTile *tiles, const int *nb_start,
+                                              const int *nb_list, const HBox *cbox, const int *cb_start,
+                                              const int *cb_list, int N, int ng, R *U, const R *Uo, const R *Un,
+                                              double alpha_d, int *missing)
+{
+    const HTile t = tiles[blockIdx.x];
+    const HBox b = box[t.box];
+    const long long li = (long long)t.start + threadIdx.x;
+    if (li >= b.cells) return;
+    const int i = (int)(li % b.N[0]), j = (int)((li / b.N[0]) % b.N[1]), k = (int)(li / ((long long)b.N[0] * b.N[1]));
+    if (i >= ng && i < ng + b.n[0] && j >= ng && j < ng + b.n[1] && k >= ng && k < ng + b.n[2]) return;
+    const int gi = wrapi(b.lo[0] + i - ng, N), gj = wrapi(b.lo[1] + j - ng, N), gk = wrapi(b.lo[2] + k - ng, N);
+    R *dst = U + b.off + li;
+    // same level
+    for (int e = nb_start[t.box]; e < nb_start[t.box + 1]; e++) {
+        const HBox c = box[nb_list[e]];
+        if (!holds(c, gi, gj, gk)) continue;
+        const long long p = hidx(c, gi, gj, gk, ng);
+#pragma unroll
+        for (int q = 0; q < NV; q++) dst[q * b.cells] = U[p + q * c.cells];
+        return;
+    }
+    bool ok = cbox != nullptr;
+    R out[NV];
+    if (ok) {
+        // Eq. prolong: parent value plus -+1/4 of the MC slope per direction
+        const int Nc = N / 2, c0 = cb_start[t.box], c1 = cb_start[t.box + 1];
+        const int pi = gi / 2, pj = gj / 2, pk = gk / 2;
+        const R alpha = R(alpha_d);
+        R u0[NV];
+        ok = coarse_state(cbox, cb_list, c0, c1, pi, pj, pk, ng, Uo, Un, alpha, u0);
+#pragma unroll
+        for (int q = 0; q < NV; q++) out[q] = u0[q];
+#pragma unroll
+        for (int d = 0; d < 3; d++) {
+            R up[NV], dn[NV];
+            const int di = (d == 0), dj = (d == 1), dk = (d == 2);
+            ok = ok && coarse_state(cbox, cb_list, c0, c1, wrapi(pi + di, Nc), wrapi(pj + dj, Nc), wrapi(pk + dk, Nc),
+                                    ng, Uo, Un, alpha, up);
+            ok = ok && coarse_state(cbox, cb_list, c0, c1, wrapi(pi - di, Nc), wrapi(pj - dj, Nc), wrapi(pk - dk, Nc),
+                                    ng, Uo, Un, alpha, dn);
+            const int f = (d == 0) ? gi : (d == 1 ? gj : gk);
+            const R off = (f & 1) ? R(0.25) : R(-0.25);
+            if (ok) {
+#pragma unroll
+                for (int q = 0; q < NV; q++) out[q] += off * mc_slope(up[q] - u0[q], u0[q] - dn[q]);
+            }
+        }
+    }
+    if (!ok) {
+#pragma unroll
+        for (int q = 0; q < NV; q++) out[q] = R(NAN);
+        if (missing) atomicAdd(missing, 1);
+    }
+#pragma unroll
+    for (int q = 0; q < NV; q++) dst[q * b.cells] = out[q];
+}
+
+// Eq. avgdown (ratio 2, equal Cartesian volumes): each coarse cell under a
+// fine box interior becomes the mean of its 8 children, summed in (k, j, i)
+// child order.
+template <typename R>
+__global__ __launch_bounds__(NT) void k_havg(const HBox *fbox, const HTile *tiles, const int *pb_start,
+                                             const int *pb_list, const HBox *cbox, int ng, const R *Uf, R *Uc,
+                                             int *missing)
+{
+    const HTile t = tiles[blockIdx.x];
+    const HBox f = fbox[t.box];
+    const int m0 = f.n[0] / 2, m1 = f.n[1] / 2, m2 = f.n[2] / 2;
+    const long long li = (long long)t.start + threadIdx.x;
+    if (li >= (long long)m0 * m1 * m2) return;
+    const int a = (int)(li % m0), b = (int)((li / m0) % m1), c = (int)(li / ((long long)m0 * m1));
+    R s[NV];
+#pragma unroll
+    for (int q = 0; q < NV; q++) s[q] = R(0);
+    for (int dk = 0; dk < 2; dk++)
+        for (int dj = 0; dj < 2; dj++)
+            for (int di = 0; di < 2; di++) {
+                const long long p = f.off + ((long long)(2 * c + dk + ng) * f.N[1] + (2 * b + dj + ng)) * f.N[0] +
+                                    (2 * a + di + ng);
+#pragma unroll
+                for (int q = 0; q < NV; q++) s[q] += Uf[p + q * f.cells];
+            }
+    const int gi = f.lo[0] / 2 + a, gj = f.lo[1] / 2 + b, gk = f.lo[2] / 2 + c;
+    for (int e = pb_start[t.box]; e < pb_start[t.box + 1]; e++) {
+        const HBox cb = cbox[pb_list[e]];
+        if (!holds(cb, gi, gj, gk)) continue;
+        const long long p = hidx(cb, gi, gj, gk, ng);
+#pragma unroll
+        for (int q = 0; q < NV; q++) Uc[p + q * cb.cells] = s[q] / R(8);
+        return;
+    }
+    if (missing) atomicAdd(missing, 1);
+}
+
+// fails_acc[q] += fails[q]
+__global__ void k_add_fails(int *acc, const int *f)
+{
+    const int t = threadIdx.x;
+    if (t < 5) acc[t] += f[t];
+}
+
+}  // namespace ctu

@@ -820,9 +820,11 @@ struct KRefl {
     long long fslot[4];
 };
 
+// With consume != 0 the register slots read are cleared afterwards: each
+// slot belongs to one face and so to one corrected cell (one thread).
 template <typename R>
 __global__ __launch_bounds__(NT) void k_reflux(const KBox *boxes, const KRefl *ent, const int *cell_start, int ncell,
-                                               R *U, const double *reg)
+                                               R *U, double *reg, int consume)
 {
     int cidx_ = blockIdx.x * NT + threadIdx.x;
     if (cidx_ >= ncell) return;
@@ -852,6 +854,16 @@ __global__ __launch_bounds__(NT) void k_reflux(const KBox *boxes, const KRefl *e
     for (int q = 0; q < NV; q++) {
         R *p = &U[bx.uoff + q * bx.cells + c];
         *p = R((double)(*p) + du[q]);
+    }
+    if (consume) {
+        for (int e = e0; e < e1; e++) {
+            KRefl en = ent[e];
+#pragma unroll
+            for (int q = 0; q < NV; q++) {
+                reg[9 * en.cslot + q] = 0.0;
+                for (int f = 0; f < en.nfine; f++) reg[9 * en.fslot[f] + q] = 0.0;
+            }
+        }
     }
 }
 

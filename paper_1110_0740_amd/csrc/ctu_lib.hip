@@ -16,6 +16,7 @@
 
 #include "../../include/ctu.h"
 #include "ctu_dispatch.hpp"
+#include "ctu_hier.hpp"
 
 using namespace ctu;
 
@@ -663,7 +664,7 @@ ctu_status ctu_plan_set_reflux(ctu_plan *plan, const ctu_refluxface *faces, int3
     return CTU_OK;
 }
 
-ctu_status ctu_reflux(ctu_plan *plan, void *U_dev, const double *reg_dev, void *stream)
+static ctu_status reflux_launch(ctu_plan *plan, void *U_dev, double *reg_dev, int consume, void *stream)
 {
     if (!plan || !U_dev || !reg_dev) return fail(CTU_ERR_ARG, "plan, U and reg are required");
     if (plan->nrefl_cells == 0) return CTU_OK;
@@ -671,12 +672,352 @@ ctu_status ctu_reflux(ctu_plan *plan, void *U_dev, const double *reg_dev, void *
     hipStream_t s = (hipStream_t)stream;
     if (plan->esize == 4)
         hipLaunchKernelGGL((k_reflux<float>), dim3(nb), dim3(NT), 0, s, plan->dboxes, plan->drefl, plan->dcell_start,
-                           plan->nrefl_cells, (float *)U_dev, reg_dev);
+                           plan->nrefl_cells, (float *)U_dev, reg_dev, consume);
     else
         hipLaunchKernelGGL((k_reflux<double>), dim3(nb), dim3(NT), 0, s, plan->dboxes, plan->drefl,
-                           plan->dcell_start, plan->nrefl_cells, (double *)U_dev, reg_dev);
+                           plan->dcell_start, plan->nrefl_cells, (double *)U_dev, reg_dev, consume);
     HIP_TRY(hipGetLastError());
     return CTU_OK;
+}
+
+ctu_status ctu_reflux(ctu_plan *plan, void *U_dev, const double *reg_dev, void *stream)
+{
+    return reflux_launch(plan, U_dev, const_cast<double *>(reg_dev), 0, stream);
+}
+
+ctu_status ctu_reflux_consume(ctu_plan *plan, void *U_dev, double *reg_dev, void *stream)
+{
+    return reflux_launch(plan, U_dev, reg_dev, 1, stream);
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// AMR hierarchy: ghost filling, restriction and the subcycled level cycle
+// ---------------------------------------------------------------------------
+
+namespace {
+
+struct HierLevel {
+    int N = 0;  // cells per side of the periodic level
+    std::vector<HBox> hb;
+    std::vector<int> nb_start, nb_list, cb_start, cb_list, pb_start, pb_list;
+    std::vector<HTile> fill_t, avg_t;
+    HBox *db = nullptr;
+    int *d_nb_start = nullptr, *d_nb_list = nullptr, *d_cb_start = nullptr, *d_cb_list = nullptr;
+    int *d_pb_start = nullptr, *d_pb_list = nullptr;
+    HTile *d_fill_t = nullptr, *d_avg_t = nullptr;
+};
+
+int floor_div(int a, int b) { return (a >= 0) ? a / b : -((-a + b - 1) / b); }
+
+// do [a0, a1) and [b0, b1) + s meet for a shift s in {-N, 0, N}?
+bool meets_periodic(int a0, int a1, int b0, int b1, int N)
+{
+    for (int s = -N; s <= N; s += N)
+        if (std::max(a0, b0 + s) < std::min(a1, b1 + s)) return true;
+    return false;
+}
+
+// boxes whose interior meets the region [lo, hi) (per axis) under the
+// periodic shifts of an N-cell level (or without shifts when N == 0)
+void candidates(const std::vector<HBox> &boxes, const int lo[3], const int hi[3], int N, std::vector<int> &out)
+{
+    for (int c = 0; c < (int)boxes.size(); c++) {
+        const HBox &b = boxes[c];
+        bool ok = true;
+        for (int d = 0; d < 3 && ok; d++) {
+            if (N > 0) ok = meets_periodic(lo[d], hi[d], b.lo[d], b.lo[d] + b.n[d], N);
+            else ok = std::max(lo[d], b.lo[d]) < std::min(hi[d], b.lo[d] + b.n[d]);
+        }
+        if (ok) out.push_back(c);
+    }
+}
+
+long long overlap_volume(const HBox &a, const int lo[3], const int hi[3])
+{
+    long long v = 1;
+    for (int d = 0; d < 3; d++) {
+        int e = std::min(a.lo[d] + a.n[d], hi[d]) - std::max(a.lo[d], lo[d]);
+        if (e <= 0) return 0;
+        v *= e;
+    }
+    return v;
+}
+
+}  // namespace
+
+struct ctu_hier {
+    int esize = 8, base = 0, nlev = 0, ng = 0;
+    std::vector<HierLevel> lev;
+    int *dfails = nullptr;  // per-step failure counts inside the cycle
+};
+
+namespace {
+
+void free_hier(ctu_hier *h)
+{
+    if (!h) return;
+    for (HierLevel &L : h->lev) {
+        void *ptrs[] = { L.db, L.d_nb_start, L.d_nb_list, L.d_cb_start, L.d_cb_list, L.d_pb_start, L.d_pb_list,
+                         L.d_fill_t, L.d_avg_t };
+        for (void *q : ptrs)
+            if (q) (void)hipFree(q);
+    }
+    if (h->dfails) (void)hipFree(h->dfails);
+    delete h;
+}
+
+template <typename R>
+ctu_status hier_fill(ctu_hier *h, int level, void *U, const void *Uo, const void *Un, double alpha, int32_t *missing,
+                     hipStream_t s)
+{
+    HierLevel &L = h->lev[level];
+    if (L.fill_t.empty()) return CTU_OK;
+    const HBox *cbox = nullptr;
+    const int *cbs = nullptr, *cbl = nullptr;
+    if (level > 0) {
+        cbox = h->lev[level - 1].db;
+        cbs = L.d_cb_start;
+        cbl = L.d_cb_list;
+    }
+    hipLaunchKernelGGL((k_hfill<R>), dim3((unsigned)L.fill_t.size()), dim3(NT), 0, s, L.db, L.d_fill_t,
+                       L.d_nb_start, L.d_nb_list, cbox, cbs, cbl, L.N, h->ng, (R *)U, (const R *)Uo,
+                       (const R *)(Un ? Un : Uo), alpha, (int *)missing);
+    HIP_TRY(hipGetLastError());
+    return CTU_OK;
+}
+
+template <typename R>
+ctu_status hier_avg(ctu_hier *h, int fine, const void *Uf, void *Uc, hipStream_t s)
+{
+    HierLevel &F = h->lev[fine];
+    if (F.avg_t.empty()) return CTU_OK;
+    hipLaunchKernelGGL((k_havg<R>), dim3((unsigned)F.avg_t.size()), dim3(NT), 0, s, F.db, F.d_avg_t, F.d_pb_start,
+                       F.d_pb_list, h->lev[fine - 1].db, h->ng, (const R *)Uf, (R *)Uc, (int *)nullptr);
+    HIP_TRY(hipGetLastError());
+    return CTU_OK;
+}
+
+ctu_status hier_fill_any(ctu_hier *h, int level, void *U, const void *Uo, const void *Un, double alpha,
+                         int32_t *missing, hipStream_t s)
+{
+    return h->esize == 4 ? hier_fill<float>(h, level, U, Uo, Un, alpha, missing, s)
+                         : hier_fill<double>(h, level, U, Uo, Un, alpha, missing, s);
+}
+
+ctu_status hier_avg_any(ctu_hier *h, int fine, const void *Uf, void *Uc, hipStream_t s)
+{
+    return h->esize == 4 ? hier_avg<float>(h, fine, Uf, Uc, s) : hier_avg<double>(h, fine, Uf, Uc, s);
+}
+
+struct CycleArgs {
+    ctu_hier *h;
+    ctu_plan *const *plans;
+    void *const *Ua;
+    void *const *Ub;
+    int32_t *cur;
+    const double *const *params;
+    double *reg, *rate;
+    int32_t *fails, *missing;
+    hipStream_t s;
+};
+
+// advance `lev` by its dt; then, when a finer level exists, advance it twice
+// (ghosts from this level's old / new states at alpha = 0 and 1/2),
+// restrict it and reflux this level
+ctu_status advance_level(const CycleArgs &c, int lev, const void *pold, const void *pnew, double alpha)
+{
+    ctu_hier *h = c.h;
+    void *in = c.cur[lev] ? c.Ub[lev] : c.Ua[lev];
+    void *out = c.cur[lev] ? c.Ua[lev] : c.Ub[lev];
+    ctu_status st = hier_fill_any(h, lev, in, pold, pnew, alpha, c.missing, c.s);
+    if (st != CTU_OK) return st;
+    st = ctu_step(c.plans[lev], in, out, c.params[lev], nullptr, c.reg, c.rate + lev, nullptr, h->dfails, c.s);
+    if (st != CTU_OK) return st;
+    if (c.fails) {
+        hipLaunchKernelGGL(k_add_fails, dim3(1), dim3(64), 0, c.s, (int *)c.fails, (const int *)h->dfails);
+        HIP_TRY(hipGetLastError());
+    }
+    c.cur[lev] ^= 1;
+    if (lev + 1 < h->nlev) {
+        for (int q = 0; q < 2; q++)
+            if ((st = advance_level(c, lev + 1, in, out, 0.5 * q)) != CTU_OK) return st;
+        const void *fine_now = c.cur[lev + 1] ? c.Ub[lev + 1] : c.Ua[lev + 1];
+        if ((st = hier_avg_any(h, lev + 1, fine_now, out, c.s)) != CTU_OK) return st;
+        if ((st = reflux_launch(c.plans[lev], out, c.reg, 1, (void *)c.s)) != CTU_OK) return st;
+    }
+    return CTU_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+ctu_status ctu_hier_create(int32_t precision, int32_t base, int32_t nlev, const int32_t *level_nbox,
+                           const ctu_box *boxes, int32_t nghost, ctu_hier **out)
+{
+    if (!out) return fail(CTU_ERR_ARG, "out is required");
+    *out = nullptr;
+    if (precision != CTU_FP32 && precision != CTU_FP64) return fail(CTU_ERR_ARG, "bad precision");
+    if (base < 2 || nlev < 1 || nlev > 16 || nghost < 1 || !level_nbox || !boxes)
+        return fail(CTU_ERR_ARG, "need base >= 2, 1 <= nlev <= 16, nghost >= 1, level_nbox and boxes");
+    if ((long long)base << (nlev - 1) > (1LL << 30)) return fail(CTU_ERR_ARG, "finest level too large");
+    ctu_hier *h = new ctu_hier();
+    h->esize = (precision == CTU_FP32) ? 4 : 8;
+    h->base = base;
+    h->nlev = nlev;
+    h->ng = nghost;
+    h->lev.resize(nlev);
+    int pos = 0;
+    for (int l = 0; l < nlev; l++) {
+        HierLevel &L = h->lev[l];
+        L.N = base << l;
+        if (level_nbox[l] < 0) {
+            free_hier(h);
+            return fail(CTU_ERR_ARG, "negative box count");
+        }
+        for (int b = 0; b < level_nbox[l]; b++, pos++) {
+            const ctu_box &B = boxes[pos];
+            HBox hb{};
+            long long cells = 1;
+            for (int d = 0; d < 3; d++) {
+                hb.lo[d] = B.lo[d];
+                hb.n[d] = B.n[d];
+                hb.N[d] = B.n[d] + 2 * nghost;
+                cells *= hb.N[d];
+                if (B.n[d] < 1 || B.lo[d] < 0 || B.lo[d] + B.n[d] > L.N || (l > 0 && ((B.lo[d] | B.n[d]) & 1))) {
+                    free_hier(h);
+                    return fail(CTU_ERR_ARG, "box outside its level, empty, or (levels >= 1) not 2-aligned");
+                }
+            }
+            if (B.level != l || B.offset < 0) {
+                free_hier(h);
+                return fail(CTU_ERR_ARG, "box level must match its position; offsets must be >= 0");
+            }
+            if (NV * cells * h->esize > 0xFFFFFFFFLL) {
+                free_hier(h);
+                return fail(CTU_ERR_ARG, "a box's nine variable planes must fit in 4 GiB");
+            }
+            hb.off = B.offset;
+            hb.cells = cells;
+            L.hb.push_back(hb);
+        }
+        // disjoint interiors; level 0 covers the domain
+        long long vol = 0;
+        for (size_t a = 0; a < L.hb.size(); a++) {
+            int hi[3];
+            for (int d = 0; d < 3; d++) hi[d] = L.hb[a].lo[d] + L.hb[a].n[d];
+            vol += (long long)L.hb[a].n[0] * L.hb[a].n[1] * L.hb[a].n[2];
+            for (size_t c = a + 1; c < L.hb.size(); c++)
+                if (overlap_volume(L.hb[c], L.hb[a].lo, hi) > 0) {
+                    free_hier(h);
+                    return fail(CTU_ERR_ARG, "boxes of one level overlap");
+                }
+        }
+        if (l == 0 && vol != (long long)L.N * L.N * L.N) {
+            free_hier(h);
+            return fail(CTU_ERR_ARG, "level 0 must cover the periodic domain");
+        }
+    }
+    for (int l = 0; l < nlev; l++) {
+        HierLevel &L = h->lev[l];
+        L.nb_start.push_back(0);
+        L.cb_start.push_back(0);
+        L.pb_start.push_back(0);
+        for (int b = 0; b < (int)L.hb.size(); b++) {
+            const HBox &B = L.hb[b];
+            int lo[3], hi[3];
+            for (int d = 0; d < 3; d++) {
+                lo[d] = B.lo[d] - nghost;
+                hi[d] = B.lo[d] + B.n[d] + nghost;
+            }
+            candidates(L.hb, lo, hi, L.N, L.nb_list);
+            L.nb_start.push_back((int)L.nb_list.size());
+            if (l > 0) {
+                const HierLevel &C = h->lev[l - 1];
+                int clo[3], chi[3], flo[3], fhi[3];
+                for (int d = 0; d < 3; d++) {
+                    clo[d] = floor_div(lo[d], 2) - 1;
+                    chi[d] = floor_div(hi[d] - 1, 2) + 2;
+                    flo[d] = B.lo[d] / 2;
+                    fhi[d] = (B.lo[d] + B.n[d]) / 2;
+                }
+                candidates(C.hb, clo, chi, C.N, L.cb_list);
+                size_t p0 = L.pb_list.size();
+                candidates(C.hb, flo, fhi, 0, L.pb_list);
+                long long cover = 0;
+                for (size_t e = p0; e < L.pb_list.size(); e++) cover += overlap_volume(C.hb[L.pb_list[e]], flo, fhi);
+                if (cover != (long long)(fhi[0] - flo[0]) * (fhi[1] - flo[1]) * (fhi[2] - flo[2])) {
+                    free_hier(h);
+                    return fail(CTU_ERR_ARG, "a fine box is not covered by the coarser level (nesting)");
+                }
+            }
+            L.cb_start.push_back((int)L.cb_list.size());
+            L.pb_start.push_back((int)L.pb_list.size());
+            for (long long s0 = 0; s0 < B.cells; s0 += NT) L.fill_t.push_back(HTile{ b, (int)s0 });
+            if (l > 0) {
+                long long fc = (long long)(B.n[0] / 2) * (B.n[1] / 2) * (B.n[2] / 2);
+                for (long long s0 = 0; s0 < fc; s0 += NT) L.avg_t.push_back(HTile{ b, (int)s0 });
+            }
+        }
+    }
+    // every check passed: upload the tables
+    for (int l = 0; l < nlev; l++) {
+        HierLevel &L = h->lev[l];
+        ctu_status st;
+        if ((st = upload(L.hb, &L.db)) != CTU_OK || (st = upload(L.nb_start, &L.d_nb_start)) != CTU_OK ||
+            (st = upload(L.nb_list, &L.d_nb_list)) != CTU_OK || (st = upload(L.cb_start, &L.d_cb_start)) != CTU_OK ||
+            (st = upload(L.cb_list, &L.d_cb_list)) != CTU_OK || (st = upload(L.pb_start, &L.d_pb_start)) != CTU_OK ||
+            (st = upload(L.pb_list, &L.d_pb_list)) != CTU_OK || (st = upload(L.fill_t, &L.d_fill_t)) != CTU_OK ||
+            (st = upload(L.avg_t, &L.d_avg_t)) != CTU_OK) {
+            free_hier(h);
+            return st;
+        }
+    }
+    if (hipMalloc((void **)&h->dfails, 8 * sizeof(int)) != hipSuccess) {
+        free_hier(h);
+        return fail(CTU_ERR_NOMEM, "hipMalloc of the cycle counters failed");
+    }
+    *out = h;
+    return CTU_OK;
+}
+
+void ctu_hier_destroy(ctu_hier *h) { free_hier(h); }
+
+ctu_status ctu_hier_fill_ghosts(ctu_hier *h, int32_t level, void *U_dev, const void *Uc_old_dev,
+                                const void *Uc_new_dev, double alpha, int32_t *missing_dev, void *stream)
+{
+    if (!h || !U_dev || level < 0 || level >= h->nlev) return fail(CTU_ERR_ARG, "bad hierarchy, level or U");
+    if (level > 0 && !Uc_old_dev) return fail(CTU_ERR_ARG, "levels >= 1 need the coarse state");
+    if (level > 0 && alpha != 0.0 && !Uc_new_dev) return fail(CTU_ERR_ARG, "alpha != 0 needs the new coarse state");
+    if (!(alpha >= 0.0 && alpha <= 1.0)) return fail(CTU_ERR_ARG, "alpha must lie in [0, 1]");
+    return hier_fill_any(h, level, U_dev, Uc_old_dev, Uc_new_dev, alpha, missing_dev, (hipStream_t)stream);
+}
+
+ctu_status ctu_hier_average_down(ctu_hier *h, int32_t fine_level, const void *U_fine_dev, void *U_coarse_dev,
+                                 void *stream)
+{
+    if (!h || fine_level < 1 || fine_level >= h->nlev || !U_fine_dev || !U_coarse_dev)
+        return fail(CTU_ERR_ARG, "bad hierarchy, level or states");
+    return hier_avg_any(h, fine_level, U_fine_dev, U_coarse_dev, (hipStream_t)stream);
+}
+
+ctu_status ctu_hier_advance(ctu_hier *h, ctu_plan *const *plans, void *const *U_a, void *const *U_b, int32_t *cur,
+                            const double *const *params_dev, double *reg_dev, double *rate_dev, int32_t *fails_dev,
+                            int32_t *missing_dev, void *stream)
+{
+    if (!h || !plans || !U_a || !U_b || !cur || !params_dev || !rate_dev)
+        return fail(CTU_ERR_ARG, "hierarchy, plans, states, cur, params and rate are required");
+    for (int l = 0; l < h->nlev; l++) {
+        if (!plans[l] || !U_a[l] || !U_b[l] || !params_dev[l] || (cur[l] != 0 && cur[l] != 1))
+            return fail(CTU_ERR_ARG, "every level needs a plan, two state buffers, params and cur in {0, 1}");
+        if (plans[l]->esize != h->esize) return fail(CTU_ERR_ARG, "plan and hierarchy precisions differ");
+        if (plans[l]->hboxes.size() != h->lev[l].hb.size())
+            return fail(CTU_ERR_ARG, "plan of a level must hold that level's boxes");
+    }
+    CycleArgs c{ h, plans, U_a, U_b, cur, params_dev, reg_dev, rate_dev, fails_dev, missing_dev, (hipStream_t)stream };
+    return advance_level(c, 0, nullptr, nullptr, 0.0);
 }
 
 }  // extern "C"

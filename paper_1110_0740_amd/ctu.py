@@ -26,7 +26,9 @@ NFAIL = 5
 SYMBOLS = [
     "ctu_plan_create", "ctu_plan_destroy", "ctu_plan_state_elems", "ctu_plan_workspace_bytes", "ctu_step",
     "ctu_step_graph_capture", "ctu_step_graph_launch", "ctu_cfl_rate", "ctu_prim_to_cons", "ctu_cons_to_prim",
-    "ctu_plan_set_reflux", "ctu_reflux", "ctu_plan_enable_timing", "ctu_plan_read_timing", "ctu_last_error",
+    "ctu_plan_set_reflux", "ctu_reflux", "ctu_reflux_consume", "ctu_plan_enable_timing", "ctu_plan_read_timing",
+    "ctu_last_error", "ctu_hier_create", "ctu_hier_destroy", "ctu_hier_fill_ghosts", "ctu_hier_average_down",
+    "ctu_hier_advance",
 ]
 NSTAGE = 8
 STAGES = ["prim", "tcouple", "unused2", "unused3", "unused4", "sweep_x", "sweep_y", "sweep_z"]
@@ -95,6 +97,19 @@ def lib() -> C.CDLL:
         L.ctu_plan_set_reflux.argtypes = [_vp, C.POINTER(CtuRefluxFace), C.c_int32]
         L.ctu_reflux.restype = C.c_int32
         L.ctu_reflux.argtypes = [_vp, _vp, _vp, _vp]
+        L.ctu_reflux_consume.restype = C.c_int32
+        L.ctu_reflux_consume.argtypes = [_vp, _vp, _vp, _vp]
+        L.ctu_hier_create.restype = C.c_int32
+        L.ctu_hier_create.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_int32), C.POINTER(CtuBox),
+                                      C.c_int32, C.POINTER(_vp)]
+        L.ctu_hier_destroy.argtypes = [_vp]
+        L.ctu_hier_fill_ghosts.restype = C.c_int32
+        L.ctu_hier_fill_ghosts.argtypes = [_vp, C.c_int32, _vp, _vp, _vp, C.c_double, _vp, _vp]
+        L.ctu_hier_average_down.restype = C.c_int32
+        L.ctu_hier_average_down.argtypes = [_vp, C.c_int32, _vp, _vp, _vp]
+        L.ctu_hier_advance.restype = C.c_int32
+        L.ctu_hier_advance.argtypes = [_vp, C.POINTER(_vp), C.POINTER(_vp), C.POINTER(_vp), C.POINTER(C.c_int32),
+                                       C.POINTER(_vp), _vp, _vp, _vp, _vp, _vp]
         L.ctu_plan_enable_timing.restype = C.c_int32
         L.ctu_plan_enable_timing.argtypes = [_vp, C.c_int32]
         L.ctu_plan_read_timing.restype = C.c_int32
@@ -236,3 +251,55 @@ class Plan:
 
     def reflux(self, U, reg, stream=None):
         _check(lib().ctu_reflux(self._h, _ptr(U), _ptr(reg), _stream(stream)))
+
+    def reflux_consume(self, U, reg, stream=None):
+        _check(lib().ctu_reflux_consume(self._h, _ptr(U), _ptr(reg), _stream(stream)))
+
+
+class Hier:
+    """A ctu_hier: the boxes of every level of a ratio-2 hierarchy on the
+    periodic cube of `base` level-0 cells; levels[l] = list of
+    (lo, n, offset) in level-l indices."""
+
+    def __init__(self, precision: str, base: int, levels, nghost: int):
+        L = lib()
+        flat = [(lo, n, lev, off) for lev, boxes in enumerate(levels) for (lo, n, off) in boxes]
+        arr = (CtuBox * max(1, len(flat)))()
+        for q, (lo, n, lev, off) in enumerate(flat):
+            for d in range(3):
+                arr[q].lo[d] = lo[d]
+                arr[q].n[d] = n[d]
+            arr[q].level = lev
+            arr[q].offset = off
+        nb = (C.c_int32 * len(levels))(*[len(b) for b in levels])
+        self.nlev = len(levels)
+        self._h = C.c_void_p()
+        _check(L.ctu_hier_create({"fp64": FP64, "fp32": FP32}[precision], base, len(levels), nb, arr, nghost,
+                                 C.byref(self._h)))
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.ctu_hier_destroy(h)
+            self._h = None
+
+    def fill_ghosts(self, level, U, Uc_old=None, Uc_new=None, alpha=0.0, missing=None, stream=None):
+        _check(lib().ctu_hier_fill_ghosts(self._h, level, _ptr(U), _ptr(Uc_old), _ptr(Uc_new), float(alpha),
+                                          _ptr(missing), _stream(stream)))
+
+    def average_down(self, fine_level, U_fine, U_coarse, stream=None):
+        _check(lib().ctu_hier_average_down(self._h, fine_level, _ptr(U_fine), _ptr(U_coarse), _stream(stream)))
+
+    def advance(self, plans, U_a, U_b, cur, params, reg, rate, fails=None, missing=None, stream=None):
+        """One level-0 step with subcycling; `cur` (list of 0/1 per level) is
+        updated in place to name the buffers holding the new states."""
+        n = self.nlev
+        P = (_vp * n)(*[p._h for p in plans])
+        A = (_vp * n)(*[C.c_void_p(t.data_ptr()) for t in U_a])
+        B = (_vp * n)(*[C.c_void_p(t.data_ptr()) for t in U_b])
+        cu = (C.c_int32 * n)(*cur)
+        prm = (_vp * n)(*[C.c_void_p(t.data_ptr()) for t in params])
+        _check(lib().ctu_hier_advance(self._h, P, A, B, cu, prm, _ptr(reg), _ptr(rate), _ptr(fails), _ptr(missing),
+                                      _stream(stream)))
+        for l in range(n):
+            cur[l] = int(cu[l])

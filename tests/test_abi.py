@@ -57,3 +57,20 @@ def test_plan_creation_validates_options_without_gpu():
                  [((0, 0, 0), (8, 8, 8), 0, 0)], 4)
     with pytest.raises(ctu.CtuError, match="nghost"):
         ctu.Plan(ctu.make_opts(dim=3, recon="ppm"), [((0, 0, 0), (8, 8, 8), 0, 0)], 2)
+
+
+def test_hierarchy_creation_validates_boxes_without_gpu():
+    """Geometry checks of ctu_hier_create run on the host before any device call."""
+    l0 = [((0, 0, 0), (8, 8, 8), 0), ((8, 0, 0), (8, 8, 8), 0)]
+    with pytest.raises(ctu.CtuError, match="cover"):
+        ctu.Hier("fp64", 16, [l0], 4)
+    with pytest.raises(ctu.CtuError, match="overlap"):
+        ctu.Hier("fp64", 8, [[((0, 0, 0), (8, 8, 8), 0), ((4, 0, 0), (4, 8, 8), 0)]], 4)
+    full = [((0, 0, 0), (8, 8, 8), 0)]
+    with pytest.raises(ctu.CtuError, match="2-aligned"):
+        ctu.Hier("fp64", 8, [full, [((3, 4, 4), (4, 4, 4), 0)]], 4)
+    with pytest.raises(ctu.CtuError, match="outside"):
+        ctu.Hier("fp64", 8, [full, [((14, 4, 4), (4, 4, 4), 0)]], 4)
+    with pytest.raises(ctu.CtuError, match="nesting"):
+        coarse = [((0, 0, 0), (4, 8, 8), 0), ((4, 0, 0), (4, 8, 8), 0)]
+        ctu.Hier("fp64", 8, [coarse, [((4, 4, 4), (8, 8, 8), 0)], [((2, 2, 2), (4, 4, 4), 0)]], 4)
