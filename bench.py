@@ -103,18 +103,20 @@ def cpu_baseline(Vfull, ng, dx, gamma, sub=96, nsub=3):
 
 
 def amr_leg(K, W, dev, s):
-    """AMR batch: 3 levels, ratio 2, ~1500 patches of 16^3-32^3 around density
-    blobs (4 ghosts, fields evaluated at each level's resolution).  One AMR
-    step = one CTU step of every patch of every level plus the two reflux
-    launches.  FP32 batched: one plan and one captured graph per level.
-    FP64 plain: one plan per patch, eager launches, no graph."""
+    """AMR batch: 3 levels, ratio 2, ~1200 patches of 16^3-32^3 around density
+    blobs (4 ghosts, fields evaluated at each level's resolution; level-2
+    boxes 3 parent cells inside their parents).  One AMR step = one CTU step
+    of every patch of every level plus the two reflux launches.  FP32
+    batched: one plan and one captured graph per level.  FP64 plain: one
+    plan per patch, eager launches, no graph.  FP32 cycle: one level-0 step
+    of the subcycled level cycle (ctu_hier_advance)."""
     import numpy as np
     import torch
 
     from paper_1110_0740_amd import amr, ctu, inputs as I
 
     ng = 4
-    h = I.amr_hierarchy()
+    h = I.amr_hierarchy(nest=3)
     tables, nslots = amr.build_tables(h.levels, h.base, ng)
     zones = int(sum(int(np.prod(B.n)) for L in h.levels for B in L))
     npatch = sum(len(L) for L in h.levels)
@@ -182,7 +184,39 @@ def amr_leg(K, W, dev, s):
     assert fails.sum().item() == 0, fails
     out["fp32_batched"] = {"ms_per_step": ms32, "zone_updates_per_s": zones / (ms32 * 1e-3),
                            "launches_per_step": len(plans) + len(plans) - 1}
-    del plans, Uin, Uout
+
+    # FP32 level cycle: one level-0 step with ratio-2 subcycling (ghost fill
+    # and prolongation, steps, restriction, refluxing), eager launches
+    nlev = len(h.levels)
+    hier = ctu.Hier("fp32", h.base, [[(B.lo, B.n, ob) for B, ob in zip(L, offs[lev])]
+                                     for lev, L in enumerate(h.levels)], ng)
+    rate_l = torch.zeros(nlev, dtype=torch.float64, device=dev)
+    fails_acc = torch.zeros(5, dtype=torch.int32, device=dev)
+    missing = torch.zeros(1, dtype=torch.int32, device=dev)
+    reg.zero_()
+    cur = [0] * nlev
+
+    def amr_cycle32():
+        hier.advance(plans, Uin, Uout, cur, params, reg, rate_l, fails=fails_acc, missing=missing, stream=s)
+
+    with torch.cuda.stream(s):
+        for _ in range(W):
+            amr_cycle32()
+    s.synchronize()
+    with torch.cuda.stream(s):
+        e0.record(s)
+        for _ in range(K):
+            amr_cycle32()
+        e1.record(s)
+    s.synchronize()
+    msc = e0.elapsed_time(e1) / K
+    assert fails_acc.sum().item() == 0 and missing.item() == 0, (fails_acc, missing)
+    cyc_zones = sum(int(np.prod(B.n)) << lev for lev, L in enumerate(h.levels) for B in L)
+    nsteps = sum(1 << lev for lev in range(nlev))
+    out["fp32_cycle"] = {"ms_per_cycle": msc, "zone_updates_per_cycle": cyc_zones,
+                         "zone_updates_per_s": cyc_zones / (msc * 1e-3), "level_steps_per_cycle": nsteps,
+                         "launches_per_cycle": 8 * nsteps + 2 * sum(1 << lev for lev in range(nlev - 1))}
+    del plans, Uin, Uout, hier
     torch.cuda.synchronize()
 
     # FP64 plain, one plan per patch
