@@ -83,7 +83,7 @@ def lib():
         _lib = C.CDLL(build())
         _lib.orc_step.restype = C.c_int
         _lib.orc_step.argtypes = [C.POINTER(Opts), C.c_int, C.c_int, C.c_int, C.c_int, _dp, _dp, C.c_double,
-                                  C.c_double, _dp, _dp, _dp, _ip]
+                                  C.c_double, _dp, _dp, _dp, _ip, C.POINTER(C.c_ubyte)]
         _lib.orc_cfl_rate.restype = C.c_double
         _lib.orc_cfl_rate.argtypes = [C.POINTER(Opts), C.c_int, C.c_int, C.c_int, C.c_int, _dp]
         _lib.orc_prim2cons.argtypes = [C.POINTER(Opts), C.c_long, _dp, _dp]
@@ -180,9 +180,10 @@ def predict(o: Opts, Vs, U0, d: int, dt: float, ch: float):
 
 
 def step(o: Opts, U: np.ndarray, ng: int, dt: float, ch: float, L0: np.ndarray | None = None,
-         want_faces: bool = False):
+         want_faces: bool = False, leaf: np.ndarray | None = None):
     """One CTU step of a ghosted box U[9, NZ, NY, NX].  Returns
-    (U_out, rate, dpp, fails[, face_flux])."""
+    (U_out, rate, dpp, fails[, face_flux]); with `leaf` (a [NZ, NY, NX]
+    mask) dpp is the maximum over the masked cells only."""
     U = np.ascontiguousarray(U, dtype=np.float64)
     dim = o.dim
     NZ, NY, NX = U.shape[1:]
@@ -196,8 +197,12 @@ def step(o: Opts, U: np.ndarray, ng: int, dt: float, ch: float, L0: np.ndarray |
     if L0 is not None:
         L0 = np.ascontiguousarray(L0, dtype=np.float64)
         L0p = _p(L0)
+    lf = None
+    if leaf is not None:
+        leaf = np.ascontiguousarray(leaf, dtype=np.uint8)
+        lf = leaf.ctypes.data_as(C.POINTER(C.c_ubyte))
     rc = lib().orc_step(C.byref(o), nx, ny, nz, ng, _p(U), L0p, dt, ch, _p(Uo),
-                        _p(ff) if ff is not None else None, _p(sc), fails)
+                        _p(ff) if ff is not None else None, _p(sc), fails, lf)
     if rc != 0:
         raise ValueError(f"orc_step rejected the options (code {rc})")
     out = (Uo, float(sc[0]), float(sc[1]), list(fails))

@@ -1114,11 +1114,16 @@ void orc_predict(const orc_opts *o, const double *Vs /*[5][9]*/, const double *U
  *                is dt*(F - Pi) on the face between c-e_d and c, interior
  *                faces only (others zero)
  *   out_scalars: [0] = CFL rate (Eq. Ca), [1] = max |dp/p| of the cooling step
+ *                over the cells whose `leaf` entry is nonzero (all cells when
+ *                leaf is NULL: the time-step estimate of Sec. 4.2 on
+ *                unrefined cells only)
+ *   leaf       : optional per-cell mask on the ghosted layout, or NULL
  *   fails      : [5] counters
  * Returns 0 on success, <0 on unsupported options.
  */
 int orc_step(const orc_opts *o, int nx, int ny, int nz, int ng, const double *U_in, const double *L0, double dt,
-             double ch, double *U_out, double *face_flux, double *out_scalars, int *fails)
+             double ch, double *U_out, double *face_flux, double *out_scalars, int *fails,
+             const unsigned char *leaf)
 {
     if (o->dim != 2 && o->dim != 3) return -1;
     if (o->dim == 2 && nz != 1) return -1;
@@ -1368,7 +1373,7 @@ int orc_step(const orc_opts *o, int nx, int ny, int nz, int ng, const double *U_
                         double Tn = pow(x, 1.0 / (1.0 - beta));
                         double pn = v[RHO] * Tn;
                         u[ENG] += (pn - v[PRS]) / (o->gamma - 1.0);
-                        dpp = fmax(dpp, fabs(pn - v[PRS]) / v[PRS]);
+                        if (!leaf || leaf[c]) dpp = fmax(dpp, fabs(pn - v[PRS]) / v[PRS]);
                     }
                 }
                 for (int q = 0; q < NVAR; q++) U_out[q * NC + c] = u[q];
