@@ -252,6 +252,36 @@ ctu_status ctu_hier_fill_ghosts(ctu_hier *hier, int32_t level, void *U_dev, cons
 ctu_status ctu_hier_average_down(ctu_hier *hier, int32_t fine_level, const void *U_fine_dev, void *U_coarse_dev,
                                  void *stream);
 
+/* Leaf mask of `level` (one byte per ghosted cell, at offset / 9 of each box,
+ * the layout of cool_L0): 1 on interior cells that no box of the next finer
+ * level covers, 0 on covered and ghost cells. */
+ctu_status ctu_hier_leaf_mask(ctu_hier *hier, int32_t level, uint8_t *leaf_dev, void *stream);
+
+/* Refinement criterion (Eq. RefCrit, second-derivative error norm) with
+ * sigma = conserved variable `var` of U_dev (ghosts filled), undivided
+ * differences, sigma_ref,d = |s_{+1}| + 2|s_0| + |s_{-1}| weighted by eps;
+ * evaluated in FP64, chi = 0 where its denominator vanishes.  tags_dev (the
+ * layout of ctu_hier_leaf_mask) receives 1 on interior cells with
+ * chi > chi_r and 0 on the other interior cells; *ntag_dev (nullable) is
+ * increased by the number of tagged cells. */
+ctu_status ctu_hier_tag(ctu_hier *hier, int32_t level, const void *U_dev, int32_t var, double eps, double chi_r,
+                        uint8_t *tags_dev, int32_t *ntag_dev, void *stream);
+
+/* Next level steps on the device (Eq. Ca, Eq. dt_cool, Eq. level_dt):
+ * dt_l = min(cfl / rate_dev[l], eps_c dt_l / dpp_dev[l]) with dt_l read from
+ * params_dev[l][0] (the cooling term only where dpp > 0; dpp_dev nullable),
+ * dt_0 = min_l 2^l dt_l, and params_dev[l][0] <- dt_0 / 2^l (c_h in
+ * params_dev[l][1] is left as it is).  One thread; no allocation. */
+ctu_status ctu_hier_next_dt(ctu_hier *hier, const double *rate_dev, const double *dpp_dev, double cfl, double eps_c,
+                            double *const *params_dev, void *stream);
+
+/* Restrict the cooling time-step estimate of a plan's steps (dpp_dev of
+ * ctu_step) to the cells whose byte in leaf_dev is nonzero (Sec. 4.2: the
+ * source-term time step counts on leaf cells only); leaf_dev uses the layout
+ * of cool_L0 and stays owned by the caller; null restores every cell.  The
+ * cooling itself is applied on every cell. */
+ctu_status ctu_plan_set_leaf_mask(ctu_plan *plan, const uint8_t *leaf_dev);
+
 /* One level-0 step of the whole hierarchy with time subcycling (Sec. 4):
  * level l is filled (level 0 periodically; level l >= 1 at alpha = 0 and
  * 1/2 of its parent's step), advanced by ctu_step with plans[l], then level
@@ -261,14 +291,17 @@ ctu_status ctu_hier_average_down(ctu_hier *hier, int32_t fine_level, const void 
  * caller builds both); params_dev[l] = {dt_l, c_h} on the device with
  * dt_l = dt_0 / 2^l.  Each level has two state arrays U_a[l], U_b[l];
  * cur[l] (host, 0 or 1) names the one holding the current state and is
- * updated on return.  reg_dev (FP64 registers, zero on the first call) is
- * left with every slot it read cleared.  rate_dev[l] receives the CFL rate
- * of level l's last substep; fails_dev[5] (nullable) accumulates the
- * failure counts of every step; missing_dev (nullable) as above.
+ * updated on return.  cool_L0_dev (nullable; else per level, entries
+ * nullable) gives each level's cooling coefficients.  reg_dev (FP64
+ * registers, zero on the first call) is left with every slot it read
+ * cleared.  rate_dev[l] / dpp_dev[l] (dpp nullable) receive the CFL rate and
+ * max |dp/p| of level l's last substep; fails_dev[5] (nullable) accumulates
+ * the failure counts of every step; missing_dev (nullable) as above.
  * Asynchronous on `stream`; allocation-free. */
 ctu_status ctu_hier_advance(ctu_hier *hier, ctu_plan *const *plans, void *const *U_a, void *const *U_b,
-                            int32_t *cur, const double *const *params_dev, double *reg_dev, double *rate_dev,
-                            int32_t *fails_dev, int32_t *missing_dev, void *stream);
+                            int32_t *cur, const double *const *params_dev, const void *const *cool_L0_dev,
+                            double *reg_dev, double *rate_dev, double *dpp_dev, int32_t *fails_dev,
+                            int32_t *missing_dev, void *stream);
 
 /* Per-stage kernel timing with HIP events recorded on the launch stream
  * around each kernel of ctu_step (eager launches only, not inside captured

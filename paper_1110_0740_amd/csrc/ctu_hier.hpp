@@ -183,4 +183,92 @@ __global__ void k_add_fails(int *acc, const int *f)
     if (t < 5) acc[t] += f[t];
 }
 
+// Leaf mask of one level (one byte per ghosted cell, the state layout / 9):
+// 1 on interior cells that no box of the next finer level covers (the
+// cells of Sec. 4.2 whose source time step counts), 0 elsewhere.  fbox is
+// null on the finest level.
+__global__ __launch_bounds__(NT) void k_hleaf(const HBox *box, const HTile *tiles, const int *ch_start,
+                                              const int *ch_list, const HBox *fbox, int ng, unsigned char *leaf)
+{
+    const HTile t = tiles[blockIdx.x];
+    const HBox b = box[t.box];
+    const long long li = (long long)t.start + threadIdx.x;
+    if (li >= b.cells) return;
+    const int i = (int)(li % b.N[0]), j = (int)((li / b.N[0]) % b.N[1]), k = (int)(li / ((long long)b.N[0] * b.N[1]));
+    unsigned char v = 0;
+    if (i >= ng && i < ng + b.n[0] && j >= ng && j < ng + b.n[1] && k >= ng && k < ng + b.n[2]) {
+        v = 1;
+        if (fbox) {
+            const int gi = b.lo[0] + i - ng, gj = b.lo[1] + j - ng, gk = b.lo[2] + k - ng;
+            for (int e = ch_start[t.box]; e < ch_start[t.box + 1]; e++) {
+                const HBox f = fbox[ch_list[e]];
+                if (2 * gi >= f.lo[0] && 2 * gi < f.lo[0] + f.n[0] && 2 * gj >= f.lo[1] && 2 * gj < f.lo[1] + f.n[1] &&
+                    2 * gk >= f.lo[2] && 2 * gk < f.lo[2] + f.n[2]) {
+                    v = 0;
+                    break;
+                }
+            }
+        }
+    }
+    leaf[b.off / NV + li] = v;
+}
+
+// Eq. RefCrit on sigma = U[var] for the interior cells of one level (ghosts
+// filled): chi^2 = sum_d (D+ - D-)^2 / sum_d (|D+| + |D-| + eps sigma_ref,d)^2
+// with undivided differences and sigma_ref,d = |s+| + 2|s0| + |s-|,
+// evaluated in FP64; chi = 0 where the denominator vanishes.  tags (state
+// layout / 9) get 1 where chi > chi_r, 0 on the other interior cells; the
+// tagged cells are counted in *ntag (nullable).
+template <typename R>
+__global__ __launch_bounds__(NT) void k_htag(const HBox *box, const HTile *tiles, int ng, const R *U, int var,
+                                             double eps, double chi_r, unsigned char *tags, int *ntag)
+{
+    const HTile t = tiles[blockIdx.x];
+    const HBox b = box[t.box];
+    const long long li = (long long)t.start + threadIdx.x;
+    if (li >= b.cells) return;
+    const int i = (int)(li % b.N[0]), j = (int)((li / b.N[0]) % b.N[1]), k = (int)(li / ((long long)b.N[0] * b.N[1]));
+    if (!(i >= ng && i < ng + b.n[0] && j >= ng && j < ng + b.n[1] && k >= ng && k < ng + b.n[2])) return;
+    const R *sg = U + b.off + (long long)var * b.cells;
+    const double s0 = (double)sg[li];
+    const long long st[3] = { 1, b.N[0], (long long)b.N[0] * b.N[1] };
+    double num = 0.0, den = 0.0;
+#pragma unroll
+    for (int d = 0; d < 3; d++) {
+        const double sp = (double)sg[li + st[d]], sm = (double)sg[li - st[d]];
+        const double dp = sp - s0, dm = s0 - sm;
+        num += (dp - dm) * (dp - dm);
+        const double ref = fabs(sp) + 2.0 * fabs(s0) + fabs(sm);
+        const double e = fabs(dp) + fabs(dm) + eps * ref;
+        den += e * e;
+    }
+    const double chi = (den > 0.0) ? sqrt(num / den) : 0.0;
+    const unsigned char tag = chi > chi_r;
+    tags[b.off / NV + li] = tag;
+    if (tag && ntag) atomicAdd(ntag, 1);
+}
+
+// Next steps of every level (one thread): dt_l = min(C_a / rate_l,
+// eps_c dt_l^n / dpp_l) (Eq. Ca, Eq. dt_cool, the latter where dpp_l > 0),
+// dt0 = min_l 2^l dt_l (Eq. level_dt); params[l][0] <- dt0 / 2^l.
+struct HDtArgs {
+    double *params[16];
+    const double *rate;
+    const double *dpp;
+    int nlev;
+    double cfl, eps_c;
+};
+
+__global__ void k_next_dt(HDtArgs a)
+{
+    if (threadIdx.x != 0) return;
+    double dt0 = INFINITY;
+    for (int l = 0; l < a.nlev; l++) {
+        double d = a.cfl / a.rate[l];
+        if (a.dpp && a.dpp[l] > 0.0) d = fmin(d, a.eps_c * a.params[l][0] / a.dpp[l]);
+        dt0 = fmin(dt0, d * (double)(1 << l));
+    }
+    for (int l = 0; l < a.nlev; l++) a.params[l][0] = dt0 / (double)(1 << l);
+}
+
 }  // namespace ctu

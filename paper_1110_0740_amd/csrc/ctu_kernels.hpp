@@ -505,6 +505,7 @@ template <typename R> struct SweepArgs {
     const R *Vh;      // V^{n+1/2} (workspace) or null
     R *lam;           // per-cell rate accumulator (workspace, parabolic only)
     const R *L0;      // cooling coefficient (caller layout / 9) or null
+    const unsigned char *leaf;  // cells entering max |dp/p| (caller layout / 9) or null = all
     double *reg;      // flux registers or null
     const double *params;
     double *rate;
@@ -726,7 +727,8 @@ __global__ __launch_bounds__(NT, (sizeof(R) == 4 ? CTU_SWEEP_WAVES_F32 : CTU_SWE
                         x = fmax(x, xf);
                         R pn = v[RHO] * pow(x, R(1) / om);
                         u[ENG] += (pn - v[PRS]) / (gam - R(1));
-                        dpp_loc = fmax(dpp_loc, (double)(fabs(pn - v[PRS]) / v[PRS]));
+                        if (!a.leaf || a.leaf[bx.uoff / NV + cu])
+                            dpp_loc = fmax(dpp_loc, (double)(fabs(pn - v[PRS]) / v[PRS]));
                     }
                 }
                 double r = (double)lamt;

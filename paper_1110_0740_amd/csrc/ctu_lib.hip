@@ -70,6 +70,8 @@ struct ctu_plan {
     void *wsV = nullptr, *wsT[3] = { nullptr, nullptr, nullptr };
     void *wsVh = nullptr, *wsLam = nullptr;
     int64_t ws_bytes = 0;
+    // cells entering the cooling time-step estimate (caller-owned) or null
+    const unsigned char *leaf = nullptr;
     // reflux
     KRefl *drefl = nullptr;
     int *dcell_start = nullptr;
@@ -244,6 +246,7 @@ ctu_status enqueue_step(ctu_plan *p, const void *U_in, void *U_out, const double
     a.Vh = (const R *)p->wsVh;
     a.lam = (R *)p->wsLam;
     a.L0 = (const R *)L0;
+    a.leaf = p->leaf;
     a.reg = p->hregs.empty() ? nullptr : reg;
     a.params = params;
     a.rate = rate;
@@ -690,6 +693,13 @@ ctu_status ctu_reflux_consume(ctu_plan *plan, void *U_dev, double *reg_dev, void
     return reflux_launch(plan, U_dev, reg_dev, 1, stream);
 }
 
+ctu_status ctu_plan_set_leaf_mask(ctu_plan *plan, const uint8_t *leaf_dev)
+{
+    if (!plan) return fail(CTU_ERR_ARG, "null plan");
+    plan->leaf = leaf_dev;
+    return CTU_OK;
+}
+
 }  // extern "C"
 
 // ---------------------------------------------------------------------------
@@ -701,11 +711,11 @@ namespace {
 struct HierLevel {
     int N = 0;  // cells per side of the periodic level
     std::vector<HBox> hb;
-    std::vector<int> nb_start, nb_list, cb_start, cb_list, pb_start, pb_list;
+    std::vector<int> nb_start, nb_list, cb_start, cb_list, pb_start, pb_list, ch_start, ch_list;
     std::vector<HTile> fill_t, avg_t;
     HBox *db = nullptr;
     int *d_nb_start = nullptr, *d_nb_list = nullptr, *d_cb_start = nullptr, *d_cb_list = nullptr;
-    int *d_pb_start = nullptr, *d_pb_list = nullptr;
+    int *d_pb_start = nullptr, *d_pb_list = nullptr, *d_ch_start = nullptr, *d_ch_list = nullptr;
     HTile *d_fill_t = nullptr, *d_avg_t = nullptr;
 };
 
@@ -760,7 +770,7 @@ void free_hier(ctu_hier *h)
     if (!h) return;
     for (HierLevel &L : h->lev) {
         void *ptrs[] = { L.db, L.d_nb_start, L.d_nb_list, L.d_cb_start, L.d_cb_list, L.d_pb_start, L.d_pb_list,
-                         L.d_fill_t, L.d_avg_t };
+                         L.d_ch_start, L.d_ch_list, L.d_fill_t, L.d_avg_t };
         for (void *q : ptrs)
             if (q) (void)hipFree(q);
     }
@@ -818,8 +828,9 @@ struct CycleArgs {
     void *const *Ub;
     int32_t *cur;
     const double *const *params;
-    double *reg, *rate;
+    double *reg, *rate, *dpp;
     int32_t *fails, *missing;
+    const void *const *L0;
     hipStream_t s;
 };
 
@@ -833,7 +844,8 @@ ctu_status advance_level(const CycleArgs &c, int lev, const void *pold, const vo
     void *out = c.cur[lev] ? c.Ua[lev] : c.Ub[lev];
     ctu_status st = hier_fill_any(h, lev, in, pold, pnew, alpha, c.missing, c.s);
     if (st != CTU_OK) return st;
-    st = ctu_step(c.plans[lev], in, out, c.params[lev], nullptr, c.reg, c.rate + lev, nullptr, h->dfails, c.s);
+    st = ctu_step(c.plans[lev], in, out, c.params[lev], c.L0 ? c.L0[lev] : nullptr, c.reg, c.rate + lev,
+                  c.dpp ? c.dpp + lev : nullptr, h->dfails, c.s);
     if (st != CTU_OK) return st;
     if (c.fails) {
         hipLaunchKernelGGL(k_add_fails, dim3(1), dim3(64), 0, c.s, (int *)c.fails, (const int *)h->dfails);
@@ -962,10 +974,30 @@ ctu_status ctu_hier_create(int32_t precision, int32_t base, int32_t nlev, const 
             }
         }
     }
+    // children: boxes of the next finer level whose footprint meets each box
+    for (int l = 0; l < nlev; l++) {
+        HierLevel &L = h->lev[l];
+        L.ch_start.push_back(0);
+        for (const HBox &B : L.hb) {
+            if (l + 1 < nlev) {
+                int lo[3], hi[3];
+                for (int d = 0; d < 3; d++) {
+                    lo[d] = 2 * B.lo[d];
+                    hi[d] = 2 * (B.lo[d] + B.n[d]);
+                }
+                candidates(h->lev[l + 1].hb, lo, hi, 0, L.ch_list);
+            }
+            L.ch_start.push_back((int)L.ch_list.size());
+        }
+    }
     // every check passed: upload the tables
     for (int l = 0; l < nlev; l++) {
         HierLevel &L = h->lev[l];
         ctu_status st;
+        if ((st = upload(L.ch_start, &L.d_ch_start)) != CTU_OK || (st = upload(L.ch_list, &L.d_ch_list)) != CTU_OK) {
+            free_hier(h);
+            return st;
+        }
         if ((st = upload(L.hb, &L.db)) != CTU_OK || (st = upload(L.nb_start, &L.d_nb_start)) != CTU_OK ||
             (st = upload(L.nb_list, &L.d_nb_list)) != CTU_OK || (st = upload(L.cb_start, &L.d_cb_start)) != CTU_OK ||
             (st = upload(L.cb_list, &L.d_cb_list)) != CTU_OK || (st = upload(L.pb_start, &L.d_pb_start)) != CTU_OK ||
@@ -1004,8 +1036,8 @@ ctu_status ctu_hier_average_down(ctu_hier *h, int32_t fine_level, const void *U_
 }
 
 ctu_status ctu_hier_advance(ctu_hier *h, ctu_plan *const *plans, void *const *U_a, void *const *U_b, int32_t *cur,
-                            const double *const *params_dev, double *reg_dev, double *rate_dev, int32_t *fails_dev,
-                            int32_t *missing_dev, void *stream)
+                            const double *const *params_dev, const void *const *cool_L0_dev, double *reg_dev,
+                            double *rate_dev, double *dpp_dev, int32_t *fails_dev, int32_t *missing_dev, void *stream)
 {
     if (!h || !plans || !U_a || !U_b || !cur || !params_dev || !rate_dev)
         return fail(CTU_ERR_ARG, "hierarchy, plans, states, cur, params and rate are required");
@@ -1016,8 +1048,59 @@ ctu_status ctu_hier_advance(ctu_hier *h, ctu_plan *const *plans, void *const *U_
         if (plans[l]->hboxes.size() != h->lev[l].hb.size())
             return fail(CTU_ERR_ARG, "plan of a level must hold that level's boxes");
     }
-    CycleArgs c{ h, plans, U_a, U_b, cur, params_dev, reg_dev, rate_dev, fails_dev, missing_dev, (hipStream_t)stream };
+    CycleArgs c{ h,       plans,     U_a,       U_b,         cur,         params_dev,         reg_dev,
+                 rate_dev, dpp_dev, fails_dev, missing_dev, cool_L0_dev, (hipStream_t)stream };
     return advance_level(c, 0, nullptr, nullptr, 0.0);
+}
+
+ctu_status ctu_hier_leaf_mask(ctu_hier *h, int32_t level, uint8_t *leaf_dev, void *stream)
+{
+    if (!h || !leaf_dev || level < 0 || level >= h->nlev) return fail(CTU_ERR_ARG, "bad hierarchy, level or mask");
+    HierLevel &L = h->lev[level];
+    if (L.fill_t.empty()) return CTU_OK;
+    const HBox *fbox = (level + 1 < h->nlev) ? h->lev[level + 1].db : nullptr;
+    hipLaunchKernelGGL(k_hleaf, dim3((unsigned)L.fill_t.size()), dim3(NT), 0, (hipStream_t)stream, L.db, L.d_fill_t,
+                       L.d_ch_start, L.d_ch_list, fbox, h->ng, (unsigned char *)leaf_dev);
+    HIP_TRY(hipGetLastError());
+    return CTU_OK;
+}
+
+ctu_status ctu_hier_tag(ctu_hier *h, int32_t level, const void *U_dev, int32_t var, double eps, double chi_r,
+                        uint8_t *tags_dev, int32_t *ntag_dev, void *stream)
+{
+    if (!h || !U_dev || !tags_dev || level < 0 || level >= h->nlev) return fail(CTU_ERR_ARG, "bad hierarchy, level or arrays");
+    if (var < 0 || var >= NV || !(eps >= 0.0)) return fail(CTU_ERR_ARG, "var must name a conserved variable; eps >= 0");
+    HierLevel &L = h->lev[level];
+    if (L.fill_t.empty()) return CTU_OK;
+    hipStream_t s = (hipStream_t)stream;
+    if (h->esize == 4)
+        hipLaunchKernelGGL((k_htag<float>), dim3((unsigned)L.fill_t.size()), dim3(NT), 0, s, L.db, L.d_fill_t, h->ng,
+                           (const float *)U_dev, var, eps, chi_r, (unsigned char *)tags_dev, (int *)ntag_dev);
+    else
+        hipLaunchKernelGGL((k_htag<double>), dim3((unsigned)L.fill_t.size()), dim3(NT), 0, s, L.db, L.d_fill_t, h->ng,
+                           (const double *)U_dev, var, eps, chi_r, (unsigned char *)tags_dev, (int *)ntag_dev);
+    HIP_TRY(hipGetLastError());
+    return CTU_OK;
+}
+
+ctu_status ctu_hier_next_dt(ctu_hier *h, const double *rate_dev, const double *dpp_dev, double cfl, double eps_c,
+                            double *const *params_dev, void *stream)
+{
+    if (!h || !rate_dev || !params_dev || !(cfl > 0.0) || !(eps_c > 0.0))
+        return fail(CTU_ERR_ARG, "hierarchy, rate and params are required; cfl, eps_c > 0");
+    HDtArgs a{};
+    for (int l = 0; l < h->nlev; l++) {
+        if (!params_dev[l]) return fail(CTU_ERR_ARG, "params of every level are required");
+        a.params[l] = params_dev[l];
+    }
+    a.rate = rate_dev;
+    a.dpp = dpp_dev;
+    a.nlev = h->nlev;
+    a.cfl = cfl;
+    a.eps_c = eps_c;
+    hipLaunchKernelGGL(k_next_dt, dim3(1), dim3(64), 0, (hipStream_t)stream, a);
+    HIP_TRY(hipGetLastError());
+    return CTU_OK;
 }
 
 }  // extern "C"

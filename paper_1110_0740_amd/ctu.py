@@ -28,7 +28,7 @@ SYMBOLS = [
     "ctu_step_graph_capture", "ctu_step_graph_launch", "ctu_cfl_rate", "ctu_prim_to_cons", "ctu_cons_to_prim",
     "ctu_plan_set_reflux", "ctu_reflux", "ctu_reflux_consume", "ctu_plan_enable_timing", "ctu_plan_read_timing",
     "ctu_last_error", "ctu_hier_create", "ctu_hier_destroy", "ctu_hier_fill_ghosts", "ctu_hier_average_down",
-    "ctu_hier_advance",
+    "ctu_hier_advance", "ctu_hier_leaf_mask", "ctu_hier_tag", "ctu_hier_next_dt", "ctu_plan_set_leaf_mask",
 ]
 NSTAGE = 8
 STAGES = ["prim", "tcouple", "unused2", "unused3", "unused4", "sweep_x", "sweep_y", "sweep_z"]
@@ -109,7 +109,15 @@ def lib() -> C.CDLL:
         L.ctu_hier_average_down.argtypes = [_vp, C.c_int32, _vp, _vp, _vp]
         L.ctu_hier_advance.restype = C.c_int32
         L.ctu_hier_advance.argtypes = [_vp, C.POINTER(_vp), C.POINTER(_vp), C.POINTER(_vp), C.POINTER(C.c_int32),
-                                       C.POINTER(_vp), _vp, _vp, _vp, _vp, _vp]
+                                       C.POINTER(_vp), C.POINTER(_vp), _vp, _vp, _vp, _vp, _vp, _vp]
+        L.ctu_hier_leaf_mask.restype = C.c_int32
+        L.ctu_hier_leaf_mask.argtypes = [_vp, C.c_int32, _vp, _vp]
+        L.ctu_hier_tag.restype = C.c_int32
+        L.ctu_hier_tag.argtypes = [_vp, C.c_int32, _vp, C.c_int32, C.c_double, C.c_double, _vp, _vp, _vp]
+        L.ctu_hier_next_dt.restype = C.c_int32
+        L.ctu_hier_next_dt.argtypes = [_vp, _vp, _vp, C.c_double, C.c_double, C.POINTER(_vp), _vp]
+        L.ctu_plan_set_leaf_mask.restype = C.c_int32
+        L.ctu_plan_set_leaf_mask.argtypes = [_vp, _vp]
         L.ctu_plan_enable_timing.restype = C.c_int32
         L.ctu_plan_enable_timing.argtypes = [_vp, C.c_int32]
         L.ctu_plan_read_timing.restype = C.c_int32
@@ -255,6 +263,11 @@ class Plan:
     def reflux_consume(self, U, reg, stream=None):
         _check(lib().ctu_reflux_consume(self._h, _ptr(U), _ptr(reg), _stream(stream)))
 
+    def set_leaf_mask(self, leaf):
+        """uint8 tensor in the cool_L0 layout (kept alive by the caller) or None"""
+        self._leaf = leaf
+        _check(lib().ctu_plan_set_leaf_mask(self._h, _ptr(leaf)))
+
 
 class Hier:
     """A ctu_hier: the boxes of every level of a ratio-2 hierarchy on the
@@ -290,16 +303,30 @@ class Hier:
     def average_down(self, fine_level, U_fine, U_coarse, stream=None):
         _check(lib().ctu_hier_average_down(self._h, fine_level, _ptr(U_fine), _ptr(U_coarse), _stream(stream)))
 
-    def advance(self, plans, U_a, U_b, cur, params, reg, rate, fails=None, missing=None, stream=None):
+    def advance(self, plans, U_a, U_b, cur, params, reg, rate, dpp=None, L0=None, fails=None, missing=None,
+                stream=None):
         """One level-0 step with subcycling; `cur` (list of 0/1 per level) is
-        updated in place to name the buffers holding the new states."""
+        updated in place to name the buffers holding the new states.  rate
+        (and dpp) hold one double per level; L0 is None or a per-level list."""
         n = self.nlev
         P = (_vp * n)(*[p._h for p in plans])
         A = (_vp * n)(*[C.c_void_p(t.data_ptr()) for t in U_a])
         B = (_vp * n)(*[C.c_void_p(t.data_ptr()) for t in U_b])
         cu = (C.c_int32 * n)(*cur)
         prm = (_vp * n)(*[C.c_void_p(t.data_ptr()) for t in params])
-        _check(lib().ctu_hier_advance(self._h, P, A, B, cu, prm, _ptr(reg), _ptr(rate), _ptr(fails), _ptr(missing),
-                                      _stream(stream)))
+        l0 = None if L0 is None else (_vp * n)(*[_ptr(t) for t in L0])
+        _check(lib().ctu_hier_advance(self._h, P, A, B, cu, prm, l0, _ptr(reg), _ptr(rate), _ptr(dpp), _ptr(fails),
+                                      _ptr(missing), _stream(stream)))
         for l in range(n):
             cur[l] = int(cu[l])
+
+    def leaf_mask(self, level, leaf, stream=None):
+        _check(lib().ctu_hier_leaf_mask(self._h, level, _ptr(leaf), _stream(stream)))
+
+    def tag(self, level, U, var, eps, chi_r, tags, ntag=None, stream=None):
+        _check(lib().ctu_hier_tag(self._h, level, _ptr(U), var, float(eps), float(chi_r), _ptr(tags), _ptr(ntag),
+                                  _stream(stream)))
+
+    def next_dt(self, rate, dpp, cfl, eps_c, params, stream=None):
+        prm = (_vp * self.nlev)(*[C.c_void_p(t.data_ptr()) for t in params])
+        _check(lib().ctu_hier_next_dt(self._h, _ptr(rate), _ptr(dpp), float(cfl), float(eps_c), prm, _stream(stream)))
