@@ -45,13 +45,14 @@ class Opts(C.Structure):
         ("parabolic_mask", C.c_uint), ("nu", C.c_double), ("eta", C.c_double),
         ("kappa_par", C.c_double), ("kappa_perp", C.c_double), ("tc_phi", C.c_double),
         ("cooling", C.c_int), ("cool_beta", C.c_double), ("T_floor", C.c_double),
-        ("hyperbolic_off", C.c_int),
+        ("hyperbolic_off", C.c_int), ("shock_eps", C.c_double),
     ]
 
 
 def make_opts(dim=3, physics="mhd", recon="ppm", predictor="char", wref="face", riemann="hlld", gamma=5.0 / 3.0,
               dx=(1.0, 1.0, 1.0), glm=True, glm_alpha=0.1, parabolic_mask=0, nu=0.0, eta=0.0, kappa_par=0.0,
-              kappa_perp=0.0, tc_phi=0.0, cooling=False, cool_beta=0.5, T_floor=0.0, hyperbolic_off=False) -> Opts:
+              kappa_perp=0.0, tc_phi=0.0, cooling=False, cool_beta=0.5, T_floor=0.0, hyperbolic_off=False,
+              shock_eps=0.0) -> Opts:
     o = Opts()
     o.dim = dim
     o.physics = PHYS[physics]
@@ -69,6 +70,7 @@ def make_opts(dim=3, physics="mhd", recon="ppm", predictor="char", wref="face", 
     o.cooling = int(bool(cooling))
     o.cool_beta, o.T_floor = cool_beta, T_floor
     o.hyperbolic_off = int(bool(hyperbolic_off))
+    o.shock_eps = shock_eps
     return o
 
 
@@ -84,6 +86,9 @@ def lib():
         _lib.orc_step.restype = C.c_int
         _lib.orc_step.argtypes = [C.POINTER(Opts), C.c_int, C.c_int, C.c_int, C.c_int, _dp, _dp, C.c_double,
                                   C.c_double, _dp, _dp, _dp, _ip, C.POINTER(C.c_ubyte)]
+        _lib.orc_shock_flags.restype = C.c_int
+        _lib.orc_shock_flags.argtypes = [C.POINTER(Opts), C.c_int, C.c_int, C.c_int, C.c_int, _dp,
+                                         C.POINTER(C.c_ubyte)]
         _lib.orc_cfl_rate.restype = C.c_double
         _lib.orc_cfl_rate.argtypes = [C.POINTER(Opts), C.c_int, C.c_int, C.c_int, C.c_int, _dp]
         _lib.orc_prim2cons.argtypes = [C.POINTER(Opts), C.c_long, _dp, _dp]
@@ -215,3 +220,16 @@ def cfl_rate(o: Opts, U: np.ndarray, ng: int) -> float:
     nx, ny = NX - 2 * ng, NY - 2 * ng
     nz = NZ - 2 * ng if o.dim == 3 else 1
     return float(lib().orc_cfl_rate(C.byref(o), nx, ny, nz, ng, _p(U)))
+
+
+def shock_flags(o: Opts, U: np.ndarray, ng: int) -> np.ndarray:
+    """App. B flags of a ghosted box (bit 1: HLL zone, bit 2: MinMod zone)."""
+    U = np.ascontiguousarray(U, dtype=np.float64)
+    NZ, NY, NX = U.shape[1:]
+    nx, ny = NX - 2 * ng, NY - 2 * ng
+    nz = NZ - 2 * ng if o.dim == 3 else 1
+    out = np.zeros((NZ, NY, NX), dtype=np.uint8)
+    rc = lib().orc_shock_flags(C.byref(o), nx, ny, nz, ng, _p(U), out.ctypes.data_as(C.POINTER(C.c_ubyte)))
+    if rc != 0:
+        raise ValueError("orc_shock_flags rejected the options")
+    return out

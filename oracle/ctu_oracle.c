@@ -62,6 +62,7 @@ typedef struct {
     int cooling;
     double cool_beta, T_floor;
     int hyperbolic_off;
+    double shock_eps; /* App. B shock detection threshold eps_q; 0 = off */
 } orc_opts;
 
 /* ------------------------------------------------------------------------ */
@@ -1103,6 +1104,79 @@ void orc_predict(const orc_opts *o, const double *Vs /*[5][9]*/, const double *U
 /* The CTU step on one ghosted box (Sec. 3.1)                                */
 /* ------------------------------------------------------------------------ */
 
+/* App. B: flag zones inside strong compressive pressure jumps,
+ * sum_d |p_{+1} - p_{-1}| / min(p_{+1}, p_{-1}) > eps_q with div v < 0
+ * (central differences), for the HLL solver (FLAG_HLL); every zone whose
+ * reconstruction stencil (radius 2 for PPM, else 1) along an axis reaches
+ * a flagged zone is flagged for MinMod linear reconstruction
+ * (FLAG_MINMOD).  Zones without both neighbours along every axis are not
+ * tested.  V: primitive [9][cells]. */
+enum { FLAG_HLL = 1, FLAG_MINMOD = 2 };
+static const int shock_offs[3][3] = { { 1, 0, 0 }, { 0, 1, 0 }, { 0, 0, 1 } };
+
+static void shock_flags(const orc_opts *o, const grid_t *g, const double *V, const int N[3], unsigned char *flag)
+{
+    const int dim = o->dim;
+    const long NC = g->NC;
+    for (int k = 0; k < g->NZ; k++)
+        for (int j = 0; j < g->NY; j++)
+            for (int i = 0; i < g->NX; i++) {
+                int ci[3] = { i, j, k }, ok = 1;
+                for (int d = 0; d < dim; d++)
+                    if (ci[d] < 1 || ci[d] > N[d] - 2) ok = 0;
+                if (!ok) continue;
+                double gradp = 0.0, divv = 0.0;
+                for (int d = 0; d < dim; d++) {
+                    const int *e = shock_offs[d];
+                    long cp = cidx(g, i + e[0], j + e[1], k + e[2]);
+                    long cm = cidx(g, i - e[0], j - e[1], k - e[2]);
+                    double pp = V[PRS * NC + cp], pm = V[PRS * NC + cm];
+                    gradp += fabs(pp - pm) / fmin(pp, pm);
+                    divv += (V[(MX1 + d) * NC + cp] - V[(MX1 + d) * NC + cm]) / (2.0 * o->dx[d]);
+                }
+                if (gradp > o->shock_eps && divv < 0.0) flag[cidx(g, i, j, k)] |= FLAG_HLL;
+            }
+    int S = (o->recon == REC_PPM) ? 2 : 1;
+    for (int k = 0; k < g->NZ; k++)
+        for (int j = 0; j < g->NY; j++)
+            for (int i = 0; i < g->NX; i++) {
+                if (!(flag[cidx(g, i, j, k)] & FLAG_HLL)) continue;
+                for (int d = 0; d < dim; d++) {
+                    const int *e = shock_offs[d];
+                    for (int s2 = -S; s2 <= S; s2++) {
+                        int ii = i + s2 * e[0], jj = j + s2 * e[1], kk = k + s2 * e[2];
+                        if (ii < 0 || ii >= g->NX || jj < 0 || jj >= g->NY || kk < 0 || kk >= g->NZ) continue;
+                        flag[cidx(g, ii, jj, kk)] |= FLAG_MINMOD;
+                    }
+                }
+            }
+}
+
+/* Exported for the pins: the App. B flags of a ghosted box (flags_out has
+ * one byte per ghosted cell). */
+int orc_shock_flags(const orc_opts *o, int nx, int ny, int nz, int ng, const double *U, unsigned char *flags_out)
+{
+    if (o->dim != 2 && o->dim != 3) return -1;
+    grid_t g;
+    int gz = (o->dim == 3) ? ng : 0;
+    g.NX = nx + 2 * ng;
+    g.NY = ny + 2 * ng;
+    g.NZ = nz + 2 * gz;
+    g.NC = (long)g.NX * g.NY * g.NZ;
+    int N[3] = { g.NX, g.NY, g.NZ };
+    double *V = malloc(sizeof(double) * NVAR * g.NC);
+    for (long c = 0; c < g.NC; c++) {
+        double u[NVAR], v[NVAR];
+        for (int q = 0; q < NVAR; q++) u[q] = U[q * g.NC + c];
+        cons2prim(o, u, v, NULL);
+        for (int q = 0; q < NVAR; q++) V[q * g.NC + c] = v[q];
+    }
+    memset(flags_out, 0, g.NC);
+    if (o->shock_eps > 0.0) shock_flags(o, &g, V, N, flags_out);
+    free(V);
+    return 0;
+}
+
 /*
  * orc_step: advance the interior of one ghosted box by dt.
  *   nx, ny, nz : interior extents (nz == 1 when dim == 2)
@@ -1175,6 +1249,13 @@ int orc_step(const orc_opts *o, int nx, int ny, int nz, int ng, const double *U_
         for (int q = 0; q < NVAR; q++) V[q * NC + c] = v[q];
     }
 
+    /* 1b. App. B shock flags (see shock_flags) */
+    unsigned char *flag = calloc(NC, 1);
+    if (o->shock_eps > 0.0) shock_flags(o, &g, V, N, flag);
+    orc_opts o_hll = *o, o_mm = *o;
+    o_hll.riemann = RS_HLL;
+    o_mm.recon = REC_LIN_MINMOD;
+
     /* 2-3. first-order Godunov fluxes and parabolic fluxes at t^n, on every
      * face whose stencil lies inside the ghosted box */
     for (int d = 0; d < dim; d++) {
@@ -1188,7 +1269,8 @@ int orc_step(const orc_opts *o, int nx, int ny, int nz, int ng, const double *U_
                     double VL[NVAR], VR[NVAR], F[NVAR], sm;
                     for (int q = 0; q < NVAR; q++) { VL[q] = V[q * NC + cA]; VR[q] = V[q * NC + cB]; }
                     if (hyp) {
-                        riemann(o, VL, VR, d, ch, F, &sm);
+                        int hl = (flag[cA] | flag[cB]) & FLAG_HLL;
+                        riemann(hl ? &o_hll : o, VL, VR, d, ch, F, &sm);
                         for (int q = 0; q < NVAR; q++) Fn[(d * NVAR + q) * NC + cB] = F[q];
                     }
                     if (par) {
@@ -1238,8 +1320,9 @@ int orc_step(const orc_opts *o, int nx, int ny, int nz, int ng, const double *U_
                             for (int q = 0; q < NVAR; q++) Vs[l + 2][q] = V[q * NC + cl];
                         }
                         for (int q = 0; q < NVAR; q++) U0[q] = U_in[q * NC + c];
-                        if (o->predictor == PRED_CHAR) predict_char(o, Vs, d, dt, ch, Vm, Vp);
-                        else predict_mh(o, Vs, U0, d, dt, ch, Vm, Vp, lf);
+                        const orc_opts *op = (flag[c] & FLAG_MINMOD) ? &o_mm : o;
+                        if (o->predictor == PRED_CHAR) predict_char(op, Vs, d, dt, ch, Vm, Vp);
+                        else predict_mh(op, Vs, U0, d, dt, ch, Vm, Vp, lf);
                     } else {
                         for (int q = 0; q < NVAR; q++) Vm[q] = Vp[q] = V[q * NC + c];
                     }
@@ -1286,7 +1369,8 @@ int orc_step(const orc_opts *o, int nx, int ny, int nz, int ng, const double *U_
                     if (bl) for (int q = 0; q < NVAR; q++) VL[q] = V[q * NC + cA];
                     if (br) for (int q = 0; q < NVAR; q++) VR[q] = V[q * NC + cB];
                     if (hyp) {
-                        riemann(o, VL, VR, d, ch, F, &sm);
+                        int hl = (flag[cA] | flag[cB]) & FLAG_HLL;
+                        riemann(hl ? &o_hll : o, VL, VR, d, ch, F, &sm);
                     } else {
                         for (int q = 0; q < NVAR; q++) F[q] = 0.0;
                     }
@@ -1414,6 +1498,7 @@ int orc_step(const orc_opts *o, int nx, int ny, int nz, int ng, const double *U_
     if (out_scalars) { out_scalars[0] = rate; out_scalars[1] = dpp; }
     if (fails) for (int k = 0; k < NFAIL; k++) fails[k] += lf[k];
 
+    free(flag);
     free(V); free(Fn); free(Pn); free(Ln); free(LPn); free(Uhm); free(Uhp); free(Fh); free(Ph);
     free(lamf); free(pfL); free(pfR); free(rfL); free(rfR); free(Uhalf); free(Vhalf);
     return 0;
