@@ -104,6 +104,11 @@ typedef struct {
     double T_floor;
     int32_t hyperbolic_off; /* 1: skip hyperbolic fluxes (isolates Pi / sources) */
     int32_t pad;
+    double shock_eps;      /* App. B shock detection threshold eps_q (5 is the paper's
+                              default); 0 = off.  Zones with sum_d |p_{+1} - p_{-1}| /
+                              min(p_{+1}, p_{-1}) > eps_q and div v < 0 at t^n take HLL
+                              on their faces; zones whose reconstruction stencil along
+                              an axis reaches one use MinMod linear reconstruction */
 } ctu_opts;
 
 /* One ghosted box: interior cells [lo, lo+n) in level-global indices.

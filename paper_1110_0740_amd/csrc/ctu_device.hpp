@@ -24,9 +24,13 @@ enum { PB_VISC = 1, PB_RES = 2, PB_TC = 4 };
 
 // Options as seen by the kernels (by value in every launch).
 struct KOpts {
-    int dim, limiter, wref, glm, parab, cooling, hyp_off, pad;
-    double gamma, glm_alpha, nu, eta, kpar, kperp, phi, cool_beta, T_floor;
+    int dim, limiter, wref, glm, parab, cooling, hyp_off, shock_r;  // shock_r: MinMod radius of App. B
+    double gamma, glm_alpha, nu, eta, kpar, kperp, phi, cool_beta, T_floor, shock_eps;
 };
+
+// App. B zone flags (one byte per cell): HLL on the zone's faces, MinMod
+// linear reconstruction of the zone
+constexpr unsigned char FLAG_HLL = 1, FLAG_MINMOD = 2;
 
 // (normal, transverse, binormal) component indices of direction D.
 template <int D> struct Ax {
@@ -663,7 +667,7 @@ template <int D, typename R> __device__ __forceinline__ void recombine(const Eig
 // (l = -2..2; linear and WENO3 read l = -1..1).  Outputs V*_- and V*_+.
 template <int D, int RK, typename R>
 __device__ __forceinline__ void predict_char(const R (*Vs)[NV], const KOpts &o, R gam, R dtdx, R dxr, R ch, R *Vm,
-                                             R *Vp)
+                                             R *Vp, int lim)
 {
     const R *V0 = Vs[2];
     Eigen<R> e;
@@ -711,7 +715,7 @@ __device__ __forceinline__ void predict_char(const R (*Vs)[NV], const KOpts &o, 
 #pragma unroll
     for (int k = 0; k < 7; k++) {
         R dm, dp;
-        recon_offsets<RK>(d[k], o.limiter, dxr, dm, dp);
+        recon_offsets<RK>(d[k], lim, dxr, dm, dp);
         trace(o.wref, dm, dp, nu[k], numax, numin, cm[k], cp[k]);
     }
 #pragma unroll
@@ -728,7 +732,7 @@ __device__ __forceinline__ void predict_char(const R (*Vs)[NV], const KOpts &o, 
         R hm[2], hp[2], tm[2], tp[2];
 #pragma unroll
         for (int k = 0; k < 2; k++) {
-            recon_offsets<RK>(dh[k], o.limiter, dxr, hm[k], hp[k]);
+            recon_offsets<RK>(dh[k], lim, dxr, hm[k], hp[k]);
             trace(o.wref, hm[k], hp[k], k ? nuh : -nuh, numax, numin, tm[k], tp[k]);
         }
         dBn = (hp[0] + hp[1]) - (hm[0] + hm[1]);
@@ -739,7 +743,7 @@ __device__ __forceinline__ void predict_char(const R (*Vs)[NV], const KOpts &o, 
         Vp[PSI] += ch * (tp[1] - tp[0]);
     } else {
         R bm, bp;
-        recon_offsets<RK>(dh[0], o.limiter, dxr, bm, bp);
+        recon_offsets<RK>(dh[0], lim, dxr, bm, bp);
         dBn = bp - bm;
         dpsi = R(0);
         Vm[BX1 + D] += bm;
@@ -772,13 +776,13 @@ __device__ __forceinline__ void predict_char(const R (*Vs)[NV], const KOpts &o, 
 // slopes of the cell; a failed V(U*) falls back to V_i.  Returns failure bits.
 template <int D, int PHYS, typename R>
 __device__ __forceinline__ int predict_mh(const R (*Vs)[NV], const R *U0, const KOpts &o, R gam, R dtdx, R ch, R *Vm,
-                                          R *Vp)
+                                          R *Vp, int lim)
 {
     int fl = 0;
     R dV[NV], Vlo[NV], Vhi[NV];
 #pragma unroll
     for (int q = 0; q < NV; q++) {
-        dV[q] = limiter(o.limiter, Vs[3][q] - Vs[2][q], Vs[2][q] - Vs[1][q]);
+        dV[q] = limiter(lim, Vs[3][q] - Vs[2][q], Vs[2][q] - Vs[1][q]);
         Vlo[q] = Vs[2][q] - R(0.5) * dV[q];
         Vhi[q] = Vs[2][q] + R(0.5) * dV[q];
     }

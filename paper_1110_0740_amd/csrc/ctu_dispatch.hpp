@@ -11,6 +11,7 @@ namespace ctu {
 
 struct Combo {
     int phys, pred, rk, rs;
+    int shk;  // App. B shock flags in use
 };
 
 // supported (physics, predictor, reconstruction, solver) combinations
@@ -43,11 +44,16 @@ template <> inline hipError_t launch_sweep<double>(int D, const Combo &c, int nb
 // Body of one precision's dispatch translation unit.
 #define CTU_DEFINE_DISPATCH(R, SUFFIX)                                                                            \
     namespace ctu {                                                                                              \
+    template <int D, int PHYS, int PRED, int RK, int RS, int SHK>                                                \
+    static hipError_t sweep_one2(int nb, const SweepArgs<R> &a, hipStream_t s)                                  \
+    {                                                                                                            \
+        hipLaunchKernelGGL((k_sweep<D, PHYS, PRED, RK, RS, SHK, R>), dim3(nb), dim3(NT), 0, s, a);             \
+        return hipGetLastError();                                                                                \
+    }                                                                                                            \
     template <int D, int PHYS, int PRED, int RK, int RS>                                                         \
     static hipError_t sweep_one(int nb, const SweepArgs<R> &a, hipStream_t s)                                   \
     {                                                                                                            \
-        hipLaunchKernelGGL((k_sweep<D, PHYS, PRED, RK, RS, R>), dim3(nb), dim3(NT), 0, s, a);                  \
-        return hipGetLastError();                                                                                \
+        return a.flag ? sweep_one2<D, PHYS, PRED, RK, RS, 1>(nb, a, s) : sweep_one2<D, PHYS, PRED, RK, RS, 0>(nb, a, s); \
     }                                                                                                            \
     template <int D>                                                                                             \
     static hipError_t sweep_dir(const Combo &c, int nb, const SweepArgs<R> &a, hipStream_t s)                   \
@@ -78,12 +84,15 @@ template <> inline hipError_t launch_sweep<double>(int D, const Combo &c, int nb
     template <int DIM, int PAR>                                                                                  \
     static hipError_t tc_one(const Combo &c, int nb, const TArgs<R> &a, hipStream_t s)                          \
     {                                                                                                            \
+        /* the HLL fallback changes only HLLD runs */                                                           \
         if (c.phys == PHYS_RMHD)                                                                                 \
-            hipLaunchKernelGGL((k_tcouple<DIM, PHYS_RMHD, RS_HLL, 0, R>), dim3(nb), dim3(NT), 0, s, a);         \
+            hipLaunchKernelGGL((k_tcouple<DIM, PHYS_RMHD, RS_HLL, 0, 0, R>), dim3(nb), dim3(NT), 0, s, a);      \
+        else if (c.rs == RS_HLLD && a.flag)                                                                      \
+            hipLaunchKernelGGL((k_tcouple<DIM, PHYS_MHD, RS_HLLD, PAR, 1, R>), dim3(nb), dim3(NT), 0, s, a);    \
         else if (c.rs == RS_HLLD)                                                                                \
-            hipLaunchKernelGGL((k_tcouple<DIM, PHYS_MHD, RS_HLLD, PAR, R>), dim3(nb), dim3(NT), 0, s, a);       \
+            hipLaunchKernelGGL((k_tcouple<DIM, PHYS_MHD, RS_HLLD, PAR, 0, R>), dim3(nb), dim3(NT), 0, s, a);    \
         else                                                                                                     \
-            hipLaunchKernelGGL((k_tcouple<DIM, PHYS_MHD, RS_HLL, PAR, R>), dim3(nb), dim3(NT), 0, s, a);        \
+            hipLaunchKernelGGL((k_tcouple<DIM, PHYS_MHD, RS_HLL, PAR, 0, R>), dim3(nb), dim3(NT), 0, s, a);     \
         return hipGetLastError();                                                                                \
     }                                                                                                            \
     hipError_t launch_tcouple_##SUFFIX(int dim, int par, const Combo &c, int nb, const TArgs<R> &a,            \

@@ -170,6 +170,70 @@ __global__ __launch_bounds__(NT) void k_prim2cons(const KBox *boxes, const KTile
 }
 
 // ---------------------------------------------------------------------------
+// App. B shock flags from V^n (workspace layout; one byte per cell at
+// woff / NV): pass 1 marks FLAG_HLL where sum_d |p_{+1} - p_{-1}| /
+// min(p_{+1}, p_{-1}) > eps_q and div v < 0 (central differences, FP64
+// arithmetic on the stored values), on cells with both neighbours along
+// every axis; pass 2 adds FLAG_MINMOD to every cell within the
+// reconstruction radius of a FLAG_HLL cell along an axis.
+// ---------------------------------------------------------------------------
+
+template <typename R>
+__global__ __launch_bounds__(NT) void k_shock_hll(const KBox *boxes, const KTile *tiles, const R *V,
+                                                  unsigned char *flag, double eps, int dim)
+{
+    KTile tl = tiles[blockIdx.x];
+    const KBox &bx = boxes[tl.box];
+    const int c = tl.a + threadIdx.x;
+    if (c >= bx.cells) return;
+    const int i = c % bx.N[0], j = (c / bx.N[0]) % bx.N[1], k = c / (bx.N[0] * bx.N[1]);
+    const int ci[3] = { i, j, k };
+    const int cs = (int)bx.cells;
+    const R *Vb = V + bx.woff;
+    bool inside = true;
+    for (int d = 0; d < dim; d++)
+        if (ci[d] < 1 || ci[d] > bx.N[d] - 2) inside = false;
+    unsigned char f = 0;
+    if (inside) {
+        double gradp = 0.0, divv = 0.0;
+        for (int d = 0; d < dim; d++) {
+            const int st = (d == 0) ? 1 : (d == 1 ? bx.N[0] : bx.N[0] * bx.N[1]);
+            const double pp = (double)Vb[PRS * cs + c + st], pm = (double)Vb[PRS * cs + c - st];
+            gradp += fabs(pp - pm) / fmin(pp, pm);
+            divv += ((double)Vb[(MX1 + d) * cs + c + st] - (double)Vb[(MX1 + d) * cs + c - st]) / (2.0 * bx.dx[d]);
+        }
+        if (gradp > eps && divv < 0.0) f = FLAG_HLL;
+    }
+    flag[bx.woff / NV + c] = f;
+}
+
+template <int Z = 0>
+__global__ __launch_bounds__(NT) void k_shock_mm(const KBox *boxes, const KTile *tiles, unsigned char *flag, int rad,
+                                                 int dim)
+{
+    KTile tl = tiles[blockIdx.x];
+    const KBox &bx = boxes[tl.box];
+    const int c = tl.a + threadIdx.x;
+    if (c >= bx.cells) return;
+    const int i = c % bx.N[0], j = (c / bx.N[0]) % bx.N[1], k = c / (bx.N[0] * bx.N[1]);
+    const int ci[3] = { i, j, k };
+    unsigned char *fb = flag + bx.woff / NV;
+    bool mm = false;
+    for (int d = 0; d < dim && !mm; d++) {
+        const int st = (d == 0) ? 1 : (d == 1 ? bx.N[0] : bx.N[0] * bx.N[1]);
+        for (int s = -rad; s <= rad; s++) {
+            const int e = ci[d] + s;
+            if (e < 0 || e >= bx.N[d]) continue;
+            if (fb[c + s * st] & FLAG_HLL) {
+                mm = true;
+                break;
+            }
+        }
+    }
+    if (mm) fb[c] |= FLAG_MINMOD;
+}
+
+// ---------------------------------------------------------------------------
 // Parabolic face flux (Sec. 2.1.1, Sec. 3.1, App. A) on the D-face between
 // cells A = c - e_D and B = c, from primitive point values Vf of the box.
 // Face coefficients use the average of the conserved variables of A and B;
@@ -302,19 +366,21 @@ template <typename R> struct TArgs {
     const R *V;       // V^n (workspace)
     R *T[3];          // transverse increments (workspace)
     R *Vh;            // V^{n+1/2} (workspace) or null
+    const unsigned char *flag;  // App. B zone flags (workspace) or null
     const double *params;
     KOpts o;
 };
 
 // one face: G = F - Pi (and Pi separately) on the D-face below cell (i,j,k)
-template <int D, int PHYS, int RS, int PAR, typename R>
+template <int D, int PHYS, int RS, int PAR, int SHK, typename R>
 __device__ __forceinline__ void tface(const Blk<R> &bV, const R *Vb, const KBox &bx, int i, int j, int k,
-                                      const KOpts &o, R gam, R ch, R *G, R *Pi)
+                                      const KOpts &o, R gam, R ch, R *G, R *Pi, const unsigned char *fb)
 {
     int di, dj, dk;
     unit<D>(di, dj, dk);
     const int cs = (int)bx.cells;
     const int cB = cidx(bx, i, j, k), cA = cidx(bx, i - di, j - dj, k - dk);
+    const bool hl = SHK && ((fb[cA] | fb[cB]) & FLAG_HLL);
     R VL[NV], VR[NV];
 #pragma unroll
     for (int q = 0; q < NV; q++) {
@@ -324,7 +390,8 @@ __device__ __forceinline__ void tface(const Blk<R> &bV, const R *Vb, const KBox 
     R pL = VL[PRS], pR = VR[PRS], rL = VL[RHO], rR = VR[RHO];
     if (!o.hyp_off) {
         R sm;
-        riemann<D, PHYS, RS>(VL, VR, G, sm, gam, ch, o.glm);
+        if (SHK && hl) riemann<D, PHYS, RS_HLL>(VL, VR, G, sm, gam, ch, o.glm);
+        else riemann<D, PHYS, RS>(VL, VR, G, sm, gam, ch, o.glm);
     } else {
 #pragma unroll
         for (int q = 0; q < NV; q++) G[q] = R(0);
@@ -336,7 +403,7 @@ __device__ __forceinline__ void tface(const Blk<R> &bV, const R *Vb, const KBox 
     }
 }
 
-template <int DIM, int PHYS, int RS, int PAR, typename R>
+template <int DIM, int PHYS, int RS, int PAR, int SHK, typename R>
 __global__ __launch_bounds__(NT) void k_tcouple(TArgs<R> a)
 {
     constexpr int TX = TTile<DIM>::TX, TY = TTile<DIM>::TY;
@@ -357,6 +424,7 @@ __global__ __launch_bounds__(NT) void k_tcouple(TArgs<R> a)
     const int cs = (int)bx.cells;
     const R *Vb = a.V + bx.woff;
     const Blk<R> bV(Vb, bx.cells);
+    const unsigned char *fb = SHK ? a.flag + bx.woff / NV : nullptr;
     const Blk<R> bT0(a.T[0] + bx.woff, bx.cells), bT1(a.T[1] + bx.woff, bx.cells), bT2(DIM == 3 ? a.T[2] + bx.woff : Vb, bx.cells);
     const R ix = R(1.0 / bx.dx[0]), iy = R(1.0 / bx.dx[1]), iz = R(1.0 / bx.dx[2]);
     // in-plane cell of this thread (ghosted coordinates) and region bounds
@@ -377,11 +445,11 @@ __global__ __launch_bounds__(NT) void k_tcouple(TArgs<R> a)
         // and the in-plane low faces of every cell whose face borders the
         // region (one cell past it along x / y computes only that face) ----
         R Gm[NV], Pm[NV];
-        if (inplane) tface<AM, PHYS, RS, PAR>(bV, Vb, bx, ci, cj, ck, o, gam, ch, Gm, Pm);
+        if (inplane) tface<AM, PHYS, RS, PAR, SHK>(bV, Vb, bx, ci, cj, ck, o, gam, ch, Gm, Pm, fb);
         if (m <= m1) {
             R G[NV], P[NV];
             if (i <= hi0 + 1 && (DIM == 2 || j <= hi1)) {
-                tface<0, PHYS, RS, PAR>(bV, Vb, bx, ci, cj, ck, o, gam, ch, G, P);
+                tface<0, PHYS, RS, PAR, SHK>(bV, Vb, bx, ci, cj, ck, o, gam, ch, G, P, fb);
 #pragma unroll
                 for (int q = 0; q < NV; q++) {
                     Gx[q][ty][tx] = G[q];
@@ -390,7 +458,7 @@ __global__ __launch_bounds__(NT) void k_tcouple(TArgs<R> a)
             }
             if constexpr (DIM == 3) {
                 if (i <= hi0 && j <= hi1 + 1) {
-                    tface<1, PHYS, RS, PAR>(bV, Vb, bx, ci, cj, ck, o, gam, ch, G, P);
+                    tface<1, PHYS, RS, PAR, SHK>(bV, Vb, bx, ci, cj, ck, o, gam, ch, G, P, fb);
 #pragma unroll
                     for (int q = 0; q < NV; q++) {
                         Gy[q][ty][tx] = G[q];
@@ -406,7 +474,7 @@ __global__ __launch_bounds__(NT) void k_tcouple(TArgs<R> a)
                 const int ek = (DIM == 3) ? m : 0;
                 if (ei <= hi0 + 1 && (DIM == 2 || ej <= hi1)) {
                     R G[NV], P[NV];
-                    tface<0, PHYS, RS, PAR>(bV, Vb, bx, ei, ej, ek, o, gam, ch, G, P);
+                    tface<0, PHYS, RS, PAR, SHK>(bV, Vb, bx, ei, ej, ek, o, gam, ch, G, P, fb);
 #pragma unroll
                     for (int q = 0; q < NV; q++) {
                         Gx[q][tid][TX] = G[q];
@@ -418,7 +486,7 @@ __global__ __launch_bounds__(NT) void k_tcouple(TArgs<R> a)
                 const int ei = bx.g[0] - 1 + tl.a + c, ej = bx.g[1] - 1 + tl.b + TY;
                 if (ei <= hi0 && ej <= hi1 + 1) {
                     R G[NV], P[NV];
-                    tface<(DIM == 3 ? 1 : 0), PHYS, RS, PAR>(bV, Vb, bx, ei, ej, m, o, gam, ch, G, P);
+                    tface<(DIM == 3 ? 1 : 0), PHYS, RS, PAR, SHK>(bV, Vb, bx, ei, ej, m, o, gam, ch, G, P, fb);
 #pragma unroll
                     for (int q = 0; q < NV; q++) {
                         Gy[q][TY][c] = G[q];
@@ -506,6 +574,7 @@ template <typename R> struct SweepArgs {
     R *lam;           // per-cell rate accumulator (workspace, parabolic only)
     const R *L0;      // cooling coefficient (caller layout / 9) or null
     const unsigned char *leaf;  // cells entering max |dp/p| (caller layout / 9) or null = all
+    const unsigned char *flag;  // App. B zone flags (workspace) or null
     double *reg;      // flux registers or null
     const double *params;
     double *rate;
@@ -526,7 +595,7 @@ template <typename R> struct SweepArgs {
 #define CTU_SWEEP_WAVES_F64 2
 #endif
 
-template <int D, int PHYS, int PRED, int RK, int RS, typename R>
+template <int D, int PHYS, int PRED, int RK, int RS, int SHK, typename R>
 __global__ __launch_bounds__(NT, (sizeof(R) == 4 ? CTU_SWEEP_WAVES_F32 : CTU_SWEEP_WAVES_F64)) void k_sweep(
     SweepArgs<R> a)
 {
@@ -572,6 +641,7 @@ __global__ __launch_bounds__(NT, (sizeof(R) == 4 ? CTU_SWEEP_WAVES_F32 : CTU_SWE
     unit<D>(di, dj, dk);
     const Blk<R> bV(a.V + bx.woff, bx.cells), bU(a.U + bx.uoff, bx.cells), bUo(a.Uout + bx.uoff, bx.cells);
     const Blk<R> bT(a.T[D] + bx.woff, bx.cells);
+    const unsigned char *fb = SHK ? a.flag + bx.woff / NV : nullptr;
     double rate_loc = 0.0, dpp_loc = 0.0;
 
     for (int base = 0; base < items; base += NT) {
@@ -607,16 +677,19 @@ __global__ __launch_bounds__(NT, (sizeof(R) == 4 ? CTU_SWEEP_WAVES_F32 : CTU_SWE
 #pragma unroll
                 for (int q = 0; q < NV; q++) Vs[l][q] = bV.ld(q, c + (l - 2) * sD);
             R Vm[NV], Vp[NV];
+            // App. B: MinMod linear reconstruction near a flagged zone
+            const bool mm = SHK && (fb[c] & FLAG_MINMOD);
             if (o.hyp_off) {
 #pragma unroll
                 for (int q = 0; q < NV; q++) Vm[q] = Vp[q] = Vs[2][q];
             } else if constexpr (PRED == PRED_CHAR) {
-                predict_char<D, RK>(Vs, o, gam, dtdx, dxD, ch, Vm, Vp);
+                if (SHK && mm) predict_char<D, RK_LIN>(Vs, o, gam, dtdx, dxD, ch, Vm, Vp, LIM_MINMOD);
+                else predict_char<D, RK>(Vs, o, gam, dtdx, dxD, ch, Vm, Vp, o.limiter);
             } else {
                 R U0[NV];
 #pragma unroll
                 for (int q = 0; q < NV; q++) U0[q] = bU.ld(q, c);
-                fl |= predict_mh<D, PHYS>(Vs, U0, o, gam, dtdx, ch, Vm, Vp);
+                fl |= predict_mh<D, PHYS>(Vs, U0, o, gam, dtdx, ch, Vm, Vp, mm ? LIM_MINMOD : o.limiter);
             }
             R Up[NV];
             p2c<PHYS>(Vm, Um, gam);
@@ -654,7 +727,9 @@ __global__ __launch_bounds__(NT, (sizeof(R) == 4 ? CTU_SWEEP_WAVES_F32 : CTU_SWE
             R pL = VL[PRS], pR = VR[PRS], rL = VL[RHO], rR = VR[RHO];
             R smax = R(0);
             if (!o.hyp_off) {
-                riemann<D, PHYS, RS>(VL, VR, F, smax, gam, ch, o.glm);
+                // App. B: HLL on the faces of a flagged zone
+                if (SHK && ((fb[c - sD] | fb[c]) & FLAG_HLL)) riemann<D, PHYS, RS_HLL>(VL, VR, F, smax, gam, ch, o.glm);
+                else riemann<D, PHYS, RS>(VL, VR, F, smax, gam, ch, o.glm);
             } else {
 #pragma unroll
                 for (int q = 0; q < NV; q++) F[q] = R(0);

@@ -69,6 +69,7 @@ struct ctu_plan {
     // workspace fields: V^n, the transverse increments T_d, V^{n+1/2}, rate
     void *wsV = nullptr, *wsT[3] = { nullptr, nullptr, nullptr };
     void *wsVh = nullptr, *wsLam = nullptr;
+    unsigned char *wsFlag = nullptr;  // App. B zone flags (one byte per cell) or null
     int64_t ws_bytes = 0;
     // cells entering the cooling time-step estimate (caller-owned) or null
     const unsigned char *leaf = nullptr;
@@ -98,7 +99,7 @@ void free_plan(ctu_plan *p)
     if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
     if (p->graph) (void)hipGraphDestroy(p->graph);
     void *ptrs[] = { p->dboxes, p->dregs, p->t_cells.d, p->t_tc.d, p->t_sweep[0].d, p->t_sweep[1].d,
-                     p->t_sweep[2].d, p->t_cfl.d, p->wsV, p->wsT[0], p->wsT[1], p->wsT[2], p->wsVh, p->wsLam,
+                     p->t_sweep[2].d, p->t_cfl.d, p->wsV, p->wsT[0], p->wsT[1], p->wsT[2], p->wsVh, p->wsLam, p->wsFlag,
                      p->drefl, p->dcell_start };
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
@@ -216,6 +217,14 @@ ctu_status enqueue_step(ctu_plan *p, const void *U_in, void *U_out, const double
         else
             hipLaunchKernelGGL((k_cons2prim<PHYS_RMHD, R>), dim3(p->t_cells.n()), dim3(NT), 0, s, p->dboxes,
                                p->t_cells.d, (const R *)U_in, (R *)p->wsV, (int *)fails, gam, 1);
+        if (p->wsFlag) {
+            HIP_TRY(hipGetLastError());
+            hipLaunchKernelGGL((k_shock_hll<R>), dim3(p->t_cells.n()), dim3(NT), 0, s, p->dboxes, p->t_cells.d,
+                               (const R *)p->wsV, p->wsFlag, p->opts.shock_eps, dim);
+            HIP_TRY(hipGetLastError());
+            hipLaunchKernelGGL(k_shock_mm<0>, dim3(p->t_cells.n()), dim3(NT), 0, s, p->dboxes, p->t_cells.d, p->wsFlag,
+                               p->ko.shock_r, dim);
+        }
     }
     HIP_TRY(hipGetLastError());
     {
@@ -227,6 +236,7 @@ ctu_status enqueue_step(ctu_plan *p, const void *U_in, void *U_out, const double
         ta.V = (const R *)p->wsV;
         for (int d = 0; d < 3; d++) ta.T[d] = (R *)p->wsT[d];
         ta.Vh = (R *)p->wsVh;
+        ta.flag = p->wsFlag;
         ta.params = params;
         ta.o = p->ko;
         hipError_t e;
@@ -247,6 +257,7 @@ ctu_status enqueue_step(ctu_plan *p, const void *U_in, void *U_out, const double
     a.lam = (R *)p->wsLam;
     a.L0 = (const R *)L0;
     a.leaf = p->leaf;
+    a.flag = p->wsFlag;
     a.reg = p->hregs.empty() ? nullptr : reg;
     a.params = params;
     a.rate = rate;
@@ -303,11 +314,13 @@ ctu_status ctu_plan_create(const ctu_opts *opts, const ctu_box *boxes, int32_t n
     for (int d = 0; d < o.dim; d++)
         if (!(o.dx[d] > 0.0)) return fail(CTU_ERR_ARG, "dx must be positive");
     if (o.parabolic_mask & ~7u) return fail(CTU_ERR_ARG, "unknown parabolic bits");
+    if (!(o.shock_eps >= 0.0)) return fail(CTU_ERR_ARG, "shock_eps must be >= 0");
     Combo c;
     c.phys = o.physics;
     c.pred = o.predictor;
     c.rk = (o.recon == CTU_PPM) ? RK_PPM : (o.recon == CTU_WENO3 ? RK_WENO : RK_LIN);
     c.rs = o.riemann;
+    c.shk = o.shock_eps > 0.0 ? 1 : 0;
     if (o.physics == CTU_RMHD && o.riemann == CTU_HLLD) c.rs = RS_HLL;
     if (o.physics == CTU_RMHD && o.riemann == CTU_HLLD)
         return fail(CTU_ERR_UNSUPPORTED, "RMHD supports the HLL solver only");
@@ -333,7 +346,8 @@ ctu_status ctu_plan_create(const ctu_opts *opts, const ctu_box *boxes, int32_t n
     k.parab = (int)o.parabolic_mask;
     k.cooling = o.cooling ? 1 : 0;
     k.hyp_off = o.hyperbolic_off ? 1 : 0;
-    k.pad = 0;
+    k.shock_r = (o.recon == CTU_PPM) ? 2 : 1;
+    k.shock_eps = o.shock_eps;
     k.gamma = o.gamma;
     k.glm_alpha = o.glm_alpha;
     k.nu = o.nu;
@@ -441,6 +455,13 @@ ctu_status ctu_plan_create(const ctu_opts *opts, const ctu_box *boxes, int32_t n
             free_plan(p);
             return st;
         }
+    }
+    if (c.shk) {
+        if (hipMalloc((void **)&p->wsFlag, p->ws_cells) != hipSuccess) {
+            free_plan(p);
+            return fail(CTU_ERR_NOMEM, "hipMalloc of the shock flags failed");
+        }
+        p->ws_bytes += p->ws_cells;
     }
     *plan_out = p;
     return CTU_OK;

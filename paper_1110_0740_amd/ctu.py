@@ -42,7 +42,7 @@ class CtuOpts(C.Structure):
         ("parabolic_mask", C.c_uint32), ("cooling", C.c_int32),
         ("nu", C.c_double), ("eta", C.c_double), ("kappa_par", C.c_double), ("kappa_perp", C.c_double),
         ("tc_phi", C.c_double), ("cool_beta", C.c_double), ("T_floor", C.c_double),
-        ("hyperbolic_off", C.c_int32), ("pad", C.c_int32),
+        ("hyperbolic_off", C.c_int32), ("pad", C.c_int32), ("shock_eps", C.c_double),
     ]
 
 
@@ -139,7 +139,7 @@ def _check(rc: int):
 def make_opts(dim=3, physics="mhd", precision="fp64", recon="ppm", predictor="char", wref="face", riemann="hlld",
               glm=True, gamma=5.0 / 3.0, dx=(1.0, 1.0, 1.0), glm_alpha=0.1, parabolic_mask=0, cooling=False,
               nu=0.0, eta=0.0, kappa_par=0.0, kappa_perp=0.0, tc_phi=0.0, cool_beta=0.5, T_floor=0.0,
-              hyperbolic_off=False) -> CtuOpts:
+              hyperbolic_off=False, shock_eps=0.0) -> CtuOpts:
     o = CtuOpts()
     o.dim = dim
     o.physics = {"mhd": MHD, "rmhd": RMHD}[physics]
@@ -158,6 +158,7 @@ def make_opts(dim=3, physics="mhd", precision="fp64", recon="ppm", predictor="ch
     o.nu, o.eta, o.kappa_par, o.kappa_perp, o.tc_phi = nu, eta, kappa_par, kappa_perp, tc_phi
     o.cool_beta, o.T_floor = cool_beta, T_floor
     o.hyperbolic_off = int(bool(hyperbolic_off))
+    o.shock_eps = shock_eps
     return o
 
 
