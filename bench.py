@@ -36,9 +36,8 @@ KERNEL_FLOPS_PER_ZONE = {"prim": 37.0, "tcouple": 1481.0, "sweep_x": 1397.0, "sw
 # 524,308 KiB of FETCH_SIZE and 1,048,576 KiB of WRITE_SIZE, hence the
 # factors.  Same profile file; set an entry to None when its kernel changes
 # after the counter runs.
-KERNEL_TRAFFIC_BYTES = {"prim": (327952 * 2 + 646866) * 1024, "tcouple": (1626130 * 2 + 2304169) * 1024,
-                        "sweep_x": (918923 * 2 + 639105) * 1024, "sweep_y": (1447951 * 2 + 663584) * 1024,
-                        "sweep_z": (1446567 * 2 + 663584) * 1024}
+KERNEL_TRAFFIC_BYTES = {"prim": (327952 * 2 + 646866) * 1024, "tcouple": None, "sweep_x": None, "sweep_y": None,
+                        "sweep_z": None}
 # Algorithmic HBM bytes per zone of a whole step (read U^n on the ghosted box,
 # write U^{n+1}): 36 B x (264/256)^3 + 36 B in FP32, twice that in FP64.
 PEAK_HBM_GBS = 8000.0

@@ -11,7 +11,8 @@ namespace ctu {
 
 struct Combo {
     int phys, pred, rk, rs;
-    int shk;  // App. B shock flags in use
+    int shk;   // App. B shock flags in use
+    int fast;  // options equal the fast variant's fixed set (see variant_opts)
 };
 
 // supported (physics, predictor, reconstruction, solver) combinations
@@ -44,35 +45,37 @@ template <> inline hipError_t launch_sweep<double>(int D, const Combo &c, int nb
 // Body of one precision's dispatch translation unit.
 #define CTU_DEFINE_DISPATCH(R, SUFFIX)                                                                            \
     namespace ctu {                                                                                              \
-    template <int D, int PHYS, int PRED, int RK, int RS, int SHK>                                                \
+    template <int D, int PHYS, int PRED, int RK, int RS, int VAR>                                                \
     static hipError_t sweep_one2(int nb, const SweepArgs<R> &a, hipStream_t s)                                  \
     {                                                                                                            \
-        hipLaunchKernelGGL((k_sweep<D, PHYS, PRED, RK, RS, SHK, R>), dim3(nb), dim3(NT), 0, s, a);             \
+        hipLaunchKernelGGL((k_sweep<D, PHYS, PRED, RK, RS, VAR, R>), dim3(nb), dim3(NT), 0, s, a);             \
         return hipGetLastError();                                                                                \
     }                                                                                                            \
     template <int D, int PHYS, int PRED, int RK, int RS>                                                         \
-    static hipError_t sweep_one(int nb, const SweepArgs<R> &a, hipStream_t s)                                   \
+    static hipError_t sweep_one(const Combo &c, int nb, const SweepArgs<R> &a, hipStream_t s)                   \
     {                                                                                                            \
-        return a.flag ? sweep_one2<D, PHYS, PRED, RK, RS, 1>(nb, a, s) : sweep_one2<D, PHYS, PRED, RK, RS, 0>(nb, a, s); \
+        if (a.flag) return sweep_one2<D, PHYS, PRED, RK, RS, VAR_SHOCK>(nb, a, s);                               \
+        if (c.fast) return sweep_one2<D, PHYS, PRED, RK, RS, VAR_FAST>(nb, a, s);                                \
+        return sweep_one2<D, PHYS, PRED, RK, RS, VAR_GENERIC>(nb, a, s);                                         \
     }                                                                                                            \
     template <int D>                                                                                             \
     static hipError_t sweep_dir(const Combo &c, int nb, const SweepArgs<R> &a, hipStream_t s)                   \
     {                                                                                                            \
-        if (c.phys == PHYS_RMHD) return sweep_one<D, PHYS_RMHD, PRED_MH, RK_LIN, RS_HLL>(nb, a, s);            \
+        if (c.phys == PHYS_RMHD) return sweep_one<D, PHYS_RMHD, PRED_MH, RK_LIN, RS_HLL>(c, nb, a, s);            \
         if (c.pred == PRED_MH) {                                                                                 \
-            if (c.rs == RS_HLLD) return sweep_one<D, PHYS_MHD, PRED_MH, RK_LIN, RS_HLLD>(nb, a, s);            \
-            return sweep_one<D, PHYS_MHD, PRED_MH, RK_LIN, RS_HLL>(nb, a, s);                                  \
+            if (c.rs == RS_HLLD) return sweep_one<D, PHYS_MHD, PRED_MH, RK_LIN, RS_HLLD>(c, nb, a, s);            \
+            return sweep_one<D, PHYS_MHD, PRED_MH, RK_LIN, RS_HLL>(c, nb, a, s);                                  \
         }                                                                                                        \
         if (c.rk == RK_PPM) {                                                                                    \
-            if (c.rs == RS_HLLD) return sweep_one<D, PHYS_MHD, PRED_CHAR, RK_PPM, RS_HLLD>(nb, a, s);          \
-            return sweep_one<D, PHYS_MHD, PRED_CHAR, RK_PPM, RS_HLL>(nb, a, s);                                \
+            if (c.rs == RS_HLLD) return sweep_one<D, PHYS_MHD, PRED_CHAR, RK_PPM, RS_HLLD>(c, nb, a, s);          \
+            return sweep_one<D, PHYS_MHD, PRED_CHAR, RK_PPM, RS_HLL>(c, nb, a, s);                                \
         }                                                                                                        \
         if (c.rk == RK_WENO) {                                                                                   \
-            if (c.rs == RS_HLLD) return sweep_one<D, PHYS_MHD, PRED_CHAR, RK_WENO, RS_HLLD>(nb, a, s);         \
-            return sweep_one<D, PHYS_MHD, PRED_CHAR, RK_WENO, RS_HLL>(nb, a, s);                               \
+            if (c.rs == RS_HLLD) return sweep_one<D, PHYS_MHD, PRED_CHAR, RK_WENO, RS_HLLD>(c, nb, a, s);         \
+            return sweep_one<D, PHYS_MHD, PRED_CHAR, RK_WENO, RS_HLL>(c, nb, a, s);                               \
         }                                                                                                        \
-        if (c.rs == RS_HLLD) return sweep_one<D, PHYS_MHD, PRED_CHAR, RK_LIN, RS_HLLD>(nb, a, s);              \
-        return sweep_one<D, PHYS_MHD, PRED_CHAR, RK_LIN, RS_HLL>(nb, a, s);                                    \
+        if (c.rs == RS_HLLD) return sweep_one<D, PHYS_MHD, PRED_CHAR, RK_LIN, RS_HLLD>(c, nb, a, s);              \
+        return sweep_one<D, PHYS_MHD, PRED_CHAR, RK_LIN, RS_HLL>(c, nb, a, s);                                    \
     }                                                                                                            \
     hipError_t launch_sweep_##SUFFIX(int D, const Combo &c, int nb, const SweepArgs<R> &a, hipStream_t s)      \
     {                                                                                                            \
@@ -86,13 +89,17 @@ template <> inline hipError_t launch_sweep<double>(int D, const Combo &c, int nb
     {                                                                                                            \
         /* the HLL fallback changes only HLLD runs */                                                           \
         if (c.phys == PHYS_RMHD)                                                                                 \
-            hipLaunchKernelGGL((k_tcouple<DIM, PHYS_RMHD, RS_HLL, 0, 0, R>), dim3(nb), dim3(NT), 0, s, a);      \
+            hipLaunchKernelGGL((k_tcouple<DIM, PHYS_RMHD, RS_HLL, 0, VAR_GENERIC, R>), dim3(nb), dim3(NT), 0, s, a); \
         else if (c.rs == RS_HLLD && a.flag)                                                                      \
-            hipLaunchKernelGGL((k_tcouple<DIM, PHYS_MHD, RS_HLLD, PAR, 1, R>), dim3(nb), dim3(NT), 0, s, a);    \
+            hipLaunchKernelGGL((k_tcouple<DIM, PHYS_MHD, RS_HLLD, PAR, VAR_SHOCK, R>), dim3(nb), dim3(NT), 0, s, a); \
+        else if (c.fast && c.rs == RS_HLLD)                                                                      \
+            hipLaunchKernelGGL((k_tcouple<DIM, PHYS_MHD, RS_HLLD, 0, VAR_FAST, R>), dim3(nb), dim3(NT), 0, s, a); \
+        else if (c.fast)                                                                                         \
+            hipLaunchKernelGGL((k_tcouple<DIM, PHYS_MHD, RS_HLL, 0, VAR_FAST, R>), dim3(nb), dim3(NT), 0, s, a); \
         else if (c.rs == RS_HLLD)                                                                                \
-            hipLaunchKernelGGL((k_tcouple<DIM, PHYS_MHD, RS_HLLD, PAR, 0, R>), dim3(nb), dim3(NT), 0, s, a);    \
+            hipLaunchKernelGGL((k_tcouple<DIM, PHYS_MHD, RS_HLLD, PAR, VAR_GENERIC, R>), dim3(nb), dim3(NT), 0, s, a); \
         else                                                                                                     \
-            hipLaunchKernelGGL((k_tcouple<DIM, PHYS_MHD, RS_HLL, PAR, 0, R>), dim3(nb), dim3(NT), 0, s, a);     \
+            hipLaunchKernelGGL((k_tcouple<DIM, PHYS_MHD, RS_HLL, PAR, VAR_GENERIC, R>), dim3(nb), dim3(NT), 0, s, a); \
         return hipGetLastError();                                                                                \
     }                                                                                                            \
     hipError_t launch_tcouple_##SUFFIX(int dim, int par, const Combo &c, int nb, const TArgs<R> &a,            \

@@ -170,6 +170,29 @@ __global__ __launch_bounds__(NT) void k_prim2cons(const KBox *boxes, const KTile
 }
 
 // ---------------------------------------------------------------------------
+// Kernel variants of the t^n kernel and the sweeps: generic (every option
+// read at run time), shock (App. B flags in use), and fast: the common option
+// set (face-value reference states, GLM on, hyperbolic fluxes on, no
+// parabolic terms, no cooling) fixed at compile time, so that the code of the
+// other options folds away (about half the instructions and registers of the
+// generic sweep).
+// ---------------------------------------------------------------------------
+constexpr int VAR_GENERIC = 0, VAR_SHOCK = 1, VAR_FAST = 2;
+
+template <int VAR> __device__ __forceinline__ KOpts variant_opts(const KOpts &in)
+{
+    KOpts o = in;
+    if constexpr (VAR == VAR_FAST) {
+        o.wref = WREF_FACE;
+        o.glm = 1;
+        o.hyp_off = 0;
+        o.parab = 0;
+        o.cooling = 0;
+    }
+    return o;
+}
+
+// ---------------------------------------------------------------------------
 // App. B shock flags from V^n (workspace layout; one byte per cell at
 // woff / NV): pass 1 marks FLAG_HLL where sum_d |p_{+1} - p_{-1}| /
 // min(p_{+1}, p_{-1}) > eps_q and div v < 0 (central differences, FP64
@@ -403,9 +426,10 @@ __device__ __forceinline__ void tface(const Blk<R> &bV, const R *Vb, const KBox 
     }
 }
 
-template <int DIM, int PHYS, int RS, int PAR, int SHK, typename R>
+template <int DIM, int PHYS, int RS, int PAR, int VAR, typename R>
 __global__ __launch_bounds__(NT) void k_tcouple(TArgs<R> a)
 {
+    constexpr int SHK = (VAR == VAR_SHOCK);
     constexpr int TX = TTile<DIM>::TX, TY = TTile<DIM>::TY;
     constexpr int AM = DIM - 1;                 // marching axis
     constexpr int NPX = PAR ? NV : 1;           // Pi planes kept only with parabolic terms
@@ -418,7 +442,7 @@ __global__ __launch_bounds__(NT) void k_tcouple(TArgs<R> a)
     const int tx = tid % TX, ty = tid / TX;
     const KTile tl = a.tiles[blockIdx.x];
     const KBox bx = a.boxes[tl.box];
-    const KOpts &o = a.o;
+    const KOpts o = variant_opts<VAR>(a.o);
     const R gam = R(o.gamma), ch = R(a.params[1]);
     const R hdt = R(0.5 * a.params[0]);
     const int cs = (int)bx.cells;
@@ -595,10 +619,11 @@ template <typename R> struct SweepArgs {
 #define CTU_SWEEP_WAVES_F64 2
 #endif
 
-template <int D, int PHYS, int PRED, int RK, int RS, int SHK, typename R>
+template <int D, int PHYS, int PRED, int RK, int RS, int VAR, typename R>
 __global__ __launch_bounds__(NT, (sizeof(R) == 4 ? CTU_SWEEP_WAVES_F32 : CTU_SWEEP_WAVES_F64)) void k_sweep(
     SweepArgs<R> a)
 {
+    constexpr int SHK = (VAR == VAR_SHOCK);
     constexpr int DEL = (D == 0) ? 1 : 64;
     __shared__ R sP[NV][NT];
     __shared__ R sF[NV][NT];
@@ -611,7 +636,7 @@ __global__ __launch_bounds__(NT, (sizeof(R) == 4 ? CTU_SWEEP_WAVES_F32 : CTU_SWE
     const int tid = threadIdx.x;
     const KTile tl = a.tiles[blockIdx.x];
     const KBox bx = a.boxes[tl.box];
-    const KOpts &o = a.o;
+    const KOpts o = variant_opts<VAR>(a.o);
     const int dim = o.dim;
     const int cs = (int)bx.cells;
     const int nD = bx.n[D];

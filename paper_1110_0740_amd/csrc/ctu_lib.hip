@@ -321,6 +321,7 @@ ctu_status ctu_plan_create(const ctu_opts *opts, const ctu_box *boxes, int32_t n
     c.rk = (o.recon == CTU_PPM) ? RK_PPM : (o.recon == CTU_WENO3 ? RK_WENO : RK_LIN);
     c.rs = o.riemann;
     c.shk = o.shock_eps > 0.0 ? 1 : 0;
+    c.fast = (o.wref == CTU_WREF_FACE && o.glm && !o.hyperbolic_off && !o.parabolic_mask && !o.cooling && !c.shk) ? 1 : 0;
     if (o.physics == CTU_RMHD && o.riemann == CTU_HLLD) c.rs = RS_HLL;
     if (o.physics == CTU_RMHD && o.riemann == CTU_HLLD)
         return fail(CTU_ERR_UNSUPPORTED, "RMHD supports the HLL solver only");
