@@ -29,15 +29,16 @@ METRIC = "zone-updates/sec per CTU step (FP32 batched vs FP64 plain) + achieved 
 # 64 x (ADD + MUL + 2 FMA + TRANS) wave instructions); recorded with the
 # commands in profiles/ctu_step_fp32_256cube_counters.md.  They include
 # the ~1 % of items computed for the pencil ends.
-KERNEL_FLOPS_PER_ZONE = {"prim": 37.0, "tcouple": 1481.0, "sweep_x": 1397.0, "sweep_y": 1396.0,
-                         "sweep_z": 1399.0}
+KERNEL_FLOPS_PER_ZONE = {"prim": 37.0, "tcouple": 1481.0, "sweep_x": 1389.0, "sweep_y": 1387.0,
+                         "sweep_z": 1386.0}
 # HBM bytes per launch, FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (KiB x 1024): a
 # plain 1 GiB device copy (bench.py --copy-calibration) reads back as
 # 524,308 KiB of FETCH_SIZE and 1,048,576 KiB of WRITE_SIZE, hence the
 # factors.  Same profile file; set an entry to None when its kernel changes
 # after the counter runs.
-KERNEL_TRAFFIC_BYTES = {"prim": (327952 * 2 + 646866) * 1024, "tcouple": None, "sweep_x": None, "sweep_y": None,
-                        "sweep_z": None}
+KERNEL_TRAFFIC_BYTES = {"prim": (327952 * 2 + 646866) * 1024, "tcouple": (675800 * 2 + 2367052) * 1024,
+                        "sweep_x": (947122 * 2 + 632383) * 1024, "sweep_y": (1007071 * 2 + 629461) * 1024,
+                        "sweep_z": (993966 * 2 + 626051) * 1024}
 # Algorithmic HBM bytes per zone of a whole step (read U^n on the ghosted box,
 # write U^{n+1}): 36 B x (264/256)^3 + 36 B in FP32, twice that in FP64.
 PEAK_HBM_GBS = 8000.0

@@ -30,7 +30,11 @@ struct KBox {
     long long woff;  // element offset of the box block in workspace arrays
     long long cells; // N0*N1*N2
     double dx[3];
-    int reg0, reg1;  // register entries [reg0, reg1)
+    int reg0, reg1;  // register entries [reg0, reg1), sorted by (dir, face)
+    // per direction d: offset of this box's face index in the register face
+    // table: entries [t[f], t[f + 1]) lie on the face lo[d] + f, f = 0..n[d]
+    int rface[3];
+    int pad;
 };
 
 struct KTile {
@@ -440,6 +444,10 @@ __global__ __launch_bounds__(NT) void k_tcouple(TArgs<R> a)
 
     const int tid = threadIdx.x;
     const int tx = tid % TX, ty = tid / TX;
+    // lane in the wave that solves the tile's high faces; consecutive blocks
+    // go to the eight XCDs in turn, so the choice mixes in the block's place
+    // within its XCD
+    const int et = tid - 64 * (int)((blockIdx.x ^ (blockIdx.x >> 3)) & (NT / 64 - 1));
     const KTile tl = a.tiles[blockIdx.x];
     const KBox bx = a.boxes[tl.box];
     const KOpts o = variant_opts<VAR>(a.o);
@@ -491,22 +499,24 @@ __global__ __launch_bounds__(NT) void k_tcouple(TArgs<R> a)
                 }
             }
         }
-        // the tile's high in-plane faces (TY along x, TX along y)
+        // the tile's high in-plane faces (TY along x, TX along y), solved by
+        // one wave chosen by block index so that over the blocks resident on
+        // a compute unit the extra solves spread over its four SIMDs
         if (m <= m1) {
-            if (tid < TY) {
-                const int ei = bx.g[0] - 1 + tl.a + TX, ej = (DIM == 3) ? bx.g[1] - 1 + tl.b + tid : m;
+            if (et >= 0 && et < TY) {
+                const int ei = bx.g[0] - 1 + tl.a + TX, ej = (DIM == 3) ? bx.g[1] - 1 + tl.b + et : m;
                 const int ek = (DIM == 3) ? m : 0;
                 if (ei <= hi0 + 1 && (DIM == 2 || ej <= hi1)) {
                     R G[NV], P[NV];
                     tface<0, PHYS, RS, PAR, SHK>(bV, Vb, bx, ei, ej, ek, o, gam, ch, G, P, fb);
 #pragma unroll
                     for (int q = 0; q < NV; q++) {
-                        Gx[q][tid][TX] = G[q];
-                        if (PAR) Px[q][tid][TX] = P[q];
+                        Gx[q][et][TX] = G[q];
+                        if (PAR) Px[q][et][TX] = P[q];
                     }
                 }
-            } else if (DIM == 3 && tid < TY + TX) {
-                const int c = tid - TY;
+            } else if (DIM == 3 && et >= TY && et < TY + TX) {
+                const int c = et - TY;
                 const int ei = bx.g[0] - 1 + tl.a + c, ej = bx.g[1] - 1 + tl.b + TY;
                 if (ei <= hi0 && ej <= hi1 + 1) {
                     R G[NV], P[NV];
@@ -590,6 +600,7 @@ template <typename R> struct SweepArgs {
     const KBox *boxes;
     const KTile *tiles;
     const KReg *regs;
+    const int *rface;  // per-face ranges of regs (see KBox::rface)
     const R *U;       // U^n (caller layout)
     R *Uout;          // U^{n+1} (caller layout)
     const R *V;       // V^n (workspace)
@@ -767,11 +778,12 @@ __global__ __launch_bounds__(NT, (sizeof(R) == 4 ? CTU_SWEEP_WAVES_F32 : CTU_SWE
             }
             // ---- flux registers: dt * A * (F - Pi) on listed faces ----
             if (a.reg && bx.reg1 > bx.reg0) {
-                int gface = bx.lo[D] + (s - 1);
                 int gt0 = bx.lo[T0] + tc0, gt1 = (T1 < dim) ? bx.lo[T1] + tc1 : 0;
-                for (int r = bx.reg0; r < bx.reg1; r++) {
+                // only the rectangles on this face plane
+                const int *rf = a.rface + bx.rface[D] + (s - 1);
+                const int r0 = rf[0], r1 = rf[1];
+                for (int r = r0; r < r1; r++) {
                     KReg rg = a.regs[r];
-                    if (rg.dir != D || rg.face != gface) continue;
                     int u0 = gt0 - rg.tlo0, u1 = gt1 - rg.tlo1;
                     if (u0 < 0 || u0 >= rg.tn0 || u1 < 0 || u1 >= rg.tn1) continue;
                     double area = 1.0;

@@ -63,6 +63,9 @@ struct ctu_plan {
     KBox *dboxes = nullptr;
     std::vector<KReg> hregs;
     KReg *dregs = nullptr;
+    bool has_regs = false;    // register faces were given (reg is then required)
+    std::vector<int> hrface;  // per box and direction: n[d] + 2 range starts into hregs
+    int *drface = nullptr;
     int64_t state_elems = 0;
     int64_t ws_cells = 0;  // sum of ghosted cells
     TileSet t_cells, t_tc, t_sweep[3], t_cfl;
@@ -98,7 +101,7 @@ void free_plan(ctu_plan *p)
         if (e) (void)hipEventDestroy(e);
     if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
     if (p->graph) (void)hipGraphDestroy(p->graph);
-    void *ptrs[] = { p->dboxes, p->dregs, p->t_cells.d, p->t_tc.d, p->t_sweep[0].d, p->t_sweep[1].d,
+    void *ptrs[] = { p->dboxes, p->dregs, p->drface, p->t_cells.d, p->t_tc.d, p->t_sweep[0].d, p->t_sweep[1].d,
                      p->t_sweep[2].d, p->t_cfl.d, p->wsV, p->wsT[0], p->wsT[1], p->wsT[2], p->wsVh, p->wsLam, p->wsFlag,
                      p->drefl, p->dcell_start };
     for (void *q : ptrs)
@@ -125,6 +128,26 @@ int pencils_per_block(int L, int npos)
         }
     }
     return best;
+}
+
+// Launch order that gives each XCD a contiguous run of the tile list.  The
+// dispatcher sends block b to XCD b % 8, and each XCD has its own L2: with
+// the list in place order, tiles that share halo cache lines (neighbours in
+// x and y) would run on different XCDs and fetch those lines once per XCD.
+// Block b takes tile start[b % 8] + b / 8, where XCD x owns the run of
+// n / 8 tiles (one more for the first n % 8 XCDs) from start[x].
+constexpr int kXcds = 8;
+
+void xcd_order(std::vector<KTile> &h)
+{
+    const size_t n = h.size(), q = n / kXcds, rem = n % kXcds;
+    if (n < 2 * kXcds) return;
+    std::vector<KTile> out(n);
+    for (size_t b = 0; b < n; b++) {
+        const size_t x = b % kXcds, r = b / kXcds;
+        out[b] = h[x * q + std::min(x, rem) + r];
+    }
+    h.swap(out);
 }
 
 void add_linear_tiles(TileSet &ts, int box, long long count)
@@ -163,6 +186,8 @@ ctu_status build_tables(ctu_plan *p)
             }
         }
     }
+    xcd_order(p->t_tc.h);
+    for (int D = 0; D < dim; D++) xcd_order(p->t_sweep[D].h);
     ctu_status st;
     TileSet *all[] = { &p->t_cells, &p->t_tc, &p->t_sweep[0], &p->t_sweep[1], &p->t_sweep[2], &p->t_cfl };
     for (TileSet *ts : all)
@@ -249,6 +274,7 @@ ctu_status enqueue_step(ctu_plan *p, const void *U_in, void *U_out, const double
     SweepArgs<R> a;
     a.boxes = p->dboxes;
     a.regs = p->dregs;
+    a.rface = p->drface;
     a.U = (const R *)U_in;
     a.Uout = (R *)U_out;
     a.V = (const R *)p->wsV;
@@ -258,7 +284,7 @@ ctu_status enqueue_step(ctu_plan *p, const void *U_in, void *U_out, const double
     a.L0 = (const R *)L0;
     a.leaf = p->leaf;
     a.flag = p->wsFlag;
-    a.reg = p->hregs.empty() ? nullptr : reg;
+    a.reg = p->hregs.empty() ? nullptr : reg;  // no entry lies on a box face: nothing to write
     a.params = params;
     a.rate = rate;
     a.dpp = dpp;
@@ -286,7 +312,7 @@ ctu_status check_step_args(ctu_plan *p, const void *U_in, void *U_out, const dou
     if (!U_in || !U_out || !params || !rate) return fail(CTU_ERR_ARG, "U_in, U_out, params and rate are required");
     if (U_in == U_out) return fail(CTU_ERR_ARG, "U_out must not alias U_in");
     if (p->opts.cooling && !L0) return fail(CTU_ERR_ARG, "cooling needs cool_L0");
-    if (!p->hregs.empty() && !reg) return fail(CTU_ERR_ARG, "the plan has register faces: reg is required");
+    if (p->has_regs && !reg) return fail(CTU_ERR_ARG, "the plan has register faces: reg is required");
     return CTU_OK;
 }
 
@@ -400,6 +426,8 @@ ctu_status ctu_plan_create(const ctu_opts *opts, const ctu_box *boxes, int32_t n
         p->state_elems = std::max<int64_t>(p->state_elems, B.offset + NV * kb.cells);
         p->ws_cells += kb.cells;
         kb.reg0 = kb.reg1 = 0;
+        kb.rface[0] = kb.rface[1] = kb.rface[2] = 0;
+        kb.pad = 0;
         p->hboxes.push_back(kb);
     }
     std::sort(spans.begin(), spans.end());
@@ -429,14 +457,32 @@ ctu_status ctu_plan_create(const ctu_opts *opts, const ctu_box *boxes, int32_t n
         kr.slot = R.slot;
         per[R.box].push_back(kr);
     }
+    // each box's entries sorted by (dir, face), with per-face ranges so that a
+    // sweep reads only the rectangles on its own face plane; entries off the
+    // box's faces lo[d] .. lo[d] + n[d] are never written and are dropped
     for (int b = 0; b < nbox; b++) {
-        p->hboxes[b].reg0 = (int)p->hregs.size();
-        for (auto &r : per[b]) p->hregs.push_back(r);
-        p->hboxes[b].reg1 = (int)p->hregs.size();
+        KBox &kb = p->hboxes[b];
+        std::stable_sort(per[b].begin(), per[b].end(), [](const KReg &x, const KReg &y) {
+            return x.dir != y.dir ? x.dir < y.dir : x.face < y.face;
+        });
+        kb.reg0 = (int)p->hregs.size();
+        for (int d = 0; d < o.dim; d++) {
+            kb.rface[d] = (int)p->hrface.size();
+            for (int f = 0; f <= kb.n[d]; f++) {
+                p->hrface.push_back((int)p->hregs.size());
+                for (auto &r : per[b])
+                    if (r.dir == d && r.face == kb.lo[d] + f) p->hregs.push_back(r);
+            }
+            p->hrface.push_back((int)p->hregs.size());
+        }
+        kb.reg1 = (int)p->hregs.size();
     }
+    if (p->hrface.empty()) p->hrface.push_back(0);
+    p->has_regs = nreg > 0;
 
     ctu_status st;
     if ((st = upload(p->hboxes, &p->dboxes)) != CTU_OK || (st = upload(p->hregs, &p->dregs)) != CTU_OK ||
+        (st = upload(p->hrface, &p->drface)) != CTU_OK ||
         (st = build_tables(p)) != CTU_OK) {
         free_plan(p);
         return st;
