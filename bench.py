@@ -23,22 +23,29 @@ sys.path.insert(0, ROOT)
 
 METRIC = "zone-updates/sec per CTU step (FP32 batched vs FP64 plain) + achieved HBM GB/s"
 
-# FP32 floating-point operations per interior zone of each kernel of the
-# FP32 step (256^3, PPM + HLLD + GLM), counted by rocprofv3
+# Algorithmic FP32 floating-point operations per interior zone of each
+# kernel of the FP32 step (256^3, PPM + HLLD + GLM), counted by rocprofv3
 # (SQ_INSTS_VALU_FLOPS_FP32 x 64 lanes / 16,777,216 zones, which equals
-# 64 x (ADD + MUL + 2 FMA + TRANS) wave instructions); recorded with the
-# commands in profiles/ctu_step_fp32_256cube_counters.md.  They include
-# the ~1 % of items computed for the pencil ends.
-KERNEL_FLOPS_PER_ZONE = {"prim": 37.0, "tcouple": 1481.0, "sweep_x": 1389.0, "sweep_y": 1387.0,
+# 64 x (ADD + MUL + 2 FMA + TRANS) wave instructions) with the commands in
+# profiles/ctu_step_fp32_256cube_counters.md.  t^n: the run with one chunk
+# per tile column (--shape tiles,4096,16,1), which recomputes no marching
+# face (8-plane chunks execute 1507); x sweep: 64 pencils per block, the
+# least per-block setup (16 pencils execute 1403).  They include the ~1 %
+# of items computed for the pencil ends and the region's halo faces.
+KERNEL_FLOPS_PER_ZONE = {"prim": 37.0, "tcouple": 1455.0, "sweep_x": 1389.0, "sweep_y": 1387.0,
                          "sweep_z": 1386.0}
 # HBM bytes per launch, FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (KiB x 1024): a
 # plain 1 GiB device copy (bench.py --copy-calibration) reads back as
 # 524,308 KiB of FETCH_SIZE and 1,048,576 KiB of WRITE_SIZE, hence the
 # factors.  Same profile file; set an entry to None when its kernel changes
 # after the counter runs.
-KERNEL_TRAFFIC_BYTES = {"prim": (327952 * 2 + 646866) * 1024, "tcouple": (675800 * 2 + 2367052) * 1024,
-                        "sweep_x": (947122 * 2 + 632383) * 1024, "sweep_y": (1007071 * 2 + 629461) * 1024,
-                        "sweep_z": (993966 * 2 + 626051) * 1024}
+KERNEL_TRAFFIC_BYTES = {"prim": (327952 * 2 + 646866) * 1024, "tcouple": (597382 * 2 + 2400708) * 1024,
+                        "sweep_x": (949111 * 2 + 638087) * 1024, "sweep_y": (1009667 * 2 + 630693) * 1024,
+                        "sweep_z": (994293 * 2 + 625506) * 1024}
+# The launch shape of the single-box FP32 plan the counters above were taken
+# with (bench.py --shape tiles,8,16,1); traffic depends on it, so the
+# roofline reports it only when the tuned shape is this one.
+PROFILE_SHAPE = {"tc_layout": "tiles", "tc_chunk": 8, "x_pencils": 16, "xcd_order": 1}
 # Algorithmic HBM bytes per zone of a whole step (read U^n on the ghosted box,
 # write U^{n+1}): 36 B x (264/256)^3 + 36 B in FP32, twice that in FP64.
 PEAK_HBM_GBS = 8000.0
@@ -56,6 +63,11 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle cpu_baseline leg")
     ap.add_argument("--precision", default="both", choices=["both", "fp32", "fp64"])
     ap.add_argument("--no-amr", action="store_true", help="skip the AMR batch leg")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default launch shapes instead of tuning the FP32 plans first")
+    ap.add_argument("--shape", default=None,
+                    help="force the launch shape of the single-box FP32 plan instead of tuning it: "
+                         "LAYOUT,CHUNK,PENCILS,XCD (e.g. tiles,8,16,1)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (HBM counter calibration) and exit")
     return ap.parse_args()
@@ -102,7 +114,7 @@ def cpu_baseline(Vfull, ng, dx, gamma, sub=96, nsub=3):
                       f"{elapsed:.1f} s single-threaded"}
 
 
-def amr_leg(K, W, dev, s):
+def amr_leg(K, W, dev, s, tune=True):
     """AMR batch: 3 levels, ratio 2, ~1200 patches of 16^3-32^3 around density
     blobs (4 ghosts, fields evaluated at each level's resolution; level-2
     boxes 3 parent cells inside their parents).  One AMR step = one CTU step
@@ -159,6 +171,13 @@ def amr_leg(K, W, dev, s):
         Uin.append(U64[lev].to(torch.float32))
         Uout.append(torch.empty_like(Uin[-1]))
     torch.cuda.synchronize()
+    # launch shapes: measured per level plan (untimed setup), then captured
+    shapes = []
+    for lev, p in enumerate(plans):
+        if tune:
+            shapes.append(p.autotune(Uin[lev], Uout[lev], params[lev], reps=3, stream=s)[0])
+        else:
+            shapes.append(p.get_shape()[0])
     with torch.cuda.stream(s):
         for lev, p in enumerate(plans):
             p.graph_capture(Uin[lev], Uout[lev], params[lev], rate, reg=reg, fails=fails, stream=s)
@@ -183,7 +202,7 @@ def amr_leg(K, W, dev, s):
     ms32 = e0.elapsed_time(e1) / K
     assert fails.sum().item() == 0, fails
     out["fp32_batched"] = {"ms_per_step": ms32, "zone_updates_per_s": zones / (ms32 * 1e-3),
-                           "launches_per_step": len(plans) + len(plans) - 1}
+                           "launches_per_step": len(plans) + len(plans) - 1, "shapes": shapes}
 
     # FP32 level cycle: one level-0 step with ratio-2 subcycling (ghost fill
     # and prolongation, steps, restriction, refluxing), eager launches
@@ -320,6 +339,14 @@ def main():
         U32 = U64.to(torch.float32)
         Uo = torch.empty_like(U32)
         torch.cuda.synchronize()
+        if args.shape:
+            lay, chunk, pen, xcd = args.shape.split(",")
+            p32.set_shape(tc_layout=lay, tc_chunk=int(chunk), x_pencils=int(pen), xcd_order=int(xcd))
+            shape = p32.get_shape()[0]
+        elif args.no_autotune:
+            shape = p32.get_shape()[0]
+        else:
+            shape = p32.autotune(U32, Uo, params, reps=3, stream=s)[0]
         with torch.cuda.stream(s):
             p32.graph_capture(U32, Uo, params, rate, fails=fails, stream=s)
             for _ in range(W):
@@ -345,7 +372,7 @@ def main():
         s.synchronize()
         stage_ms, nrec = p32.read_timing()
         p32.enable_timing(False)
-        result["fp32_batched"] = {"ms_per_step": ms, "zone_updates_per_s": zones / (ms * 1e-3),
+        result["fp32_batched"] = {"ms_per_step": ms, "zone_updates_per_s": zones / (ms * 1e-3), "shape": shape,
                                   "stage_ms": {k: v / max(nrec, 1) for k, v in stage_ms.items() if v > 0}}
         del Uo, U32, p32
 
@@ -369,7 +396,8 @@ def main():
             achieved = fpz * zones / (dom_ms * 1e-3) / 1e12
             roofline = {"bound": "alu", "kernel": dom, "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
                         "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
-                        "traffic": KERNEL_TRAFFIC_BYTES.get(dom), "avg_ms": dom_ms,
+                        "traffic": (KERNEL_TRAFFIC_BYTES.get(dom) if res.get("shape") == PROFILE_SHAPE else None),
+                        "avg_ms": dom_ms, "shape": res.get("shape"),
                         "flop_per_zone": fpz, "peak_unpacked": PEAK_FP32_UNPACKED_TFLOPS,
                         "frac_unpacked": achieved / PEAK_FP32_UNPACKED_TFLOPS}
         else:
@@ -403,7 +431,7 @@ def main():
         print("[bench] AMR batch leg", file=sys.stderr, flush=True)
         del U64
         torch.cuda.empty_cache()
-        line["amr"] = amr_leg(max(3, K // 2), min(W, 2), dev, s)
+        line["amr"] = amr_leg(max(3, K // 2), min(W, 2), dev, s, tune=not args.no_autotune)
     if not args.no_cpu:
         print("[bench] oracle cpu_baseline", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(Vhost, ng, dx, gamma)

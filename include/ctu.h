@@ -190,6 +190,53 @@ ctu_status ctu_step(ctu_plan *plan, const void *U_in_dev, void *U_out_dev, const
                     const void *cool_L0_dev, double *reg_dev, double *rate_dev, double *dpp_dev,
                     int32_t *fails_dev, void *stream);
 
+/* Launch shape of a plan's t^n and sweep kernels.  The per-cell arithmetic
+ * does not depend on it: every shape gives the same results (bitwise in
+ * FP64), only the speed differs.
+ *  tc_layout : in-plane layout of the t^n kernel's blocks:
+ *              CTU_TC_TILES   32 x 8 rectangles (256 x 1 in 2D);
+ *              CTU_TC_FLAT    256 consecutive positions of each box's plane,
+ *                             row by row (3D boxes with n[0] <= 37; others
+ *                             keep the rectangles);
+ *              CTU_TC_AUTO    per box, the one that needs fewer blocks
+ *  tc_chunk  : planes per t^n block along the marching axis, 1..4096; 0 = 16
+ *  x_pencils : x-sweep pencils per block, 1..64; 0 = the count that idles
+ *              the fewest lanes
+ *  xcd_order : 1 = launch order that gives each XCD a contiguous run of
+ *              tiles (halo lines shared in one L2); 0 = place order */
+typedef enum { CTU_TC_AUTO = 0, CTU_TC_TILES = 1, CTU_TC_FLAT = 2 } ctu_tc_layout;
+typedef struct {
+    int32_t tc_layout;
+    int32_t tc_chunk;
+    int32_t x_pencils;
+    int32_t xcd_order;
+} ctu_shape;
+
+/* Rebuild the plan's tables for a shape (CTU_ERR_ARG for a field out of
+ * range).  Allocates the new tables; drops a captured graph, which must be
+ * captured again.  A new plan starts with {AUTO, 0, 0, 1}, or with the
+ * shape that ctu_plan_autotune found for the same option set and box
+ * extents earlier in the process. */
+ctu_status ctu_plan_set_shape(ctu_plan *plan, const ctu_shape *shape);
+/* The shape in use, and (if flat_boxes_out) how many boxes use the flat
+ * t^n layout under it. */
+ctu_status ctu_plan_get_shape(const ctu_plan *plan, ctu_shape *shape_out, int32_t *flat_boxes_out);
+
+/* Measure candidate shapes on the caller's data and keep the fastest: the
+ * t^n layout and chunk (8, 16, 32), then the x-sweep pencils per block, then
+ * the launch order, one coordinate at a time.  Each candidate runs 1 + reps
+ * steps of U_in_dev into U_out_dev on the stream (U_out_dev is overwritten;
+ * no registers, rate, dpp or failure counts are written), timed with HIP
+ * events; the call synchronizes the stream.  The winner is applied (as by
+ * ctu_plan_set_shape), cached for plans of the same option set and box
+ * extents created later in the process, and returned with its time per
+ * step in ms.  cool_L0_dev is required when opts.cooling. */
+ctu_status ctu_plan_autotune(ctu_plan *plan, const void *U_in_dev, void *U_out_dev, const double *params_dev,
+                             const void *cool_L0_dev, int32_t reps, void *stream, ctu_shape *best_out,
+                             double *best_ms_out);
+/* Forget every shape found by ctu_plan_autotune in this process. */
+ctu_status ctu_tune_cache_clear(void);
+
 /* Capture ctu_step with the given arguments into a HIP graph owned by the
  * plan (replacing a previous one), and replay it.  The graph holds no
  * memset nodes; buffers are re-zeroed by kernels on every replay. */

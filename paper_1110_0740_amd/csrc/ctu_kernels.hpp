@@ -2,11 +2,14 @@
 //
 // One step of a batch of ghosted boxes is a short chain of launches:
 //   k_reset      zero the rate / dpp / failure outputs (graph-safe, no memset)
-//   k_prim       V = V(U) on every ghosted cell                       (a1)
-//   k_godunov<D> first-order fluxes R(V_j, V_{j+1}) at t^n, and the
-//                parabolic fluxes Pi^n, on the faces the corner coupling
-//                and the half step need                                (a2, a3)
-//   k_halfstep   cell-centred V^{n+1/2} for Pi^{n+1/2} (parabolic only) (a7)
+//   k_cons2prim  V = V(U) on every ghosted cell                       (a1)
+//   k_shock_hll, k_shock_mm
+//                App. B zone flags (shock-adaptive runs only)
+//   k_tcouple    first-order fluxes R(V_j, V_{j+1}) at t^n and the
+//                parabolic fluxes Pi^n on every face of the region
+//                [g-1, g+n], differenced into the per-cell increments T_d
+//                of Eq. transv; with parabolic terms also the cell-centred
+//                V^{n+1/2}                                   (a2, a3, a5, a7)
 //   k_sweep<D>   for direction D: normal predictor, corner coupling
 //                (Eq. transv), final Riemann solve (Eq. ctu_flux), flux
 //                registers, and the conservative update of U^{n+1}; the
@@ -367,23 +370,41 @@ template <typename R> __device__ __forceinline__ R diff_coeff(const KOpts &o, R 
 // ---------------------------------------------------------------------------
 // k_tcouple: the t^n part of the step in one marching kernel.
 //
-// A block owns an in-plane tile of TX x TY cells (x, y in 3D; x in 2D) of the
-// region [g-1, g+n] and marches along the last axis over the same range.
-// For each plane it solves the first-order Riemann problems R(V_j, V_{j+1})
-// (and, with parabolic terms, evaluates Pi^n) on the low faces of its cells
-// plus the tile's high faces, hands them over through LDS, and forms per
-// cell the increments L_d = -(G_{d,+} - G_{d,-})/dx_d of G = F - Pi and
-// Lp_d = (Pi_{d,+} - Pi_{d,-})/dx_d.  The marching-axis faces of one plane
-// are the high faces of the previous one, so each cell is finished one plane
-// later.  Outputs, per cell:
+// A block owns 256 in-plane positions of the region [g-1, g+n] (x, y in 3D;
+// x in 2D) and marches along the last axis over a chunk of its planes.  For
+// each plane it solves the first-order Riemann problems R(V_j, V_{j+1})
+// (and, with parabolic terms, evaluates Pi^n) on the low faces of its
+// positions plus the faces above its last ones, hands them over through
+// LDS, and forms per cell the increments L_d = -(G_{d,+} - G_{d,-})/dx_d of
+// G = F - Pi and Lp_d = (Pi_{d,+} - Pi_{d,-})/dx_d.  The marching-axis faces
+// of one plane are the high faces of the previous one, so each cell is
+// finished one plane later.  Outputs, per cell:
 //   T_d = sum_{d' != d} L_{d'} + Lp_d     (the Eq. transv increment of sweep d)
 //   V^{n+1/2} = V(U^n + dt/2 sum_d L_d)   (parabolic runs only)
+//
+// Two in-plane layouts, chosen per tile on the host:
+//  * tile (b >= 0): a TX x TY rectangle at (a, b); the TY faces right of it
+//    and the TX faces above it are the extra faces;
+//  * flat (3D, b == -1): positions a .. a+255 of the extended plane of
+//    (W+1) x (H+1) positions, W x H the region's extent, row by row; a
+//    position with x = W or y = H only solves the face below it.  The extra
+//    faces are the x face below position a+256 and the y faces below a+256 ..
+//    a+256+W, so W + 2 <= 64 is required (and W + 1 <= MAXW1 for the LDS
+//    slots).  On the 16-32 cell patches of an
+//    AMR level this uses ~78 % of the lanes against ~61 % for 32 x 8 tiles.
 // ---------------------------------------------------------------------------
 
 template <int DIM> struct TTile {
     static constexpr int TX = (DIM == 3) ? 32 : NT;
     static constexpr int TY = (DIM == 3) ? 8 : 1;
-    static constexpr int LM = 16;  // planes per block along the marching axis
+    static constexpr int LM = 16;   // default planes per block along the marching axis
+    // flat layout: at most 40 positions per row (boxes up to 37 cells wide),
+    // which keeps the face planes of four FP64 blocks within 160 KiB of LDS
+    static constexpr int MAXW1 = 40;
+    // LDS face slots: the larger of the two layouts (flat: 256 + 1 and
+    // 256 + MAXW1 + 1)
+    static constexpr int GXS = (DIM == 3) ? ((TY * (TX + 1) > 257) ? TY * (TX + 1) : 257) : TY * (TX + 1);
+    static constexpr int GYS = (DIM == 3) ? (((TY + 1) * TX > 256 + MAXW1 + 1) ? (TY + 1) * TX : 256 + MAXW1 + 1) : 1;
 };
 
 template <typename R> struct TArgs {
@@ -396,6 +417,7 @@ template <typename R> struct TArgs {
     const unsigned char *flag;  // App. B zone flags (workspace) or null
     const double *params;
     KOpts o;
+    int lm;           // planes per chunk along the marching axis (>= 1)
 };
 
 // one face: G = F - Pi (and Pi separately) on the D-face below cell (i,j,k)
@@ -435,18 +457,19 @@ __global__ __launch_bounds__(NT) void k_tcouple(TArgs<R> a)
 {
     constexpr int SHK = (VAR == VAR_SHOCK);
     constexpr int TX = TTile<DIM>::TX, TY = TTile<DIM>::TY;
+    constexpr int GXS = TTile<DIM>::GXS, GYS = TTile<DIM>::GYS;
     constexpr int AM = DIM - 1;                 // marching axis
     constexpr int NPX = PAR ? NV : 1;           // Pi planes kept only with parabolic terms
-    __shared__ R Gx[NV][TY][TX + 1];
-    __shared__ R Px[NPX][TY][TX + 1];
-    __shared__ R Gy[(DIM == 3) ? NV : 1][TY + 1][TX];
-    __shared__ R Py[(DIM == 3) ? NPX : 1][TY + 1][TX];
+    __shared__ R Gx[NV][GXS];
+    __shared__ R Px[NPX][GXS];
+    __shared__ R Gy[(DIM == 3) ? NV : 1][GYS];
+    __shared__ R Py[(DIM == 3) ? NPX : 1][GYS];
 
     const int tid = threadIdx.x;
-    const int tx = tid % TX, ty = tid / TX;
-    // lane in the wave that solves the tile's high faces; consecutive blocks
-    // go to the eight XCDs in turn, so the choice mixes in the block's place
-    // within its XCD
+    // lane in the wave that solves the extra faces; consecutive blocks go to
+    // the eight XCDs in turn, so the choice mixes in the block's place within
+    // its XCD, and over the blocks resident on a compute unit the extra
+    // solves spread over its four SIMDs
     const int et = tid - 64 * (int)((blockIdx.x ^ (blockIdx.x >> 3)) & (NT / 64 - 1));
     const KTile tl = a.tiles[blockIdx.x];
     const KBox bx = a.boxes[tl.box];
@@ -459,73 +482,108 @@ __global__ __launch_bounds__(NT) void k_tcouple(TArgs<R> a)
     const unsigned char *fb = SHK ? a.flag + bx.woff / NV : nullptr;
     const Blk<R> bT0(a.T[0] + bx.woff, bx.cells), bT1(a.T[1] + bx.woff, bx.cells), bT2(DIM == 3 ? a.T[2] + bx.woff : Vb, bx.cells);
     const R ix = R(1.0 / bx.dx[0]), iy = R(1.0 / bx.dx[1]), iz = R(1.0 / bx.dx[2]);
-    // in-plane cell of this thread (ghosted coordinates) and region bounds
-    const int i = bx.g[0] - 1 + tl.a + tx;
-    const int j = (DIM == 3) ? bx.g[1] - 1 + tl.b + ty : 0;
     const int hi0 = bx.g[0] + bx.n[0];                       // last region cell along x
     const int hi1 = (DIM == 3) ? bx.g[1] + bx.n[1] : 0;
-    const bool inplane = (i <= hi0) && (DIM == 2 || j <= hi1);
+
+    // this lane's in-plane position (ghosted coordinates), the faces it
+    // solves, whether it finishes a cell, and its LDS slots: the x / y face
+    // below it sits at lx / ly, the faces above it at lx + 1 / ly + sy
+    int i, j, lx, ly, sy;
+    bool xf, yf, inplane;
+    // the extra face of this lane (if any): below position (ei, ej), along
+    // x (ed = 0) or y (ed = 1), into slot es
+    int ei = 0, ej = 0, ed = -1, es = 0;
+    if (DIM == 3 && tl.b < 0) {
+        const int W1 = bx.n[0] + 3, H1 = bx.n[1] + 3, P = W1 * H1;
+        const int p = tl.a + tid, x = p % W1, y = p / W1;
+        i = bx.g[0] - 1 + x;
+        j = bx.g[1] - 1 + y;
+        xf = p < P && y < H1 - 1;
+        yf = p < P && x < W1 - 1;
+        inplane = xf && yf;
+        lx = ly = tid;
+        sy = W1;
+        if (et >= 0 && et <= W1) {
+            const int q = tl.a + NT + (et < W1 ? et : 0), qx = q % W1, qy = q / W1;
+            ei = bx.g[0] - 1 + qx;
+            ej = bx.g[1] - 1 + qy;
+            if (et < W1) {
+                if (q < P && qx < W1 - 1) ed = 1;
+                es = NT + et;
+            } else {
+                if (q < P && qy < H1 - 1) ed = 0;
+                es = NT;
+            }
+        }
+    } else {
+        const int tx = tid % TX, ty = tid / TX;
+        i = bx.g[0] - 1 + tl.a + tx;
+        j = (DIM == 3) ? bx.g[1] - 1 + tl.b + ty : 0;
+        xf = (i <= hi0 + 1) && (DIM == 2 || j <= hi1);
+        yf = (DIM == 3) && (i <= hi0) && (j <= hi1 + 1);
+        inplane = (i <= hi0) && (DIM == 2 || j <= hi1);
+        lx = ty * (TX + 1) + tx;
+        ly = ty * TX + tx;
+        sy = TX;
+        if (et >= 0 && et < TY) {
+            ei = bx.g[0] - 1 + tl.a + TX;
+            ej = (DIM == 3) ? bx.g[1] - 1 + tl.b + et : 0;
+            if (ei <= hi0 + 1 && (DIM == 2 || ej <= hi1)) ed = 0;
+            es = et * (TX + 1) + TX;
+        } else if (DIM == 3 && et >= TY && et < TY + TX) {
+            ei = bx.g[0] - 1 + tl.a + (et - TY);
+            ej = bx.g[1] - 1 + tl.b + TY;
+            if (ei <= hi0 && ej <= hi1 + 1) ed = 1;
+            es = TY * TX + (et - TY);
+        }
+    }
     // this block's chunk of the region [g-1, g+n] along the marching axis;
     // its first marching faces are recomputed, not shared with the chunk below
     const int m0 = bx.g[AM] - 1 + tl.c;
-    const int m1 = min(m0 + TTile<DIM>::LM - 1, bx.g[AM] + bx.n[AM]);
+    const int m1 = min(m0 + a.lm - 1, bx.g[AM] + bx.n[AM]);
 
     R Gm_prev[NV], Pm_prev[NV], Lx_prev[NV], Ly_prev[NV], Px_prev[NV], Py_prev[NV];
     for (int m = m0; m <= m1 + 1; m++) {
-        const int ci = i, cj = (DIM == 3) ? j : m, ck = (DIM == 3) ? m : 0;
+        const int cj = (DIM == 3) ? j : m, ck = (DIM == 3) ? m : 0;
         // ---- faces of this plane: the marching face below each region cell,
-        // and the in-plane low faces of every cell whose face borders the
-        // region (one cell past it along x / y computes only that face) ----
+        // and the in-plane low faces of every position whose face borders the
+        // region ----
         R Gm[NV], Pm[NV];
-        if (inplane) tface<AM, PHYS, RS, PAR, SHK>(bV, Vb, bx, ci, cj, ck, o, gam, ch, Gm, Pm, fb);
+        if (inplane) tface<AM, PHYS, RS, PAR, SHK>(bV, Vb, bx, i, cj, ck, o, gam, ch, Gm, Pm, fb);
         if (m <= m1) {
             R G[NV], P[NV];
-            if (i <= hi0 + 1 && (DIM == 2 || j <= hi1)) {
-                tface<0, PHYS, RS, PAR, SHK>(bV, Vb, bx, ci, cj, ck, o, gam, ch, G, P, fb);
+            if (xf) {
+                tface<0, PHYS, RS, PAR, SHK>(bV, Vb, bx, i, cj, ck, o, gam, ch, G, P, fb);
 #pragma unroll
                 for (int q = 0; q < NV; q++) {
-                    Gx[q][ty][tx] = G[q];
-                    if (PAR) Px[q][ty][tx] = P[q];
+                    Gx[q][lx] = G[q];
+                    if (PAR) Px[q][lx] = P[q];
                 }
             }
             if constexpr (DIM == 3) {
-                if (i <= hi0 && j <= hi1 + 1) {
-                    tface<1, PHYS, RS, PAR, SHK>(bV, Vb, bx, ci, cj, ck, o, gam, ch, G, P, fb);
+                if (yf) {
+                    tface<1, PHYS, RS, PAR, SHK>(bV, Vb, bx, i, cj, ck, o, gam, ch, G, P, fb);
 #pragma unroll
                     for (int q = 0; q < NV; q++) {
-                        Gy[q][ty][tx] = G[q];
-                        if (PAR) Py[q][ty][tx] = P[q];
+                        Gy[q][ly] = G[q];
+                        if (PAR) Py[q][ly] = P[q];
                     }
                 }
             }
-        }
-        // the tile's high in-plane faces (TY along x, TX along y), solved by
-        // one wave chosen by block index so that over the blocks resident on
-        // a compute unit the extra solves spread over its four SIMDs
-        if (m <= m1) {
-            if (et >= 0 && et < TY) {
-                const int ei = bx.g[0] - 1 + tl.a + TX, ej = (DIM == 3) ? bx.g[1] - 1 + tl.b + et : m;
-                const int ek = (DIM == 3) ? m : 0;
-                if (ei <= hi0 + 1 && (DIM == 2 || ej <= hi1)) {
-                    R G[NV], P[NV];
-                    tface<0, PHYS, RS, PAR, SHK>(bV, Vb, bx, ei, ej, ek, o, gam, ch, G, P, fb);
+            // the extra faces
+            if (ed == 0) {
+                tface<0, PHYS, RS, PAR, SHK>(bV, Vb, bx, ei, (DIM == 3) ? ej : m, ck, o, gam, ch, G, P, fb);
 #pragma unroll
-                    for (int q = 0; q < NV; q++) {
-                        Gx[q][et][TX] = G[q];
-                        if (PAR) Px[q][et][TX] = P[q];
-                    }
+                for (int q = 0; q < NV; q++) {
+                    Gx[q][es] = G[q];
+                    if (PAR) Px[q][es] = P[q];
                 }
-            } else if (DIM == 3 && et >= TY && et < TY + TX) {
-                const int c = et - TY;
-                const int ei = bx.g[0] - 1 + tl.a + c, ej = bx.g[1] - 1 + tl.b + TY;
-                if (ei <= hi0 && ej <= hi1 + 1) {
-                    R G[NV], P[NV];
-                    tface<(DIM == 3 ? 1 : 0), PHYS, RS, PAR, SHK>(bV, Vb, bx, ei, ej, m, o, gam, ch, G, P, fb);
+            } else if (DIM == 3 && ed == 1) {
+                tface<(DIM == 3 ? 1 : 0), PHYS, RS, PAR, SHK>(bV, Vb, bx, ei, ej, m, o, gam, ch, G, P, fb);
 #pragma unroll
-                    for (int q = 0; q < NV; q++) {
-                        Gy[q][TY][c] = G[q];
-                        if (PAR) Py[q][TY][c] = P[q];
-                    }
+                for (int q = 0; q < NV; q++) {
+                    Gy[q][es] = G[q];
+                    if (PAR) Py[q][es] = P[q];
                 }
             }
         }
@@ -565,11 +623,11 @@ __global__ __launch_bounds__(NT) void k_tcouple(TArgs<R> a)
             if (m <= m1) {
 #pragma unroll
                 for (int q = 0; q < NV; q++) {
-                    Lx_prev[q] = -(Gx[q][ty][tx + 1] - Gx[q][ty][tx]) * ix;
-                    if (PAR) Px_prev[q] = (Px[q][ty][tx + 1] - Px[q][ty][tx]) * ix;
+                    Lx_prev[q] = -(Gx[q][lx + 1] - Gx[q][lx]) * ix;
+                    if (PAR) Px_prev[q] = (Px[q][lx + 1] - Px[q][lx]) * ix;
                     if constexpr (DIM == 3) {
-                        Ly_prev[q] = -(Gy[q][ty + 1][tx] - Gy[q][ty][tx]) * iy;
-                        if (PAR) Py_prev[q] = (Py[q][ty + 1][tx] - Py[q][ty][tx]) * iy;
+                        Ly_prev[q] = -(Gy[q][ly + sy] - Gy[q][ly]) * iy;
+                        if (PAR) Py_prev[q] = (Py[q][ly + sy] - Py[q][ly]) * iy;
                     }
                 }
             }

@@ -10,7 +10,9 @@
 #include <algorithm>
 #include <cstdio>
 #include <cstring>
+#include <array>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -80,6 +82,9 @@ struct ctu_plan {
     KRefl *drefl = nullptr;
     int *dcell_start = nullptr;
     int nrefl_cells = 0;
+    // launch shape of the t^n and sweep tables (see ctu_shape)
+    ctu_shape shape{ CTU_TC_AUTO, 0, 0, 1 };
+    std::string tune_key;  // autotune cache key of the option set and box extents
     // graph
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
@@ -155,44 +160,90 @@ void add_linear_tiles(TileSet &ts, int box, long long count)
     for (long long s = 0; s < count; s += NT) ts.h.push_back(KTile{ box, (int)s, 0, 0 });
 }
 
-ctu_status build_tables(ctu_plan *p)
+// Flat t^n layout (3D only): rows of at most MAXW1 positions.  AUTO picks it
+// for a box when it needs fewer blocks per plane than the 32 x 8 tiles.
+bool flat_allowed(const ctu_plan *p, const KBox &bx)
+{
+    return p->opts.dim == 3 && bx.n[0] + 3 <= TTile<3>::MAXW1;
+}
+
+bool use_flat(const ctu_plan *p, const KBox &bx)
+{
+    if (!flat_allowed(p, bx) || p->shape.tc_layout == CTU_TC_TILES) return false;
+    if (p->shape.tc_layout == CTU_TC_FLAT) return true;
+    const long long W = bx.n[0] + 2, H = bx.n[1] + 2;
+    const long long tiles = ((W + TTile<3>::TX - 1) / TTile<3>::TX) * ((H + TTile<3>::TY - 1) / TTile<3>::TY);
+    const long long flat = ((W + 1) * (H + 1) + NT - 1) / NT;
+    return flat < tiles;
+}
+
+int tc_chunk(const ctu_plan *p) { return p->shape.tc_chunk > 0 ? p->shape.tc_chunk : TTile<3>::LM; }
+
+void free_tiles(TileSet &ts)
+{
+    if (ts.d) (void)hipFree(ts.d);
+    ts.d = nullptr;
+    ts.h.clear();
+}
+
+// the tables that depend on the launch shape: t^n tiles and sweep columns
+ctu_status build_shape_tables(ctu_plan *p)
 {
     const int dim = p->opts.dim;
-    const int par = p->opts.parabolic_mask ? 1 : 0;
+    free_tiles(p->t_tc);
+    for (int D = 0; D < 3; D++) free_tiles(p->t_sweep[D]);
+    const int LM = tc_chunk(p);
     for (int b = 0; b < (int)p->hboxes.size(); b++) {
         const KBox &bx = p->hboxes[b];
-        add_linear_tiles(p->t_cells, b, bx.cells);
         // t^n marching kernel: in-plane tiles of the region [g-1, g+n]
-        {
+        const int em = bx.n[dim - 1] + 2;
+        if (use_flat(p, bx)) {
+            const int npos = (bx.n[0] + 3) * (bx.n[1] + 3);
+            for (int m0 = 0; m0 < em; m0 += LM)
+                for (int p0 = 0; p0 < npos; p0 += NT) p->t_tc.h.push_back(KTile{ b, p0, -1, m0 });
+        } else {
             const int TX = (dim == 3) ? TTile<3>::TX : TTile<2>::TX;
             const int TY = (dim == 3) ? TTile<3>::TY : TTile<2>::TY;
-            const int LM = TTile<3>::LM;
             const int ex = bx.n[0] + 2, ey = (dim == 3) ? bx.n[1] + 2 : 1;
-            const int em = bx.n[dim - 1] + 2;
             for (int m0 = 0; m0 < em; m0 += LM)
                 for (int y0 = 0; y0 < ey; y0 += TY)
                     for (int x0 = 0; x0 < ex; x0 += TX) p->t_tc.h.push_back(KTile{ b, x0, y0, m0 });
         }
-        long long interior = (long long)bx.n[0] * bx.n[1] * bx.n[2];
-        add_linear_tiles(p->t_cfl, b, interior);
         for (int D = 0; D < dim; D++) {
             int T0 = (D == 0) ? 1 : 0, T1 = (D == 2) ? 1 : 2;
             int npos = bx.n[T0] * ((T1 < dim) ? bx.n[T1] : 1);
             if (D == 0) {
-                int P = pencils_per_block(bx.n[0] + 2, npos);
+                int P = p->shape.x_pencils > 0 ? std::min(p->shape.x_pencils, npos)
+                                               : pencils_per_block(bx.n[0] + 2, npos);
                 for (int s = 0; s < npos; s += P) p->t_sweep[0].h.push_back(KTile{ b, s, P, 0 });
             } else {
                 for (int s = 0; s < npos; s += 64) p->t_sweep[D].h.push_back(KTile{ b, s, 64, 0 });
             }
         }
     }
-    xcd_order(p->t_tc.h);
-    for (int D = 0; D < dim; D++) xcd_order(p->t_sweep[D].h);
+    if (p->shape.xcd_order) {
+        xcd_order(p->t_tc.h);
+        for (int D = 0; D < dim; D++) xcd_order(p->t_sweep[D].h);
+    }
     ctu_status st;
-    TileSet *all[] = { &p->t_cells, &p->t_tc, &p->t_sweep[0], &p->t_sweep[1], &p->t_sweep[2], &p->t_cfl };
+    TileSet *all[] = { &p->t_tc, &p->t_sweep[0], &p->t_sweep[1], &p->t_sweep[2] };
     for (TileSet *ts : all)
         if ((st = upload(ts->h, &ts->d)) != CTU_OK) return st;
     return CTU_OK;
+}
+
+ctu_status build_tables(ctu_plan *p)
+{
+    for (int b = 0; b < (int)p->hboxes.size(); b++) {
+        const KBox &bx = p->hboxes[b];
+        add_linear_tiles(p->t_cells, b, bx.cells);
+        add_linear_tiles(p->t_cfl, b, (long long)bx.n[0] * bx.n[1] * bx.n[2]);
+    }
+    ctu_status st;
+    TileSet *all[] = { &p->t_cells, &p->t_cfl };
+    for (TileSet *ts : all)
+        if ((st = upload(ts->h, &ts->d)) != CTU_OK) return st;
+    return build_shape_tables(p);
 }
 
 ctu_status alloc_ws(ctu_plan *p, void **ptr, int64_t elems)
@@ -264,6 +315,7 @@ ctu_status enqueue_step(ctu_plan *p, const void *U_in, void *U_out, const double
         ta.flag = p->wsFlag;
         ta.params = params;
         ta.o = p->ko;
+        ta.lm = tc_chunk(p);
         hipError_t e;
         if constexpr (sizeof(R) == 4)
             e = launch_tcouple_f32(dim, par ? 1 : 0, p->combo, p->t_tc.n(), ta, s);
@@ -303,6 +355,55 @@ ctu_status enqueue_step(ctu_plan *p, const void *U_in, void *U_out, const double
     }
     if (p->timing && p->tsteps < kMaxTimedSteps) p->tsteps++;
     return CTU_OK;
+}
+
+// Autotune cache: the best shape found per option set and box extents,
+// for the life of the process; ctu_plan_create applies a cached shape.
+std::mutex g_tune_mu;
+std::map<std::string, ctu_shape> g_tune_cache;
+
+std::string tune_key(const ctu_plan *p)
+{
+    const ctu_opts &o = p->opts;
+    std::vector<std::array<int, 3>> ext;
+    for (const KBox &b : p->hboxes) ext.push_back({ b.n[0], b.n[1], b.n[2] });
+    std::sort(ext.begin(), ext.end());
+    unsigned long long h = 1469598103934665603ULL;  // FNV-1a over the sorted extents
+    for (auto &e : ext)
+        for (int v : e) {
+            h ^= (unsigned)v;
+            h *= 1099511628211ULL;
+        }
+    char buf[256];
+    std::snprintf(buf, sizeof buf, "p%d d%d ph%d r%d pr%d rs%d w%d g%d pb%u c%d s%d h%u ng%d nb%zu x%016llx", p->esize,
+                  o.dim, o.physics, o.recon, o.predictor, o.riemann, o.wref, o.glm, o.parabolic_mask, o.cooling,
+                  o.shock_eps > 0.0 ? 1 : 0, o.hyperbolic_off, p->nghost, p->hboxes.size(), h);
+    return buf;
+}
+
+ctu_status check_shape(const ctu_shape *sh)
+{
+    if (!sh) return fail(CTU_ERR_ARG, "null shape");
+    if (sh->tc_layout < CTU_TC_AUTO || sh->tc_layout > CTU_TC_FLAT) return fail(CTU_ERR_ARG, "bad tc_layout");
+    if (sh->tc_chunk < 0 || sh->tc_chunk > 4096) return fail(CTU_ERR_ARG, "tc_chunk must be 0 (default) or 1..4096");
+    if (sh->x_pencils < 0 || sh->x_pencils > 64) return fail(CTU_ERR_ARG, "x_pencils must be 0 (auto) or 1..64");
+    if (sh->xcd_order != 0 && sh->xcd_order != 1) return fail(CTU_ERR_ARG, "xcd_order must be 0 or 1");
+    return CTU_OK;
+}
+
+// rebuild the shape's tables; a captured graph refers to the old ones
+ctu_status apply_shape(ctu_plan *p, const ctu_shape &sh)
+{
+    if (p->gexec) {
+        HIP_TRY(hipGraphExecDestroy(p->gexec));
+        p->gexec = nullptr;
+    }
+    if (p->graph) {
+        HIP_TRY(hipGraphDestroy(p->graph));
+        p->graph = nullptr;
+    }
+    p->shape = sh;
+    return build_shape_tables(p);
 }
 
 ctu_status check_step_args(ctu_plan *p, const void *U_in, void *U_out, const double *params, const void *L0,
@@ -487,6 +588,23 @@ ctu_status ctu_plan_create(const ctu_opts *opts, const ctu_box *boxes, int32_t n
         free_plan(p);
         return st;
     }
+    p->tune_key = tune_key(p);
+    {
+        ctu_shape cached;
+        bool hit = false;
+        {
+            std::lock_guard<std::mutex> lk(g_tune_mu);
+            auto it = g_tune_cache.find(p->tune_key);
+            if (it != g_tune_cache.end()) {
+                cached = it->second;
+                hit = true;
+            }
+        }
+        if (hit && (st = apply_shape(p, cached)) != CTU_OK) {
+            free_plan(p);
+            return st;
+        }
+    }
     const int64_t f9 = NV * p->ws_cells;
     if ((st = alloc_ws(p, &p->wsV, f9)) != CTU_OK) {
         free_plan(p);
@@ -518,6 +636,123 @@ void ctu_plan_destroy(ctu_plan *plan) { free_plan(plan); }
 
 int64_t ctu_plan_state_elems(const ctu_plan *plan) { return plan ? plan->state_elems : 0; }
 int64_t ctu_plan_workspace_bytes(const ctu_plan *plan) { return plan ? plan->ws_bytes : 0; }
+
+ctu_status ctu_plan_set_shape(ctu_plan *plan, const ctu_shape *shape)
+{
+    if (!plan) return fail(CTU_ERR_ARG, "null plan");
+    ctu_status st = check_shape(shape);
+    if (st != CTU_OK) return st;
+    return apply_shape(plan, *shape);
+}
+
+ctu_status ctu_plan_get_shape(const ctu_plan *plan, ctu_shape *shape_out, int32_t *flat_boxes_out)
+{
+    if (!plan || !shape_out) return fail(CTU_ERR_ARG, "null plan or shape");
+    *shape_out = plan->shape;
+    if (flat_boxes_out) {
+        int nf = 0;
+        for (const KBox &b : plan->hboxes) nf += use_flat(plan, b) ? 1 : 0;
+        *flat_boxes_out = nf;
+    }
+    return CTU_OK;
+}
+
+ctu_status ctu_plan_autotune(ctu_plan *plan, const void *U_in_dev, void *U_out_dev, const double *params_dev,
+                             const void *cool_L0_dev, int32_t reps, void *stream, ctu_shape *best_out,
+                             double *best_ms_out)
+{
+    if (!plan) return fail(CTU_ERR_ARG, "null plan");
+    if (!U_in_dev || !U_out_dev || !params_dev) return fail(CTU_ERR_ARG, "U_in, U_out and params are required");
+    if (U_in_dev == U_out_dev) return fail(CTU_ERR_ARG, "U_out must not alias U_in");
+    if (plan->opts.cooling && !cool_L0_dev) return fail(CTU_ERR_ARG, "cooling needs cool_L0");
+    if (reps < 1 || reps > 1000) return fail(CTU_ERR_ARG, "reps must be in 1..1000");
+    hipStream_t s = (hipStream_t)stream;
+    const bool timing = plan->timing;
+    plan->timing = false;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    ctu_status st = CTU_OK;
+    auto run = [&](double &ms) -> ctu_status {
+        ctu_status r;
+        for (int k = 0; k <= reps; k++) {
+            if (k == 1) HIP_TRY(hipEventRecord(e0, s));
+            // no registers, rate, dpp or failure counts: only the timing matters
+            r = (plan->esize == 4) ? enqueue_step<float>(plan, U_in_dev, U_out_dev, params_dev, cool_L0_dev, nullptr,
+                                                         nullptr, nullptr, nullptr, s)
+                                   : enqueue_step<double>(plan, U_in_dev, U_out_dev, params_dev, cool_L0_dev,
+                                                          nullptr, nullptr, nullptr, nullptr, s);
+            if (r != CTU_OK) return r;
+        }
+        HIP_TRY(hipEventRecord(e1, s));
+        HIP_TRY(hipEventSynchronize(e1));
+        float f = 0.0f;
+        HIP_TRY(hipEventElapsedTime(&f, e0, e1));
+        ms = f / reps;
+        return CTU_OK;
+    };
+    auto body = [&]() -> ctu_status {
+        HIP_TRY(hipEventCreate(&e0));
+        HIP_TRY(hipEventCreate(&e1));
+        bool any_flat = false;
+        for (const KBox &b : plan->hboxes) any_flat = any_flat || flat_allowed(plan, b);
+        ctu_shape best = plan->shape;
+        double best_ms = 0.0;
+        ctu_status r;
+        if ((r = apply_shape(plan, best)) != CTU_OK || (r = run(best_ms)) != CTU_OK) return r;
+        auto consider = [&](const ctu_shape &c) -> ctu_status {
+            double ms;
+            ctu_status q;
+            if ((q = apply_shape(plan, c)) != CTU_OK || (q = run(ms)) != CTU_OK) return q;
+            if (ms < best_ms) {
+                best_ms = ms;
+                best = c;
+            }
+            return CTU_OK;
+        };
+        // coordinate descent: t^n layout and chunk, x-sweep pencils, launch order
+        const int layouts[] = { CTU_TC_AUTO, CTU_TC_TILES, CTU_TC_FLAT };
+        const int chunks[] = { 8, 16, 32 };
+        for (int L : layouts) {
+            if (L != CTU_TC_TILES && !any_flat) continue;
+            for (int ch : chunks) {
+                ctu_shape c = best;
+                c.tc_layout = L;
+                c.tc_chunk = ch;
+                if ((r = consider(c)) != CTU_OK) return r;
+            }
+        }
+        const int pencils[] = { 0, 4, 8, 16, 32 };
+        for (int P : pencils) {
+            ctu_shape c = best;
+            c.x_pencils = P;
+            if ((r = consider(c)) != CTU_OK) return r;
+        }
+        {
+            ctu_shape c = best;
+            c.xcd_order = 1 - c.xcd_order;
+            if ((r = consider(c)) != CTU_OK) return r;
+        }
+        if ((r = apply_shape(plan, best)) != CTU_OK) return r;
+        {
+            std::lock_guard<std::mutex> lk(g_tune_mu);
+            g_tune_cache[plan->tune_key] = best;
+        }
+        if (best_out) *best_out = best;
+        if (best_ms_out) *best_ms_out = best_ms;
+        return CTU_OK;
+    };
+    st = body();
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    plan->timing = timing;
+    return st;
+}
+
+ctu_status ctu_tune_cache_clear(void)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_cache.clear();
+    return CTU_OK;
+}
 
 ctu_status ctu_step(ctu_plan *plan, const void *U_in_dev, void *U_out_dev, const double *params_dev,
                     const void *cool_L0_dev, double *reg_dev, double *rate_dev, double *dpp_dev, int32_t *fails_dev,

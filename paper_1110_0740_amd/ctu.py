@@ -29,7 +29,9 @@ SYMBOLS = [
     "ctu_plan_set_reflux", "ctu_reflux", "ctu_reflux_consume", "ctu_plan_enable_timing", "ctu_plan_read_timing",
     "ctu_last_error", "ctu_hier_create", "ctu_hier_destroy", "ctu_hier_fill_ghosts", "ctu_hier_average_down",
     "ctu_hier_advance", "ctu_hier_leaf_mask", "ctu_hier_tag", "ctu_hier_next_dt", "ctu_plan_set_leaf_mask",
+    "ctu_plan_set_shape", "ctu_plan_get_shape", "ctu_plan_autotune", "ctu_tune_cache_clear",
 ]
+TC_LAYOUT = {"auto": 0, "tiles": 1, "flat": 2}
 NSTAGE = 8
 STAGES = ["prim", "tcouple", "unused2", "unused3", "unused4", "sweep_x", "sweep_y", "sweep_z"]
 
@@ -54,6 +56,16 @@ class CtuBox(C.Structure):
 class CtuRegFace(C.Structure):
     _fields_ = [("box", C.c_int32), ("dir", C.c_int32), ("face", C.c_int32), ("pad", C.c_int32),
                 ("tlo", C.c_int32 * 2), ("tn", C.c_int32 * 2), ("slot", C.c_int64)]
+
+
+class CtuShape(C.Structure):
+    _fields_ = [("tc_layout", C.c_int32), ("tc_chunk", C.c_int32), ("x_pencils", C.c_int32),
+                ("xcd_order", C.c_int32)]
+
+    def as_dict(self):
+        inv = {v: k for k, v in TC_LAYOUT.items()}
+        return {"tc_layout": inv.get(self.tc_layout, self.tc_layout), "tc_chunk": self.tc_chunk,
+                "x_pencils": self.x_pencils, "xcd_order": self.xcd_order}
 
 
 class CtuRefluxFace(C.Structure):
@@ -122,6 +134,15 @@ def lib() -> C.CDLL:
         L.ctu_plan_enable_timing.argtypes = [_vp, C.c_int32]
         L.ctu_plan_read_timing.restype = C.c_int32
         L.ctu_plan_read_timing.argtypes = [_vp, C.POINTER(C.c_double), C.POINTER(C.c_int32)]
+        L.ctu_plan_set_shape.restype = C.c_int32
+        L.ctu_plan_set_shape.argtypes = [_vp, C.POINTER(CtuShape)]
+        L.ctu_plan_get_shape.restype = C.c_int32
+        L.ctu_plan_get_shape.argtypes = [_vp, C.POINTER(CtuShape), C.POINTER(C.c_int32)]
+        L.ctu_plan_autotune.restype = C.c_int32
+        L.ctu_plan_autotune.argtypes = [_vp, _vp, _vp, _vp, _vp, C.c_int32, _vp, C.POINTER(CtuShape),
+                                        C.POINTER(C.c_double)]
+        L.ctu_tune_cache_clear.restype = C.c_int32
+        L.ctu_tune_cache_clear.argtypes = []
         L.ctu_last_error.restype = C.c_char_p
         _lib = L
     return _lib
@@ -268,6 +289,31 @@ class Plan:
         """uint8 tensor in the cool_L0 layout (kept alive by the caller) or None"""
         self._leaf = leaf
         _check(lib().ctu_plan_set_leaf_mask(self._h, _ptr(leaf)))
+
+    def set_shape(self, tc_layout="auto", tc_chunk=0, x_pencils=0, xcd_order=1):
+        sh = CtuShape(TC_LAYOUT[tc_layout] if isinstance(tc_layout, str) else int(tc_layout), int(tc_chunk),
+                      int(x_pencils), int(xcd_order))
+        _check(lib().ctu_plan_set_shape(self._h, C.byref(sh)))
+
+    def get_shape(self):
+        """(shape dict, number of boxes on the flat t^n layout)"""
+        sh = CtuShape()
+        nf = C.c_int32()
+        _check(lib().ctu_plan_get_shape(self._h, C.byref(sh), C.byref(nf)))
+        return sh.as_dict(), nf.value
+
+    def autotune(self, U_in, U_out, params, L0=None, reps=3, stream=None):
+        """Time candidate shapes on these buffers, keep the fastest; returns
+        (shape dict, ms per step).  U_out is overwritten."""
+        sh = CtuShape()
+        ms = C.c_double()
+        _check(lib().ctu_plan_autotune(self._h, _ptr(U_in), _ptr(U_out), _ptr(params), _ptr(L0), int(reps),
+                                       _stream(stream), C.byref(sh), C.byref(ms)))
+        return sh.as_dict(), ms.value
+
+
+def tune_cache_clear():
+    _check(lib().ctu_tune_cache_clear())
 
 
 class Hier:

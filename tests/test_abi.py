@@ -34,7 +34,8 @@ def test_struct_layouts_match_c(tmp_path):
     src.write_text(
         '#include <stdio.h>\n#include <stddef.h>\n#include "ctu.h"\n'
         "int main(void){\n"
-        'printf("%zu %zu %zu %zu\\n", sizeof(ctu_opts), sizeof(ctu_box), sizeof(ctu_regface), sizeof(ctu_refluxface));\n'
+        'printf("%zu %zu %zu %zu %zu\\n", sizeof(ctu_opts), sizeof(ctu_box), sizeof(ctu_regface), sizeof(ctu_refluxface), '
+        'sizeof(ctu_shape));\n'
         'printf("%zu %zu %zu %zu\\n", offsetof(ctu_opts, gamma), offsetof(ctu_opts, parabolic_mask), '
         "offsetof(ctu_opts, T_floor), offsetof(ctu_refluxface, fine_slot));\n"
         "return 0;}\n")
@@ -42,9 +43,9 @@ def test_struct_layouts_match_c(tmp_path):
     subprocess.check_call(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
     out = subprocess.check_output([str(exe)]).decode().split()
     sizes = [int(x) for x in out]
-    assert sizes[:4] == [ctypes.sizeof(ctu.CtuOpts), ctypes.sizeof(ctu.CtuBox), ctypes.sizeof(ctu.CtuRegFace),
-                         ctypes.sizeof(ctu.CtuRefluxFace)]
-    assert sizes[4:] == [ctu.CtuOpts.gamma.offset, ctu.CtuOpts.parabolic_mask.offset, ctu.CtuOpts.T_floor.offset,
+    assert sizes[:5] == [ctypes.sizeof(ctu.CtuOpts), ctypes.sizeof(ctu.CtuBox), ctypes.sizeof(ctu.CtuRegFace),
+                         ctypes.sizeof(ctu.CtuRefluxFace), ctypes.sizeof(ctu.CtuShape)]
+    assert sizes[5:] == [ctu.CtuOpts.gamma.offset, ctu.CtuOpts.parabolic_mask.offset, ctu.CtuOpts.T_floor.offset,
                          ctu.CtuRefluxFace.fine_slot.offset]
 
 
@@ -74,3 +75,14 @@ def test_hierarchy_creation_validates_boxes_without_gpu():
     with pytest.raises(ctu.CtuError, match="nesting"):
         coarse = [((0, 0, 0), (4, 8, 8), 0), ((4, 0, 0), (4, 8, 8), 0)]
         ctu.Hier("fp64", 8, [coarse, [((4, 4, 4), (8, 8, 8), 0)], [((2, 2, 2), (4, 4, 4), 0)]], 4)
+
+
+def test_shape_calls_validate_without_gpu():
+    """The shape entry points reject a null plan on the host; clearing the
+    tuning cache touches no device."""
+    L = ctu.lib()
+    sh = ctu.CtuShape(0, 0, 0, 1)
+    assert L.ctu_plan_set_shape(None, ctypes.byref(sh)) != 0
+    assert L.ctu_plan_get_shape(None, ctypes.byref(sh), None) != 0
+    assert L.ctu_plan_autotune(None, None, None, None, None, 1, None, None, None) != 0
+    assert L.ctu_tune_cache_clear() == 0

@@ -1,0 +1,158 @@
+"""Launch shapes and the autotuner: every shape of the t^n and sweep tables
+(rectangular or flat t^n blocks, chunk length, x-sweep pencils per block,
+launch order) gives bitwise the same step -- state, CFL rate and flux
+registers -- in FP64 and FP32, because the per-cell arithmetic does not
+depend on the tiling; the flat layout also matches the oracle.  The
+autotuner keeps a valid shape, does not change results, and caches its
+choice for plans of the same option set and box extents."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_1110_0740_amd import ctu, inputs as I
+from tests.gpu_common import DEV, l1rel, tdtype
+
+pytestmark = pytest.mark.gpu
+
+NG = 4
+LEVEL_N = 64
+# widths 16, 37 and 8 admit the flat t^n layout (n0 + 3 <= 40), 48 does not
+BOXES = [((0, 0, 0), (16, 20, 18)), ((16, 0, 0), (37, 24, 16)), ((0, 24, 0), (48, 40, 20)), ((8, 8, 40), (8, 8, 8))]
+SHAPES = [
+    {},
+    {"tc_layout": "tiles"},
+    {"tc_layout": "flat"},
+    {"tc_layout": "flat", "tc_chunk": 5, "x_pencils": 3, "xcd_order": 0},
+    {"tc_layout": "tiles", "tc_chunk": 1, "x_pencils": 64},
+    {"tc_chunk": 4096, "x_pencils": 1},
+]
+
+
+def box_states():
+    """per box: ghosted conserved state (FP64) of the seeded 3D MHD field
+    sampled on a 64^3 level"""
+    oo = O.make_opts(dim=3, gamma=5.0 / 3.0, dx=(1.0 / LEVEL_N,) * 3, recon="ppm", riemann="hlld")
+    out = []
+    for lo, n in BOXES:
+        V, _ = I.mhd3d_fields(ng=NG, seed=2100, box=I.Box(lo, n), level_n=LEVEL_N)
+        out.append(O.prim2cons(oo, V))
+    return oo, out
+
+
+def regfaces():
+    """register rectangles: the whole low-x face of box 0, part of an
+    interior y plane of box 1, the high-z face of box 3"""
+    return [(0, 0, 0, (0, 0), (20, 18), 0),
+            (1, 1, 7, (20, 3), (10, 9), 20 * 18),
+            (3, 2, 48, (8, 8), (8, 8), 20 * 18 + 90)], 20 * 18 + 90 + 64
+
+
+def make_plan(precision):
+    go = ctu.make_opts(dim=3, recon="ppm", riemann="hlld", gamma=5.0 / 3.0, dx=(1.0 / LEVEL_N,) * 3,
+                       precision=precision)
+    offs, pos = [], 0
+    for lo, n in BOXES:
+        offs.append(pos)
+        pos += 9 * int(np.prod([m + 2 * NG for m in n]))
+    rf, nslots = regfaces()
+    plan = ctu.Plan(go, [(lo, n, 0, o) for (lo, n), o in zip(BOXES, offs)], NG, regfaces=rf)
+    return plan, offs, pos, nslots
+
+
+class Run:
+    def __init__(self, precision):
+        self.plan, self.offs, total, nslots = make_plan(precision)
+        _, U = box_states()
+        self.U = U
+        dt = tdtype(precision)
+        self.Uin = torch.from_numpy(np.concatenate([u.reshape(-1) for u in U])).to(dt).to(DEV)
+        assert self.Uin.numel() == total
+        self.Uout = torch.zeros_like(self.Uin)
+        self.dt, self.ch = 5e-4, 0.5
+        self.params = torch.tensor([self.dt, self.ch], dtype=torch.float64, device=DEV)
+        self.rate = torch.zeros(1, dtype=torch.float64, device=DEV)
+        self.fails = torch.zeros(5, dtype=torch.int32, device=DEV)
+        self.reg = torch.zeros(9 * nslots, dtype=torch.float64, device=DEV)
+
+    def step(self):
+        self.Uout.zero_()
+        self.reg.zero_()
+        self.plan.step(self.Uin, self.Uout, self.params, self.rate, reg=self.reg, fails=self.fails)
+        torch.cuda.synchronize()
+        assert self.fails.cpu().tolist() == [0] * 5
+        return self.Uout.cpu().numpy().copy(), self.rate.item(), self.reg.cpu().numpy().copy()
+
+    def boxes_out(self, flat):
+        out = []
+        for (lo, n), o, u in zip(BOXES, self.offs, self.U):
+            out.append(flat[o:o + u.size].astype(np.float64).reshape(u.shape))
+        return out
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_every_shape_gives_bitwise_the_same_step(precision):
+    r = Run(precision)
+    ref = None
+    for sh in SHAPES:
+        r.plan.set_shape(**sh)
+        got_shape, nflat = r.plan.get_shape()
+        layout = sh.get("tc_layout", "auto")
+        assert got_shape["tc_layout"] == layout
+        assert nflat == (0 if layout == "tiles" else 3)
+        U, rate, reg = r.step()
+        if ref is None:
+            ref = (U, rate, reg)
+            assert np.any(reg != 0.0)
+            continue
+        assert np.array_equal(U, ref[0]), sh
+        assert rate == ref[1], sh
+        assert np.array_equal(reg, ref[2]), sh
+
+
+def test_flat_layout_matches_oracle():
+    r = Run("fp64")
+    r.plan.set_shape(tc_layout="flat", tc_chunk=7)
+    U, _, _ = r.step()
+    oo, _ = box_states()
+    for u_in, got in zip(r.U, r.boxes_out(U)):
+        ref, _, _, fails = O.step(oo, u_in, NG, r.dt, r.ch)
+        assert fails == [0] * 5
+        assert l1rel(got, ref, NG, 3, r.ch).max() <= 1e-12
+
+
+def test_autotune_keeps_results_and_caches_the_shape():
+    ctu.tune_cache_clear()
+    r = Run("fp64")
+    U0, rate0, reg0 = r.step()
+    best, ms = r.plan.autotune(r.Uin, r.Uout, r.params, reps=1)
+    assert ms > 0.0
+    assert best["tc_layout"] in ("auto", "tiles", "flat") and best["tc_chunk"] in (8, 16, 32)
+    assert 0 <= best["x_pencils"] <= 64 and best["xcd_order"] in (0, 1)
+    assert r.plan.get_shape()[0] == best
+    U1, rate1, reg1 = r.step()
+    assert np.array_equal(U0, U1) and rate0 == rate1 and np.array_equal(reg0, reg1)
+    # a new plan of the same options and boxes starts from the tuned shape
+    p2, _, _, _ = make_plan("fp64")
+    assert p2.get_shape()[0] == best
+    # another precision is another key
+    p3, _, _, _ = make_plan("fp32")
+    assert p3.get_shape()[0] == {"tc_layout": "auto", "tc_chunk": 0, "x_pencils": 0, "xcd_order": 1}
+    ctu.tune_cache_clear()
+    p4, _, _, _ = make_plan("fp64")
+    assert p4.get_shape()[0] == {"tc_layout": "auto", "tc_chunk": 0, "x_pencils": 0, "xcd_order": 1}
+
+
+def test_set_shape_validates_and_drops_the_graph():
+    r = Run("fp32")
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        r.plan.graph_capture(r.Uin, r.Uout, r.params, r.rate, reg=r.reg, fails=r.fails, stream=s)
+        r.plan.graph_launch(stream=s)
+    s.synchronize()
+    for bad in ({"tc_layout": 3}, {"tc_chunk": -1}, {"tc_chunk": 4097}, {"x_pencils": 65}, {"xcd_order": 2}):
+        with pytest.raises(ctu.CtuError):
+            r.plan.set_shape(**bad)
+    r.plan.set_shape(tc_layout="flat")
+    with pytest.raises(ctu.CtuError):
+        r.plan.graph_launch(stream=s)
