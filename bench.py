@@ -39,13 +39,25 @@ KERNEL_FLOPS_PER_ZONE = {"prim": 37.0, "tcouple": 1455.0, "sweep_x": 1389.0, "sw
 # 524,308 KiB of FETCH_SIZE and 1,048,576 KiB of WRITE_SIZE, hence the
 # factors.  Same profile file; set an entry to None when its kernel changes
 # after the counter runs.
-KERNEL_TRAFFIC_BYTES = {"prim": (327952 * 2 + 646866) * 1024, "tcouple": (597382 * 2 + 2400708) * 1024,
-                        "sweep_x": (949111 * 2 + 638087) * 1024, "sweep_y": (1009667 * 2 + 630693) * 1024,
-                        "sweep_z": (994293 * 2 + 625506) * 1024}
+KERNEL_TRAFFIC_BYTES = {"prim": (327952 * 2 + 646866) * 1024, "tcouple": (414005 * 2 + 2231380) * 1024,
+                        "sweep_x": (949088 * 2 + 638081) * 1024, "sweep_y": (1010164 * 2 + 630622) * 1024,
+                        "sweep_z": (995657 * 2 + 626022) * 1024}
 # The launch shape of the single-box FP32 plan the counters above were taken
-# with (bench.py --shape tiles,8,16,1); traffic depends on it, so the
-# roofline reports it only when the tuned shape is this one.
+# with (bench.py --shape tiles,8,16,1).  A kernel's traffic depends on the
+# shape fields that change its tiles (the t^n layout -- no box of the 256^3
+# plan can take the flat one -- and chunk, the x-sweep pencils, the launch
+# order), so the roofline reports it only when the tuned shape agrees on
+# those fields.
 PROFILE_SHAPE = {"tc_layout": "tiles", "tc_chunk": 8, "x_pencils": 16, "xcd_order": 1}
+SHAPE_FIELDS = {"prim": (), "tcouple": ("tc_chunk", "xcd_order"), "sweep_x": ("x_pencils", "xcd_order"),
+                "sweep_y": ("xcd_order",), "sweep_z": ("xcd_order",)}
+
+
+def same_profiled_shape(kernel, res):
+    shape = res.get("shape")
+    if shape is None or res.get("flat_boxes", 0) != 0:
+        return False
+    return all(shape[f] == PROFILE_SHAPE[f] for f in SHAPE_FIELDS.get(kernel, ("?",)))
 # Algorithmic HBM bytes per zone of a whole step (read U^n on the ghosted box,
 # write U^{n+1}): 36 B x (264/256)^3 + 36 B in FP32, twice that in FP64.
 PEAK_HBM_GBS = 8000.0
@@ -175,7 +187,7 @@ def amr_leg(K, W, dev, s, tune=True):
     shapes = []
     for lev, p in enumerate(plans):
         if tune:
-            shapes.append(p.autotune(Uin[lev], Uout[lev], params[lev], reps=3, stream=s)[0])
+            shapes.append(p.autotune(Uin[lev], Uout[lev], params[lev], reps=5, stream=s)[0])
         else:
             shapes.append(p.get_shape()[0])
     with torch.cuda.stream(s):
@@ -342,11 +354,9 @@ def main():
         if args.shape:
             lay, chunk, pen, xcd = args.shape.split(",")
             p32.set_shape(tc_layout=lay, tc_chunk=int(chunk), x_pencils=int(pen), xcd_order=int(xcd))
-            shape = p32.get_shape()[0]
-        elif args.no_autotune:
-            shape = p32.get_shape()[0]
-        else:
-            shape = p32.autotune(U32, Uo, params, reps=3, stream=s)[0]
+        elif not args.no_autotune:
+            p32.autotune(U32, Uo, params, reps=5, stream=s)
+        shape, flat_boxes = p32.get_shape()
         with torch.cuda.stream(s):
             p32.graph_capture(U32, Uo, params, rate, fails=fails, stream=s)
             for _ in range(W):
@@ -373,6 +383,7 @@ def main():
         stage_ms, nrec = p32.read_timing()
         p32.enable_timing(False)
         result["fp32_batched"] = {"ms_per_step": ms, "zone_updates_per_s": zones / (ms * 1e-3), "shape": shape,
+                                  "flat_boxes": flat_boxes,
                                   "stage_ms": {k: v / max(nrec, 1) for k, v in stage_ms.items() if v > 0}}
         del Uo, U32, p32
 
@@ -396,7 +407,7 @@ def main():
             achieved = fpz * zones / (dom_ms * 1e-3) / 1e12
             roofline = {"bound": "alu", "kernel": dom, "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
                         "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
-                        "traffic": (KERNEL_TRAFFIC_BYTES.get(dom) if res.get("shape") == PROFILE_SHAPE else None),
+                        "traffic": (KERNEL_TRAFFIC_BYTES.get(dom) if same_profiled_shape(dom, res) else None),
                         "avg_ms": dom_ms, "shape": res.get("shape"),
                         "flop_per_zone": fpz, "peak_unpacked": PEAK_FP32_UNPACKED_TFLOPS,
                         "frac_unpacked": achieved / PEAK_FP32_UNPACKED_TFLOPS}

@@ -224,7 +224,9 @@ ctu_status ctu_plan_get_shape(const ctu_plan *plan, ctu_shape *shape_out, int32_
 
 /* Measure candidate shapes on the caller's data and keep the fastest: the
  * t^n layout and chunk (8, 16, 32), then the x-sweep pencils per block, then
- * the launch order, one coordinate at a time.  Each candidate runs 1 + reps
+ * the launch order, one coordinate at a time, starting from the plan's
+ * shape; a candidate replaces the incumbent only when it is more than 1 %
+ * faster.  Each candidate runs 1 + reps
  * steps of U_in_dev into U_out_dev on the stream (U_out_dev is overwritten;
  * no registers, rate, dpp or failure counts are written), timed with HIP
  * events; the call synchronizes the stream.  The winner is applied (as by

@@ -420,21 +420,37 @@ template <typename R> struct TArgs {
     int lm;           // planes per chunk along the marching axis (>= 1)
 };
 
-// one face: G = F - Pi (and Pi separately) on the D-face below cell (i,j,k)
-template <int D, int PHYS, int RS, int PAR, int SHK, typename R>
-__device__ __forceinline__ void tface(const Blk<R> &bV, const R *Vb, const KBox &bx, int i, int j, int k,
-                                      const KOpts &o, R gam, R ch, R *G, R *Pi, const unsigned char *fb)
+// the nine primitive variables of cell c
+template <typename R> __device__ __forceinline__ void ld_cell(const Blk<R> &bV, int c, R *V)
 {
-    int di, dj, dk;
-    unit<D>(di, dj, dk);
-    const int cs = (int)bx.cells;
-    const int cB = cidx(bx, i, j, k), cA = cidx(bx, i - di, j - dj, k - dk);
-    const bool hl = SHK && ((fb[cA] | fb[cB]) & FLAG_HLL);
+#pragma unroll
+    for (int q = 0; q < NV; q++) V[q] = bV.ld(q, c);
+}
+
+// one face: G = F - Pi (and Pi separately) on the D-face below cell (i,j,k),
+// from states already in registers: VL of the cell below the face, VR of
+// cell (i,j,k).  Both are copied (the solver overwrites B_n) through an
+// empty register barrier: a cell's state is shared by its three faces, and
+// without the barrier the compiler would share and contract their
+// arithmetic differently from a face solved alone, so the same face would
+// round differently under another launch shape
+template <int D, int PHYS, int RS, int PAR, int SHK, typename R>
+__device__ __forceinline__ void tface_s(const R *VL_in, const R *VR_in, const R *Vb, const KBox &bx, int i, int j,
+                                        int k, const KOpts &o, R gam, R ch, R *G, R *Pi, const unsigned char *fb)
+{
+    bool hl = false;
+    if constexpr (SHK) {
+        int di, dj, dk;
+        unit<D>(di, dj, dk);
+        hl = ((fb[cidx(bx, i - di, j - dj, k - dk)] | fb[cidx(bx, i, j, k)]) & FLAG_HLL) != 0;
+    }
     R VL[NV], VR[NV];
 #pragma unroll
     for (int q = 0; q < NV; q++) {
-        VL[q] = bV.ld(q, cA);
-        VR[q] = bV.ld(q, cB);
+        VL[q] = VL_in[q];
+        VR[q] = VR_in[q];
+        asm volatile("" : "+v"(VL[q]));
+        asm volatile("" : "+v"(VR[q]));
     }
     R pL = VL[PRS], pR = VR[PRS], rL = VL[RHO], rR = VR[RHO];
     if (!o.hyp_off) {
@@ -542,18 +558,26 @@ __global__ __launch_bounds__(NT) void k_tcouple(TArgs<R> a)
     const int m0 = bx.g[AM] - 1 + tl.c;
     const int m1 = min(m0 + a.lm - 1, bx.g[AM] + bx.n[AM]);
 
+    // the lane's cell state on this plane (the right state of its three
+    // faces) and on the previous one (the left state of the marching face),
+    // loaded once and carried from plane to plane
+    R Vc[NV], Vp[NV];
+    if (inplane) ld_cell(bV, cidx(bx, i, (DIM == 3) ? j : m0 - 1, (DIM == 3) ? m0 - 1 : 0), Vp);
     R Gm_prev[NV], Pm_prev[NV], Lx_prev[NV], Ly_prev[NV], Px_prev[NV], Py_prev[NV];
     for (int m = m0; m <= m1 + 1; m++) {
         const int cj = (DIM == 3) ? j : m, ck = (DIM == 3) ? m : 0;
+        if (inplane || (m <= m1 && (xf || yf))) ld_cell(bV, cidx(bx, i, cj, ck), Vc);
         // ---- faces of this plane: the marching face below each region cell,
         // and the in-plane low faces of every position whose face borders the
         // region ----
         R Gm[NV], Pm[NV];
-        if (inplane) tface<AM, PHYS, RS, PAR, SHK>(bV, Vb, bx, i, cj, ck, o, gam, ch, Gm, Pm, fb);
+        if (inplane) tface_s<AM, PHYS, RS, PAR, SHK>(Vp, Vc, Vb, bx, i, cj, ck, o, gam, ch, Gm, Pm, fb);
         if (m <= m1) {
             R G[NV], P[NV];
             if (xf) {
-                tface<0, PHYS, RS, PAR, SHK>(bV, Vb, bx, i, cj, ck, o, gam, ch, G, P, fb);
+                R VL[NV];
+                ld_cell(bV, cidx(bx, i - 1, cj, ck), VL);
+                tface_s<0, PHYS, RS, PAR, SHK>(VL, Vc, Vb, bx, i, cj, ck, o, gam, ch, G, P, fb);
 #pragma unroll
                 for (int q = 0; q < NV; q++) {
                     Gx[q][lx] = G[q];
@@ -562,7 +586,9 @@ __global__ __launch_bounds__(NT) void k_tcouple(TArgs<R> a)
             }
             if constexpr (DIM == 3) {
                 if (yf) {
-                    tface<1, PHYS, RS, PAR, SHK>(bV, Vb, bx, i, cj, ck, o, gam, ch, G, P, fb);
+                    R VL[NV];
+                    ld_cell(bV, cidx(bx, i, j - 1, ck), VL);
+                    tface_s<1, PHYS, RS, PAR, SHK>(VL, Vc, Vb, bx, i, cj, ck, o, gam, ch, G, P, fb);
 #pragma unroll
                     for (int q = 0; q < NV; q++) {
                         Gy[q][ly] = G[q];
@@ -572,14 +598,21 @@ __global__ __launch_bounds__(NT) void k_tcouple(TArgs<R> a)
             }
             // the extra faces
             if (ed == 0) {
-                tface<0, PHYS, RS, PAR, SHK>(bV, Vb, bx, ei, (DIM == 3) ? ej : m, ck, o, gam, ch, G, P, fb);
+                const int ej2 = (DIM == 3) ? ej : m;
+                R VL[NV], VR[NV];
+                ld_cell(bV, cidx(bx, ei - 1, ej2, ck), VL);
+                ld_cell(bV, cidx(bx, ei, ej2, ck), VR);
+                tface_s<0, PHYS, RS, PAR, SHK>(VL, VR, Vb, bx, ei, ej2, ck, o, gam, ch, G, P, fb);
 #pragma unroll
                 for (int q = 0; q < NV; q++) {
                     Gx[q][es] = G[q];
                     if (PAR) Px[q][es] = P[q];
                 }
             } else if (DIM == 3 && ed == 1) {
-                tface<(DIM == 3 ? 1 : 0), PHYS, RS, PAR, SHK>(bV, Vb, bx, ei, ej, m, o, gam, ch, G, P, fb);
+                R VL[NV], VR[NV];
+                ld_cell(bV, cidx(bx, ei, ej - 1, m), VL);
+                ld_cell(bV, cidx(bx, ei, ej, m), VR);
+                tface_s<(DIM == 3 ? 1 : 0), PHYS, RS, PAR, SHK>(VL, VR, Vb, bx, ei, ej, m, o, gam, ch, G, P, fb);
 #pragma unroll
                 for (int q = 0; q < NV; q++) {
                     Gy[q][es] = G[q];
@@ -635,6 +668,7 @@ __global__ __launch_bounds__(NT) void k_tcouple(TArgs<R> a)
             for (int q = 0; q < NV; q++) {
                 Gm_prev[q] = Gm[q];
                 if (PAR) Pm_prev[q] = Pm[q];
+                Vp[q] = Vc[q];
             }
         }
         __syncthreads();

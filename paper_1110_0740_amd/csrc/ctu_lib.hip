@@ -702,7 +702,9 @@ ctu_status ctu_plan_autotune(ctu_plan *plan, const void *U_in_dev, void *U_out_d
             double ms;
             ctu_status q;
             if ((q = apply_shape(plan, c)) != CTU_OK || (q = run(ms)) != CTU_OK) return q;
-            if (ms < best_ms) {
+            // a candidate must beat the incumbent by 1 %, so that timing
+            // noise does not flip between shapes of equal speed
+            if (ms < 0.99 * best_ms) {
                 best_ms = ms;
                 best = c;
             }
