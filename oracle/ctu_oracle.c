@@ -44,7 +44,7 @@ enum { REC_LIN_MC = 0, REC_LIN_MINMOD = 1, REC_LIN_VANLEER = 2, REC_LIN_VANALBAD
        REC_PPM = 4, REC_WENO3 = 5 };
 enum { PRED_CHAR = 0, PRED_MH = 1 };
 enum { WREF_FACE = 0, WREF_CELL = 1, WREF_CW84 = 2 };
-enum { RS_HLLD = 0, RS_HLL = 1 };
+enum { RS_HLLD = 0, RS_HLL = 1, RS_RUSANOV = 2 };
 enum { FAIL_RHO = 0, FAIL_PRS = 1, FAIL_NEWTON = 2, FAIL_VEL = 3, FAIL_NAN = 4, NFAIL = 5 };
 
 #define PARAB_VISC 1u
@@ -391,6 +391,26 @@ static void riemann_hll(const orc_opts *o, const double *VL, const double *VR, i
     }
 }
 
+/* Rusanov (local Lax-Friedrichs), Sec. 3.1's list of solvers common to the
+ * classical and relativistic modules: the centred flux minus a dissipation
+ * set by the largest signal speed magnitude a of the two states,
+ * F = (F_L + F_R)/2 - a (U_R - U_L)/2. */
+static void riemann_rusanov(const orc_opts *o, const double *VL, const double *VR, int d, double ch,
+                            double *F, double *smax)
+{
+    double lminL, lmaxL, lminR, lmaxR;
+    signal_speeds(o, VL, d, &lminL, &lmaxL);
+    signal_speeds(o, VR, d, &lminR, &lmaxR);
+    double a = fmax(fmax(fabs(lminL), fabs(lmaxL)), fmax(fabs(lminR), fabs(lmaxR)));
+    *smax = a;
+    double FL[NVAR], FR[NVAR], UL[NVAR], UR[NVAR];
+    phys_flux(o, VL, d, ch, FL);
+    phys_flux(o, VR, d, ch, FR);
+    prim2cons(o, VL, UL);
+    prim2cons(o, VR, UR);
+    for (int v = 0; v < NVAR; v++) F[v] = 0.5 * (FL[v] + FR[v]) - 0.5 * a * (UR[v] - UL[v]);
+}
+
 /* HLLD for ideal MHD (Miyoshi & Kusano 2005), for states sharing B_n. */
 static void riemann_hlld(const orc_opts *o, const double *VL, const double *VR, int d, double ch,
                          double *F, double *smax)
@@ -522,6 +542,8 @@ static void riemann(const orc_opts *o, const double *VLin, const double *VRin, i
     VL[BX1 + d] = VR[BX1 + d] = Bm;
     if (o->riemann == RS_HLLD && o->physics == PHYS_MHD)
         riemann_hlld(o, VL, VR, d, ch, F, smax);
+    else if (o->riemann == RS_RUSANOV)
+        riemann_rusanov(o, VL, VR, d, ch, F, smax);
     else
         riemann_hll(o, VL, VR, d, ch, F, smax);
     if (o->glm) {

@@ -196,7 +196,8 @@ def test_rmhd_speed_bound_brute_force():
 # --------------------------------------------------------------------------
 
 
-@pytest.mark.parametrize("physics,solver", [("mhd", "hlld"), ("mhd", "hll"), ("rmhd", "hll")])
+@pytest.mark.parametrize("physics,solver", [("mhd", "hlld"), ("mhd", "hll"), ("rmhd", "hll"), ("mhd", "rusanov"),
+                                            ("rmhd", "rusanov")])
 def test_riemann_consistency(physics, solver):
     rng = np.random.default_rng(16)
     G = G53 if physics == "mhd" else 4 / 3
