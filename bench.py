@@ -77,6 +77,8 @@ def parse():
     ap.add_argument("--no-amr", action="store_true", help="skip the AMR batch leg")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default launch shapes instead of tuning the FP32 plans first")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the shock-hybrid and Rusanov variants of the FP32 step")
     ap.add_argument("--shape", default=None,
                     help="force the launch shape of the single-box FP32 plan instead of tuning it: "
                          "LAYOUT,CHUNK,PENCILS,XCD (e.g. tiles,8,16,1)")
@@ -387,11 +389,44 @@ def main():
                                   "stage_ms": {k: v / max(nrec, 1) for k, v in stage_ms.items() if v > 0}}
         del Uo, U32, p32
 
+    def run_variants():
+        """The same FP32 workload under the option sets of the widened rows:
+        the App. B shock-adaptive hybrid (flags from V^n every step, HLL and
+        MinMod where flagged) and the Rusanov solver; tuned, graph-replayed."""
+        out = {}
+        variants = {"shock_hybrid": dict(riemann="hlld", shock_eps=5.0), "rusanov": dict(riemann="rusanov")}
+        for name, kw in variants.items():
+            o = ctu.make_opts(dim=3, recon="ppm", gamma=gamma, dx=dx, precision="fp32", **kw)
+            p = ctu.Plan(o, box, ng)
+            U32 = U64.to(torch.float32)
+            Uo = torch.empty_like(U32)
+            torch.cuda.synchronize()
+            if not args.no_autotune:
+                p.autotune(U32, Uo, params, reps=3, stream=s)
+            with torch.cuda.stream(s):
+                p.graph_capture(U32, Uo, params, rate, fails=fails, stream=s)
+                for _ in range(W):
+                    p.graph_launch(stream=s)
+            s.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            with torch.cuda.stream(s):
+                e0.record(s)
+                for _ in range(K):
+                    p.graph_launch(stream=s)
+                e1.record(s)
+            s.synchronize()
+            ms = e0.elapsed_time(e1) / K
+            assert fails.sum().item() == 0, (name, fails)
+            out[name] = {"ms_per_step": ms, "zone_updates_per_s": zones / (ms * 1e-3), "shape": p.get_shape()[0]}
+            del p, U32, Uo
+        return out
+
     print(f"[bench] timing {K} steps after {W} warm-up steps", file=sys.stderr, flush=True)
     if args.precision in ("both", "fp32"):
         run_fp32()
     if args.precision in ("both", "fp64"):
         run_fp64()
+    variants = run_variants() if args.precision in ("both", "fp32") and not args.no_variants else None
 
     main_key = "fp32_batched" if "fp32_batched" in result else "fp64_plain"
     res = result[main_key]
@@ -435,6 +470,8 @@ def main():
         "roofline": roofline,
         "paths": result,
     }
+    if variants:
+        line["variants"] = variants
     if "fp64_plain" in result and "fp32_batched" in result:
         line["fp32_over_fp64"] = result["fp32_batched"]["zone_updates_per_s"] / result["fp64_plain"][
             "zone_updates_per_s"]

@@ -74,8 +74,10 @@ typedef enum { CTU_PRED_CHAR = 0, CTU_PRED_MUSCL_HANCOCK = 1 } ctu_predictor;
 /* Reference state of Eq. wnorm_predp/m: w_ref = w_{i,+-} (FACE, default),
  * w_{i,0} (CELL) or the nu_max / nu_min form (CW84). */
 typedef enum { CTU_WREF_FACE = 0, CTU_WREF_CELL = 1, CTU_WREF_CW84 = 2 } ctu_wref;
-/* Sec. 3.1: HLLD (MHD) or HLL (MHD, RMHD). */
-typedef enum { CTU_HLLD = 0, CTU_HLL = 1 } ctu_riemann;
+/* Sec. 3.1: HLLD (MHD), HLL (MHD, RMHD) or Rusanov, the local Lax-Friedrichs
+ * flux (F_L + F_R)/2 - a (U_R - U_L)/2 with a the largest signal speed
+ * magnitude of the two states (MHD, RMHD; not with shock_eps > 0). */
+typedef enum { CTU_HLLD = 0, CTU_HLL = 1, CTU_RUSANOV = 2 } ctu_riemann;
 
 #define CTU_PARAB_VISC 1u /* Eq. visc_tens */
 #define CTU_PARAB_RES 2u  /* resistive term -curl(eta J) */
@@ -159,8 +161,9 @@ typedef struct ctu_plan ctu_plan;
  * tables, builds the work decomposition and allocates the device workspace
  * (the only allocating call).  nghost must be >= 3 (PPM needs 3, parabolic
  * terms one more); box blocks must not overlap.  Returns CTU_ERR_UNSUPPORTED
- * for PPM/WENO3 with MUSCL-Hancock, characteristic tracing with RMHD, or
- * parabolic/cooling terms with RMHD. */
+ * for PPM/WENO3 with MUSCL-Hancock, characteristic tracing with RMHD,
+ * parabolic/cooling terms with RMHD, HLLD with RMHD, or the shock-adaptive
+ * hybrid with the Rusanov solver. */
 ctu_status ctu_plan_create(const ctu_opts *opts, const ctu_box *boxes, int32_t nbox, int32_t nghost,
                            const ctu_regface *regfaces, int32_t nreg, ctu_plan **plan_out);
 void ctu_plan_destroy(ctu_plan *plan);

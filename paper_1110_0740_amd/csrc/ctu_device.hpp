@@ -18,7 +18,7 @@ enum { RK_LIN = 0, RK_PPM = 1, RK_WENO = 2 };            // reconstruction kinds
 enum { LIM_MC = 0, LIM_MINMOD = 1, LIM_VANLEER = 2, LIM_VANALBADA = 3 };
 enum { PRED_CHAR = 0, PRED_MH = 1 };
 enum { WREF_FACE = 0, WREF_CELL = 1, WREF_CW84 = 2 };
-enum { RS_HLLD = 0, RS_HLL = 1 };
+enum { RS_HLLD = 0, RS_HLL = 1, RS_RUSANOV = 2 };
 enum { F_RHO = 1, F_PRS = 2, F_INV = 4, F_VEL = 8, F_NAN = 16 };  // failure bits
 enum { PB_VISC = 1, PB_RES = 2, PB_TC = 4 };
 
@@ -332,6 +332,24 @@ __device__ __forceinline__ void hll(const R *VL, const R *VR, R *F, R &smax, R g
     }
 }
 
+// Rusanov (local Lax-Friedrichs; Sec. 3.1 lists it for both modules): the
+// centred flux minus a (U_R - U_L)/2, a the largest signal speed magnitude
+// of the two states (the HLL bounds' max(|S_L|, |S_R|))
+template <int D, int PHYS, typename R>
+__device__ __forceinline__ void rusanov(const R *VL, const R *VR, R *F, R &smax, R gam, R ch, int glm)
+{
+    R lmL, lpL, lmR, lpR;
+    wave_speeds<D, PHYS>(VL, gam, lmL, lpL);
+    wave_speeds<D, PHYS>(VR, gam, lmR, lpR);
+    const R a = fmax(fmax(fabs(lmL), fabs(lpL)), fmax(fabs(lmR), fabs(lpR)));
+    smax = a;
+    R UL[NV], UR[NV], FL[NV], FR[NV];
+    phys_flux<D, PHYS>(VL, UL, FL, gam, ch, glm);
+    phys_flux<D, PHYS>(VR, UR, FR, gam, ch, glm);
+#pragma unroll
+    for (int q = 0; q < NV; q++) F[q] = R(0.5) * (FL[q] + FR[q]) - R(0.5) * a * (UR[q] - UL[q]);
+}
+
 // HLLD (Miyoshi & Kusano 2005) for states sharing the normal field.
 //
 // Evaluated without branches: all star states are formed and the flux of
@@ -462,6 +480,7 @@ __device__ __forceinline__ void riemann(R *VL, R *VR, R *F, R &smax, R gam, R ch
     VL[BX1 + D] = Bm;
     VR[BX1 + D] = Bm;
     if constexpr (RS == RS_HLLD && PHYS == PHYS_MHD) hlld<D>(VL, VR, F, smax, gam, ch, glm);
+    else if constexpr (RS == RS_RUSANOV) rusanov<D, PHYS>(VL, VR, F, smax, gam, ch, glm);
     else hll<D, PHYS>(VL, VR, F, smax, gam, ch, glm);
     F[BX1 + D] = glm ? psim : R(0);
     F[PSI] = glm ? ch * ch * Bm : R(0);

@@ -22,7 +22,7 @@ __host__ inline bool combo_supported(const Combo &c)
         if (c.pred == PRED_CHAR) return true;
         return c.rk == RK_LIN;
     }
-    return c.pred == PRED_MH && c.rk == RK_LIN && c.rs == RS_HLL;
+    return c.pred == PRED_MH && c.rk == RK_LIN && (c.rs == RS_HLL || c.rs == RS_RUSANOV);
 }
 
 hipError_t launch_sweep_f32(int D, const Combo &c, int nblocks, const SweepArgs<float> &a, hipStream_t s);
@@ -54,27 +54,39 @@ template <> inline hipError_t launch_sweep<double>(int D, const Combo &c, int nb
     template <int D, int PHYS, int PRED, int RK, int RS>                                                         \
     static hipError_t sweep_one(const Combo &c, int nb, const SweepArgs<R> &a, hipStream_t s)                   \
     {                                                                                                            \
-        if (a.flag) return sweep_one2<D, PHYS, PRED, RK, RS, VAR_SHOCK>(nb, a, s);                               \
-        if (c.fast) return sweep_one2<D, PHYS, PRED, RK, RS, VAR_FAST>(nb, a, s);                                \
-        return sweep_one2<D, PHYS, PRED, RK, RS, VAR_GENERIC>(nb, a, s);                                         \
+        /* Rusanov runs the generic variant only (no hybrid flags, no fixed set) */                              \
+        if constexpr (RS == RS_RUSANOV) {                                                                        \
+            return sweep_one2<D, PHYS, PRED, RK, RS, VAR_GENERIC>(nb, a, s);                                     \
+        } else {                                                                                                 \
+            if (a.flag) return sweep_one2<D, PHYS, PRED, RK, RS, VAR_SHOCK>(nb, a, s);                           \
+            if (c.fast) return sweep_one2<D, PHYS, PRED, RK, RS, VAR_FAST>(nb, a, s);                            \
+            return sweep_one2<D, PHYS, PRED, RK, RS, VAR_GENERIC>(nb, a, s);                                     \
+        }                                                                                                        \
     }                                                                                                            \
     template <int D>                                                                                             \
     static hipError_t sweep_dir(const Combo &c, int nb, const SweepArgs<R> &a, hipStream_t s)                   \
     {                                                                                                            \
-        if (c.phys == PHYS_RMHD) return sweep_one<D, PHYS_RMHD, PRED_MH, RK_LIN, RS_HLL>(c, nb, a, s);            \
+        if (c.phys == PHYS_RMHD) {                                                                               \
+            if (c.rs == RS_RUSANOV) return sweep_one<D, PHYS_RMHD, PRED_MH, RK_LIN, RS_RUSANOV>(c, nb, a, s);     \
+            return sweep_one<D, PHYS_RMHD, PRED_MH, RK_LIN, RS_HLL>(c, nb, a, s);                                 \
+        }                                                                                                        \
         if (c.pred == PRED_MH) {                                                                                 \
             if (c.rs == RS_HLLD) return sweep_one<D, PHYS_MHD, PRED_MH, RK_LIN, RS_HLLD>(c, nb, a, s);            \
+            if (c.rs == RS_RUSANOV) return sweep_one<D, PHYS_MHD, PRED_MH, RK_LIN, RS_RUSANOV>(c, nb, a, s);      \
             return sweep_one<D, PHYS_MHD, PRED_MH, RK_LIN, RS_HLL>(c, nb, a, s);                                  \
         }                                                                                                        \
         if (c.rk == RK_PPM) {                                                                                    \
             if (c.rs == RS_HLLD) return sweep_one<D, PHYS_MHD, PRED_CHAR, RK_PPM, RS_HLLD>(c, nb, a, s);          \
+            if (c.rs == RS_RUSANOV) return sweep_one<D, PHYS_MHD, PRED_CHAR, RK_PPM, RS_RUSANOV>(c, nb, a, s);    \
             return sweep_one<D, PHYS_MHD, PRED_CHAR, RK_PPM, RS_HLL>(c, nb, a, s);                                \
         }                                                                                                        \
         if (c.rk == RK_WENO) {                                                                                   \
             if (c.rs == RS_HLLD) return sweep_one<D, PHYS_MHD, PRED_CHAR, RK_WENO, RS_HLLD>(c, nb, a, s);         \
+            if (c.rs == RS_RUSANOV) return sweep_one<D, PHYS_MHD, PRED_CHAR, RK_WENO, RS_RUSANOV>(c, nb, a, s);   \
             return sweep_one<D, PHYS_MHD, PRED_CHAR, RK_WENO, RS_HLL>(c, nb, a, s);                               \
         }                                                                                                        \
         if (c.rs == RS_HLLD) return sweep_one<D, PHYS_MHD, PRED_CHAR, RK_LIN, RS_HLLD>(c, nb, a, s);              \
+        if (c.rs == RS_RUSANOV) return sweep_one<D, PHYS_MHD, PRED_CHAR, RK_LIN, RS_RUSANOV>(c, nb, a, s);        \
         return sweep_one<D, PHYS_MHD, PRED_CHAR, RK_LIN, RS_HLL>(c, nb, a, s);                                    \
     }                                                                                                            \
     hipError_t launch_sweep_##SUFFIX(int D, const Combo &c, int nb, const SweepArgs<R> &a, hipStream_t s)      \
@@ -88,8 +100,12 @@ template <> inline hipError_t launch_sweep<double>(int D, const Combo &c, int nb
     static hipError_t tc_one(const Combo &c, int nb, const TArgs<R> &a, hipStream_t s)                          \
     {                                                                                                            \
         /* the HLL fallback changes only HLLD runs */                                                           \
-        if (c.phys == PHYS_RMHD)                                                                                 \
+        if (c.phys == PHYS_RMHD && c.rs == RS_RUSANOV)                                                           \
+            hipLaunchKernelGGL((k_tcouple<DIM, PHYS_RMHD, RS_RUSANOV, 0, VAR_GENERIC, R>), dim3(nb), dim3(NT), 0, s, a); \
+        else if (c.phys == PHYS_RMHD)                                                                            \
             hipLaunchKernelGGL((k_tcouple<DIM, PHYS_RMHD, RS_HLL, 0, VAR_GENERIC, R>), dim3(nb), dim3(NT), 0, s, a); \
+        else if (c.rs == RS_RUSANOV)                                                                             \
+            hipLaunchKernelGGL((k_tcouple<DIM, PHYS_MHD, RS_RUSANOV, PAR, VAR_GENERIC, R>), dim3(nb), dim3(NT), 0, s, a); \
         else if (c.rs == RS_HLLD && a.flag)                                                                      \
             hipLaunchKernelGGL((k_tcouple<DIM, PHYS_MHD, RS_HLLD, PAR, VAR_SHOCK, R>), dim3(nb), dim3(NT), 0, s, a); \
         else if (c.fast && c.rs == RS_HLLD)                                                                      \

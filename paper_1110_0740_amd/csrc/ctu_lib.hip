@@ -436,7 +436,7 @@ ctu_status ctu_plan_create(const ctu_opts *opts, const ctu_box *boxes, int32_t n
     if (o.recon < CTU_LIN_MC || o.recon > CTU_WENO3) return fail(CTU_ERR_ARG, "bad recon");
     if (o.predictor != CTU_PRED_CHAR && o.predictor != CTU_PRED_MUSCL_HANCOCK) return fail(CTU_ERR_ARG, "bad predictor");
     if (o.wref < CTU_WREF_FACE || o.wref > CTU_WREF_CW84) return fail(CTU_ERR_ARG, "bad wref");
-    if (o.riemann != CTU_HLLD && o.riemann != CTU_HLL) return fail(CTU_ERR_ARG, "bad riemann");
+    if (o.riemann != CTU_HLLD && o.riemann != CTU_HLL && o.riemann != CTU_RUSANOV) return fail(CTU_ERR_ARG, "bad riemann");
     if (!(o.gamma > 1.0)) return fail(CTU_ERR_ARG, "gamma must exceed 1");
     for (int d = 0; d < o.dim; d++)
         if (!(o.dx[d] > 0.0)) return fail(CTU_ERR_ARG, "dx must be positive");
@@ -448,10 +448,13 @@ ctu_status ctu_plan_create(const ctu_opts *opts, const ctu_box *boxes, int32_t n
     c.rk = (o.recon == CTU_PPM) ? RK_PPM : (o.recon == CTU_WENO3 ? RK_WENO : RK_LIN);
     c.rs = o.riemann;
     c.shk = o.shock_eps > 0.0 ? 1 : 0;
-    c.fast = (o.wref == CTU_WREF_FACE && o.glm && !o.hyperbolic_off && !o.parabolic_mask && !o.cooling && !c.shk) ? 1 : 0;
+    c.fast = (o.wref == CTU_WREF_FACE && o.glm && !o.hyperbolic_off && !o.parabolic_mask && !o.cooling && !c.shk &&
+              o.riemann != CTU_RUSANOV) ? 1 : 0;
+    if (o.riemann == CTU_RUSANOV && c.shk)
+        return fail(CTU_ERR_UNSUPPORTED, "the shock-adaptive hybrid (HLL on flagged faces) needs HLLD or HLL");
     if (o.physics == CTU_RMHD && o.riemann == CTU_HLLD) c.rs = RS_HLL;
     if (o.physics == CTU_RMHD && o.riemann == CTU_HLLD)
-        return fail(CTU_ERR_UNSUPPORTED, "RMHD supports the HLL solver only");
+        return fail(CTU_ERR_UNSUPPORTED, "RMHD supports the HLL and Rusanov solvers only");
     if (!combo_supported(c))
         return fail(CTU_ERR_UNSUPPORTED, "unsupported combination (characteristic tracing is MHD only; "
                                          "MUSCL-Hancock needs a linear reconstruction)");

@@ -58,6 +58,9 @@ def test_plan_creation_validates_options_without_gpu():
                  [((0, 0, 0), (8, 8, 8), 0, 0)], 4)
     with pytest.raises(ctu.CtuError, match="nghost"):
         ctu.Plan(ctu.make_opts(dim=3, recon="ppm"), [((0, 0, 0), (8, 8, 8), 0, 0)], 2)
+    with pytest.raises(ctu.CtuError, match="hybrid"):
+        ctu.Plan(ctu.make_opts(dim=3, recon="ppm", riemann="rusanov", shock_eps=5.0), [((0, 0, 0), (8, 8, 8), 0, 0)],
+                 4)
 
 
 def test_hierarchy_creation_validates_boxes_without_gpu():
