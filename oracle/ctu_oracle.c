@@ -63,7 +63,10 @@ typedef struct {
     double cool_beta, T_floor;
     int hyperbolic_off;
     double shock_eps; /* App. B shock detection threshold eps_q; 0 = off */
+    int eos;          /* RMHD equation of state: EOS_IDEAL (Eq. gammaEos) or EOS_TM (Eq. TMEos) */
 } orc_opts;
+
+enum { EOS_IDEAL = 0, EOS_TM = 1 };
 
 /* ------------------------------------------------------------------------ */
 /* small helpers                                                             */
@@ -157,18 +160,44 @@ static void mhd_flux(const orc_opts *o, const double *V, const double *U, int d,
 }
 
 /* ------------------------------------------------------------------------ */
-/* Relativistic MHD: Eq. rmhd with the ideal EOS Eq. gammaEos (Sec. 2.2)     */
+/* Relativistic MHD: Eq. rmhd with the ideal EOS Eq. gammaEos or the TM EOS  */
+/* Eq. TMEos (Sec. 2.2)                                                      */
 /* ------------------------------------------------------------------------ */
+
+/* Gas enthalpy w(rho, p). */
+static double rmhd_enthalpy(const orc_opts *o, double rho, double p)
+{
+    if (o->eos == EOS_TM) return 2.5 * p + sqrt(2.25 * p * p + rho * rho);
+    return rho + o->gamma * p / (o->gamma - 1.0);
+}
+
+/* Pressure from (rho, w), the inverse of rmhd_enthalpy.  TM: squaring
+ * w - 5p/2 = sqrt(9p^2/4 + rho^2) gives 4p^2 - 5wp + w^2 - rho^2 = 0, whose
+ * root with w - 5p/2 >= 0 is the smaller one. */
+static double rmhd_pressure(const orc_opts *o, double rho, double w)
+{
+    if (o->eos == EOS_TM) return (5.0 * w - sqrt(9.0 * w * w + 16.0 * rho * rho)) / 8.0;
+    return (o->gamma - 1.0) / o->gamma * (w - rho);
+}
+
+/* Sound speed squared c_s^2 = (dp/drho)_s rho / w (the adiabat has
+ * de = (w/rho) drho for the energy density e = w - p).  Ideal: Gamma p / w.
+ * TM: differentiating e = 3p/2 + sqrt(9p^2/4 + rho^2) along the adiabat and
+ * eliminating rho^2 = w^2 - 5wp + 4p^2 gives p (5w - 8p) / (3 w (w - p)). */
+static double rmhd_cs2(const orc_opts *o, double p, double w)
+{
+    if (o->eos == EOS_TM) return p * (5.0 * w - 8.0 * p) / (3.0 * w * (w - p));
+    return o->gamma * p / w;
+}
 
 static void rmhd_prim2cons(const orc_opts *o, const double *V, double *U)
 {
-    double G = o->gamma;
     double v2 = V[MX1] * V[MX1] + V[MX2] * V[MX2] + V[MX3] * V[MX3];
     double B2 = V[BX1] * V[BX1] + V[BX2] * V[BX2] + V[BX3] * V[BX3];
     double vB = V[MX1] * V[BX1] + V[MX2] * V[BX2] + V[MX3] * V[BX3];
     double lor2 = 1.0 / (1.0 - v2);
     double lor = sqrt(lor2);
-    double w = V[RHO] + G * V[PRS] / (G - 1.0);
+    double w = rmhd_enthalpy(o, V[RHO], V[PRS]);
     double E2 = B2 * v2 - vB * vB; /* |v x B|^2 */
     U[RHO] = V[RHO] * lor;
     /* m = w gamma^2 v + E x B, with E = -v x B  =>  E x B = B^2 v - (v.B) B */
@@ -183,7 +212,8 @@ static void rmhd_prim2cons(const orc_opts *o, const double *V, double *U)
 /* Velocity squared and pressure as functions of W = w gamma^2 for fixed
  * conserved variables (the map that the inversion must undo). */
 typedef struct {
-    double D, E, m2, S, B2, G;
+    double D, E, m2, S, B2;
+    const orc_opts *o;
 } rmhd_inv;
 
 static double rmhd_v2_of_W(const rmhd_inv *q, double W)
@@ -199,7 +229,8 @@ static double rmhd_resid(const rmhd_inv *q, double W, double *p_out, double *v2_
 {
     double v2 = rmhd_v2_of_W(q, W);
     double sq = sqrt(1.0 - v2);
-    double p = (q->G - 1.0) / q->G * (W * (1.0 - v2) - q->D * sq);
+    /* w = W / gamma^2, rho = D / gamma */
+    double p = rmhd_pressure(q->o, q->D * sq, W * (1.0 - v2));
     if (p_out) *p_out = p;
     if (v2_out) *v2_out = v2;
     double sw = q->S / W;
@@ -212,7 +243,7 @@ static double rmhd_resid(const rmhd_inv *q, double W, double *p_out, double *v2_
 static int rmhd_cons2prim(const orc_opts *o, const double *U, double *V, int *fails)
 {
     rmhd_inv q;
-    q.G = o->gamma;
+    q.o = o;
     q.D = U[RHO];
     q.E = U[ENG];
     q.m2 = U[MX1] * U[MX1] + U[MX2] * U[MX2] + U[MX3] * U[MX3];
@@ -276,12 +307,11 @@ static void rmhd_flux(const orc_opts *o, const double *V, const double *U, int d
 {
     int n, t, b;
     dir_axes(d, &n, &t, &b);
-    double G = o->gamma;
     double v2 = V[MX1] * V[MX1] + V[MX2] * V[MX2] + V[MX3] * V[MX3];
     double B2 = V[BX1] * V[BX1] + V[BX2] * V[BX2] + V[BX3] * V[BX3];
     double vB = V[MX1] * V[BX1] + V[MX2] * V[BX2] + V[MX3] * V[BX3];
     double lor2 = 1.0 / (1.0 - v2);
-    double w = V[RHO] + G * V[PRS] / (G - 1.0);
+    double w = rmhd_enthalpy(o, V[RHO], V[PRS]);
     double E[3];
     /* E = -v x B */
     E[0] = -(V[MX2] * V[BX3] - V[MX3] * V[BX2]);
@@ -306,12 +336,11 @@ static void rmhd_flux(const orc_opts *o, const double *V, const double *U, int d
  * relativistic velocity addition along d. */
 static void rmhd_speeds(const orc_opts *o, const double *V, int d, double *lmin, double *lmax)
 {
-    double G = o->gamma;
     double v2 = V[MX1] * V[MX1] + V[MX2] * V[MX2] + V[MX3] * V[MX3];
     double B2 = V[BX1] * V[BX1] + V[BX2] * V[BX2] + V[BX3] * V[BX3];
     double vB = V[MX1] * V[BX1] + V[MX2] * V[BX2] + V[MX3] * V[BX3];
-    double w = V[RHO] + G * V[PRS] / (G - 1.0);
-    double cs2 = G * V[PRS] / w;
+    double w = rmhd_enthalpy(o, V[RHO], V[PRS]);
+    double cs2 = rmhd_cs2(o, V[PRS], w);
     double bb2 = B2 * (1.0 - v2) + vB * vB; /* b^2 = B^2/gamma^2 + (v.B)^2 */
     double ca2 = bb2 / (w + bb2);
     double a2 = cs2 + ca2 - cs2 * ca2;
