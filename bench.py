@@ -392,7 +392,8 @@ def main():
     def run_variants():
         """The same FP32 workload under the option sets of the widened rows:
         the App. B shock-adaptive hybrid (flags from V^n every step, HLL and
-        MinMod where flagged) and the Rusanov solver; tuned, graph-replayed."""
+        MinMod where flagged) and the Rusanov solver; and the relativistic
+        workload under both equations of state.  Tuned, graph-replayed."""
         out = {}
         variants = {"shock_hybrid": dict(riemann="hlld", shock_eps=5.0), "rusanov": dict(riemann="rusanov")}
         for name, kw in variants.items():
@@ -419,6 +420,48 @@ def main():
             assert fails.sum().item() == 0, (name, fails)
             out[name] = {"ms_per_step": ms, "zone_updates_per_s": zones / (ms * 1e-3), "shape": p.get_shape()[0]}
             del p, U32, Uo
+        # relativistic MHD, 192^3 jets and blobs (Lorentz factors up to 10),
+        # MUSCL-Hancock + MC + HLL + GLM, FP32 fluxes with the FP64 inversion,
+        # under the ideal EOS (Gamma = 4/3) and the Taub-Matthews EOS
+        nr = 192
+        Vr, mr = I.rmhd3d_fields(n=nr, ng=ng, seed=4000)
+        Vr = torch.from_numpy(Vr.reshape(-1)).to(dev)
+        zr = nr ** 3
+        boxr = [((0, 0, 0), (nr, nr, nr), 0, 0)]
+        for eos in ("ideal", "tm"):
+            kw = dict(dim=3, physics="rmhd", predictor="mh", recon="lin_mc", riemann="hll", gamma=mr["gamma"],
+                      dx=mr["dx"], eos=eos)
+            p64 = ctu.Plan(ctu.make_opts(precision="fp64", **kw), boxr, ng)
+            Ur64 = torch.empty_like(Vr)
+            p64.prim_to_cons(Vr, Ur64)
+            p64.cfl_rate(Ur64, rate)
+            torch.cuda.synchronize()
+            dtr = 0.3 / rate.item()
+            pr = torch.tensor([dtr, min(0.3 * mr["dx"][0] / dtr, 1.0)], dtype=torch.float64, device=dev)
+            p = ctu.Plan(ctu.make_opts(precision="fp32", **kw), boxr, ng)
+            U32 = Ur64.to(torch.float32)
+            Uo = torch.empty_like(U32)
+            del p64, Ur64
+            if not args.no_autotune:
+                p.autotune(U32, Uo, pr, reps=3, stream=s)
+            with torch.cuda.stream(s):
+                p.graph_capture(U32, Uo, pr, rate, fails=fails, stream=s)
+                for _ in range(W):
+                    p.graph_launch(stream=s)
+            s.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            with torch.cuda.stream(s):
+                e0.record(s)
+                for _ in range(K):
+                    p.graph_launch(stream=s)
+                e1.record(s)
+            s.synchronize()
+            ms = e0.elapsed_time(e1) / K
+            assert fails.sum().item() == 0, ("rmhd", eos, fails)
+            out[f"rmhd192_{eos}"] = {"ms_per_step": ms, "zone_updates_per_s": zr / (ms * 1e-3),
+                                     "shape": p.get_shape()[0]}
+            del p, U32, Uo
+        del Vr
         return out
 
     print(f"[bench] timing {K} steps after {W} warm-up steps", file=sys.stderr, flush=True)

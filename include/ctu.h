@@ -79,6 +79,11 @@ typedef enum { CTU_WREF_FACE = 0, CTU_WREF_CELL = 1, CTU_WREF_CW84 = 2 } ctu_wre
  * magnitude of the two states (MHD, RMHD; not with shock_eps > 0). */
 typedef enum { CTU_HLLD = 0, CTU_HLL = 1, CTU_RUSANOV = 2 } ctu_riemann;
 
+/* Sec. 2.2: the RMHD gas enthalpy w(rho, p) of the ideal EOS (Eq. gammaEos,
+ * w = rho + Gamma p / (Gamma - 1)) or of the Taub-Matthews EOS (Eq. TMEos,
+ * w = 5p/2 + sqrt(9p^2/4 + rho^2); gamma is then unused). */
+typedef enum { CTU_EOS_IDEAL = 0, CTU_EOS_TM = 1 } ctu_eos;
+
 #define CTU_PARAB_VISC 1u /* Eq. visc_tens */
 #define CTU_PARAB_RES 2u  /* resistive term -curl(eta J) */
 #define CTU_PARAB_TC 4u   /* Eq. tc_flux with the App. A saturated flux */
@@ -111,6 +116,8 @@ typedef struct {
                               min(p_{+1}, p_{-1}) > eps_q and div v < 0 at t^n take HLL
                               on their faces; zones whose reconstruction stencil along
                               an axis reaches one use MinMod linear reconstruction */
+    int32_t eos;           /* ctu_eos: RMHD equation of state (MHD: CTU_EOS_IDEAL only) */
+    int32_t pad2;
 } ctu_opts;
 
 /* One ghosted box: interior cells [lo, lo+n) in level-global indices.

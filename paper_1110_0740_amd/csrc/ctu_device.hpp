@@ -13,7 +13,9 @@ namespace ctu {
 
 enum { RHO = 0, MX1 = 1, MX2 = 2, MX3 = 3, ENG = 4, BX1 = 5, BX2 = 6, BX3 = 7, PSI = 8, NV = 9 };
 enum { PRS = 4 };
-enum { PHYS_MHD = 0, PHYS_RMHD = 1 };
+// physics module: ideal MHD, relativistic MHD with the ideal EOS (Eq.
+// gammaEos) or with the Taub-Matthews EOS (Eq. TMEos)
+enum { PHYS_MHD = 0, PHYS_RMHD = 1, PHYS_RMHD_TM = 2 };
 enum { RK_LIN = 0, RK_PPM = 1, RK_WENO = 2 };            // reconstruction kinds
 enum { LIM_MC = 0, LIM_MINMOD = 1, LIM_VANLEER = 2, LIM_VANALBADA = 3 };
 enum { PRED_CHAR = 0, PRED_MH = 1 };
@@ -122,18 +124,33 @@ template <int D, typename R> __device__ __forceinline__ void flux_mhd(const R *V
 }
 
 // ---------------------------------------------------------------------------
-// Relativistic MHD (Sec. 2.2, Eq. rmhd, Eq. gammaEos) -- always FP64 for the
-// inversion; fluxes in the working precision.
+// Relativistic MHD (Sec. 2.2, Eq. rmhd; Eq. gammaEos or, TM = true, Eq.
+// TMEos) -- always FP64 for the inversion; fluxes in the working precision.
 // ---------------------------------------------------------------------------
 
-template <typename R> __device__ __forceinline__ void p2c_rmhd(const R *V, R *U, R gam)
+// gas enthalpy w(rho, p)
+template <bool TM, typename R> __device__ __forceinline__ R rmhd_w(R rho, R p, R gam)
+{
+    if constexpr (TM) return R(2.5) * p + sqrt(R(2.25) * p * p + rho * rho);
+    else return rho + gam * p / (gam - R(1));
+}
+
+// sound speed squared, (dp/drho)_s rho / w along the adiabat de = (w/rho)
+// drho of e = w - p: Gamma p / w, or p (5w - 8p) / (3 w (w - p)) for TM
+template <bool TM, typename R> __device__ __forceinline__ R rmhd_cs2(R p, R w, R gam)
+{
+    if constexpr (TM) return p * (R(5) * w - R(8) * p) / (R(3) * w * (w - p));
+    else return gam * p / w;
+}
+
+template <bool TM, typename R> __device__ __forceinline__ void p2c_rmhd(const R *V, R *U, R gam)
 {
     R v2 = sq(V[MX1]) + sq(V[MX2]) + sq(V[MX3]);
     R B2 = sq(V[BX1]) + sq(V[BX2]) + sq(V[BX3]);
     R vB = V[MX1] * V[BX1] + V[MX2] * V[BX2] + V[MX3] * V[BX3];
     R lor2 = R(1) / (R(1) - v2);
     R lor = sqrt(lor2);
-    R w = V[RHO] + gam * V[PRS] / (gam - R(1));
+    R w = rmhd_w<TM>(V[RHO], V[PRS], gam);
     R wl2 = w * lor2;
     U[RHO] = V[RHO] * lor;
     U[MX1] = (wl2 + B2) * V[MX1] - vB * V[BX1];
@@ -148,24 +165,40 @@ template <typename R> __device__ __forceinline__ void p2c_rmhd(const R *V, R *U,
 
 // Conserved -> primitive for RMHD: Newton-Raphson on W = w gamma^2 for the
 // energy residual f(W) = W - p(W) + B^2/2 + (v^2(W) B^2 - S^2/W^2)/2 - D - E,
-// with S = m.B and v^2(W) = (m^2 + S^2 (2W + B^2)/W^2)/(W + B^2)^2, kept
-// inside a bracket [lo, hi] (bisection when a step leaves it).  The upper
-// end Gamma (E + D) has f >= 0 for the Gamma-law EOS.  Converged when
-// |dW| <= 1e-14 W.
-__device__ __forceinline__ int c2p_rmhd(const double *U, double *V, double gam, double Wguess)
+// with S = m.B and v^2(W) = (m^2 + S^2 (2W + B^2)/W^2)/(W + B^2)^2 and
+// p(W) the EOS pressure of rho = D / gamma, w = W / gamma^2, kept inside a
+// bracket [lo, hi] (bisection when a step leaves it).  As v^2 B^2 >= (v.B)^2
+// and p <= k W (k = (Gamma - 1)/Gamma, or 1/4 for TM, whose p is at most
+// w/4), f >= (1 - k) W - D - E: the upper end (E + D)/(1 - k) has f >= 0.
+// Converged when |dW| <= 1e-14 W.
+template <bool TM> __device__ __forceinline__ int c2p_rmhd(const double *U, double *V, double gam, double Wguess)
 {
     const double D = U[RHO], E = U[ENG];
     const double m2 = U[MX1] * U[MX1] + U[MX2] * U[MX2] + U[MX3] * U[MX3];
     const double S = U[MX1] * U[BX1] + U[MX2] * U[BX2] + U[MX3] * U[BX3];
     const double B2 = U[BX1] * U[BX1] + U[BX2] * U[BX2] + U[BX3] * U[BX3];
     const double gfac = (gam - 1.0) / gam;
+    // p(rho, w) and its partial derivatives; TM: the root of
+    // 4p^2 - 5wp + w^2 - rho^2 = 0 with w - 5p/2 >= 0
+    auto pres = [&](double rho, double w, double &dpdw, double &dpdr) {
+        if constexpr (TM) {
+            const double s = sqrt(9.0 * w * w + 16.0 * rho * rho);
+            dpdw = 0.125 * (5.0 - 9.0 * w / s);
+            dpdr = -2.0 * rho / s;
+            return 0.125 * (5.0 * w - s);
+        } else {
+            dpdw = gfac;
+            dpdr = -gfac;
+            return gfac * (w - rho);
+        }
+    };
     V[BX1] = U[BX1];
     V[BX2] = U[BX2];
     V[BX3] = U[BX3];
     V[PSI] = U[PSI];
     int fl = 0;
     if (!(D > 0.0)) fl |= F_RHO;
-    double hi = gam * (E + D);
+    double hi = TM ? (4.0 / 3.0) * (E + D) : gam * (E + D);
     double lo = 0.0;
     double W = (Wguess > 0.0 && Wguess < hi) ? Wguess : hi;
     bool conv = false;
@@ -183,10 +216,12 @@ __device__ __forceinline__ int c2p_rmhd(const double *U, double *V, double gam, 
             df = 0.0;
         } else {
             double sq1 = sqrt(1.0 - v2);
-            double p = gfac * (W * (1.0 - v2) - D * sq1);
+            double dpdw, dpdr;
+            double p = pres(D * sq1, W * (1.0 - v2), dpdw, dpdr);
             f = W - p + 0.5 * B2 + 0.5 * (v2 * B2 - sw * sw) - D - E;
             double dv2 = -2.0 * sw * sw / (W * WB) - 2.0 * v2 * iWB;
-            double dp = gfac * ((1.0 - v2) + dv2 * (-W + 0.5 * D / sq1));
+            // w = W (1 - v^2), rho = D sqrt(1 - v^2)
+            double dp = dpdw * ((1.0 - v2) - W * dv2) + dpdr * (-0.5 * D * dv2 / sq1);
             df = 1.0 - dp + 0.5 * B2 * dv2 + sw * sw / W;
             if (f > 0.0) hi = W; else lo = W;
         }
@@ -199,7 +234,10 @@ __device__ __forceinline__ int c2p_rmhd(const double *U, double *V, double gam, 
     v2 = (m2 + sw * sw * (2.0 * W + B2)) / ((W + B2) * (W + B2));
     double sq1 = sqrt(1.0 - v2);
     V[RHO] = D * sq1;
-    V[PRS] = gfac * (W * (1.0 - v2) - D * sq1);
+    {
+        double dpdw, dpdr;
+        V[PRS] = pres(V[RHO], W * (1.0 - v2), dpdw, dpdr);
+    }
     double iWB = 1.0 / (W + B2);
     V[MX1] = (U[MX1] + sw * U[BX1]) * iWB;
     V[MX2] = (U[MX2] + sw * U[BX2]) * iWB;
@@ -212,13 +250,13 @@ __device__ __forceinline__ int c2p_rmhd(const double *U, double *V, double gam, 
     return fl;
 }
 
-template <int D, typename R> __device__ __forceinline__ void flux_rmhd(const R *V, const R *U, R *F, R gam)
+template <int D, bool TM, typename R> __device__ __forceinline__ void flux_rmhd(const R *V, const R *U, R *F, R gam)
 {
     constexpr int n = Ax<D>::n, t = Ax<D>::t, b = Ax<D>::b;
     R v2 = sq(V[MX1]) + sq(V[MX2]) + sq(V[MX3]);
     R B2 = sq(V[BX1]) + sq(V[BX2]) + sq(V[BX3]);
     R vB = V[MX1] * V[BX1] + V[MX2] * V[BX2] + V[MX3] * V[BX3];
-    R wl2 = (V[RHO] + gam * V[PRS] / (gam - R(1))) / (R(1) - v2);
+    R wl2 = rmhd_w<TM>(V[RHO], V[PRS], gam) / (R(1) - v2);
     // E = -v x B; E_n E_c terms and |E|^2 = v^2 B^2 - (v.B)^2
     R E0 = V[MX3] * V[BX2] - V[MX2] * V[BX3];
     R E1 = V[MX1] * V[BX3] - V[MX3] * V[BX1];
@@ -239,13 +277,13 @@ template <int D, typename R> __device__ __forceinline__ void flux_rmhd(const R *
 
 // outer characteristic speeds along D from the isotropic bound
 // a^2 = cs^2 + ca^2 - cs^2 ca^2 combined with v_n by relativistic addition
-template <int D, typename R> __device__ __forceinline__ void speeds_rmhd(const R *V, R gam, R &lmin, R &lmax)
+template <int D, bool TM, typename R> __device__ __forceinline__ void speeds_rmhd(const R *V, R gam, R &lmin, R &lmax)
 {
     R v2 = sq(V[MX1]) + sq(V[MX2]) + sq(V[MX3]);
     R B2 = sq(V[BX1]) + sq(V[BX2]) + sq(V[BX3]);
     R vB = V[MX1] * V[BX1] + V[MX2] * V[BX2] + V[MX3] * V[BX3];
-    R w = V[RHO] + gam * V[PRS] / (gam - R(1));
-    R cs2 = gam * V[PRS] / w;
+    R w = rmhd_w<TM>(V[RHO], V[PRS], gam);
+    R cs2 = rmhd_cs2<TM>(V[PRS], w, gam);
     R bb2 = B2 * (R(1) - v2) + vB * vB;
     R ca2 = bb2 / (w + bb2);
     R a2 = cs2 + ca2 - cs2 * ca2;
@@ -265,7 +303,7 @@ template <int D, typename R> __device__ __forceinline__ void speeds_rmhd(const R
 template <int PHYS, typename R> __device__ __forceinline__ void p2c(const R *V, R *U, R gam)
 {
     if constexpr (PHYS == PHYS_MHD) p2c_mhd(V, U, R(1) / (gam - R(1)));
-    else p2c_rmhd(V, U, gam);
+    else p2c_rmhd<PHYS == PHYS_RMHD_TM>(V, U, gam);
 }
 
 // conserved -> primitive; RMHD always inverts in FP64
@@ -277,7 +315,7 @@ template <int PHYS, typename R> __device__ __forceinline__ int c2p(const R *U, R
         double u[NV], v[NV];
 #pragma unroll
         for (int q = 0; q < NV; q++) u[q] = (double)U[q];
-        int f = c2p_rmhd(u, v, (double)gam, Wguess);
+        int f = c2p_rmhd<PHYS == PHYS_RMHD_TM>(u, v, (double)gam, Wguess);
 #pragma unroll
         for (int q = 0; q < NV; q++) V[q] = (R)v[q];
         return f;
@@ -290,7 +328,7 @@ __device__ __forceinline__ void phys_flux(const R *V, R *U, R *F, R gam, R ch, i
 {
     p2c<PHYS>(V, U, gam);
     if constexpr (PHYS == PHYS_MHD) flux_mhd<D>(V, U, F);
-    else flux_rmhd<D>(V, U, F, gam);
+    else flux_rmhd<D, PHYS == PHYS_RMHD_TM>(V, U, F, gam);
     if (glm) {
         F[BX1 + D] = V[PSI];
         F[PSI] = ch * ch * V[BX1 + D];
@@ -304,7 +342,7 @@ template <int D, int PHYS, typename R> __device__ __forceinline__ void wave_spee
         lm = V[MX1 + D] - cf;
         lp = V[MX1 + D] + cf;
     } else {
-        speeds_rmhd<D>(V, gam, lm, lp);
+        speeds_rmhd<D, PHYS == PHYS_RMHD_TM>(V, gam, lm, lp);
     }
 }
 
@@ -805,7 +843,7 @@ __device__ __forceinline__ int predict_mh(const R (*Vs)[NV], const R *U0, const 
         Vlo[q] = Vs[2][q] - R(0.5) * dV[q];
         Vhi[q] = Vs[2][q] + R(0.5) * dV[q];
     }
-    if constexpr (PHYS == PHYS_RMHD) {
+    if constexpr (PHYS != PHYS_MHD) {
         R v2l = sq(Vlo[MX1]) + sq(Vlo[MX2]) + sq(Vlo[MX3]);
         R v2h = sq(Vhi[MX1]) + sq(Vhi[MX2]) + sq(Vhi[MX3]);
         if (!(v2l < R(1)) || !(v2h < R(1))) {
@@ -824,7 +862,7 @@ __device__ __forceinline__ int predict_mh(const R (*Vs)[NV], const R *U0, const 
 #pragma unroll
     for (int q = 0; q < NV; q++) Us[q] = U0[q] - R(0.5) * dtdx * (Fhi[q] - Flo[q]);
     double Wg = 0.0;
-    if constexpr (PHYS == PHYS_RMHD) Wg = (double)(U0[ENG] + U0[RHO]);
+    if constexpr (PHYS != PHYS_MHD) Wg = (double)(U0[ENG] + U0[RHO]);
     int f2 = c2p<PHYS>(Us, Vh, gam, Wg);
     if (f2) {
         fl |= f2;

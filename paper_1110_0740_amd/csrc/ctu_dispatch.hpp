@@ -18,6 +18,7 @@ struct Combo {
 // supported (physics, predictor, reconstruction, solver) combinations
 __host__ inline bool combo_supported(const Combo &c)
 {
+    // c.phys: PHYS_MHD, PHYS_RMHD or PHYS_RMHD_TM (RMHD with the TM EOS)
     if (c.phys == PHYS_MHD) {
         if (c.pred == PRED_CHAR) return true;
         return c.rk == RK_LIN;
@@ -70,6 +71,10 @@ template <> inline hipError_t launch_sweep<double>(int D, const Combo &c, int nb
             if (c.rs == RS_RUSANOV) return sweep_one<D, PHYS_RMHD, PRED_MH, RK_LIN, RS_RUSANOV>(c, nb, a, s);     \
             return sweep_one<D, PHYS_RMHD, PRED_MH, RK_LIN, RS_HLL>(c, nb, a, s);                                 \
         }                                                                                                        \
+        if (c.phys == PHYS_RMHD_TM) {                                                                            \
+            if (c.rs == RS_RUSANOV) return sweep_one<D, PHYS_RMHD_TM, PRED_MH, RK_LIN, RS_RUSANOV>(c, nb, a, s);  \
+            return sweep_one<D, PHYS_RMHD_TM, PRED_MH, RK_LIN, RS_HLL>(c, nb, a, s);                              \
+        }                                                                                                        \
         if (c.pred == PRED_MH) {                                                                                 \
             if (c.rs == RS_HLLD) return sweep_one<D, PHYS_MHD, PRED_MH, RK_LIN, RS_HLLD>(c, nb, a, s);            \
             if (c.rs == RS_RUSANOV) return sweep_one<D, PHYS_MHD, PRED_MH, RK_LIN, RS_RUSANOV>(c, nb, a, s);      \
@@ -104,6 +109,10 @@ template <> inline hipError_t launch_sweep<double>(int D, const Combo &c, int nb
             hipLaunchKernelGGL((k_tcouple<DIM, PHYS_RMHD, RS_RUSANOV, 0, VAR_GENERIC, R>), dim3(nb), dim3(NT), 0, s, a); \
         else if (c.phys == PHYS_RMHD)                                                                            \
             hipLaunchKernelGGL((k_tcouple<DIM, PHYS_RMHD, RS_HLL, 0, VAR_GENERIC, R>), dim3(nb), dim3(NT), 0, s, a); \
+        else if (c.phys == PHYS_RMHD_TM && c.rs == RS_RUSANOV)                                                   \
+            hipLaunchKernelGGL((k_tcouple<DIM, PHYS_RMHD_TM, RS_RUSANOV, 0, VAR_GENERIC, R>), dim3(nb), dim3(NT), 0, s, a); \
+        else if (c.phys == PHYS_RMHD_TM)                                                                         \
+            hipLaunchKernelGGL((k_tcouple<DIM, PHYS_RMHD_TM, RS_HLL, 0, VAR_GENERIC, R>), dim3(nb), dim3(NT), 0, s, a); \
         else if (c.rs == RS_RUSANOV)                                                                             \
             hipLaunchKernelGGL((k_tcouple<DIM, PHYS_MHD, RS_RUSANOV, PAR, VAR_GENERIC, R>), dim3(nb), dim3(NT), 0, s, a); \
         else if (c.rs == RS_HLLD && a.flag)                                                                      \

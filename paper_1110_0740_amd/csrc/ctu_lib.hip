@@ -14,6 +14,7 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/ctu.h"
@@ -52,6 +53,14 @@ struct TileSet {
     KTile *d = nullptr;
     int n() const { return (int)h.size(); }
 };
+
+// call f(std::integral_constant<int, PHYS>) for a plan's physics module
+template <typename F> hipError_t with_phys(int phys, F &&f)
+{
+    if (phys == PHYS_MHD) return f(std::integral_constant<int, PHYS_MHD>{});
+    if (phys == PHYS_RMHD) return f(std::integral_constant<int, PHYS_RMHD>{});
+    return f(std::integral_constant<int, PHYS_RMHD_TM>{});
+}
 
 }  // namespace
 
@@ -287,12 +296,11 @@ ctu_status enqueue_step(ctu_plan *p, const void *U_in, void *U_out, const double
     const R gam = (R)p->opts.gamma;
     {
         StageTimer tm(p, 0, s);
-        if (p->combo.phys == PHYS_MHD)
-            hipLaunchKernelGGL((k_cons2prim<PHYS_MHD, R>), dim3(p->t_cells.n()), dim3(NT), 0, s, p->dboxes,
-                               p->t_cells.d, (const R *)U_in, (R *)p->wsV, (int *)fails, gam, 1);
-        else
-            hipLaunchKernelGGL((k_cons2prim<PHYS_RMHD, R>), dim3(p->t_cells.n()), dim3(NT), 0, s, p->dboxes,
-                               p->t_cells.d, (const R *)U_in, (R *)p->wsV, (int *)fails, gam, 1);
+        with_phys(p->combo.phys, [&](auto P) {
+            hipLaunchKernelGGL((k_cons2prim<decltype(P)::value, R>), dim3(p->t_cells.n()), dim3(NT), 0, s,
+                               p->dboxes, p->t_cells.d, (const R *)U_in, (R *)p->wsV, (int *)fails, gam, 1);
+            return hipGetLastError();
+        });
         if (p->wsFlag) {
             HIP_TRY(hipGetLastError());
             hipLaunchKernelGGL((k_shock_hll<R>), dim3(p->t_cells.n()), dim3(NT), 0, s, p->dboxes, p->t_cells.d,
@@ -437,13 +445,16 @@ ctu_status ctu_plan_create(const ctu_opts *opts, const ctu_box *boxes, int32_t n
     if (o.predictor != CTU_PRED_CHAR && o.predictor != CTU_PRED_MUSCL_HANCOCK) return fail(CTU_ERR_ARG, "bad predictor");
     if (o.wref < CTU_WREF_FACE || o.wref > CTU_WREF_CW84) return fail(CTU_ERR_ARG, "bad wref");
     if (o.riemann != CTU_HLLD && o.riemann != CTU_HLL && o.riemann != CTU_RUSANOV) return fail(CTU_ERR_ARG, "bad riemann");
+    if (o.eos != CTU_EOS_IDEAL && o.eos != CTU_EOS_TM) return fail(CTU_ERR_ARG, "bad eos");
+    if (o.eos == CTU_EOS_TM && o.physics != CTU_RMHD)
+        return fail(CTU_ERR_UNSUPPORTED, "the Taub-Matthews EOS belongs to the RMHD module");
     if (!(o.gamma > 1.0)) return fail(CTU_ERR_ARG, "gamma must exceed 1");
     for (int d = 0; d < o.dim; d++)
         if (!(o.dx[d] > 0.0)) return fail(CTU_ERR_ARG, "dx must be positive");
     if (o.parabolic_mask & ~7u) return fail(CTU_ERR_ARG, "unknown parabolic bits");
     if (!(o.shock_eps >= 0.0)) return fail(CTU_ERR_ARG, "shock_eps must be >= 0");
     Combo c;
-    c.phys = o.physics;
+    c.phys = (o.physics == CTU_RMHD && o.eos == CTU_EOS_TM) ? PHYS_RMHD_TM : o.physics;
     c.pred = o.predictor;
     c.rk = (o.recon == CTU_PPM) ? RK_PPM : (o.recon == CTU_WENO3 ? RK_WENO : RK_LIN);
     c.rs = o.riemann;
@@ -855,22 +866,16 @@ ctu_status ctu_cfl_rate(ctu_plan *plan, const void *U_dev, double *rate_dev, voi
     hipLaunchKernelGGL(k_reset<0>, dim3(1), dim3(64), 0, s, rate_dev, (double *)nullptr, (int *)nullptr);
     HIP_TRY(hipGetLastError());
     int nb = plan->t_cfl.n();
-    if (plan->esize == 4) {
-        if (plan->combo.phys == PHYS_MHD)
-            hipLaunchKernelGGL((k_cfl<PHYS_MHD, float>), dim3(nb), dim3(NT), 0, s, plan->dboxes, plan->t_cfl.d,
+    HIP_TRY(with_phys(plan->combo.phys, [&](auto P) {
+        constexpr int PH = decltype(P)::value;
+        if (plan->esize == 4)
+            hipLaunchKernelGGL((k_cfl<PH, float>), dim3(nb), dim3(NT), 0, s, plan->dboxes, plan->t_cfl.d,
                                (const float *)U_dev, rate_dev, plan->ko);
         else
-            hipLaunchKernelGGL((k_cfl<PHYS_RMHD, float>), dim3(nb), dim3(NT), 0, s, plan->dboxes, plan->t_cfl.d,
-                               (const float *)U_dev, rate_dev, plan->ko);
-    } else {
-        if (plan->combo.phys == PHYS_MHD)
-            hipLaunchKernelGGL((k_cfl<PHYS_MHD, double>), dim3(nb), dim3(NT), 0, s, plan->dboxes, plan->t_cfl.d,
+            hipLaunchKernelGGL((k_cfl<PH, double>), dim3(nb), dim3(NT), 0, s, plan->dboxes, plan->t_cfl.d,
                                (const double *)U_dev, rate_dev, plan->ko);
-        else
-            hipLaunchKernelGGL((k_cfl<PHYS_RMHD, double>), dim3(nb), dim3(NT), 0, s, plan->dboxes, plan->t_cfl.d,
-                               (const double *)U_dev, rate_dev, plan->ko);
-    }
-    HIP_TRY(hipGetLastError());
+        return hipGetLastError();
+    }));
     return CTU_OK;
 }
 
@@ -879,20 +884,16 @@ ctu_status ctu_prim_to_cons(ctu_plan *plan, const void *V_dev, void *U_dev, void
     if (!plan || !V_dev || !U_dev) return fail(CTU_ERR_ARG, "plan, V and U are required");
     hipStream_t s = (hipStream_t)stream;
     int nb = plan->t_cells.n();
-    bool f32 = plan->esize == 4, mhd = plan->combo.phys == PHYS_MHD;
-    if (f32 && mhd)
-        hipLaunchKernelGGL((k_prim2cons<PHYS_MHD, float>), dim3(nb), dim3(NT), 0, s, plan->dboxes, plan->t_cells.d,
-                           (const float *)V_dev, (float *)U_dev, (float)plan->opts.gamma);
-    else if (f32)
-        hipLaunchKernelGGL((k_prim2cons<PHYS_RMHD, float>), dim3(nb), dim3(NT), 0, s, plan->dboxes, plan->t_cells.d,
-                           (const float *)V_dev, (float *)U_dev, (float)plan->opts.gamma);
-    else if (mhd)
-        hipLaunchKernelGGL((k_prim2cons<PHYS_MHD, double>), dim3(nb), dim3(NT), 0, s, plan->dboxes, plan->t_cells.d,
-                           (const double *)V_dev, (double *)U_dev, plan->opts.gamma);
-    else
-        hipLaunchKernelGGL((k_prim2cons<PHYS_RMHD, double>), dim3(nb), dim3(NT), 0, s, plan->dboxes,
-                           plan->t_cells.d, (const double *)V_dev, (double *)U_dev, plan->opts.gamma);
-    HIP_TRY(hipGetLastError());
+    HIP_TRY(with_phys(plan->combo.phys, [&](auto P) {
+        constexpr int PH = decltype(P)::value;
+        if (plan->esize == 4)
+            hipLaunchKernelGGL((k_prim2cons<PH, float>), dim3(nb), dim3(NT), 0, s, plan->dboxes, plan->t_cells.d,
+                               (const float *)V_dev, (float *)U_dev, (float)plan->opts.gamma);
+        else
+            hipLaunchKernelGGL((k_prim2cons<PH, double>), dim3(nb), dim3(NT), 0, s, plan->dboxes, plan->t_cells.d,
+                               (const double *)V_dev, (double *)U_dev, plan->opts.gamma);
+        return hipGetLastError();
+    }));
     return CTU_OK;
 }
 
@@ -905,21 +906,16 @@ ctu_status ctu_cons_to_prim(ctu_plan *plan, const void *U_dev, void *V_dev, int3
         HIP_TRY(hipGetLastError());
     }
     int nb = plan->t_cells.n();
-    bool f32 = plan->esize == 4, mhd = plan->combo.phys == PHYS_MHD;
-    if (f32 && mhd)
-        hipLaunchKernelGGL((k_cons2prim<PHYS_MHD, float>), dim3(nb), dim3(NT), 0, s, plan->dboxes, plan->t_cells.d,
-                           (const float *)U_dev, (float *)V_dev, (int *)fails_dev, (float)plan->opts.gamma, 0);
-    else if (f32)
-        hipLaunchKernelGGL((k_cons2prim<PHYS_RMHD, float>), dim3(nb), dim3(NT), 0, s, plan->dboxes, plan->t_cells.d,
-                           (const float *)U_dev, (float *)V_dev, (int *)fails_dev, (float)plan->opts.gamma, 0);
-    else if (mhd)
-        hipLaunchKernelGGL((k_cons2prim<PHYS_MHD, double>), dim3(nb), dim3(NT), 0, s, plan->dboxes, plan->t_cells.d,
-                           (const double *)U_dev, (double *)V_dev, (int *)fails_dev, plan->opts.gamma, 0);
-    else
-        hipLaunchKernelGGL((k_cons2prim<PHYS_RMHD, double>), dim3(nb), dim3(NT), 0, s, plan->dboxes,
-                           plan->t_cells.d, (const double *)U_dev, (double *)V_dev, (int *)fails_dev,
-                           plan->opts.gamma, 0);
-    HIP_TRY(hipGetLastError());
+    HIP_TRY(with_phys(plan->combo.phys, [&](auto P) {
+        constexpr int PH = decltype(P)::value;
+        if (plan->esize == 4)
+            hipLaunchKernelGGL((k_cons2prim<PH, float>), dim3(nb), dim3(NT), 0, s, plan->dboxes, plan->t_cells.d,
+                               (const float *)U_dev, (float *)V_dev, (int *)fails_dev, (float)plan->opts.gamma, 0);
+        else
+            hipLaunchKernelGGL((k_cons2prim<PH, double>), dim3(nb), dim3(NT), 0, s, plan->dboxes, plan->t_cells.d,
+                               (const double *)U_dev, (double *)V_dev, (int *)fails_dev, plan->opts.gamma, 0);
+        return hipGetLastError();
+    }));
     return CTU_OK;
 }
 

@@ -19,6 +19,7 @@ RECON = {"lin_mc": 0, "lin_minmod": 1, "lin_vanleer": 2, "lin_vanalbada": 3, "pp
 PRED = {"char": 0, "mh": 1}
 WREF = {"face": 0, "cell": 1, "cw84": 2}
 RIEMANN = {"hlld": 0, "hll": 1, "rusanov": 2}
+EOS = {"ideal": 0, "tm": 1}
 PARAB_VISC, PARAB_RES, PARAB_TC = 1, 2, 4
 NFAIL = 5
 
@@ -45,6 +46,7 @@ class CtuOpts(C.Structure):
         ("nu", C.c_double), ("eta", C.c_double), ("kappa_par", C.c_double), ("kappa_perp", C.c_double),
         ("tc_phi", C.c_double), ("cool_beta", C.c_double), ("T_floor", C.c_double),
         ("hyperbolic_off", C.c_int32), ("pad", C.c_int32), ("shock_eps", C.c_double),
+        ("eos", C.c_int32), ("pad2", C.c_int32),
     ]
 
 
@@ -160,7 +162,7 @@ def _check(rc: int):
 def make_opts(dim=3, physics="mhd", precision="fp64", recon="ppm", predictor="char", wref="face", riemann="hlld",
               glm=True, gamma=5.0 / 3.0, dx=(1.0, 1.0, 1.0), glm_alpha=0.1, parabolic_mask=0, cooling=False,
               nu=0.0, eta=0.0, kappa_par=0.0, kappa_perp=0.0, tc_phi=0.0, cool_beta=0.5, T_floor=0.0,
-              hyperbolic_off=False, shock_eps=0.0) -> CtuOpts:
+              hyperbolic_off=False, shock_eps=0.0, eos="ideal") -> CtuOpts:
     o = CtuOpts()
     o.dim = dim
     o.physics = {"mhd": MHD, "rmhd": RMHD}[physics]
@@ -180,6 +182,7 @@ def make_opts(dim=3, physics="mhd", precision="fp64", recon="ppm", predictor="ch
     o.cool_beta, o.T_floor = cool_beta, T_floor
     o.hyperbolic_off = int(bool(hyperbolic_off))
     o.shock_eps = shock_eps
+    o.eos = EOS[eos]
     return o
 
 

@@ -58,6 +58,8 @@ def test_plan_creation_validates_options_without_gpu():
                  [((0, 0, 0), (8, 8, 8), 0, 0)], 4)
     with pytest.raises(ctu.CtuError, match="nghost"):
         ctu.Plan(ctu.make_opts(dim=3, recon="ppm"), [((0, 0, 0), (8, 8, 8), 0, 0)], 2)
+    with pytest.raises(ctu.CtuError, match="Taub"):
+        ctu.Plan(ctu.make_opts(dim=3, recon="ppm", eos="tm"), [((0, 0, 0), (8, 8, 8), 0, 0)], 4)
     with pytest.raises(ctu.CtuError, match="hybrid"):
         ctu.Plan(ctu.make_opts(dim=3, recon="ppm", riemann="rusanov", shock_eps=5.0), [((0, 0, 0), (8, 8, 8), 0, 0)],
                  4)
