@@ -306,6 +306,19 @@ template <int PHYS, typename R> __device__ __forceinline__ void p2c(const R *V, 
     else p2c_rmhd<PHYS == PHYS_RMHD_TM>(V, U, gam);
 }
 
+// W = w gamma^2 of a primitive RMHD state (FP64): the starting point of the
+// inversion of a nearby conserved state (0 for MHD, which needs none)
+template <int PHYS, typename R> __device__ __forceinline__ double w_guess(const R *V, R gam)
+{
+    if constexpr (PHYS == PHYS_MHD) {
+        return 0.0;
+    } else {
+        const double v2 = sq((double)V[MX1]) + sq((double)V[MX2]) + sq((double)V[MX3]);
+        const double w = rmhd_w<PHYS == PHYS_RMHD_TM>((double)V[RHO], (double)V[PRS], (double)gam);
+        return (v2 < 1.0) ? w / (1.0 - v2) : 0.0;
+    }
+}
+
 // conserved -> primitive; RMHD always inverts in FP64
 template <int PHYS, typename R> __device__ __forceinline__ int c2p(const R *U, R *V, R gam, double Wguess = 0.0)
 {
@@ -861,9 +874,8 @@ __device__ __forceinline__ int predict_mh(const R (*Vs)[NV], const R *U0, const 
     phys_flux<D, PHYS>(Vhi, Ut, Fhi, gam, ch, o.glm);
 #pragma unroll
     for (int q = 0; q < NV; q++) Us[q] = U0[q] - R(0.5) * dtdx * (Fhi[q] - Flo[q]);
-    double Wg = 0.0;
-    if constexpr (PHYS != PHYS_MHD) Wg = (double)(U0[ENG] + U0[RHO]);
-    int f2 = c2p<PHYS>(Us, Vh, gam, Wg);
+    // the half step starts the inversion from the cell's own W
+    int f2 = c2p<PHYS>(Us, Vh, gam, w_guess<PHYS>(Vs[2], gam));
     if (f2) {
         fl |= f2;
 #pragma unroll

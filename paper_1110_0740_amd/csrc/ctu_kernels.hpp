@@ -796,6 +796,7 @@ __global__ __launch_bounds__(NT, (sizeof(R) == 4 ? CTU_SWEEP_WAVES_F32 : CTU_SWE
 
         R Um[NV];
         int fl = 0;
+        double Wc = 0.0;  // RMHD: W of the item's cell, the start of the face-state inversions
         if (valid) {
             // ---- normal predictor (Sec. 3.2 / 3.3) ----
             R Vs[5][NV];
@@ -805,6 +806,7 @@ __global__ __launch_bounds__(NT, (sizeof(R) == 4 ? CTU_SWEEP_WAVES_F32 : CTU_SWE
 #pragma unroll
                 for (int q = 0; q < NV; q++) Vs[l][q] = bV.ld(q, c + (l - 2) * sD);
             R Vm[NV], Vp[NV];
+            Wc = w_guess<PHYS>(Vs[2], gam);
             // App. B: MinMod linear reconstruction near a flagged zone
             const bool mm = SHK && (fb[c] & FLAG_MINMOD);
             if (o.hyp_off) {
@@ -839,9 +841,8 @@ __global__ __launch_bounds__(NT, (sizeof(R) == 4 ? CTU_SWEEP_WAVES_F32 : CTU_SWE
             R UL[NV], VL[NV], VR[NV], F[NV];
 #pragma unroll
             for (int q = 0; q < NV; q++) UL[q] = (tid >= DEL) ? sP[q][tid - DEL] : cP[q][tid];
-            double Wg = 0.0;
-            int fL = c2p<PHYS>(UL, VL, gam, Wg);
-            int fR = c2p<PHYS>(Um, VR, gam, Wg);
+            int fL = c2p<PHYS>(UL, VL, gam, Wc);
+            int fR = c2p<PHYS>(Um, VR, gam, Wc);
             fl |= fL | fR;
             // rare fallback to the cell-centred states: reloaded, not kept live
             if (fL) {
