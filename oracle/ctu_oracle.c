@@ -64,6 +64,7 @@ typedef struct {
     int hyperbolic_off;
     double shock_eps; /* App. B shock detection threshold eps_q; 0 = off */
     int eos;          /* RMHD equation of state: EOS_IDEAL (Eq. gammaEos) or EOS_TM (Eq. TMEos) */
+    int exact_speeds; /* RMHD signal speeds: 0 = isotropic bound, 1 = fast roots of the quartic */
 } orc_opts;
 
 enum { EOS_IDEAL = 0, EOS_TM = 1 };
@@ -351,6 +352,32 @@ static void rmhd_speeds(const orc_opts *o, const double *V, int d, double *lmin,
     double root = sqrt(a2) * sqrt(disc);
     *lmin = (vn * (1.0 - a2) - root) / den;
     *lmax = (vn * (1.0 - a2) + root) / den;
+    if (!o->exact_speeds) return;
+    /* The exact fast magnetosonic speeds are the outermost roots of the
+     * lab-frame dispersion relation (a quartic in lambda)
+     *   g = w (1 - cs^2) A^4 - (w cs^2 + b^2) A^2 (1 - l^2) + cs^2 Bl^2 (1 - l^2)
+     * with A = gamma (v_d - l), Bl = b^d - l b^0, b^0 = gamma v.B,
+     * b^d = B_d / gamma + b^0 v_d.  Its four roots are real and the bounds
+     * above enclose them, so Newton from each bound moves monotonically
+     * inwards to the fast root. */
+    double lor = 1.0 / sqrt(1.0 - v2);
+    double b0 = lor * vB;
+    double bd = V[BX1 + d] / lor + b0 * vn;
+    double c4 = w * (1.0 - cs2), c2 = w * cs2 + bb2;
+    for (int side = 0; side < 2; side++) {
+        double l = side ? *lmax : *lmin;
+        for (int it = 0; it < 100; it++) {
+            double A = lor * (vn - l), Bl = bd - l * b0, G = 1.0 - l * l;
+            double g = c4 * A * A * A * A - c2 * A * A * G + cs2 * Bl * Bl * G;
+            double dg = -4.0 * lor * c4 * A * A * A - c2 * (-2.0 * lor * A * G - 2.0 * l * A * A) +
+                        cs2 * (-2.0 * b0 * Bl * G - 2.0 * l * Bl * Bl);
+            if (dg == 0.0) break;
+            double ln = l - g / dg;
+            if (fabs(ln - l) <= 1e-15 * fmax(fabs(l), 1e-300)) { l = ln; break; }
+            l = ln;
+        }
+        if (side) *lmax = l; else *lmin = l;
+    }
 }
 
 /* ------------------------------------------------------------------------ */
