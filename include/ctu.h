@@ -117,7 +117,11 @@ typedef struct {
                               on their faces; zones whose reconstruction stencil along
                               an axis reaches one use MinMod linear reconstruction */
     int32_t eos;           /* ctu_eos: RMHD equation of state (MHD: CTU_EOS_IDEAL only) */
-    int32_t pad2;
+    int32_t exact_speeds;  /* RMHD signal speeds of HLL / Rusanov and the CFL rate: 0 = the
+                              isotropic bound (a^2 = cs^2 + ca^2 - cs^2 ca^2 with relativistic
+                              velocity addition), 1 = the exact fast magnetosonic speeds (the
+                              outermost roots of the dispersion quartic); ignored for MHD,
+                              whose fast speeds are exact */
 } ctu_opts;
 
 /* One ghosted box: interior cells [lo, lo+n) in level-global indices.

@@ -27,6 +27,7 @@ enum { PB_VISC = 1, PB_RES = 2, PB_TC = 4 };
 // Options as seen by the kernels (by value in every launch).
 struct KOpts {
     int dim, limiter, wref, glm, parab, cooling, hyp_off, shock_r;  // shock_r: MinMod radius of App. B
+    int xspeeds, pad;  // RMHD: 1 = exact fast magnetosonic speeds, 0 = isotropic bound
     double gamma, glm_alpha, nu, eta, kpar, kperp, phi, cool_beta, T_floor, shock_eps;
 };
 
@@ -277,7 +278,8 @@ template <int D, bool TM, typename R> __device__ __forceinline__ void flux_rmhd(
 
 // outer characteristic speeds along D from the isotropic bound
 // a^2 = cs^2 + ca^2 - cs^2 ca^2 combined with v_n by relativistic addition
-template <int D, bool TM, typename R> __device__ __forceinline__ void speeds_rmhd(const R *V, R gam, R &lmin, R &lmax)
+template <int D, bool TM, typename R>
+__device__ __forceinline__ void speeds_rmhd(const R *V, R gam, R &lmin, R &lmax, int xs)
 {
     R v2 = sq(V[MX1]) + sq(V[MX2]) + sq(V[MX3]);
     R B2 = sq(V[BX1]) + sq(V[BX2]) + sq(V[BX3]);
@@ -294,6 +296,35 @@ template <int D, bool TM, typename R> __device__ __forceinline__ void speeds_rmh
     R root = sqrt(a2 * disc);
     lmin = (vn * (R(1) - a2) - root) * den;
     lmax = (vn * (R(1) - a2) + root) * den;
+    if (!xs) return;
+    // exact fast speeds: the outermost roots of the lab-frame dispersion
+    // quartic g = w (1 - cs^2) A^4 - (w cs^2 + b^2) A^2 (1 - l^2)
+    // + cs^2 Bl^2 (1 - l^2), A = gamma (v_n - l), Bl = b^n - l b^0; its four
+    // roots are real and enclosed by the bounds above, so Newton from each
+    // bound moves monotonically inwards to the fast root
+    const R lor = R(1) / sqrt(R(1) - v2);
+    const R b0 = lor * vB, bn = V[BX1 + D] / lor + b0 * vn;
+    const R c4 = w * (R(1) - cs2), c2 = w * cs2 + bb2;
+    const R tol = (sizeof(R) == 4) ? R(2e-7) : R(1e-15);
+    R ls[2] = { lmin, lmax };
+#pragma unroll
+    for (int side = 0; side < 2; side++) {
+        R l = ls[side];
+        for (int it = 0; it < 100; it++) {
+            const R A = lor * (vn - l), Bl = bn - l * b0, G = R(1) - l * l;
+            const R g = c4 * A * A * A * A - c2 * A * A * G + cs2 * Bl * Bl * G;
+            const R dg = -R(4) * lor * c4 * A * A * A - c2 * (-R(2) * lor * A * G - R(2) * l * A * A) +
+                         cs2 * (-R(2) * b0 * Bl * G - R(2) * l * Bl * Bl);
+            if (dg == R(0)) break;
+            const R ln = l - g / dg;
+            const bool done = fabs(ln - l) <= tol * fmax(fabs(l), R(1e-30));
+            l = ln;
+            if (done) break;
+        }
+        ls[side] = l;
+    }
+    lmin = ls[0];
+    lmax = ls[1];
 }
 
 // ---------------------------------------------------------------------------
@@ -348,14 +379,15 @@ __device__ __forceinline__ void phys_flux(const R *V, R *U, R *F, R gam, R ch, i
     }
 }
 
-template <int D, int PHYS, typename R> __device__ __forceinline__ void wave_speeds(const R *V, R gam, R &lm, R &lp)
+template <int D, int PHYS, typename R>
+__device__ __forceinline__ void wave_speeds(const R *V, R gam, R &lm, R &lp, int xs = 0)
 {
     if constexpr (PHYS == PHYS_MHD) {
         R cf = cfast_mhd<D>(V, gam);
         lm = V[MX1 + D] - cf;
         lp = V[MX1 + D] + cf;
     } else {
-        speeds_rmhd<D, PHYS == PHYS_RMHD_TM>(V, gam, lm, lp);
+        speeds_rmhd<D, PHYS == PHYS_RMHD_TM>(V, gam, lm, lp, xs);
     }
 }
 
@@ -364,11 +396,11 @@ template <int D, int PHYS, typename R> __device__ __forceinline__ void wave_spee
 // ---------------------------------------------------------------------------
 
 template <int D, int PHYS, typename R>
-__device__ __forceinline__ void hll(const R *VL, const R *VR, R *F, R &smax, R gam, R ch, int glm)
+__device__ __forceinline__ void hll(const R *VL, const R *VR, R *F, R &smax, R gam, R ch, int glm, int xs)
 {
     R lmL, lpL, lmR, lpR;
-    wave_speeds<D, PHYS>(VL, gam, lmL, lpL);
-    wave_speeds<D, PHYS>(VR, gam, lmR, lpR);
+    wave_speeds<D, PHYS>(VL, gam, lmL, lpL, xs);
+    wave_speeds<D, PHYS>(VR, gam, lmR, lpR, xs);
     R SL = fmin(lmL, lmR), SR = fmax(lpL, lpR);
     smax = fmax(fabs(SL), fabs(SR));
     R UL[NV], UR[NV], FL[NV], FR[NV];
@@ -387,11 +419,11 @@ __device__ __forceinline__ void hll(const R *VL, const R *VR, R *F, R &smax, R g
 // centred flux minus a (U_R - U_L)/2, a the largest signal speed magnitude
 // of the two states (the HLL bounds' max(|S_L|, |S_R|))
 template <int D, int PHYS, typename R>
-__device__ __forceinline__ void rusanov(const R *VL, const R *VR, R *F, R &smax, R gam, R ch, int glm)
+__device__ __forceinline__ void rusanov(const R *VL, const R *VR, R *F, R &smax, R gam, R ch, int glm, int xs)
 {
     R lmL, lpL, lmR, lpR;
-    wave_speeds<D, PHYS>(VL, gam, lmL, lpL);
-    wave_speeds<D, PHYS>(VR, gam, lmR, lpR);
+    wave_speeds<D, PHYS>(VL, gam, lmL, lpL, xs);
+    wave_speeds<D, PHYS>(VR, gam, lmR, lpR, xs);
     const R a = fmax(fmax(fabs(lmL), fabs(lpL)), fmax(fabs(lmR), fabs(lpR)));
     smax = a;
     R UL[NV], UR[NV], FL[NV], FR[NV];
@@ -517,7 +549,7 @@ __device__ __forceinline__ void hlld(const R *VL, const R *VR, R *F, R &smax, R 
 // right), then HLLD / HLL on the states with the common B_n.  VL, VR are
 // modified in place (their B_n is replaced).
 template <int D, int PHYS, int RS, typename R>
-__device__ __forceinline__ void riemann(R *VL, R *VR, R *F, R &smax, R gam, R ch, int glm)
+__device__ __forceinline__ void riemann(R *VL, R *VR, R *F, R &smax, R gam, R ch, int glm, int xs = 0)
 {
     R Bm, psim;
     if (glm) {
@@ -531,8 +563,8 @@ __device__ __forceinline__ void riemann(R *VL, R *VR, R *F, R &smax, R gam, R ch
     VL[BX1 + D] = Bm;
     VR[BX1 + D] = Bm;
     if constexpr (RS == RS_HLLD && PHYS == PHYS_MHD) hlld<D>(VL, VR, F, smax, gam, ch, glm);
-    else if constexpr (RS == RS_RUSANOV) rusanov<D, PHYS>(VL, VR, F, smax, gam, ch, glm);
-    else hll<D, PHYS>(VL, VR, F, smax, gam, ch, glm);
+    else if constexpr (RS == RS_RUSANOV) rusanov<D, PHYS>(VL, VR, F, smax, gam, ch, glm, xs);
+    else hll<D, PHYS>(VL, VR, F, smax, gam, ch, glm, xs);
     F[BX1 + D] = glm ? psim : R(0);
     F[PSI] = glm ? ch * ch * Bm : R(0);
 }

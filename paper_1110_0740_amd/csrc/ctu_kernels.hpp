@@ -455,8 +455,8 @@ __device__ __forceinline__ void tface_s(const R *VL_in, const R *VR_in, const R 
     R pL = VL[PRS], pR = VR[PRS], rL = VL[RHO], rR = VR[RHO];
     if (!o.hyp_off) {
         R sm;
-        if (SHK && hl) riemann<D, PHYS, RS_HLL>(VL, VR, G, sm, gam, ch, o.glm);
-        else riemann<D, PHYS, RS>(VL, VR, G, sm, gam, ch, o.glm);
+        if (SHK && hl) riemann<D, PHYS, RS_HLL>(VL, VR, G, sm, gam, ch, o.glm, o.xspeeds);
+        else riemann<D, PHYS, RS>(VL, VR, G, sm, gam, ch, o.glm, o.xspeeds);
     } else {
 #pragma unroll
         for (int q = 0; q < NV; q++) G[q] = R(0);
@@ -857,8 +857,9 @@ __global__ __launch_bounds__(NT, (sizeof(R) == 4 ? CTU_SWEEP_WAVES_F32 : CTU_SWE
             R smax = R(0);
             if (!o.hyp_off) {
                 // App. B: HLL on the faces of a flagged zone
-                if (SHK && ((fb[c - sD] | fb[c]) & FLAG_HLL)) riemann<D, PHYS, RS_HLL>(VL, VR, F, smax, gam, ch, o.glm);
-                else riemann<D, PHYS, RS>(VL, VR, F, smax, gam, ch, o.glm);
+                if (SHK && ((fb[c - sD] | fb[c]) & FLAG_HLL))
+                    riemann<D, PHYS, RS_HLL>(VL, VR, F, smax, gam, ch, o.glm, o.xspeeds);
+                else riemann<D, PHYS, RS>(VL, VR, F, smax, gam, ch, o.glm, o.xspeeds);
             } else {
 #pragma unroll
                 for (int q = 0; q < NV; q++) F[q] = R(0);
@@ -997,12 +998,12 @@ __global__ __launch_bounds__(NT) void k_cfl(const KBox *boxes, const KTile *tile
         R gam = R(o.gamma);
         c2p<PHYS>(u, v, gam);
         R lm, lp;
-        wave_speeds<0, PHYS>(v, gam, lm, lp);
+        wave_speeds<0, PHYS>(v, gam, lm, lp, o.xspeeds);
         r = fmax(r, (double)fmax(fabs(lm), fabs(lp)) / bx.dx[0]);
-        wave_speeds<1, PHYS>(v, gam, lm, lp);
+        wave_speeds<1, PHYS>(v, gam, lm, lp, o.xspeeds);
         r = fmax(r, (double)fmax(fabs(lm), fabs(lp)) / bx.dx[1]);
         if (o.dim == 3) {
-            wave_speeds<2, PHYS>(v, gam, lm, lp);
+            wave_speeds<2, PHYS>(v, gam, lm, lp, o.xspeeds);
             r = fmax(r, (double)fmax(fabs(lm), fabs(lp)) / bx.dx[2]);
         }
         if (o.parab) {

@@ -446,6 +446,7 @@ ctu_status ctu_plan_create(const ctu_opts *opts, const ctu_box *boxes, int32_t n
     if (o.wref < CTU_WREF_FACE || o.wref > CTU_WREF_CW84) return fail(CTU_ERR_ARG, "bad wref");
     if (o.riemann != CTU_HLLD && o.riemann != CTU_HLL && o.riemann != CTU_RUSANOV) return fail(CTU_ERR_ARG, "bad riemann");
     if (o.eos != CTU_EOS_IDEAL && o.eos != CTU_EOS_TM) return fail(CTU_ERR_ARG, "bad eos");
+    if (o.exact_speeds != 0 && o.exact_speeds != 1) return fail(CTU_ERR_ARG, "exact_speeds must be 0 or 1");
     if (o.eos == CTU_EOS_TM && o.physics != CTU_RMHD)
         return fail(CTU_ERR_UNSUPPORTED, "the Taub-Matthews EOS belongs to the RMHD module");
     if (!(o.gamma > 1.0)) return fail(CTU_ERR_ARG, "gamma must exceed 1");
@@ -489,6 +490,8 @@ ctu_status ctu_plan_create(const ctu_opts *opts, const ctu_box *boxes, int32_t n
     k.cooling = o.cooling ? 1 : 0;
     k.hyp_off = o.hyperbolic_off ? 1 : 0;
     k.shock_r = (o.recon == CTU_PPM) ? 2 : 1;
+    k.xspeeds = (o.physics == CTU_RMHD && o.exact_speeds) ? 1 : 0;
+    k.pad = 0;
     k.shock_eps = o.shock_eps;
     k.gamma = o.gamma;
     k.glm_alpha = o.glm_alpha;
