@@ -77,6 +77,8 @@ def parse():
     ap.add_argument("--no-amr", action="store_true", help="skip the AMR batch leg")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default launch shapes instead of tuning the FP32 plans first")
+    ap.add_argument("--only-amr", action="store_true",
+                    help="run the AMR batch leg alone and print it (profiling aid; not the bench line)")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the shock-hybrid and Rusanov variants of the FP32 step")
     ap.add_argument("--shape", default=None,
@@ -289,8 +291,8 @@ def main():
         copy_calibration()
         return
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU decomposition is "
-              f"described in DESIGN.md but not built.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): this build has no multi-GPU path "
+              f"(boxes would shard by zone count with one halo exchange per substep; not built).", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -301,6 +303,11 @@ def main():
     dev = torch.device("cuda:0")
     n, ng = args.n, 4
     K, W = args.steps, args.warmup
+    if args.only_amr:
+        # the AMR batch leg alone (for profiling its kernels); not the bench line
+        print(json.dumps({"amr": amr_leg(max(3, K // 2), min(W, 2), dev, torch.cuda.Stream(),
+                                         tune=not args.no_autotune)}), flush=True)
+        return
     print(f"[bench] generating {n}^3 inputs on the GPU", file=sys.stderr, flush=True)
     V64, meta = I.mhd3d_fields_torch(n=n, ng=ng, seed=2000, device=dev)
     dx, gamma = meta["dx"], meta["gamma"]
