@@ -44,7 +44,7 @@ enum { REC_LIN_MC = 0, REC_LIN_MINMOD = 1, REC_LIN_VANLEER = 2, REC_LIN_VANALBAD
        REC_PPM = 4, REC_WENO3 = 5 };
 enum { PRED_CHAR = 0, PRED_MH = 1 };
 enum { WREF_FACE = 0, WREF_CELL = 1, WREF_CW84 = 2 };
-enum { RS_HLLD = 0, RS_HLL = 1, RS_RUSANOV = 2 };
+enum { RS_HLLD = 0, RS_HLL = 1, RS_RUSANOV = 2, RS_HLLC = 3 };
 enum { FAIL_RHO = 0, FAIL_PRS = 1, FAIL_NEWTON = 2, FAIL_VEL = 3, FAIL_NAN = 4, NFAIL = 5 };
 
 #define PARAB_VISC 1u
@@ -467,6 +467,64 @@ static void riemann_rusanov(const orc_opts *o, const double *VL, const double *V
     for (int v = 0; v < NVAR; v++) F[v] = 0.5 * (FL[v] + FR[v]) - 0.5 * a * (UR[v] - UL[v]);
 }
 
+/* HLLC for ideal MHD (Sec. 3.1's list; the single-contact construction of
+ * Li 2005), for states sharing B_n.  The outer speeds are HLL's; the contact
+ * moves with the HLL average of the normal velocity, S_M = m_n^hll /
+ * rho^hll; both star states carry the HLL average B* of the transverse
+ * field, and v*.B* is taken from the HLL state.  The rest follows from the
+ * jump conditions across the outer wave S of each side:
+ *   rho*      = rho (S - u) / (S - S_M),
+ *   p_t*      = p_t + rho (S - u)(S_M - u),
+ *   (rho v_t)* = (rho v_t (S - u) - B_n (B_t* - B_t)) / (S - S_M),
+ *   E*        = ((S - u) E - p_t u + p_t* S_M + B_n (v.B - v*.B*)) / (S - S_M),
+ * and F* = F + S (U* - U) on the side holding the interface.  With B = 0 it
+ * is the hydrodynamic HLLC of Toro, Spruce & Speares. */
+static void riemann_hllc(const orc_opts *o, const double *VL, const double *VR, int d, double ch,
+                         double *F, double *smax)
+{
+    int n, t, b;
+    dir_axes(d, &n, &t, &b);
+    double cfL = mhd_fast_speed(o, VL, d), cfR = mhd_fast_speed(o, VR, d);
+    double uL = VL[MX1 + n], uR = VR[MX1 + n];
+    double SL = fmin(uL - cfL, uR - cfR);
+    double SR = fmax(uL + cfL, uR + cfR);
+    *smax = fmax(fabs(SL), fabs(SR));
+    double UL[NVAR], UR[NVAR], FL[NVAR], FR[NVAR];
+    prim2cons(o, VL, UL);
+    prim2cons(o, VR, UR);
+    phys_flux(o, VL, d, ch, FL);
+    phys_flux(o, VR, d, ch, FR);
+    if (SL >= 0.0) { memcpy(F, FL, sizeof(FL)); return; }
+    if (SR <= 0.0) { memcpy(F, FR, sizeof(FR)); return; }
+    double Uh[NVAR];
+    for (int v = 0; v < NVAR; v++) Uh[v] = (SR * UR[v] - SL * UL[v] - (FR[v] - FL[v])) / (SR - SL);
+    double SM = Uh[MX1 + n] / Uh[RHO];
+    double vt = Uh[MX1 + t] / Uh[RHO], vb = Uh[MX1 + b] / Uh[RHO];
+    double Bn = VL[BX1 + n], Bt = Uh[BX1 + t], Bb = Uh[BX1 + b];
+    double vBs = SM * Bn + vt * Bt + vb * Bb;
+    const double *V = (SM >= 0.0) ? VL : VR;
+    const double *U = (SM >= 0.0) ? UL : UR;
+    const double *Fs = (SM >= 0.0) ? FL : FR;
+    double S = (SM >= 0.0) ? SL : SR;
+    double u = V[MX1 + n];
+    double B2 = V[BX1] * V[BX1] + V[BX2] * V[BX2] + V[BX3] * V[BX3];
+    double pt = V[PRS] + 0.5 * B2;
+    double vB = V[MX1] * V[BX1] + V[MX2] * V[BX2] + V[MX3] * V[BX3];
+    double rs = V[RHO] * (S - u) / (S - SM);
+    double pts = pt + V[RHO] * (S - u) * (SM - u);
+    double Us[NVAR];
+    Us[RHO] = rs;
+    Us[MX1 + n] = rs * SM;
+    Us[MX1 + t] = (U[MX1 + t] * (S - u) - Bn * (Bt - V[BX1 + t])) / (S - SM);
+    Us[MX1 + b] = (U[MX1 + b] * (S - u) - Bn * (Bb - V[BX1 + b])) / (S - SM);
+    Us[ENG] = ((S - u) * U[ENG] - pt * u + pts * SM + Bn * (vB - vBs)) / (S - SM);
+    Us[BX1 + n] = Bn;
+    Us[BX1 + t] = Bt;
+    Us[BX1 + b] = Bb;
+    Us[PSI] = U[PSI];
+    for (int v = 0; v < NVAR; v++) F[v] = Fs[v] + S * (Us[v] - U[v]);
+}
+
 /* HLLD for ideal MHD (Miyoshi & Kusano 2005), for states sharing B_n. */
 static void riemann_hlld(const orc_opts *o, const double *VL, const double *VR, int d, double ch,
                          double *F, double *smax)
@@ -598,6 +656,8 @@ static void riemann(const orc_opts *o, const double *VLin, const double *VRin, i
     VL[BX1 + d] = VR[BX1 + d] = Bm;
     if (o->riemann == RS_HLLD && o->physics == PHYS_MHD)
         riemann_hlld(o, VL, VR, d, ch, F, smax);
+    else if (o->riemann == RS_HLLC && o->physics == PHYS_MHD)
+        riemann_hllc(o, VL, VR, d, ch, F, smax);
     else if (o->riemann == RS_RUSANOV)
         riemann_rusanov(o, VL, VR, d, ch, F, smax);
     else
