@@ -20,7 +20,7 @@ enum { RK_LIN = 0, RK_PPM = 1, RK_WENO = 2 };            // reconstruction kinds
 enum { LIM_MC = 0, LIM_MINMOD = 1, LIM_VANLEER = 2, LIM_VANALBADA = 3 };
 enum { PRED_CHAR = 0, PRED_MH = 1 };
 enum { WREF_FACE = 0, WREF_CELL = 1, WREF_CW84 = 2 };
-enum { RS_HLLD = 0, RS_HLL = 1, RS_RUSANOV = 2 };
+enum { RS_HLLD = 0, RS_HLL = 1, RS_RUSANOV = 2, RS_HLLC = 3 };
 enum { F_RHO = 1, F_PRS = 2, F_INV = 4, F_VEL = 8, F_NAN = 16 };  // failure bits
 enum { PB_VISC = 1, PB_RES = 2, PB_TC = 4 };
 
@@ -392,7 +392,7 @@ __device__ __forceinline__ void wave_speeds(const R *V, R gam, R &lm, R &lp, int
 }
 
 // ---------------------------------------------------------------------------
-// Riemann solvers (Sec. 3.1: HLL, HLLD) with the GLM interface subsystem
+// Riemann solvers (Sec. 3.1: HLL, Rusanov, HLLC, HLLD) with the GLM interface subsystem
 // ---------------------------------------------------------------------------
 
 template <int D, int PHYS, typename R>
@@ -544,9 +544,73 @@ __device__ __forceinline__ void hlld(const R *VL, const R *VR, R *F, R &smax, R 
     }
 }
 
+// HLLC for MHD (Sec. 3.1 lists it for both modules), the single-contact
+// solver of Li 2005 for states sharing the normal field.  HLL outer speeds;
+// the contact moves with the HLL-averaged normal velocity S_M; both star
+// states hold the HLL-averaged transverse field B*, and v*.B* is the HLL
+// state's.  On the side k that holds the interface the jump conditions
+// across its outer wave S give
+//   rho* = rho (S - u)/(S - S_M),       p_t* = p_t + rho (S - u)(S_M - u),
+//   (rho v_t)* = (rho v_t (S - u) - B_n (B_t* - B_t))/(S - S_M),
+//   E* = ((S - u) E - p_t u + p_t* S_M + B_n (v.B - v*.B*))/(S - S_M),
+// and the flux is F_k + S (U* - U_k).  As in HLLD only side k's star state
+// is formed and every region is chosen by selects (no divergent branches);
+// star quantities of a region not chosen may be non-finite.
+template <int D, typename R>
+__device__ __forceinline__ void hllc(const R *VL, const R *VR, R *F, R &smax, R gam, R ch, int glm)
+{
+    constexpr int n = Ax<D>::n, t = Ax<D>::t, b = Ax<D>::b;
+    R cfL = cfast_mhd<D>(VL, gam), cfR = cfast_mhd<D>(VR, gam);
+    R uL = VL[MX1 + n], uR = VR[MX1 + n];
+    R SL = fmin(uL - cfL, uR - cfR);
+    R SR = fmax(uL + cfL, uR + cfR);
+    smax = fmax(fabs(SL), fabs(SR));
+    R UL[NV], UR[NV], FL[NV], FR[NV];
+    phys_flux<D, PHYS_MHD>(VL, UL, FL, gam, ch, glm);
+    phys_flux<D, PHYS_MHD>(VR, UR, FR, gam, ch, glm);
+    // HLL averages (S_R U_R - S_L U_L - (F_R - F_L)) / (S_R - S_L)
+    const R id = R(1) / (SR - SL);
+    auto hav = [&](int q) { return (SR * UR[q] - SL * UL[q] - (FR[q] - FL[q])) * id; };
+    const R irh = R(1) / hav(RHO);
+    const R SM = hav(MX1 + n) * irh;
+    const R vth = hav(MX1 + t) * irh, vbh = hav(MX1 + b) * irh;
+    const R Bth = hav(BX1 + t), Bbh = hav(BX1 + b);
+    const R Bn = VL[BX1 + n];
+    const R vBs = SM * Bn + vth * Bth + vbh * Bbh;
+
+    const bool outerL = SL >= R(0), outerR = SR <= R(0);
+    const bool outer = outerL || outerR;
+    const bool k = outerL ? false : (outerR ? true : !(SM >= R(0)));
+    R Vk[NV], Uk[NV], Fk[NV];
+#pragma unroll
+    for (int q = 0; q < NV; q++) {
+        Vk[q] = k ? VR[q] : VL[q];
+        Uk[q] = k ? UR[q] : UL[q];
+        Fk[q] = k ? FR[q] : FL[q];
+    }
+    const R S = k ? SR : SL;
+    const R u = Vk[MX1 + n], rho = Vk[RHO];
+    const R Su = S - u, iSSM = R(1) / (S - SM);
+    const R pt = Vk[PRS] + R(0.5) * (sq(Vk[BX1]) + sq(Vk[BX2]) + sq(Vk[BX3]));
+    const R pts = pt + rho * Su * (SM - u);
+    const R vB = Vk[MX1] * Vk[BX1] + Vk[MX2] * Vk[BX2] + Vk[MX3] * Vk[BX3];
+    R Us[NV];
+    Us[RHO] = rho * Su * iSSM;
+    Us[MX1 + n] = Us[RHO] * SM;
+    Us[MX1 + t] = (Uk[MX1 + t] * Su - Bn * (Bth - Vk[BX1 + t])) * iSSM;
+    Us[MX1 + b] = (Uk[MX1 + b] * Su - Bn * (Bbh - Vk[BX1 + b])) * iSSM;
+    Us[ENG] = (Su * Uk[ENG] - pt * u + pts * SM + Bn * (vB - vBs)) * iSSM;
+    Us[BX1 + n] = Bn;
+    Us[BX1 + t] = Bth;
+    Us[BX1 + b] = Bbh;
+    Us[PSI] = Uk[PSI];
+#pragma unroll
+    for (int q = 0; q < NV; q++) F[q] = outer ? Fk[q] : Fk[q] + S * (Us[q] - Uk[q]);
+}
+
 // Interface solve: exact solution of the linear (B_n, psi) subsystem of
 // Eq. glm2x2 (psi + c_h B_n carried from the left, psi - c_h B_n from the
-// right), then HLLD / HLL on the states with the common B_n.  VL, VR are
+// right), then the chosen solver on the states with the common B_n.  VL, VR are
 // modified in place (their B_n is replaced).
 template <int D, int PHYS, int RS, typename R>
 __device__ __forceinline__ void riemann(R *VL, R *VR, R *F, R &smax, R gam, R ch, int glm, int xs = 0)
@@ -563,6 +627,7 @@ __device__ __forceinline__ void riemann(R *VL, R *VR, R *F, R &smax, R gam, R ch
     VL[BX1 + D] = Bm;
     VR[BX1 + D] = Bm;
     if constexpr (RS == RS_HLLD && PHYS == PHYS_MHD) hlld<D>(VL, VR, F, smax, gam, ch, glm);
+    else if constexpr (RS == RS_HLLC && PHYS == PHYS_MHD) hllc<D>(VL, VR, F, smax, gam, ch, glm);
     else if constexpr (RS == RS_RUSANOV) rusanov<D, PHYS>(VL, VR, F, smax, gam, ch, glm, xs);
     else hll<D, PHYS>(VL, VR, F, smax, gam, ch, glm, xs);
     F[BX1 + D] = glm ? psim : R(0);

@@ -55,8 +55,8 @@ template <> inline hipError_t launch_sweep<double>(int D, const Combo &c, int nb
     template <int D, int PHYS, int PRED, int RK, int RS>                                                         \
     static hipError_t sweep_one(const Combo &c, int nb, const SweepArgs<R> &a, hipStream_t s)                   \
     {                                                                                                            \
-        /* Rusanov runs the generic variant only (no hybrid flags, no fixed set) */                              \
-        if constexpr (RS == RS_RUSANOV) {                                                                        \
+        /* Rusanov and HLLC run the generic variant only (no hybrid flags, no fixed set) */                      \
+        if constexpr (RS == RS_RUSANOV || RS == RS_HLLC) {                                                       \
             return sweep_one2<D, PHYS, PRED, RK, RS, VAR_GENERIC>(nb, a, s);                                     \
         } else {                                                                                                 \
             if (a.flag) return sweep_one2<D, PHYS, PRED, RK, RS, VAR_SHOCK>(nb, a, s);                           \
@@ -78,20 +78,24 @@ template <> inline hipError_t launch_sweep<double>(int D, const Combo &c, int nb
         if (c.pred == PRED_MH) {                                                                                 \
             if (c.rs == RS_HLLD) return sweep_one<D, PHYS_MHD, PRED_MH, RK_LIN, RS_HLLD>(c, nb, a, s);            \
             if (c.rs == RS_RUSANOV) return sweep_one<D, PHYS_MHD, PRED_MH, RK_LIN, RS_RUSANOV>(c, nb, a, s);      \
+            if (c.rs == RS_HLLC) return sweep_one<D, PHYS_MHD, PRED_MH, RK_LIN, RS_HLLC>(c, nb, a, s);            \
             return sweep_one<D, PHYS_MHD, PRED_MH, RK_LIN, RS_HLL>(c, nb, a, s);                                  \
         }                                                                                                        \
         if (c.rk == RK_PPM) {                                                                                    \
             if (c.rs == RS_HLLD) return sweep_one<D, PHYS_MHD, PRED_CHAR, RK_PPM, RS_HLLD>(c, nb, a, s);          \
             if (c.rs == RS_RUSANOV) return sweep_one<D, PHYS_MHD, PRED_CHAR, RK_PPM, RS_RUSANOV>(c, nb, a, s);    \
+            if (c.rs == RS_HLLC) return sweep_one<D, PHYS_MHD, PRED_CHAR, RK_PPM, RS_HLLC>(c, nb, a, s);          \
             return sweep_one<D, PHYS_MHD, PRED_CHAR, RK_PPM, RS_HLL>(c, nb, a, s);                                \
         }                                                                                                        \
         if (c.rk == RK_WENO) {                                                                                   \
             if (c.rs == RS_HLLD) return sweep_one<D, PHYS_MHD, PRED_CHAR, RK_WENO, RS_HLLD>(c, nb, a, s);         \
             if (c.rs == RS_RUSANOV) return sweep_one<D, PHYS_MHD, PRED_CHAR, RK_WENO, RS_RUSANOV>(c, nb, a, s);   \
+            if (c.rs == RS_HLLC) return sweep_one<D, PHYS_MHD, PRED_CHAR, RK_WENO, RS_HLLC>(c, nb, a, s);         \
             return sweep_one<D, PHYS_MHD, PRED_CHAR, RK_WENO, RS_HLL>(c, nb, a, s);                               \
         }                                                                                                        \
         if (c.rs == RS_HLLD) return sweep_one<D, PHYS_MHD, PRED_CHAR, RK_LIN, RS_HLLD>(c, nb, a, s);              \
         if (c.rs == RS_RUSANOV) return sweep_one<D, PHYS_MHD, PRED_CHAR, RK_LIN, RS_RUSANOV>(c, nb, a, s);        \
+        if (c.rs == RS_HLLC) return sweep_one<D, PHYS_MHD, PRED_CHAR, RK_LIN, RS_HLLC>(c, nb, a, s);              \
         return sweep_one<D, PHYS_MHD, PRED_CHAR, RK_LIN, RS_HLL>(c, nb, a, s);                                    \
     }                                                                                                            \
     hipError_t launch_sweep_##SUFFIX(int D, const Combo &c, int nb, const SweepArgs<R> &a, hipStream_t s)      \
@@ -115,6 +119,8 @@ template <> inline hipError_t launch_sweep<double>(int D, const Combo &c, int nb
             hipLaunchKernelGGL((k_tcouple<DIM, PHYS_RMHD_TM, RS_HLL, 0, VAR_GENERIC, R>), dim3(nb), dim3(NT), 0, s, a); \
         else if (c.rs == RS_RUSANOV)                                                                             \
             hipLaunchKernelGGL((k_tcouple<DIM, PHYS_MHD, RS_RUSANOV, PAR, VAR_GENERIC, R>), dim3(nb), dim3(NT), 0, s, a); \
+        else if (c.rs == RS_HLLC)                                                                                \
+            hipLaunchKernelGGL((k_tcouple<DIM, PHYS_MHD, RS_HLLC, PAR, VAR_GENERIC, R>), dim3(nb), dim3(NT), 0, s, a); \
         else if (c.rs == RS_HLLD && a.flag)                                                                      \
             hipLaunchKernelGGL((k_tcouple<DIM, PHYS_MHD, RS_HLLD, PAR, VAR_SHOCK, R>), dim3(nb), dim3(NT), 0, s, a); \
         else if (c.fast && c.rs == RS_HLLD)                                                                      \

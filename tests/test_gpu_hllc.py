@@ -1,0 +1,37 @@
+"""GPU parity of the HLLC solver for MHD through the C ABI, against the
+oracle: PPM characteristic tracing on a ragged box (t^n and time-centred
+solves), the 2D workload with MC-linear tracing, WENO3 tracing and
+MUSCL-Hancock."""
+import pytest
+
+from paper_1110_0740_amd import inputs as I
+from tests.test_gpu_parity import TOL32, TOL64, _compare_one_step
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", TOL64), ("fp32", TOL32)])
+def test_mhd3d_ppm_hllc_ragged_box(precision, tol):
+    V, meta = I.mhd3d_fields(n=19, ng=4, seed=2008)
+    # a 19^3 generator box cut to 19 x 13 x 11 interior cells: several tiles
+    # along x, ragged tails along y and z
+    V = V[:, :11 + 8, :13 + 8, :]
+    meta = dict(meta)
+    meta["box"] = I.Box((0, 0, 0), (19, 13, 11))
+    _compare_one_step(V, meta, precision, tol, (19, 13, 11), recon="ppm", riemann="hllc")
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", TOL64), ("fp32", TOL32)])
+def test_mhd2d_mc_hllc(precision, tol):
+    V, meta = I.mhd2d_fields(n=128, ng=4, seed=1001)
+    _compare_one_step(V, meta, precision, tol, (128, 128), recon="lin_mc", riemann="hllc")
+
+
+def test_mhd3d_weno3_hllc():
+    V, meta = I.mhd3d_fields(n=16, ng=4, seed=2009)
+    _compare_one_step(V, meta, "fp64", TOL64, (16, 16, 16), recon="weno3", riemann="hllc")
+
+
+def test_mhd3d_muscl_hancock_hllc():
+    V, meta = I.mhd3d_fields(n=16, ng=4, seed=2010)
+    _compare_one_step(V, meta, "fp64", TOL64, (16, 16, 16), recon="lin_vanleer", predictor="mh", riemann="hllc")
