@@ -55,8 +55,9 @@ template <> inline hipError_t launch_sweep<double>(int D, const Combo &c, int nb
     template <int D, int PHYS, int PRED, int RK, int RS>                                                         \
     static hipError_t sweep_one(const Combo &c, int nb, const SweepArgs<R> &a, hipStream_t s)                   \
     {                                                                                                            \
-        /* Rusanov and HLLC run the generic variant only (no hybrid flags, no fixed set) */                      \
+        /* Rusanov and HLLC have no hybrid-flag variant */                                                       \
         if constexpr (RS == RS_RUSANOV || RS == RS_HLLC) {                                                       \
+            if (c.fast) return sweep_one2<D, PHYS, PRED, RK, RS, VAR_FAST>(nb, a, s);                            \
             return sweep_one2<D, PHYS, PRED, RK, RS, VAR_GENERIC>(nb, a, s);                                     \
         } else {                                                                                                 \
             if (a.flag) return sweep_one2<D, PHYS, PRED, RK, RS, VAR_SHOCK>(nb, a, s);                           \
@@ -117,8 +118,12 @@ template <> inline hipError_t launch_sweep<double>(int D, const Combo &c, int nb
             hipLaunchKernelGGL((k_tcouple<DIM, PHYS_RMHD_TM, RS_RUSANOV, 0, VAR_GENERIC, R>), dim3(nb), dim3(NT), 0, s, a); \
         else if (c.phys == PHYS_RMHD_TM)                                                                         \
             hipLaunchKernelGGL((k_tcouple<DIM, PHYS_RMHD_TM, RS_HLL, 0, VAR_GENERIC, R>), dim3(nb), dim3(NT), 0, s, a); \
+        else if (c.rs == RS_RUSANOV && c.fast)                                                                   \
+            hipLaunchKernelGGL((k_tcouple<DIM, PHYS_MHD, RS_RUSANOV, 0, VAR_FAST, R>), dim3(nb), dim3(NT), 0, s, a); \
         else if (c.rs == RS_RUSANOV)                                                                             \
             hipLaunchKernelGGL((k_tcouple<DIM, PHYS_MHD, RS_RUSANOV, PAR, VAR_GENERIC, R>), dim3(nb), dim3(NT), 0, s, a); \
+        else if (c.rs == RS_HLLC && c.fast)                                                                      \
+            hipLaunchKernelGGL((k_tcouple<DIM, PHYS_MHD, RS_HLLC, 0, VAR_FAST, R>), dim3(nb), dim3(NT), 0, s, a); \
         else if (c.rs == RS_HLLC)                                                                                \
             hipLaunchKernelGGL((k_tcouple<DIM, PHYS_MHD, RS_HLLC, PAR, VAR_GENERIC, R>), dim3(nb), dim3(NT), 0, s, a); \
         else if (c.rs == RS_HLLD && a.flag)                                                                      \

@@ -461,8 +461,7 @@ ctu_status ctu_plan_create(const ctu_opts *opts, const ctu_box *boxes, int32_t n
     c.rk = (o.recon == CTU_PPM) ? RK_PPM : (o.recon == CTU_WENO3 ? RK_WENO : RK_LIN);
     c.rs = o.riemann;
     c.shk = o.shock_eps > 0.0 ? 1 : 0;
-    c.fast = (o.wref == CTU_WREF_FACE && o.glm && !o.hyperbolic_off && !o.parabolic_mask && !o.cooling && !c.shk &&
-              o.riemann != CTU_RUSANOV && o.riemann != CTU_HLLC) ? 1 : 0;
+    c.fast = (o.wref == CTU_WREF_FACE && o.glm && !o.hyperbolic_off && !o.parabolic_mask && !o.cooling && !c.shk) ? 1 : 0;
     if ((o.riemann == CTU_RUSANOV || o.riemann == CTU_HLLC) && c.shk)
         return fail(CTU_ERR_UNSUPPORTED, "the shock-adaptive hybrid (HLL on flagged faces) needs HLLD or HLL");
     if (o.physics == CTU_RMHD && (o.riemann == CTU_HLLD || o.riemann == CTU_HLLC))

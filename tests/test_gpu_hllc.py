@@ -35,3 +35,11 @@ def test_mhd3d_weno3_hllc():
 def test_mhd3d_muscl_hancock_hllc():
     V, meta = I.mhd3d_fields(n=16, ng=4, seed=2010)
     _compare_one_step(V, meta, "fp64", TOL64, (16, 16, 16), recon="lin_vanleer", predictor="mh", riemann="hllc")
+
+
+@pytest.mark.parametrize("recon,wref", [("weno3", "cw84"), ("lin_mc", "cell")])
+def test_generic_variant_hllc(recon, wref):
+    """A reference state other than the face value selects the kernels'
+    generic option variant (the tests above run the fixed-option one)."""
+    V, meta = I.mhd2d_fields(n=40, ng=4, seed=1003)
+    _compare_one_step(V, meta, "fp64", TOL64, (40, 40), recon=recon, riemann="hllc", wref=wref)

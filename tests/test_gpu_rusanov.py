@@ -1,7 +1,8 @@
 """GPU parity of the Rusanov (local Lax-Friedrichs) solver through the C
 ABI, against the oracle: 3D MHD with PPM characteristic tracing on a ragged
 box (t^n and time-centred solves), the 2D workload with MC-linear tracing,
-MUSCL-Hancock MHD, and relativistic MHD with the FP64 inversion."""
+MUSCL-Hancock MHD, relativistic MHD with the FP64 inversion, and the generic
+option variant."""
 import pytest
 
 from paper_1110_0740_amd import inputs as I
@@ -38,3 +39,11 @@ def test_rmhd_rusanov(precision, tol):
     _compare_one_step(V, meta, precision, tol, (16, 16, 16), physics="rmhd", recon="lin_mc", predictor="mh",
                       riemann="rusanov")
 
+
+
+@pytest.mark.parametrize("recon,wref", [("ppm", "cw84"), ("lin_mc", "cell")])
+def test_generic_variant_rusanov(recon, wref):
+    """A reference state other than the face value selects the kernels'
+    generic option variant (the tests above run the fixed-option one)."""
+    V, meta = I.mhd2d_fields(n=40, ng=4, seed=1003)
+    _compare_one_step(V, meta, "fp64", TOL64, (40, 40), recon=recon, riemann="rusanov", wref=wref)
