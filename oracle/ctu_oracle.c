@@ -44,7 +44,7 @@ enum { REC_LIN_MC = 0, REC_LIN_MINMOD = 1, REC_LIN_VANLEER = 2, REC_LIN_VANALBAD
        REC_PPM = 4, REC_WENO3 = 5 };
 enum { PRED_CHAR = 0, PRED_MH = 1 };
 enum { WREF_FACE = 0, WREF_CELL = 1, WREF_CW84 = 2 };
-enum { RS_HLLD = 0, RS_HLL = 1, RS_RUSANOV = 2, RS_HLLC = 3 };
+enum { RS_HLLD = 0, RS_HLL = 1, RS_RUSANOV = 2, RS_HLLC = 3, RS_ROE = 4 };
 enum { FAIL_RHO = 0, FAIL_PRS = 1, FAIL_NEWTON = 2, FAIL_VEL = 3, FAIL_NAN = 4, NFAIL = 5 };
 
 #define PARAB_VISC 1u
@@ -635,6 +635,129 @@ static void riemann_hlld(const orc_opts *o, const double *VL, const double *VR, 
     }
 }
 
+static void rot7(const double *V, int d, double *q);
+static void unrot7(const double *q, int d, double *V);
+static void mhd_right_eigen(const orc_opts *o, const double *V, int d, double R[7][7], double lam[7]);
+static int invert7(double A[7][7], double Ainv[7][7]);
+
+/* Roe's linearised solver for ideal MHD (Sec. 3.1's list), for states
+ * sharing B_n:  F = (F_L + F_R)/2 - (1/2) |A| (U_R - U_L)  with a matrix A
+ * for which F_R - F_L = A (U_R - U_L) holds exactly.
+ *
+ * Averages (weights sqrt(rho_L), sqrt(rho_R)): v~ and H~ = (E + p_t)/rho;
+ * the transverse field takes the swapped weights,
+ *   B~_t = (sqrt(rho_R) B_tL + sqrt(rho_L) B_tR) / (sqrt(rho_L) + sqrt(rho_R)),
+ * rho^ = sqrt(rho_L rho_R) and X = |B_tR - B_tL|^2 / (2 (sqrt(rho_L) +
+ * sqrt(rho_R))^2) (Cargo & Gallice 1997).  The exact jump identities
+ *   d(rho v^2/2) = v~.dm - v~^2/2 drho,   d(B_t^2/2) = B~_t.dB_t + X drho,
+ *   d(v_k B_t) = v~_k dB_t + B~_t dv_k,   dv = (dm - v~ drho)/rho^,
+ *   d(rho H v_n) = H~ dm_n + v~_n d(rho H) - H~ v~_n drho
+ * make the flux jump A dU with A the primitive-variable Jacobian at the
+ * state (rho^, v~, B_n, B~_t, p^), gamma p^ / rho^ = a~^2 =
+ * (gamma - 1)(H~ - v~^2/2 - (B_n^2 + B~_t^2)/rho^) - (gamma - 2) X, acting on
+ *   dW = (drho, (dm - v~ drho)/rho^, dB_t, dp),
+ *   dp = (gamma - 1)(dE - v~.dm + v~^2/2 drho - B~_t.dB_t) - (gamma - 2) X drho.
+ * So |A| dU is sum_k |lambda_k| (l_k . dW) r_k mapped back to conserved
+ * differences, with the primitive eigenvectors of that state.  No entropy
+ * fix is applied: |lambda| depends on the averaged speed alone, so waves of
+ * equal speed are damped alike whichever family their degenerate
+ * eigenvectors are counted in.  The signal speed is the largest fast-wave
+ * |lambda| of the average and both states. */
+static void riemann_roe(const orc_opts *o, const double *VL, const double *VR, int d, double ch,
+                        double *F, double *smax)
+{
+    int n, t, b;
+    dir_axes(d, &n, &t, &b);
+    const double g = o->gamma;
+    double UL[NVAR], UR[NVAR], FL[NVAR], FR[NVAR];
+    prim2cons(o, VL, UL);
+    prim2cons(o, VR, UR);
+    phys_flux(o, VL, d, ch, FL);
+    phys_flux(o, VR, d, ch, FR);
+
+    double sL = sqrt(VL[RHO]), sR = sqrt(VR[RHO]);
+    double wL = sL / (sL + sR), wR = sR / (sL + sR);
+    double rhoh = sL * sR;
+    double v[3], q2 = 0.0;
+    for (int k = 0; k < 3; k++) {
+        v[k] = wL * VL[MX1 + k] + wR * VR[MX1 + k];
+        q2 += v[k] * v[k];
+    }
+    double B2L = VL[BX1] * VL[BX1] + VL[BX2] * VL[BX2] + VL[BX3] * VL[BX3];
+    double B2R = VR[BX1] * VR[BX1] + VR[BX2] * VR[BX2] + VR[BX3] * VR[BX3];
+    double HL = (UL[ENG] + VL[PRS] + 0.5 * B2L) / VL[RHO];
+    double HR = (UR[ENG] + VR[PRS] + 0.5 * B2R) / VR[RHO];
+    double H = wL * HL + wR * HR;
+    double Bn = VL[BX1 + n];
+    double Bt[3] = { 0.0, 0.0, 0.0 };
+    double dB2 = 0.0;
+    Bt[t] = wR * VL[BX1 + t] + wL * VR[BX1 + t];
+    Bt[b] = wR * VL[BX1 + b] + wL * VR[BX1 + b];
+    dB2 = (VR[BX1 + t] - VL[BX1 + t]) * (VR[BX1 + t] - VL[BX1 + t]) +
+          (VR[BX1 + b] - VL[BX1 + b]) * (VR[BX1 + b] - VL[BX1 + b]);
+    double X = dB2 / (2.0 * (sL + sR) * (sL + sR));
+    double a2 = (g - 1.0) * (H - 0.5 * q2 - (Bn * Bn + Bt[t] * Bt[t] + Bt[b] * Bt[b]) / rhoh) - (g - 2.0) * X;
+
+    /* the averaged primitive state and its eigensystem */
+    double Vh[NVAR];
+    memset(Vh, 0, sizeof(Vh));
+    Vh[RHO] = rhoh;
+    for (int k = 0; k < 3; k++) Vh[MX1 + k] = v[k];
+    Vh[BX1 + n] = Bn;
+    Vh[BX1 + t] = Bt[t];
+    Vh[BX1 + b] = Bt[b];
+    Vh[PRS] = rhoh * a2 / g;
+    double R[7][7], L[7][7], lam[7], RL[7][7], lamL[7], RR[7][7], lamR[7];
+    mhd_right_eigen(o, Vh, d, R, lam);
+    invert7(R, L);
+    mhd_right_eigen(o, VL, d, RL, lamL);
+    mhd_right_eigen(o, VR, d, RR, lamR);
+
+    /* dU -> dW */
+    double dU[NVAR], dW[NVAR], q[7];
+    for (int k = 0; k < NVAR; k++) dU[k] = UR[k] - UL[k];
+    memset(dW, 0, sizeof(dW));
+    dW[RHO] = dU[RHO];
+    double vdm = 0.0;
+    for (int k = 0; k < 3; k++) {
+        dW[MX1 + k] = (dU[MX1 + k] - v[k] * dU[RHO]) / rhoh;
+        vdm += v[k] * dU[MX1 + k];
+    }
+    dW[BX1 + t] = dU[BX1 + t];
+    dW[BX1 + b] = dU[BX1 + b];
+    dW[PRS] = (g - 1.0) * (dU[ENG] - vdm + 0.5 * q2 * dU[RHO] - Bt[t] * dU[BX1 + t] - Bt[b] * dU[BX1 + b]) -
+              (g - 2.0) * X * dU[RHO];
+    rot7(dW, d, q);
+
+    /* sum_k |lambda_k| (l_k . dW) r_k */
+    double D7[7] = { 0.0 };
+    for (int k = 0; k < 7; k++) {
+        double al = 0.0;
+        for (int m = 0; m < 7; m++) al += L[k][m] * q[m];
+        for (int m = 0; m < 7; m++) D7[m] += fabs(lam[k]) * al * R[m][k];
+    }
+    double DW[NVAR];
+    memset(DW, 0, sizeof(DW));
+    unrot7(D7, d, DW);
+
+    /* dW -> dU */
+    double DU[NVAR];
+    memset(DU, 0, sizeof(DU));
+    DU[RHO] = DW[RHO];
+    double vdv = 0.0;
+    for (int k = 0; k < 3; k++) {
+        DU[MX1 + k] = v[k] * DW[RHO] + rhoh * DW[MX1 + k];
+        vdv += v[k] * DW[MX1 + k];
+    }
+    DU[BX1 + t] = DW[BX1 + t];
+    DU[BX1 + b] = DW[BX1 + b];
+    DU[ENG] = (DW[PRS] + (g - 2.0) * X * DW[RHO]) / (g - 1.0) + Bt[t] * DW[BX1 + t] + Bt[b] * DW[BX1 + b] +
+              0.5 * q2 * DW[RHO] + rhoh * vdv;
+    for (int k = 0; k < NVAR; k++) F[k] = 0.5 * (FL[k] + FR[k]) - 0.5 * DU[k];
+    *smax = fmax(fmax(fabs(lam[0]), fabs(lam[6])),
+                 fmax(fmax(fabs(lamL[0]), fabs(lamL[6])), fmax(fabs(lamR[0]), fabs(lamR[6]))));
+}
+
 /* Full interface solve along d: the linear (B_n, psi) subsystem of Eq.
  * glm2x2 is solved exactly (characteristics psi +- c_h B_n), its interface
  * value of B_n is imposed on both states, then HLLD or HLL gives the other
@@ -658,6 +781,8 @@ static void riemann(const orc_opts *o, const double *VLin, const double *VRin, i
         riemann_hlld(o, VL, VR, d, ch, F, smax);
     else if (o->riemann == RS_HLLC && o->physics == PHYS_MHD)
         riemann_hllc(o, VL, VR, d, ch, F, smax);
+    else if (o->riemann == RS_ROE && o->physics == PHYS_MHD)
+        riemann_roe(o, VL, VR, d, ch, F, smax);
     else if (o->riemann == RS_RUSANOV)
         riemann_rusanov(o, VL, VR, d, ch, F, smax);
     else

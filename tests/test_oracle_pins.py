@@ -196,7 +196,7 @@ def test_rmhd_speed_bound_brute_force():
 # --------------------------------------------------------------------------
 
 
-@pytest.mark.parametrize("physics,solver", [("mhd", "hlld"), ("mhd", "hll"), ("rmhd", "hll"), ("mhd", "rusanov"), ("mhd", "hllc"),
+@pytest.mark.parametrize("physics,solver", [("mhd", "hlld"), ("mhd", "hll"), ("rmhd", "hll"), ("mhd", "rusanov"), ("mhd", "hllc"), ("mhd", "roe"),
                                             ("rmhd", "rusanov")])
 def test_riemann_consistency(physics, solver):
     rng = np.random.default_rng(16)
