@@ -76,11 +76,13 @@ typedef enum { CTU_PRED_CHAR = 0, CTU_PRED_MUSCL_HANCOCK = 1 } ctu_predictor;
 typedef enum { CTU_WREF_FACE = 0, CTU_WREF_CELL = 1, CTU_WREF_CW84 = 2 } ctu_wref;
 /* Sec. 3.1: HLLD (MHD), HLL (MHD, RMHD), Rusanov, the local Lax-Friedrichs
  * flux (F_L + F_R)/2 - a (U_R - U_L)/2 with a the largest signal speed
- * magnitude of the two states (MHD, RMHD), or HLLC (MHD), the three-wave
+ * magnitude of the two states (MHD, RMHD), HLLC (MHD), the three-wave
  * solver with one contact at the HLL-averaged normal velocity and the
- * HLL-averaged transverse field in both star states.  Rusanov and HLLC are
- * not available with shock_eps > 0. */
-typedef enum { CTU_HLLD = 0, CTU_HLL = 1, CTU_RUSANOV = 2, CTU_HLLC = 3 } ctu_riemann;
+ * HLL-averaged transverse field in both star states, or Roe (MHD), the
+ * linearised solver on the Cargo-Gallice averages (exact jump property,
+ * seven waves, no entropy fix).  Rusanov, HLLC and Roe are not available
+ * with shock_eps > 0. */
+typedef enum { CTU_HLLD = 0, CTU_HLL = 1, CTU_RUSANOV = 2, CTU_HLLC = 3, CTU_ROE = 4 } ctu_riemann;
 
 /* Sec. 2.2: the RMHD gas enthalpy w(rho, p) of the ideal EOS (Eq. gammaEos,
  * w = rho + Gamma p / (Gamma - 1)) or of the Taub-Matthews EOS (Eq. TMEos,
@@ -176,8 +178,8 @@ typedef struct ctu_plan ctu_plan;
  * (the only allocating call).  nghost must be >= 3 (PPM needs 3, parabolic
  * terms one more); box blocks must not overlap.  Returns CTU_ERR_UNSUPPORTED
  * for PPM/WENO3 with MUSCL-Hancock, characteristic tracing with RMHD,
- * parabolic/cooling terms with RMHD, HLLD or HLLC with RMHD, or the
- * shock-adaptive hybrid with the Rusanov or HLLC solver. */
+ * parabolic/cooling terms with RMHD, HLLD, HLLC or Roe with RMHD, or the
+ * shock-adaptive hybrid with the Rusanov, HLLC or Roe solver. */
 ctu_status ctu_plan_create(const ctu_opts *opts, const ctu_box *boxes, int32_t nbox, int32_t nghost,
                            const ctu_regface *regfaces, int32_t nreg, ctu_plan **plan_out);
 void ctu_plan_destroy(ctu_plan *plan);

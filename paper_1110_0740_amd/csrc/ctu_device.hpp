@@ -20,7 +20,7 @@ enum { RK_LIN = 0, RK_PPM = 1, RK_WENO = 2 };            // reconstruction kinds
 enum { LIM_MC = 0, LIM_MINMOD = 1, LIM_VANLEER = 2, LIM_VANALBADA = 3 };
 enum { PRED_CHAR = 0, PRED_MH = 1 };
 enum { WREF_FACE = 0, WREF_CELL = 1, WREF_CW84 = 2 };
-enum { RS_HLLD = 0, RS_HLL = 1, RS_RUSANOV = 2, RS_HLLC = 3 };
+enum { RS_HLLD = 0, RS_HLL = 1, RS_RUSANOV = 2, RS_HLLC = 3, RS_ROE = 4 };
 enum { F_RHO = 1, F_PRS = 2, F_INV = 4, F_VEL = 8, F_NAN = 16 };  // failure bits
 enum { PB_VISC = 1, PB_RES = 2, PB_TC = 4 };
 
@@ -392,7 +392,7 @@ __device__ __forceinline__ void wave_speeds(const R *V, R gam, R &lm, R &lp, int
 }
 
 // ---------------------------------------------------------------------------
-// Riemann solvers (Sec. 3.1: HLL, Rusanov, HLLC, HLLD) with the GLM interface subsystem
+// Riemann solvers (Sec. 3.1: HLL, Rusanov, HLLC, HLLD; Roe further below) with the GLM interface subsystem
 // ---------------------------------------------------------------------------
 
 template <int D, int PHYS, typename R>
@@ -608,6 +608,10 @@ __device__ __forceinline__ void hllc(const R *VL, const R *VR, R *F, R &smax, R 
     for (int q = 0; q < NV; q++) F[q] = outer ? Fk[q] : Fk[q] + S * (Us[q] - Uk[q]);
 }
 
+// Roe's solver (defined after the eigenvector helpers it uses)
+template <int D, typename R>
+__device__ __forceinline__ void roe(const R *VL, const R *VR, R *F, R &smax, R gam, R ch, int glm);
+
 // Interface solve: exact solution of the linear (B_n, psi) subsystem of
 // Eq. glm2x2 (psi + c_h B_n carried from the left, psi - c_h B_n from the
 // right), then the chosen solver on the states with the common B_n.  VL, VR are
@@ -628,6 +632,7 @@ __device__ __forceinline__ void riemann(R *VL, R *VR, R *F, R &smax, R gam, R ch
     VR[BX1 + D] = Bm;
     if constexpr (RS == RS_HLLD && PHYS == PHYS_MHD) hlld<D>(VL, VR, F, smax, gam, ch, glm);
     else if constexpr (RS == RS_HLLC && PHYS == PHYS_MHD) hllc<D>(VL, VR, F, smax, gam, ch, glm);
+    else if constexpr (RS == RS_ROE && PHYS == PHYS_MHD) roe<D>(VL, VR, F, smax, gam, ch, glm);
     else if constexpr (RS == RS_RUSANOV) rusanov<D, PHYS>(VL, VR, F, smax, gam, ch, glm, xs);
     else hll<D, PHYS>(VL, VR, F, smax, gam, ch, glm, xs);
     F[BX1 + D] = glm ? psim : R(0);
@@ -828,6 +833,112 @@ template <int D, typename R> __device__ __forceinline__ void recombine(const Eig
     V[BX1 + t] += e.by * Bpa - e.bz * Bpe;
     V[BX1 + b] += e.bz * Bpa + e.by * Bpe;
     V[PRS] += e.rho * e.a2 * (e.af * f + e.as * sl);
+}
+
+// Roe's linearised solver for MHD (Sec. 3.1 lists it) for states sharing
+// B_n: F = (F_L + F_R)/2 - |A| (U_R - U_L)/2 with F_R - F_L = A (U_R - U_L)
+// exactly.  Averages with weights sqrt(rho): v~ and H~ = (E + p_t)/rho; the
+// transverse field with the weights swapped, rho^ = sqrt(rho_L rho_R) and
+// X = |dB_t|^2 / (2 (sqrt(rho_L) + sqrt(rho_R))^2) (Cargo & Gallice 1997).
+// In the differences dW = (drho, (dm - v~ drho)/rho^, dB_t, dp) with
+//   dp = (gamma - 1)(dE - v~.dm + v~^2 drho/2 - B~_t.dB_t) - (gamma - 2) X drho
+// A acts as the primitive-variable Jacobian of the state (rho^, v~, B_n,
+// B~_t, p^), gamma p^ = rho^ a~^2, a~^2 = (gamma - 1)(H~ - v~^2/2 - B~^2/rho^)
+// - (gamma - 2) X, so |A| dU is the closed-form eigen-decomposition of that
+// state (project / recombine) weighted by |lambda| and mapped back to
+// conserved differences.  No entropy fix.  Signal speed: the largest fast
+// |lambda| of the average and of both states.
+template <int D, typename R>
+__device__ __forceinline__ void roe(const R *VL, const R *VR, R *F, R &smax, R gam, R ch, int glm)
+{
+    constexpr int n = Ax<D>::n, t = Ax<D>::t, b = Ax<D>::b;
+    R UL[NV], UR[NV], FL[NV], FR[NV];
+    phys_flux<D, PHYS_MHD>(VL, UL, FL, gam, ch, glm);
+    phys_flux<D, PHYS_MHD>(VR, UR, FR, gam, ch, glm);
+    const R gm1 = gam - R(1), gm2 = gam - R(2);
+    const R sL = sqrt(VL[RHO]), sR = sqrt(VR[RHO]);
+    const R is = R(1) / (sL + sR);
+    const R wL = sL * is, wR = sR * is;
+    const R rh = sL * sR, irh = R(1) / rh;
+    R Vh[NV];
+    Vh[RHO] = rh;
+    R q2 = R(0);
+#pragma unroll
+    for (int k = 0; k < 3; k++) {
+        Vh[MX1 + k] = wL * VL[MX1 + k] + wR * VR[MX1 + k];
+        q2 += Vh[MX1 + k] * Vh[MX1 + k];
+    }
+    const R ptL = VL[PRS] + R(0.5) * (sq(VL[BX1]) + sq(VL[BX2]) + sq(VL[BX3]));
+    const R ptR = VR[PRS] + R(0.5) * (sq(VR[BX1]) + sq(VR[BX2]) + sq(VR[BX3]));
+    const R H = wL * (UL[ENG] + ptL) / VL[RHO] + wR * (UR[ENG] + ptR) / VR[RHO];
+    const R Bn = VL[BX1 + n];
+    const R Bt = wR * VL[BX1 + t] + wL * VR[BX1 + t];
+    const R Bb = wR * VL[BX1 + b] + wL * VR[BX1 + b];
+    const R dBt = VR[BX1 + t] - VL[BX1 + t], dBb = VR[BX1 + b] - VL[BX1 + b];
+    const R X = R(0.5) * (dBt * dBt + dBb * dBb) * is * is;
+    const R a2 = gm1 * (H - R(0.5) * q2 - (Bn * Bn + Bt * Bt + Bb * Bb) * irh) - gm2 * X;
+    Vh[BX1 + n] = Bn;
+    Vh[BX1 + t] = Bt;
+    Vh[BX1 + b] = Bb;
+    Vh[PRS] = rh * a2 / gam;
+    Vh[PSI] = R(0);
+    Eigen<R> e;
+    eigen_setup<D>(Vh, gam, e);
+
+    // conserved differences -> dW
+    R dq[NV];
+    dq[RHO] = UR[RHO] - UL[RHO];
+    R vdm = R(0);
+#pragma unroll
+    for (int k = 0; k < 3; k++) {
+        const R dm = UR[MX1 + k] - UL[MX1 + k];
+        dq[MX1 + k] = (dm - Vh[MX1 + k] * dq[RHO]) * irh;
+        vdm += Vh[MX1 + k] * dm;
+    }
+    dq[BX1 + n] = R(0);
+    dq[BX1 + t] = dBt;
+    dq[BX1 + b] = dBb;
+    dq[PSI] = R(0);
+    dq[PRS] = gm1 * (UR[ENG] - UL[ENG] - vdm + R(0.5) * q2 * dq[RHO] - Bt * dBt - Bb * dBb) - gm2 * X * dq[RHO];
+
+    // sum_k |lambda_k| (l_k . dW) r_k
+    R w[7];
+    project<D>(e, dq, w);
+    const R u = Vh[MX1 + n];
+    R c[7];
+    c[0] = fabs(u - e.cf) * w[0];
+    c[1] = fabs(u - e.ca) * w[1];
+    c[2] = fabs(u - e.cs) * w[2];
+    c[3] = fabs(u) * w[3];
+    c[4] = fabs(u + e.cs) * w[4];
+    c[5] = fabs(u + e.ca) * w[5];
+    c[6] = fabs(u + e.cf) * w[6];
+    R Dw[NV];
+#pragma unroll
+    for (int q = 0; q < NV; q++) Dw[q] = R(0);
+    recombine<D>(e, c, Dw);
+
+    // dW -> conserved differences, then the flux
+    R Du[NV];
+    Du[RHO] = Dw[RHO];
+    R vdv = R(0);
+#pragma unroll
+    for (int k = 0; k < 3; k++) {
+        Du[MX1 + k] = Vh[MX1 + k] * Dw[RHO] + rh * Dw[MX1 + k];
+        vdv += Vh[MX1 + k] * Dw[MX1 + k];
+    }
+    Du[BX1 + n] = R(0);
+    Du[BX1 + t] = Dw[BX1 + t];
+    Du[BX1 + b] = Dw[BX1 + b];
+    Du[PSI] = R(0);
+    Du[ENG] = (Dw[PRS] + gm2 * X * Dw[RHO]) / gm1 + Bt * Dw[BX1 + t] + Bb * Dw[BX1 + b] + R(0.5) * q2 * Dw[RHO] +
+              rh * vdv;
+#pragma unroll
+    for (int q = 0; q < NV; q++) F[q] = R(0.5) * (FL[q] + FR[q]) - R(0.5) * Du[q];
+    const R cfL = cfast_mhd<D>(VL, gam), cfR = cfast_mhd<D>(VR, gam);
+    const R uL = VL[MX1 + n], uR = VR[MX1 + n];
+    smax = fmax(fmax(fabs(u - e.cf), fabs(u + e.cf)),
+                fmax(fmax(fabs(uL - cfL), fabs(uL + cfL)), fmax(fabs(uR - cfR), fabs(uR + cfR))));
 }
 
 // Characteristic predictor for cell 0 of the primitive stencil Vs[l+2]

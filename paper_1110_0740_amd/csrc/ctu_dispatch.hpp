@@ -55,8 +55,8 @@ template <> inline hipError_t launch_sweep<double>(int D, const Combo &c, int nb
     template <int D, int PHYS, int PRED, int RK, int RS>                                                         \
     static hipError_t sweep_one(const Combo &c, int nb, const SweepArgs<R> &a, hipStream_t s)                   \
     {                                                                                                            \
-        /* Rusanov and HLLC have no hybrid-flag variant */                                                       \
-        if constexpr (RS == RS_RUSANOV || RS == RS_HLLC) {                                                       \
+        /* Rusanov, HLLC and Roe have no hybrid-flag variant */                                                  \
+        if constexpr (RS == RS_RUSANOV || RS == RS_HLLC || RS == RS_ROE) {                                       \
             if (c.fast) return sweep_one2<D, PHYS, PRED, RK, RS, VAR_FAST>(nb, a, s);                            \
             return sweep_one2<D, PHYS, PRED, RK, RS, VAR_GENERIC>(nb, a, s);                                     \
         } else {                                                                                                 \
@@ -80,23 +80,27 @@ template <> inline hipError_t launch_sweep<double>(int D, const Combo &c, int nb
             if (c.rs == RS_HLLD) return sweep_one<D, PHYS_MHD, PRED_MH, RK_LIN, RS_HLLD>(c, nb, a, s);            \
             if (c.rs == RS_RUSANOV) return sweep_one<D, PHYS_MHD, PRED_MH, RK_LIN, RS_RUSANOV>(c, nb, a, s);      \
             if (c.rs == RS_HLLC) return sweep_one<D, PHYS_MHD, PRED_MH, RK_LIN, RS_HLLC>(c, nb, a, s);            \
+            if (c.rs == RS_ROE) return sweep_one<D, PHYS_MHD, PRED_MH, RK_LIN, RS_ROE>(c, nb, a, s);              \
             return sweep_one<D, PHYS_MHD, PRED_MH, RK_LIN, RS_HLL>(c, nb, a, s);                                  \
         }                                                                                                        \
         if (c.rk == RK_PPM) {                                                                                    \
             if (c.rs == RS_HLLD) return sweep_one<D, PHYS_MHD, PRED_CHAR, RK_PPM, RS_HLLD>(c, nb, a, s);          \
             if (c.rs == RS_RUSANOV) return sweep_one<D, PHYS_MHD, PRED_CHAR, RK_PPM, RS_RUSANOV>(c, nb, a, s);    \
             if (c.rs == RS_HLLC) return sweep_one<D, PHYS_MHD, PRED_CHAR, RK_PPM, RS_HLLC>(c, nb, a, s);          \
+            if (c.rs == RS_ROE) return sweep_one<D, PHYS_MHD, PRED_CHAR, RK_PPM, RS_ROE>(c, nb, a, s);            \
             return sweep_one<D, PHYS_MHD, PRED_CHAR, RK_PPM, RS_HLL>(c, nb, a, s);                                \
         }                                                                                                        \
         if (c.rk == RK_WENO) {                                                                                   \
             if (c.rs == RS_HLLD) return sweep_one<D, PHYS_MHD, PRED_CHAR, RK_WENO, RS_HLLD>(c, nb, a, s);         \
             if (c.rs == RS_RUSANOV) return sweep_one<D, PHYS_MHD, PRED_CHAR, RK_WENO, RS_RUSANOV>(c, nb, a, s);   \
             if (c.rs == RS_HLLC) return sweep_one<D, PHYS_MHD, PRED_CHAR, RK_WENO, RS_HLLC>(c, nb, a, s);         \
+            if (c.rs == RS_ROE) return sweep_one<D, PHYS_MHD, PRED_CHAR, RK_WENO, RS_ROE>(c, nb, a, s);           \
             return sweep_one<D, PHYS_MHD, PRED_CHAR, RK_WENO, RS_HLL>(c, nb, a, s);                               \
         }                                                                                                        \
         if (c.rs == RS_HLLD) return sweep_one<D, PHYS_MHD, PRED_CHAR, RK_LIN, RS_HLLD>(c, nb, a, s);              \
         if (c.rs == RS_RUSANOV) return sweep_one<D, PHYS_MHD, PRED_CHAR, RK_LIN, RS_RUSANOV>(c, nb, a, s);        \
         if (c.rs == RS_HLLC) return sweep_one<D, PHYS_MHD, PRED_CHAR, RK_LIN, RS_HLLC>(c, nb, a, s);              \
+        if (c.rs == RS_ROE) return sweep_one<D, PHYS_MHD, PRED_CHAR, RK_LIN, RS_ROE>(c, nb, a, s);                \
         return sweep_one<D, PHYS_MHD, PRED_CHAR, RK_LIN, RS_HLL>(c, nb, a, s);                                    \
     }                                                                                                            \
     hipError_t launch_sweep_##SUFFIX(int D, const Combo &c, int nb, const SweepArgs<R> &a, hipStream_t s)      \
@@ -126,6 +130,10 @@ template <> inline hipError_t launch_sweep<double>(int D, const Combo &c, int nb
             hipLaunchKernelGGL((k_tcouple<DIM, PHYS_MHD, RS_HLLC, 0, VAR_FAST, R>), dim3(nb), dim3(NT), 0, s, a); \
         else if (c.rs == RS_HLLC)                                                                                \
             hipLaunchKernelGGL((k_tcouple<DIM, PHYS_MHD, RS_HLLC, PAR, VAR_GENERIC, R>), dim3(nb), dim3(NT), 0, s, a); \
+        else if (c.rs == RS_ROE && c.fast)                                                                       \
+            hipLaunchKernelGGL((k_tcouple<DIM, PHYS_MHD, RS_ROE, 0, VAR_FAST, R>), dim3(nb), dim3(NT), 0, s, a); \
+        else if (c.rs == RS_ROE)                                                                                 \
+            hipLaunchKernelGGL((k_tcouple<DIM, PHYS_MHD, RS_ROE, PAR, VAR_GENERIC, R>), dim3(nb), dim3(NT), 0, s, a); \
         else if (c.rs == RS_HLLD && a.flag)                                                                      \
             hipLaunchKernelGGL((k_tcouple<DIM, PHYS_MHD, RS_HLLD, PAR, VAR_SHOCK, R>), dim3(nb), dim3(NT), 0, s, a); \
         else if (c.fast && c.rs == RS_HLLD)                                                                      \

@@ -444,7 +444,8 @@ ctu_status ctu_plan_create(const ctu_opts *opts, const ctu_box *boxes, int32_t n
     if (o.recon < CTU_LIN_MC || o.recon > CTU_WENO3) return fail(CTU_ERR_ARG, "bad recon");
     if (o.predictor != CTU_PRED_CHAR && o.predictor != CTU_PRED_MUSCL_HANCOCK) return fail(CTU_ERR_ARG, "bad predictor");
     if (o.wref < CTU_WREF_FACE || o.wref > CTU_WREF_CW84) return fail(CTU_ERR_ARG, "bad wref");
-    if (o.riemann != CTU_HLLD && o.riemann != CTU_HLL && o.riemann != CTU_RUSANOV && o.riemann != CTU_HLLC)
+    if (o.riemann != CTU_HLLD && o.riemann != CTU_HLL && o.riemann != CTU_RUSANOV && o.riemann != CTU_HLLC &&
+        o.riemann != CTU_ROE)
         return fail(CTU_ERR_ARG, "bad riemann");
     if (o.eos != CTU_EOS_IDEAL && o.eos != CTU_EOS_TM) return fail(CTU_ERR_ARG, "bad eos");
     if (o.exact_speeds != 0 && o.exact_speeds != 1) return fail(CTU_ERR_ARG, "exact_speeds must be 0 or 1");
@@ -462,9 +463,9 @@ ctu_status ctu_plan_create(const ctu_opts *opts, const ctu_box *boxes, int32_t n
     c.rs = o.riemann;
     c.shk = o.shock_eps > 0.0 ? 1 : 0;
     c.fast = (o.wref == CTU_WREF_FACE && o.glm && !o.hyperbolic_off && !o.parabolic_mask && !o.cooling && !c.shk) ? 1 : 0;
-    if ((o.riemann == CTU_RUSANOV || o.riemann == CTU_HLLC) && c.shk)
+    if ((o.riemann == CTU_RUSANOV || o.riemann == CTU_HLLC || o.riemann == CTU_ROE) && c.shk)
         return fail(CTU_ERR_UNSUPPORTED, "the shock-adaptive hybrid (HLL on flagged faces) needs HLLD or HLL");
-    if (o.physics == CTU_RMHD && (o.riemann == CTU_HLLD || o.riemann == CTU_HLLC))
+    if (o.physics == CTU_RMHD && (o.riemann == CTU_HLLD || o.riemann == CTU_HLLC || o.riemann == CTU_ROE))
         return fail(CTU_ERR_UNSUPPORTED, "RMHD supports the HLL and Rusanov solvers only");
     if (!combo_supported(c))
         return fail(CTU_ERR_UNSUPPORTED, "unsupported combination (characteristic tracing is MHD only; "

@@ -18,7 +18,7 @@ FP64, FP32 = 0, 1
 RECON = {"lin_mc": 0, "lin_minmod": 1, "lin_vanleer": 2, "lin_vanalbada": 3, "ppm": 4, "weno3": 5}
 PRED = {"char": 0, "mh": 1}
 WREF = {"face": 0, "cell": 1, "cw84": 2}
-RIEMANN = {"hlld": 0, "hll": 1, "rusanov": 2, "hllc": 3}
+RIEMANN = {"hlld": 0, "hll": 1, "rusanov": 2, "hllc": 3, "roe": 4}
 EOS = {"ideal": 0, "tm": 1}
 PARAB_VISC, PARAB_RES, PARAB_TC = 1, 2, 4
 NFAIL = 5
