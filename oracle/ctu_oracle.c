@@ -525,6 +525,111 @@ static void riemann_hllc(const orc_opts *o, const double *VL, const double *VR, 
     for (int v = 0; v < NVAR; v++) F[v] = Fs[v] + S * (Us[v] - U[v]);
 }
 
+/* HLLC for relativistic MHD (Sec. 3.1's list; Mignone & Bodo 2006), for
+ * states sharing B_n.  E below is the total energy U[ENG] + D, whose flux is
+ * m_n.  From the HLL averages U^hll, F^hll:
+ *  B_n != 0: both star states hold B*_t = B_t^hll; the contact speed
+ *    lambda* is the root with the minus sign of
+ *      (F_E - B*.F_B) l^2 - (E + F_mn - B*^2 - F_B^2) l + (m_n - B*.F_B) = 0
+ *    (B* and F_B the transverse HLL field and its HLL flux), which follows
+ *    from m*_n = (E* + p_t*) lambda* - (v*.B*) B_n and
+ *    F*_mn = F*_E lambda* - B_n (B_n / gamma*^2 + (v*.B*) lambda*) + p_t*
+ *    taken on the HLL state and flux, with the transverse velocity from the
+ *    induction flux v*_t = (B*_t lambda* - F_Bt) / B_n (the cubic terms
+ *    cancel); p_t* then follows from the second relation;
+ *  B_n = 0 (B_n^2 <= 1e-12 (B_n^2 + B*^2)): the hydrodynamic relations with
+ *    p_t: F_E l^2 - (E + F_mn) l + m_n = 0, p_t* = F_mn - F_E lambda*.
+ * The star state of the side holding the interface follows from the jump
+ * conditions across its outer wave S:
+ *   D* = (S D - F_D) / (S - l*),  E* = (S E - m_n + p_t* l* - (v*.B*) B_n) / (S - l*),
+ *   m*_n = (E* + p_t*) l* - (v*.B*) B_n,
+ *   m*_t = (S m_t - F_mt - B_n (B*_t / gamma*^2 + (v*.B*) v*_t)) / (S - l*)
+ *   (B_n = 0: m*_t = (S m_t - F_mt)/(S - l*), B*_t = (S B_t - F_Bt)/(S - l*)),
+ * and F* = F + S (U* - U).  The root is taken in the form 2c / (-b +
+ * sqrt(b^2 - 4ac)), which has no cancellation as a -> 0.  Where the star
+ * state is not admissible (negative discriminant, l* outside (S_L, S_R),
+ * v*^2 >= 1 or D* <= 0) the face takes the HLL flux. */
+static void riemann_hllc_rmhd(const orc_opts *o, const double *VL, const double *VR, int d, double ch, double *F,
+                              double *smax)
+{
+    int n, t, b;
+    dir_axes(d, &n, &t, &b);
+    double lminL, lmaxL, lminR, lmaxR;
+    signal_speeds(o, VL, d, &lminL, &lmaxL);
+    signal_speeds(o, VR, d, &lminR, &lmaxR);
+    double SL = fmin(lminL, lminR), SR = fmax(lmaxL, lmaxR);
+    *smax = fmax(fabs(SL), fabs(SR));
+    double UL[NVAR], UR[NVAR], FL[NVAR], FR[NVAR];
+    prim2cons(o, VL, UL);
+    prim2cons(o, VR, UR);
+    phys_flux(o, VL, d, ch, FL);
+    phys_flux(o, VR, d, ch, FR);
+    if (SL >= 0.0) { memcpy(F, FL, sizeof(FL)); return; }
+    if (SR <= 0.0) { memcpy(F, FR, sizeof(FR)); return; }
+    double Uh[NVAR], Fh[NVAR];
+    for (int v = 0; v < NVAR; v++) {
+        Uh[v] = (SR * UR[v] - SL * UL[v] - (FR[v] - FL[v])) / (SR - SL);
+        Fh[v] = (SR * FL[v] - SL * FR[v] + SL * SR * (UR[v] - UL[v])) / (SR - SL);
+    }
+    double Eh = Uh[ENG] + Uh[RHO], FEh = Fh[ENG] + Fh[RHO];
+    double Bn = VL[BX1 + n];
+    double Bt = Uh[BX1 + t], Bb = Uh[BX1 + b], Ft = Fh[BX1 + t], Fb = Fh[BX1 + b];
+    int magnetic = Bn * Bn > 1e-12 * (Bn * Bn + Bt * Bt + Bb * Bb);
+    double qa, qb, qc;
+    if (magnetic) {
+        double BF = Bt * Ft + Bb * Fb;
+        qa = FEh - BF;
+        qb = -(Eh + Fh[MX1 + n]) + Bt * Bt + Bb * Bb + Ft * Ft + Fb * Fb;
+        qc = Uh[MX1 + n] - BF;
+    } else {
+        qa = FEh;
+        qb = -(Eh + Fh[MX1 + n]);
+        qc = Uh[MX1 + n];
+    }
+    double disc = qb * qb - 4.0 * qa * qc;
+    int ok = disc >= 0.0;
+    double ls = ok ? 2.0 * qc / (-qb + sqrt(disc)) : 0.0;
+    ok = ok && ls > SL && ls < SR;
+    double vt = 0.0, vb = 0.0, vBs = 0.0, ig2 = 1.0, pts;
+    if (magnetic) {
+        vt = (Bt * ls - Ft) / Bn;
+        vb = (Bb * ls - Fb) / Bn;
+        double vs2 = ls * ls + vt * vt + vb * vb;
+        ok = ok && vs2 < 1.0;
+        ig2 = 1.0 - vs2;
+        vBs = ls * Bn + vt * Bt + vb * Bb;
+        pts = Fh[MX1 + n] - FEh * ls + Bn * (Bn * ig2 + vBs * ls);
+    } else {
+        pts = Fh[MX1 + n] - FEh * ls;
+    }
+    int right = !(ls >= 0.0);
+    const double *U = right ? UR : UL;
+    const double *Fk = right ? FR : FL;
+    double S = right ? SR : SL;
+    double iS = 1.0 / (S - ls);
+    double Us[NVAR];
+    Us[RHO] = (S * U[RHO] - Fk[RHO]) * iS;
+    double Ek = U[ENG] + U[RHO];
+    double Es = (S * Ek - U[MX1 + n] + pts * ls - vBs * Bn) * iS;
+    Us[MX1 + n] = (Es + pts) * ls - vBs * Bn;
+    if (magnetic) {
+        Us[MX1 + t] = (S * U[MX1 + t] - Fk[MX1 + t] - Bn * (Bt * ig2 + vBs * vt)) * iS;
+        Us[MX1 + b] = (S * U[MX1 + b] - Fk[MX1 + b] - Bn * (Bb * ig2 + vBs * vb)) * iS;
+        Us[BX1 + t] = Bt;
+        Us[BX1 + b] = Bb;
+    } else {
+        Us[MX1 + t] = (S * U[MX1 + t] - Fk[MX1 + t]) * iS;
+        Us[MX1 + b] = (S * U[MX1 + b] - Fk[MX1 + b]) * iS;
+        Us[BX1 + t] = (S * U[BX1 + t] - Fk[BX1 + t]) * iS;
+        Us[BX1 + b] = (S * U[BX1 + b] - Fk[BX1 + b]) * iS;
+    }
+    Us[ENG] = Es - Us[RHO];
+    Us[BX1 + n] = Bn;
+    Us[PSI] = U[PSI];
+    ok = ok && Us[RHO] > 0.0;
+    for (int v = 0; v < NVAR; v++) F[v] = ok ? Fk[v] + S * (Us[v] - U[v]) : Fh[v];
+}
+
 /* HLLD for ideal MHD (Miyoshi & Kusano 2005), for states sharing B_n. */
 static void riemann_hlld(const orc_opts *o, const double *VL, const double *VR, int d, double ch,
                          double *F, double *smax)
@@ -781,6 +886,8 @@ static void riemann(const orc_opts *o, const double *VLin, const double *VRin, i
         riemann_hlld(o, VL, VR, d, ch, F, smax);
     else if (o->riemann == RS_HLLC && o->physics == PHYS_MHD)
         riemann_hllc(o, VL, VR, d, ch, F, smax);
+    else if (o->riemann == RS_HLLC)
+        riemann_hllc_rmhd(o, VL, VR, d, ch, F, smax);
     else if (o->riemann == RS_ROE && o->physics == PHYS_MHD)
         riemann_roe(o, VL, VR, d, ch, F, smax);
     else if (o->riemann == RS_RUSANOV)
