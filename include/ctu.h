@@ -76,9 +76,11 @@ typedef enum { CTU_PRED_CHAR = 0, CTU_PRED_MUSCL_HANCOCK = 1 } ctu_predictor;
 typedef enum { CTU_WREF_FACE = 0, CTU_WREF_CELL = 1, CTU_WREF_CW84 = 2 } ctu_wref;
 /* Sec. 3.1: HLLD (MHD), HLL (MHD, RMHD), Rusanov, the local Lax-Friedrichs
  * flux (F_L + F_R)/2 - a (U_R - U_L)/2 with a the largest signal speed
- * magnitude of the two states (MHD, RMHD), HLLC (MHD), the three-wave
- * solver with one contact at the HLL-averaged normal velocity and the
- * HLL-averaged transverse field in both star states, or Roe (MHD), the
+ * magnitude of the two states (MHD, RMHD), HLLC (MHD: one contact at the
+ * HLL-averaged normal velocity with the HLL-averaged transverse field in
+ * both star states; RMHD: the contact speed from the quadratic of Mignone &
+ * Bodo 2006 on the HLL averages, HLL where the star state is not
+ * admissible), or Roe (MHD), the
  * linearised solver on the Cargo-Gallice averages (exact jump property,
  * seven waves, no entropy fix).  Rusanov, HLLC and Roe are not available
  * with shock_eps > 0. */
@@ -178,7 +180,7 @@ typedef struct ctu_plan ctu_plan;
  * (the only allocating call).  nghost must be >= 3 (PPM needs 3, parabolic
  * terms one more); box blocks must not overlap.  Returns CTU_ERR_UNSUPPORTED
  * for PPM/WENO3 with MUSCL-Hancock, characteristic tracing with RMHD,
- * parabolic/cooling terms with RMHD, HLLD, HLLC or Roe with RMHD, or the
+ * parabolic/cooling terms with RMHD, HLLD or Roe with RMHD, or the
  * shock-adaptive hybrid with the Rusanov, HLLC or Roe solver. */
 ctu_status ctu_plan_create(const ctu_opts *opts, const ctu_box *boxes, int32_t nbox, int32_t nghost,
                            const ctu_regface *regfaces, int32_t nreg, ctu_plan **plan_out);

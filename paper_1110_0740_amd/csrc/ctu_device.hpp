@@ -608,6 +608,91 @@ __device__ __forceinline__ void hllc(const R *VL, const R *VR, R *F, R &smax, R 
     for (int q = 0; q < NV; q++) F[q] = outer ? Fk[q] : Fk[q] + S * (Us[q] - Uk[q]);
 }
 
+// HLLC for relativistic MHD (Sec. 3.1 lists it for both modules; Mignone &
+// Bodo 2006) for states sharing B_n.  With E the total energy U[ENG] + D
+// (flux m_n) and the HLL averages U^hll, F^hll:
+//  * B_n != 0: both star states hold the HLL transverse field B*; the
+//    contact speed l* is the root with the minus sign of
+//      (F_E - B*.F_B) l^2 - (E + F_mn - B*^2 - F_B^2) l + (m_n - B*.F_B) = 0
+//    (F_B the HLL flux of the transverse field), the star transverse
+//    velocity v*_t = (B*_t l* - F_Bt) / B_n, and
+//    p_t* = F_mn - F_E l* + B_n (B_n / gamma*^2 + (v*.B*) l*);
+//  * B_n = 0 (B_n^2 <= 1e-12 (B_n^2 + B*^2)): F_E l^2 - (E + F_mn) l + m_n = 0
+//    and p_t* = F_mn - F_E l*; the transverse field jumps with the state.
+// The star state of the side holding the interface comes from the jump
+// conditions across its outer wave S, and the flux is F + S (U* - U).  The
+// root is formed as 2c / (-b + sqrt(b^2 - 4ac)).  A star state that is not
+// admissible (negative discriminant, l* outside (S_L, S_R), v*^2 >= 1,
+// D* <= 0) gives the HLL flux.  Both field cases, both sides and the
+// fallback are formed and chosen by selects.
+template <int D, int PHYS, typename R>
+__device__ __forceinline__ void hllc_rmhd(const R *VL, const R *VR, R *F, R &smax, R gam, R ch, int glm, int xs)
+{
+    constexpr int n = Ax<D>::n, t = Ax<D>::t, b = Ax<D>::b;
+    R lmL, lpL, lmR, lpR;
+    wave_speeds<D, PHYS>(VL, gam, lmL, lpL, xs);
+    wave_speeds<D, PHYS>(VR, gam, lmR, lpR, xs);
+    const R SL = fmin(lmL, lmR), SR = fmax(lpL, lpR);
+    smax = fmax(fabs(SL), fabs(SR));
+    R UL[NV], UR[NV], FL[NV], FR[NV];
+    phys_flux<D, PHYS>(VL, UL, FL, gam, ch, glm);
+    phys_flux<D, PHYS>(VR, UR, FR, gam, ch, glm);
+    const R id = R(1) / (SR - SL);
+    R Uh[NV], Fh[NV];
+#pragma unroll
+    for (int q = 0; q < NV; q++) {
+        Uh[q] = (SR * UR[q] - SL * UL[q] - (FR[q] - FL[q])) * id;
+        Fh[q] = (SR * FL[q] - SL * FR[q] + SL * SR * (UR[q] - UL[q])) * id;
+    }
+    const R Eh = Uh[ENG] + Uh[RHO], FEh = Fh[ENG] + Fh[RHO];
+    const R Bn = VL[BX1 + n];
+    const R Bt = Uh[BX1 + t], Bb = Uh[BX1 + b], Ft = Fh[BX1 + t], Fb = Fh[BX1 + b];
+    const bool mag = Bn * Bn > R(1e-12) * (Bn * Bn + Bt * Bt + Bb * Bb);
+    const R BF = mag ? Bt * Ft + Bb * Fb : R(0);
+    const R qa = FEh - BF;
+    const R qb = -(Eh + Fh[MX1 + n]) + (mag ? Bt * Bt + Bb * Bb + Ft * Ft + Fb * Fb : R(0));
+    const R qc = Uh[MX1 + n] - BF;
+    const R disc = qb * qb - R(4) * qa * qc;
+    bool ok = disc >= R(0);
+    const R ls = R(2) * qc / (-qb + sqrt(fmax(disc, R(0))));
+    ok = ok && ls > SL && ls < SR;
+    const R iBn = mag ? R(1) / Bn : R(0);
+    const R vt = (Bt * ls - Ft) * iBn, vb = (Bb * ls - Fb) * iBn;
+    const R ig2 = R(1) - (ls * ls + vt * vt + vb * vb);
+    ok = ok && (!mag || ig2 > R(0));
+    const R vBs = mag ? ls * Bn + vt * Bt + vb * Bb : R(0);
+    const R pts = Fh[MX1 + n] - FEh * ls + (mag ? Bn * (Bn * ig2 + vBs * ls) : R(0));
+
+    const bool k = !(ls >= R(0));
+    R Uk[NV], Fk[NV];
+#pragma unroll
+    for (int q = 0; q < NV; q++) {
+        Uk[q] = k ? UR[q] : UL[q];
+        Fk[q] = k ? FR[q] : FL[q];
+    }
+    const R S = k ? SR : SL;
+    const R iS = R(1) / (S - ls);
+    R Us[NV];
+    Us[RHO] = (S * Uk[RHO] - Fk[RHO]) * iS;
+    const R Es = (S * (Uk[ENG] + Uk[RHO]) - Uk[MX1 + n] + pts * ls - vBs * Bn) * iS;
+    Us[MX1 + n] = (Es + pts) * ls - vBs * Bn;
+    const R mt = S * Uk[MX1 + t] - Fk[MX1 + t], mb = S * Uk[MX1 + b] - Fk[MX1 + b];
+    Us[MX1 + t] = (mag ? mt - Bn * (Bt * ig2 + vBs * vt) : mt) * iS;
+    Us[MX1 + b] = (mag ? mb - Bn * (Bb * ig2 + vBs * vb) : mb) * iS;
+    Us[BX1 + t] = mag ? Bt : (S * Uk[BX1 + t] - Fk[BX1 + t]) * iS;
+    Us[BX1 + b] = mag ? Bb : (S * Uk[BX1 + b] - Fk[BX1 + b]) * iS;
+    Us[ENG] = Es - Us[RHO];
+    Us[BX1 + n] = Bn;
+    Us[PSI] = Uk[PSI];
+    ok = ok && Us[RHO] > R(0);
+    const bool outerL = SL >= R(0), outerR = SR <= R(0);
+#pragma unroll
+    for (int q = 0; q < NV; q++) {
+        const R fs = ok ? Fk[q] + S * (Us[q] - Uk[q]) : Fh[q];
+        F[q] = outerL ? FL[q] : (outerR ? FR[q] : fs);
+    }
+}
+
 // Roe's solver (defined after the eigenvector helpers it uses)
 template <int D, typename R>
 __device__ __forceinline__ void roe(const R *VL, const R *VR, R *F, R &smax, R gam, R ch, int glm);
@@ -633,6 +718,7 @@ __device__ __forceinline__ void riemann(R *VL, R *VR, R *F, R &smax, R gam, R ch
     if constexpr (RS == RS_HLLD && PHYS == PHYS_MHD) hlld<D>(VL, VR, F, smax, gam, ch, glm);
     else if constexpr (RS == RS_HLLC && PHYS == PHYS_MHD) hllc<D>(VL, VR, F, smax, gam, ch, glm);
     else if constexpr (RS == RS_ROE && PHYS == PHYS_MHD) roe<D>(VL, VR, F, smax, gam, ch, glm);
+    else if constexpr (RS == RS_HLLC) hllc_rmhd<D, PHYS>(VL, VR, F, smax, gam, ch, glm, xs);
     else if constexpr (RS == RS_RUSANOV) rusanov<D, PHYS>(VL, VR, F, smax, gam, ch, glm, xs);
     else hll<D, PHYS>(VL, VR, F, smax, gam, ch, glm, xs);
     F[BX1 + D] = glm ? psim : R(0);

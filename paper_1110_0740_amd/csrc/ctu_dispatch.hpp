@@ -23,7 +23,7 @@ __host__ inline bool combo_supported(const Combo &c)
         if (c.pred == PRED_CHAR) return true;
         return c.rk == RK_LIN;
     }
-    return c.pred == PRED_MH && c.rk == RK_LIN && (c.rs == RS_HLL || c.rs == RS_RUSANOV);
+    return c.pred == PRED_MH && c.rk == RK_LIN && (c.rs == RS_HLL || c.rs == RS_RUSANOV || c.rs == RS_HLLC);
 }
 
 hipError_t launch_sweep_f32(int D, const Combo &c, int nblocks, const SweepArgs<float> &a, hipStream_t s);
@@ -70,10 +70,12 @@ template <> inline hipError_t launch_sweep<double>(int D, const Combo &c, int nb
     {                                                                                                            \
         if (c.phys == PHYS_RMHD) {                                                                               \
             if (c.rs == RS_RUSANOV) return sweep_one<D, PHYS_RMHD, PRED_MH, RK_LIN, RS_RUSANOV>(c, nb, a, s);     \
+            if (c.rs == RS_HLLC) return sweep_one<D, PHYS_RMHD, PRED_MH, RK_LIN, RS_HLLC>(c, nb, a, s);           \
             return sweep_one<D, PHYS_RMHD, PRED_MH, RK_LIN, RS_HLL>(c, nb, a, s);                                 \
         }                                                                                                        \
         if (c.phys == PHYS_RMHD_TM) {                                                                            \
             if (c.rs == RS_RUSANOV) return sweep_one<D, PHYS_RMHD_TM, PRED_MH, RK_LIN, RS_RUSANOV>(c, nb, a, s);  \
+            if (c.rs == RS_HLLC) return sweep_one<D, PHYS_RMHD_TM, PRED_MH, RK_LIN, RS_HLLC>(c, nb, a, s);        \
             return sweep_one<D, PHYS_RMHD_TM, PRED_MH, RK_LIN, RS_HLL>(c, nb, a, s);                              \
         }                                                                                                        \
         if (c.pred == PRED_MH) {                                                                                 \
@@ -116,10 +118,14 @@ template <> inline hipError_t launch_sweep<double>(int D, const Combo &c, int nb
         /* the HLL fallback changes only HLLD runs */                                                           \
         if (c.phys == PHYS_RMHD && c.rs == RS_RUSANOV)                                                           \
             hipLaunchKernelGGL((k_tcouple<DIM, PHYS_RMHD, RS_RUSANOV, 0, VAR_GENERIC, R>), dim3(nb), dim3(NT), 0, s, a); \
+        else if (c.phys == PHYS_RMHD && c.rs == RS_HLLC)                                                         \
+            hipLaunchKernelGGL((k_tcouple<DIM, PHYS_RMHD, RS_HLLC, 0, VAR_GENERIC, R>), dim3(nb), dim3(NT), 0, s, a); \
         else if (c.phys == PHYS_RMHD)                                                                            \
             hipLaunchKernelGGL((k_tcouple<DIM, PHYS_RMHD, RS_HLL, 0, VAR_GENERIC, R>), dim3(nb), dim3(NT), 0, s, a); \
         else if (c.phys == PHYS_RMHD_TM && c.rs == RS_RUSANOV)                                                   \
             hipLaunchKernelGGL((k_tcouple<DIM, PHYS_RMHD_TM, RS_RUSANOV, 0, VAR_GENERIC, R>), dim3(nb), dim3(NT), 0, s, a); \
+        else if (c.phys == PHYS_RMHD_TM && c.rs == RS_HLLC)                                                      \
+            hipLaunchKernelGGL((k_tcouple<DIM, PHYS_RMHD_TM, RS_HLLC, 0, VAR_GENERIC, R>), dim3(nb), dim3(NT), 0, s, a); \
         else if (c.phys == PHYS_RMHD_TM)                                                                         \
             hipLaunchKernelGGL((k_tcouple<DIM, PHYS_RMHD_TM, RS_HLL, 0, VAR_GENERIC, R>), dim3(nb), dim3(NT), 0, s, a); \
         else if (c.rs == RS_RUSANOV && c.fast)                                                                   \
