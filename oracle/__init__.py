@@ -23,6 +23,7 @@ PRED = {"char": 0, "mh": 1}
 WREF = {"face": 0, "cell": 1, "cw84": 2}
 RIEMANN = {"hlld": 0, "hll": 1, "rusanov": 2, "hllc": 3, "roe": 4}
 EOS = {"ideal": 0, "tm": 1}
+CORNER = {"tn": 0, "mt": 1}  # Eq. transv with t^n fluxes, or predictor fluxes
 PARAB_VISC, PARAB_RES, PARAB_TC = 1, 2, 4
 
 
@@ -47,13 +48,14 @@ class Opts(C.Structure):
         ("kappa_par", C.c_double), ("kappa_perp", C.c_double), ("tc_phi", C.c_double),
         ("cooling", C.c_int), ("cool_beta", C.c_double), ("T_floor", C.c_double),
         ("hyperbolic_off", C.c_int), ("shock_eps", C.c_double), ("eos", C.c_int), ("exact_speeds", C.c_int),
+        ("corner", C.c_int),
     ]
 
 
 def make_opts(dim=3, physics="mhd", recon="ppm", predictor="char", wref="face", riemann="hlld", gamma=5.0 / 3.0,
               dx=(1.0, 1.0, 1.0), glm=True, glm_alpha=0.1, parabolic_mask=0, nu=0.0, eta=0.0, kappa_par=0.0,
               kappa_perp=0.0, tc_phi=0.0, cooling=False, cool_beta=0.5, T_floor=0.0, hyperbolic_off=False,
-              shock_eps=0.0, eos="ideal", exact_speeds=False) -> Opts:
+              shock_eps=0.0, eos="ideal", exact_speeds=False, corner="tn") -> Opts:
     o = Opts()
     o.dim = dim
     o.physics = PHYS[physics]
@@ -63,6 +65,7 @@ def make_opts(dim=3, physics="mhd", recon="ppm", predictor="char", wref="face", 
     o.riemann = RIEMANN[riemann]
     o.eos = EOS[eos]
     o.exact_speeds = int(bool(exact_speeds))
+    o.corner = CORNER[corner]
     o.gamma = gamma
     for q in range(3):
         o.dx[q] = dx[q]

@@ -45,6 +45,7 @@ enum { REC_LIN_MC = 0, REC_LIN_MINMOD = 1, REC_LIN_VANLEER = 2, REC_LIN_VANALBAD
 enum { PRED_CHAR = 0, PRED_MH = 1 };
 enum { WREF_FACE = 0, WREF_CELL = 1, WREF_CW84 = 2 };
 enum { RS_HLLD = 0, RS_HLL = 1, RS_RUSANOV = 2, RS_HLLC = 3, RS_ROE = 4 };
+enum { CORNER_TN = 0, CORNER_MT = 1 };
 enum { FAIL_RHO = 0, FAIL_PRS = 1, FAIL_NEWTON = 2, FAIL_VEL = 3, FAIL_NAN = 4, NFAIL = 5 };
 
 #define PARAB_VISC 1u
@@ -65,6 +66,7 @@ typedef struct {
     double shock_eps; /* App. B shock detection threshold eps_q; 0 = off */
     int eos;          /* RMHD equation of state: EOS_IDEAL (Eq. gammaEos) or EOS_TM (Eq. TMEos) */
     int exact_speeds; /* RMHD signal speeds: 0 = isotropic bound, 1 = fast roots of the quartic */
+    int corner;       /* CORNER_TN (Eq. transv with t^n fluxes) or CORNER_MT (predictor fluxes) */
 } orc_opts;
 
 enum { EOS_IDEAL = 0, EOS_TM = 1 };
@@ -1575,7 +1577,10 @@ int orc_step(const orc_opts *o, int nx, int ny, int nz, int ng, const double *U_
     if (o->predictor == PRED_MH && (o->recon == REC_PPM || o->recon == REC_WENO3)) return -3;
     if (o->physics == PHYS_RMHD && (o->parabolic_mask || o->cooling)) return -4;
     if (o->glm && !(ch > 0.0)) return -5;
+    int mt = (o->corner == CORNER_MT);
+    if (mt && (o->parabolic_mask || o->hyperbolic_off || o->shock_eps > 0.0)) return -7;
     int need = (o->recon == REC_PPM ? 3 : 2) + (o->parabolic_mask ? 1 : 0);
+    if (mt && need < 3) need = 3;
     if (ng < need) return -6;
 
     grid_t g;
@@ -1594,7 +1599,9 @@ int orc_step(const orc_opts *o, int nx, int ny, int nz, int ng, const double *U_
     int hyp = !o->hyperbolic_off;
 
     double *V = calloc(NVAR * NC, sizeof(double));
-    double *Fn = calloc(3 * NVAR * NC, sizeof(double)); /* t^n Godunov fluxes */
+    double *Fn = calloc(3 * NVAR * NC, sizeof(double)); /* t^n Godunov fluxes (MT: predictor fluxes) */
+    double *PVm = mt ? calloc(NVAR * NC, sizeof(double)) : NULL; /* MT: normal-predictor states */
+    double *PVp = mt ? calloc(NVAR * NC, sizeof(double)) : NULL;
     double *Pn = calloc(3 * NVAR * NC, sizeof(double)); /* t^n parabolic fluxes */
     double *Ln = calloc(3 * NVAR * NC, sizeof(double)); /* -dF/dx per direction */
     double *LPn = calloc(3 * NVAR * NC, sizeof(double)); /* +dPi/dx per direction */
@@ -1627,8 +1634,46 @@ int orc_step(const orc_opts *o, int nx, int ny, int nz, int ng, const double *U_
     o_mm.recon = REC_LIN_MINMOD;
 
     /* 2-3. first-order Godunov fluxes and parabolic fluxes at t^n, on every
-     * face whose stencil lies inside the ghosted box */
+     * face whose stencil lies inside the ghosted box.  With the MT corner
+     * coupling (no parabolic terms) the transverse fluxes are instead the
+     * Riemann fluxes between the normal-predictor states of the two cells
+     * of a face (the predictor of step 4), on the faces whose both cells
+     * have their whole predictor stencil inside the box. */
     for (int d = 0; d < dim; d++) {
+        if (mt) {
+            int dummy[NFAIL] = { 0 };
+            for (int k = 0; k < g.NZ; k++)
+                for (int j = 0; j < g.NY; j++)
+                    for (int i = 0; i < g.NX; i++) {
+                        int ci[3] = { i, j, k };
+                        if (ci[d] < 2 || ci[d] > N[d] - 3) continue;
+                        long c = cidx(&g, i, j, k);
+                        double Vs[5][NVAR], U0[NVAR], Vm[NVAR], Vp[NVAR];
+                        for (int l = -2; l <= 2; l++) {
+                            long cl = cidx(&g, i + l * offs[d][0], j + l * offs[d][1], k + l * offs[d][2]);
+                            for (int q = 0; q < NVAR; q++) Vs[l + 2][q] = V[q * NC + cl];
+                        }
+                        for (int q = 0; q < NVAR; q++) U0[q] = U_in[q * NC + c];
+                        if (o->predictor == PRED_CHAR) predict_char(o, Vs, d, dt, ch, Vm, Vp);
+                        else predict_mh(o, Vs, U0, d, dt, ch, Vm, Vp, dummy);
+                        for (int q = 0; q < NVAR; q++) {
+                            PVm[q * NC + c] = Vm[q];
+                            PVp[q * NC + c] = Vp[q];
+                        }
+                    }
+            for (int k = 0; k < g.NZ; k++)
+                for (int j = 0; j < g.NY; j++)
+                    for (int i = 0; i < g.NX; i++) {
+                        int ci[3] = { i, j, k };
+                        if (ci[d] < 3 || ci[d] > N[d] - 3) continue;
+                        long cB = cidx(&g, i, j, k);
+                        long cA = cidx(&g, i - offs[d][0], j - offs[d][1], k - offs[d][2]);
+                        double VL[NVAR], VR[NVAR], F[NVAR], sm;
+                        for (int q = 0; q < NVAR; q++) { VL[q] = PVp[q * NC + cA]; VR[q] = PVm[q * NC + cB]; }
+                        riemann(o, VL, VR, d, ch, F, &sm);
+                        for (int q = 0; q < NVAR; q++) Fn[(d * NVAR + q) * NC + cB] = F[q];
+                    }
+        }
         for (int k = 0; k < g.NZ; k++)
             for (int j = 0; j < g.NY; j++)
                 for (int i = 0; i < g.NX; i++) {
@@ -1638,7 +1683,7 @@ int orc_step(const orc_opts *o, int nx, int ny, int nz, int ng, const double *U_
                     long cA = cidx(&g, i - offs[d][0], j - offs[d][1], k - offs[d][2]);
                     double VL[NVAR], VR[NVAR], F[NVAR], sm;
                     for (int q = 0; q < NVAR; q++) { VL[q] = V[q * NC + cA]; VR[q] = V[q * NC + cB]; }
-                    if (hyp) {
+                    if (hyp && !mt) {
                         int hl = (flag[cA] | flag[cB]) & FLAG_HLL;
                         riemann(hl ? &o_hll : o, VL, VR, d, ch, F, &sm);
                         for (int q = 0; q < NVAR; q++) Fn[(d * NVAR + q) * NC + cB] = F[q];
@@ -1870,6 +1915,7 @@ int orc_step(const orc_opts *o, int nx, int ny, int nz, int ng, const double *U_
 
     free(flag);
     free(V); free(Fn); free(Pn); free(Ln); free(LPn); free(Uhm); free(Uhp); free(Fh); free(Ph);
+    free(PVm); free(PVp);
     free(lamf); free(pfL); free(pfR); free(rfL); free(rfR); free(Uhalf); free(Vhalf);
     return 0;
 }
