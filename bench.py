@@ -399,11 +399,12 @@ def main():
     def run_variants():
         """The same FP32 workload under the option sets of the widened rows:
         the App. B shock-adaptive hybrid (flags from V^n every step, HLL and
-        MinMod where flagged), the Rusanov, HLLC and Roe solvers; and the relativistic
+        MinMod where flagged), the Rusanov, HLLC and Roe solvers, the MT corner coupling; and the relativistic
         workload under both equations of state.  Tuned, graph-replayed."""
         out = {}
         variants = {"shock_hybrid": dict(riemann="hlld", shock_eps=5.0), "rusanov": dict(riemann="rusanov"),
-                    "hllc": dict(riemann="hllc"), "roe": dict(riemann="roe")}
+                    "hllc": dict(riemann="hllc"), "roe": dict(riemann="roe"),
+                    "mt_corner": dict(riemann="hlld", corner="mt")}
         for name, kw in variants.items():
             o = ctu.make_opts(dim=3, recon="ppm", gamma=gamma, dx=dx, precision="fp32", **kw)
             p = ctu.Plan(o, box, ng)

@@ -91,6 +91,15 @@ typedef enum { CTU_HLLD = 0, CTU_HLL = 1, CTU_RUSANOV = 2, CTU_HLLC = 3, CTU_ROE
  * w = 5p/2 + sqrt(9p^2/4 + rho^2); gamma is then unused). */
 typedef enum { CTU_EOS_IDEAL = 0, CTU_EOS_TM = 1 } ctu_eos;
 
+/* Sec. 3.1 corner coupling of the face states: TN, Eq. transv with the
+ * transverse increments of first-order Riemann fluxes between the t^n cell
+ * states (every option set; the default), or MT, for runs without parabolic
+ * terms, with the transverse increments of Riemann fluxes between the
+ * normal-predictor states of the two cells of each face (the form the paper
+ * takes from Mignone & Tzeferacos 2010 when Pi = 0; needs nghost >= 3, no
+ * shock_eps, hyperbolic fluxes on). */
+typedef enum { CTU_CORNER_TN = 0, CTU_CORNER_MT = 1 } ctu_corner;
+
 #define CTU_PARAB_VISC 1u /* Eq. visc_tens */
 #define CTU_PARAB_RES 2u  /* resistive term -curl(eta J) */
 #define CTU_PARAB_TC 4u   /* Eq. tc_flux with the App. A saturated flux */
@@ -129,6 +138,8 @@ typedef struct {
                               velocity addition), 1 = the exact fast magnetosonic speeds (the
                               outermost roots of the dispersion quartic); ignored for MHD,
                               whose fast speeds are exact */
+    int32_t corner;        /* ctu_corner */
+    int32_t pad2;
 } ctu_opts;
 
 /* One ghosted box: interior cells [lo, lo+n) in level-global indices.

@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libctu.so")
 BUILD = os.path.join(HERE, "_build")
-UNITS = ["ctu_lib.hip", "ctu_inst_f32.hip", "ctu_inst_f64.hip"]
+UNITS = ["ctu_lib.hip", "ctu_inst_f32.hip", "ctu_inst_f64.hip", "ctu_inst_mt_f32.hip", "ctu_inst_mt_f64.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [
@@ -35,7 +35,8 @@ FLAGS = [
 # single instructions without range scaling (the state variables stay many
 # orders of magnitude above 1e-38); FP64 keeps the correctly rounded forms
 # and subnormals.
-UNIT_FLAGS = {"ctu_inst_f32.hip": ["-fno-hip-fp32-correctly-rounded-divide-sqrt", "-fgpu-flush-denormals-to-zero"]}
+_F32 = ["-fno-hip-fp32-correctly-rounded-divide-sqrt", "-fgpu-flush-denormals-to-zero"]
+UNIT_FLAGS = {"ctu_inst_f32.hip": _F32, "ctu_inst_mt_f32.hip": _F32}
 
 
 def _compile(unit: str, extra: list[str], build_dir: str = BUILD) -> str:

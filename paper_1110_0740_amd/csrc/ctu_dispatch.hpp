@@ -28,6 +28,8 @@ __host__ inline bool combo_supported(const Combo &c)
 
 hipError_t launch_sweep_f32(int D, const Combo &c, int nblocks, const SweepArgs<float> &a, hipStream_t s);
 hipError_t launch_sweep_f64(int D, const Combo &c, int nblocks, const SweepArgs<double> &a, hipStream_t s);
+hipError_t launch_mtflux_f32(int D, const Combo &c, int nblocks, const MtArgs<float> &a, hipStream_t s);
+hipError_t launch_mtflux_f64(int D, const Combo &c, int nblocks, const MtArgs<double> &a, hipStream_t s);
 hipError_t launch_tcouple_f32(int dim, int par, const Combo &c, int nblocks, const TArgs<float> &a, hipStream_t s);
 hipError_t launch_tcouple_f64(int dim, int par, const Combo &c, int nblocks, const TArgs<double> &a, hipStream_t s);
 
@@ -158,5 +160,45 @@ template <> inline hipError_t launch_sweep<double>(int D, const Combo &c, int nb
         if (nb <= 0) return hipSuccess;                                                                          \
         if (dim == 2) return par ? tc_one<2, 1>(c, nb, a, s) : tc_one<2, 0>(c, nb, a, s);                        \
         return par ? tc_one<3, 1>(c, nb, a, s) : tc_one<3, 0>(c, nb, a, s);                                      \
+    }                                                                                                            \
+    }
+
+// Body of one precision's MT predictor-flux translation unit: k_mtflux for
+// every supported (physics, predictor, reconstruction, solver) set.
+#define CTU_DEFINE_MT_DISPATCH(R, SUFFIX)                                                                         \
+    namespace ctu {                                                                                              \
+    template <int D, int PHYS, int PRED, int RK, int RS>                                                         \
+    static hipError_t mt_one(int nb, const MtArgs<R> &a, hipStream_t s)                                         \
+    {                                                                                                            \
+        hipLaunchKernelGGL((k_mtflux<D, PHYS, PRED, RK, RS, R>), dim3(nb), dim3(NT), 0, s, a);                 \
+        return hipGetLastError();                                                                                \
+    }                                                                                                            \
+    template <int D, int PHYS, int PRED, int RK>                                                                 \
+    static hipError_t mt_rs(const Combo &c, int nb, const MtArgs<R> &a, hipStream_t s)                          \
+    {                                                                                                            \
+        if constexpr (PHYS == PHYS_MHD) {                                                                        \
+            if (c.rs == RS_HLLD) return mt_one<D, PHYS, PRED, RK, RS_HLLD>(nb, a, s);                           \
+            if (c.rs == RS_ROE) return mt_one<D, PHYS, PRED, RK, RS_ROE>(nb, a, s);                             \
+        }                                                                                                        \
+        if (c.rs == RS_RUSANOV) return mt_one<D, PHYS, PRED, RK, RS_RUSANOV>(nb, a, s);                         \
+        if (c.rs == RS_HLLC) return mt_one<D, PHYS, PRED, RK, RS_HLLC>(nb, a, s);                               \
+        return mt_one<D, PHYS, PRED, RK, RS_HLL>(nb, a, s);                                                      \
+    }                                                                                                            \
+    template <int D>                                                                                             \
+    static hipError_t mt_dir(const Combo &c, int nb, const MtArgs<R> &a, hipStream_t s)                         \
+    {                                                                                                            \
+        if (c.phys == PHYS_RMHD) return mt_rs<D, PHYS_RMHD, PRED_MH, RK_LIN>(c, nb, a, s);                      \
+        if (c.phys == PHYS_RMHD_TM) return mt_rs<D, PHYS_RMHD_TM, PRED_MH, RK_LIN>(c, nb, a, s);                \
+        if (c.pred == PRED_MH) return mt_rs<D, PHYS_MHD, PRED_MH, RK_LIN>(c, nb, a, s);                         \
+        if (c.rk == RK_PPM) return mt_rs<D, PHYS_MHD, PRED_CHAR, RK_PPM>(c, nb, a, s);                          \
+        if (c.rk == RK_WENO) return mt_rs<D, PHYS_MHD, PRED_CHAR, RK_WENO>(c, nb, a, s);                        \
+        return mt_rs<D, PHYS_MHD, PRED_CHAR, RK_LIN>(c, nb, a, s);                                               \
+    }                                                                                                            \
+    hipError_t launch_mtflux_##SUFFIX(int D, const Combo &c, int nb, const MtArgs<R> &a, hipStream_t s)        \
+    {                                                                                                            \
+        if (nb <= 0) return hipSuccess;                                                                          \
+        if (D == 0) return mt_dir<0>(c, nb, a, s);                                                               \
+        if (D == 1) return mt_dir<1>(c, nb, a, s);                                                               \
+        return mt_dir<2>(c, nb, a, s);                                                                           \
     }                                                                                                            \
     }

@@ -676,6 +676,109 @@ __global__ __launch_bounds__(NT) void k_tcouple(TArgs<R> a)
 }
 
 // ---------------------------------------------------------------------------
+// MT corner coupling (runs without parabolic terms): the transverse fluxes of
+// Eq. transv are Riemann fluxes between the normal-predictor states of the
+// two cells of a face instead of first-order t^n fluxes.
+//   k_mtflux<D>  one thread per ghosted cell (cell tiles): the face below it
+//                along D, for D-faces g..g+n at transverse positions
+//                g-1..g+n; both cells' normal predictors (the sweep's own
+//                predictor, from the six-cell stencil c-3..c+2 along D) and
+//                the Riemann solve, stored on the face below the cell;
+//   k_mtT        T_d = sum_{e != d} -(F_e(c + e) - F_e(c)) / dx_e on the cells
+//                the sweep of d reads (d-layer g-1..g+n, interior across d).
+// ---------------------------------------------------------------------------
+
+template <typename R> struct MtArgs {
+    const KBox *boxes;
+    const KTile *tiles;   // cell tiles: (box, first cell), NT cells each
+    const R *U;           // U^n (caller layout)
+    const R *V;           // V^n (workspace)
+    R *F[3];              // predictor fluxes per direction (workspace)
+    R *T[3];              // transverse increments (workspace)
+    const double *params;
+    KOpts o;
+};
+
+template <int D, int PHYS, int PRED, int RK, int RS, typename R>
+__global__ __launch_bounds__(NT) void k_mtflux(MtArgs<R> a)
+{
+    const KTile tl = a.tiles[blockIdx.x];
+    const KBox bx = a.boxes[tl.box];
+    const int c = tl.a + (int)threadIdx.x;
+    if (c >= bx.cells) return;
+    const KOpts &o = a.o;
+    const int dim = o.dim;
+    const int cc[3] = { c % bx.N[0], (c / bx.N[0]) % bx.N[1], c / (bx.N[0] * bx.N[1]) };
+#pragma unroll
+    for (int e = 0; e < 3; e++) {
+        if (e >= dim) continue;
+        const int lo = (e == D) ? bx.g[e] : bx.g[e] - 1;
+        if (cc[e] < lo || cc[e] > bx.g[e] + bx.n[e]) return;
+    }
+    const int sD = (D == 0) ? 1 : (D == 1 ? bx.N[0] : bx.N[0] * bx.N[1]);
+    const R gam = R(o.gamma);
+    const R dt = R(a.params[0]), ch = R(a.params[1]);
+    const R dxD = R(bx.dx[D]);
+    const R dtdx = dt / dxD;
+    const Blk<R> bV(a.V + bx.woff, bx.cells);
+    // cells c-3 .. c+2 along D: W[0..4] is the stencil of the cell below the
+    // face, W[1..5] that of the cell above (linear / WENO3 read W[1..4])
+    R W[6][NV];
+    constexpr int w0 = (RK == RK_PPM) ? 0 : 1, w1 = (RK == RK_PPM) ? 6 : 5;
+#pragma unroll
+    for (int l = w0; l < w1; l++) ld_cell(bV, c + (l - 3) * sD, W[l]);
+    R VmL[NV], VpL[NV], VmR[NV], VpR[NV];
+    if constexpr (PRED == PRED_CHAR) {
+        predict_char<D, RK>(W, o, gam, dtdx, dxD, ch, VmL, VpL, o.limiter);
+        predict_char<D, RK>(W + 1, o, gam, dtdx, dxD, ch, VmR, VpR, o.limiter);
+    } else {
+        const Blk<R> bU(a.U + bx.uoff, bx.cells);
+        R U0[NV];
+        ld_cell(bU, c - sD, U0);
+        (void)predict_mh<D, PHYS>(W, U0, o, gam, dtdx, ch, VmL, VpL, o.limiter);
+        ld_cell(bU, c, U0);
+        (void)predict_mh<D, PHYS>(W + 1, U0, o, gam, dtdx, ch, VmR, VpR, o.limiter);
+    }
+    R F[NV], smax;
+    riemann<D, PHYS, RS>(VpL, VmR, F, smax, gam, ch, o.glm, o.xspeeds);
+    const Blk<R> bF(a.F[D] + bx.woff, bx.cells);
+#pragma unroll
+    for (int q = 0; q < NV; q++) bF.st(q, c, F[q]);
+}
+
+template <typename R>
+__global__ __launch_bounds__(NT) void k_mtT(MtArgs<R> a)
+{
+    const KTile tl = a.tiles[blockIdx.x];
+    const KBox bx = a.boxes[tl.box];
+    const int c = tl.a + (int)threadIdx.x;
+    if (c >= bx.cells) return;
+    const int dim = a.o.dim;
+    const int cc[3] = { c % bx.N[0], (c / bx.N[0]) % bx.N[1], c / (bx.N[0] * bx.N[1]) };
+    const int st[3] = { 1, bx.N[0], bx.N[0] * bx.N[1] };
+    for (int d = 0; d < dim; d++) {
+        bool ok = cc[d] >= bx.g[d] - 1 && cc[d] <= bx.g[d] + bx.n[d];
+        for (int e = 0; e < dim; e++)
+            if (e != d) ok = ok && cc[e] >= bx.g[e] && cc[e] < bx.g[e] + bx.n[e];
+        if (!ok) continue;
+        const Blk<R> bT(a.T[d] + bx.woff, bx.cells);
+#pragma unroll
+        for (int q = 0; q < NV; q++) {
+            R t = R(0);
+            bool first = true;
+            for (int e = 0; e < dim; e++) {
+                if (e == d) continue;
+                const Blk<R> bF(a.F[e] + bx.woff, bx.cells);
+                const R L = -(bF.ld(q, c + st[e]) - bF.ld(q, c)) * R(1.0 / bx.dx[e]);
+                t = first ? L : t + L;
+                first = false;
+            }
+            bT.st(q, c, t);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // k_sweep<D>: one direction of the corner-coupled update.
 //
 // A block owns a column of transverse positions and marches along D over

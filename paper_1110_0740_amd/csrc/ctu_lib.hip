@@ -83,6 +83,7 @@ struct ctu_plan {
     // workspace fields: V^n, the transverse increments T_d, V^{n+1/2}, rate
     void *wsV = nullptr, *wsT[3] = { nullptr, nullptr, nullptr };
     void *wsVh = nullptr, *wsLam = nullptr;
+    void *wsF[3] = { nullptr, nullptr, nullptr };  // MT corner coupling: predictor fluxes per direction
     unsigned char *wsFlag = nullptr;  // App. B zone flags (one byte per cell) or null
     int64_t ws_bytes = 0;
     // cells entering the cooling time-step estimate (caller-owned) or null
@@ -117,7 +118,7 @@ void free_plan(ctu_plan *p)
     if (p->graph) (void)hipGraphDestroy(p->graph);
     void *ptrs[] = { p->dboxes, p->dregs, p->drface, p->t_cells.d, p->t_tc.d, p->t_sweep[0].d, p->t_sweep[1].d,
                      p->t_sweep[2].d, p->t_cfl.d, p->wsV, p->wsT[0], p->wsT[1], p->wsT[2], p->wsVh, p->wsLam, p->wsFlag,
-                     p->drefl, p->dcell_start };
+                     p->drefl, p->dcell_start, p->wsF[0], p->wsF[1], p->wsF[2] };
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
     delete p;
@@ -311,7 +312,30 @@ ctu_status enqueue_step(ctu_plan *p, const void *U_in, void *U_out, const double
         }
     }
     HIP_TRY(hipGetLastError());
-    {
+    if (p->opts.corner == CTU_CORNER_MT) {
+        StageTimer tm(p, 1, s);
+        MtArgs<R> ma;
+        ma.boxes = p->dboxes;
+        ma.tiles = p->t_cells.d;
+        ma.U = (const R *)U_in;
+        ma.V = (const R *)p->wsV;
+        for (int d = 0; d < 3; d++) {
+            ma.F[d] = (R *)p->wsF[d];
+            ma.T[d] = (R *)p->wsT[d];
+        }
+        ma.params = params;
+        ma.o = p->ko;
+        for (int D = 0; D < dim; D++) {
+            hipError_t e;
+            if constexpr (sizeof(R) == 4)
+                e = launch_mtflux_f32(D, p->combo, p->t_cells.n(), ma, s);
+            else
+                e = launch_mtflux_f64(D, p->combo, p->t_cells.n(), ma, s);
+            if (e != hipSuccess) return fail(CTU_ERR_HIP, std::string("MT flux launch: ") + hipGetErrorString(e));
+        }
+        hipLaunchKernelGGL((k_mtT<R>), dim3(p->t_cells.n()), dim3(NT), 0, s, ma);
+        HIP_TRY(hipGetLastError());
+    } else {
         StageTimer tm(p, 1, s);
         TArgs<R> ta;
         ta.boxes = p->dboxes;
@@ -383,9 +407,9 @@ std::string tune_key(const ctu_plan *p)
             h *= 1099511628211ULL;
         }
     char buf[256];
-    std::snprintf(buf, sizeof buf, "p%d d%d ph%d r%d pr%d rs%d w%d g%d pb%u c%d s%d h%u ng%d nb%zu x%016llx", p->esize,
-                  o.dim, o.physics, o.recon, o.predictor, o.riemann, o.wref, o.glm, o.parabolic_mask, o.cooling,
-                  o.shock_eps > 0.0 ? 1 : 0, o.hyperbolic_off, p->nghost, p->hboxes.size(), h);
+    std::snprintf(buf, sizeof buf, "p%d d%d ph%d r%d pr%d rs%d w%d g%d pb%u c%d s%d h%u ng%d nb%zu k%d x%016llx",
+                  p->esize, o.dim, o.physics, o.recon, o.predictor, o.riemann, o.wref, o.glm, o.parabolic_mask,
+                  o.cooling, o.shock_eps > 0.0 ? 1 : 0, o.hyperbolic_off, p->nghost, p->hboxes.size(), o.corner, h);
     return buf;
 }
 
@@ -449,6 +473,10 @@ ctu_status ctu_plan_create(const ctu_opts *opts, const ctu_box *boxes, int32_t n
         return fail(CTU_ERR_ARG, "bad riemann");
     if (o.eos != CTU_EOS_IDEAL && o.eos != CTU_EOS_TM) return fail(CTU_ERR_ARG, "bad eos");
     if (o.exact_speeds != 0 && o.exact_speeds != 1) return fail(CTU_ERR_ARG, "exact_speeds must be 0 or 1");
+    if (o.corner != CTU_CORNER_TN && o.corner != CTU_CORNER_MT) return fail(CTU_ERR_ARG, "bad corner");
+    if (o.corner == CTU_CORNER_MT && (o.parabolic_mask || o.hyperbolic_off || o.shock_eps > 0.0))
+        return fail(CTU_ERR_UNSUPPORTED, "the MT corner coupling needs hyperbolic fluxes without parabolic terms "
+                                         "or shock flags");
     if (o.eos == CTU_EOS_TM && o.physics != CTU_RMHD)
         return fail(CTU_ERR_UNSUPPORTED, "the Taub-Matthews EOS belongs to the RMHD module");
     if (!(o.gamma > 1.0)) return fail(CTU_ERR_ARG, "gamma must exceed 1");
@@ -473,6 +501,7 @@ ctu_status ctu_plan_create(const ctu_opts *opts, const ctu_box *boxes, int32_t n
     if (o.physics == CTU_RMHD && (o.parabolic_mask || o.cooling))
         return fail(CTU_ERR_UNSUPPORTED, "parabolic terms and cooling are MHD only");
     int need = (o.recon == CTU_PPM ? 3 : 2) + (o.parabolic_mask ? 1 : 0);
+    if (o.corner == CTU_CORNER_MT && need < 3) need = 3;
     if (nghost < 3 || nghost < need) return fail(CTU_ERR_ARG, "nghost too small for the stencil");
     if (nreg > 0 && !regfaces) return fail(CTU_ERR_ARG, "regfaces is null");
 
@@ -638,6 +667,12 @@ ctu_status ctu_plan_create(const ctu_opts *opts, const ctu_box *boxes, int32_t n
             return st;
         }
     }
+    if (o.corner == CTU_CORNER_MT)
+        for (int d = 0; d < o.dim; d++)
+            if ((st = alloc_ws(p, &p->wsF[d], f9)) != CTU_OK) {
+                free_plan(p);
+                return st;
+            }
     if (c.shk) {
         if (hipMalloc((void **)&p->wsFlag, p->ws_cells) != hipSuccess) {
             free_plan(p);

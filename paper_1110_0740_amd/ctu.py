@@ -20,6 +20,7 @@ PRED = {"char": 0, "mh": 1}
 WREF = {"face": 0, "cell": 1, "cw84": 2}
 RIEMANN = {"hlld": 0, "hll": 1, "rusanov": 2, "hllc": 3, "roe": 4}
 EOS = {"ideal": 0, "tm": 1}
+CORNER = {"tn": 0, "mt": 1}
 PARAB_VISC, PARAB_RES, PARAB_TC = 1, 2, 4
 NFAIL = 5
 
@@ -46,7 +47,7 @@ class CtuOpts(C.Structure):
         ("nu", C.c_double), ("eta", C.c_double), ("kappa_par", C.c_double), ("kappa_perp", C.c_double),
         ("tc_phi", C.c_double), ("cool_beta", C.c_double), ("T_floor", C.c_double),
         ("hyperbolic_off", C.c_int32), ("pad", C.c_int32), ("shock_eps", C.c_double),
-        ("eos", C.c_int32), ("exact_speeds", C.c_int32),
+        ("eos", C.c_int32), ("exact_speeds", C.c_int32), ("corner", C.c_int32), ("pad2", C.c_int32),
     ]
 
 
@@ -162,7 +163,7 @@ def _check(rc: int):
 def make_opts(dim=3, physics="mhd", precision="fp64", recon="ppm", predictor="char", wref="face", riemann="hlld",
               glm=True, gamma=5.0 / 3.0, dx=(1.0, 1.0, 1.0), glm_alpha=0.1, parabolic_mask=0, cooling=False,
               nu=0.0, eta=0.0, kappa_par=0.0, kappa_perp=0.0, tc_phi=0.0, cool_beta=0.5, T_floor=0.0,
-              hyperbolic_off=False, shock_eps=0.0, eos="ideal", exact_speeds=False) -> CtuOpts:
+              hyperbolic_off=False, shock_eps=0.0, eos="ideal", exact_speeds=False, corner="tn") -> CtuOpts:
     o = CtuOpts()
     o.dim = dim
     o.physics = {"mhd": MHD, "rmhd": RMHD}[physics]
@@ -184,6 +185,7 @@ def make_opts(dim=3, physics="mhd", precision="fp64", recon="ppm", predictor="ch
     o.shock_eps = shock_eps
     o.eos = EOS[eos]
     o.exact_speeds = int(bool(exact_speeds))
+    o.corner = CORNER[corner]
     return o
 
 
