@@ -632,6 +632,212 @@ static void riemann_hllc_rmhd(const orc_opts *o, const double *VL, const double 
     for (int v = 0; v < NVAR; v++) F[v] = ok ? Fk[v] + S * (Us[v] - U[v]) : Fh[v];
 }
 
+/* HLLD for relativistic MHD (Mignone, Ugliano & Bodo 2009), for states
+ * sharing B_n.  Five waves: the outer fast waves S_L, S_R (HLL's speeds),
+ * two rotational discontinuities and the contact, with the total pressure
+ * p uniform between the fast waves.  E is the total energy U[ENG] + D.
+ *  - Across a fast wave S with R = S U - F (known from the outer state), the
+ *    state a for a trial p has, with A = R_mn - S R_E + p (1 - S^2),
+ *    G = R_Bt^2 + R_Bb^2, C = R_mt R_Bt + R_mb R_Bb, Q = -A - G + B_n^2 (1 - S^2)
+ *    and X = B_n (A S B_n + C) - (A + G)(S p + R_E):
+ *      v_n = (B_n (A B_n + S C) - (A + G)(p + R_mn)) / X,
+ *      v_t = (Q R_mt + R_Bt (C + B_n (S R_mn - R_E))) / X  (and b),
+ *      B_t = (R_Bt - B_n v_t) / (S - v_n),  w_t = p + (R_E - v.R_m) / (S - v_n),
+ *    D_a = R_D / (S - v_n), E_a = (R_E + p v_n - (v.B) B_n) / (S - v_n),
+ *    m_a = (E_a + p) v - (v.B) B.
+ *  - The rotational discontinuity next to it moves at K_n with
+ *      K = (R_m + p e_n + eta R_B) / (S p + R_E + eta B_n),
+ *    eta = -+ sgn(B_n) sqrt(w_t) on the left / right (R_Bn = S B_n).
+ *  - The contact region holds B_c, the field that conserves B across the two
+ *    rotational discontinuities,
+ *      B_c = ((B (K_n - v_n) + B_n v)_R - (B (K_n - v_n) + B_n v)_L) / (K_nR - K_nL),
+ *    and on each side v_c = K - B_c (1 - K^2) / (eta - K.B_c).
+ *  - p solves v_cn(R) - v_cn(L) = 0 (secant iteration from the HLLC estimate
+ *    of p_t* and 1.025 times it, until successive iterates agree to 1e-14).
+ *  - The contact states follow from the jump conditions across the
+ *    rotational discontinuities: D_c = D_a (K_n - v_an) / (K_n - v_cn),
+ *    E_c = (K_n E_a - m_an + p v_cn - (v_c.B_c) B_n) / (K_n - v_cn),
+ *    m_c = (E_c + p) v_c - (v_c.B_c) B_c.
+ * The flux of the region holding the interface follows by F* = F + S (U* - U)
+ * across each wave in turn.  B_n = 0 (B_n^2 <= 1e-12 (B_n^2 + B^hll_t^2)), or
+ * a fan that is not admissible (no convergence, |v| >= 1, D <= 0, w_t <= p,
+ * or wave speeds out of order), gives the HLLC flux. */
+static void riemann_hllc_rmhd(const orc_opts *o, const double *VL, const double *VR, int d, double ch, double *F,
+                              double *smax);
+
+typedef struct {
+    double U[8]; /* D, m_n, m_t, m_b, E, B_n, B_t, B_b */
+    double v[3], B[3], wt, eta, K[3];
+    int ok;
+} rhlld_side;
+
+/* state a behind a fast wave of speed S for the trial pressure p */
+static void rhlld_astate(const double *R, double S, double p, double Bn, double sg, rhlld_side *a)
+{
+    double A = R[1] - S * R[4] + p * (1.0 - S * S);
+    double G = R[6] * R[6] + R[7] * R[7];
+    double C = R[2] * R[6] + R[3] * R[7];
+    double Q = -A - G + Bn * Bn * (1.0 - S * S);
+    double X = Bn * (A * S * Bn + C) - (A + G) * (S * p + R[4]);
+    a->v[0] = (Bn * (A * Bn + S * C) - (A + G) * (p + R[1])) / X;
+    a->v[1] = (Q * R[2] + R[6] * (C + Bn * (S * R[1] - R[4]))) / X;
+    a->v[2] = (Q * R[3] + R[7] * (C + Bn * (S * R[1] - R[4]))) / X;
+    double iS = 1.0 / (S - a->v[0]);
+    a->B[0] = Bn;
+    a->B[1] = (R[6] - Bn * a->v[1]) * iS;
+    a->B[2] = (R[7] - Bn * a->v[2]) * iS;
+    a->wt = p + (R[4] - (a->v[0] * R[1] + a->v[1] * R[2] + a->v[2] * R[3])) * iS;
+    double vB = a->v[0] * a->B[0] + a->v[1] * a->B[1] + a->v[2] * a->B[2];
+    a->U[0] = R[0] * iS;
+    a->U[4] = (R[4] + p * a->v[0] - vB * Bn) * iS;
+    for (int k = 0; k < 3; k++) a->U[1 + k] = (a->U[4] + p) * a->v[k] - vB * a->B[k];
+    for (int k = 0; k < 3; k++) a->U[5 + k] = a->B[k];
+    double v2 = a->v[0] * a->v[0] + a->v[1] * a->v[1] + a->v[2] * a->v[2];
+    a->ok = isfinite(X) && X != 0.0 && v2 < 1.0 && a->wt > p && a->U[0] > 0.0;
+    a->eta = sg * sgn1(Bn) * sqrt(fmax(a->wt, 0.0));
+    double den = S * p + R[4] + a->eta * Bn;
+    a->K[0] = (R[1] + p + a->eta * R[5]) / den;
+    a->K[1] = (R[2] + a->eta * R[6]) / den;
+    a->K[2] = (R[3] + a->eta * R[7]) / den;
+}
+
+/* both sides for the trial p; returns v_cn(R) - v_cn(L) and the contact data */
+static double rhlld_fan(const double *RL, const double *RR, double SL, double SR, double p, double Bn,
+                        rhlld_side *aL, rhlld_side *aR, double *Bc, double *vcL, double *vcR)
+{
+    rhlld_astate(RL, SL, p, Bn, -1.0, aL);
+    rhlld_astate(RR, SR, p, Bn, +1.0, aR);
+    double dK = aR->K[0] - aL->K[0];
+    Bc[0] = Bn;
+    for (int k = 1; k < 3; k++)
+        Bc[k] = ((aR->B[k] * (aR->K[0] - aR->v[0]) + Bn * aR->v[k]) - (aL->B[k] * (aL->K[0] - aL->v[0]) + Bn * aL->v[k])) /
+                dK;
+    const rhlld_side *sd[2] = { aL, aR };
+    double *vc[2] = { vcL, vcR };
+    for (int s2 = 0; s2 < 2; s2++) {
+        const double *K = sd[s2]->K;
+        double K2 = K[0] * K[0] + K[1] * K[1] + K[2] * K[2];
+        double KB = K[0] * Bc[0] + K[1] * Bc[1] + K[2] * Bc[2];
+        double y = (1.0 - K2) / (sd[s2]->eta - KB);
+        for (int k = 0; k < 3; k++) vc[s2][k] = K[k] - Bc[k] * y;
+    }
+    return vcR[0] - vcL[0];
+}
+
+static void riemann_hlld_rmhd(const orc_opts *o, const double *VL, const double *VR, int d, double ch, double *F,
+                              double *smax)
+{
+    int n, t, b;
+    dir_axes(d, &n, &t, &b);
+    double lminL, lmaxL, lminR, lmaxR;
+    signal_speeds(o, VL, d, &lminL, &lmaxL);
+    signal_speeds(o, VR, d, &lminR, &lmaxR);
+    double SL = fmin(lminL, lminR), SR = fmax(lmaxL, lmaxR);
+    *smax = fmax(fabs(SL), fabs(SR));
+    double UL9[NVAR], UR9[NVAR], FL9[NVAR], FR9[NVAR];
+    prim2cons(o, VL, UL9);
+    prim2cons(o, VR, UR9);
+    phys_flux(o, VL, d, ch, FL9);
+    phys_flux(o, VR, d, ch, FR9);
+    if (SL >= 0.0) { memcpy(F, FL9, sizeof(FL9)); return; }
+    if (SR <= 0.0) { memcpy(F, FR9, sizeof(FR9)); return; }
+    /* rotated 8-vectors with the total energy; the hyperbolic B_n flux is 0 */
+    double UL[8], UR[8], FL[8], FR[8];
+    const int map[8] = { RHO, MX1 + n, MX1 + t, MX1 + b, ENG, BX1 + n, BX1 + t, BX1 + b };
+    for (int k = 0; k < 8; k++) {
+        UL[k] = UL9[map[k]];
+        UR[k] = UR9[map[k]];
+        FL[k] = FL9[map[k]];
+        FR[k] = FR9[map[k]];
+    }
+    UL[4] += UL[0]; UR[4] += UR[0];
+    FL[4] += FL[0]; FR[4] += FR[0];
+    FL[5] = FR[5] = 0.0;
+    double Bn = VL[BX1 + n];
+    double Uh[8], Fh[8], RL[8], RR[8];
+    for (int k = 0; k < 8; k++) {
+        Uh[k] = (SR * UR[k] - SL * UL[k] - (FR[k] - FL[k])) / (SR - SL);
+        Fh[k] = (SR * FL[k] - SL * FR[k] + SL * SR * (UR[k] - UL[k])) / (SR - SL);
+        RL[k] = SL * UL[k] - FL[k];
+        RR[k] = SR * UR[k] - FR[k];
+    }
+    int use_hllc = !(Bn * Bn > 1e-12 * (Bn * Bn + Uh[6] * Uh[6] + Uh[7] * Uh[7]));
+    /* initial guess: the relativistic HLLC total pressure */
+    double p0 = 0.0;
+    if (!use_hllc) {
+        double BF = Uh[6] * Fh[6] + Uh[7] * Fh[7];
+        double qa = Fh[4] - BF;
+        double qb = -(Uh[4] + Fh[1]) + Uh[6] * Uh[6] + Uh[7] * Uh[7] + Fh[6] * Fh[6] + Fh[7] * Fh[7];
+        double qc = Uh[1] - BF;
+        double disc = qb * qb - 4.0 * qa * qc;
+        double ls = 2.0 * qc / (-qb + sqrt(fmax(disc, 0.0)));
+        double vt = (Uh[6] * ls - Fh[6]) / Bn, vb = (Uh[7] * ls - Fh[7]) / Bn;
+        double ig2 = 1.0 - ls * ls - vt * vt - vb * vb;
+        double vBs = ls * Bn + vt * Uh[6] + vb * Uh[7];
+        p0 = Fh[1] - Fh[4] * ls + Bn * (Bn * ig2 + vBs * ls);
+        if (!(disc >= 0.0) || !(p0 > 0.0) || !isfinite(p0)) use_hllc = 1;
+    }
+    rhlld_side aL, aR;
+    double Bc[3], vcL[3], vcR[3], p = p0;
+    int ok = !use_hllc;
+    if (ok) {
+        double pa = p0, pb = 1.025 * p0;
+        double fa = rhlld_fan(RL, RR, SL, SR, pa, Bn, &aL, &aR, Bc, vcL, vcR);
+        double fb = rhlld_fan(RL, RR, SL, SR, pb, Bn, &aL, &aR, Bc, vcL, vcR);
+        int conv = 0;
+        for (int it = 0; it < 40; it++) {
+            if (fb == fa || !isfinite(fa) || !isfinite(fb)) break;
+            double pc = pb - fb * (pb - pa) / (fb - fa);
+            pa = pb;
+            fa = fb;
+            pb = pc;
+            fb = rhlld_fan(RL, RR, SL, SR, pb, Bn, &aL, &aR, Bc, vcL, vcR);
+            if (fabs(pb - pa) <= 1e-14 * fabs(pb)) { conv = 1; break; }
+        }
+        if (fb == 0.0) conv = 1;
+        p = pb;
+        rhlld_fan(RL, RR, SL, SR, p, Bn, &aL, &aR, Bc, vcL, vcR);
+        double vc2 = vcL[0] * vcL[0] + vcL[1] * vcL[1] + vcL[2] * vcL[2];
+        double vr2 = vcR[0] * vcR[0] + vcR[1] * vcR[1] + vcR[2] * vcR[2];
+        ok = conv && p > 0.0 && aL.ok && aR.ok && vc2 < 1.0 && vr2 < 1.0 && SL <= aL.K[0] && aL.K[0] <= vcL[0] &&
+             vcR[0] <= aR.K[0] && aR.K[0] <= SR;
+    }
+    if (!ok) {
+        riemann_hllc_rmhd(o, VL, VR, d, ch, F, smax);
+        return;
+    }
+    /* contact states */
+    double vc[3];
+    for (int k = 0; k < 3; k++) vc[k] = 0.5 * (vcL[k] + vcR[k]);
+    double vBc = vc[0] * Bc[0] + vc[1] * Bc[1] + vc[2] * Bc[2];
+    double UcL[8], UcR[8];
+    const rhlld_side *sd[2] = { &aL, &aR };
+    double *Uc[2] = { UcL, UcR };
+    for (int s2 = 0; s2 < 2; s2++) {
+        const rhlld_side *a = sd[s2];
+        double la = a->K[0];
+        double iS = 1.0 / (la - vc[0]);
+        Uc[s2][0] = a->U[0] * (la - a->v[0]) * iS;
+        Uc[s2][4] = (la * a->U[4] - a->U[1] + p * vc[0] - vBc * Bn) * iS;
+        for (int k = 0; k < 3; k++) Uc[s2][1 + k] = (Uc[s2][4] + p) * vc[k] - vBc * Bc[k];
+        for (int k = 0; k < 3; k++) Uc[s2][5 + k] = Bc[k];
+    }
+    double Fr[8];
+    for (int k = 0; k < 8; k++) {
+        double FaL = FL[k] + SL * (aL.U[k] - UL[k]);
+        double FcL = FaL + aL.K[0] * (UcL[k] - aL.U[k]);
+        double FaR = FR[k] + SR * (aR.U[k] - UR[k]);
+        double FcR = FaR + aR.K[0] * (UcR[k] - aR.U[k]);
+        if (aL.K[0] >= 0.0) Fr[k] = FaL;
+        else if (vc[0] >= 0.0) Fr[k] = FcL;
+        else if (aR.K[0] >= 0.0) Fr[k] = FcR;
+        else Fr[k] = FaR;
+    }
+    Fr[4] -= Fr[0];
+    for (int k = 0; k < 8; k++) F[map[k]] = Fr[k];
+    F[PSI] = 0.0;
+}
+
 /* HLLD for ideal MHD (Miyoshi & Kusano 2005), for states sharing B_n. */
 static void riemann_hlld(const orc_opts *o, const double *VL, const double *VR, int d, double ch,
                          double *F, double *smax)
@@ -886,6 +1092,8 @@ static void riemann(const orc_opts *o, const double *VLin, const double *VRin, i
     VL[BX1 + d] = VR[BX1 + d] = Bm;
     if (o->riemann == RS_HLLD && o->physics == PHYS_MHD)
         riemann_hlld(o, VL, VR, d, ch, F, smax);
+    else if (o->riemann == RS_HLLD)
+        riemann_hlld_rmhd(o, VL, VR, d, ch, F, smax);
     else if (o->riemann == RS_HLLC && o->physics == PHYS_MHD)
         riemann_hllc(o, VL, VR, d, ch, F, smax);
     else if (o->riemann == RS_HLLC)

@@ -197,7 +197,7 @@ def test_rmhd_speed_bound_brute_force():
 
 
 @pytest.mark.parametrize("physics,solver", [("mhd", "hlld"), ("mhd", "hll"), ("rmhd", "hll"), ("mhd", "rusanov"), ("mhd", "hllc"), ("mhd", "roe"),
-                                            ("rmhd", "rusanov"), ("rmhd", "hllc")])
+                                            ("rmhd", "rusanov"), ("rmhd", "hllc"), ("rmhd", "hlld")])
 def test_riemann_consistency(physics, solver):
     rng = np.random.default_rng(16)
     G = G53 if physics == "mhd" else 4 / 3
