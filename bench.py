@@ -439,7 +439,7 @@ def main():
         zr = nr ** 3
         boxr = [((0, 0, 0), (nr, nr, nr), 0, 0)]
         for eos, xs, rs in (("ideal", False, "hll"), ("tm", False, "hll"), ("ideal", True, "hll"),
-                            ("ideal", False, "hllc")):
+                            ("ideal", False, "hllc"), ("ideal", False, "hlld")):
             kw = dict(dim=3, physics="rmhd", predictor="mh", recon="lin_mc", riemann=rs, gamma=mr["gamma"],
                       dx=mr["dx"], eos=eos, exact_speeds=xs)
             p64 = ctu.Plan(ctu.make_opts(precision="fp64", **kw), boxr, ng)
@@ -469,7 +469,7 @@ def main():
             s.synchronize()
             ms = e0.elapsed_time(e1) / K
             assert fails.sum().item() == 0, ("rmhd", eos, fails)
-            out[f"rmhd192_{eos}" + ("_exact_speeds" if xs else "") + ("_hllc" if rs == "hllc" else "")] = {
+            out[f"rmhd192_{eos}" + ("_exact_speeds" if xs else "") + ("" if rs == "hll" else "_" + rs)] = {
                 "ms_per_step": ms, "zone_updates_per_s": zr / (ms * 1e-3), "shape": p.get_shape()[0]}
             del p, U32, Uo
         del Vr

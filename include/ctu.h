@@ -74,7 +74,9 @@ typedef enum { CTU_PRED_CHAR = 0, CTU_PRED_MUSCL_HANCOCK = 1 } ctu_predictor;
 /* Reference state of Eq. wnorm_predp/m: w_ref = w_{i,+-} (FACE, default),
  * w_{i,0} (CELL) or the nu_max / nu_min form (CW84). */
 typedef enum { CTU_WREF_FACE = 0, CTU_WREF_CELL = 1, CTU_WREF_CW84 = 2 } ctu_wref;
-/* Sec. 3.1: HLLD (MHD), HLL (MHD, RMHD), Rusanov, the local Lax-Friedrichs
+/* Sec. 3.1: HLLD (MHD: Miyoshi & Kusano; RMHD: Mignone, Ugliano & Bodo 2009,
+ * with a secant iteration on the total pressure and HLLC where its fan is not
+ * admissible), HLL (MHD, RMHD), Rusanov, the local Lax-Friedrichs
  * flux (F_L + F_R)/2 - a (U_R - U_L)/2 with a the largest signal speed
  * magnitude of the two states (MHD, RMHD), HLLC (MHD: one contact at the
  * HLL-averaged normal velocity with the HLL-averaged transverse field in
@@ -191,7 +193,7 @@ typedef struct ctu_plan ctu_plan;
  * (the only allocating call).  nghost must be >= 3 (PPM needs 3, parabolic
  * terms one more); box blocks must not overlap.  Returns CTU_ERR_UNSUPPORTED
  * for PPM/WENO3 with MUSCL-Hancock, characteristic tracing with RMHD,
- * parabolic/cooling terms with RMHD, HLLD or Roe with RMHD, or the
+ * parabolic/cooling terms with RMHD, Roe with RMHD, or the
  * shock-adaptive hybrid with the Rusanov, HLLC or Roe solver. */
 ctu_status ctu_plan_create(const ctu_opts *opts, const ctu_box *boxes, int32_t nbox, int32_t nghost,
                            const ctu_regface *regfaces, int32_t nreg, ctu_plan **plan_out);

@@ -693,6 +693,231 @@ __device__ __forceinline__ void hllc_rmhd(const R *VL, const R *VR, R *F, R &sma
     }
 }
 
+// HLLD for relativistic MHD (Mignone, Ugliano & Bodo 2009) for states
+// sharing B_n.  Between the outer fast waves (HLL's speeds) the total
+// pressure p is uniform; for a trial p the state a behind each fast wave S
+// is closed-form in R = S U - F (E the total energy U[ENG] + D):
+//   A = R_mn - S R_E + p (1 - S^2), G = R_Bt^2 + R_Bb^2, C = R_mt R_Bt + R_mb R_Bb,
+//   Q = -A - G + B_n^2 (1 - S^2), X = B_n (A S B_n + C) - (A + G)(S p + R_E),
+//   v_n = (B_n (A B_n + S C) - (A + G)(p + R_mn)) / X,
+//   v_t = (Q R_mt + R_Bt (C + B_n (S R_mn - R_E))) / X,
+//   B_t = (R_Bt - B_n v_t) / (S - v_n), w_t = p + (R_E - v.R_m) / (S - v_n);
+// the rotational discontinuity beside it moves at K_n, K = (R_m + p e_n +
+// eta R_B) / (S p + R_E + eta B_n), eta = -+ sgn(B_n) sqrt(w_t) (left /
+// right); the contact region holds the field B_c conserved across both
+// rotational discontinuities and, on each side, v_c = K - B_c (1 - K^2) /
+// (eta - K.B_c).  p solves v_cn(R) = v_cn(L) by secant steps from the
+// relativistic HLLC estimate (and 1.025 times it) until successive iterates
+// agree to 1e-14 (FP64) / 1e-6 (FP32) relatively, at most 40 steps.  The
+// fan's states follow from the jump conditions and the flux from F* = F +
+// S (U* - U) across each wave.  B_n = 0 (B_n^2 <= 1e-12 (B_n^2 + B^hll_t^2))
+// or a fan that is not admissible (no convergence, |v| >= 1, D <= 0,
+// w_t <= p, wave speeds out of order) takes the HLLC flux.
+template <typename R> struct RHSide {
+    R U[8];  // D, m_n, m_t, m_b, E, B_n, B_t, B_b
+    R v[3], B[3], wt, eta, K[3];
+    bool ok;
+};
+
+template <typename R>
+__device__ __forceinline__ void rhlld_astate(const R *Rv, R S, R p, R Bn, R sg, RHSide<R> &a)
+{
+    const R A = Rv[1] - S * Rv[4] + p * (R(1) - S * S);
+    const R Gq = Rv[6] * Rv[6] + Rv[7] * Rv[7];
+    const R C = Rv[2] * Rv[6] + Rv[3] * Rv[7];
+    const R Q = -A - Gq + Bn * Bn * (R(1) - S * S);
+    const R X = Bn * (A * S * Bn + C) - (A + Gq) * (S * p + Rv[4]);
+    const R iX = R(1) / X;
+    a.v[0] = (Bn * (A * Bn + S * C) - (A + Gq) * (p + Rv[1])) * iX;
+    a.v[1] = (Q * Rv[2] + Rv[6] * (C + Bn * (S * Rv[1] - Rv[4]))) * iX;
+    a.v[2] = (Q * Rv[3] + Rv[7] * (C + Bn * (S * Rv[1] - Rv[4]))) * iX;
+    const R iS = R(1) / (S - a.v[0]);
+    a.B[0] = Bn;
+    a.B[1] = (Rv[6] - Bn * a.v[1]) * iS;
+    a.B[2] = (Rv[7] - Bn * a.v[2]) * iS;
+    a.wt = p + (Rv[4] - (a.v[0] * Rv[1] + a.v[1] * Rv[2] + a.v[2] * Rv[3])) * iS;
+    const R vB = a.v[0] * a.B[0] + a.v[1] * a.B[1] + a.v[2] * a.B[2];
+    a.U[0] = Rv[0] * iS;
+    a.U[4] = (Rv[4] + p * a.v[0] - vB * Bn) * iS;
+#pragma unroll
+    for (int k = 0; k < 3; k++) {
+        a.U[1 + k] = (a.U[4] + p) * a.v[k] - vB * a.B[k];
+        a.U[5 + k] = a.B[k];
+    }
+    const R v2 = a.v[0] * a.v[0] + a.v[1] * a.v[1] + a.v[2] * a.v[2];
+    a.ok = isfinite(X) && X != R(0) && v2 < R(1) && a.wt > p && a.U[0] > R(0);
+    a.eta = sg * sgn1(Bn) * sqrt(fmax(a.wt, R(0)));
+    const R iden = R(1) / (S * p + Rv[4] + a.eta * Bn);
+    a.K[0] = (Rv[1] + p + a.eta * Rv[5]) * iden;
+    a.K[1] = (Rv[2] + a.eta * Rv[6]) * iden;
+    a.K[2] = (Rv[3] + a.eta * Rv[7]) * iden;
+}
+
+template <typename R>
+__device__ __forceinline__ R rhlld_fan(const R *RL, const R *RR, R SL, R SR, R p, R Bn, RHSide<R> &aL, RHSide<R> &aR,
+                                       R *Bc, R *vcL, R *vcR)
+{
+    rhlld_astate(RL, SL, p, Bn, R(-1), aL);
+    rhlld_astate(RR, SR, p, Bn, R(1), aR);
+    const R idK = R(1) / (aR.K[0] - aL.K[0]);
+    Bc[0] = Bn;
+#pragma unroll
+    for (int k = 1; k < 3; k++)
+        Bc[k] = ((aR.B[k] * (aR.K[0] - aR.v[0]) + Bn * aR.v[k]) - (aL.B[k] * (aL.K[0] - aL.v[0]) + Bn * aL.v[k])) * idK;
+    {
+        const R K2 = aL.K[0] * aL.K[0] + aL.K[1] * aL.K[1] + aL.K[2] * aL.K[2];
+        const R KB = aL.K[0] * Bc[0] + aL.K[1] * Bc[1] + aL.K[2] * Bc[2];
+        const R y = (R(1) - K2) / (aL.eta - KB);
+#pragma unroll
+        for (int k = 0; k < 3; k++) vcL[k] = aL.K[k] - Bc[k] * y;
+    }
+    {
+        const R K2 = aR.K[0] * aR.K[0] + aR.K[1] * aR.K[1] + aR.K[2] * aR.K[2];
+        const R KB = aR.K[0] * Bc[0] + aR.K[1] * Bc[1] + aR.K[2] * Bc[2];
+        const R y = (R(1) - K2) / (aR.eta - KB);
+#pragma unroll
+        for (int k = 0; k < 3; k++) vcR[k] = aR.K[k] - Bc[k] * y;
+    }
+    return vcR[0] - vcL[0];
+}
+
+template <int D, int PHYS, typename R>
+__device__ __forceinline__ void hlld_rmhd(const R *VL, const R *VR, R *F, R &smax, R gam, R ch, int glm, int xs)
+{
+    constexpr int n = Ax<D>::n, t = Ax<D>::t, b = Ax<D>::b;
+    R lmL, lpL, lmR, lpR;
+    wave_speeds<D, PHYS>(VL, gam, lmL, lpL, xs);
+    wave_speeds<D, PHYS>(VR, gam, lmR, lpR, xs);
+    const R SL = fmin(lmL, lmR), SR = fmax(lpL, lpR);
+    smax = fmax(fabs(SL), fabs(SR));
+    R U9L[NV], U9R[NV], F9L[NV], F9R[NV];
+    phys_flux<D, PHYS>(VL, U9L, F9L, gam, ch, glm);
+    phys_flux<D, PHYS>(VR, U9R, F9R, gam, ch, glm);
+    if (SL >= R(0) || SR <= R(0)) {
+#pragma unroll
+        for (int q = 0; q < NV; q++) F[q] = (SL >= R(0)) ? F9L[q] : F9R[q];
+        return;
+    }
+    constexpr int map[8] = { RHO, MX1 + n, MX1 + t, MX1 + b, ENG, BX1 + n, BX1 + t, BX1 + b };
+    R UL[8], UR[8], FL[8], FR[8];
+#pragma unroll
+    for (int k = 0; k < 8; k++) {
+        UL[k] = U9L[map[k]];
+        UR[k] = U9R[map[k]];
+        FL[k] = F9L[map[k]];
+        FR[k] = F9R[map[k]];
+    }
+    UL[4] += UL[0];
+    UR[4] += UR[0];
+    FL[4] += FL[0];
+    FR[4] += FR[0];
+    FL[5] = R(0);
+    FR[5] = R(0);
+    const R Bn = VL[BX1 + n];
+    const R id = R(1) / (SR - SL);
+    R Uh[8], Fh[8], RL[8], RR[8];
+#pragma unroll
+    for (int k = 0; k < 8; k++) {
+        Uh[k] = (SR * UR[k] - SL * UL[k] - (FR[k] - FL[k])) * id;
+        Fh[k] = (SR * FL[k] - SL * FR[k] + SL * SR * (UR[k] - UL[k])) * id;
+        RL[k] = SL * UL[k] - FL[k];
+        RR[k] = SR * UR[k] - FR[k];
+    }
+    bool ok = Bn * Bn > R(1e-12) * (Bn * Bn + Uh[6] * Uh[6] + Uh[7] * Uh[7]);
+    R p0 = R(0);
+    if (ok) {
+        const R BF = Uh[6] * Fh[6] + Uh[7] * Fh[7];
+        const R qa = Fh[4] - BF;
+        const R qb = -(Uh[4] + Fh[1]) + Uh[6] * Uh[6] + Uh[7] * Uh[7] + Fh[6] * Fh[6] + Fh[7] * Fh[7];
+        const R qc = Uh[1] - BF;
+        const R disc = qb * qb - R(4) * qa * qc;
+        const R ls = R(2) * qc / (-qb + sqrt(fmax(disc, R(0))));
+        const R vt = (Uh[6] * ls - Fh[6]) / Bn, vb = (Uh[7] * ls - Fh[7]) / Bn;
+        const R ig2 = R(1) - ls * ls - vt * vt - vb * vb;
+        const R vBs = ls * Bn + vt * Uh[6] + vb * Uh[7];
+        p0 = Fh[1] - Fh[4] * ls + Bn * (Bn * ig2 + vBs * ls);
+        ok = disc >= R(0) && p0 > R(0) && isfinite(p0);
+    }
+    RHSide<R> aL, aR;
+    R Bc[3], vcL[3], vcR[3], p = p0;
+    if (ok) {
+        constexpr R tol = (sizeof(R) == 8) ? R(1e-14) : R(1e-6);
+        R pa = p0, pb = R(1.025) * p0;
+        R fa = rhlld_fan(RL, RR, SL, SR, pa, Bn, aL, aR, Bc, vcL, vcR);
+        R fb = rhlld_fan(RL, RR, SL, SR, pb, Bn, aL, aR, Bc, vcL, vcR);
+        bool conv = false;
+        for (int it = 0; it < 40; it++) {
+            if (fb == fa || !isfinite(fa) || !isfinite(fb)) break;
+            const R pc = pb - fb * (pb - pa) / (fb - fa);
+            pa = pb;
+            fa = fb;
+            pb = pc;
+            fb = rhlld_fan(RL, RR, SL, SR, pb, Bn, aL, aR, Bc, vcL, vcR);
+            if (fabs(pb - pa) <= tol * fabs(pb)) {
+                conv = true;
+                break;
+            }
+        }
+        if (fb == R(0)) conv = true;
+        // FP32: iterates that stop moving within a few ulps count as converged
+        if (sizeof(R) == 4 && fabs(pb - pa) <= tol * fabs(pb)) conv = true;
+        p = pb;
+        (void)rhlld_fan(RL, RR, SL, SR, p, Bn, aL, aR, Bc, vcL, vcR);
+        const R vc2 = vcL[0] * vcL[0] + vcL[1] * vcL[1] + vcL[2] * vcL[2];
+        const R vr2 = vcR[0] * vcR[0] + vcR[1] * vcR[1] + vcR[2] * vcR[2];
+        ok = conv && p > R(0) && aL.ok && aR.ok && vc2 < R(1) && vr2 < R(1) && SL <= aL.K[0] &&
+             aL.K[0] <= vcL[0] && vcR[0] <= aR.K[0] && aR.K[0] <= SR;
+    }
+    if (!ok) {
+        R VLc[NV], VRc[NV];
+#pragma unroll
+        for (int q = 0; q < NV; q++) {
+            VLc[q] = VL[q];
+            VRc[q] = VR[q];
+        }
+        hllc_rmhd<D, PHYS>(VLc, VRc, F, smax, gam, ch, glm, xs);
+        return;
+    }
+    R vc[3];
+#pragma unroll
+    for (int k = 0; k < 3; k++) vc[k] = R(0.5) * (vcL[k] + vcR[k]);
+    const R vBc = vc[0] * Bc[0] + vc[1] * Bc[1] + vc[2] * Bc[2];
+    R UcL[8], UcR[8];
+    {
+        const R la = aL.K[0], iS = R(1) / (la - vc[0]);
+        UcL[0] = aL.U[0] * (la - aL.v[0]) * iS;
+        UcL[4] = (la * aL.U[4] - aL.U[1] + p * vc[0] - vBc * Bn) * iS;
+#pragma unroll
+        for (int k = 0; k < 3; k++) {
+            UcL[1 + k] = (UcL[4] + p) * vc[k] - vBc * Bc[k];
+            UcL[5 + k] = Bc[k];
+        }
+    }
+    {
+        const R la = aR.K[0], iS = R(1) / (la - vc[0]);
+        UcR[0] = aR.U[0] * (la - aR.v[0]) * iS;
+        UcR[4] = (la * aR.U[4] - aR.U[1] + p * vc[0] - vBc * Bn) * iS;
+#pragma unroll
+        for (int k = 0; k < 3; k++) {
+            UcR[1 + k] = (UcR[4] + p) * vc[k] - vBc * Bc[k];
+            UcR[5 + k] = Bc[k];
+        }
+    }
+    R Fr[8];
+#pragma unroll
+    for (int k = 0; k < 8; k++) {
+        const R FaL = FL[k] + SL * (aL.U[k] - UL[k]);
+        const R FcL = FaL + aL.K[0] * (UcL[k] - aL.U[k]);
+        const R FaR = FR[k] + SR * (aR.U[k] - UR[k]);
+        const R FcR = FaR + aR.K[0] * (UcR[k] - aR.U[k]);
+        Fr[k] = (aL.K[0] >= R(0)) ? FaL : ((vc[0] >= R(0)) ? FcL : ((aR.K[0] >= R(0)) ? FcR : FaR));
+    }
+    Fr[4] -= Fr[0];
+#pragma unroll
+    for (int k = 0; k < 8; k++) F[map[k]] = Fr[k];
+    F[PSI] = R(0);
+}
+
 // Roe's solver (defined after the eigenvector helpers it uses)
 template <int D, typename R>
 __device__ __forceinline__ void roe(const R *VL, const R *VR, R *F, R &smax, R gam, R ch, int glm);
@@ -716,6 +941,7 @@ __device__ __forceinline__ void riemann(R *VL, R *VR, R *F, R &smax, R gam, R ch
     VL[BX1 + D] = Bm;
     VR[BX1 + D] = Bm;
     if constexpr (RS == RS_HLLD && PHYS == PHYS_MHD) hlld<D>(VL, VR, F, smax, gam, ch, glm);
+    else if constexpr (RS == RS_HLLD) hlld_rmhd<D, PHYS>(VL, VR, F, smax, gam, ch, glm, xs);
     else if constexpr (RS == RS_HLLC && PHYS == PHYS_MHD) hllc<D>(VL, VR, F, smax, gam, ch, glm);
     else if constexpr (RS == RS_ROE && PHYS == PHYS_MHD) roe<D>(VL, VR, F, smax, gam, ch, glm);
     else if constexpr (RS == RS_HLLC) hllc_rmhd<D, PHYS>(VL, VR, F, smax, gam, ch, glm, xs);

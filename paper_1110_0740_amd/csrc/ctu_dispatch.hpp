@@ -23,7 +23,8 @@ __host__ inline bool combo_supported(const Combo &c)
         if (c.pred == PRED_CHAR) return true;
         return c.rk == RK_LIN;
     }
-    return c.pred == PRED_MH && c.rk == RK_LIN && (c.rs == RS_HLL || c.rs == RS_RUSANOV || c.rs == RS_HLLC);
+    return c.pred == PRED_MH && c.rk == RK_LIN &&
+           (c.rs == RS_HLL || c.rs == RS_RUSANOV || c.rs == RS_HLLC || c.rs == RS_HLLD);
 }
 
 hipError_t launch_sweep_f32(int D, const Combo &c, int nblocks, const SweepArgs<float> &a, hipStream_t s);
@@ -73,11 +74,13 @@ template <> inline hipError_t launch_sweep<double>(int D, const Combo &c, int nb
         if (c.phys == PHYS_RMHD) {                                                                               \
             if (c.rs == RS_RUSANOV) return sweep_one<D, PHYS_RMHD, PRED_MH, RK_LIN, RS_RUSANOV>(c, nb, a, s);     \
             if (c.rs == RS_HLLC) return sweep_one<D, PHYS_RMHD, PRED_MH, RK_LIN, RS_HLLC>(c, nb, a, s);           \
+            if (c.rs == RS_HLLD) return sweep_one<D, PHYS_RMHD, PRED_MH, RK_LIN, RS_HLLD>(c, nb, a, s);           \
             return sweep_one<D, PHYS_RMHD, PRED_MH, RK_LIN, RS_HLL>(c, nb, a, s);                                 \
         }                                                                                                        \
         if (c.phys == PHYS_RMHD_TM) {                                                                            \
             if (c.rs == RS_RUSANOV) return sweep_one<D, PHYS_RMHD_TM, PRED_MH, RK_LIN, RS_RUSANOV>(c, nb, a, s);  \
             if (c.rs == RS_HLLC) return sweep_one<D, PHYS_RMHD_TM, PRED_MH, RK_LIN, RS_HLLC>(c, nb, a, s);        \
+            if (c.rs == RS_HLLD) return sweep_one<D, PHYS_RMHD_TM, PRED_MH, RK_LIN, RS_HLLD>(c, nb, a, s);        \
             return sweep_one<D, PHYS_RMHD_TM, PRED_MH, RK_LIN, RS_HLL>(c, nb, a, s);                              \
         }                                                                                                        \
         if (c.pred == PRED_MH) {                                                                                 \
@@ -122,12 +125,16 @@ template <> inline hipError_t launch_sweep<double>(int D, const Combo &c, int nb
             hipLaunchKernelGGL((k_tcouple<DIM, PHYS_RMHD, RS_RUSANOV, 0, VAR_GENERIC, R>), dim3(nb), dim3(NT), 0, s, a); \
         else if (c.phys == PHYS_RMHD && c.rs == RS_HLLC)                                                         \
             hipLaunchKernelGGL((k_tcouple<DIM, PHYS_RMHD, RS_HLLC, 0, VAR_GENERIC, R>), dim3(nb), dim3(NT), 0, s, a); \
+        else if (c.phys == PHYS_RMHD && c.rs == RS_HLLD)                                                         \
+            hipLaunchKernelGGL((k_tcouple<DIM, PHYS_RMHD, RS_HLLD, 0, VAR_GENERIC, R>), dim3(nb), dim3(NT), 0, s, a); \
         else if (c.phys == PHYS_RMHD)                                                                            \
             hipLaunchKernelGGL((k_tcouple<DIM, PHYS_RMHD, RS_HLL, 0, VAR_GENERIC, R>), dim3(nb), dim3(NT), 0, s, a); \
         else if (c.phys == PHYS_RMHD_TM && c.rs == RS_RUSANOV)                                                   \
             hipLaunchKernelGGL((k_tcouple<DIM, PHYS_RMHD_TM, RS_RUSANOV, 0, VAR_GENERIC, R>), dim3(nb), dim3(NT), 0, s, a); \
         else if (c.phys == PHYS_RMHD_TM && c.rs == RS_HLLC)                                                      \
             hipLaunchKernelGGL((k_tcouple<DIM, PHYS_RMHD_TM, RS_HLLC, 0, VAR_GENERIC, R>), dim3(nb), dim3(NT), 0, s, a); \
+        else if (c.phys == PHYS_RMHD_TM && c.rs == RS_HLLD)                                                      \
+            hipLaunchKernelGGL((k_tcouple<DIM, PHYS_RMHD_TM, RS_HLLD, 0, VAR_GENERIC, R>), dim3(nb), dim3(NT), 0, s, a); \
         else if (c.phys == PHYS_RMHD_TM)                                                                         \
             hipLaunchKernelGGL((k_tcouple<DIM, PHYS_RMHD_TM, RS_HLL, 0, VAR_GENERIC, R>), dim3(nb), dim3(NT), 0, s, a); \
         else if (c.rs == RS_RUSANOV && c.fast)                                                                   \
@@ -176,8 +183,8 @@ template <> inline hipError_t launch_sweep<double>(int D, const Combo &c, int nb
     template <int D, int PHYS, int PRED, int RK>                                                                 \
     static hipError_t mt_rs(const Combo &c, int nb, const MtArgs<R> &a, hipStream_t s)                          \
     {                                                                                                            \
+        if (c.rs == RS_HLLD) return mt_one<D, PHYS, PRED, RK, RS_HLLD>(nb, a, s);                               \
         if constexpr (PHYS == PHYS_MHD) {                                                                        \
-            if (c.rs == RS_HLLD) return mt_one<D, PHYS, PRED, RK, RS_HLLD>(nb, a, s);                           \
             if (c.rs == RS_ROE) return mt_one<D, PHYS, PRED, RK, RS_ROE>(nb, a, s);                             \
         }                                                                                                        \
         if (c.rs == RS_RUSANOV) return mt_one<D, PHYS, PRED, RK, RS_RUSANOV>(nb, a, s);                         \

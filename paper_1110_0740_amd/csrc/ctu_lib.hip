@@ -493,8 +493,8 @@ ctu_status ctu_plan_create(const ctu_opts *opts, const ctu_box *boxes, int32_t n
     c.fast = (o.wref == CTU_WREF_FACE && o.glm && !o.hyperbolic_off && !o.parabolic_mask && !o.cooling && !c.shk) ? 1 : 0;
     if ((o.riemann == CTU_RUSANOV || o.riemann == CTU_HLLC || o.riemann == CTU_ROE) && c.shk)
         return fail(CTU_ERR_UNSUPPORTED, "the shock-adaptive hybrid (HLL on flagged faces) needs HLLD or HLL");
-    if (o.physics == CTU_RMHD && (o.riemann == CTU_HLLD || o.riemann == CTU_ROE))
-        return fail(CTU_ERR_UNSUPPORTED, "RMHD supports the HLL, Rusanov and HLLC solvers only");
+    if (o.physics == CTU_RMHD && o.riemann == CTU_ROE)
+        return fail(CTU_ERR_UNSUPPORTED, "the Roe solver belongs to the MHD module");
     if (!combo_supported(c))
         return fail(CTU_ERR_UNSUPPORTED, "unsupported combination (characteristic tracing is MHD only; "
                                          "MUSCL-Hancock needs a linear reconstruction)");
