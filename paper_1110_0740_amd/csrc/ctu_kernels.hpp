@@ -746,33 +746,53 @@ __global__ __launch_bounds__(NT) void k_mtflux(MtArgs<R> a)
     for (int q = 0; q < NV; q++) bF.st(q, c, F[q]);
 }
 
-template <typename R>
+template <int DIM, typename R>
 __global__ __launch_bounds__(NT) void k_mtT(MtArgs<R> a)
 {
     const KTile tl = a.tiles[blockIdx.x];
     const KBox bx = a.boxes[tl.box];
     const int c = tl.a + (int)threadIdx.x;
     if (c >= bx.cells) return;
-    const int dim = a.o.dim;
     const int cc[3] = { c % bx.N[0], (c / bx.N[0]) % bx.N[1], c / (bx.N[0] * bx.N[1]) };
     const int st[3] = { 1, bx.N[0], bx.N[0] * bx.N[1] };
-    for (int d = 0; d < dim; d++) {
-        bool ok = cc[d] >= bx.g[d] - 1 && cc[d] <= bx.g[d] + bx.n[d];
-        for (int e = 0; e < dim; e++)
-            if (e != d) ok = ok && cc[e] >= bx.g[e] && cc[e] < bx.g[e] + bx.n[e];
-        if (!ok) continue;
+    bool in[3], lay[3], need[3];
+#pragma unroll
+    for (int e = 0; e < DIM; e++) {
+        in[e] = cc[e] >= bx.g[e] && cc[e] < bx.g[e] + bx.n[e];
+        lay[e] = cc[e] >= bx.g[e] - 1 && cc[e] <= bx.g[e] + bx.n[e];
+    }
+    bool any = false;
+#pragma unroll
+    for (int d = 0; d < DIM; d++) {
+        need[d] = lay[d];
+#pragma unroll
+        for (int e = 0; e < DIM; e++)
+            if (e != d) need[d] = need[d] && in[e];
+        any = any || need[d];
+    }
+    if (!any) return;
+    // L_e = -(F_e(c + e) - F_e(c)) / dx_e, formed once for every T_d that uses it
+    R L[DIM][NV];
+#pragma unroll
+    for (int e = 0; e < DIM; e++) {
+        bool want = false;
+#pragma unroll
+        for (int d = 0; d < DIM; d++)
+            if (d != e) want = want || need[d];
+        const Blk<R> bF(a.F[e] + bx.woff, bx.cells);
+        const R idx = R(1.0 / bx.dx[e]);
+#pragma unroll
+        for (int q = 0; q < NV; q++) L[e][q] = want ? -(bF.ld(q, c + st[e]) - bF.ld(q, c)) * idx : R(0);
+    }
+#pragma unroll
+    for (int d = 0; d < DIM; d++) {
+        if (!need[d]) continue;
         const Blk<R> bT(a.T[d] + bx.woff, bx.cells);
 #pragma unroll
         for (int q = 0; q < NV; q++) {
-            R t = R(0);
-            bool first = true;
-            for (int e = 0; e < dim; e++) {
-                if (e == d) continue;
-                const Blk<R> bF(a.F[e] + bx.woff, bx.cells);
-                const R L = -(bF.ld(q, c + st[e]) - bF.ld(q, c)) * R(1.0 / bx.dx[e]);
-                t = first ? L : t + L;
-                first = false;
-            }
+            R t;
+            if constexpr (DIM == 3) t = (d == 0) ? L[1][q] + L[2][q] : ((d == 1) ? L[0][q] + L[2][q] : L[0][q] + L[1][q]);
+            else t = (d == 0) ? L[1][q] : L[0][q];
             bT.st(q, c, t);
         }
     }

@@ -333,7 +333,8 @@ ctu_status enqueue_step(ctu_plan *p, const void *U_in, void *U_out, const double
                 e = launch_mtflux_f64(D, p->combo, p->t_cells.n(), ma, s);
             if (e != hipSuccess) return fail(CTU_ERR_HIP, std::string("MT flux launch: ") + hipGetErrorString(e));
         }
-        hipLaunchKernelGGL((k_mtT<R>), dim3(p->t_cells.n()), dim3(NT), 0, s, ma);
+        if (dim == 3) hipLaunchKernelGGL((k_mtT<3, R>), dim3(p->t_cells.n()), dim3(NT), 0, s, ma);
+        else hipLaunchKernelGGL((k_mtT<2, R>), dim3(p->t_cells.n()), dim3(NT), 0, s, ma);
         HIP_TRY(hipGetLastError());
     } else {
         StageTimer tm(p, 1, s);
