@@ -679,18 +679,17 @@ __global__ __launch_bounds__(NT) void k_tcouple(TArgs<R> a)
 // MT corner coupling (runs without parabolic terms): the transverse fluxes of
 // Eq. transv are Riemann fluxes between the normal-predictor states of the
 // two cells of a face instead of first-order t^n fluxes.
-//   k_mtflux<D>  one thread per ghosted cell (cell tiles): the face below it
-//                along D, for D-faces g..g+n at transverse positions
-//                g-1..g+n; both cells' normal predictors (the sweep's own
-//                predictor, from the six-cell stencil c-3..c+2 along D) and
-//                the Riemann solve, stored on the face below the cell;
+//   k_mtflux<D>  the Riemann fluxes of the D-faces g..g+n at transverse
+//                positions g-1..g+n between the normal-predictor states (the
+//                sweep's own predictor) of their two cells, stored on the
+//                face below each cell; MT tiles of 4 x 64 cells;
 //   k_mtT        T_d = sum_{e != d} -(F_e(c + e) - F_e(c)) / dx_e on the cells
 //                the sweep of d reads (d-layer g-1..g+n, interior across d).
 // ---------------------------------------------------------------------------
 
 template <typename R> struct MtArgs {
     const KBox *boxes;
-    const KTile *tiles;   // cell tiles: (box, first cell), NT cells each
+    const KTile *tiles;   // k_mtflux: MT tiles of its direction; k_mtT: cell tiles
     const R *U;           // U^n (caller layout)
     const R *V;           // V^n (workspace)
     R *F[3];              // predictor fluxes per direction (workspace)
@@ -699,21 +698,64 @@ template <typename R> struct MtArgs {
     KOpts o;
 };
 
+// normal predictor (the sweep's) of the cell at c along D
+template <int D, int PHYS, int PRED, int RK, typename R>
+__device__ __forceinline__ void mt_predict(const Blk<R> &bV, const R *Ub, const KBox &bx, int c, int sD,
+                                           const KOpts &o, R gam, R dtdx, R dxD, R ch, R *Vm, R *Vp)
+{
+    R Vs[5][NV];
+    constexpr int l0 = (RK == RK_PPM) ? 0 : 1, l1 = (RK == RK_PPM) ? 5 : 4;
+#pragma unroll
+    for (int l = l0; l < l1; l++) ld_cell(bV, c + (l - 2) * sD, Vs[l]);
+    if constexpr (PRED == PRED_CHAR) {
+        predict_char<D, RK>(Vs, o, gam, dtdx, dxD, ch, Vm, Vp, o.limiter);
+    } else {
+        R U0[NV];
+        ld_cell(Blk<R>(Ub + bx.uoff, bx.cells), c, U0);
+        (void)predict_mh<D, PHYS>(Vs, U0, o, gam, dtdx, ch, Vm, Vp, o.limiter);
+    }
+}
+
+// One block = 4 rows of 64 lanes (see the MT tile tables).  D = 0: the lanes
+// run along x from a-1, the rows along y (b..b+3) at z = c; lane l > 0 owns
+// the face below its cell and takes the left state from lane l-1.  D = 1, 2:
+// the lanes run along x from a, the rows along D over the faces b..b+3 (the
+// third axis at c); row r > 0 takes the left state from row r-1, row 0
+// forms the predictor of the cell below its face itself.  Every cell's
+// predictor is thus formed once (plus one row per block across x).
 template <int D, int PHYS, int PRED, int RK, int RS, typename R>
 __global__ __launch_bounds__(NT) void k_mtflux(MtArgs<R> a)
 {
+    __shared__ R sVp[NV][NT];
     const KTile tl = a.tiles[blockIdx.x];
     const KBox bx = a.boxes[tl.box];
-    const int c = tl.a + (int)threadIdx.x;
-    if (c >= bx.cells) return;
+    const int tid = (int)threadIdx.x;
+    const int lane = tid & 63, row = tid >> 6;
     const KOpts &o = a.o;
     const int dim = o.dim;
-    const int cc[3] = { c % bx.N[0], (c / bx.N[0]) % bx.N[1], c / (bx.N[0] * bx.N[1]) };
+    int cc[3];
+    if (D == 0) {
+        cc[0] = tl.a - 1 + lane;
+        cc[1] = tl.b + row;
+        cc[2] = tl.c;
+    } else if (D == 1) {
+        cc[0] = tl.a + lane;
+        cc[1] = tl.b + row;
+        cc[2] = tl.c;
+    } else {
+        cc[0] = tl.a + lane;
+        cc[1] = tl.c;
+        cc[2] = tl.b + row;
+    }
+    bool valid = true;
 #pragma unroll
     for (int e = 0; e < 3; e++) {
-        if (e >= dim) continue;
-        const int lo = (e == D) ? bx.g[e] : bx.g[e] - 1;
-        if (cc[e] < lo || cc[e] > bx.g[e] + bx.n[e]) return;
+        if (e < dim) {
+            const int lo = (e == D && D != 0) ? bx.g[e] : bx.g[e] - 1;
+            valid = valid && cc[e] >= lo && cc[e] <= bx.g[e] + bx.n[e];
+        } else {
+            valid = valid && cc[e] == 0;
+        }
     }
     const int sD = (D == 0) ? 1 : (D == 1 ? bx.N[0] : bx.N[0] * bx.N[1]);
     const R gam = R(o.gamma);
@@ -721,26 +763,27 @@ __global__ __launch_bounds__(NT) void k_mtflux(MtArgs<R> a)
     const R dxD = R(bx.dx[D]);
     const R dtdx = dt / dxD;
     const Blk<R> bV(a.V + bx.woff, bx.cells);
-    // cells c-3 .. c+2 along D: W[0..4] is the stencil of the cell below the
-    // face, W[1..5] that of the cell above (linear / WENO3 read W[1..4])
-    R W[6][NV];
-    constexpr int w0 = (RK == RK_PPM) ? 0 : 1, w1 = (RK == RK_PPM) ? 6 : 5;
+    const int c = valid ? cidx(bx, cc[0], cc[1], cc[2]) : 0;
+    R Vm[NV], Vp[NV], VL[NV];
+    if (valid) {
+        mt_predict<D, PHYS, PRED, RK>(bV, a.U, bx, c, sD, o, gam, dtdx, dxD, ch, Vm, Vp);
 #pragma unroll
-    for (int l = w0; l < w1; l++) ld_cell(bV, c + (l - 3) * sD, W[l]);
-    R VmL[NV], VpL[NV], VmR[NV], VpR[NV];
-    if constexpr (PRED == PRED_CHAR) {
-        predict_char<D, RK>(W, o, gam, dtdx, dxD, ch, VmL, VpL, o.limiter);
-        predict_char<D, RK>(W + 1, o, gam, dtdx, dxD, ch, VmR, VpR, o.limiter);
-    } else {
-        const Blk<R> bU(a.U + bx.uoff, bx.cells);
-        R U0[NV];
-        ld_cell(bU, c - sD, U0);
-        (void)predict_mh<D, PHYS>(W, U0, o, gam, dtdx, ch, VmL, VpL, o.limiter);
-        ld_cell(bU, c, U0);
-        (void)predict_mh<D, PHYS>(W + 1, U0, o, gam, dtdx, ch, VmR, VpR, o.limiter);
+        for (int q = 0; q < NV; q++) sVp[q][tid] = Vp[q];
+        if (D != 0 && row == 0) {
+            R Vm2[NV];
+            mt_predict<D, PHYS, PRED, RK>(bV, a.U, bx, c - sD, sD, o, gam, dtdx, dxD, ch, Vm2, VL);
+        }
+    }
+    __syncthreads();
+    const bool face = valid && (D == 0 ? (lane >= 1 && cc[0] >= bx.g[0]) : true);
+    if (!face) return;
+    if (D == 0 || row > 0) {
+        const int src = (D == 0) ? tid - 1 : tid - 64;
+#pragma unroll
+        for (int q = 0; q < NV; q++) VL[q] = sVp[q][src];
     }
     R F[NV], smax;
-    riemann<D, PHYS, RS>(VpL, VmR, F, smax, gam, ch, o.glm, o.xspeeds);
+    riemann<D, PHYS, RS>(VL, Vm, F, smax, gam, ch, o.glm, o.xspeeds);
     const Blk<R> bF(a.F[D] + bx.woff, bx.cells);
 #pragma unroll
     for (int q = 0; q < NV; q++) bF.st(q, c, F[q]);

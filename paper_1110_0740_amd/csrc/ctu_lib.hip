@@ -80,6 +80,7 @@ struct ctu_plan {
     int64_t state_elems = 0;
     int64_t ws_cells = 0;  // sum of ghosted cells
     TileSet t_cells, t_tc, t_sweep[3], t_cfl;
+    TileSet t_mt[3];  // MT corner coupling: 4 x 64 face tiles per direction
     // workspace fields: V^n, the transverse increments T_d, V^{n+1/2}, rate
     void *wsV = nullptr, *wsT[3] = { nullptr, nullptr, nullptr };
     void *wsVh = nullptr, *wsLam = nullptr;
@@ -118,7 +119,8 @@ void free_plan(ctu_plan *p)
     if (p->graph) (void)hipGraphDestroy(p->graph);
     void *ptrs[] = { p->dboxes, p->dregs, p->drface, p->t_cells.d, p->t_tc.d, p->t_sweep[0].d, p->t_sweep[1].d,
                      p->t_sweep[2].d, p->t_cfl.d, p->wsV, p->wsT[0], p->wsT[1], p->wsT[2], p->wsVh, p->wsLam, p->wsFlag,
-                     p->drefl, p->dcell_start, p->wsF[0], p->wsF[1], p->wsF[2] };
+                     p->drefl, p->dcell_start, p->wsF[0], p->wsF[1], p->wsF[2], p->t_mt[0].d, p->t_mt[1].d,
+                     p->t_mt[2].d };
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
     delete p;
@@ -242,17 +244,41 @@ ctu_status build_shape_tables(ctu_plan *p)
     return CTU_OK;
 }
 
+// MT face tiles of direction D (see k_mtflux): D = 0: 63 x-faces from a
+// (lanes from a-1) by 4 rows of y from b at z = c; D = 1, 2: 64 x-positions
+// from a by 4 D-faces from b, the third axis at c.  Faces g..g+n along D,
+// transverse positions g-1..g+n.
+void add_mt_tiles(TileSet &ts, int b, const KBox &bx, int D, int dim)
+{
+    const int lo[3] = { bx.g[0] - 1, bx.g[1] - 1, dim == 3 ? bx.g[2] - 1 : 0 };
+    const int hi[3] = { bx.g[0] + bx.n[0], bx.g[1] + bx.n[1], dim == 3 ? bx.g[2] + bx.n[2] : 0 };
+    if (D == 0) {
+        for (int z = lo[2]; z <= hi[2]; z++)
+            for (int y = lo[1]; y <= hi[1]; y += 4)
+                for (int x = bx.g[0]; x <= hi[0]; x += 63) ts.h.push_back({ b, x, y, z });
+    } else {
+        const int T = (D == 1) ? 2 : 1;
+        for (int t = lo[T]; t <= hi[T]; t++)
+            for (int f = bx.g[D]; f <= hi[D]; f += 4)
+                for (int x = lo[0]; x <= hi[0]; x += 64) ts.h.push_back({ b, x, f, t });
+    }
+}
+
 ctu_status build_tables(ctu_plan *p)
 {
+    const int dim = p->opts.dim;
+    const bool mt = p->opts.corner == CTU_CORNER_MT;
     for (int b = 0; b < (int)p->hboxes.size(); b++) {
         const KBox &bx = p->hboxes[b];
         add_linear_tiles(p->t_cells, b, bx.cells);
         add_linear_tiles(p->t_cfl, b, (long long)bx.n[0] * bx.n[1] * bx.n[2]);
+        if (mt)
+            for (int D = 0; D < dim; D++) add_mt_tiles(p->t_mt[D], b, bx, D, dim);
     }
     ctu_status st;
-    TileSet *all[] = { &p->t_cells, &p->t_cfl };
+    TileSet *all[] = { &p->t_cells, &p->t_cfl, &p->t_mt[0], &p->t_mt[1], &p->t_mt[2] };
     for (TileSet *ts : all)
-        if ((st = upload(ts->h, &ts->d)) != CTU_OK) return st;
+        if (!ts->h.empty() && (st = upload(ts->h, &ts->d)) != CTU_OK) return st;
     return build_shape_tables(p);
 }
 
@@ -327,12 +353,14 @@ ctu_status enqueue_step(ctu_plan *p, const void *U_in, void *U_out, const double
         ma.o = p->ko;
         for (int D = 0; D < dim; D++) {
             hipError_t e;
+            ma.tiles = p->t_mt[D].d;
             if constexpr (sizeof(R) == 4)
-                e = launch_mtflux_f32(D, p->combo, p->t_cells.n(), ma, s);
+                e = launch_mtflux_f32(D, p->combo, p->t_mt[D].n(), ma, s);
             else
-                e = launch_mtflux_f64(D, p->combo, p->t_cells.n(), ma, s);
+                e = launch_mtflux_f64(D, p->combo, p->t_mt[D].n(), ma, s);
             if (e != hipSuccess) return fail(CTU_ERR_HIP, std::string("MT flux launch: ") + hipGetErrorString(e));
         }
+        ma.tiles = p->t_cells.d;
         if (dim == 3) hipLaunchKernelGGL((k_mtT<3, R>), dim3(p->t_cells.n()), dim3(NT), 0, s, ma);
         else hipLaunchKernelGGL((k_mtT<2, R>), dim3(p->t_cells.n()), dim3(NT), 0, s, ma);
         HIP_TRY(hipGetLastError());
