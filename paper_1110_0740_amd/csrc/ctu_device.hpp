@@ -171,8 +171,11 @@ template <bool TM, typename R> __device__ __forceinline__ void p2c_rmhd(const R 
 // bracket [lo, hi] (bisection when a step leaves it).  As v^2 B^2 >= (v.B)^2
 // and p <= k W (k = (Gamma - 1)/Gamma, or 1/4 for TM, whose p is at most
 // w/4), f >= (1 - k) W - D - E: the upper end (E + D)/(1 - k) has f >= 0.
-// Converged when |dW| <= 1e-14 W.
-template <bool TM> __device__ __forceinline__ int c2p_rmhd(const double *U, double *V, double gam, double Wguess)
+// Converged when |dW| <= tol W: 1e-14 for FP64 storage; 1e-10 for FP32
+// storage, where Newton's quadratic convergence leaves an error far below
+// the FP32 rounding of the result once a step is that small.
+template <bool TM>
+__device__ __forceinline__ int c2p_rmhd(const double *U, double *V, double gam, double Wguess, double tol = 1e-14)
 {
     const double D = U[RHO], E = U[ENG];
     const double m2 = U[MX1] * U[MX1] + U[MX2] * U[MX2] + U[MX3] * U[MX3];
@@ -228,7 +231,7 @@ template <bool TM> __device__ __forceinline__ int c2p_rmhd(const double *U, doub
         }
         double Wn = (df > 0.0) ? W - f / df : 0.5 * (lo + hi);
         if (!(Wn > lo && Wn < hi)) Wn = 0.5 * (lo + hi);
-        if (fabs(Wn - W) <= 1e-14 * W) { W = Wn; conv = true; break; }
+        if (fabs(Wn - W) <= tol * W) { W = Wn; conv = true; break; }
         W = Wn;
     }
     double sw = S / W;
@@ -359,7 +362,7 @@ template <int PHYS, typename R> __device__ __forceinline__ int c2p(const R *U, R
         double u[NV], v[NV];
 #pragma unroll
         for (int q = 0; q < NV; q++) u[q] = (double)U[q];
-        int f = c2p_rmhd<PHYS == PHYS_RMHD_TM>(u, v, (double)gam, Wguess);
+        int f = c2p_rmhd<PHYS == PHYS_RMHD_TM>(u, v, (double)gam, Wguess, sizeof(R) == 4 ? 1e-10 : 1e-14);
 #pragma unroll
         for (int q = 0; q < NV; q++) V[q] = (R)v[q];
         return f;
