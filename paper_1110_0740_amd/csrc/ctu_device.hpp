@@ -171,9 +171,11 @@ template <bool TM, typename R> __device__ __forceinline__ void p2c_rmhd(const R 
 // bracket [lo, hi] (bisection when a step leaves it).  As v^2 B^2 >= (v.B)^2
 // and p <= k W (k = (Gamma - 1)/Gamma, or 1/4 for TM, whose p is at most
 // w/4), f >= (1 - k) W - D - E: the upper end (E + D)/(1 - k) has f >= 0.
-// Converged when |dW| <= tol W: 1e-14 for FP64 storage; 1e-10 for FP32
-// storage, where Newton's quadratic convergence leaves an error far below
-// the FP32 rounding of the result once a step is that small.
+// Converged when |dW| <= tol max(W, E + D + B^2): the residual f carries
+// rounding of order eps (E + D + B^2), so a strongly magnetised cell cannot
+// resolve W better than that; tol = 1e-14 for FP64 storage, 1e-10 for FP32
+// storage (Newton's quadratic convergence leaves an error far below the
+// FP32 rounding of the result once a step is that small).
 template <bool TM>
 __device__ __forceinline__ int c2p_rmhd(const double *U, double *V, double gam, double Wguess, double tol = 1e-14)
 {
@@ -205,6 +207,7 @@ __device__ __forceinline__ int c2p_rmhd(const double *U, double *V, double gam, 
     double hi = TM ? (4.0 / 3.0) * (E + D) : gam * (E + D);
     double lo = 0.0;
     double W = (Wguess > 0.0 && Wguess < hi) ? Wguess : hi;
+    const double wscale = fmax(E + D + B2, 0.0);
     bool conv = false;
     double v2 = 0.0;
     for (int it = 0; it < 60; ++it) {
@@ -231,7 +234,7 @@ __device__ __forceinline__ int c2p_rmhd(const double *U, double *V, double gam, 
         }
         double Wn = (df > 0.0) ? W - f / df : 0.5 * (lo + hi);
         if (!(Wn > lo && Wn < hi)) Wn = 0.5 * (lo + hi);
-        if (fabs(Wn - W) <= tol * W) { W = Wn; conv = true; break; }
+        if (fabs(Wn - W) <= tol * fmax(W, wscale)) { W = Wn; conv = true; break; }
         W = Wn;
     }
     double sw = S / W;
