@@ -8,10 +8,12 @@
  * It follows Mignone et al., "The PLUTO code for adaptive mesh computations
  * in astrophysical fluid dynamics" (ApJS 2012):
  *   Sec. 2.1  ideal / non-ideal MHD equations (Eq. mhd, visc_tens, tc_flux)
- *   Sec. 2.2  relativistic MHD (Eq. rmhd, gammaEos)
+ *   Sec. 2.2  relativistic MHD (Eq. rmhd, gammaEos, TMEos)
  *   Sec. 3    GLM cleaning (Eq. glm2x2)
  *   Sec. 3.1  unsplit CTU update (Eq. update, incrementop_hyp/par, ctu_flux,
- *             transv, Ca, dt_cool)
+ *             transv, Ca, dt_cool); the listed solvers Rusanov, HLL, HLLC,
+ *             HLLD and Roe; the predictor-flux corner coupling for Pi = 0
+ *   App. B    shock-adaptive hybrid (HLL and MinMod near flagged zones)
  *   Sec. 3.2  characteristic normal predictors (Eq. char_var, wnorm_predp/m,
  *             ppm1, MClim, minmod, ppm_parabolic_lim, WENO3, WENO3a, Linear,
  *             harmonic_lim, vanalbada_lim)
@@ -20,7 +22,10 @@
  * and, where the paper defers to published methods, their textbook form:
  *   HLLD (Miyoshi & Kusano 2005), HLL (Harten, Lax & van Leer 1983),
  *   normalized MHD eigenvectors (Roe & Balsara 1996), GLM Riemann subsystem
- *   (Dedner et al. 2002).
+ *   (Dedner et al. 2002), MHD HLLC (Li 2005), MHD Roe averages (Cargo &
+ *   Gallice 1997), relativistic HLLC (Mignone & Bodo 2006) and HLLD
+ *   (Mignone, Ugliano & Bodo 2009), each re-derived from its jump conditions
+ *   as its comment states.
  *
  * Plain scalar loops, one box at a time, full-size temporaries, no tiling and
  * no fusion.  Left eigenvectors are obtained by numerically inverting the
