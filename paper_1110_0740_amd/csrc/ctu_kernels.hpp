@@ -10,6 +10,10 @@
 //                [g-1, g+n], differenced into the per-cell increments T_d
 //                of Eq. transv; with parabolic terms also the cell-centred
 //                V^{n+1/2}                                   (a2, a3, a5, a7)
+//   k_mtflux<D>, k_mtT
+//                instead of k_tcouple with the MT corner coupling: the
+//                transverse fluxes between normal-predictor states and their
+//                differences T_d
 //   k_sweep<D>   for direction D: normal predictor, corner coupling
 //                (Eq. transv), final Riemann solve (Eq. ctu_flux), flux
 //                registers, and the conservative update of U^{n+1}; the
