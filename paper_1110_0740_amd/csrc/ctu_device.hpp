@@ -323,7 +323,10 @@ __device__ __forceinline__ void speeds_rmhd(const R *V, R gam, R &lmin, R &lmax,
                          cs2 * (-R(2) * b0 * Bl * G - R(2) * l * Bl * Bl);
             if (dg == R(0)) break;
             const R ln = l - g / dg;
-            const bool done = fabs(ln - l) <= tol * fmax(fabs(l), R(1e-30));
+            // speeds are bounded by 1: a step below tol is at the precision
+            // of any root, also near l = 0, where a relative test would sit
+            // under the rounding of g and run to the iteration cap
+            const bool done = fabs(ln - l) <= tol * fmax(fabs(l), R(1));
             l = ln;
             if (done) break;
         }
