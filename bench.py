@@ -29,7 +29,7 @@ METRIC = "zone-updates/sec per CTU step (FP32 batched vs FP64 plain) + achieved 
 # 64 x (ADD + MUL + 2 FMA + TRANS) wave instructions) with the commands in
 # profiles/ctu_step_fp32_256cube_counters.md.  t^n: the run with one chunk
 # per tile column (--shape tiles,4096,16,1), which recomputes no marching
-# face (8-plane chunks execute 1507); x sweep: 64 pencils per block, the
+# face (4-plane chunks execute 1558); x sweep: 64 pencils per block, the
 # least per-block setup (16 pencils execute 1403).  They include the ~1 %
 # of items computed for the pencil ends and the region's halo faces.
 KERNEL_FLOPS_PER_ZONE = {"prim": 37.0, "tcouple": 1455.0, "sweep_x": 1389.0, "sweep_y": 1387.0,
@@ -39,16 +39,16 @@ KERNEL_FLOPS_PER_ZONE = {"prim": 37.0, "tcouple": 1455.0, "sweep_x": 1389.0, "sw
 # 524,308 KiB of FETCH_SIZE and 1,048,576 KiB of WRITE_SIZE, hence the
 # factors.  Same profile file; set an entry to None when its kernel changes
 # after the counter runs.
-KERNEL_TRAFFIC_BYTES = {"prim": (327952 * 2 + 646866) * 1024, "tcouple": (414005 * 2 + 2231380) * 1024,
-                        "sweep_x": (949088 * 2 + 638081) * 1024, "sweep_y": (1010164 * 2 + 630622) * 1024,
-                        "sweep_z": (995657 * 2 + 626022) * 1024}
+KERNEL_TRAFFIC_BYTES = {"prim": (327952 * 2 + 646866) * 1024, "tcouple": (473794 * 2 + 2098384) * 1024,
+                        "sweep_x": (948683 * 2 + 638250) * 1024, "sweep_y": (1007067 * 2 + 630046) * 1024,
+                        "sweep_z": (993793 * 2 + 626128) * 1024}
 # The launch shape of the single-box FP32 plan the counters above were taken
-# with (bench.py --shape tiles,8,16,1).  A kernel's traffic depends on the
+# with (bench.py --shape tiles,4,16,1).  A kernel's traffic depends on the
 # shape fields that change its tiles (the t^n layout -- no box of the 256^3
 # plan can take the flat one -- and chunk, the x-sweep pencils, the launch
 # order), so the roofline reports it only when the tuned shape agrees on
 # those fields.
-PROFILE_SHAPE = {"tc_layout": "tiles", "tc_chunk": 8, "x_pencils": 16, "xcd_order": 1}
+PROFILE_SHAPE = {"tc_layout": "tiles", "tc_chunk": 4, "x_pencils": 16, "xcd_order": 1}
 SHAPE_FIELDS = {"prim": (), "tcouple": ("tc_chunk", "xcd_order"), "sweep_x": ("x_pencils", "xcd_order"),
                 "sweep_y": ("xcd_order",), "sweep_z": ("xcd_order",)}
 
@@ -364,7 +364,7 @@ def main():
             lay, chunk, pen, xcd = args.shape.split(",")
             p32.set_shape(tc_layout=lay, tc_chunk=int(chunk), x_pencils=int(pen), xcd_order=int(xcd))
         elif not args.no_autotune:
-            p32.autotune(U32, Uo, params, reps=5, stream=s)
+            p32.autotune(U32, Uo, params, reps=20, stream=s)
         shape, flat_boxes = p32.get_shape()
         with torch.cuda.stream(s):
             p32.graph_capture(U32, Uo, params, rate, fails=fails, stream=s)

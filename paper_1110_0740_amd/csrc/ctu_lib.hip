@@ -793,7 +793,7 @@ ctu_status ctu_plan_autotune(ctu_plan *plan, const void *U_in_dev, void *U_out_d
         };
         // coordinate descent: t^n layout and chunk, x-sweep pencils, launch order
         const int layouts[] = { CTU_TC_AUTO, CTU_TC_TILES, CTU_TC_FLAT };
-        const int chunks[] = { 8, 16, 32 };
+        const int chunks[] = { 4, 8, 16, 32 };
         for (int L : layouts) {
             if (L != CTU_TC_TILES && !any_flat) continue;
             for (int ch : chunks) {
