@@ -1,7 +1,10 @@
 """Full-size parity: the whole 256^3 (3D MHD, non-ideal MHD) and 192^3
 (RMHD) steps run on the GPU in the launch configuration the bench times;
 the oracle recomputes sampled 8^3 sub-boxes (corners, edges and interior
-positions) exactly from the same input, and the two are compared there."""
+positions) exactly from the same input, and the two are compared there.
+The widened option sets (other Riemann solvers, the MT corner coupling, the
+App. B shock hybrid, the Taub-Matthews EOS, the exact relativistic fast
+speeds) are checked the same way in FP32 at the autotuned launch shape."""
 import numpy as np
 import pytest
 import torch
@@ -23,7 +26,7 @@ def sample_origins(n, rng):
     return pts
 
 
-def run_fullsize(V, n, gamma, dx, precision, cfl, okw, L0=None, chmax=None, seed=0):
+def run_fullsize(V, n, gamma, dx, precision, cfl, okw, L0=None, chmax=None, seed=0, tune=False):
     physics = okw.get("physics", "mhd")
     oo = O.make_opts(dim=3, gamma=gamma, dx=dx, **okw)
     U = O.prim2cons(oo, V)
@@ -41,6 +44,8 @@ def run_fullsize(V, n, gamma, dx, precision, cfl, okw, L0=None, chmax=None, seed
     params = torch.tensor([dt, ch], dtype=torch.float64, device=DEV)
     rate = torch.zeros(1, dtype=torch.float64, device=DEV)
     fails = torch.zeros(5, dtype=torch.int32, device=DEV)
+    if tune:
+        plan.autotune(Ud, Uo, params, L0=L0d, reps=1)
     plan.step(Ud, Uo, params, rate, L0=L0d, fails=fails)
     torch.cuda.synchronize()
     got = Uo.cpu().numpy().astype(np.float64).reshape(U.shape)
@@ -101,3 +106,36 @@ def test_nonideal_256_fullsize_sampled(precision, tol):
     worst, fails, rate, rate0 = run_fullsize(V, n, G, meta["dx"], precision, 0.4, okw, L0=L0, seed=3)
     assert fails == [0] * 5
     assert worst.max() <= tol, worst
+
+
+@pytest.fixture(scope="module")
+def mhd256():
+    Vt, meta = I.mhd3d_fields_torch(n=256, ng=NG, seed=2000, device=DEV)
+    V = Vt.cpu().numpy()
+    del Vt
+    return V, meta
+
+
+@pytest.mark.parametrize("okw", [dict(riemann="rusanov"), dict(riemann="hllc"), dict(riemann="roe"),
+                                 dict(riemann="hlld", corner="mt"), dict(riemann="hlld", shock_eps=5.0)],
+                         ids=["rusanov", "hllc", "roe", "mt_corner", "shock_hybrid"])
+def test_mhd3d_256_variants_fullsize_sampled_fp32(mhd256, okw):
+    V, meta = mhd256
+    worst, fails, rate, rate0 = run_fullsize(V, 256, meta["gamma"], meta["dx"], "fp32", 0.4,
+                                             dict(recon="ppm", **okw), seed=4, tune=True)
+    assert fails == [0] * 5
+    assert worst.max() <= 2e-6, worst
+    assert 0.5 * rate0 < rate < 2.0 * rate0
+
+
+@pytest.mark.parametrize("eos,xs,rs", [("tm", False, "hll"), ("ideal", True, "hll"), ("ideal", False, "hllc"),
+                                       ("ideal", False, "hlld")],
+                         ids=["tm", "exact_speeds", "hllc", "hlld"])
+def test_rmhd_192_variants_fullsize_sampled_fp32(eos, xs, rs):
+    V, meta = I.rmhd3d_fields(n=192, ng=NG, seed=4000)
+    worst, fails, rate, rate0 = run_fullsize(V, 192, meta["gamma"], meta["dx"], "fp32", 0.3,
+                                             dict(physics="rmhd", recon="lin_mc", predictor="mh", riemann=rs,
+                                                  eos=eos, exact_speeds=xs),
+                                             chmax=1.0, seed=5, tune=True)
+    assert fails == [0] * 5
+    assert worst.max() <= 2e-6, worst
