@@ -39,18 +39,18 @@ KERNEL_FLOPS_PER_ZONE = {"prim": 37.0, "tcouple": 1455.0, "sweep_x": 1389.0, "sw
 # 524,308 KiB of FETCH_SIZE and 1,048,576 KiB of WRITE_SIZE, hence the
 # factors.  Same profile file; set an entry to None when its kernel changes
 # after the counter runs.
-KERNEL_TRAFFIC_BYTES = {"prim": (327952 * 2 + 646866) * 1024, "tcouple": (473794 * 2 + 2098384) * 1024,
-                        "sweep_x": (948683 * 2 + 638250) * 1024, "sweep_y": (1007067 * 2 + 630046) * 1024,
-                        "sweep_z": (993793 * 2 + 626128) * 1024}
+KERNEL_TRAFFIC_BYTES = {"prim": (327952 * 2 + 646866) * 1024, "tcouple": (473739 * 2 + 2099500) * 1024,
+                        "sweep_x": (949173 * 2 + 638239) * 1024, "sweep_y": (1014995 * 2 + 632507) * 1024,
+                        "sweep_z": (1005719 * 2 + 629251) * 1024}
 # The launch shape of the single-box FP32 plan the counters above were taken
-# with (bench.py --shape tiles,4,16,1).  A kernel's traffic depends on the
+# with (bench.py --shape tiles,4,16,1,2).  A kernel's traffic depends on the
 # shape fields that change its tiles (the t^n layout -- no box of the 256^3
 # plan can take the flat one -- and chunk, the x-sweep pencils, the launch
-# order), so the roofline reports it only when the tuned shape agrees on
+# order, the y / z sweep segments), so the roofline reports it only when the tuned shape agrees on
 # those fields.
-PROFILE_SHAPE = {"tc_layout": "tiles", "tc_chunk": 4, "x_pencils": 16, "xcd_order": 1}
+PROFILE_SHAPE = {"tc_layout": "tiles", "tc_chunk": 4, "x_pencils": 16, "xcd_order": 1, "yz_segments": 2}
 SHAPE_FIELDS = {"prim": (), "tcouple": ("tc_chunk", "xcd_order"), "sweep_x": ("x_pencils", "xcd_order"),
-                "sweep_y": ("xcd_order",), "sweep_z": ("xcd_order",)}
+                "sweep_y": ("xcd_order", "yz_segments"), "sweep_z": ("xcd_order", "yz_segments")}
 
 
 def same_profiled_shape(kernel, res):
@@ -83,7 +83,7 @@ def parse():
                     help="skip the shock-hybrid and Rusanov variants of the FP32 step")
     ap.add_argument("--shape", default=None,
                     help="force the launch shape of the single-box FP32 plan instead of tuning it: "
-                         "LAYOUT,CHUNK,PENCILS,XCD (e.g. tiles,8,16,1)")
+                         "LAYOUT,CHUNK,PENCILS,XCD[,YZSEGMENTS] (e.g. tiles,4,16,1,2)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (HBM counter calibration) and exit")
     return ap.parse_args()
@@ -361,8 +361,9 @@ def main():
         Uo = torch.empty_like(U32)
         torch.cuda.synchronize()
         if args.shape:
-            lay, chunk, pen, xcd = args.shape.split(",")
-            p32.set_shape(tc_layout=lay, tc_chunk=int(chunk), x_pencils=int(pen), xcd_order=int(xcd))
+            f = args.shape.split(",")
+            p32.set_shape(tc_layout=f[0], tc_chunk=int(f[1]), x_pencils=int(f[2]), xcd_order=int(f[3]),
+                          yz_segments=int(f[4]) if len(f) > 4 else 0)
         elif not args.no_autotune:
             p32.autotune(U32, Uo, params, reps=20, stream=s)
         shape, flat_boxes = p32.get_shape()

@@ -237,18 +237,24 @@ ctu_status ctu_step(ctu_plan *plan, const void *U_in_dev, void *U_out_dev, const
  *  x_pencils : x-sweep pencils per block, 1..64; 0 = the count that idles
  *              the fewest lanes
  *  xcd_order : 1 = launch order that gives each XCD a contiguous run of
- *              tiles (halo lines shared in one L2); 0 = place order */
+ *              tiles (halo lines shared in one L2); 0 = place order
+ *  yz_segments: blocks per y- and z-sweep column of 64 pencils, 1..8
+ *              (0 = 1): each block updates a run of the line's cells and
+ *              first recomputes the two predicted states below its run, so
+ *              results do not depend on it; more, shorter blocks leave fewer
+ *              compute units with a single block at the end of a launch */
 typedef enum { CTU_TC_AUTO = 0, CTU_TC_TILES = 1, CTU_TC_FLAT = 2 } ctu_tc_layout;
 typedef struct {
     int32_t tc_layout;
     int32_t tc_chunk;
     int32_t x_pencils;
     int32_t xcd_order;
+    int32_t yz_segments;
 } ctu_shape;
 
 /* Rebuild the plan's tables for a shape (CTU_ERR_ARG for a field out of
  * range).  Allocates the new tables; drops a captured graph, which must be
- * captured again.  A new plan starts with {AUTO, 0, 0, 1}, or with the
+ * captured again.  A new plan starts with {AUTO, 0, 0, 1, 0}, or with the
  * shape that ctu_plan_autotune found for the same option set and box
  * extents earlier in the process. */
 ctu_status ctu_plan_set_shape(ctu_plan *plan, const ctu_shape *shape);
@@ -257,8 +263,10 @@ ctu_status ctu_plan_set_shape(ctu_plan *plan, const ctu_shape *shape);
 ctu_status ctu_plan_get_shape(const ctu_plan *plan, ctu_shape *shape_out, int32_t *flat_boxes_out);
 
 /* Measure candidate shapes on the caller's data and keep the fastest: the
- * t^n layout and chunk (8, 16, 32), then the x-sweep pencils per block, then
- * the launch order, one coordinate at a time, starting from the plan's
+ * t^n layout and chunk (4, 8, 16, 32), then the x-sweep pencils per block
+ * (16, 8, 32, 4, auto),
+ * then the y / z sweep segments (1, 2, 3, 4), then the launch order, one
+ * coordinate at a time, starting from the plan's
  * shape; a candidate replaces the incumbent only when it is more than 1 %
  * faster.  Each candidate runs 1 + reps
  * steps of U_in_dev into U_out_dev on the stream (U_out_dev is overwritten;

@@ -922,12 +922,20 @@ __global__ __launch_bounds__(NT, (sizeof(R) == 4 ? CTU_SWEEP_WAVES_F32 : CTU_SWE
     const int pos0 = tl.a;
     int items;
     int P = 0;
+    // y / z: the tile owns rows [r0, r1) of its 64 pencils (faces and updates
+    // below those rows); a segment that starts inside the line first re-runs
+    // rows r0 - 2 and r0 - 1 for the states and the flux below row r0, with
+    // the same arithmetic as the segment that owns them
+    int r0 = 0, rs = 0;
     if (D == 0) {
         P = min(tl.b, npos_tot - pos0);
         items = P * Lc;
     } else {
-        items = Lc * DEL;
+        r0 = tl.b;
+        rs = max(r0 - 2, 0);
+        items = (tl.c - rs) * DEL;
     }
+    const int sface = max(1, r0 - 1), supd = max(2, r0);
     const R gam = R(o.gamma);
     const R dt = R(a.params[0]);
     const R ch = R(a.params[1]);
@@ -950,7 +958,7 @@ __global__ __launch_bounds__(NT, (sizeof(R) == 4 ? CTU_SWEEP_WAVES_F32 : CTU_SWE
             s = kit % Lc;
             pos = pos0 + kit / Lc;
         } else {
-            s = kit / DEL;
+            s = rs + kit / DEL;
             pos = pos0 + kit % DEL;
             valid = valid && pos < npos_tot;
         }
@@ -1007,7 +1015,7 @@ __global__ __launch_bounds__(NT, (sizeof(R) == 4 ? CTU_SWEEP_WAVES_F32 : CTU_SWE
         __syncthreads();
 
         // ---- time-centred Riemann solve on the face below the item ----
-        if (valid && s >= 1) {
+        if (valid && s >= sface) {
             R UL[NV], VL[NV], VR[NV], F[NV];
 #pragma unroll
             for (int q = 0; q < NV; q++) UL[q] = (tid >= DEL) ? sP[q][tid - DEL] : cP[q][tid];
@@ -1041,7 +1049,7 @@ __global__ __launch_bounds__(NT, (sizeof(R) == 4 ? CTU_SWEEP_WAVES_F32 : CTU_SWE
                 for (int q = 0; q < NV; q++) F[q] -= Pi[q];
             }
             // ---- flux registers: dt * A * (F - Pi) on listed faces ----
-            if (a.reg && bx.reg1 > bx.reg0) {
+            if (a.reg && bx.reg1 > bx.reg0 && s >= r0) {
                 int gt0 = bx.lo[T0] + tc0, gt1 = (T1 < dim) ? bx.lo[T1] + tc1 : 0;
                 // only the rectangles on this face plane
                 const int *rf = a.rface + bx.rface[D] + (s - 1);
@@ -1067,7 +1075,7 @@ __global__ __launch_bounds__(NT, (sizeof(R) == 4 ? CTU_SWEEP_WAVES_F32 : CTU_SWE
         __syncthreads();
 
         // ---- conservative update (Eq. update) of the cell below the item ----
-        if (valid && s >= 2) {
+        if (valid && s >= supd) {
             const int cu = c - sD;
             R lamc = fmax(sL[tid], (tid >= DEL) ? sL[tid - DEL] : cL[tid]) * idxD;
             R u[NV];
@@ -1122,7 +1130,7 @@ __global__ __launch_bounds__(NT, (sizeof(R) == 4 ? CTU_SWEEP_WAVES_F32 : CTU_SWE
 #pragma unroll
             for (int q = 0; q < NV; q++) bUo.st(q, cu, u[q]);
         }
-        count_fails(fl, a.fails);
+        count_fails(s >= r0 ? fl : 0, a.fails);
         __syncthreads();
         // ---- carry the last DEL items into the next round ----
         if (tid >= NT - DEL) {

@@ -94,7 +94,7 @@ struct ctu_plan {
     int *dcell_start = nullptr;
     int nrefl_cells = 0;
     // launch shape of the t^n and sweep tables (see ctu_shape)
-    ctu_shape shape{ CTU_TC_AUTO, 0, 0, 1 };
+    ctu_shape shape{ CTU_TC_AUTO, 0, 0, 1, 0 };
     std::string tune_key;  // autotune cache key of the option set and box extents
     // graph
     hipGraph_t graph = nullptr;
@@ -229,7 +229,14 @@ ctu_status build_shape_tables(ctu_plan *p)
                                                : pencils_per_block(bx.n[0] + 2, npos);
                 for (int s = 0; s < npos; s += P) p->t_sweep[0].h.push_back(KTile{ b, s, P, 0 });
             } else {
-                for (int s = 0; s < npos; s += 64) p->t_sweep[D].h.push_back(KTile{ b, s, 64, 0 });
+                // rows [r0, r1) of the line of Lc items per tile: more, shorter
+                // blocks, so that the last blocks of the launch keep more
+                // waves per SIMD (each later segment re-runs two rows)
+                const int Lc = bx.n[D] + 2;
+                const int S = std::max(1, std::min(std::max(p->shape.yz_segments, 1), Lc / 2));
+                const int L = (Lc + S - 1) / S;
+                for (int s = 0; s < npos; s += 64)
+                    for (int r0 = 0; r0 < Lc; r0 += L) p->t_sweep[D].h.push_back(KTile{ b, s, r0, std::min(Lc, r0 + L) });
             }
         }
     }
@@ -449,6 +456,7 @@ ctu_status check_shape(const ctu_shape *sh)
     if (sh->tc_chunk < 0 || sh->tc_chunk > 4096) return fail(CTU_ERR_ARG, "tc_chunk must be 0 (default) or 1..4096");
     if (sh->x_pencils < 0 || sh->x_pencils > 64) return fail(CTU_ERR_ARG, "x_pencils must be 0 (auto) or 1..64");
     if (sh->xcd_order != 0 && sh->xcd_order != 1) return fail(CTU_ERR_ARG, "xcd_order must be 0 or 1");
+    if (sh->yz_segments < 0 || sh->yz_segments > 8) return fail(CTU_ERR_ARG, "yz_segments must be 0 (one) or 1..8");
     return CTU_OK;
 }
 
@@ -791,7 +799,8 @@ ctu_status ctu_plan_autotune(ctu_plan *plan, const void *U_in_dev, void *U_out_d
             }
             return CTU_OK;
         };
-        // coordinate descent: t^n layout and chunk, x-sweep pencils, launch order
+        // coordinate descent: t^n layout and chunk, x-sweep pencils, y / z
+        // sweep segments, launch order
         const int layouts[] = { CTU_TC_AUTO, CTU_TC_TILES, CTU_TC_FLAT };
         const int chunks[] = { 4, 8, 16, 32 };
         for (int L : layouts) {
@@ -803,10 +812,18 @@ ctu_status ctu_plan_autotune(ctu_plan *plan, const void *U_in_dev, void *U_out_d
                 if ((r = consider(c)) != CTU_OK) return r;
             }
         }
-        const int pencils[] = { 0, 4, 8, 16, 32 };
+        // the counts that measure fastest on a full line first: a later one
+        // must win by the 1 % margin against them, not against a slow start
+        const int pencils[] = { 16, 8, 32, 4, 0 };
         for (int P : pencils) {
             ctu_shape c = best;
             c.x_pencils = P;
+            if ((r = consider(c)) != CTU_OK) return r;
+        }
+        const int segs[] = { 0, 2, 3, 4 };
+        for (int S : segs) {
+            ctu_shape c = best;
+            c.yz_segments = S;
             if ((r = consider(c)) != CTU_OK) return r;
         }
         {

@@ -63,12 +63,12 @@ class CtuRegFace(C.Structure):
 
 class CtuShape(C.Structure):
     _fields_ = [("tc_layout", C.c_int32), ("tc_chunk", C.c_int32), ("x_pencils", C.c_int32),
-                ("xcd_order", C.c_int32)]
+                ("xcd_order", C.c_int32), ("yz_segments", C.c_int32)]
 
     def as_dict(self):
         inv = {v: k for k, v in TC_LAYOUT.items()}
         return {"tc_layout": inv.get(self.tc_layout, self.tc_layout), "tc_chunk": self.tc_chunk,
-                "x_pencils": self.x_pencils, "xcd_order": self.xcd_order}
+                "x_pencils": self.x_pencils, "xcd_order": self.xcd_order, "yz_segments": self.yz_segments}
 
 
 class CtuRefluxFace(C.Structure):
@@ -296,9 +296,9 @@ class Plan:
         self._leaf = leaf
         _check(lib().ctu_plan_set_leaf_mask(self._h, _ptr(leaf)))
 
-    def set_shape(self, tc_layout="auto", tc_chunk=0, x_pencils=0, xcd_order=1):
+    def set_shape(self, tc_layout="auto", tc_chunk=0, x_pencils=0, xcd_order=1, yz_segments=0):
         sh = CtuShape(TC_LAYOUT[tc_layout] if isinstance(tc_layout, str) else int(tc_layout), int(tc_chunk),
-                      int(x_pencils), int(xcd_order))
+                      int(x_pencils), int(xcd_order), int(yz_segments))
         _check(lib().ctu_plan_set_shape(self._h, C.byref(sh)))
 
     def get_shape(self):

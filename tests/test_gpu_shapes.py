@@ -1,6 +1,6 @@
 """Launch shapes and the autotuner: every shape of the t^n and sweep tables
 (rectangular or flat t^n blocks, chunk length, x-sweep pencils per block,
-launch order) gives bitwise the same step -- state, CFL rate and flux
+y / z sweep segments per column, launch order) gives bitwise the same step -- state, CFL rate and flux
 registers -- in FP64 and FP32, because the per-cell arithmetic does not
 depend on the tiling; the flat layout also matches the oracle.  The
 autotuner keeps a valid shape, does not change results, and caches its
@@ -24,8 +24,9 @@ SHAPES = [
     {"tc_layout": "tiles"},
     {"tc_layout": "flat"},
     {"tc_layout": "flat", "tc_chunk": 5, "x_pencils": 3, "xcd_order": 0},
-    {"tc_layout": "tiles", "tc_chunk": 1, "x_pencils": 64},
-    {"tc_chunk": 4096, "x_pencils": 1},
+    {"tc_layout": "tiles", "tc_chunk": 1, "x_pencils": 64, "yz_segments": 2},
+    {"tc_chunk": 4096, "x_pencils": 1, "yz_segments": 8},
+    {"yz_segments": 3, "xcd_order": 0},
 ]
 
 
@@ -128,7 +129,7 @@ def test_autotune_keeps_results_and_caches_the_shape():
     best, ms = r.plan.autotune(r.Uin, r.Uout, r.params, reps=1)
     assert ms > 0.0
     assert best["tc_layout"] in ("auto", "tiles", "flat") and best["tc_chunk"] in (0, 4, 8, 16, 32)
-    assert 0 <= best["x_pencils"] <= 64 and best["xcd_order"] in (0, 1)
+    assert 0 <= best["x_pencils"] <= 64 and best["xcd_order"] in (0, 1) and best["yz_segments"] in (0, 2, 3, 4)
     assert r.plan.get_shape()[0] == best
     U1, rate1, reg1 = r.step()
     assert np.array_equal(U0, U1) and rate0 == rate1 and np.array_equal(reg0, reg1)
@@ -137,10 +138,12 @@ def test_autotune_keeps_results_and_caches_the_shape():
     assert p2.get_shape()[0] == best
     # another precision is another key
     p3, _, _, _ = make_plan("fp32")
-    assert p3.get_shape()[0] == {"tc_layout": "auto", "tc_chunk": 0, "x_pencils": 0, "xcd_order": 1}
+    assert p3.get_shape()[0] == {"tc_layout": "auto", "tc_chunk": 0, "x_pencils": 0, "xcd_order": 1,
+                                 "yz_segments": 0}
     ctu.tune_cache_clear()
     p4, _, _, _ = make_plan("fp64")
-    assert p4.get_shape()[0] == {"tc_layout": "auto", "tc_chunk": 0, "x_pencils": 0, "xcd_order": 1}
+    assert p4.get_shape()[0] == {"tc_layout": "auto", "tc_chunk": 0, "x_pencils": 0, "xcd_order": 1,
+                                 "yz_segments": 0}
 
 
 def test_set_shape_validates_and_drops_the_graph():
@@ -150,9 +153,37 @@ def test_set_shape_validates_and_drops_the_graph():
         r.plan.graph_capture(r.Uin, r.Uout, r.params, r.rate, reg=r.reg, fails=r.fails, stream=s)
         r.plan.graph_launch(stream=s)
     s.synchronize()
-    for bad in ({"tc_layout": 3}, {"tc_chunk": -1}, {"tc_chunk": 4097}, {"x_pencils": 65}, {"xcd_order": 2}):
+    for bad in ({"tc_layout": 3}, {"tc_chunk": -1}, {"tc_chunk": 4097}, {"x_pencils": 65}, {"xcd_order": 2},
+                {"yz_segments": -1}, {"yz_segments": 9}):
         with pytest.raises(ctu.CtuError):
             r.plan.set_shape(**bad)
     r.plan.set_shape(tc_layout="flat")
     with pytest.raises(ctu.CtuError):
         r.plan.graph_launch(stream=s)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_failure_counts_do_not_depend_on_segments(precision):
+    """A cell whose energy is below its kinetic + magnetic part lies in the
+    rows that a later y segment re-runs below its own (2, 3 and 4 segments
+    of the 18-item line start at rows 9, 6 and 5): every segment count gives
+    the same state and the same failure counts, each failure counted once."""
+    from tests.gpu_common import GpuStepper, gpu_opts, single_box_plan
+    n, ng = 16, 4
+    V, meta = I.mhd2d_fields(n=n, ng=ng, seed=1003)
+    oo = O.make_opts(dim=2, dx=meta["dx"], gamma=meta["gamma"], recon="lin_mc")
+    U = O.prim2cons(oo, V)
+    U[4, 0, ng + 5, ng + 5] = 0.0
+    U[4, 0, ng + 3, ng + 9] = 0.0
+    plan = single_box_plan(gpu_opts(2, meta["dx"], meta["gamma"], precision=precision, recon="lin_mc"), (n, n), ng)
+    st = GpuStepper(plan, U.shape, precision)
+    ref = None
+    for S in (0, 2, 3, 4):
+        plan.set_shape(yz_segments=S)
+        out, rate, _, fails = st.step(U, 1e-3, 1.0)
+        assert sum(fails) >= 1
+        if ref is None:
+            ref = (out.copy(), rate, list(fails))
+            continue
+        assert np.array_equal(out, ref[0]), S
+        assert rate == ref[1] and list(fails) == ref[2], (S, fails, ref[2])
