@@ -187,3 +187,37 @@ def test_failure_counts_do_not_depend_on_segments(precision):
             continue
         assert np.array_equal(out, ref[0]), S
         assert rate == ref[1] and list(fails) == ref[2], (S, fails, ref[2])
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_segments_with_parabolic_terms_and_cooling(precision):
+    """With viscosity, resistivity, conduction and cooling the sweeps also
+    carry the per-cell signal rate between directions and reduce the cooling
+    change: 1, 2, 3 and 8 y / z segments give bitwise the same state, rate
+    and dp/p on a ragged box."""
+    from tests.gpu_common import GpuStepper, gpu_opts, single_box_plan
+    n, ng = (17, 14, 19), 4
+    V, meta = I.mhd3d_fields(n=n[0], ng=ng, seed=5000, box=I.Box((0, 0, 0), n), level_n=32)
+    coef = I.nonideal_coeffs(5001)
+    oo = O.make_opts(dim=3, dx=meta["dx"], gamma=meta["gamma"], recon="ppm", riemann="hlld")
+    U = O.prim2cons(oo, V)
+    dt = 0.4 / O.cfl_rate(oo, U, ng)
+    X, Y, Z = I.cell_centres(meta["box"], ng, meta["dx"], 3)
+    tc = I.cooling_time_field(5002, X, Y, Z, dt)
+    G = meta["gamma"]
+    T = V[4] / V[0]
+    L0 = V[4] / ((G - 1) * V[0] ** 2 * np.sqrt(T) * tc)
+    go = gpu_opts(3, meta["dx"], G, precision=precision, recon="ppm", riemann="hlld", parabolic_mask=7,
+                  tc_phi=0.3, cooling=True, cool_beta=0.5, T_floor=0.1 * float(T.min()), **coef)
+    plan = single_box_plan(go, n, ng)
+    st = GpuStepper(plan, U.shape, precision)
+    ref = None
+    for S in (0, 2, 3, 8):
+        plan.set_shape(yz_segments=S)
+        out, rate, dpp, fails = st.step(U, 0.5 * dt, 1.0, L0=L0)
+        assert fails == [0] * 5 and dpp > 0.0
+        if ref is None:
+            ref = (out.copy(), rate, dpp)
+            continue
+        assert np.array_equal(out, ref[0]), S
+        assert rate == ref[1] and dpp == ref[2], S
