@@ -570,7 +570,13 @@ __global__ __launch_bounds__(NT) void k_tcouple(TArgs<R> a)
     R Gm_prev[NV], Pm_prev[NV], Lx_prev[NV], Ly_prev[NV], Px_prev[NV], Py_prev[NV];
     for (int m = m0; m <= m1 + 1; m++) {
         const int cj = (DIM == 3) ? j : m, ck = (DIM == 3) ? m : 0;
+        // every state this plane's faces read, loaded together so that one
+        // wait covers the three loads
+        R VLx[NV], VLy[NV];
         if (inplane || (m <= m1 && (xf || yf))) ld_cell(bV, cidx(bx, i, cj, ck), Vc);
+        if (m <= m1 && xf) ld_cell(bV, cidx(bx, i - 1, cj, ck), VLx);
+        if constexpr (DIM == 3)
+            if (m <= m1 && yf) ld_cell(bV, cidx(bx, i, j - 1, ck), VLy);
         // ---- faces of this plane: the marching face below each region cell,
         // and the in-plane low faces of every position whose face borders the
         // region ----
@@ -579,9 +585,7 @@ __global__ __launch_bounds__(NT) void k_tcouple(TArgs<R> a)
         if (m <= m1) {
             R G[NV], P[NV];
             if (xf) {
-                R VL[NV];
-                ld_cell(bV, cidx(bx, i - 1, cj, ck), VL);
-                tface_s<0, PHYS, RS, PAR, SHK>(VL, Vc, Vb, bx, i, cj, ck, o, gam, ch, G, P, fb);
+                tface_s<0, PHYS, RS, PAR, SHK>(VLx, Vc, Vb, bx, i, cj, ck, o, gam, ch, G, P, fb);
 #pragma unroll
                 for (int q = 0; q < NV; q++) {
                     Gx[q][lx] = G[q];
@@ -590,9 +594,7 @@ __global__ __launch_bounds__(NT) void k_tcouple(TArgs<R> a)
             }
             if constexpr (DIM == 3) {
                 if (yf) {
-                    R VL[NV];
-                    ld_cell(bV, cidx(bx, i, j - 1, ck), VL);
-                    tface_s<1, PHYS, RS, PAR, SHK>(VL, Vc, Vb, bx, i, cj, ck, o, gam, ch, G, P, fb);
+                    tface_s<1, PHYS, RS, PAR, SHK>(VLy, Vc, Vb, bx, i, cj, ck, o, gam, ch, G, P, fb);
 #pragma unroll
                     for (int q = 0; q < NV; q++) {
                         Gy[q][ly] = G[q];
