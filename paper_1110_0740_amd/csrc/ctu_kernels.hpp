@@ -570,13 +570,18 @@ __global__ __launch_bounds__(NT) void k_tcouple(TArgs<R> a)
     R Gm_prev[NV], Pm_prev[NV], Lx_prev[NV], Ly_prev[NV], Px_prev[NV], Py_prev[NV];
     for (int m = m0; m <= m1 + 1; m++) {
         const int cj = (DIM == 3) ? j : m, ck = (DIM == 3) ? m : 0;
-        // every state this plane's faces read, loaded together so that one
-        // wait covers the three loads
+        // in FP32 every state this plane's faces read is loaded together, so
+        // that one wait covers the three loads; in FP64 the two neighbour
+        // states are loaded at their faces (held across the marching face
+        // they would take the registers of the second wave per SIMD)
+        constexpr bool GROUP = sizeof(R) == 4;
         R VLx[NV], VLy[NV];
         if (inplane || (m <= m1 && (xf || yf))) ld_cell(bV, cidx(bx, i, cj, ck), Vc);
-        if (m <= m1 && xf) ld_cell(bV, cidx(bx, i - 1, cj, ck), VLx);
-        if constexpr (DIM == 3)
-            if (m <= m1 && yf) ld_cell(bV, cidx(bx, i, j - 1, ck), VLy);
+        if constexpr (GROUP) {
+            if (m <= m1 && xf) ld_cell(bV, cidx(bx, i - 1, cj, ck), VLx);
+            if constexpr (DIM == 3)
+                if (m <= m1 && yf) ld_cell(bV, cidx(bx, i, j - 1, ck), VLy);
+        }
         // ---- faces of this plane: the marching face below each region cell,
         // and the in-plane low faces of every position whose face borders the
         // region ----
@@ -585,6 +590,7 @@ __global__ __launch_bounds__(NT) void k_tcouple(TArgs<R> a)
         if (m <= m1) {
             R G[NV], P[NV];
             if (xf) {
+                if constexpr (!GROUP) ld_cell(bV, cidx(bx, i - 1, cj, ck), VLx);
                 tface_s<0, PHYS, RS, PAR, SHK>(VLx, Vc, Vb, bx, i, cj, ck, o, gam, ch, G, P, fb);
 #pragma unroll
                 for (int q = 0; q < NV; q++) {
@@ -594,6 +600,7 @@ __global__ __launch_bounds__(NT) void k_tcouple(TArgs<R> a)
             }
             if constexpr (DIM == 3) {
                 if (yf) {
+                    if constexpr (!GROUP) ld_cell(bV, cidx(bx, i, j - 1, ck), VLy);
                     tface_s<1, PHYS, RS, PAR, SHK>(VLy, Vc, Vb, bx, i, cj, ck, o, gam, ch, G, P, fb);
 #pragma unroll
                     for (int q = 0; q < NV; q++) {
