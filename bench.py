@@ -39,7 +39,7 @@ KERNEL_FLOPS_PER_ZONE = {"prim": 37.0, "tcouple": 1455.0, "sweep_x": 1389.0, "sw
 # 524,308 KiB of FETCH_SIZE and 1,048,576 KiB of WRITE_SIZE, hence the
 # factors.  Same profile file; set an entry to None when its kernel changes
 # after the counter runs.
-KERNEL_TRAFFIC_BYTES = {"prim": (327952 * 2 + 646866) * 1024, "tcouple": (489676 * 2 + 2061260) * 1024,
+KERNEL_TRAFFIC_BYTES = {"prim": (327952 * 2 + 646866) * 1024, "tcouple": (471996 * 2 + 1987027) * 1024,
                         "sweep_x": (949173 * 2 + 638239) * 1024, "sweep_y": (1014995 * 2 + 632507) * 1024,
                         "sweep_z": (1005719 * 2 + 629251) * 1024}
 # The launch shape of the single-box FP32 plan the counters above were taken

@@ -575,12 +575,21 @@ __global__ __launch_bounds__(NT) void k_tcouple(TArgs<R> a)
         // states are loaded at their faces (held across the marching face
         // they would take the registers of the second wave per SIMD)
         constexpr bool GROUP = sizeof(R) == 4;
-        R VLx[NV], VLy[NV];
+        R VLx[NV], VLy[NV], VLe[NV], VRe[NV];
         if (inplane || (m <= m1 && (xf || yf))) ld_cell(bV, cidx(bx, i, cj, ck), Vc);
         if constexpr (GROUP) {
             if (m <= m1 && xf) ld_cell(bV, cidx(bx, i - 1, cj, ck), VLx);
             if constexpr (DIM == 3)
                 if (m <= m1 && yf) ld_cell(bV, cidx(bx, i, j - 1, ck), VLy);
+            // and the two states of the lane's extra face
+            if (m <= m1 && ed == 0) {
+                const int ej2 = (DIM == 3) ? ej : m;
+                ld_cell(bV, cidx(bx, ei - 1, ej2, ck), VLe);
+                ld_cell(bV, cidx(bx, ei, ej2, ck), VRe);
+            } else if (DIM == 3 && m <= m1 && ed == 1) {
+                ld_cell(bV, cidx(bx, ei, ej - 1, m), VLe);
+                ld_cell(bV, cidx(bx, ei, ej, m), VRe);
+            }
         }
         // ---- faces of this plane: the marching face below each region cell,
         // and the in-plane low faces of every position whose face borders the
@@ -612,20 +621,22 @@ __global__ __launch_bounds__(NT) void k_tcouple(TArgs<R> a)
             // the extra faces
             if (ed == 0) {
                 const int ej2 = (DIM == 3) ? ej : m;
-                R VL[NV], VR[NV];
-                ld_cell(bV, cidx(bx, ei - 1, ej2, ck), VL);
-                ld_cell(bV, cidx(bx, ei, ej2, ck), VR);
-                tface_s<0, PHYS, RS, PAR, SHK>(VL, VR, Vb, bx, ei, ej2, ck, o, gam, ch, G, P, fb);
+                if constexpr (!GROUP) {
+                    ld_cell(bV, cidx(bx, ei - 1, ej2, ck), VLe);
+                    ld_cell(bV, cidx(bx, ei, ej2, ck), VRe);
+                }
+                tface_s<0, PHYS, RS, PAR, SHK>(VLe, VRe, Vb, bx, ei, ej2, ck, o, gam, ch, G, P, fb);
 #pragma unroll
                 for (int q = 0; q < NV; q++) {
                     Gx[q][es] = G[q];
                     if (PAR) Px[q][es] = P[q];
                 }
             } else if (DIM == 3 && ed == 1) {
-                R VL[NV], VR[NV];
-                ld_cell(bV, cidx(bx, ei, ej - 1, m), VL);
-                ld_cell(bV, cidx(bx, ei, ej, m), VR);
-                tface_s<(DIM == 3 ? 1 : 0), PHYS, RS, PAR, SHK>(VL, VR, Vb, bx, ei, ej, m, o, gam, ch, G, P, fb);
+                if constexpr (!GROUP) {
+                    ld_cell(bV, cidx(bx, ei, ej - 1, m), VLe);
+                    ld_cell(bV, cidx(bx, ei, ej, m), VRe);
+                }
+                tface_s<(DIM == 3 ? 1 : 0), PHYS, RS, PAR, SHK>(VLe, VRe, Vb, bx, ei, ej, m, o, gam, ch, G, P, fb);
 #pragma unroll
                 for (int q = 0; q < NV; q++) {
                     Gy[q][es] = G[q];
