@@ -575,20 +575,25 @@ __global__ __launch_bounds__(NT) void k_tcouple(TArgs<R> a)
         // states are loaded at their faces (held across the marching face
         // they would take the registers of the second wave per SIMD)
         constexpr bool GROUP = sizeof(R) == 4;
+        constexpr bool GROUP_E = GROUP && !PAR && !SHK && RS != RS_ROE;
         R VLx[NV], VLy[NV], VLe[NV], VRe[NV];
         if (inplane || (m <= m1 && (xf || yf))) ld_cell(bV, cidx(bx, i, cj, ck), Vc);
         if constexpr (GROUP) {
             if (m <= m1 && xf) ld_cell(bV, cidx(bx, i - 1, cj, ck), VLx);
             if constexpr (DIM == 3)
                 if (m <= m1 && yf) ld_cell(bV, cidx(bx, i, j - 1, ck), VLy);
-            // and the two states of the lane's extra face
-            if (m <= m1 && ed == 0) {
-                const int ej2 = (DIM == 3) ? ej : m;
-                ld_cell(bV, cidx(bx, ei - 1, ej2, ck), VLe);
-                ld_cell(bV, cidx(bx, ei, ej2, ck), VRe);
-            } else if (DIM == 3 && m <= m1 && ed == 1) {
-                ld_cell(bV, cidx(bx, ei, ej - 1, m), VLe);
-                ld_cell(bV, cidx(bx, ei, ej, m), VRe);
+            // and the two states of the lane's extra face, where the registers
+            // they take keep three waves per SIMD (not with parabolic terms,
+            // shock flags or the Roe solver)
+            if constexpr (GROUP_E) {
+                if (m <= m1 && ed == 0) {
+                    const int ej2 = (DIM == 3) ? ej : m;
+                    ld_cell(bV, cidx(bx, ei - 1, ej2, ck), VLe);
+                    ld_cell(bV, cidx(bx, ei, ej2, ck), VRe);
+                } else if (DIM == 3 && m <= m1 && ed == 1) {
+                    ld_cell(bV, cidx(bx, ei, ej - 1, m), VLe);
+                    ld_cell(bV, cidx(bx, ei, ej, m), VRe);
+                }
             }
         }
         // ---- faces of this plane: the marching face below each region cell,
@@ -621,7 +626,7 @@ __global__ __launch_bounds__(NT) void k_tcouple(TArgs<R> a)
             // the extra faces
             if (ed == 0) {
                 const int ej2 = (DIM == 3) ? ej : m;
-                if constexpr (!GROUP) {
+                if constexpr (!GROUP_E) {
                     ld_cell(bV, cidx(bx, ei - 1, ej2, ck), VLe);
                     ld_cell(bV, cidx(bx, ei, ej2, ck), VRe);
                 }
@@ -632,7 +637,7 @@ __global__ __launch_bounds__(NT) void k_tcouple(TArgs<R> a)
                     if (PAR) Px[q][es] = P[q];
                 }
             } else if (DIM == 3 && ed == 1) {
-                if constexpr (!GROUP) {
+                if constexpr (!GROUP_E) {
                     ld_cell(bV, cidx(bx, ei, ej - 1, m), VLe);
                     ld_cell(bV, cidx(bx, ei, ej, m), VRe);
                 }
