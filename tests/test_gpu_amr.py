@@ -9,7 +9,7 @@ import torch
 import oracle as O
 from oracle import amr_reflux
 from paper_1110_0740_amd import amr, ctu, inputs as I
-from tests.gpu_common import DEV, l1rel
+from tests.gpu_common import DEV, assert_parity
 
 pytestmark = pytest.mark.gpu
 
@@ -71,8 +71,7 @@ def test_amr_batch_step_registers_and_reflux(precision):
     # 1. every patch of every level
     for lev in range(nlev):
         for b in range(len(h.levels[lev])):
-            e = l1rel(got_U[lev][b], ref_U[lev][b], NG, 3, ch)
-            assert e.max() <= tol, (lev, b, e)
+            assert_parity(got_U[lev][b], ref_U[lev][b], NG, 3, ch, tol, what=(lev, b))
     # 2. registers: dt * A * (F - Pi) of the oracle's faces
     regh = reg.cpu().numpy().reshape(-1, 9)
     worst = 0.0
@@ -104,8 +103,7 @@ def test_amr_batch_step_registers_and_reflux(precision):
         host = Uout.cpu().numpy().astype(np.float64)
         for b, (o, s) in enumerate(zip(offs, shapes)):
             g = host[o:o + int(np.prod(s))].reshape(s)
-            e = l1rel(g, want[b], NG, 3, ch)
-            assert e.max() <= tol * 5, (lev, b, e)
+            assert_parity(g, want[b], NG, 3, ch, tol * 5, what=(lev, b))
             # the correction is not zero where the box touches the fine level
             moved = np.abs(I.interior(want[b], NG, 3) - I.interior(ref_U[lev][b], NG, 3)).max()
             if any(ent[0] == b for ent in tables[lev].reflux):

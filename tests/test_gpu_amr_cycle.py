@@ -10,7 +10,7 @@ import torch
 import oracle as O
 from oracle import amr_cycle as AC
 from paper_1110_0740_amd import amr, ctu, inputs as I
-from tests.gpu_common import DEV, l1rel
+from tests.gpu_common import DEV, assert_parity
 
 pytestmark = pytest.mark.gpu
 
@@ -157,8 +157,7 @@ def test_subcycled_cycle_matches_oracle(precision, tol):
     assert fails == [0] * 5 and missing == 0
     for lev in range(len(h.levels)):
         for b in range(len(h.levels[lev])):
-            e = l1rel(got[lev][b], ref[lev][b], NG, 3, ch)
-            assert e.max() <= tol, (lev, b, e)
+            assert_parity(got[lev][b], ref[lev][b], NG, 3, ch, tol, what=(lev, b))
 
 
 def test_gpu_cycle_conserves_and_consumes_registers():

@@ -11,7 +11,7 @@ import torch
 
 import oracle as O
 from paper_1110_0740_amd import ctu, inputs as I
-from tests.gpu_common import DEV, l1rel, tdtype
+from tests.gpu_common import DEV, assert_parity, tdtype
 
 pytestmark = pytest.mark.gpu
 
@@ -119,7 +119,7 @@ def test_flat_layout_matches_oracle():
     for u_in, got in zip(r.U, r.boxes_out(U)):
         ref, _, _, fails = O.step(oo, u_in, NG, r.dt, r.ch)
         assert fails == [0] * 5
-        assert l1rel(got, ref, NG, 3, r.ch).max() <= 1e-12
+        assert_parity(got, ref, NG, 3, r.ch, 1e-12)
 
 
 def test_autotune_keeps_results_and_caches_the_shape():
