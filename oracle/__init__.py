@@ -28,10 +28,11 @@ PARAB_VISC, PARAB_RES, PARAB_TC = 1, 2, 4
 
 
 def build(force: bool = False) -> str:
-    """Compile the oracle shared object with gcc (OpenMP not used: the oracle
-    is single-threaded by design)."""
+    """Compile the oracle shared object with gcc.  Its independent cell and
+    face loops run on OpenMP threads (set_threads); results do not depend on
+    the thread count."""
     if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
-        cmd = ["gcc", "-O2", "-std=c99", "-fno-fast-math", "-ffp-contract=off", "-fPIC", "-shared",
+        cmd = ["gcc", "-O2", "-std=c99", "-fno-fast-math", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared",
                "-o", LIB + ".tmp", SRC, "-lm"]
         subprocess.check_call(cmd)
         os.replace(LIB + ".tmp", LIB)
@@ -85,29 +86,50 @@ _dp = C.POINTER(C.c_double)
 _ip = C.POINTER(C.c_int)
 
 
+def configure(L):
+    """Declare the argument types of a loaded oracle library (the built one,
+    or a test's copy of it)."""
+    L.orc_step.restype = C.c_int
+    L.orc_step.argtypes = [C.POINTER(Opts), C.c_int, C.c_int, C.c_int, C.c_int, _dp, _dp, C.c_double,
+                           C.c_double, _dp, _dp, _dp, _ip, C.POINTER(C.c_ubyte)]
+    L.orc_shock_flags.restype = C.c_int
+    L.orc_shock_flags.argtypes = [C.POINTER(Opts), C.c_int, C.c_int, C.c_int, C.c_int, _dp,
+                                  C.POINTER(C.c_ubyte)]
+    L.orc_cfl_rate.restype = C.c_double
+    L.orc_cfl_rate.argtypes = [C.POINTER(Opts), C.c_int, C.c_int, C.c_int, C.c_int, _dp]
+    L.orc_prim2cons.argtypes = [C.POINTER(Opts), C.c_long, _dp, _dp]
+    L.orc_cons2prim.argtypes = [C.POINTER(Opts), C.c_long, _dp, _dp, _ip]
+    L.orc_flux.argtypes = [C.POINTER(Opts), _dp, C.c_int, C.c_double, _dp]
+    L.orc_riemann.argtypes = [C.POINTER(Opts), _dp, _dp, C.c_int, C.c_double, _dp, _dp]
+    L.orc_speeds.argtypes = [C.POINTER(Opts), _dp, C.c_int, _dp, _dp]
+    L.orc_eigen.argtypes = [C.POINTER(Opts), _dp, C.c_int, _dp, _dp, _dp]
+    L.orc_reconstruct.argtypes = [C.c_int, _dp, C.c_double, _dp, _dp]
+    L.orc_trace.argtypes = [C.c_int, C.c_double, C.c_double, C.c_double, C.c_double, C.c_double,
+                            C.c_double, _dp, _dp]
+    L.orc_predict.argtypes = [C.POINTER(Opts), _dp, _dp, C.c_int, C.c_double, C.c_double, _dp, _dp, _ip]
+    L.orc_riemann_count.restype = C.c_long
+    L.orc_riemann_count.argtypes = [C.c_int]
+    L.orc_set_threads.restype = C.c_int
+    L.orc_set_threads.argtypes = [C.c_int]
+    return L
+
+
 def lib():
     global _lib
     if _lib is None:
-        _lib = C.CDLL(build())
-        _lib.orc_step.restype = C.c_int
-        _lib.orc_step.argtypes = [C.POINTER(Opts), C.c_int, C.c_int, C.c_int, C.c_int, _dp, _dp, C.c_double,
-                                  C.c_double, _dp, _dp, _dp, _ip, C.POINTER(C.c_ubyte)]
-        _lib.orc_shock_flags.restype = C.c_int
-        _lib.orc_shock_flags.argtypes = [C.POINTER(Opts), C.c_int, C.c_int, C.c_int, C.c_int, _dp,
-                                         C.POINTER(C.c_ubyte)]
-        _lib.orc_cfl_rate.restype = C.c_double
-        _lib.orc_cfl_rate.argtypes = [C.POINTER(Opts), C.c_int, C.c_int, C.c_int, C.c_int, _dp]
-        _lib.orc_prim2cons.argtypes = [C.POINTER(Opts), C.c_long, _dp, _dp]
-        _lib.orc_cons2prim.argtypes = [C.POINTER(Opts), C.c_long, _dp, _dp, _ip]
-        _lib.orc_flux.argtypes = [C.POINTER(Opts), _dp, C.c_int, C.c_double, _dp]
-        _lib.orc_riemann.argtypes = [C.POINTER(Opts), _dp, _dp, C.c_int, C.c_double, _dp, _dp]
-        _lib.orc_speeds.argtypes = [C.POINTER(Opts), _dp, C.c_int, _dp, _dp]
-        _lib.orc_eigen.argtypes = [C.POINTER(Opts), _dp, C.c_int, _dp, _dp, _dp]
-        _lib.orc_reconstruct.argtypes = [C.c_int, _dp, C.c_double, _dp, _dp]
-        _lib.orc_trace.argtypes = [C.c_int, C.c_double, C.c_double, C.c_double, C.c_double, C.c_double,
-                                   C.c_double, _dp, _dp]
-        _lib.orc_predict.argtypes = [C.POINTER(Opts), _dp, _dp, C.c_int, C.c_double, C.c_double, _dp, _dp, _ip]
+        _lib = configure(C.CDLL(build()))
     return _lib
+
+
+def set_threads(n: int = 0) -> int:
+    """Threads of the oracle's OpenMP loops for the next calls (0: the
+    OpenMP default, OMP_NUM_THREADS or every core); returns the count."""
+    return int(lib().orc_set_threads(int(n)))
+
+
+def riemann_count(reset: bool = True) -> int:
+    """Riemann solves since the last reset (then cleared if `reset`)."""
+    return int(lib().orc_riemann_count(int(bool(reset))))
 
 
 def _p(a: np.ndarray):

@@ -28,7 +28,11 @@
  *   as its comment states.
  *
  * Plain scalar loops, one box at a time, full-size temporaries, no tiling and
- * no fusion.  Left eigenvectors are obtained by numerically inverting the
+ * no fusion.  The cell and face loops of a stage are independent, so they
+ * are shared among OpenMP threads (orc_set_threads) with the failure counts
+ * summed and the CFL rate and |dp/p| maxima reduced; every value is computed
+ * by the same expression in the same order whatever the thread count, so
+ * the results are bitwise those of one thread.  Left eigenvectors are obtained by numerically inverting the
  * right-eigenvector matrix; the relativistic conserved-to-primitive map is
  * solved by bracketing bisection.  Both are slow and obviously correct.
  *
@@ -1080,9 +1084,16 @@ static void riemann_roe(const orc_opts *o, const double *VL, const double *VR, i
  * glm2x2 is solved exactly (characteristics psi +- c_h B_n), its interface
  * value of B_n is imposed on both states, then HLLD or HLL gives the other
  * seven fluxes.  Without GLM the two normal fields are averaged. */
+/* Number of Riemann solves since the last orc_riemann_count(1): an
+ * instrument for the statement of Sec. 3.1 that a 3D step takes six solves
+ * per zone (two per face direction). */
+static long orc_nsolve = 0;
+
 static void riemann(const orc_opts *o, const double *VLin, const double *VRin, int d, double ch,
                     double *F, double *smax)
 {
+#pragma omp atomic
+    orc_nsolve++;
     double VL[NVAR], VR[NVAR];
     memcpy(VL, VLin, sizeof(VL));
     memcpy(VR, VRin, sizeof(VR));
@@ -1832,6 +1843,7 @@ int orc_step(const orc_opts *o, int nx, int ny, int nz, int ng, const double *U_
     int lf[NFAIL] = { 0 };
 
     /* 1. primitive recovery on every cell */
+#pragma omp parallel for schedule(static) reduction(+ : lf[:NFAIL])
     for (long c = 0; c < NC; c++) {
         double u[NVAR], v[NVAR];
         for (int q = 0; q < NVAR; q++) u[q] = U_in[q * NC + c];
@@ -1854,13 +1866,14 @@ int orc_step(const orc_opts *o, int nx, int ny, int nz, int ng, const double *U_
      * have their whole predictor stencil inside the box. */
     for (int d = 0; d < dim; d++) {
         if (mt) {
-            int dummy[NFAIL] = { 0 };
+#pragma omp parallel for collapse(2) schedule(static)
             for (int k = 0; k < g.NZ; k++)
                 for (int j = 0; j < g.NY; j++)
                     for (int i = 0; i < g.NX; i++) {
                         int ci[3] = { i, j, k };
                         if (ci[d] < 2 || ci[d] > N[d] - 3) continue;
                         long c = cidx(&g, i, j, k);
+                        int dummy[NFAIL] = { 0 };
                         double Vs[5][NVAR], U0[NVAR], Vm[NVAR], Vp[NVAR];
                         for (int l = -2; l <= 2; l++) {
                             long cl = cidx(&g, i + l * offs[d][0], j + l * offs[d][1], k + l * offs[d][2]);
@@ -1874,6 +1887,7 @@ int orc_step(const orc_opts *o, int nx, int ny, int nz, int ng, const double *U_
                             PVp[q * NC + c] = Vp[q];
                         }
                     }
+#pragma omp parallel for collapse(2) schedule(static)
             for (int k = 0; k < g.NZ; k++)
                 for (int j = 0; j < g.NY; j++)
                     for (int i = 0; i < g.NX; i++) {
@@ -1887,6 +1901,7 @@ int orc_step(const orc_opts *o, int nx, int ny, int nz, int ng, const double *U_
                         for (int q = 0; q < NVAR; q++) Fn[(d * NVAR + q) * NC + cB] = F[q];
                     }
         }
+#pragma omp parallel for collapse(2) schedule(static)
         for (int k = 0; k < g.NZ; k++)
             for (int j = 0; j < g.NY; j++)
                 for (int i = 0; i < g.NX; i++) {
@@ -1913,6 +1928,7 @@ int orc_step(const orc_opts *o, int nx, int ny, int nz, int ng, const double *U_
                     }
                 }
         /* increment operators per cell (Eq. incrementop_hyp / incrementop_par) */
+#pragma omp parallel for collapse(2) schedule(static)
         for (int k = 0; k < g.NZ; k++)
             for (int j = 0; j < g.NY; j++)
                 for (int i = 0; i < g.NX; i++) {
@@ -1934,6 +1950,7 @@ int orc_step(const orc_opts *o, int nx, int ny, int nz, int ng, const double *U_
         for (int e = 0; e < 3; e++) { rlo[e] = lo[e]; rhi[e] = hi[e]; }
         rlo[d] = lo[d] - 1;
         rhi[d] = hi[d] + 1;
+#pragma omp parallel for collapse(2) schedule(static) reduction(+ : lf[:NFAIL])
         for (int k = rlo[2]; k < rhi[2]; k++)
             for (int j = rlo[1]; j < rhi[1]; j++)
                 for (int i = rlo[0]; i < rhi[0]; i++) {
@@ -1974,6 +1991,7 @@ int orc_step(const orc_opts *o, int nx, int ny, int nz, int ng, const double *U_
         int rlo[3], rhi[3];
         for (int e = 0; e < 3; e++) { rlo[e] = lo[e]; rhi[e] = hi[e]; }
         rhi[d] = hi[d] + 1;
+#pragma omp parallel for collapse(2) schedule(static) reduction(+ : lf[:NFAIL])
         for (int k = rlo[2]; k < rhi[2]; k++)
             for (int j = rlo[1]; j < rhi[1]; j++)
                 for (int i = rlo[0]; i < rhi[0]; i++) {
@@ -2019,6 +2037,7 @@ int orc_step(const orc_opts *o, int nx, int ny, int nz, int ng, const double *U_
             rlo[e] = lo[e] - (e < dim ? 1 : 0);
             rhi[e] = hi[e] + (e < dim ? 1 : 0);
         }
+#pragma omp parallel for collapse(2) schedule(static)
         for (int k = rlo[2]; k < rhi[2]; k++)
             for (int j = rlo[1]; j < rhi[1]; j++)
                 for (int i = rlo[0]; i < rhi[0]; i++) {
@@ -2029,6 +2048,7 @@ int orc_step(const orc_opts *o, int nx, int ny, int nz, int ng, const double *U_
                         Uhalf[q * NC + c] = U_in[q * NC + c] + 0.5 * dt * s;
                     }
                 }
+#pragma omp parallel for schedule(static)
         for (long c = 0; c < NC; c++) {
             double u[NVAR], v[NVAR];
             for (int q = 0; q < NVAR; q++) u[q] = Uhalf[q * NC + c];
@@ -2039,6 +2059,7 @@ int orc_step(const orc_opts *o, int nx, int ny, int nz, int ng, const double *U_
             int flo[3], fhi[3];
             for (int e = 0; e < 3; e++) { flo[e] = lo[e]; fhi[e] = hi[e]; }
             fhi[d] = hi[d] + 1;
+#pragma omp parallel for collapse(2) schedule(static)
             for (int k = flo[2]; k < fhi[2]; k++)
                 for (int j = flo[1]; j < fhi[1]; j++)
                     for (int i = flo[0]; i < fhi[0]; i++) {
@@ -2056,6 +2077,7 @@ int orc_step(const orc_opts *o, int nx, int ny, int nz, int ng, const double *U_
     double rate = 0.0, dpp = 0.0;
     double dxmin = o->dx[0];
     for (int e = 1; e < dim; e++) dxmin = fmin(dxmin, o->dx[e]);
+#pragma omp parallel for collapse(2) schedule(static) reduction(max : rate, dpp)
     for (int k = lo[2]; k < hi[2]; k++)
         for (int j = lo[1]; j < hi[1]; j++)
             for (int i = lo[0]; i < hi[0]; i++) {
@@ -2145,6 +2167,7 @@ double orc_cfl_rate(const orc_opts *o, int nx, int ny, int nz, int ng, const dou
     g.NZ = nz + 2 * gz;
     g.NC = (long)g.NX * g.NY * g.NZ;
     double rate = 0.0;
+#pragma omp parallel for collapse(2) schedule(static) reduction(max : rate)
     for (int k = gz; k < gz + nz; k++)
         for (int j = ng; j < ng + ny; j++)
             for (int i = ng; i < ng + nx; i++) {
@@ -2163,4 +2186,34 @@ double orc_cfl_rate(const orc_opts *o, int nx, int ny, int nz, int ng, const dou
                 rate = fmax(rate, r);
             }
     return rate;
+}
+
+/* Riemann solves counted since the last reset (reset != 0 clears it after
+ * reading). */
+long orc_riemann_count(int reset)
+{
+    long n;
+#pragma omp atomic read
+    n = orc_nsolve;
+    if (reset) {
+#pragma omp atomic write
+        orc_nsolve = 0;
+    }
+    return n;
+}
+
+/* Threads used by the OpenMP loops of the next calls (n <= 0: the OpenMP
+ * default); returns the count in force. */
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+int orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+    return omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
 }
