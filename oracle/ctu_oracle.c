@@ -2203,14 +2203,17 @@ long orc_riemann_count(int reset)
 }
 
 /* Threads used by the OpenMP loops of the next calls (n <= 0: the OpenMP
- * default); returns the count in force. */
+ * default of the process, OMP_NUM_THREADS or every core); returns the count
+ * in force. */
 #ifdef _OPENMP
 #include <omp.h>
 #endif
 int orc_set_threads(int n)
 {
 #ifdef _OPENMP
-    if (n > 0) omp_set_num_threads(n);
+    static int deflt = 0;
+    if (deflt == 0) deflt = omp_get_max_threads();
+    omp_set_num_threads(n > 0 ? n : deflt);
     return omp_get_max_threads();
 #else
     (void)n;
