@@ -1,0 +1,147 @@
+"""GPU parity of the batched AMR step on the configured hierarchy: 3 levels,
+ratio 2, 64 / 442 / 951 boxes of 16-32 cells around eight density blobs
+(1,457 patches, 17.4 M zones), one plan per level, FP64 flux registers and
+refluxing (Sec. 4, Eq. fluxcorr, Eq. addreflux), as the benchmark runs it.
+
+The oracle recomputes 36 seeded patches (12 per level, boxes with reflux
+entries among them): their updated states, every register slot of their
+faces, and, on the coarse ones, the refluxed state (the oracle's brute-force
+reflux with every fine box that touches the coarse box)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from oracle import amr_reflux
+from paper_1110_0740_amd import amr, ctu, inputs as I
+from tests.gpu_common import DEV, assert_parity
+
+pytestmark = pytest.mark.gpu
+
+NG = 4
+GAMMA = 5.0 / 3.0
+PER_LEVEL = 12
+
+
+def _touches(C, F):
+    """Fine box F (next level) covers a cell of coarse box C or a face
+    neighbour of one."""
+    for q in range(3):
+        flo, fhi = F.lo[q] // 2, (F.lo[q] + F.n[q]) // 2
+        if fhi <= C.lo[q] - 1 or flo >= C.lo[q] + C.n[q] + 1:
+            return False
+    return True
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_configured_hierarchy_sampled_patches_registers_reflux(precision):
+    h = I.amr_hierarchy()
+    nlev = len(h.levels)
+    npatch = sum(len(L) for L in h.levels)
+    assert 1400 <= npatch <= 1600, npatch
+    tables, nslots = amr.build_tables(h.levels, h.base, NG)
+    dt0 = 1e-4
+    ch = 0.4 * h.dx(0)[0] / dt0
+    dtype = torch.float64 if precision == "fp64" else torch.float32
+    reg = torch.zeros(9 * nslots, dtype=torch.float64, device=DEV)
+    rate = torch.zeros(1, dtype=torch.float64, device=DEV)
+    fails = torch.zeros(5, dtype=torch.int32, device=DEV)
+    rng = np.random.default_rng(3030)
+    samples, offs_all, U_host, got_host, plans, outs = [], [], [], [], [], []
+    for lev, L in enumerate(h.levels):
+        offs, o = [], 0
+        for B in L:
+            offs.append(o)
+            o += 9 * int(np.prod([n + 2 * NG for n in B.n]))
+        V = torch.empty(o, dtype=torch.float64, device=DEV)
+        for B, ob in zip(L, offs):
+            v = I.amr_fields_torch(h, B, NG, device=DEV).reshape(-1)
+            V[ob:ob + v.numel()] = v
+        go = ctu.make_opts(dim=3, recon="ppm", riemann="hlld", gamma=GAMMA, dx=h.dx(0), precision=precision)
+        boxes = [(B.lo, B.n, lev, ob) for B, ob in zip(L, offs)]
+        plan = ctu.Plan(go, boxes, NG, regfaces=tables[lev].regfaces)
+        p64 = ctu.Plan(ctu.make_opts(dim=3, recon="ppm", riemann="hlld", gamma=GAMMA, dx=h.dx(0)), boxes, NG)
+        U = torch.empty_like(V)
+        p64.prim_to_cons(V, U)
+        del V, p64
+        Uin = U.to(dtype)
+        Uout = Uin.clone()
+        params = torch.tensor([dt0 / (1 << lev), ch], dtype=torch.float64, device=DEV)
+        plan.step(Uin, Uout, params, rate, reg=reg, fails=fails)
+        torch.cuda.synchronize()
+        assert fails.sum().item() == 0
+        U_host.append(U.cpu().numpy())
+        got_host.append(Uout.cpu().numpy().astype(np.float64))
+        plans.append(plan)
+        outs.append(Uout)
+        offs_all.append(offs)
+        with_reflux = sorted({e[0] for e in tables[lev].reflux})
+        pick = list(rng.choice(len(L), size=PER_LEVEL // 2, replace=False))
+        if with_reflux:
+            pick += list(rng.choice(with_reflux, size=min(PER_LEVEL // 2, len(with_reflux)), replace=False))
+        samples.append(sorted(set(int(b) for b in pick)))
+        del U
+    regh = reg.cpu().numpy().reshape(-1, 9)
+
+    def box_state(lev, b, arr):
+        B = h.levels[lev][b]
+        shape = (9,) + tuple(n + 2 * NG for n in reversed(B.n))
+        o = offs_all[lev][b]
+        return arr[lev][o:o + int(np.prod(shape))].reshape(shape)
+
+    cache = {}
+
+    def oracle_box(lev, b):
+        if (lev, b) not in cache:
+            oo = O.make_opts(dim=3, recon="ppm", riemann="hlld", gamma=GAMMA, dx=h.dx(lev))
+            out = O.step(oo, box_state(lev, b, U_host), NG, dt0 / (1 << lev), ch, want_faces=True)
+            assert out[3] == [0] * 5
+            cache[(lev, b)] = out
+        return cache[(lev, b)]
+
+    tol = 1e-12 if precision == "fp64" else 2e-6
+    worst_reg = 0.0
+    for lev in range(nlev):
+        A = h.dx(lev)[0] ** 2
+        for b in samples[lev]:
+            ref, _, _, _, ff = oracle_box(lev, b)
+            assert_parity(box_state(lev, b, got_host), ref, NG, 3, ch, tol, what=(lev, b))
+            B = h.levels[lev][b]
+            for (rb, d, face, tlo, tn, slot) in tables[lev].regfaces:
+                if rb != b:
+                    continue
+                t = [e for e in range(3) if e != d]
+                for u1 in range(tn[1]):
+                    for u0 in range(tn[0]):
+                        idx = [0, 0, 0]
+                        idx[d] = face - B.lo[d] + NG
+                        idx[t[0]] = tlo[0] + u0 - B.lo[t[0]] + NG
+                        idx[t[1]] = tlo[1] + u1 - B.lo[t[1]] + NG
+                        want = ff[d][:, idx[2], idx[1], idx[0]] * A
+                        gotr = regh[slot + u1 * tn[0] + u0]
+                        worst_reg = max(worst_reg, np.abs(gotr - want).max() / (np.abs(want).max() + 1e-300))
+    assert worst_reg <= (1e-12 if precision == "fp64" else 5e-5), worst_reg
+    # reflux of every coarse level, then the sampled coarse boxes against the
+    # oracle's brute-force reflux over the fine boxes that touch them
+    for lev in range(nlev - 1):
+        plans[lev].set_reflux(tables[lev].reflux)
+        plans[lev].reflux(outs[lev], reg)
+    torch.cuda.synchronize()
+    nref = 0
+    for lev in range(nlev - 1):
+        host = outs[lev].cpu().numpy().astype(np.float64)
+        fine = h.levels[lev + 1]
+        for b in samples[lev]:
+            C = h.levels[lev][b]
+            near = [f for f, F in enumerate(fine) if _touches(C, F)]
+            if not near:
+                continue
+            ref_c = oracle_box(lev, b)
+            want = amr_reflux.reflux([C], [ref_c[0]], [ref_c[4]], h.dx(lev)[0], [fine[f] for f in near],
+                                     [oracle_box(lev + 1, f)[4] for f in near], h.dx(lev + 1)[0],
+                                     h.base << lev, NG)[0]
+            o = offs_all[lev][b]
+            g = host[o:o + want.size].reshape(want.shape)
+            assert_parity(g, want, NG, 3, ch, tol * 5, what=("reflux", lev, b))
+            nref += 1
+    assert nref >= 6, nref

@@ -96,12 +96,16 @@ def test_mhd3d_ppm_fp32_one_step():
 
 
 def test_mhd3d_ppm_fp32_hundred_chained_steps():
-    """FP32 GPU vs FP64 oracle after 100 chained steps on smooth data (the
-    oracle's dt sequence drives both)."""
-    n, ng = 16, 4
-    # at 16^3 the |k| <= 4 modes have 4 cells per wavelength: a Mach-1 flow
-    # steepens into unphysical states within 10 steps on both sides, so the
-    # smooth-data run uses v_rms = 0.3
+    """FP32 GPU vs FP64 oracle after 100 chained steps of the 3D workload's
+    generator at 64^3 (PPM + HLLD + GLM; the oracle's dt sequence drives
+    both, ghosts refilled periodically), every cell compared.
+
+    Smooth-data settings: at the configured Mach 1 the flow steepens and the
+    oracle itself reaches p < 0 by step 33 (no floors); at v_rms = 0.3 and
+    CFL 0.4 the PPM run with psi damping 0.1 breaks down at step 14 (it
+    survives with damping 0.8 or MC slopes), so the run uses v_rms = 0.3 at
+    CFL 0.3, which stays physical over the 100 steps."""
+    n, ng, cfl = 64, 4, 0.3
     V, meta = I.mhd3d_fields(n=n, ng=ng, seed=2001, v_rms=0.3)
     oo = oracle_opts(3, meta["dx"], meta["gamma"], recon="ppm", riemann="hlld")
     U = O.prim2cons(oo, V)
@@ -109,18 +113,18 @@ def test_mhd3d_ppm_fp32_hundred_chained_steps():
     st = GpuStepper(single_box_plan(go, (n, n, n), ng), U.shape, "fp32")
     Uo = U.copy()
     Ug = U.astype(np.float32).astype(np.float64)
-    dt, ch = _first_dt(oo, U, ng)
+    dt, ch = _first_dt(oo, U, ng, cfl)
     for s in range(100):
-        Uo_next, rref, _, _ = O.step(oo, Uo, ng, dt, ch)
+        Uo_next, rref, _, fref = O.step(oo, Uo, ng, dt, ch)
         Ug_next, _, _, fails = st.step(Ug, dt, ch)
-        assert fails == [0] * 5, (s, fails)
+        assert fails == [0] * 5 and fref == [0] * 5, (s, fails, fref)
         I.fill_periodic(Uo_next, ng, 3)
         I.fill_periodic(Ug_next, ng, 3)
         Uo, Ug = Uo_next, Ug_next
-        dt = 0.4 / rref
-        ch = 0.4 * meta["dx"][0] / dt
-    e = l1rel(Ug, Uo, ng, 3, ch)
-    assert e.max() <= TOL32_CHAIN, e
+        dt = cfl / rref
+        ch = cfl * meta["dx"][0] / dt
+    e, c = assert_parity(Ug, Uo, ng, 3, ch, TOL32_CHAIN, ctol=1e-3)
+    print(f"64^3 FP32 100 steps: L1 {e.max():.2e} cell {c.max():.2e}")
 
 
 @pytest.mark.parametrize("recon,riemann,wref", [
