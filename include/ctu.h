@@ -11,6 +11,10 @@
  * interpolation).
  *
  * Conventions shared by every entry point
+ *  - A plan (and a hierarchy) belongs to one HIP device, named at creation;
+ *    each call on it makes that device current for its duration and then
+ *    restores the caller's current device.  Streams passed with a plan must
+ *    belong to its device.
  *  - All pointers named *_dev are device pointers (hipMalloc / torch CUDA
  *    tensors) owned by the caller; the library never frees them.
  *  - Host pointers (options, box and register tables) are read during the
@@ -174,7 +178,7 @@ typedef struct {
  * side = +1 when the refined region lies on the cell's high face along the
  * correction direction, -1 on its low face.  Several entries may name the
  * same cell; they are applied by one thread per cell in table order. */
-typedef struct {
+typedef struct ctu_refluxface {
     int32_t box;        /* coarse box */
     int32_t i, j, k;    /* ghosted-local cell index inside that box */
     int32_t dir;        /* direction normal to the corrected face */
@@ -187,22 +191,54 @@ typedef struct {
 
 typedef struct ctu_plan ctu_plan;
 
-/* Create a plan for a batch of boxes (Sec. 3.1 applied to each patch of a
- * level, Sec. 4).  Validates the options, uploads the box and register
- * tables, builds the work decomposition and allocates the device workspace
- * (the only allocating call).  nghost must be >= 3 (PPM needs 3, parabolic
- * terms one more); box blocks must not overlap.  Returns CTU_ERR_UNSUPPORTED
- * for PPM/WENO3 with MUSCL-Hancock, characteristic tracing with RMHD,
- * parabolic/cooling terms with RMHD, Roe with RMHD, or the
- * shock-adaptive hybrid with the Rusanov, HLLC or Roe solver. */
+/* ctu_plan_create_ex flags: the library allocates no workspace; the caller
+ * supplies it with ctu_plan_set_workspace before the first step. */
+#define CTU_PLAN_CALLER_WORKSPACE 1u
+
+/* Create a plan for a batch of boxes on HIP device hip_device (Sec. 3.1
+ * applied to each patch of a level; Sec. 4 states the per-patch problem:
+ * advance one patch by dt with ghost zones filled by the caller).
+ * Validates the options, uploads the box, register and (optional, reflux /
+ * nreflux, as for ctu_plan_set_reflux) reflux tables, reserves the tile
+ * tables of every launch shape and, unless flags has
+ * CTU_PLAN_CALLER_WORKSPACE, allocates the device workspace.  This is the
+ * call that allocates; steps, launches, shape changes and the autotuner do
+ * not.  nghost must be >= 3 (PPM needs 3, parabolic terms one more); box
+ * blocks must not overlap.  Returns CTU_ERR_ARG for a device out of range
+ * or unknown flags, CTU_ERR_UNSUPPORTED for PPM/WENO3 with MUSCL-Hancock,
+ * characteristic tracing with RMHD, parabolic/cooling terms with RMHD, Roe
+ * with RMHD, or the shock-adaptive hybrid with the Rusanov, HLLC or Roe
+ * solver, CTU_ERR_NOMEM when an allocation fails. */
+ctu_status ctu_plan_create_ex(int32_t hip_device, uint32_t flags, const ctu_opts *opts, const ctu_box *boxes,
+                              int32_t nbox, int32_t nghost, const ctu_regface *regfaces, int32_t nreg,
+                              const struct ctu_refluxface *reflux, int32_t nreflux, ctu_plan **plan_out);
+/* ctu_plan_create_ex on the current device, library-owned workspace, no
+ * reflux table. */
 ctu_status ctu_plan_create(const ctu_opts *opts, const ctu_box *boxes, int32_t nbox, int32_t nghost,
                            const ctu_regface *regfaces, int32_t nreg, ctu_plan **plan_out);
 void ctu_plan_destroy(ctu_plan *plan);
+/* The plan's HIP device (-1 for a null plan). */
+int32_t ctu_plan_device(const ctu_plan *plan);
 
 /* Number of state elements the plan addresses: max over boxes of
- * offset + 9*NX*NY*NZ.  Device workspace bytes held by the plan. */
+ * offset + 9*NX*NY*NZ.  Bytes of device workspace the plan's option set
+ * needs (held by the plan, or to be supplied by the caller): V^n and the
+ * three corner-coupling increments T_d (9 values per ghosted cell each; in
+ * the state's element type), with parabolic terms V^{n+1/2} and one rate
+ * per cell, with the MT corner coupling three predictor-flux fields, with
+ * the App. B hybrid one flag byte per cell, each field 256-byte aligned. */
 int64_t ctu_plan_state_elems(const ctu_plan *plan);
 int64_t ctu_plan_workspace_bytes(const ctu_plan *plan);
+
+/* Give a plan created with CTU_PLAN_CALLER_WORKSPACE its workspace: ws_dev
+ * on the plan's device, 256-byte aligned, at least
+ * ctu_plan_workspace_bytes; it stays owned by the caller, who keeps it
+ * alive and unused by anything else while the plan steps.  May be called
+ * again to move the plan to another buffer (waits for the device first).
+ * Drops a captured graph.  CTU_ERR_ARG for a null, short or misaligned
+ * buffer or a plan that owns its workspace.  Steps of a plan without a
+ * workspace return CTU_ERR_ARG. */
+ctu_status ctu_plan_set_workspace(ctu_plan *plan, void *ws_dev, int64_t bytes);
 
 /* One CTU step (Sec. 3.1) of every box of the plan.
  *  U_in_dev   : state at t^n with ghosts filled (read only)
@@ -253,8 +289,9 @@ typedef struct {
 } ctu_shape;
 
 /* Rebuild the plan's tables for a shape (CTU_ERR_ARG for a field out of
- * range).  Allocates the new tables; drops a captured graph, which must be
- * captured again.  A new plan starts with {AUTO, 0, 0, 1, 0}, or with the
+ * range), in the buffers reserved at creation (no allocation; waits for the
+ * device first, as a step in flight reads the tables); drops a captured
+ * graph, which must be captured again.  A new plan starts with {AUTO, 0, 0, 1, 0}, or with the
  * shape that ctu_plan_autotune found for the same option set and box
  * extents earlier in the process. */
 ctu_status ctu_plan_set_shape(ctu_plan *plan, const ctu_shape *shape);
@@ -274,7 +311,8 @@ ctu_status ctu_plan_get_shape(const ctu_plan *plan, ctu_shape *shape_out, int32_
  * events; the call synchronizes the stream.  The winner is applied (as by
  * ctu_plan_set_shape), cached for plans of the same option set and box
  * extents created later in the process, and returned with its time per
- * step in ms.  cool_L0_dev is required when opts.cooling. */
+ * step in ms.  cool_L0_dev is required when opts.cooling.  Allocates
+ * nothing (its events and every shape's tables exist from creation). */
 ctu_status ctu_plan_autotune(ctu_plan *plan, const void *U_in_dev, void *U_out_dev, const double *params_dev,
                              const void *cool_L0_dev, int32_t reps, void *stream, ctu_shape *best_out,
                              double *best_ms_out);
@@ -301,7 +339,8 @@ ctu_status ctu_cons_to_prim(ctu_plan *plan, const void *U_dev, void *V_dev, int3
 /* Refluxing at level synchronisation (Eq. fluxcorr, Eq. addreflux).
  * ctu_plan_set_reflux uploads (and groups per coarse cell) a table of
  * corrections for the boxes of this (coarse) plan, replacing any previous
- * table; it allocates device memory.  ctu_reflux applies them to the coarse
+ * table (the one given to ctu_plan_create_ex included); a setup call that
+ * allocates device memory and waits for the device.  ctu_reflux applies them to the coarse
  * state in FP64 arithmetic; reg_dev holds both the coarse slots (dt*A*F of
  * the coarse step) and the fine slots (dt*A*F summed over the fine
  * substeps) that the table names. */
@@ -324,7 +363,8 @@ ctu_status ctu_reflux_consume(ctu_plan *coarse_plan, void *U_dev, double *reg_de
  * on levels >= 1, disjoint per level, level 0 covering the domain, every
  * fine box inside the coarser level's interiors, each box block below 4 GiB.
  * Host-side tables (candidate boxes per box for the lookups below) are
- * uploaded once; creation is the only allocating call. */
+ * uploaded once; creation is the only allocating call.  The hierarchy
+ * belongs to the device current at creation; its plans must too. */
 typedef struct ctu_hier ctu_hier;
 ctu_status ctu_hier_create(int32_t precision, int32_t base, int32_t nlev, const int32_t *level_nbox,
                            const ctu_box *boxes, int32_t nghost, ctu_hier **out);
@@ -402,7 +442,7 @@ ctu_status ctu_hier_advance(ctu_hier *hier, ctu_plan *const *plans, void *const 
 /* Per-stage kernel timing with HIP events recorded on the launch stream
  * around each kernel of ctu_step (eager launches only, not inside captured
  * graphs).  Enabling (re)starts the accumulation; up to 256 steps are
- * recorded.  ctu_plan_read_timing synchronises on the recorded events and
+ * recorded.  The first enable creates the events (a profiling setup call).  ctu_plan_read_timing synchronises on the recorded events and
  * writes the total milliseconds per stage into ms_out[CTU_NSTAGE] and the
  * number of recorded steps into nsteps_out.  Stages: 0 primitive recovery,
  * 1 the t^n fluxes and transverse increments (with the half step), 2-4

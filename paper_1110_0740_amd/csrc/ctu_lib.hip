@@ -1,10 +1,13 @@
 // ctu_lib.hip -- host side of libctu: plans, work tables, launches, graphs.
 //
-// Implements the C ABI declared in include/ctu.h.  A plan owns the uploaded
-// box / register / reflux tables, the tile tables of every kernel and the
-// device workspace (V^n, the t^n face fluxes, V^{n+1/2}, the per-cell rate
-// accumulator).  ctu_step enqueues the launch chain described in
-// ctu_kernels.hpp on the caller's stream; nothing in it allocates.
+// Implements the C ABI declared in include/ctu.h.  A plan belongs to one
+// device and owns the uploaded box / register / reflux tables and the tile
+// tables of every kernel (sized at creation for every launch shape); its
+// device workspace (V^n, the corner-coupling increments, V^{n+1/2}, the
+// per-cell rate accumulator, predictor fluxes, shock flags) is one block,
+// allocated at creation or supplied by the caller.  ctu_step enqueues the
+// launch chain described in ctu_kernels.hpp on the caller's stream; nothing
+// in it allocates.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -48,10 +51,40 @@ template <typename T> ctu_status upload(const std::vector<T> &h, T **d)
     return CTU_OK;
 }
 
+// copy a host table into a device buffer of `cap` entries reserved earlier
+template <typename T> ctu_status upload_into(const std::vector<T> &h, T *d, size_t cap)
+{
+    if (h.size() > cap) return fail(CTU_ERR_ARG, "table larger than its reserved capacity");
+    if (h.empty()) return CTU_OK;
+    HIP_TRY(hipMemcpy(d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
+    return CTU_OK;
+}
+
 struct TileSet {
     std::vector<KTile> h;
     KTile *d = nullptr;
+    size_t cap = 0;  // device entries reserved (shape tables: enough for every shape)
     int n() const { return (int)h.size(); }
+};
+
+// makes a plan's device current for the duration of a call and restores the
+// caller's device afterwards
+struct DevGuard {
+    int old = -1;
+    hipError_t err = hipSuccess;
+    explicit DevGuard(int dev)
+    {
+        int cur = -1;
+        err = hipGetDevice(&cur);
+        if (err == hipSuccess && cur != dev) {
+            err = hipSetDevice(dev);
+            if (err == hipSuccess) old = cur;
+        }
+    }
+    ~DevGuard()
+    {
+        if (old >= 0) (void)hipSetDevice(old);
+    }
 };
 
 // call f(std::integral_constant<int, PHYS>) for a plan's physics module
@@ -65,6 +98,7 @@ template <typename F> hipError_t with_phys(int phys, F &&f)
 }  // namespace
 
 struct ctu_plan {
+    int dev = 0;  // HIP device of the tables, the workspace and every launch
     ctu_opts opts;
     KOpts ko;
     Combo combo;
@@ -86,7 +120,9 @@ struct ctu_plan {
     void *wsVh = nullptr, *wsLam = nullptr;
     void *wsF[3] = { nullptr, nullptr, nullptr };  // MT corner coupling: predictor fluxes per direction
     unsigned char *wsFlag = nullptr;  // App. B zone flags (one byte per cell) or null
-    int64_t ws_bytes = 0;
+    int64_t ws_bytes = 0;      // bytes of the workspace block the option set needs
+    void *ws_block = nullptr;  // library-allocated workspace block (null: caller-owned or not yet set)
+    bool has_ws = false;       // a workspace is in place
     // cells entering the cooling time-step estimate (caller-owned) or null
     const unsigned char *leaf = nullptr;
     // reflux
@@ -99,6 +135,7 @@ struct ctu_plan {
     // graph
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
+    hipEvent_t tune_ev[2] = { nullptr, nullptr };  // autotuner timing events
     // per-stage event timing
     bool timing = false;
     int tsteps = 0;
@@ -113,13 +150,15 @@ namespace {
 void free_plan(ctu_plan *p)
 {
     if (!p) return;
+    DevGuard g(p->dev);
     for (hipEvent_t e : p->tev)
+        if (e) (void)hipEventDestroy(e);
+    for (hipEvent_t e : p->tune_ev)
         if (e) (void)hipEventDestroy(e);
     if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
     if (p->graph) (void)hipGraphDestroy(p->graph);
     void *ptrs[] = { p->dboxes, p->dregs, p->drface, p->t_cells.d, p->t_tc.d, p->t_sweep[0].d, p->t_sweep[1].d,
-                     p->t_sweep[2].d, p->t_cfl.d, p->wsV, p->wsT[0], p->wsT[1], p->wsT[2], p->wsVh, p->wsLam, p->wsFlag,
-                     p->drefl, p->dcell_start, p->wsF[0], p->wsF[1], p->wsF[2], p->t_mt[0].d, p->t_mt[1].d,
+                     p->t_sweep[2].d, p->t_cfl.d, p->ws_block, p->drefl, p->dcell_start, p->t_mt[0].d, p->t_mt[1].d,
                      p->t_mt[2].d };
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
@@ -191,19 +230,36 @@ bool use_flat(const ctu_plan *p, const KBox &bx)
 
 int tc_chunk(const ctu_plan *p) { return p->shape.tc_chunk > 0 ? p->shape.tc_chunk : TTile<3>::LM; }
 
-void free_tiles(TileSet &ts)
+// Entries of the shape-dependent tables for the largest shape: one-plane
+// t^n chunks in the layout with more blocks per plane, one pencil per x-sweep
+// block, eight y / z segments.
+void shape_capacity(const ctu_plan *p, size_t cap[4])
 {
-    if (ts.d) (void)hipFree(ts.d);
-    ts.d = nullptr;
-    ts.h.clear();
+    const int dim = p->opts.dim;
+    for (int q = 0; q < 4; q++) cap[q] = 0;
+    for (const KBox &bx : p->hboxes) {
+        const long long em = bx.n[dim - 1] + 2;
+        const int TX = (dim == 3) ? TTile<3>::TX : TTile<2>::TX;
+        const int TY = (dim == 3) ? TTile<3>::TY : TTile<2>::TY;
+        const long long ex = bx.n[0] + 2, ey = (dim == 3) ? bx.n[1] + 2 : 1;
+        long long per = ((ex + TX - 1) / TX) * ((ey + TY - 1) / TY);
+        if (flat_allowed(p, bx)) per = std::max(per, ((long long)(bx.n[0] + 3) * (bx.n[1] + 3) + NT - 1) / NT);
+        cap[0] += (size_t)(em * per);
+        for (int D = 0; D < dim; D++) {
+            int T0 = (D == 0) ? 1 : 0, T1 = (D == 2) ? 1 : 2;
+            long long npos = (long long)bx.n[T0] * ((T1 < dim) ? bx.n[T1] : 1);
+            cap[1 + D] += (size_t)(D == 0 ? npos : ((npos + 63) / 64) * 8);
+        }
+    }
 }
 
-// the tables that depend on the launch shape: t^n tiles and sweep columns
+// the tables that depend on the launch shape: t^n tiles and sweep columns,
+// rebuilt on the host and copied into the buffers reserved at creation
 ctu_status build_shape_tables(ctu_plan *p)
 {
     const int dim = p->opts.dim;
-    free_tiles(p->t_tc);
-    for (int D = 0; D < 3; D++) free_tiles(p->t_sweep[D]);
+    p->t_tc.h.clear();
+    for (int D = 0; D < 3; D++) p->t_sweep[D].h.clear();
     const int LM = tc_chunk(p);
     for (int b = 0; b < (int)p->hboxes.size(); b++) {
         const KBox &bx = p->hboxes[b];
@@ -246,8 +302,25 @@ ctu_status build_shape_tables(ctu_plan *p)
     }
     ctu_status st;
     TileSet *all[] = { &p->t_tc, &p->t_sweep[0], &p->t_sweep[1], &p->t_sweep[2] };
+    // a previous step may still read the tables being replaced
+    HIP_TRY(hipDeviceSynchronize());
     for (TileSet *ts : all)
-        if ((st = upload(ts->h, &ts->d)) != CTU_OK) return st;
+        if ((st = upload_into(ts->h, ts->d, ts->cap)) != CTU_OK) return st;
+    return CTU_OK;
+}
+
+// reserve the shape tables' device buffers for every shape (creation only)
+ctu_status reserve_shape_tables(ctu_plan *p)
+{
+    size_t cap[4];
+    shape_capacity(p, cap);
+    TileSet *all[] = { &p->t_tc, &p->t_sweep[0], &p->t_sweep[1], &p->t_sweep[2] };
+    for (int q = 0; q < 4; q++) {
+        all[q]->cap = cap[q];
+        if (cap[q] == 0) continue;
+        if (hipMalloc((void **)&all[q]->d, cap[q] * sizeof(KTile)) != hipSuccess)
+            return fail(CTU_ERR_NOMEM, "hipMalloc of a tile table failed");
+    }
     return CTU_OK;
 }
 
@@ -286,14 +359,47 @@ ctu_status build_tables(ctu_plan *p)
     TileSet *all[] = { &p->t_cells, &p->t_cfl, &p->t_mt[0], &p->t_mt[1], &p->t_mt[2] };
     for (TileSet *ts : all)
         if (!ts->h.empty() && (st = upload(ts->h, &ts->d)) != CTU_OK) return st;
+    if ((st = reserve_shape_tables(p)) != CTU_OK) return st;
     return build_shape_tables(p);
 }
 
-ctu_status alloc_ws(ctu_plan *p, void **ptr, int64_t elems)
+// Workspace fields of the option set, in block order, each starting on a
+// 256-byte boundary: V^n (9 per cell), T_d per direction, with parabolic
+// terms V^{n+1/2} and the per-cell rate, with the MT coupling the predictor
+// fluxes per direction, with the App. B hybrid one flag byte per cell.
+// With base == null only the size is computed.
+int64_t carve_ws(ctu_plan *p, char *base)
 {
-    int64_t bytes = elems * p->esize;
-    if (hipMalloc(ptr, bytes) != hipSuccess) return fail(CTU_ERR_NOMEM, "hipMalloc of the workspace failed");
-    p->ws_bytes += bytes;
+    const int64_t f9 = (int64_t)NV * p->ws_cells * p->esize;
+    int64_t off = 0;
+    auto take = [&](void **ptr, int64_t bytes) {
+        if (base) *ptr = base + off;
+        off += (bytes + 255) / 256 * 256;
+    };
+    void *dummy = nullptr;
+    take(base ? &p->wsV : &dummy, f9);
+    for (int d = 0; d < p->opts.dim; d++) take(base ? &p->wsT[d] : &dummy, f9);
+    if (p->opts.parabolic_mask) {
+        take(base ? &p->wsVh : &dummy, f9);
+        take(base ? &p->wsLam : &dummy, p->ws_cells * p->esize);
+    }
+    if (p->opts.corner == CTU_CORNER_MT)
+        for (int d = 0; d < p->opts.dim; d++) take(base ? &p->wsF[d] : &dummy, f9);
+    if (p->combo.shk) take(base ? (void **)&p->wsFlag : &dummy, p->ws_cells);
+    return off;
+}
+
+// drop a captured graph (it refers to the old tables or workspace)
+ctu_status drop_graph(ctu_plan *p)
+{
+    if (p->gexec) {
+        HIP_TRY(hipGraphExecDestroy(p->gexec));
+        p->gexec = nullptr;
+    }
+    if (p->graph) {
+        HIP_TRY(hipGraphDestroy(p->graph));
+        p->graph = nullptr;
+    }
     return CTU_OK;
 }
 
@@ -330,11 +436,11 @@ ctu_status enqueue_step(ctu_plan *p, const void *U_in, void *U_out, const double
     const R gam = (R)p->opts.gamma;
     {
         StageTimer tm(p, 0, s);
-        with_phys(p->combo.phys, [&](auto P) {
+        HIP_TRY(with_phys(p->combo.phys, [&](auto P) {
             hipLaunchKernelGGL((k_cons2prim<decltype(P)::value, R>), dim3(p->t_cells.n()), dim3(NT), 0, s,
                                p->dboxes, p->t_cells.d, (const R *)U_in, (R *)p->wsV, (int *)fails, gam, 1);
             return hipGetLastError();
-        });
+        }));
         if (p->wsFlag) {
             HIP_TRY(hipGetLastError());
             hipLaunchKernelGGL((k_shock_hll<R>), dim3(p->t_cells.n()), dim3(NT), 0, s, p->dboxes, p->t_cells.d,
@@ -463,14 +569,8 @@ ctu_status check_shape(const ctu_shape *sh)
 // rebuild the shape's tables; a captured graph refers to the old ones
 ctu_status apply_shape(ctu_plan *p, const ctu_shape &sh)
 {
-    if (p->gexec) {
-        HIP_TRY(hipGraphExecDestroy(p->gexec));
-        p->gexec = nullptr;
-    }
-    if (p->graph) {
-        HIP_TRY(hipGraphDestroy(p->graph));
-        p->graph = nullptr;
-    }
+    ctu_status st = drop_graph(p);
+    if (st != CTU_OK) return st;
     p->shape = sh;
     return build_shape_tables(p);
 }
@@ -479,6 +579,7 @@ ctu_status check_step_args(ctu_plan *p, const void *U_in, void *U_out, const dou
                            double *reg, double *rate)
 {
     if (!p) return fail(CTU_ERR_ARG, "null plan");
+    if (!p->has_ws) return fail(CTU_ERR_ARG, "the plan has no workspace: call ctu_plan_set_workspace first");
     if (!U_in || !U_out || !params || !rate) return fail(CTU_ERR_ARG, "U_in, U_out, params and rate are required");
     if (U_in == U_out) return fail(CTU_ERR_ARG, "U_out must not alias U_in");
     if (p->opts.cooling && !L0) return fail(CTU_ERR_ARG, "cooling needs cool_L0");
@@ -492,12 +593,17 @@ extern "C" {
 
 const char *ctu_last_error(void) { return g_err.c_str(); }
 
-ctu_status ctu_plan_create(const ctu_opts *opts, const ctu_box *boxes, int32_t nbox, int32_t nghost,
-                           const ctu_regface *regfaces, int32_t nreg, ctu_plan **plan_out)
+static ctu_status set_reflux_table(ctu_plan *plan, const ctu_refluxface *faces, int32_t nfaces);
+
+static ctu_status create_plan(int32_t dev, uint32_t flags, const ctu_opts *opts, const ctu_box *boxes, int32_t nbox,
+                              int32_t nghost, const ctu_regface *regfaces, int32_t nreg, const ctu_refluxface *reflux,
+                              int32_t nreflux, ctu_plan **plan_out)
 {
     if (!plan_out) return fail(CTU_ERR_ARG, "plan_out is null");
     *plan_out = nullptr;
     if (!opts || !boxes || nbox <= 0) return fail(CTU_ERR_ARG, "options and at least one box are required");
+    if (flags & ~(uint32_t)CTU_PLAN_CALLER_WORKSPACE) return fail(CTU_ERR_ARG, "unknown plan flags");
+    if (nreflux < 0 || (nreflux > 0 && !reflux)) return fail(CTU_ERR_ARG, "bad reflux table");
     const ctu_opts &o = *opts;
     if (o.dim != 2 && o.dim != 3) return fail(CTU_ERR_ARG, "dim must be 2 or 3");
     if (o.physics != CTU_MHD && o.physics != CTU_RMHD) return fail(CTU_ERR_ARG, "bad physics");
@@ -542,7 +648,16 @@ ctu_status ctu_plan_create(const ctu_opts *opts, const ctu_box *boxes, int32_t n
     if (nghost < 3 || nghost < need) return fail(CTU_ERR_ARG, "nghost too small for the stencil");
     if (nreg > 0 && !regfaces) return fail(CTU_ERR_ARG, "regfaces is null");
 
+    // the option checks above run on the host; the device is needed from here
+    {
+        int ndev = 0;
+        if (hipGetDeviceCount(&ndev) != hipSuccess) ndev = 0;
+        if (dev < 0 || dev >= ndev) return fail(CTU_ERR_ARG, "hip_device out of range (no such HIP device)");
+    }
+    DevGuard guard(dev);
+    HIP_TRY(guard.err);
     ctu_plan *p = new ctu_plan();
+    p->dev = dev;
     p->opts = o;
     p->combo = c;
     p->nghost = nghost;
@@ -688,38 +803,61 @@ ctu_status ctu_plan_create(const ctu_opts *opts, const ctu_box *boxes, int32_t n
             return st;
         }
     }
-    const int64_t f9 = NV * p->ws_cells;
-    if ((st = alloc_ws(p, &p->wsV, f9)) != CTU_OK) {
+    if (nreflux > 0 && (st = set_reflux_table(p, reflux, nreflux)) != CTU_OK) {
         free_plan(p);
         return st;
     }
-    for (int d = 0; d < o.dim; d++)
-        if ((st = alloc_ws(p, &p->wsT[d], f9)) != CTU_OK) {
-            free_plan(p);
-            return st;
-        }
-    if (o.parabolic_mask) {
-        if ((st = alloc_ws(p, &p->wsVh, f9)) != CTU_OK || (st = alloc_ws(p, &p->wsLam, p->ws_cells)) != CTU_OK) {
-            free_plan(p);
-            return st;
-        }
+    if (hipEventCreate(&p->tune_ev[0]) != hipSuccess || hipEventCreate(&p->tune_ev[1]) != hipSuccess) {
+        free_plan(p);
+        return fail(CTU_ERR_HIP, "hipEventCreate failed");
     }
-    if (o.corner == CTU_CORNER_MT)
-        for (int d = 0; d < o.dim; d++)
-            if ((st = alloc_ws(p, &p->wsF[d], f9)) != CTU_OK) {
-                free_plan(p);
-                return st;
-            }
-    if (c.shk) {
-        if (hipMalloc((void **)&p->wsFlag, p->ws_cells) != hipSuccess) {
+    p->ws_bytes = carve_ws(p, nullptr);
+    if (!(flags & CTU_PLAN_CALLER_WORKSPACE)) {
+        if (hipMalloc(&p->ws_block, p->ws_bytes) != hipSuccess) {
             free_plan(p);
-            return fail(CTU_ERR_NOMEM, "hipMalloc of the shock flags failed");
+            return fail(CTU_ERR_NOMEM, "hipMalloc of the workspace failed");
         }
-        p->ws_bytes += p->ws_cells;
+        carve_ws(p, (char *)p->ws_block);
+        p->has_ws = true;
     }
     *plan_out = p;
     return CTU_OK;
 }
+
+ctu_status ctu_plan_create(const ctu_opts *opts, const ctu_box *boxes, int32_t nbox, int32_t nghost,
+                           const ctu_regface *regfaces, int32_t nreg, ctu_plan **plan_out)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) dev = 0;  // no device: the option checks still report first
+    return create_plan(dev, 0u, opts, boxes, nbox, nghost, regfaces, nreg, nullptr, 0, plan_out);
+}
+
+ctu_status ctu_plan_create_ex(int32_t hip_device, uint32_t flags, const ctu_opts *opts, const ctu_box *boxes,
+                              int32_t nbox, int32_t nghost, const ctu_regface *regfaces, int32_t nreg,
+                              const ctu_refluxface *reflux, int32_t nreflux, ctu_plan **plan_out)
+{
+    return create_plan(hip_device, flags, opts, boxes, nbox, nghost, regfaces, nreg, reflux, nreflux, plan_out);
+}
+
+ctu_status ctu_plan_set_workspace(ctu_plan *plan, void *ws_dev, int64_t bytes)
+{
+    if (!plan) return fail(CTU_ERR_ARG, "null plan");
+    if (!ws_dev) return fail(CTU_ERR_ARG, "null workspace");
+    if (plan->ws_block) return fail(CTU_ERR_ARG, "the plan owns its workspace (created without CTU_PLAN_CALLER_WORKSPACE)");
+    if (bytes < plan->ws_bytes) return fail(CTU_ERR_ARG, "workspace smaller than ctu_plan_workspace_bytes");
+    if (((uintptr_t)ws_dev & 255u) != 0) return fail(CTU_ERR_ARG, "workspace must be 256-byte aligned");
+    DevGuard guard(plan->dev);
+    HIP_TRY(guard.err);
+    ctu_status st = drop_graph(plan);
+    if (st != CTU_OK) return st;
+    // a previous step may still use the old workspace
+    HIP_TRY(hipDeviceSynchronize());
+    carve_ws(plan, (char *)ws_dev);
+    plan->has_ws = true;
+    return CTU_OK;
+}
+
+int32_t ctu_plan_device(const ctu_plan *plan) { return plan ? plan->dev : -1; }
 
 void ctu_plan_destroy(ctu_plan *plan) { free_plan(plan); }
 
@@ -729,6 +867,8 @@ int64_t ctu_plan_workspace_bytes(const ctu_plan *plan) { return plan ? plan->ws_
 ctu_status ctu_plan_set_shape(ctu_plan *plan, const ctu_shape *shape)
 {
     if (!plan) return fail(CTU_ERR_ARG, "null plan");
+    DevGuard guard(plan->dev);
+    HIP_TRY(guard.err);
     ctu_status st = check_shape(shape);
     if (st != CTU_OK) return st;
     return apply_shape(plan, *shape);
@@ -755,10 +895,13 @@ ctu_status ctu_plan_autotune(ctu_plan *plan, const void *U_in_dev, void *U_out_d
     if (U_in_dev == U_out_dev) return fail(CTU_ERR_ARG, "U_out must not alias U_in");
     if (plan->opts.cooling && !cool_L0_dev) return fail(CTU_ERR_ARG, "cooling needs cool_L0");
     if (reps < 1 || reps > 1000) return fail(CTU_ERR_ARG, "reps must be in 1..1000");
+    if (!plan->has_ws) return fail(CTU_ERR_ARG, "the plan has no workspace: call ctu_plan_set_workspace first");
+    DevGuard guard(plan->dev);
+    HIP_TRY(guard.err);
     hipStream_t s = (hipStream_t)stream;
     const bool timing = plan->timing;
     plan->timing = false;
-    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipEvent_t e0 = plan->tune_ev[0], e1 = plan->tune_ev[1];
     ctu_status st = CTU_OK;
     auto run = [&](double &ms) -> ctu_status {
         ctu_status r;
@@ -779,8 +922,6 @@ ctu_status ctu_plan_autotune(ctu_plan *plan, const void *U_in_dev, void *U_out_d
         return CTU_OK;
     };
     auto body = [&]() -> ctu_status {
-        HIP_TRY(hipEventCreate(&e0));
-        HIP_TRY(hipEventCreate(&e1));
         bool any_flat = false;
         for (const KBox &b : plan->hboxes) any_flat = any_flat || flat_allowed(plan, b);
         ctu_shape best = plan->shape;
@@ -841,8 +982,6 @@ ctu_status ctu_plan_autotune(ctu_plan *plan, const void *U_in_dev, void *U_out_d
         return CTU_OK;
     };
     st = body();
-    if (e0) (void)hipEventDestroy(e0);
-    if (e1) (void)hipEventDestroy(e1);
     plan->timing = timing;
     return st;
 }
@@ -860,6 +999,8 @@ ctu_status ctu_step(ctu_plan *plan, const void *U_in_dev, void *U_out_dev, const
 {
     ctu_status st = check_step_args(plan, U_in_dev, U_out_dev, params_dev, cool_L0_dev, reg_dev, rate_dev);
     if (st != CTU_OK) return st;
+    DevGuard guard(plan->dev);
+    HIP_TRY(guard.err);
     hipStream_t s = (hipStream_t)stream;
     if (plan->esize == 4)
         return enqueue_step<float>(plan, U_in_dev, U_out_dev, params_dev, cool_L0_dev, reg_dev, rate_dev, dpp_dev,
@@ -875,15 +1016,10 @@ ctu_status ctu_step_graph_capture(ctu_plan *plan, const void *U_in_dev, void *U_
     ctu_status st = check_step_args(plan, U_in_dev, U_out_dev, params_dev, cool_L0_dev, reg_dev, rate_dev);
     if (st != CTU_OK) return st;
     if (!stream) return fail(CTU_ERR_ARG, "graph capture needs a non-default stream");
+    DevGuard guard(plan->dev);
+    HIP_TRY(guard.err);
     hipStream_t s = (hipStream_t)stream;
-    if (plan->gexec) {
-        HIP_TRY(hipGraphExecDestroy(plan->gexec));
-        plan->gexec = nullptr;
-    }
-    if (plan->graph) {
-        HIP_TRY(hipGraphDestroy(plan->graph));
-        plan->graph = nullptr;
-    }
+    if ((st = drop_graph(plan)) != CTU_OK) return st;
     bool was_timing = plan->timing;
     plan->timing = false;
     HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
@@ -909,6 +1045,8 @@ ctu_status ctu_step_graph_capture(ctu_plan *plan, const void *U_in_dev, void *U_
 ctu_status ctu_step_graph_launch(ctu_plan *plan, void *stream)
 {
     if (!plan || !plan->gexec) return fail(CTU_ERR_ARG, "no captured graph");
+    DevGuard guard(plan->dev);
+    HIP_TRY(guard.err);
     HIP_TRY(hipGraphLaunch(plan->gexec, (hipStream_t)stream));
     return CTU_OK;
 }
@@ -916,6 +1054,8 @@ ctu_status ctu_step_graph_launch(ctu_plan *plan, void *stream)
 ctu_status ctu_plan_enable_timing(ctu_plan *plan, int32_t enable)
 {
     if (!plan) return fail(CTU_ERR_ARG, "null plan");
+    DevGuard guard(plan->dev);
+    HIP_TRY(guard.err);
     if (enable && plan->tev.empty()) {
         plan->tev.assign(2 * (size_t)kMaxTimedSteps * CTU_NSTAGE, nullptr);
         for (auto &e : plan->tev) HIP_TRY(hipEventCreate(&e));
@@ -929,6 +1069,8 @@ ctu_status ctu_plan_enable_timing(ctu_plan *plan, int32_t enable)
 ctu_status ctu_plan_read_timing(ctu_plan *plan, double *ms_out, int32_t *nsteps_out)
 {
     if (!plan || !ms_out) return fail(CTU_ERR_ARG, "plan and ms_out are required");
+    DevGuard guard(plan->dev);
+    HIP_TRY(guard.err);
     for (int st = 0; st < CTU_NSTAGE; st++) ms_out[st] = 0.0;
     for (int step = 0; step < plan->tsteps; step++)
         for (int st = 0; st < CTU_NSTAGE; st++) {
@@ -946,6 +1088,8 @@ ctu_status ctu_plan_read_timing(ctu_plan *plan, double *ms_out, int32_t *nsteps_
 ctu_status ctu_cfl_rate(ctu_plan *plan, const void *U_dev, double *rate_dev, void *stream)
 {
     if (!plan || !U_dev || !rate_dev) return fail(CTU_ERR_ARG, "plan, U and rate are required");
+    DevGuard guard(plan->dev);
+    HIP_TRY(guard.err);
     hipStream_t s = (hipStream_t)stream;
     hipLaunchKernelGGL(k_reset<0>, dim3(1), dim3(64), 0, s, rate_dev, (double *)nullptr, (int *)nullptr);
     HIP_TRY(hipGetLastError());
@@ -966,6 +1110,8 @@ ctu_status ctu_cfl_rate(ctu_plan *plan, const void *U_dev, double *rate_dev, voi
 ctu_status ctu_prim_to_cons(ctu_plan *plan, const void *V_dev, void *U_dev, void *stream)
 {
     if (!plan || !V_dev || !U_dev) return fail(CTU_ERR_ARG, "plan, V and U are required");
+    DevGuard guard(plan->dev);
+    HIP_TRY(guard.err);
     hipStream_t s = (hipStream_t)stream;
     int nb = plan->t_cells.n();
     HIP_TRY(with_phys(plan->combo.phys, [&](auto P) {
@@ -984,6 +1130,8 @@ ctu_status ctu_prim_to_cons(ctu_plan *plan, const void *V_dev, void *U_dev, void
 ctu_status ctu_cons_to_prim(ctu_plan *plan, const void *U_dev, void *V_dev, int32_t *fails_dev, void *stream)
 {
     if (!plan || !V_dev || !U_dev) return fail(CTU_ERR_ARG, "plan, U and V are required");
+    DevGuard guard(plan->dev);
+    HIP_TRY(guard.err);
     hipStream_t s = (hipStream_t)stream;
     if (fails_dev) {
         hipLaunchKernelGGL(k_reset<0>, dim3(1), dim3(64), 0, s, (double *)nullptr, (double *)nullptr, (int *)fails_dev);
@@ -1006,6 +1154,14 @@ ctu_status ctu_cons_to_prim(ctu_plan *plan, const void *U_dev, void *V_dev, int3
 ctu_status ctu_plan_set_reflux(ctu_plan *plan, const ctu_refluxface *faces, int32_t nfaces)
 {
     if (!plan) return fail(CTU_ERR_ARG, "null plan");
+    DevGuard guard(plan->dev);
+    HIP_TRY(guard.err);
+    HIP_TRY(hipDeviceSynchronize());  // a previous reflux may still read the old table
+    return set_reflux_table(plan, faces, nfaces);
+}
+
+static ctu_status set_reflux_table(ctu_plan *plan, const ctu_refluxface *faces, int32_t nfaces)
+{
     if (nfaces > 0 && !faces) return fail(CTU_ERR_ARG, "faces is null");
     // group the entries per coarse cell, keeping table order inside a cell
     std::map<std::pair<int, long long>, std::vector<int>> groups;
@@ -1059,6 +1215,8 @@ static ctu_status reflux_launch(ctu_plan *plan, void *U_dev, double *reg_dev, in
 {
     if (!plan || !U_dev || !reg_dev) return fail(CTU_ERR_ARG, "plan, U and reg are required");
     if (plan->nrefl_cells == 0) return CTU_OK;
+    DevGuard guard(plan->dev);
+    HIP_TRY(guard.err);
     int nb = (plan->nrefl_cells + NT - 1) / NT;
     hipStream_t s = (hipStream_t)stream;
     if (plan->esize == 4)
@@ -1146,6 +1304,7 @@ long long overlap_volume(const HBox &a, const int lo[3], const int hi[3])
 }  // namespace
 
 struct ctu_hier {
+    int dev = 0;  // the device current at creation: tables, counters and launches
     int esize = 8, base = 0, nlev = 0, ng = 0;
     std::vector<HierLevel> lev;
     int *dfails = nullptr;  // per-step failure counts inside the cycle
@@ -1156,6 +1315,7 @@ namespace {
 void free_hier(ctu_hier *h)
 {
     if (!h) return;
+    DevGuard g(h->dev);
     for (HierLevel &L : h->lev) {
         void *ptrs[] = { L.db, L.d_nb_start, L.d_nb_list, L.d_cb_start, L.d_cb_list, L.d_pb_start, L.d_pb_list,
                          L.d_ch_start, L.d_ch_list, L.d_fill_t, L.d_avg_t };
@@ -1264,6 +1424,7 @@ ctu_status ctu_hier_create(int32_t precision, int32_t base, int32_t nlev, const 
         return fail(CTU_ERR_ARG, "need base >= 2, 1 <= nlev <= 16, nghost >= 1, level_nbox and boxes");
     if ((long long)base << (nlev - 1) > (1LL << 30)) return fail(CTU_ERR_ARG, "finest level too large");
     ctu_hier *h = new ctu_hier();
+    if (hipGetDevice(&h->dev) != hipSuccess) h->dev = 0;  // host checks below report first; uploads then fail
     h->esize = (precision == CTU_FP32) ? 4 : 8;
     h->base = base;
     h->nlev = nlev;
@@ -1412,6 +1573,8 @@ ctu_status ctu_hier_fill_ghosts(ctu_hier *h, int32_t level, void *U_dev, const v
     if (level > 0 && !Uc_old_dev) return fail(CTU_ERR_ARG, "levels >= 1 need the coarse state");
     if (level > 0 && alpha != 0.0 && !Uc_new_dev) return fail(CTU_ERR_ARG, "alpha != 0 needs the new coarse state");
     if (!(alpha >= 0.0 && alpha <= 1.0)) return fail(CTU_ERR_ARG, "alpha must lie in [0, 1]");
+    DevGuard guard(h->dev);
+    HIP_TRY(guard.err);
     return hier_fill_any(h, level, U_dev, Uc_old_dev, Uc_new_dev, alpha, missing_dev, (hipStream_t)stream);
 }
 
@@ -1420,6 +1583,8 @@ ctu_status ctu_hier_average_down(ctu_hier *h, int32_t fine_level, const void *U_
 {
     if (!h || fine_level < 1 || fine_level >= h->nlev || !U_fine_dev || !U_coarse_dev)
         return fail(CTU_ERR_ARG, "bad hierarchy, level or states");
+    DevGuard guard(h->dev);
+    HIP_TRY(guard.err);
     return hier_avg_any(h, fine_level, U_fine_dev, U_coarse_dev, (hipStream_t)stream);
 }
 
@@ -1435,7 +1600,12 @@ ctu_status ctu_hier_advance(ctu_hier *h, ctu_plan *const *plans, void *const *U_
         if (plans[l]->esize != h->esize) return fail(CTU_ERR_ARG, "plan and hierarchy precisions differ");
         if (plans[l]->hboxes.size() != h->lev[l].hb.size())
             return fail(CTU_ERR_ARG, "plan of a level must hold that level's boxes");
+        if (plans[l]->dev != h->dev) return fail(CTU_ERR_ARG, "plans and hierarchy belong to different devices");
+        if (!plans[l]->has_ws) return fail(CTU_ERR_ARG, "a level's plan has no workspace");
     }
+    DevGuard guard(h->dev);
+    HIP_TRY(guard.err);
+
     CycleArgs c{ h,       plans,     U_a,       U_b,         cur,         params_dev,         reg_dev,
                  rate_dev, dpp_dev, fails_dev, missing_dev, cool_L0_dev, (hipStream_t)stream };
     return advance_level(c, 0, nullptr, nullptr, 0.0);
@@ -1444,6 +1614,8 @@ ctu_status ctu_hier_advance(ctu_hier *h, ctu_plan *const *plans, void *const *U_
 ctu_status ctu_hier_leaf_mask(ctu_hier *h, int32_t level, uint8_t *leaf_dev, void *stream)
 {
     if (!h || !leaf_dev || level < 0 || level >= h->nlev) return fail(CTU_ERR_ARG, "bad hierarchy, level or mask");
+    DevGuard guard(h->dev);
+    HIP_TRY(guard.err);
     HierLevel &L = h->lev[level];
     if (L.fill_t.empty()) return CTU_OK;
     const HBox *fbox = (level + 1 < h->nlev) ? h->lev[level + 1].db : nullptr;
@@ -1458,6 +1630,8 @@ ctu_status ctu_hier_tag(ctu_hier *h, int32_t level, const void *U_dev, int32_t v
 {
     if (!h || !U_dev || !tags_dev || level < 0 || level >= h->nlev) return fail(CTU_ERR_ARG, "bad hierarchy, level or arrays");
     if (var < 0 || var >= NV || !(eps >= 0.0)) return fail(CTU_ERR_ARG, "var must name a conserved variable; eps >= 0");
+    DevGuard guard(h->dev);
+    HIP_TRY(guard.err);
     HierLevel &L = h->lev[level];
     if (L.fill_t.empty()) return CTU_OK;
     hipStream_t s = (hipStream_t)stream;
@@ -1486,6 +1660,8 @@ ctu_status ctu_hier_next_dt(ctu_hier *h, const double *rate_dev, const double *d
     a.nlev = h->nlev;
     a.cfl = cfl;
     a.eps_c = eps_c;
+    DevGuard guard(h->dev);
+    HIP_TRY(guard.err);
     hipLaunchKernelGGL(k_next_dt, dim3(1), dim3(64), 0, (hipStream_t)stream, a);
     HIP_TRY(hipGetLastError());
     return CTU_OK;

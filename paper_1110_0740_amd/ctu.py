@@ -32,7 +32,9 @@ SYMBOLS = [
     "ctu_last_error", "ctu_hier_create", "ctu_hier_destroy", "ctu_hier_fill_ghosts", "ctu_hier_average_down",
     "ctu_hier_advance", "ctu_hier_leaf_mask", "ctu_hier_tag", "ctu_hier_next_dt", "ctu_plan_set_leaf_mask",
     "ctu_plan_set_shape", "ctu_plan_get_shape", "ctu_plan_autotune", "ctu_tune_cache_clear",
+    "ctu_plan_create_ex", "ctu_plan_set_workspace", "ctu_plan_device",
 ]
+PLAN_CALLER_WORKSPACE = 1
 TC_LAYOUT = {"auto": 0, "tiles": 1, "flat": 2}
 NSTAGE = 8
 STAGES = ["prim", "tcouple", "unused2", "unused3", "unused4", "sweep_x", "sweep_y", "sweep_z"]
@@ -91,6 +93,14 @@ def lib() -> C.CDLL:
         L.ctu_plan_create.restype = C.c_int32
         L.ctu_plan_create.argtypes = [C.POINTER(CtuOpts), C.POINTER(CtuBox), C.c_int32, C.c_int32,
                                       C.POINTER(CtuRegFace), C.c_int32, C.POINTER(_vp)]
+        L.ctu_plan_create_ex.restype = C.c_int32
+        L.ctu_plan_create_ex.argtypes = [C.c_int32, C.c_uint32, C.POINTER(CtuOpts), C.POINTER(CtuBox), C.c_int32,
+                                         C.c_int32, C.POINTER(CtuRegFace), C.c_int32, C.POINTER(CtuRefluxFace),
+                                         C.c_int32, C.POINTER(_vp)]
+        L.ctu_plan_set_workspace.restype = C.c_int32
+        L.ctu_plan_set_workspace.argtypes = [_vp, _vp, C.c_int64]
+        L.ctu_plan_device.restype = C.c_int32
+        L.ctu_plan_device.argtypes = [_vp]
         L.ctu_plan_destroy.argtypes = [_vp]
         L.ctu_plan_state_elems.restype = C.c_int64
         L.ctu_plan_state_elems.argtypes = [_vp]
@@ -201,11 +211,65 @@ def _stream(stream):
     return C.c_void_p(int(stream))
 
 
-class Plan:
-    """A ctu_plan: boxes (lo, n, level, offset), ghosts, register faces."""
+def _need(name, t, dtype, numel, device, required=True, check_device=True):
+    """Reject a buffer that the kernels would read or write out of range or
+    misinterpret: wrong dtype, too few elements, not contiguous, not on the
+    plan's device."""
+    import torch
 
-    def __init__(self, opts: CtuOpts, boxes, nghost: int, regfaces=None):
+    if t is None:
+        if required:
+            raise ValueError(f"{name} is required")
+        return
+    if not isinstance(t, torch.Tensor):
+        raise ValueError(f"{name} must be a torch tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if t.numel() < numel:
+        raise ValueError(f"{name} needs at least {numel} elements, got {t.numel()}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if check_device:
+        _on_device(name, t, device)
+
+
+def _on_device(name, t, device):
+    if t is not None and (t.device.type != "cuda" or (device is not None and t.device.index != device)):
+        raise ValueError(f"{name} must be a CUDA tensor on device {device}, got {t.device}")
+
+
+def _refl_array(entries):
+    n = len(entries)
+    arr = (CtuRefluxFace * max(1, n))()
+    for q, e in enumerate(entries):
+        box, (i, j, k), d, side, cslot, fslots = e
+        a = arr[q]
+        a.box, a.i, a.j, a.k, a.dir, a.side = box, i, j, k, d, side
+        a.nfine = len(fslots)
+        a.coarse_slot = cslot
+        for f, s in enumerate(fslots):
+            a.fine_slot[f] = s
+    return arr, n
+
+
+class Plan:
+    """A ctu_plan: boxes (lo, n, level, offset), ghosts, register faces,
+    optionally the reflux table of this (coarse) level.  `device` is the HIP
+    device (default: torch's current one); workspace="caller" leaves the
+    workspace to a torch tensor that this object allocates and holds (the
+    caller-owned path of the C ABI), "library" lets the library own it."""
+
+    def __init__(self, opts: CtuOpts, boxes, nghost: int, regfaces=None, reflux=None, device=None,
+                 workspace="library"):
         L = lib()
+        if workspace not in ("library", "caller"):
+            raise ValueError("workspace must be 'library' or 'caller'")
+        if device is None:
+            import torch
+
+            # device_count() does not initialise the GPU; with none, the
+            # library's option checks still run and the device is refused after
+            device = torch.cuda.current_device() if torch.cuda.device_count() > 0 else 0
         nb = len(boxes)
         arr = (CtuBox * nb)()
         for q, b in enumerate(boxes):
@@ -224,29 +288,53 @@ class Plan:
             rarr[q].tn[0], rarr[q].tn[1] = tn
             rarr[q].slot = slot
         self.opts = opts
+        self.device = int(device)
+        self.nslots = max([r[5] + r[4][0] * r[4][1] for r in regs], default=0)
         self._h = C.c_void_p()
-        _check(L.ctu_plan_create(C.byref(opts), arr, nb, nghost, rarr if regs else None, len(regs),
-                                 C.byref(self._h)))
+        rf, nrf = _refl_array(reflux or [])
+        flags = PLAN_CALLER_WORKSPACE if workspace == "caller" else 0
+        _check(L.ctu_plan_create_ex(self.device, flags, C.byref(opts), arr, nb, nghost, rarr if regs else None,
+                                    len(regs), rf if nrf else None, nrf, C.byref(self._h)))
+        self._ws = None
+        if workspace == "caller":
+            import torch
 
-    def __del__(self):
-        h = getattr(self, "_h", None)
-        if h is not None and h.value and _lib is not None:
-            _lib.ctu_plan_destroy(h)
-            self._h = None
+            nbytes = self.workspace_bytes
+            # torch's allocator returns blocks aligned to at least 512 bytes
+            self._ws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=torch.device("cuda", self.device))
+            _check(L.ctu_plan_set_workspace(self._h, C.c_void_p(self._ws.data_ptr()), self._ws.numel()))
 
     @property
-    def state_elems(self) -> int:
-        return int(lib().ctu_plan_state_elems(self._h))
+    def dtype(self):
+        import torch
 
-    @property
-    def workspace_bytes(self) -> int:
-        return int(lib().ctu_plan_workspace_bytes(self._h))
+        return torch.float32 if self.opts.precision == FP32 else torch.float64
+
+    def _step_args(self, U_in, U_out, params, rate, L0, reg, dpp, fails, need_rate=True, need_reg=True):
+        import torch
+
+        se = self.state_elems
+        dev = self.device
+        args = [("U_in", U_in, self.dtype, se, True), ("U_out", U_out, self.dtype, se, True),
+                ("params", params, torch.float64, 2, True), ("rate", rate, torch.float64, 1, need_rate),
+                ("cool_L0", L0, self.dtype, se // 9, bool(self.opts.cooling)),
+                ("reg", reg, torch.float64, 9 * self.nslots, need_reg and self.nslots > 0),
+                ("dpp", dpp, torch.float64, 1, False), ("fails", fails, torch.int32, NFAIL, False)]
+        for name, t, dt, n, req in args:
+            _need(name, t, dt, n, dev, required=req, check_device=False)
+        if U_in.data_ptr() == U_out.data_ptr():
+            raise ValueError("U_out must not alias U_in")
+        for name, t, _, _, _ in args:
+            _on_device(name, t, dev)
 
     def step(self, U_in, U_out, params, rate, L0=None, reg=None, dpp=None, fails=None, stream=None):
+        self._step_args(U_in, U_out, params, rate, L0, reg, dpp, fails)
         _check(lib().ctu_step(self._h, _ptr(U_in), _ptr(U_out), _ptr(params), _ptr(L0), _ptr(reg), _ptr(rate),
                               _ptr(dpp), _ptr(fails), _stream(stream)))
 
     def graph_capture(self, U_in, U_out, params, rate, L0=None, reg=None, dpp=None, fails=None, stream=None):
+        self._step_args(U_in, U_out, params, rate, L0, reg, dpp, fails)
+        self._graph_args = (U_in, U_out, params, rate, L0, reg, dpp, fails)  # kept alive for the replays
         _check(lib().ctu_step_graph_capture(self._h, _ptr(U_in), _ptr(U_out), _ptr(params), _ptr(L0), _ptr(reg),
                                             _ptr(rate), _ptr(dpp), _ptr(fails), _stream(stream)))
 
@@ -254,25 +342,27 @@ class Plan:
         _check(lib().ctu_step_graph_launch(self._h, _stream(stream)))
 
     def cfl_rate(self, U, rate, stream=None):
+        import torch
+
+        _need("U", U, self.dtype, self.state_elems, self.device)
+        _need("rate", rate, torch.float64, 1, self.device)
         _check(lib().ctu_cfl_rate(self._h, _ptr(U), _ptr(rate), _stream(stream)))
 
     def prim_to_cons(self, V, U, stream=None):
+        _need("V", V, self.dtype, self.state_elems, self.device)
+        _need("U", U, self.dtype, self.state_elems, self.device)
         _check(lib().ctu_prim_to_cons(self._h, _ptr(V), _ptr(U), _stream(stream)))
 
     def cons_to_prim(self, U, V, fails=None, stream=None):
+        import torch
+
+        _need("U", U, self.dtype, self.state_elems, self.device)
+        _need("V", V, self.dtype, self.state_elems, self.device)
+        _need("fails", fails, torch.int32, NFAIL, self.device, required=False)
         _check(lib().ctu_cons_to_prim(self._h, _ptr(U), _ptr(V), _ptr(fails), _stream(stream)))
 
     def set_reflux(self, entries):
-        n = len(entries)
-        arr = (CtuRefluxFace * max(1, n))()
-        for q, e in enumerate(entries):
-            box, (i, j, k), d, side, cslot, fslots = e
-            a = arr[q]
-            a.box, a.i, a.j, a.k, a.dir, a.side = box, i, j, k, d, side
-            a.nfine = len(fslots)
-            a.coarse_slot = cslot
-            for f, s in enumerate(fslots):
-                a.fine_slot[f] = s
+        arr, n = _refl_array(entries)
         _check(lib().ctu_plan_set_reflux(self._h, arr, n))
 
     def enable_timing(self, on: bool = True):
@@ -285,14 +375,26 @@ class Plan:
         _check(lib().ctu_plan_read_timing(self._h, ms, C.byref(n)))
         return dict(zip(STAGES, list(ms))), n.value
 
+    def _reflux_args(self, U, reg):
+        import torch
+
+        _need("U", U, self.dtype, self.state_elems, self.device)
+        # the table's slots are not known here; reg must at least be FP64 on the device
+        _need("reg", reg, torch.float64, 9, self.device)
+
     def reflux(self, U, reg, stream=None):
+        self._reflux_args(U, reg)
         _check(lib().ctu_reflux(self._h, _ptr(U), _ptr(reg), _stream(stream)))
 
     def reflux_consume(self, U, reg, stream=None):
+        self._reflux_args(U, reg)
         _check(lib().ctu_reflux_consume(self._h, _ptr(U), _ptr(reg), _stream(stream)))
 
     def set_leaf_mask(self, leaf):
         """uint8 tensor in the cool_L0 layout (kept alive by the caller) or None"""
+        import torch
+
+        _need("leaf", leaf, torch.uint8, self.state_elems // 9, self.device, required=False)
         self._leaf = leaf
         _check(lib().ctu_plan_set_leaf_mask(self._h, _ptr(leaf)))
 
@@ -313,6 +415,7 @@ class Plan:
         (shape dict, ms per step).  U_out is overwritten."""
         sh = CtuShape()
         ms = C.c_double()
+        self._step_args(U_in, U_out, params, None, L0, None, None, None, need_rate=False, need_reg=False)
         _check(lib().ctu_plan_autotune(self._h, _ptr(U_in), _ptr(U_out), _ptr(params), _ptr(L0), int(reps),
                                        _stream(stream), C.byref(sh), C.byref(ms)))
         return sh.as_dict(), ms.value
@@ -362,6 +465,11 @@ class Hier:
         updated in place to name the buffers holding the new states.  rate
         (and dpp) hold one double per level; L0 is None or a per-level list."""
         n = self.nlev
+        if len(plans) != n or len(U_a) != n or len(U_b) != n or len(params) != n or len(cur) != n:
+            raise ValueError("plans, U_a, U_b, params and cur need one entry per level")
+        for l, p in enumerate(plans):
+            _need(f"U_a[{l}]", U_a[l], p.dtype, p.state_elems, p.device)
+            _need(f"U_b[{l}]", U_b[l], p.dtype, p.state_elems, p.device)
         P = (_vp * n)(*[p._h for p in plans])
         A = (_vp * n)(*[C.c_void_p(t.data_ptr()) for t in U_a])
         B = (_vp * n)(*[C.c_void_p(t.data_ptr()) for t in U_b])

@@ -15,7 +15,7 @@ HEADER = os.path.join(ROOT, "include", "ctu.h")
 
 def declared_functions():
     text = open(HEADER).read()
-    return sorted(set(re.findall(r"^\s*(?:ctu_status|void|int64_t|const char \*)\s*\*?\s*(ctu_\w+)\s*\(", text,
+    return sorted(set(re.findall(r"^\s*(?:ctu_status|void|int64_t|int32_t|const char \*)\s*\*?\s*(ctu_\w+)\s*\(", text,
                                  flags=re.M)))
 
 
