@@ -304,6 +304,20 @@ class Plan:
             self._ws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=torch.device("cuda", self.device))
             _check(L.ctu_plan_set_workspace(self._h, C.c_void_p(self._ws.data_ptr()), self._ws.numel()))
 
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.ctu_plan_destroy(h)
+            self._h = None
+
+    @property
+    def state_elems(self) -> int:
+        return int(lib().ctu_plan_state_elems(self._h))
+
+    @property
+    def workspace_bytes(self) -> int:
+        return int(lib().ctu_plan_workspace_bytes(self._h))
+
     @property
     def dtype(self):
         import torch

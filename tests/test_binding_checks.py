@@ -70,3 +70,11 @@ def test_required_buffers_and_aliasing():
 def test_host_tensors_are_refused():
     with pytest.raises(ValueError, match="CUDA tensor"):
         _step(HostPlan(), _bufs())
+
+
+def test_plan_exposes_its_sizes_and_releases_its_handle():
+    for name in ("state_elems", "workspace_bytes", "dtype"):
+        assert isinstance(getattr(ctu.Plan, name), property), name
+    for name in ("__del__", "step", "graph_capture", "autotune", "set_shape", "reflux"):
+        assert callable(getattr(ctu.Plan, name)), name
+    assert HostPlan("fp64").dtype == torch.float64 and HostPlan("fp32").dtype == torch.float32
