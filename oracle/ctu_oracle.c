@@ -80,6 +80,25 @@ typedef struct {
 
 enum { EOS_IDEAL = 0, EOS_TM = 1 };
 
+/* Stage boundaries of orc_step, where the op-counting build of the oracle
+ * (oracle/opcount.cpp) reads its operation counters; nothing otherwise. */
+#ifndef ORC_STAGE
+#define ORC_STAGE(k) ((void)0)
+#endif
+/* Around the numerical inversion of the right-eigenvector matrix, which
+ * stands in for the closed-form left eigenvectors, and around the
+ * relativistic conserved-to-primitive root finding, done here by bisection
+ * to machine precision: the op-counting build books their operations apart
+ * from the rest (ORC_SIDE_* for the former, ORC_ROOT_* for the latter). */
+#ifndef ORC_SIDE_BEGIN
+#define ORC_SIDE_BEGIN ((void)0)
+#define ORC_SIDE_END ((void)0)
+#endif
+#ifndef ORC_ROOT_BEGIN
+#define ORC_ROOT_BEGIN ((void)0)
+#define ORC_ROOT_END ((void)0)
+#endif
+
 /* ------------------------------------------------------------------------ */
 /* small helpers                                                             */
 /* ------------------------------------------------------------------------ */
@@ -402,7 +421,13 @@ static void prim2cons(const orc_opts *o, const double *V, double *U)
 
 static void cons2prim(const orc_opts *o, const double *U, double *V, int *fails)
 {
-    if (o->physics == PHYS_MHD) mhd_cons2prim(o, U, V, fails); else rmhd_cons2prim(o, U, V, fails);
+    if (o->physics == PHYS_MHD) {
+        mhd_cons2prim(o, U, V, fails);
+    } else {
+        ORC_ROOT_BEGIN;
+        rmhd_cons2prim(o, U, V, fails);
+        ORC_ROOT_END;
+    }
 }
 
 /* Physical flux along d including the GLM rows (Eq. glm2x2): F_{B_n} = psi,
@@ -1031,7 +1056,9 @@ static void riemann_roe(const orc_opts *o, const double *VL, const double *VR, i
     Vh[PRS] = rhoh * a2 / g;
     double R[7][7], L[7][7], lam[7], RL[7][7], lamL[7], RR[7][7], lamR[7];
     mhd_right_eigen(o, Vh, d, R, lam);
+    ORC_SIDE_BEGIN;
     invert7(R, L);
+    ORC_SIDE_END;
     mhd_right_eigen(o, VL, d, RL, lamL);
     mhd_right_eigen(o, VR, d, RR, lamR);
 
@@ -1382,7 +1409,9 @@ static void predict_char(const orc_opts *o, const double Vs[5][NVAR], int d, dou
     const double *V0 = Vs[2];
     double R[7][7], L[7][7], lam[7];
     mhd_right_eigen(o, V0, d, R, lam);
+    ORC_SIDE_BEGIN;
     invert7(R, L);
+    ORC_SIDE_END;
 
     /* Eq. char_var: project the stencil on the left eigenvectors of cell 0 */
     double q[5][7], w[7][5];
@@ -1671,7 +1700,9 @@ void orc_eigen(const orc_opts *o, const double *V, int d, double *R, double *L, 
 {
     double Rm[7][7], Lm[7][7];
     mhd_right_eigen(o, V, d, Rm, lam);
+    ORC_SIDE_BEGIN;
     invert7(Rm, Lm);
+    ORC_SIDE_END;
     memcpy(R, Rm, sizeof(Rm));
     memcpy(L, Lm, sizeof(Lm));
 }
@@ -1854,6 +1885,7 @@ int orc_step(const orc_opts *o, int nx, int ny, int nz, int ng, const double *U_
     /* 1b. App. B shock flags (see shock_flags) */
     unsigned char *flag = calloc(NC, 1);
     if (o->shock_eps > 0.0) shock_flags(o, &g, V, N, flag);
+    ORC_STAGE(1);
     orc_opts o_hll = *o, o_mm = *o;
     o_hll.riemann = RS_HLL;
     o_mm.recon = REC_LIN_MINMOD;
@@ -1943,6 +1975,8 @@ int orc_step(const orc_opts *o, int nx, int ny, int nz, int ng, const double *U_
                 }
     }
 
+    ORC_STAGE(2);
+
     /* 4. normal predictors and corner coupling (Eq. transv) on cells one
      * zone beyond the interior along d, interior across d */
     for (int d = 0; d < dim; d++) {
@@ -1985,6 +2019,8 @@ int orc_step(const orc_opts *o, int nx, int ny, int nz, int ng, const double *U_
                     }
                 }
     }
+
+    ORC_STAGE(3);
 
     /* 5. time-centred Riemann fluxes (Eq. ctu_flux) on interior-adjacent faces */
     for (int d = 0; d < dim; d++) {
@@ -2029,6 +2065,8 @@ int orc_step(const orc_opts *o, int nx, int ny, int nz, int ng, const double *U_
                 }
     }
 
+    ORC_STAGE(4);
+
     /* 6. parabolic fluxes at the half step from the cell-centred U^{n+1/2} */
     if (par) {
         memcpy(Uhalf, U_in, sizeof(double) * NVAR * NC);
@@ -2055,6 +2093,7 @@ int orc_step(const orc_opts *o, int nx, int ny, int nz, int ng, const double *U_
             cons2prim(o, u, v, NULL);
             for (int q = 0; q < NVAR; q++) Vhalf[q * NC + c] = v[q];
         }
+        ORC_STAGE(5);
         for (int d = 0; d < dim; d++) {
             int flo[3], fhi[3];
             for (int e = 0; e < 3; e++) { flo[e] = lo[e]; fhi[e] = hi[e]; }
@@ -2071,6 +2110,8 @@ int orc_step(const orc_opts *o, int nx, int ny, int nz, int ng, const double *U_
                     }
         }
     }
+
+    ORC_STAGE(6);
 
     /* 7. conservative update (Eq. update), directions summed in order */
     memcpy(U_out, U_in, sizeof(double) * NVAR * NC);
@@ -2145,6 +2186,7 @@ int orc_step(const orc_opts *o, int nx, int ny, int nz, int ng, const double *U_
                     }
         }
     }
+    ORC_STAGE(7);
     if (out_scalars) { out_scalars[0] = rate; out_scalars[1] = dpp; }
     if (fails) for (int k = 0; k < NFAIL; k++) fails[k] += lf[k];
 
