@@ -260,6 +260,25 @@ ctu_status ctu_step(ctu_plan *plan, const void *U_in_dev, void *U_out_dev, const
                     const void *cool_L0_dev, double *reg_dev, double *rate_dev, double *dpp_dev,
                     int32_t *fails_dev, void *stream);
 
+/* ctu_step without a workspace of the plan's: for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc).  Arguments, results and errors
+ * are those of ctu_step; the plan may have been created with
+ * CTU_PLAN_CALLER_WORKSPACE and never given one.  The workspace is instead
+ * a fixed array of ctu_static_scratch_bytes() (64 MiB) that the library
+ * holds on every GPU it runs on until the process ends; a plan whose
+ * ctu_plan_workspace_bytes exceeds it is refused with CTU_ERR_ARG (its boxes
+ * must be stepped with ctu_step or split into smaller plans).  The call
+ * allocates nothing.  All calls on one GPU share that GPU's array, which
+ * keeps the last call's contents (nothing in it needs to start at zero):
+ * calls that overlap on one GPU, on any streams or plans, race, so callers
+ * serialise them (one stream, or events between streams). */
+ctu_status ctu_step_static(ctu_plan *plan, const void *U_in_dev, void *U_out_dev, const double *params_dev,
+                           const void *cool_L0_dev, double *reg_dev, double *rate_dev, double *dpp_dev,
+                           int32_t *fails_dev, void *stream);
+/* Bytes of the fixed per-GPU array of ctu_step_static. */
+int64_t ctu_static_scratch_bytes(void);
+
 /* Launch shape of a plan's t^n and sweep kernels.  The per-cell arithmetic
  * does not depend on it: every shape gives the same results (bitwise in
  * FP64), only the speed differs.

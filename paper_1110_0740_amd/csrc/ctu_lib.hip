@@ -576,10 +576,10 @@ ctu_status apply_shape(ctu_plan *p, const ctu_shape &sh)
 }
 
 ctu_status check_step_args(ctu_plan *p, const void *U_in, void *U_out, const double *params, const void *L0,
-                           double *reg, double *rate)
+                           double *reg, double *rate, bool need_ws = true)
 {
     if (!p) return fail(CTU_ERR_ARG, "null plan");
-    if (!p->has_ws) return fail(CTU_ERR_ARG, "the plan has no workspace: call ctu_plan_set_workspace first");
+    if (need_ws && !p->has_ws) return fail(CTU_ERR_ARG, "the plan has no workspace: call ctu_plan_set_workspace first");
     if (!U_in || !U_out || !params || !rate) return fail(CTU_ERR_ARG, "U_in, U_out, params and rate are required");
     if (U_in == U_out) return fail(CTU_ERR_ARG, "U_out must not alias U_in");
     if (p->opts.cooling && !L0) return fail(CTU_ERR_ARG, "cooling needs cool_L0");
@@ -1244,6 +1244,97 @@ ctu_status ctu_plan_set_leaf_mask(ctu_plan *plan, const uint8_t *leaf_dev)
     if (!plan) return fail(CTU_ERR_ARG, "null plan");
     plan->leaf = leaf_dev;
     return CTU_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Allocation-free step: the workspace is a fixed device array of the library
+// ---------------------------------------------------------------------------
+
+namespace {
+
+// The array is a per-device object of the code object: every GPU the library
+// runs on holds its own copy, at its own address, until the process ends.  Its
+// name is only a host-side stand-in; launches use the address returned by
+// hipGetSymbolAddress for the current device.
+constexpr int64_t kScratchBytes = 64LL << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+std::mutex g_scratch_mu;
+std::map<int, void *> g_scratch_ptr;  // device -> address of its copy of `scratch`
+
+// the device address of `scratch` on `dev`, which must be current
+ctu_status scratch_address(int dev, void **out)
+{
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch_ptr.find(dev);
+    if (it != g_scratch_ptr.end()) {
+        *out = it->second;
+        return CTU_OK;
+    }
+    void *ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress((void **)&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+        return fail(CTU_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = ptr;
+    *out = ptr;
+    return CTU_OK;
+}
+
+// workspace pointers of a plan, saved around a step on the scratch
+struct WsPtrs {
+    void *V, *T[3], *Vh, *Lam, *F[3];
+    unsigned char *Flag;
+    explicit WsPtrs(const ctu_plan *p)
+        : V(p->wsV), T{ p->wsT[0], p->wsT[1], p->wsT[2] }, Vh(p->wsVh), Lam(p->wsLam),
+          F{ p->wsF[0], p->wsF[1], p->wsF[2] }, Flag(p->wsFlag)
+    {
+    }
+    void restore(ctu_plan *p) const
+    {
+        p->wsV = V;
+        p->wsVh = Vh;
+        p->wsLam = Lam;
+        p->wsFlag = Flag;
+        for (int d = 0; d < 3; d++) {
+            p->wsT[d] = T[d];
+            p->wsF[d] = F[d];
+        }
+    }
+};
+
+}  // namespace
+
+extern "C" {
+
+int64_t ctu_static_scratch_bytes(void) { return kScratchBytes; }
+
+ctu_status ctu_step_static(ctu_plan *plan, const void *U_in_dev, void *U_out_dev, const double *params_dev,
+                           const void *cool_L0_dev, double *reg_dev, double *rate_dev, double *dpp_dev,
+                           int32_t *fails_dev, void *stream)
+{
+    ctu_status st = check_step_args(plan, U_in_dev, U_out_dev, params_dev, cool_L0_dev, reg_dev, rate_dev, false);
+    if (st != CTU_OK) return st;
+    if (plan->ws_bytes > kScratchBytes)
+        return fail(CTU_ERR_ARG, "the plan's workspace (" + std::to_string(plan->ws_bytes) +
+                                     " bytes) exceeds the static scratch (" + std::to_string(kScratchBytes) +
+                                     " bytes): step it with ctu_step, or split its boxes into smaller plans");
+    DevGuard guard(plan->dev);
+    HIP_TRY(guard.err);
+    void *ptr = nullptr;
+    if ((st = scratch_address(plan->dev, &ptr)) != CTU_OK) return st;
+    // every scratch field is written before it is read within the step, so
+    // nothing needs clearing; the previous call's contents are overwritten
+    const WsPtrs saved(plan);
+    carve_ws(plan, (char *)ptr);
+    hipStream_t s = (hipStream_t)stream;
+    st = (plan->esize == 4) ? enqueue_step<float>(plan, U_in_dev, U_out_dev, params_dev, cool_L0_dev, reg_dev,
+                                                  rate_dev, dpp_dev, fails_dev, s)
+                            : enqueue_step<double>(plan, U_in_dev, U_out_dev, params_dev, cool_L0_dev, reg_dev,
+                                                   rate_dev, dpp_dev, fails_dev, s);
+    saved.restore(plan);
+    return st;
 }
 
 }  // extern "C"

@@ -32,7 +32,8 @@ SYMBOLS = [
     "ctu_last_error", "ctu_hier_create", "ctu_hier_destroy", "ctu_hier_fill_ghosts", "ctu_hier_average_down",
     "ctu_hier_advance", "ctu_hier_leaf_mask", "ctu_hier_tag", "ctu_hier_next_dt", "ctu_plan_set_leaf_mask",
     "ctu_plan_set_shape", "ctu_plan_get_shape", "ctu_plan_autotune", "ctu_tune_cache_clear",
-    "ctu_plan_create_ex", "ctu_plan_set_workspace", "ctu_plan_device",
+    "ctu_plan_create_ex", "ctu_plan_set_workspace", "ctu_plan_device", "ctu_step_static",
+    "ctu_static_scratch_bytes",
 ]
 PLAN_CALLER_WORKSPACE = 1
 TC_LAYOUT = {"auto": 0, "tiles": 1, "flat": 2}
@@ -101,6 +102,10 @@ def lib() -> C.CDLL:
         L.ctu_plan_set_workspace.argtypes = [_vp, _vp, C.c_int64]
         L.ctu_plan_device.restype = C.c_int32
         L.ctu_plan_device.argtypes = [_vp]
+        L.ctu_step_static.restype = C.c_int32
+        L.ctu_step_static.argtypes = [_vp] + [_vp] * 8 + [_vp]
+        L.ctu_static_scratch_bytes.restype = C.c_int64
+        L.ctu_static_scratch_bytes.argtypes = []
         L.ctu_plan_destroy.argtypes = [_vp]
         L.ctu_plan_state_elems.restype = C.c_int64
         L.ctu_plan_state_elems.argtypes = [_vp]
@@ -257,13 +262,15 @@ class Plan:
     optionally the reflux table of this (coarse) level.  `device` is the HIP
     device (default: torch's current one); workspace="caller" leaves the
     workspace to a torch tensor that this object allocates and holds (the
-    caller-owned path of the C ABI), "library" lets the library own it."""
+    caller-owned path of the C ABI), "library" lets the library own it,
+    "none" creates the plan without one (it then steps only through
+    step_static)."""
 
     def __init__(self, opts: CtuOpts, boxes, nghost: int, regfaces=None, reflux=None, device=None,
                  workspace="library"):
         L = lib()
-        if workspace not in ("library", "caller"):
-            raise ValueError("workspace must be 'library' or 'caller'")
+        if workspace not in ("library", "caller", "none"):
+            raise ValueError("workspace must be 'library', 'caller' or 'none'")
         if device is None:
             import torch
 
@@ -292,7 +299,7 @@ class Plan:
         self.nslots = max([r[5] + r[4][0] * r[4][1] for r in regs], default=0)
         self._h = C.c_void_p()
         rf, nrf = _refl_array(reflux or [])
-        flags = PLAN_CALLER_WORKSPACE if workspace == "caller" else 0
+        flags = PLAN_CALLER_WORKSPACE if workspace in ("caller", "none") else 0
         _check(L.ctu_plan_create_ex(self.device, flags, C.byref(opts), arr, nb, nghost, rarr if regs else None,
                                     len(regs), rf if nrf else None, nrf, C.byref(self._h)))
         self._ws = None
@@ -345,6 +352,13 @@ class Plan:
         self._step_args(U_in, U_out, params, rate, L0, reg, dpp, fails)
         _check(lib().ctu_step(self._h, _ptr(U_in), _ptr(U_out), _ptr(params), _ptr(L0), _ptr(reg), _ptr(rate),
                               _ptr(dpp), _ptr(fails), _stream(stream)))
+
+    def step_static(self, U_in, U_out, params, rate, L0=None, reg=None, dpp=None, fails=None, stream=None):
+        """ctu_step_static: the step on the library's fixed per-GPU scratch
+        array (no allocation, no plan workspace needed)."""
+        self._step_args(U_in, U_out, params, rate, L0, reg, dpp, fails)
+        _check(lib().ctu_step_static(self._h, _ptr(U_in), _ptr(U_out), _ptr(params), _ptr(L0), _ptr(reg),
+                                     _ptr(rate), _ptr(dpp), _ptr(fails), _stream(stream)))
 
     def graph_capture(self, U_in, U_out, params, rate, L0=None, reg=None, dpp=None, fails=None, stream=None):
         self._step_args(U_in, U_out, params, rate, L0, reg, dpp, fails)

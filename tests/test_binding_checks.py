@@ -75,6 +75,6 @@ def test_host_tensors_are_refused():
 def test_plan_exposes_its_sizes_and_releases_its_handle():
     for name in ("state_elems", "workspace_bytes", "dtype"):
         assert isinstance(getattr(ctu.Plan, name), property), name
-    for name in ("__del__", "step", "graph_capture", "autotune", "set_shape", "reflux"):
+    for name in ("__del__", "step", "step_static", "graph_capture", "autotune", "set_shape", "reflux"):
         assert callable(getattr(ctu.Plan, name)), name
     assert HostPlan("fp64").dtype == torch.float64 and HostPlan("fp32").dtype == torch.float32
