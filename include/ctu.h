@@ -191,9 +191,17 @@ typedef struct ctu_refluxface {
 
 typedef struct ctu_plan ctu_plan;
 
-/* ctu_plan_create_ex flags: the library allocates no workspace; the caller
- * supplies it with ctu_plan_set_workspace before the first step. */
+/* ctu_plan_create_ex flags.
+ * CTU_PLAN_CALLER_WORKSPACE: the library allocates no workspace; the caller
+ *   supplies it with ctu_plan_set_workspace before the first step.
+ * CTU_PLAN_LEVEL_DT: one plan over the boxes of several refinement levels
+ *   (Sec. 4, ratio 2): params {dt, c_h} give the level-0 step, a box of
+ *   level l steps by dt / 2^l (c_h, the same on every level for ratio 2, is
+ *   shared), and the rate output is the largest rate / 2^l (the level-0 rate
+ *   of the boxes' CFL numbers), so one launch chain advances every patch of
+ *   the hierarchy by its own level step. */
 #define CTU_PLAN_CALLER_WORKSPACE 1u
+#define CTU_PLAN_LEVEL_DT 2u
 
 /* Create a plan for a batch of boxes on HIP device hip_device (Sec. 3.1
  * applied to each patch of a level; Sec. 4 states the per-patch problem:

@@ -41,8 +41,17 @@ struct KBox {
     // per direction d: offset of this box's face index in the register face
     // table: entries [t[f], t[f + 1]) lie on the face lo[d] + f, f = 0..n[d]
     int rface[3];
-    int pad;
+    int lshift;  // the box's level when the plan's dt is the level-0 step (one plan over
+                 // several levels); 0 otherwise.  The box steps by dt / 2^lshift and
+                 // reports its rate times 2^-lshift (the level-0 rate of its CFL number)
 };
+
+// the step of a box: the plan's dt, halved per level of a multi-level plan
+// (exact: a power-of-two scaling)
+__device__ __forceinline__ double box_dt(const KBox &bx, const double *params)
+{
+    return ldexp(params[0], -bx.lshift);
+}
 
 struct KTile {
     int box, a, b, c;
@@ -495,7 +504,7 @@ __global__ __launch_bounds__(NT) void k_tcouple(TArgs<R> a)
     const KBox bx = a.boxes[tl.box];
     const KOpts o = variant_opts<VAR>(a.o);
     const R gam = R(o.gamma), ch = R(a.params[1]);
-    const R hdt = R(0.5 * a.params[0]);
+    const R hdt = R(0.5 * box_dt(bx, a.params));
     const int cs = (int)bx.cells;
     const R *Vb = a.V + bx.woff;
     const Blk<R> bV(Vb, bx.cells);
@@ -788,7 +797,7 @@ __global__ __launch_bounds__(NT) void k_mtflux(MtArgs<R> a)
     }
     const int sD = (D == 0) ? 1 : (D == 1 ? bx.N[0] : bx.N[0] * bx.N[1]);
     const R gam = R(o.gamma);
-    const R dt = R(a.params[0]), ch = R(a.params[1]);
+    const R dt = R(box_dt(bx, a.params)), ch = R(a.params[1]);
     const R dxD = R(bx.dx[D]);
     const R dtdx = dt / dxD;
     const Blk<R> bV(a.V + bx.woff, bx.cells);
@@ -962,7 +971,7 @@ __global__ __launch_bounds__(NT, (sizeof(R) == 4 ? CTU_SWEEP_WAVES_F32 : CTU_SWE
     }
     const int sface = max(1, r0 - 1), supd = max(2, r0);
     const R gam = R(o.gamma);
-    const R dt = R(a.params[0]);
+    const R dt = R(box_dt(bx, a.params));
     const R ch = R(a.params[1]);
     const R dxD = R(bx.dx[D]);
     const R dtdx = dt / dxD;
@@ -1169,7 +1178,7 @@ __global__ __launch_bounds__(NT, (sizeof(R) == 4 ? CTU_SWEEP_WAVES_F32 : CTU_SWE
         }
         __syncthreads();
     }
-    double rb = block_max(rate_loc, red);
+    double rb = ldexp(block_max(rate_loc, red), -bx.lshift);
     if (tid == 0 && a.rate) atomic_max_pos(a.rate, rb);
     if (a.last && a.dpp && o.cooling) {
         double db = block_max(dpp_loc, red);
@@ -1216,7 +1225,7 @@ __global__ __launch_bounds__(NT) void k_cfl(const KBox *boxes, const KTile *tile
                 if (e < o.dim) r += 2.0 * (double)Dc / (bx.dx[e] * bx.dx[e]);
         }
     }
-    double rb = block_max(r, red);
+    double rb = ldexp(block_max(r, red), -bx.lshift);
     if (threadIdx.x == 0) atomic_max_pos(rate, rb);
 }
 

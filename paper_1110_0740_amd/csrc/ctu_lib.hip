@@ -602,7 +602,7 @@ static ctu_status create_plan(int32_t dev, uint32_t flags, const ctu_opts *opts,
     if (!plan_out) return fail(CTU_ERR_ARG, "plan_out is null");
     *plan_out = nullptr;
     if (!opts || !boxes || nbox <= 0) return fail(CTU_ERR_ARG, "options and at least one box are required");
-    if (flags & ~(uint32_t)CTU_PLAN_CALLER_WORKSPACE) return fail(CTU_ERR_ARG, "unknown plan flags");
+    if (flags & ~(uint32_t)(CTU_PLAN_CALLER_WORKSPACE | CTU_PLAN_LEVEL_DT)) return fail(CTU_ERR_ARG, "unknown plan flags");
     if (nreflux < 0 || (nreflux > 0 && !reflux)) return fail(CTU_ERR_ARG, "bad reflux table");
     const ctu_opts &o = *opts;
     if (o.dim != 2 && o.dim != 3) return fail(CTU_ERR_ARG, "dim must be 2 or 3");
@@ -726,7 +726,7 @@ static ctu_status create_plan(int32_t dev, uint32_t flags, const ctu_opts *opts,
         p->ws_cells += kb.cells;
         kb.reg0 = kb.reg1 = 0;
         kb.rface[0] = kb.rface[1] = kb.rface[2] = 0;
-        kb.pad = 0;
+        kb.lshift = (flags & CTU_PLAN_LEVEL_DT) ? B.level : 0;
         p->hboxes.push_back(kb);
     }
     std::sort(spans.begin(), spans.end());

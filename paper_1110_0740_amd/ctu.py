@@ -36,6 +36,7 @@ SYMBOLS = [
     "ctu_static_scratch_bytes",
 ]
 PLAN_CALLER_WORKSPACE = 1
+PLAN_LEVEL_DT = 2
 TC_LAYOUT = {"auto": 0, "tiles": 1, "flat": 2}
 NSTAGE = 8
 STAGES = ["prim", "tcouple", "unused2", "unused3", "unused4", "sweep_x", "sweep_y", "sweep_z"]
@@ -264,10 +265,11 @@ class Plan:
     workspace to a torch tensor that this object allocates and holds (the
     caller-owned path of the C ABI), "library" lets the library own it,
     "none" creates the plan without one (it then steps only through
-    step_static)."""
+    step_static).  level_dt: the boxes may lie on several levels, params
+    hold the level-0 step and a level-l box steps by dt / 2^l."""
 
     def __init__(self, opts: CtuOpts, boxes, nghost: int, regfaces=None, reflux=None, device=None,
-                 workspace="library"):
+                 workspace="library", level_dt=False):
         L = lib()
         if workspace not in ("library", "caller", "none"):
             raise ValueError("workspace must be 'library', 'caller' or 'none'")
@@ -300,6 +302,8 @@ class Plan:
         self._h = C.c_void_p()
         rf, nrf = _refl_array(reflux or [])
         flags = PLAN_CALLER_WORKSPACE if workspace in ("caller", "none") else 0
+        if level_dt:
+            flags |= PLAN_LEVEL_DT
         _check(L.ctu_plan_create_ex(self.device, flags, C.byref(opts), arr, nb, nghost, rarr if regs else None,
                                     len(regs), rf if nrf else None, nrf, C.byref(self._h)))
         self._ws = None

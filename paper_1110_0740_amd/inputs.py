@@ -431,6 +431,18 @@ def mhd3d_fields_torch(n: int = 256, ng: int = 4, seed: int = 2000, device="cuda
     return V, dict(dim=3, gamma=5.0 / 3.0, dx=dx, box=box, ng=ng)
 
 
+def cooling_time_field_torch(seed: int, n: int, ng: int, dt0: float, device="cuda"):
+    """:func:`cooling_time_field` on the ghosted n^3 periodic box, with torch
+    on `device` (float64, [NZ, NY, NX])."""
+    import torch
+
+    rng = SplitMix64(seed)
+    m = draw_modes(rng, 3)
+    box = Box((0, 0, 0), (n, n, n))
+    axes = _axis_phases(torch, box, ng, (1.0 / n,) * 3, 3, device)
+    return dt0 * 10.0 ** (3.0 * _mode_sum_t(torch, m, axes))
+
+
 # --------------------------------------------------------------------------
 # AMR hierarchy around density blobs (3 levels, refinement ratio 2)
 # --------------------------------------------------------------------------

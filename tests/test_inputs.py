@@ -48,3 +48,14 @@ def test_amr_fields_torch_matches_numpy():
         Vn = I.amr_fields(h, B, 4)
         Vt = I.amr_fields_torch(h, B, 4, device="cpu")
         assert np.max(np.abs(Vt.numpy() - Vn)) < 1e-12
+
+
+def test_cooling_time_torch_matches_numpy():
+    import torch
+
+    n, ng = 12, 4
+    X, Y, Z = I.cell_centres(I.Box((0, 0, 0), (n, n, n)), ng, (1.0 / n,) * 3, 3)
+    a = I.cooling_time_field(5002, X, Y, Z, 0.25)
+    b = I.cooling_time_field_torch(5002, n, ng, 0.25, device="cpu").numpy()
+    assert np.allclose(a, b, rtol=1e-12, atol=0)
+    assert a.min() >= 0.25e-3 * (1 - 1e-12) and a.max() <= 0.25e3 * (1 + 1e-12)
