@@ -233,6 +233,11 @@ __device__ __forceinline__ int c2p_rmhd(const double *U, double *V, double gam, 
             if (f > 0.0) hi = W; else lo = W;
         }
         double Wn = (df > 0.0) ? W - f / df : 0.5 * (lo + hi);
+        // a Newton step within the tolerance has converged wherever it lands:
+        // at the root the step rounds onto the bracket end just moved to W,
+        // and falling back to bisection there would walk away from the root
+        // (then back by halving the bracket, ~30 extra iterations)
+        if (df > 0.0 && fabs(Wn - W) <= tol * fmax(W, wscale)) { W = Wn; conv = true; break; }
         if (!(Wn > lo && Wn < hi)) Wn = 0.5 * (lo + hi);
         if (fabs(Wn - W) <= tol * fmax(W, wscale)) { W = Wn; conv = true; break; }
         W = Wn;
