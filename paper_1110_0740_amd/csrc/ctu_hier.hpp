@@ -77,14 +77,17 @@ template <typename R> __device__ __forceinline__ R mc_slope(R dp, R dm)
     return (dp * dm > R(0)) ? copysign(m, c) : R(0);
 }
 
-// Ghost cells of every box of one level.  cbox == nullptr on level 0, whose
-// boxes must cover the periodic domain.  A cell that neither a same-level
-// box nor the coarse interiors can supply is set to NaN and counted.
+// Ghost cells of every box of one level that a same-level box interior
+// holds (periodic images included): copied.  On level 0 (cbox == nullptr),
+// whose boxes must cover the periodic domain, a ghost cell no box holds is
+// set to NaN and counted.  On finer levels the other ghost cells are left to
+// k_hprolong, unless `prolong` is set, which prolongs them here one cell per
+// thread (the same arithmetic as k_hprolong).
 template <typename R>
 __global__ __launch_bounds__(NT) void k_hfill(const HBox *box, const HTile *tiles, const int *nb_start,
                                               const int *nb_list, const HBox *cbox, const int *cb_start,
                                               const int *cb_list, int N, int ng, R *U, const R *Uo, const R *Un,
-                                              double alpha_d, int *missing)
+                                              double alpha_d, int *missing, int prolong)
 {
     const HTile t = tiles[blockIdx.x];
     const HBox b = box[t.box];
@@ -103,6 +106,7 @@ __global__ __launch_bounds__(NT) void k_hfill(const HBox *box, const HTile *tile
         for (int q = 0; q < NV; q++) dst[q * b.cells] = U[p + q * c.cells];
         return;
     }
+    if (cbox != nullptr && !prolong) return;
     bool ok = cbox != nullptr;
     R out[NV];
     if (ok) {
@@ -137,6 +141,98 @@ __global__ __launch_bounds__(NT) void k_hfill(const HBox *box, const HTile *tile
     }
 #pragma unroll
     for (int q = 0; q < NV; q++) dst[q * b.cells] = out[q];
+}
+
+// Eq. prolong for the ghost cells of the boxes of a level >= 1 that no
+// same-level box interior holds, one thread per coarse parent cell of a
+// box's ghosted extent: the parent's time-interpolated state (Eq. intalpha)
+// and the MC slopes of its six face neighbours are formed once and give
+// all of its children that are such ghost cells (up to eight; the same
+// arithmetic per child as the one-cell-per-thread form of k_hfill).  A
+// parent whose stencil leaves the coarse interiors sets its children to NaN
+// and counts them.
+__device__ __forceinline__ int floor_half(int a) { return (a >= 0) ? a / 2 : -((1 - a) / 2); }
+
+template <typename R>
+__global__ __launch_bounds__(NT) void k_hprolong(const HBox *box, const HTile *tiles, const int *nb_start,
+                                                 const int *nb_list, const HBox *cbox, const int *cb_start,
+                                                 const int *cb_list, int N, int ng, R *U, const R *Uo, const R *Un,
+                                                 double alpha_d, int *missing)
+{
+    const HTile t = tiles[blockIdx.x];
+    const HBox b = box[t.box];
+    int p0[3], pe[3];
+#pragma unroll
+    for (int d = 0; d < 3; d++) {
+        p0[d] = floor_half(b.lo[d] - ng);
+        pe[d] = floor_half(b.lo[d] + b.n[d] + ng - 1) - p0[d] + 1;
+    }
+    const long long li = (long long)t.start + threadIdx.x;
+    if (li >= (long long)pe[0] * pe[1] * pe[2]) return;
+    const int pu[3] = { p0[0] + (int)(li % pe[0]), p0[1] + (int)((li / pe[0]) % pe[1]),
+                        p0[2] + (int)(li / ((long long)pe[0] * pe[1])) };
+    // the children that are ghost cells of b and that no same-level box holds
+    unsigned mask = 0;
+    for (int c8 = 0; c8 < 8; c8++) {
+        int loc[3];
+        bool ghost = false, inside = true;
+#pragma unroll
+        for (int d = 0; d < 3; d++) {
+            loc[d] = 2 * pu[d] + ((c8 >> d) & 1) - b.lo[d] + ng;
+            inside = inside && loc[d] >= 0 && loc[d] < b.N[d];
+            ghost = ghost || loc[d] < ng || loc[d] >= ng + b.n[d];
+        }
+        if (!inside || !ghost) continue;
+        const int gi = wrapi(b.lo[0] + loc[0] - ng, N), gj = wrapi(b.lo[1] + loc[1] - ng, N),
+                  gk = wrapi(b.lo[2] + loc[2] - ng, N);
+        bool same = false;
+        for (int e = nb_start[t.box]; e < nb_start[t.box + 1] && !same; e++) same = holds(box[nb_list[e]], gi, gj, gk);
+        if (!same) mask |= 1u << c8;
+    }
+    if (!mask) return;
+    const int Nc = N / 2, c0 = cb_start[t.box], c1 = cb_start[t.box + 1];
+    const int pi = wrapi(pu[0], Nc), pj = wrapi(pu[1], Nc), pk = wrapi(pu[2], Nc);
+    const R alpha = R(alpha_d);
+    R u0[NV], sl[3][NV];
+    bool ok = coarse_state(cbox, cb_list, c0, c1, pi, pj, pk, ng, Uo, Un, alpha, u0);
+#pragma unroll
+    for (int d = 0; d < 3; d++) {
+        R up[NV], dn[NV];
+        const int di = (d == 0), dj = (d == 1), dk = (d == 2);
+        ok = ok && coarse_state(cbox, cb_list, c0, c1, wrapi(pi + di, Nc), wrapi(pj + dj, Nc), wrapi(pk + dk, Nc), ng,
+                                Uo, Un, alpha, up);
+        ok = ok && coarse_state(cbox, cb_list, c0, c1, wrapi(pi - di, Nc), wrapi(pj - dj, Nc), wrapi(pk - dk, Nc), ng,
+                                Uo, Un, alpha, dn);
+        if (ok) {
+#pragma unroll
+            for (int q = 0; q < NV; q++) sl[d][q] = mc_slope(up[q] - u0[q], u0[q] - dn[q]);
+        }
+    }
+    for (int c8 = 0; c8 < 8; c8++) {
+        if (!(mask & (1u << c8))) continue;
+        const long long li2 =
+            ((long long)(2 * pu[2] + ((c8 >> 2) & 1) - b.lo[2] + ng) * b.N[1] + (2 * pu[1] + ((c8 >> 1) & 1) - b.lo[1] + ng)) *
+                b.N[0] +
+            (2 * pu[0] + (c8 & 1) - b.lo[0] + ng);
+        R *dst = U + b.off + li2;
+        R out[NV];
+        if (ok) {
+#pragma unroll
+            for (int q = 0; q < NV; q++) out[q] = u0[q];
+#pragma unroll
+            for (int d = 0; d < 3; d++) {
+                const R off = ((c8 >> d) & 1) ? R(0.25) : R(-0.25);
+#pragma unroll
+                for (int q = 0; q < NV; q++) out[q] += off * sl[d][q];
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < NV; q++) out[q] = R(NAN);
+            if (missing) atomicAdd(missing, 1);
+        }
+#pragma unroll
+        for (int q = 0; q < NV; q++) dst[q * b.cells] = out[q];
+    }
 }
 
 // Eq. avgdown (ratio 2, equal Cartesian volumes): each coarse cell under a

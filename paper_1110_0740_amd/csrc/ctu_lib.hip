@@ -1349,11 +1349,11 @@ struct HierLevel {
     int N = 0;  // cells per side of the periodic level
     std::vector<HBox> hb;
     std::vector<int> nb_start, nb_list, cb_start, cb_list, pb_start, pb_list, ch_start, ch_list;
-    std::vector<HTile> fill_t, avg_t;
+    std::vector<HTile> fill_t, avg_t, prol_t;  // prol_t: coarse parents of each box's ghosted extent
     HBox *db = nullptr;
     int *d_nb_start = nullptr, *d_nb_list = nullptr, *d_cb_start = nullptr, *d_cb_list = nullptr;
     int *d_pb_start = nullptr, *d_pb_list = nullptr, *d_ch_start = nullptr, *d_ch_list = nullptr;
-    HTile *d_fill_t = nullptr, *d_avg_t = nullptr;
+    HTile *d_fill_t = nullptr, *d_avg_t = nullptr, *d_prol_t = nullptr;
 };
 
 int floor_div(int a, int b) { return (a >= 0) ? a / b : -((-a + b - 1) / b); }
@@ -1409,7 +1409,7 @@ void free_hier(ctu_hier *h)
     DevGuard g(h->dev);
     for (HierLevel &L : h->lev) {
         void *ptrs[] = { L.db, L.d_nb_start, L.d_nb_list, L.d_cb_start, L.d_cb_list, L.d_pb_start, L.d_pb_list,
-                         L.d_ch_start, L.d_ch_list, L.d_fill_t, L.d_avg_t };
+                         L.d_ch_start, L.d_ch_list, L.d_fill_t, L.d_avg_t, L.d_prol_t };
         for (void *q : ptrs)
             if (q) (void)hipFree(q);
     }
@@ -1430,10 +1430,18 @@ ctu_status hier_fill(ctu_hier *h, int level, void *U, const void *Uo, const void
         cbs = L.d_cb_start;
         cbl = L.d_cb_list;
     }
+    // same-level copies (and, on level 0, the periodic images); on finer
+    // levels the remaining ghosts are prolonged one coarse parent per thread
     hipLaunchKernelGGL((k_hfill<R>), dim3((unsigned)L.fill_t.size()), dim3(NT), 0, s, L.db, L.d_fill_t,
                        L.d_nb_start, L.d_nb_list, cbox, cbs, cbl, L.N, h->ng, (R *)U, (const R *)Uo,
-                       (const R *)(Un ? Un : Uo), alpha, (int *)missing);
+                       (const R *)(Un ? Un : Uo), alpha, (int *)missing, 0);
     HIP_TRY(hipGetLastError());
+    if (level > 0 && !L.prol_t.empty()) {
+        hipLaunchKernelGGL((k_hprolong<R>), dim3((unsigned)L.prol_t.size()), dim3(NT), 0, s, L.db, L.d_prol_t,
+                           L.d_nb_start, L.d_nb_list, cbox, cbs, cbl, L.N, h->ng, (R *)U, (const R *)Uo,
+                           (const R *)(Un ? Un : Uo), alpha, (int *)missing);
+        HIP_TRY(hipGetLastError());
+    }
     return CTU_OK;
 }
 
@@ -1611,6 +1619,11 @@ ctu_status ctu_hier_create(int32_t precision, int32_t base, int32_t nlev, const 
             if (l > 0) {
                 long long fc = (long long)(B.n[0] / 2) * (B.n[1] / 2) * (B.n[2] / 2);
                 for (long long s0 = 0; s0 < fc; s0 += NT) L.avg_t.push_back(HTile{ b, (int)s0 });
+                // coarse parents of the ghosted extent (k_hprolong)
+                long long pc = 1;
+                for (int d = 0; d < 3; d++)
+                    pc *= floor_div(B.lo[d] + B.n[d] + nghost - 1, 2) - floor_div(B.lo[d] - nghost, 2) + 1;
+                for (long long s0 = 0; s0 < pc; s0 += NT) L.prol_t.push_back(HTile{ b, (int)s0 });
             }
         }
     }
@@ -1642,6 +1655,7 @@ ctu_status ctu_hier_create(int32_t precision, int32_t base, int32_t nlev, const 
             (st = upload(L.nb_list, &L.d_nb_list)) != CTU_OK || (st = upload(L.cb_start, &L.d_cb_start)) != CTU_OK ||
             (st = upload(L.cb_list, &L.d_cb_list)) != CTU_OK || (st = upload(L.pb_start, &L.d_pb_start)) != CTU_OK ||
             (st = upload(L.pb_list, &L.d_pb_list)) != CTU_OK || (st = upload(L.fill_t, &L.d_fill_t)) != CTU_OK ||
+            (st = upload(L.prol_t, &L.d_prol_t)) != CTU_OK ||
             (st = upload(L.avg_t, &L.d_avg_t)) != CTU_OK) {
             free_hier(h);
             return st;
