@@ -398,6 +398,11 @@ template <typename R> __device__ __forceinline__ R diff_coeff(const KOpts &o, R 
 // Two in-plane layouts, chosen per tile on the host:
 //  * tile (b >= 0): a TX x TY rectangle at (a, b); the TY faces right of it
 //    and the TX faces above it are the extra faces;
+//  * strip (3D, b <= -2): the last SW = W - a <= 2 positions of rows
+//    -2 - b .. -2 - b + SH - 1 (a 258-position row is eight rectangles and
+//    one strip instead of a ninth rectangle with 2 of its 32 columns
+//    active); its extra faces are solved by the two waves that hold no
+//    position;
 //  * flat (3D, b == -1): positions a .. a+255 of the extended plane of
 //    (W+1) x (H+1) positions, W x H the region's extent, row by row; a
 //    position with x = W or y = H only solves the face below it.  The extra
@@ -411,6 +416,12 @@ template <int DIM> struct TTile {
     static constexpr int TX = (DIM == 3) ? 32 : NT;
     static constexpr int TY = (DIM == 3) ? 8 : 1;
     static constexpr int LM = 16;   // default planes per block along the marching axis
+    // strip tiles (3D): the last SW <= 2 positions of each row of the region
+    // when its width leaves that many beyond the TX-wide rectangles, SH rows
+    // per block (positions on the first two waves, the strip's extra faces
+    // on the other two)
+    static constexpr int SWMAX = 2;
+    static constexpr int SH = 64;
     // flat layout: at most 40 positions per row (boxes up to 37 cells wide),
     // which keeps the face planes of four FP64 blocks within 160 KiB of LDS
     static constexpr int MAXW1 = 40;
@@ -418,6 +429,8 @@ template <int DIM> struct TTile {
     // 256 + MAXW1 + 1)
     static constexpr int GXS = (DIM == 3) ? ((TY * (TX + 1) > 257) ? TY * (TX + 1) : 257) : TY * (TX + 1);
     static constexpr int GYS = (DIM == 3) ? (((TY + 1) * TX > 256 + MAXW1 + 1) ? (TY + 1) * TX : 256 + MAXW1 + 1) : 1;
+    static_assert(DIM == 2 || (SH * (SWMAX + 1) <= GXS && (SH + 1) * SWMAX <= GYS), "strip face slots exceed LDS");
+    static_assert(SWMAX * SH <= 2 * 64 && SH + SWMAX <= NT - 2 * 64, "strip positions / extra faces exceed their waves");
 };
 
 template <typename R> struct TArgs {
@@ -522,7 +535,7 @@ __global__ __launch_bounds__(NT) void k_tcouple(TArgs<R> a)
     // the extra face of this lane (if any): below position (ei, ej), along
     // x (ed = 0) or y (ed = 1), into slot es
     int ei = 0, ej = 0, ed = -1, es = 0;
-    if (DIM == 3 && tl.b < 0) {
+    if (DIM == 3 && tl.b == -1) {
         const int W1 = bx.n[0] + 3, H1 = bx.n[1] + 3, P = W1 * H1;
         const int p = tl.a + tid, x = p % W1, y = p / W1;
         i = bx.g[0] - 1 + x;
@@ -545,25 +558,31 @@ __global__ __launch_bounds__(NT) void k_tcouple(TArgs<R> a)
             }
         }
     } else {
-        const int tx = tid % TX, ty = tid / TX;
+        // rectangle (tw x th = TX x TY) or strip (tw = W - a, th = SH)
+        const bool strip = DIM == 3 && tl.b <= -2;
+        const int tw = strip ? bx.n[0] + 2 - tl.a : TX, th = strip ? TTile<DIM>::SH : TY;
+        const int y0 = strip ? -2 - tl.b : tl.b;
+        const int e = strip ? tid - 2 * 64 : et;
+        const bool pos = !strip || tid < tw * th;
+        const int tx = tid % tw, ty = tid / tw;
         i = bx.g[0] - 1 + tl.a + tx;
-        j = (DIM == 3) ? bx.g[1] - 1 + tl.b + ty : 0;
-        xf = (i <= hi0 + 1) && (DIM == 2 || j <= hi1);
-        yf = (DIM == 3) && (i <= hi0) && (j <= hi1 + 1);
-        inplane = (i <= hi0) && (DIM == 2 || j <= hi1);
-        lx = ty * (TX + 1) + tx;
-        ly = ty * TX + tx;
-        sy = TX;
-        if (et >= 0 && et < TY) {
-            ei = bx.g[0] - 1 + tl.a + TX;
-            ej = (DIM == 3) ? bx.g[1] - 1 + tl.b + et : 0;
+        j = (DIM == 3) ? bx.g[1] - 1 + y0 + ty : 0;
+        xf = pos && (i <= hi0 + 1) && (DIM == 2 || j <= hi1);
+        yf = pos && (DIM == 3) && (i <= hi0) && (j <= hi1 + 1);
+        inplane = pos && (i <= hi0) && (DIM == 2 || j <= hi1);
+        lx = ty * (tw + 1) + tx;
+        ly = ty * tw + tx;
+        sy = tw;
+        if (e >= 0 && e < th) {
+            ei = bx.g[0] - 1 + tl.a + tw;
+            ej = (DIM == 3) ? bx.g[1] - 1 + y0 + e : 0;
             if (ei <= hi0 + 1 && (DIM == 2 || ej <= hi1)) ed = 0;
-            es = et * (TX + 1) + TX;
-        } else if (DIM == 3 && et >= TY && et < TY + TX) {
-            ei = bx.g[0] - 1 + tl.a + (et - TY);
-            ej = bx.g[1] - 1 + tl.b + TY;
+            es = e * (tw + 1) + tw;
+        } else if (DIM == 3 && e >= th && e < th + tw) {
+            ei = bx.g[0] - 1 + tl.a + (e - th);
+            ej = bx.g[1] - 1 + y0 + th;
             if (ei <= hi0 && ej <= hi1 + 1) ed = 1;
-            es = TY * TX + (et - TY);
+            es = th * tw + (e - th);
         }
     }
     // this block's chunk of the region [g-1, g+n] along the marching axis;

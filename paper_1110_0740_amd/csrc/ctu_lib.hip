@@ -218,14 +218,30 @@ bool flat_allowed(const ctu_plan *p, const KBox &bx)
     return p->opts.dim == 3 && bx.n[0] + 3 <= TTile<3>::MAXW1;
 }
 
+// 3D rectangle layout: the region's W positions per row split into
+// 32-wide rectangles, and a last part of at most SWMAX positions into strips
+// of SH rows (a 33rd rectangle column would hold 2 of 32 active columns)
+int rect_full_width(int W)
+{
+    const int r = W % TTile<3>::TX;
+    return (r > 0 && r <= TTile<3>::SWMAX) ? W - r : W;
+}
+
+long long rect_tiles_per_plane(const KBox &bx)
+{
+    const int W = bx.n[0] + 2, H = bx.n[1] + 2, F = rect_full_width(W);
+    long long t = (long long)((F + TTile<3>::TX - 1) / TTile<3>::TX) * ((H + TTile<3>::TY - 1) / TTile<3>::TY);
+    if (F < W) t += (H + TTile<3>::SH - 1) / TTile<3>::SH;
+    return t;
+}
+
 bool use_flat(const ctu_plan *p, const KBox &bx)
 {
     if (!flat_allowed(p, bx) || p->shape.tc_layout == CTU_TC_TILES) return false;
     if (p->shape.tc_layout == CTU_TC_FLAT) return true;
     const long long W = bx.n[0] + 2, H = bx.n[1] + 2;
-    const long long tiles = ((W + TTile<3>::TX - 1) / TTile<3>::TX) * ((H + TTile<3>::TY - 1) / TTile<3>::TY);
     const long long flat = ((W + 1) * (H + 1) + NT - 1) / NT;
-    return flat < tiles;
+    return flat < rect_tiles_per_plane(bx);
 }
 
 int tc_chunk(const ctu_plan *p) { return p->shape.tc_chunk > 0 ? p->shape.tc_chunk : TTile<3>::LM; }
@@ -239,10 +255,7 @@ void shape_capacity(const ctu_plan *p, size_t cap[4])
     for (int q = 0; q < 4; q++) cap[q] = 0;
     for (const KBox &bx : p->hboxes) {
         const long long em = bx.n[dim - 1] + 2;
-        const int TX = (dim == 3) ? TTile<3>::TX : TTile<2>::TX;
-        const int TY = (dim == 3) ? TTile<3>::TY : TTile<2>::TY;
-        const long long ex = bx.n[0] + 2, ey = (dim == 3) ? bx.n[1] + 2 : 1;
-        long long per = ((ex + TX - 1) / TX) * ((ey + TY - 1) / TY);
+        long long per = (dim == 3) ? rect_tiles_per_plane(bx) : (bx.n[0] + 2 + TTile<2>::TX - 1) / TTile<2>::TX;
         if (flat_allowed(p, bx)) per = std::max(per, ((long long)(bx.n[0] + 3) * (bx.n[1] + 3) + NT - 1) / NT);
         cap[0] += (size_t)(em * per);
         for (int D = 0; D < dim; D++) {
@@ -273,9 +286,13 @@ ctu_status build_shape_tables(ctu_plan *p)
             const int TX = (dim == 3) ? TTile<3>::TX : TTile<2>::TX;
             const int TY = (dim == 3) ? TTile<3>::TY : TTile<2>::TY;
             const int ex = bx.n[0] + 2, ey = (dim == 3) ? bx.n[1] + 2 : 1;
-            for (int m0 = 0; m0 < em; m0 += LM)
+            const int fx = (dim == 3) ? rect_full_width(ex) : ex;
+            for (int m0 = 0; m0 < em; m0 += LM) {
                 for (int y0 = 0; y0 < ey; y0 += TY)
-                    for (int x0 = 0; x0 < ex; x0 += TX) p->t_tc.h.push_back(KTile{ b, x0, y0, m0 });
+                    for (int x0 = 0; x0 < fx; x0 += TX) p->t_tc.h.push_back(KTile{ b, x0, y0, m0 });
+                if (fx < ex)
+                    for (int y0 = 0; y0 < ey; y0 += TTile<3>::SH) p->t_tc.h.push_back(KTile{ b, fx, -2 - y0, m0 });
+            }
         }
         for (int D = 0; D < dim; D++) {
             int T0 = (D == 0) ? 1 : 0, T1 = (D == 2) ? 1 : 2;

@@ -17,8 +17,12 @@ pytestmark = pytest.mark.gpu
 
 NG = 4
 LEVEL_N = 64
-# widths 16, 37 and 8 admit the flat t^n layout (n0 + 3 <= 40), 48 does not
-BOXES = [((0, 0, 0), (16, 20, 18)), ((16, 0, 0), (37, 24, 16)), ((0, 24, 0), (48, 40, 20)), ((8, 8, 40), (8, 8, 8))]
+# widths 16, 37, 8 and 31 admit the flat t^n layout (n0 + 3 <= 40), 48 and
+# 64 do not; in the rectangle layout the t^n regions 33 and 66 positions wide
+# (widths 31 and 64) end in a strip of 1 and 2 positions
+BOXES = [((0, 0, 0), (16, 20, 18)), ((16, 0, 0), (37, 24, 16)), ((0, 24, 0), (48, 40, 20)), ((8, 8, 40), (8, 8, 8)),
+         ((40, 40, 0), (31, 12, 10)), ((0, 0, 24), (64, 10, 6))]
+NFLAT = 4
 SHAPES = [
     {},
     {"tc_layout": "tiles"},
@@ -100,7 +104,7 @@ def test_every_shape_gives_bitwise_the_same_step(precision):
         got_shape, nflat = r.plan.get_shape()
         layout = sh.get("tc_layout", "auto")
         assert got_shape["tc_layout"] == layout
-        assert nflat == (0 if layout == "tiles" else 3)
+        assert nflat == (0 if layout == "tiles" else NFLAT)
         U, rate, reg = r.step()
         if ref is None:
             ref = (U, rate, reg)
@@ -114,6 +118,19 @@ def test_every_shape_gives_bitwise_the_same_step(precision):
 def test_flat_layout_matches_oracle():
     r = Run("fp64")
     r.plan.set_shape(tc_layout="flat", tc_chunk=7)
+    U, _, _ = r.step()
+    oo, _ = box_states()
+    for u_in, got in zip(r.U, r.boxes_out(U)):
+        ref, _, _, fails = O.step(oo, u_in, NG, r.dt, r.ch)
+        assert fails == [0] * 5
+        assert_parity(got, ref, NG, 3, r.ch, 1e-12)
+
+
+def test_tiles_with_strips_match_oracle():
+    """the rectangle layout, whose 33- and 66-position rows end in strips of
+    1 and 2 positions, against the oracle on every box"""
+    r = Run("fp64")
+    r.plan.set_shape(tc_layout="tiles", tc_chunk=6)
     U, _, _ = r.step()
     oo, _ = box_states()
     for u_in, got in zip(r.U, r.boxes_out(U)):
