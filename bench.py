@@ -77,6 +77,8 @@ def parse():
     ap.add_argument("--no-amr", action="store_true", help="skip the AMR leg (C3)")
     ap.add_argument("--no-variants", action="store_true", help="skip the option-set variants")
     ap.add_argument("--no-autotune", action="store_true", help="default launch shapes for the FP32 plans")
+    ap.add_argument("--no-per-patch", action="store_true",
+                    help="skip C3's FP64 one-plan-per-patch path (thousands of launches; profiling aid)")
     ap.add_argument("--legs", default="c2,c1,c3,c4,c5", help="workloads to run (profiling aid)")
     ap.add_argument("--shape", default=None,
                     help="force the launch shape of the C2 FP32 plan instead of tuning it: "
@@ -703,24 +705,10 @@ def leg_c3(args, dev, s, samples):
     del one, Uin, Uout, Ucat, Uocat
     torch.cuda.synchronize()
     # FP64 plain, one plan per patch
-    log("C3: FP64 one plan per patch")
-    pplans = []
-    for lev, L in enumerate(h.levels):
-        go = ctu.make_opts(dim=3, gamma=5.0 / 3.0, dx=h.dx(0), precision="fp64", **okw)
-        for B, ob in zip(L, offs[lev]):
-            pplans.append((lev, ctu.Plan(go, [(B.lo, B.n, lev, ob)], NG)))
-    Uo64 = [torch.empty_like(u) for u in U64]
-    torch.cuda.synchronize()
-
-    def amr_step64():
-        for lev, p in pplans:
-            p.step(U64[lev], Uo64[lev], params[lev], b.rate, fails=b.fails, stream=s)
-
-    ms64 = timed(amr_step64, K, W, s)
-    assert b.fails.sum().item() == 0
-    r64 = result(ms64, zones, 2 * (36 * sum(ghost_l) + 36 * zones) / zones)
-    r64["launches_per_step"] = 6 * npatch
-    del pplans, Uo64, U64
+    r64 = ms64 = None
+    if not args.no_per_patch:
+        r64, ms64 = c3_per_patch(h, U64, params, offs, okw, zones, ghost_l, npatch, b, s, K, W)
+    del U64
     torch.cuda.synchronize()
     # the subcycled level cycle on the nested hierarchy
     log("C3: subcycled level cycle (nested hierarchy)")
@@ -748,8 +736,36 @@ def leg_c3(args, dev, s, samples):
     cycle = {"ms_per_cycle": msc, "zone_updates_per_cycle": cyc_zones, "zone_updates_per_s": cyc_zones / (msc * 1e-3),
              "patches": sum(len(L) for L in hn.levels), "level_steps_per_cycle": nsteps}
     return {"patches": npatch, "zones": zones, "levels": [len(L) for L in h.levels], "register_slots": nslots,
-            "fp32_batched": r32, "fp64_plain_per_patch": r64, "batched_fp32_over_plain_fp64": ms64 / ms32,
+            "fp32_batched": r32, "fp64_plain_per_patch": r64,
+            "batched_fp32_over_plain_fp64": ms64 / ms32 if ms64 else None,
             "fp32_cycle": cycle}
+
+
+def c3_per_patch(h, U64, params, offs, okw, zones, ghost_l, npatch, b, s, K, W):
+    """C3's FP64 plain path: one plan per patch, eager launches."""
+    import torch
+
+    from paper_1110_0740_amd import ctu
+
+    log("C3: FP64 one plan per patch")
+    pplans = []
+    for lev, L in enumerate(h.levels):
+        go = ctu.make_opts(dim=3, gamma=5.0 / 3.0, dx=h.dx(0), precision="fp64", **okw)
+        for B, ob in zip(L, offs[lev]):
+            pplans.append((lev, ctu.Plan(go, [(B.lo, B.n, lev, ob)], NG)))
+    Uo64 = [torch.empty_like(u) for u in U64]
+    torch.cuda.synchronize()
+
+    def amr_step64():
+        for lev, p in pplans:
+            p.step(U64[lev], Uo64[lev], params[lev], b.rate, fails=b.fails, stream=s)
+
+    ms64 = timed(amr_step64, K, W, s)
+    assert b.fails.sum().item() == 0
+    r64 = result(ms64, zones, 2 * (36 * sum(ghost_l) + 36 * zones) / zones)
+    r64["launches_per_step"] = 6 * npatch
+    del pplans, Uo64
+    return r64, ms64
 
 
 # ---------------------------------------------------------------------------
