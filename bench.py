@@ -43,25 +43,45 @@ NG = 4
 # FMA = 2) of what each kernel computes, from the op-counting build of the
 # FP64 oracle (profiles/oracle_opcount.md, `python oracle/opcount.py`):
 # prim = primitive recovery, tcouple = the t^n Godunov (and parabolic) fluxes
-# with their increments and, with parabolic terms, the half-step state.  The
-# sweeps are not listed: the oracle's predictor projects with dense 7 x 7
-# eigenvector products where the kernels use the sparse closed forms, so its
-# count is not the method's minimum; nor are the relativistic inversions,
-# whose oracle form is a bisection.
+# with their increments and, with parabolic terms, the half-step state; for
+# the relativistic workload also the sweeps (MUSCL-Hancock predictor and
+# coupling, time-centred solves, a third each, and the update in the last
+# one).  The characteristic-tracing sweeps are not listed: the oracle's
+# predictor projects with dense 7 x 7 eigenvector products where the kernels
+# use the sparse closed forms, so its count is not the method's minimum; nor
+# are the relativistic inversions, whose oracle form is a bisection.
 ALG_FLOP = {"C1": {"prim": 20.0, "tcouple": 943.0}, "C2": {"prim": 20.0, "tcouple": 1354.0},
-            "C4": {"tcouple": 1696.0}, "C5": {"prim": 20.0, "tcouple": 2056.0}}
+            "C4": {"tcouple": 1696.0, "sweep_x": 1190.0, "sweep_y": 1190.0, "sweep_z": 1351.0},
+            "C5": {"prim": 20.0, "tcouple": 2056.0}}
 # HBM bytes per launch of the FP32 256^3 t^n kernel, FETCH_SIZE x 2.0 +
 # WRITE_SIZE x 1.0 (KiB x 1024): a plain 1 GiB device copy (bench.py
 # --copy-calibration) reads back as 524,308 KiB of FETCH_SIZE and 1,048,576
-# KiB of WRITE_SIZE, hence the factors (profiles/ctu_step_fp32_256cube_counters.md).
+# KiB of WRITE_SIZE, hence the factors (profiles/c2_mhd3d_256_ppm_hlld.md).
 # None once the kernel has changed since the counters were taken.
-TCOUPLE_TRAFFIC_BYTES = (471996 * 2 + 1987027) * 1024
+TCOUPLE_TRAFFIC_BYTES = (529792 * 2 + 2091326) * 1024
 # the launch shape those counters were taken with (bench.py --shape tiles,4,16,1,2)
 PROFILE_SHAPE = {"tc_layout": "tiles", "tc_chunk": 4, "xcd_order": 1}
+# Step parameters of the workloads (dt and c_h; C1's ten chained steps; C5's
+# hyperbolic step that sets the cooling times), from the FP64 oracle's CFL
+# rate of each initial state, written by tests/golden/make_refs.py: the timed
+# steps and the oracle comparisons use the same values, none taken from the
+# GPU.
+STEP_PARAMS = os.path.join(ROOT, "tests", "golden", "step_params.json")
 PEAK_HBM_GBS = 8000.0
 PEAK_FP32_TFLOPS = 157.3           # published FP32 vector peak (packed FP32 issue)
 PEAK_FP32_UNPACKED_TFLOPS = 78.6   # one FP32 lane op per VALU lane per cycle (no packed FP32 emitted)
 PEAK_FP64_TFLOPS = 78.6
+
+
+_STEP = None
+
+
+def step_params():
+    global _STEP
+    if _STEP is None:
+        with open(STEP_PARAMS) as f:
+            _STEP = json.load(f)
+    return _STEP
 
 
 def log(msg):
@@ -261,8 +281,9 @@ def parity_norms(pairs, ch, physics, dim):
 
 class Samples:
     """What the oracle needs to recompute a timed result on sub-boxes: the
-    oracle options, dt, c_h, the FP64 input sub-boxes (and cooling
-    coefficients) and the GPU's output on the same sub-boxes."""
+    oracle options, dt, c_h, the input sub-boxes as primitive fields from the
+    seeded generator (the oracle forms the conserved state itself), cooling
+    coefficients, and the GPU's output on the same sub-boxes."""
 
     def __init__(self):
         self.items = {}
@@ -293,12 +314,14 @@ def leg_c2(args, dev, s, samples):
     p64 = ctu.Plan(ctu.make_opts(dim=3, gamma=gamma, dx=dx, precision="fp64", **okw), box, NG)
     U64 = torch.empty(9 * N ** 3, dtype=torch.float64, device=dev)
     p64.prim_to_cons(V64.reshape(-1), U64)
+    org = origins(n, 16, 3)
+    ins = [subbox(V64.reshape(-1), N, lo, 16, 3) for lo in org]
+    # the sub-boxes the cpu_baseline leg times the oracle on (C2's own input)
+    timing_boxes = [subbox(V64.reshape(-1), N, lo, 48, 3) for lo in ((0, 0, 0), (100, 60, 180), (200, 200, 30))]
     del V64
     b = StepBufs(dev)
-    p64.cfl_rate(U64, b.rate)
-    torch.cuda.synchronize()
-    dt = 0.4 / b.rate.item()
-    ch = 0.4 * dx[0] / dt
+    sp = step_params()["C2"]
+    dt, ch = sp["dt"], sp["ch"]
     params = torch.tensor([dt, ch], dtype=torch.float64, device=dev)
     outs = {}
     # FP32 batched: tuned shape, graph replay
@@ -321,22 +344,18 @@ def leg_c2(args, dev, s, samples):
     Uo64 = torch.empty_like(U64)
     ms64, per64 = run_plan(p64, U64, Uo64, params, b, K, W, s, graph=False)
     r64 = result(ms64, zones, ghost_bytes(n, 8), per64)
-    org = origins(n, 16, 3)
-    ins = [subbox(U64, N, lo, 16, 3) for lo in org]
     samples.add("c2_fp32", okw, dx, dt, ch, ins, [subbox(Uo32, N, lo, 16, 3) for lo in org])
     samples.add("c2_fp64", okw, dx, dt, ch, ins, [subbox(Uo64, N, lo, 16, 3) for lo in org])
-    # the sub-boxes the cpu_baseline leg times the oracle on (C2's own input)
-    timing_boxes = [subbox(U64, N, lo, 48, 3) for lo in ((0, 0, 0), (100, 60, 180), (200, 200, 30))]
     out = {"fp32_batched": r32, "fp64_plain": r64, "zones": zones, "dt": dt, "c_h": ch}
     out["fp32_batched"]["roofline"] = kernel_roofline("C2", per, zones, "f32")
     variants = None
     if not args.no_variants:
-        variants = c2_variants(args, dev, s, p64, U64, params, b, dx, gamma, samples)
+        variants = c2_variants(args, dev, s, U64, ins[:3], params, b, dx, gamma, samples)
     del Uo64, Uo32, U32
     return out, variants, timing_boxes, (dx, gamma, dt, ch)
 
 
-def c2_variants(args, dev, s, p64, U64, params, b, dx, gamma, samples):
+def c2_variants(args, dev, s, U64, ins, params, b, dx, gamma, samples):
     """The C2 workload under the widened option sets: the App. B hybrid,
     Rusanov, HLLC and Roe solvers, the MT corner coupling (FP32, tuned,
     graph-replayed)."""
@@ -349,7 +368,6 @@ def c2_variants(args, dev, s, p64, U64, params, b, dx, gamma, samples):
     box = [((0, 0, 0), (n, n, n), 0, 0)]
     out = {}
     org = origins(n, 16, 3)[:3]
-    ins = [subbox(U64, N, lo, 16, 3) for lo in org]
     variants = {"shock_hybrid": dict(riemann="hlld", shock_eps=5.0), "rusanov": dict(riemann="rusanov"),
                 "hllc": dict(riemann="hllc"), "roe": dict(riemann="roe"), "mt_corner": dict(riemann="hlld", corner="mt")}
     for name, kw in variants.items():
@@ -361,7 +379,7 @@ def c2_variants(args, dev, s, p64, U64, params, b, dx, gamma, samples):
             p.autotune(U32, Uo, params, reps=3, stream=s)
         ms, _ = run_plan(p, U32, Uo, params, b, K, W, s, stages=False)
         out[name] = result(ms, n ** 3, ghost_bytes(n, 4), shape=p.get_shape()[0])
-        samples.add(f"c2_{name}", dict(recon="ppm", **kw), dx, params[0].item(), params[1].item(), ins,
+        samples.add(f"c2_{name}", dict(recon="ppm", **kw), dx, float(params[0]), float(params[1]), ins,
                     [subbox(Uo, N, lo, 16, 3) for lo in org])
         del p, U32, Uo
     return out
@@ -370,8 +388,8 @@ def c2_variants(args, dev, s, p64, U64, params, b, dx, gamma, samples):
 def leg_c1(args, dev, s, samples):
     """2D 128^2 FP64, 10 CTU steps at CFL 0.4: timed as repeated steps (eager
     and graph); the L1 figure compares 10 chained steps (GPU ghosts refilled
-    periodically on the device between steps, the GPU's dt sequence given to
-    the oracle)."""
+    periodically on the device between steps), both sides driven by the
+    oracle's stored dt sequence."""
     import numpy as np
     import torch
 
@@ -387,10 +405,8 @@ def leg_c1(args, dev, s, samples):
     U = torch.empty_like(Vd)
     plan.prim_to_cons(Vd, U)
     b = StepBufs(dev)
-    plan.cfl_rate(U, b.rate)
-    torch.cuda.synchronize()
-    dt = 0.4 / b.rate.item()
-    ch = 0.4 * meta["dx"][0] / dt
+    chain = step_params()["C1"]
+    dt, ch = chain["dt"][0], chain["ch"][0]
     params = torch.tensor([dt, ch], dtype=torch.float64, device=dev)
     Uo = U.clone()
     log("C1: FP64 plain (eager, default shape), then batched (tuned shape, graph)")
@@ -403,11 +419,10 @@ def leg_c1(args, dev, s, samples):
            "fp64_batched": result(ms_g, zones, ghost_bytes(n, 8, 2), per_g, plan.get_shape()[0]), "zones": zones}
     out["fp64_plain"]["roofline"] = kernel_roofline("C1", per, zones, "f64")
     out["fp64_batched"]["roofline"] = kernel_roofline("C1", per_g, zones, "f64")
-    # 10 chained steps for the L1 figure
-    U0 = U.cpu().numpy().reshape(9, 1, n + 2 * NG, n + 2 * NG).copy()
+    # 10 chained steps for the L1 figure, with the oracle's dt sequence
     cur, nxt = U.clone(), torch.empty_like(U)
-    dts = []
-    for _ in range(10):
+    dts = list(zip(chain["dt"], chain["ch"]))
+    for dt, ch in dts:
         params.copy_(torch.tensor([dt, ch], dtype=torch.float64))
         plan.step(cur, nxt, params, b.rate, fails=b.fails)
         g = nxt.view(9, 1, n + 2 * NG, n + 2 * NG)
@@ -416,12 +431,9 @@ def leg_c1(args, dev, s, samples):
         g[..., :, :NG] = g[..., :, n:n + NG]
         g[..., :, n + NG:] = g[..., :, NG:2 * NG]
         torch.cuda.synchronize()
-        dts.append((dt, ch))
-        dt = 0.4 / b.rate.item()
-        ch = 0.4 * meta["dx"][0] / dt
         cur, nxt = nxt, cur
     assert b.fails.sum().item() == 0
-    samples.add("c1_fp64_10steps", okw, meta["dx"], None, None, [U0], [cur.cpu().numpy().reshape(U0.shape)], dim=2,
+    samples.add("c1_fp64_10steps", okw, meta["dx"], None, None, [V], [cur.cpu().numpy().reshape(V.shape)], dim=2,
                 chain=dts)
     return out
 
@@ -442,6 +454,7 @@ def leg_c4(args, dev, s, samples):
     out, variants = {}, {}
     b = StepBufs(dev)
     org = origins(n, 12, 3)[:4]
+    ins = [subbox(Vd, N, lo, 12, 3) for lo in org]
     for eos, xs, rs in (("ideal", False, "hll"), ("tm", False, "hll"), ("ideal", True, "hll"),
                         ("ideal", False, "hllc"), ("ideal", False, "hlld")):
         main = (eos, xs, rs) == ("ideal", False, "hll")
@@ -454,10 +467,8 @@ def leg_c4(args, dev, s, samples):
         p64 = ctu.Plan(ctu.make_opts(precision="fp64", **kw), box, NG)
         U64 = torch.empty_like(Vd)
         p64.prim_to_cons(Vd, U64)
-        p64.cfl_rate(U64, b.rate)
-        torch.cuda.synchronize()
-        dt = 0.3 / b.rate.item()
-        ch = min(0.3 * meta["dx"][0] / dt, 1.0)
+        sp = step_params()["C4"][name]
+        dt, ch = sp["dt"], sp["ch"]
         params = torch.tensor([dt, ch], dtype=torch.float64, device=dev)
         p = ctu.Plan(ctu.make_opts(precision="fp32", **kw), box, NG)
         U32 = U64.to(torch.float32)
@@ -466,7 +477,6 @@ def leg_c4(args, dev, s, samples):
             p.autotune(U32, Uo, params, reps=3, stream=s)
         ms, per = run_plan(p, U32, Uo, params, b, K, W, s, stages=main)
         r = result(ms, zones, ghost_bytes(n, 4), per, p.get_shape()[0])
-        ins = [subbox(U64, N, lo, 12, 3) for lo in org]
         samples.add(f"c4_{name}_fp32", okw, meta["dx"], dt, ch, ins, [subbox(Uo, N, lo, 12, 3) for lo in org],
                     physics="rmhd")
         if main:
@@ -503,9 +513,10 @@ def leg_c5(args, dev, s, samples):
     hyp = ctu.Plan(ctu.make_opts(dim=3, gamma=G, dx=dx, precision="fp64", recon="ppm", riemann="hlld"), box, NG)
     U64 = torch.empty(9 * N ** 3, dtype=torch.float64, device=dev)
     hyp.prim_to_cons(V.reshape(-1), U64)
-    hyp.cfl_rate(U64, b.rate)
-    torch.cuda.synchronize()
-    dt0 = 0.4 / b.rate.item()  # the hyperbolic CFL step of U^0 sets the cooling times
+    org = origins(n, 16, 3)[:4]
+    ins = [subbox(V.reshape(-1), N, lo, 16, 3) for lo in org]
+    sp = step_params()["C5"]
+    dt0 = sp["dt0"]  # the hyperbolic CFL step of U^0 sets the cooling times
     T = V[4] / V[0]
     tc = I.cooling_time_field_torch(5002, n, NG, dt0, device=dev)
     L0 = (V[4] / ((G - 1) * V[0] ** 2 * torch.sqrt(T) * tc)).reshape(-1).contiguous()
@@ -514,10 +525,7 @@ def leg_c5(args, dev, s, samples):
     okw = dict(recon="ppm", riemann="hlld", parabolic_mask=7, tc_phi=0.3, cooling=True, cool_beta=0.5,
                T_floor=Tfl, **coef)
     p64 = ctu.Plan(ctu.make_opts(dim=3, gamma=G, dx=dx, precision="fp64", **okw), box, NG)
-    p64.cfl_rate(U64, b.rate)
-    torch.cuda.synchronize()
-    dt = 0.4 / b.rate.item()
-    ch = 0.4 * dx[0] / dt
+    dt, ch = sp["dt"], sp["ch"]
     params = torch.tensor([dt, ch], dtype=torch.float64, device=dev)
     log("C5: FP32 batched (autotune, graph)")
     p32 = ctu.Plan(ctu.make_opts(dim=3, gamma=G, dx=dx, precision="fp32", **okw), box, NG)
@@ -534,8 +542,6 @@ def leg_c5(args, dev, s, samples):
     Uo64 = torch.empty_like(U64)
     ms64, per64 = run_plan(p64, U64, Uo64, params, b, K, W, s, L0=L0, graph=False)
     r64 = result(ms64, zones, ghost_bytes(n, 8) + 8 * ((n + 2 * NG) / n) ** 3, per64)
-    org = origins(n, 16, 3)[:4]
-    ins = [subbox(U64, N, lo, 16, 3) for lo in org]
     L0s64 = [subbox_cells(L0, N, lo, 16) for lo in org]
     L0s32 = [subbox_cells(L32, N, lo, 16) for lo in org]
     samples.add("c5_fp32", okw, dx, dt, ch, ins, [subbox(Uo32, N, lo, 16, 3) for lo in org], L0s=L0s32)
@@ -566,26 +572,28 @@ def leg_c3(args, dev, s, samples):
     K, W = max(3, args.steps // 2), min(args.warmup, 2)
     okw = dict(recon="ppm", riemann="hlld")
 
-    def level_states(h, precision_plans=True):
-        U64, offs = [], []
+    def level_states(h, keep_prim=False):
+        """conserved FP64 level arrays (and, with keep_prim, the primitive
+        ones from the generator)"""
+        U64, offs, Vs = [], [], []
         for lev, L in enumerate(h.levels):
             o, off = 0, []
             for B in L:
                 off.append(o)
                 o += 9 * int(np.prod([x + 2 * NG for x in B.n]))
-            V = torch.empty(o, dtype=torch.float64, device=dev)
-            for B, ob in zip(L, off):
-                v = I.amr_fields_torch(h, B, NG, device=dev).reshape(-1)
-                V[ob:ob + v.numel()] = v
+            V = I.amr_level_fields_torch(h, lev, NG, device=dev)
+            assert V.numel() == o
             tmp = ctu.Plan(ctu.make_opts(dim=3, gamma=5.0 / 3.0, dx=h.dx(0), precision="fp64", **okw),
                            [(B.lo, B.n, lev, ob) for B, ob in zip(L, off)], NG)
             U = torch.empty_like(V)
             tmp.prim_to_cons(V, U)
             U64.append(U)
             offs.append(off)
+            if keep_prim:
+                Vs.append(V)
             del tmp, V
         torch.cuda.synchronize()
-        return U64, offs
+        return U64, offs, Vs
 
     log("C3: configured hierarchy (1,457 patches)")
     h = I.amr_hierarchy()
@@ -595,7 +603,7 @@ def leg_c3(args, dev, s, samples):
     ghost_l = [int(sum(int(np.prod([x + 2 * NG for x in B.n])) for B in L)) for L in h.levels]
     zones = sum(zones_l)
     npatch = sum(len(L) for L in h.levels)
-    U64, offs = level_states(h)
+    U64, offs, V64 = level_states(h, keep_prim=True)
     dt0 = 1e-4
     ch = 0.4 * h.dx(0)[0] / dt0
     params = [torch.tensor([dt0 / (1 << lev), ch], dtype=torch.float64, device=dev) for lev in range(nlev)]
@@ -638,8 +646,9 @@ def leg_c3(args, dev, s, samples):
             shp = (9,) + tuple(x + 2 * NG for x in reversed(B.n))
             o = offs[lev][int(bi)]
             cnt = int(np.prod(shp))
-            sample.append((lev, U64[lev][o:o + cnt].cpu().numpy().reshape(shp),
+            sample.append((lev, V64[lev][o:o + cnt].cpu().numpy().reshape(shp),
                            Uout[lev][o:o + cnt].cpu().numpy().astype(np.float64).reshape(shp)))
+    del V64
 
     def amr_step32():
         for p in plans:
@@ -714,7 +723,7 @@ def leg_c3(args, dev, s, samples):
     log("C3: subcycled level cycle (nested hierarchy)")
     hn = I.amr_hierarchy(nest=3)
     tn, nsn = amr.build_tables(hn.levels, hn.base, NG)
-    U64n, offsn = level_states(hn)
+    U64n, offsn, _ = level_states(hn)
     paramsn = [torch.tensor([dt0 / (1 << lev), ch], dtype=torch.float64, device=dev) for lev in range(nlev)]
     regn = torch.zeros(9 * nsn, dtype=torch.float64, device=dev)
     plans_n = [ctu.Plan(ctu.make_opts(dim=3, gamma=5.0 / 3.0, dx=hn.dx(0), precision="fp32", **okw),
@@ -795,6 +804,7 @@ def cpu_baseline(timing_boxes, c2_params, samples):
 
     dx, gamma, dt, ch = c2_params
     oo = O.make_opts(dim=3, recon="ppm", riemann="hlld", gamma=gamma, dx=dx)
+    timing_boxes = [O.prim2cons(oo, V) for V in timing_boxes]
     zones = sum(int(np.prod([x - 2 * NG for x in U.shape[1:]])) for U in timing_boxes)
     rates = {}
     for label, nt in (("all", 0), ("one", 1)):
@@ -816,7 +826,7 @@ def cpu_baseline(timing_boxes, c2_params, samples):
         pairs = []
         if it["chain"] is not None:  # C1: chained steps on the periodic box
             o = O.make_opts(dim=it["dim"], gamma=5.0 / 3.0, dx=it["dx"], **it["okw"])
-            U = it["ins"][0].copy()
+            U = O.prim2cons(o, it["ins"][0])
             for dtk, chk in it["chain"]:
                 U, _, _, f = O.step(o, U, NG, dtk, chk)
                 I.fill_periodic(U, NG, it["dim"])
@@ -825,9 +835,9 @@ def cpu_baseline(timing_boxes, c2_params, samples):
         else:
             gam = 4.0 / 3.0 if it["physics"] == "rmhd" else 5.0 / 3.0
             o = O.make_opts(dim=3, gamma=gam, dx=it["dx"], **it["okw"])
-            for k, (Ui, Ug) in enumerate(zip(it["ins"], it["outs"])):
+            for k, (Vi, Ug) in enumerate(zip(it["ins"], it["outs"])):
                 L0 = it["L0s"][k] if it["L0s"] else None
-                ref, _, _, f = O.step(o, Ui, NG, it["dt"], it["ch"], L0=L0)
+                ref, _, _, f = O.step(o, O.prim2cons(o, Vi), NG, it["dt"], it["ch"], L0=L0)
                 pairs.append((Ug, ref))
             ch_last = it["ch"]
         e, c = parity_norms(pairs, ch_last, it["physics"], it["dim"])

@@ -577,6 +577,76 @@ def amr_fields(h: Hierarchy, box: Box, ng: int = 4, v_rms: float = 0.5, b_rms: f
     return V
 
 
+def amr_level_fields_torch(h: Hierarchy, level: int, ng: int = 4, device="cuda", v_rms: float = 0.5,
+                           b_rms: float = 0.5):
+    """:func:`amr_fields` of every box of one level at once, evaluated with
+    torch on `device` (float64) over the flat list of the level's ghosted
+    cells: the boxes' ghosted [9, NZ, NY, NX] blocks packed one after
+    another in box order, as one 1D tensor.  A few hundred vector operations
+    per level instead of a thousand per box."""
+    import torch
+
+    if not h.modes:
+        rng = SplitMix64(h.seed + 17)
+        h.modes = {name: draw_modes(rng, 3) for name in ("vx", "vy", "vz", "Ax", "Ay", "Az")}
+    m = h.modes
+    L = h.levels[level]
+    dx = h.dx(level)
+    idx, sizes = [[], [], []], []
+    for B in L:
+        ax = [np.arange(B.lo[d] - ng, B.lo[d] + B.n[d] + ng) for d in range(3)]
+        Z, Y, X = np.meshgrid(ax[2], ax[1], ax[0], indexing="ij")
+        for d, Q in enumerate((X, Y, Z)):
+            idx[d].append(Q.ravel())
+        sizes.append(X.size)
+    ncell = int(sum(sizes))
+    xs = [(torch.from_numpy(np.concatenate(idx[d]) if sizes else np.zeros(0, np.int64)).to(device=device,
+                                                                                              dtype=torch.float64)
+           + 0.5) * dx[d] for d in range(3)]
+    x, y, z = xs
+
+    def modesum(mm):
+        out = torch.zeros(ncell, dtype=torch.float64, device=device)
+        for k, ph, a in zip(mm.k, mm.phi, mm.amp):
+            out += a * torch.cos(2.0 * math.pi * (float(k[0]) * x + float(k[1]) * y + float(k[2]) * z) + ph)
+        return out
+
+    def modegrad(mm):
+        g = [torch.zeros(ncell, dtype=torch.float64, device=device) for _ in range(3)]
+        for k, ph, a in zip(mm.k, mm.phi, mm.amp):
+            sn = torch.sin(2.0 * math.pi * (float(k[0]) * x + float(k[1]) * y + float(k[2]) * z) + ph)
+            for c in range(3):
+                g[c] -= a * 2.0 * math.pi * float(k[c]) * sn
+        return g
+
+    F = torch.empty((NVAR, ncell), dtype=torch.float64, device=device)
+    bump = torch.zeros(ncell, dtype=torch.float64, device=device)
+    for c, r in h.blobs:
+        d2 = torch.zeros(ncell, dtype=torch.float64, device=device)
+        for q, Q in enumerate(xs):
+            t = Q - float(c[q])
+            t = t - torch.round(t)
+            d2 += t * t
+        bump = torch.maximum(bump, torch.exp(-d2 / (r * r)))
+    F[RHO] = 1.0 + 9.0 * bump
+    F[PRS] = 0.6
+    for c, name in enumerate(("vx", "vy", "vz")):
+        F[VX1 + c] = (v_rms / math.sqrt(3.0)) / m[name].rms() * modesum(m[name])
+    A = [m["Ax"], m["Ay"], m["Az"]]
+    scale = b_rms / curl_rms(A)
+    g = [modegrad(a) for a in A]
+    F[BX1] = scale * (g[2][1] - g[1][2])
+    F[BX2] = scale * (g[0][2] - g[2][0])
+    F[BX3] = scale * (g[1][0] - g[0][1])
+    F[PSI] = 0.0
+    out = torch.empty(NVAR * ncell, dtype=torch.float64, device=device)
+    s0 = 0
+    for n in sizes:
+        out[NVAR * s0:NVAR * (s0 + n)].view(NVAR, n).copy_(F[:, s0:s0 + n])
+        s0 += n
+    return out
+
+
 def amr_fields_torch(h: Hierarchy, box: Box, ng: int = 4, device="cuda", v_rms: float = 0.5, b_rms: float = 0.5):
     """:func:`amr_fields` evaluated with torch on `device` (float64)."""
     import torch

@@ -1,5 +1,7 @@
-"""Writes the stored FP64 oracle reference outputs (tests/golden/*.npz) that
-the GPU parity tests compare against without re-running the oracle.
+"""Writes the stored FP64 oracle values: the reference outputs
+(tests/golden/*.npz) that the GPU parity tests compare against without
+re-running the oracle, and the benchmark workloads' step parameters
+(tests/golden/step_params.json).
 
 Calls only the oracle and the seeded input generators:
 
@@ -16,6 +18,7 @@ the input generator unnoticed.
 from __future__ import annotations
 
 import hashlib
+import json
 import os
 import sys
 
@@ -71,7 +74,77 @@ def path(name):
     return os.path.join(HERE, name + ".npz")
 
 
+# The step parameters of the benchmark workloads, from the oracle's CFL rate
+# (Eq. Ca) of each workload's initial state: dt = C_a / rate, c_h = C_a dx /
+# dt (capped at 1 for RMHD).  The benchmark runs its timed steps and its
+# oracle comparisons with these values, so no step parameter the oracle is
+# given comes from the GPU.  C1 also lists its ten chained steps (each dt
+# from the oracle's rate of the previous step's result); C5 its hyperbolic
+# step dt0, which sets the cooling times.
+STEP_PARAMS = os.path.join(HERE, "step_params.json")
+C4_VARIANTS = {"rmhd192_ideal": ("ideal", False, "hll"), "rmhd192_tm": ("tm", False, "hll"),
+               "rmhd192_ideal_exact_speeds": ("ideal", True, "hll"), "rmhd192_ideal_hllc": ("ideal", False, "hllc"),
+               "rmhd192_ideal_hlld": ("ideal", False, "hlld")}
+
+
+def step_params_c1():
+    n = 128
+    V, meta = I.mhd2d_fields(n=n, ng=NG, seed=1000)
+    o = O.make_opts(dim=2, gamma=meta["gamma"], dx=meta["dx"], recon="lin_mc", riemann="hlld")
+    U = O.prim2cons(o, V)
+    rate = O.cfl_rate(o, U, NG)
+    dts, chs = [], []
+    for _ in range(10):
+        dt = 0.4 / rate
+        ch = 0.4 * meta["dx"][0] / dt
+        U, rate, _, fails = O.step(o, U, NG, dt, ch)
+        assert fails == [0] * 5
+        I.fill_periodic(U, NG, 2)
+        dts.append(dt)
+        chs.append(ch)
+    return {"dt": dts, "ch": chs}
+
+
+def step_params_c2():
+    V, meta = I.mhd3d_fields(n=256, ng=NG, seed=2000)
+    o = O.make_opts(dim=3, gamma=meta["gamma"], dx=meta["dx"], recon="ppm", riemann="hlld")
+    dt = 0.4 / O.cfl_rate(o, O.prim2cons(o, V), NG)
+    return {"dt": dt, "ch": 0.4 * meta["dx"][0] / dt}
+
+
+def step_params_c4():
+    V, meta = I.rmhd3d_fields(n=192, ng=NG, seed=4000)
+    out = {}
+    for name, (eos, xs, rs) in C4_VARIANTS.items():
+        o = O.make_opts(dim=3, gamma=meta["gamma"], dx=meta["dx"], physics="rmhd", predictor="mh", recon="lin_mc",
+                        riemann=rs, eos=eos, exact_speeds=xs)
+        dt = 0.3 / O.cfl_rate(o, O.prim2cons(o, V), NG)
+        out[name] = {"dt": dt, "ch": min(0.3 * meta["dx"][0] / dt, 1.0)}
+    return out
+
+
+def step_params_c5():
+    V, meta = I.mhd3d_fields(n=256, ng=NG, seed=5000)
+    G, dx = meta["gamma"], meta["dx"]
+    hyp = O.make_opts(dim=3, gamma=G, dx=dx, recon="ppm", riemann="hlld")
+    U = O.prim2cons(hyp, V)
+    dt0 = 0.4 / O.cfl_rate(hyp, U, NG)
+    full = O.make_opts(dim=3, gamma=G, dx=dx, recon="ppm", riemann="hlld", parabolic_mask=7, tc_phi=0.3,
+                       **I.nonideal_coeffs(5001))
+    dt = 0.4 / O.cfl_rate(full, U, NG)
+    return {"dt0": dt0, "dt": dt, "ch": 0.4 * dx[0] / dt}
+
+
+def write_step_params():
+    d = {"C1": step_params_c1(), "C2": step_params_c2(), "C4": step_params_c4(), "C5": step_params_c5()}
+    with open(STEP_PARAMS, "w") as f:
+        json.dump(d, f, indent=1)
+    return d
+
+
 def main():
+    write_step_params()
+    print(f"wrote {STEP_PARAMS}")
     for name, r in REFS.items():
         U0, U, dts, chs = run_chain(r)
         n = r["n"]

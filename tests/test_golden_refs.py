@@ -26,3 +26,17 @@ def test_stored_reference_is_the_oracle_output(name):
     assert np.array_equal(z["interior"], U[:, ng:ng + n, ng:ng + n, ng:ng + n])
     assert np.array_equal(z["dt"], dts) and np.array_equal(z["ch"], chs)
     assert len(dts) == r["steps"]
+
+
+def test_step_params_are_the_oracle_values():
+    """the stored benchmark step parameters hold every workload, and C1's
+    ten-step dt / c_h chain is bitwise the oracle's (the 3D workloads' rates
+    over 192^3-256^3 states take minutes on the host: make_refs.py writes
+    them the same way)"""
+    import json
+
+    d = json.load(open(M.STEP_PARAMS))
+    assert set(d) == {"C1", "C2", "C4", "C5"} and set(d["C4"]) == set(M.C4_VARIANTS)
+    assert d["C1"] == M.step_params_c1()
+    for leg in ("C2", "C5"):
+        assert d[leg]["dt"] > 0 and d[leg]["ch"] > 0

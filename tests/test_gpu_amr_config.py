@@ -53,24 +53,28 @@ def test_configured_hierarchy_sampled_patches_registers_reflux(precision):
         for B in L:
             offs.append(o)
             o += 9 * int(np.prod([n + 2 * NG for n in B.n]))
-        V = torch.empty(o, dtype=torch.float64, device=DEV)
+        # primitive fields from the generator, conserved state from the oracle
+        # (the GPU steps the oracle's input)
+        V = I.amr_level_fields_torch(h, lev, NG, device=DEV).cpu().numpy()
+        assert V.size == o
+        oo = O.make_opts(dim=3, recon="ppm", riemann="hlld", gamma=GAMMA, dx=h.dx(lev))
+        Uh = np.empty_like(V)
         for B, ob in zip(L, offs):
-            v = I.amr_fields_torch(h, B, NG, device=DEV).reshape(-1)
-            V[ob:ob + v.numel()] = v
+            shape = (9,) + tuple(n + 2 * NG for n in reversed(B.n))
+            cnt = int(np.prod(shape))
+            Uh[ob:ob + cnt] = O.prim2cons(oo, V[ob:ob + cnt].reshape(shape)).reshape(-1)
+        del V
         go = ctu.make_opts(dim=3, recon="ppm", riemann="hlld", gamma=GAMMA, dx=h.dx(0), precision=precision)
         boxes = [(B.lo, B.n, lev, ob) for B, ob in zip(L, offs)]
         plan = ctu.Plan(go, boxes, NG, regfaces=tables[lev].regfaces)
-        p64 = ctu.Plan(ctu.make_opts(dim=3, recon="ppm", riemann="hlld", gamma=GAMMA, dx=h.dx(0)), boxes, NG)
-        U = torch.empty_like(V)
-        p64.prim_to_cons(V, U)
-        del V, p64
+        U = torch.from_numpy(Uh).to(DEV)
         Uin = U.to(dtype)
         Uout = Uin.clone()
         params = torch.tensor([dt0 / (1 << lev), ch], dtype=torch.float64, device=DEV)
         plan.step(Uin, Uout, params, rate, reg=reg, fails=fails)
         torch.cuda.synchronize()
         assert fails.sum().item() == 0
-        U_host.append(U.cpu().numpy())
+        U_host.append(Uh)
         got_host.append(Uout.cpu().numpy().astype(np.float64))
         plans.append(plan)
         outs.append(Uout)

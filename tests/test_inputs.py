@@ -50,6 +50,20 @@ def test_amr_fields_torch_matches_numpy():
         assert np.max(np.abs(Vt.numpy() - Vn)) < 1e-12
 
 
+def test_amr_level_fields_torch_matches_numpy():
+    """the level-at-once generator packs every box's amr_fields block in box
+    order"""
+    h = I.amr_hierarchy(seed=3001, base=32, base_box=16, lattice=16, size_range=(8, 16))
+    for lev in range(len(h.levels)):
+        flat = I.amr_level_fields_torch(h, lev, 4, device="cpu").numpy()
+        o = 0
+        for B in h.levels[lev]:
+            Vn = I.amr_fields(h, B, 4)
+            assert np.max(np.abs(flat[o:o + Vn.size].reshape(Vn.shape) - Vn)) < 1e-12
+            o += Vn.size
+        assert o == flat.size
+
+
 def test_cooling_time_torch_matches_numpy():
     import torch
 
