@@ -389,9 +389,13 @@ ctu_status ctu_reflux_consume(ctu_plan *coarse_plan, void *U_dev, double *reg_de
  * creation (CTU_ERR_ARG): boxes inside their level, 2-aligned (even lo and n)
  * on levels >= 1, disjoint per level, level 0 covering the domain, every
  * fine box inside the coarser level's interiors, each box block below 4 GiB.
- * Host-side tables (candidate boxes per box for the lookups below) are
- * uploaded once; creation is the only allocating call.  The hierarchy
- * belongs to the device current at creation; its plans must too. */
+ * The ghost-fill tables are built on the host and uploaded once: per box,
+ * the rectangles of its ghost cells that same-level interiors hold (under
+ * the periodic shifts), and on levels >= 1 the coarse parents of the other
+ * ghost cells with the coarse boxes holding their 7-cell stencils; also the
+ * coarse boxes under each fine box for restriction.  Creation is the only
+ * allocating call.  The hierarchy belongs to the device current at
+ * creation; its plans must too. */
 typedef struct ctu_hier ctu_hier;
 ctu_status ctu_hier_create(int32_t precision, int32_t base, int32_t nlev, const int32_t *level_nbox,
                            const ctu_box *boxes, int32_t nghost, ctu_hier **out);

@@ -4,16 +4,15 @@
 // (Eq. avgdown), for refinement ratio 2 in 3D.
 //
 // A level's state array holds one ghosted block per box, q[v][k][j][i] with
-// i fastest, at the box's element offset.  Every thread handles one cell.
-// Candidate lists, built on the host per box, name the boxes that can hold
-// a cell the thread looks up (same level: interiors meeting the box's
-// ghosted extent under the periodic shifts; coarse level: interiors meeting
-// the coarse stencil of its ghosts; for restriction: interiors meeting its
-// coarse footprint), so no search spans the whole level.
+// i fastest, at the box's element offset.  The ghost fill runs from copy and
+// parent tables built on the host (below); restriction looks up the coarse
+// box of each coarse cell in a candidate list built per fine box (the coarse
+// interiors meeting its footprint), so no search spans the whole level.
 #pragma once
 #include <hip/hip_runtime.h>
 
 #include "ctu_device.hpp"
+#include "ctu_kernels.hpp"
 
 namespace ctu {
 
@@ -46,28 +45,6 @@ __device__ __forceinline__ long long hidx(const HBox &b, int gi, int gj, int gk,
     return b.off + ((long long)(gk - b.lo[2] + ng) * b.N[1] + (gj - b.lo[1] + ng)) * b.N[0] + (gi - b.lo[0] + ng);
 }
 
-// Time-interpolated coarse state at the (wrapped) coarse cell (ci, cj, ck),
-// read from the interiors of the candidate coarse boxes; false if none holds it.
-template <typename R>
-__device__ __forceinline__ bool coarse_state(const HBox *cbox, const int *cand, int c0, int c1, int ci, int cj, int ck,
-                                             int ng, const R *Uo, const R *Un, R alpha, R *u)
-{
-    for (int e = c0; e < c1; e++) {
-        const HBox cb = cbox[cand[e]];
-        if (!holds(cb, ci, cj, ck)) continue;
-        const long long p = hidx(cb, ci, cj, ck, ng);
-        if (alpha == R(0)) {
-#pragma unroll
-            for (int q = 0; q < NV; q++) u[q] = Uo[p + q * cb.cells];
-        } else {
-#pragma unroll
-            for (int q = 0; q < NV; q++) u[q] = (R(1) - alpha) * Uo[p + q * cb.cells] + alpha * Un[p + q * cb.cells];
-        }
-        return true;
-    }
-    return false;
-}
-
 // monotonised central slope of the one-sided differences (same value as
 // minmod((dp + dm)/2, 2 minmod(dm, dp)))
 template <typename R> __device__ __forceinline__ R mc_slope(R dp, R dm)
@@ -77,144 +54,122 @@ template <typename R> __device__ __forceinline__ R mc_slope(R dp, R dm)
     return (dp * dm > R(0)) ? copysign(m, c) : R(0);
 }
 
-// Ghost cells of every box of one level that a same-level box interior
-// holds (periodic images included): copied.  On level 0 (cbox == nullptr),
-// whose boxes must cover the periodic domain, a ghost cell no box holds is
-// set to NaN and counted.  On finer levels the other ghost cells are left to
-// k_hprolong, unless `prolong` is set, which prolongs them here one cell per
-// thread (the same arithmetic as k_hprolong).
+// Ghost filling runs from tables built on the host when the hierarchy is
+// created, so no thread searches for the box that holds its source:
+//  * HCopy: a rectangle of a box's ghost cells that one same-level box
+//    interior holds (under one periodic shift), with its place in both
+//    boxes; every ghost cell of a level-0 box lies in exactly one;
+//  * HPar: on levels >= 1, a coarse parent cell of a box's ghosted extent
+//    with at least one child that is a ghost cell no same-level box holds
+//    (`mask`, bit x + 2y + 4z), the parent's wrapped coarse coordinates, the
+//    place of its first child in the box, and the coarse box whose interior
+//    holds the parent and its six face neighbours (-1 - m: they lie in
+//    several coarse boxes, listed as entry m of a table of seven box
+//    indices, parent first, then -x, +x, -y, +y, -z, +z; INT_MIN: one of them
+//    lies in no coarse interior, the children become NaN and are counted).
+struct HCopy {
+    int dst, src;  // box indices on the level
+    int dlo[3];    // first cell in the destination's ghosted coordinates
+    int slo[3];    // first cell in the source's ghosted coordinates
+    int ext[3];
+    int pad;
+};
+
+struct HPar {
+    int box;
+    int pc[3];     // parent, wrapped coarse-level coordinates
+    int f0[3];     // child (0, 0, 0) in the box's ghosted coordinates
+    int cbox;      // coarse box holding the 7-cell stencil, -1 - m, or HPAR_MISSING
+    unsigned mask; // children to write
+    int pad;
+};
+
+constexpr int HPAR_MISSING = -2147483647 - 1;
+
+// same-level ghost copies, one thread per cell of a copy rectangle
 template <typename R>
-__global__ __launch_bounds__(NT) void k_hfill(const HBox *box, const HTile *tiles, const int *nb_start,
-                                              const int *nb_list, const HBox *cbox, const int *cb_start,
-                                              const int *cb_list, int N, int ng, R *U, const R *Uo, const R *Un,
-                                              double alpha_d, int *missing, int prolong)
+__global__ __launch_bounds__(NT) void k_hcopy(const HBox *box, const HCopy *cp, const HTile *tiles, R *U)
 {
-    const HTile t = tiles[blockIdx.x];
-    const HBox b = box[t.box];
-    const long long li = (long long)t.start + threadIdx.x;
-    if (li >= b.cells) return;
-    const int i = (int)(li % b.N[0]), j = (int)((li / b.N[0]) % b.N[1]), k = (int)(li / ((long long)b.N[0] * b.N[1]));
-    if (i >= ng && i < ng + b.n[0] && j >= ng && j < ng + b.n[1] && k >= ng && k < ng + b.n[2]) return;
-    const int gi = wrapi(b.lo[0] + i - ng, N), gj = wrapi(b.lo[1] + j - ng, N), gk = wrapi(b.lo[2] + k - ng, N);
-    R *dst = U + b.off + li;
-    // same level
-    for (int e = nb_start[t.box]; e < nb_start[t.box + 1]; e++) {
-        const HBox c = box[nb_list[e]];
-        if (!holds(c, gi, gj, gk)) continue;
-        const long long p = hidx(c, gi, gj, gk, ng);
+    const HTile t = tiles[xcd_block(blockIdx.x, gridDim.x)];
+    const HCopy c = cp[t.box];
+    const int li = t.start + threadIdx.x;
+    if (li >= c.ext[0] * c.ext[1] * c.ext[2]) return;
+    const int x = li % c.ext[0], y = (li / c.ext[0]) % c.ext[1], z = li / (c.ext[0] * c.ext[1]);
+    const HBox D = box[c.dst], S = box[c.src];
+    const long long dp = D.off + ((long long)(c.dlo[2] + z) * D.N[1] + (c.dlo[1] + y)) * D.N[0] + (c.dlo[0] + x);
+    const long long sp = S.off + ((long long)(c.slo[2] + z) * S.N[1] + (c.slo[1] + y)) * S.N[0] + (c.slo[0] + x);
 #pragma unroll
-        for (int q = 0; q < NV; q++) dst[q * b.cells] = U[p + q * c.cells];
-        return;
+    for (int q = 0; q < NV; q++) U[dp + q * D.cells] = U[sp + q * S.cells];
+}
+
+// time-interpolated state of interior cell (ci, cj, ck) of coarse box cb
+template <typename R>
+__device__ __forceinline__ void coarse_at(const HBox &cb, int ci, int cj, int ck, int ng, const R *Uo, const R *Un,
+                                          R alpha, R *u)
+{
+    const long long p = hidx(cb, ci, cj, ck, ng);
+    if (alpha == R(0)) {
+#pragma unroll
+        for (int q = 0; q < NV; q++) u[q] = Uo[p + q * cb.cells];
+    } else {
+#pragma unroll
+        for (int q = 0; q < NV; q++) u[q] = (R(1) - alpha) * Uo[p + q * cb.cells] + alpha * Un[p + q * cb.cells];
     }
-    if (cbox != nullptr && !prolong) return;
-    bool ok = cbox != nullptr;
-    R out[NV];
-    if (ok) {
-        // Eq. prolong: parent value plus -+1/4 of the MC slope per direction
-        const int Nc = N / 2, c0 = cb_start[t.box], c1 = cb_start[t.box + 1];
-        const int pi = gi / 2, pj = gj / 2, pk = gk / 2;
-        const R alpha = R(alpha_d);
-        R u0[NV];
-        ok = coarse_state(cbox, cb_list, c0, c1, pi, pj, pk, ng, Uo, Un, alpha, u0);
-#pragma unroll
-        for (int q = 0; q < NV; q++) out[q] = u0[q];
+}
+
+// Eq. prolong for the ghost cells no same-level box holds, one thread per
+// listed coarse parent: the parent's time-interpolated state (Eq. intalpha)
+// and the MC slopes of its six face neighbours are formed once and give each
+// masked child u0 + sum_d (-+1/4) slope_d.  (One thread per parent and
+// variable, with fewer lines per wave, ran 1.6x slower: each thread re-reads
+// the parent's and the box's records.)
+template <typename R>
+__global__ __launch_bounds__(NT) void k_hprolong(const HBox *box, const HPar *par, int npar, const int *multi,
+                                                 const HBox *cbox, int N, int ng, R *U, const R *Uo, const R *Un,
+                                                 double alpha_d, int *missing)
+{
+    const int idx = xcd_block(blockIdx.x, gridDim.x) * NT + threadIdx.x;
+    if (idx >= npar) return;
+    const HPar P = par[idx];
+    const HBox b = box[P.box];
+    const int Nc = N / 2, pi = P.pc[0], pj = P.pc[1], pk = P.pc[2];
+    const R alpha = R(alpha_d);
+    const bool ok = P.cbox != HPAR_MISSING;
+    R u0[NV], sl[3][NV];
+    if (P.cbox >= 0) {
+        const HBox C = cbox[P.cbox];
+        coarse_at(C, pi, pj, pk, ng, Uo, Un, alpha, u0);
 #pragma unroll
         for (int d = 0; d < 3; d++) {
             R up[NV], dn[NV];
             const int di = (d == 0), dj = (d == 1), dk = (d == 2);
-            ok = ok && coarse_state(cbox, cb_list, c0, c1, wrapi(pi + di, Nc), wrapi(pj + dj, Nc), wrapi(pk + dk, Nc),
-                                    ng, Uo, Un, alpha, up);
-            ok = ok && coarse_state(cbox, cb_list, c0, c1, wrapi(pi - di, Nc), wrapi(pj - dj, Nc), wrapi(pk - dk, Nc),
-                                    ng, Uo, Un, alpha, dn);
-            const int f = (d == 0) ? gi : (d == 1 ? gj : gk);
-            const R off = (f & 1) ? R(0.25) : R(-0.25);
-            if (ok) {
+            coarse_at(C, wrapi(pi + di, Nc), wrapi(pj + dj, Nc), wrapi(pk + dk, Nc), ng, Uo, Un, alpha, up);
+            coarse_at(C, wrapi(pi - di, Nc), wrapi(pj - dj, Nc), wrapi(pk - dk, Nc), ng, Uo, Un, alpha, dn);
 #pragma unroll
-                for (int q = 0; q < NV; q++) out[q] += off * mc_slope(up[q] - u0[q], u0[q] - dn[q]);
-            }
+            for (int q = 0; q < NV; q++) sl[d][q] = mc_slope(up[q] - u0[q], u0[q] - dn[q]);
         }
-    }
-    if (!ok) {
-#pragma unroll
-        for (int q = 0; q < NV; q++) out[q] = R(NAN);
-        if (missing) atomicAdd(missing, 1);
-    }
-#pragma unroll
-    for (int q = 0; q < NV; q++) dst[q * b.cells] = out[q];
-}
-
-// Eq. prolong for the ghost cells of the boxes of a level >= 1 that no
-// same-level box interior holds, one thread per coarse parent cell of a
-// box's ghosted extent: the parent's time-interpolated state (Eq. intalpha)
-// and the MC slopes of its six face neighbours are formed once and give
-// all of its children that are such ghost cells (up to eight; the same
-// arithmetic per child as the one-cell-per-thread form of k_hfill).  A
-// parent whose stencil leaves the coarse interiors sets its children to NaN
-// and counts them.
-__device__ __forceinline__ int floor_half(int a) { return (a >= 0) ? a / 2 : -((1 - a) / 2); }
-
-template <typename R>
-__global__ __launch_bounds__(NT) void k_hprolong(const HBox *box, const HTile *tiles, const int *nb_start,
-                                                 const int *nb_list, const HBox *cbox, const int *cb_start,
-                                                 const int *cb_list, int N, int ng, R *U, const R *Uo, const R *Un,
-                                                 double alpha_d, int *missing)
-{
-    const HTile t = tiles[blockIdx.x];
-    const HBox b = box[t.box];
-    int p0[3], pe[3];
-#pragma unroll
-    for (int d = 0; d < 3; d++) {
-        p0[d] = floor_half(b.lo[d] - ng);
-        pe[d] = floor_half(b.lo[d] + b.n[d] + ng - 1) - p0[d] + 1;
-    }
-    const long long li = (long long)t.start + threadIdx.x;
-    if (li >= (long long)pe[0] * pe[1] * pe[2]) return;
-    const int pu[3] = { p0[0] + (int)(li % pe[0]), p0[1] + (int)((li / pe[0]) % pe[1]),
-                        p0[2] + (int)(li / ((long long)pe[0] * pe[1])) };
-    // the children that are ghost cells of b and that no same-level box holds
-    unsigned mask = 0;
-    for (int c8 = 0; c8 < 8; c8++) {
-        int loc[3];
-        bool ghost = false, inside = true;
+    } else if (ok) {
+        // the coarse boxes of the parent and of its -x, +x, -y, +y, -z, +z
+        // neighbours, a row of the multi table
+        const int *ob = multi + 7 * (-1 - P.cbox);
+        coarse_at(cbox[ob[0]], pi, pj, pk, ng, Uo, Un, alpha, u0);
 #pragma unroll
         for (int d = 0; d < 3; d++) {
-            loc[d] = 2 * pu[d] + ((c8 >> d) & 1) - b.lo[d] + ng;
-            inside = inside && loc[d] >= 0 && loc[d] < b.N[d];
-            ghost = ghost || loc[d] < ng || loc[d] >= ng + b.n[d];
-        }
-        if (!inside || !ghost) continue;
-        const int gi = wrapi(b.lo[0] + loc[0] - ng, N), gj = wrapi(b.lo[1] + loc[1] - ng, N),
-                  gk = wrapi(b.lo[2] + loc[2] - ng, N);
-        bool same = false;
-        for (int e = nb_start[t.box]; e < nb_start[t.box + 1] && !same; e++) same = holds(box[nb_list[e]], gi, gj, gk);
-        if (!same) mask |= 1u << c8;
-    }
-    if (!mask) return;
-    const int Nc = N / 2, c0 = cb_start[t.box], c1 = cb_start[t.box + 1];
-    const int pi = wrapi(pu[0], Nc), pj = wrapi(pu[1], Nc), pk = wrapi(pu[2], Nc);
-    const R alpha = R(alpha_d);
-    R u0[NV], sl[3][NV];
-    bool ok = coarse_state(cbox, cb_list, c0, c1, pi, pj, pk, ng, Uo, Un, alpha, u0);
-#pragma unroll
-    for (int d = 0; d < 3; d++) {
-        R up[NV], dn[NV];
-        const int di = (d == 0), dj = (d == 1), dk = (d == 2);
-        ok = ok && coarse_state(cbox, cb_list, c0, c1, wrapi(pi + di, Nc), wrapi(pj + dj, Nc), wrapi(pk + dk, Nc), ng,
-                                Uo, Un, alpha, up);
-        ok = ok && coarse_state(cbox, cb_list, c0, c1, wrapi(pi - di, Nc), wrapi(pj - dj, Nc), wrapi(pk - dk, Nc), ng,
-                                Uo, Un, alpha, dn);
-        if (ok) {
+            R up[NV], dn[NV];
+            const int di = (d == 0), dj = (d == 1), dk = (d == 2);
+            coarse_at(cbox[ob[2 + 2 * d]], wrapi(pi + di, Nc), wrapi(pj + dj, Nc), wrapi(pk + dk, Nc), ng, Uo, Un, alpha,
+                      up);
+            coarse_at(cbox[ob[1 + 2 * d]], wrapi(pi - di, Nc), wrapi(pj - dj, Nc), wrapi(pk - dk, Nc), ng, Uo, Un, alpha,
+                      dn);
 #pragma unroll
             for (int q = 0; q < NV; q++) sl[d][q] = mc_slope(up[q] - u0[q], u0[q] - dn[q]);
         }
     }
     for (int c8 = 0; c8 < 8; c8++) {
-        if (!(mask & (1u << c8))) continue;
-        const long long li2 =
-            ((long long)(2 * pu[2] + ((c8 >> 2) & 1) - b.lo[2] + ng) * b.N[1] + (2 * pu[1] + ((c8 >> 1) & 1) - b.lo[1] + ng)) *
-                b.N[0] +
-            (2 * pu[0] + (c8 & 1) - b.lo[0] + ng);
-        R *dst = U + b.off + li2;
+        if (!(P.mask & (1u << c8))) continue;
+        const long long li =
+            ((long long)(P.f0[2] + ((c8 >> 2) & 1)) * b.N[1] + (P.f0[1] + ((c8 >> 1) & 1))) * b.N[0] + P.f0[0] + (c8 & 1);
+        R *dst = U + b.off + li;
         R out[NV];
         if (ok) {
 #pragma unroll

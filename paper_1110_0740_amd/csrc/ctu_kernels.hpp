@@ -28,6 +28,18 @@ namespace ctu {
 
 constexpr int NT = 256;  // threads per block
 
+// Block index in an XCD-contiguous order for launches whose consecutive
+// blocks touch neighbouring data: the dispatcher sends block b to XCD b % 8
+// (each XCD with its own L2), so block b works on item x * q + min(x, r) +
+// b / 8 of the n blocks' list, x = b % 8, q = n / 8, r = n % 8: every XCD
+// takes a contiguous run (the order the host gives the tile tables).
+__device__ __forceinline__ int xcd_block(int b, int n)
+{
+    if (n < 16) return b;
+    const int x = b & 7, q = n >> 3, r = n & 7;
+    return x * q + (x < r ? x : r) + (b >> 3);
+}
+
 struct KBox {
     int N[3];      // ghosted extents (N[2] = 1 in 2D)
     int n[3];      // interior extents
@@ -1257,6 +1269,7 @@ struct KRefl {
     int box, i, j, k, dir, side, nfine, pad;
     long long cslot;
     long long fslot[4];
+    double scale;  // -side / (face area) / dx_dir of the coarse box (set on the host)
 };
 
 // With consume != 0 the register slots read are cleared afterwards: each
@@ -1265,29 +1278,34 @@ template <typename R>
 __global__ __launch_bounds__(NT) void k_reflux(const KBox *boxes, const KRefl *ent, const int *cell_start, int ncell,
                                                R *U, double *reg, int consume)
 {
-    int cidx_ = blockIdx.x * NT + threadIdx.x;
-    if (cidx_ >= ncell) return;
-    int e0 = cell_start[cidx_], e1 = cell_start[cidx_ + 1];
-    KRefl first = ent[e0];
+    const int cid = xcd_block(blockIdx.x, gridDim.x) * NT + threadIdx.x;
+    if (cid >= ncell) return;
+    const int e0 = cell_start[cid], e1 = cell_start[cid + 1];
+    const KRefl first = ent[e0];
     const KBox &bx = boxes[first.box];
-    int c = cidx(bx, first.i, first.j, first.k);
+    const int c = cidx(bx, first.i, first.j, first.k);
     double du[NV];
 #pragma unroll
     for (int q = 0; q < NV; q++) du[q] = 0.0;
     for (int e = e0; e < e1; e++) {
-        KRefl en = ent[e];
-        double idx = 1.0 / bx.dx[en.dir];
+        const KRefl en = ent[e];
+        // sum of the fine registers (slots in table order), fully unrolled so
+        // that no slot index is taken from a run-time position in the entry
+        double fine[NV];
 #pragma unroll
-        for (int q = 0; q < NV; q++) {
-            double fine = 0.0;
-            for (int f = 0; f < en.nfine; f++) fine += reg[9 * en.fslot[f] + q];
-            double delta = fine - reg[9 * en.cslot + q];
-            // reg holds dt*A*F; A/V = 1/dx on a Cartesian level
-            double area = 1.0;
-            for (int d = 0; d < 3; d++)
-                if (d != en.dir && bx.n[d] > 0 && !(d == 2 && bx.N[2] == 1)) area *= bx.dx[d];
-            du[q] += -(double)en.side * delta / area * idx;
+        for (int q = 0; q < NV; q++) fine[q] = 0.0;
+#pragma unroll
+        for (int f = 0; f < 4; f++) {
+            if (f < en.nfine) {
+                const double *r = reg + 9 * en.fslot[f];
+#pragma unroll
+                for (int q = 0; q < NV; q++) fine[q] += r[q];
+            }
         }
+        // reg holds dt*A*F; A/V = 1/dx on a Cartesian level
+        const double *rc = reg + 9 * en.cslot;
+#pragma unroll
+        for (int q = 0; q < NV; q++) du[q] += en.scale * (fine[q] - rc[q]);
     }
 #pragma unroll
     for (int q = 0; q < NV; q++) {
@@ -1296,11 +1314,15 @@ __global__ __launch_bounds__(NT) void k_reflux(const KBox *boxes, const KRefl *e
     }
     if (consume) {
         for (int e = e0; e < e1; e++) {
-            KRefl en = ent[e];
+            const KRefl en = ent[e];
 #pragma unroll
-            for (int q = 0; q < NV; q++) {
-                reg[9 * en.cslot + q] = 0.0;
-                for (int f = 0; f < en.nfine; f++) reg[9 * en.fslot[f] + q] = 0.0;
+            for (int q = 0; q < NV; q++) reg[9 * en.cslot + q] = 0.0;
+#pragma unroll
+            for (int f = 0; f < 4; f++) {
+                if (f < en.nfine) {
+#pragma unroll
+                    for (int q = 0; q < NV; q++) reg[9 * en.fslot[f] + q] = 0.0;
+                }
             }
         }
     }

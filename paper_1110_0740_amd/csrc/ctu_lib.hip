@@ -1213,6 +1213,13 @@ static ctu_status set_reflux_table(ctu_plan *plan, const ctu_refluxface *faces, 
             r.pad = 0;
             r.cslot = f.coarse_slot;
             for (int q = 0; q < 4; q++) r.fslot[q] = (q < f.nfine) ? f.fine_slot[q] : 0;
+            // the correction per unit of register difference: -side / (face
+            // area) / dx_dir (the register holds dt A F; A / V = 1 / dx_dir)
+            const KBox &bx = plan->hboxes[f.box];
+            double area = 1.0;
+            for (int d = 0; d < 3; d++)
+                if (d != f.dir && bx.n[d] > 0 && !(d == 2 && bx.N[2] == 1)) area *= bx.dx[d];
+            r.scale = -(double)f.side / area * (1.0 / bx.dx[f.dir]);
             ents.push_back(r);
         }
     }
@@ -1366,11 +1373,16 @@ struct HierLevel {
     int N = 0;  // cells per side of the periodic level
     std::vector<HBox> hb;
     std::vector<int> nb_start, nb_list, cb_start, cb_list, pb_start, pb_list, ch_start, ch_list;
-    std::vector<HTile> fill_t, avg_t, prol_t;  // prol_t: coarse parents of each box's ghosted extent
+    std::vector<HTile> fill_t, avg_t, copy_t;
+    std::vector<HCopy> copies;  // same-level ghost copy rectangles
+    std::vector<HPar> pars;     // coarse parents of ghosts to prolong (levels >= 1)
+    std::vector<int> multi;     // seven coarse boxes per parent whose stencil spans several
     HBox *db = nullptr;
-    int *d_nb_start = nullptr, *d_nb_list = nullptr, *d_cb_start = nullptr, *d_cb_list = nullptr;
     int *d_pb_start = nullptr, *d_pb_list = nullptr, *d_ch_start = nullptr, *d_ch_list = nullptr;
-    HTile *d_fill_t = nullptr, *d_avg_t = nullptr, *d_prol_t = nullptr;
+    HTile *d_fill_t = nullptr, *d_avg_t = nullptr, *d_copy_t = nullptr;
+    HCopy *d_copies = nullptr;
+    HPar *d_pars = nullptr;
+    int *d_multi = nullptr;
 };
 
 int floor_div(int a, int b) { return (a >= 0) ? a / b : -((-a + b - 1) / b); }
@@ -1425,8 +1437,9 @@ void free_hier(ctu_hier *h)
     if (!h) return;
     DevGuard g(h->dev);
     for (HierLevel &L : h->lev) {
-        void *ptrs[] = { L.db, L.d_nb_start, L.d_nb_list, L.d_cb_start, L.d_cb_list, L.d_pb_start, L.d_pb_list,
-                         L.d_ch_start, L.d_ch_list, L.d_fill_t, L.d_avg_t, L.d_prol_t };
+        void *ptrs[] = { L.db, L.d_pb_start, L.d_pb_list,
+                         L.d_ch_start, L.d_ch_list, L.d_fill_t, L.d_avg_t, L.d_copy_t, L.d_copies, L.d_pars,
+                         L.d_multi };
         for (void *q : ptrs)
             if (q) (void)hipFree(q);
     }
@@ -1434,28 +1447,154 @@ void free_hier(ctu_hier *h)
     delete h;
 }
 
+bool holds_h(const HBox &b, int i, int j, int k)
+{
+    return i >= b.lo[0] && i < b.lo[0] + b.n[0] && j >= b.lo[1] && j < b.lo[1] + b.n[1] && k >= b.lo[2] &&
+           k < b.lo[2] + b.n[2];
+}
+
+int wrap_h(int a, int n)
+{
+    int r = a % n;
+    return r < 0 ? r + n : r;
+}
+
+// The ghost-fill tables of one level (after its candidate lists): for each
+// box, the rectangles of its ghosted extent that a same-level interior holds
+// under a periodic shift, and on levels >= 1 the coarse parents of the ghost
+// cells left over, each with its child mask and the coarse box that holds
+// its whole 7-cell stencil (-1: several boxes, -2: not all held).
+ctu_status build_fill_tables(ctu_hier *h, int l)
+{
+    HierLevel &L = h->lev[l];
+    const int g = h->ng, N = L.N;
+    for (int b = 0; b < (int)L.hb.size(); b++) {
+        const HBox &B = L.hb[b];
+        int lo[3], hi[3];
+        for (int d = 0; d < 3; d++) {
+            lo[d] = B.lo[d] - g;
+            hi[d] = B.lo[d] + B.n[d] + g;
+        }
+        std::vector<unsigned char> cov((size_t)B.cells, 0);
+        auto at = [&](int x, int y, int z) -> unsigned char & {
+            return cov[((size_t)z * B.N[1] + y) * B.N[0] + x];
+        };
+        for (int z = g; z < g + B.n[2]; z++)
+            for (int y = g; y < g + B.n[1]; y++)
+                for (int x = g; x < g + B.n[0]; x++) at(x, y, z) = 1;
+        // every periodic image of every candidate (all boxes of the level when
+        // the ghost width reaches past the neighbouring images)
+        const bool all = N <= 2 * g;
+        const int ne = all ? (int)L.hb.size() : L.nb_start[b + 1] - L.nb_start[b];
+        for (int e = 0; e < ne; e++) {
+            const int c = all ? e : L.nb_list[L.nb_start[b] + e];
+            const HBox &C = L.hb[c];
+            int k0[3], k1[3];
+            for (int d = 0; d < 3; d++) {
+                k0[d] = floor_div(lo[d] - (C.lo[d] + C.n[d]), N) + 1;
+                k1[d] = floor_div(hi[d] - 1 - C.lo[d], N);
+            }
+            for (int kz = k0[2]; kz <= k1[2]; kz++)
+                for (int ky = k0[1]; ky <= k1[1]; ky++)
+                    for (int kx = k0[0]; kx <= k1[0]; kx++) {
+                        if (c == b && kx == 0 && ky == 0 && kz == 0) continue;
+                        const int sh[3] = { kx * N, ky * N, kz * N };
+                        HCopy cp{};
+                        bool empty = false;
+                        for (int d = 0; d < 3 && !empty; d++) {
+                            const int a0 = std::max(lo[d], C.lo[d] + sh[d]);
+                            const int a1 = std::min(hi[d], C.lo[d] + C.n[d] + sh[d]);
+                            empty = a1 <= a0;
+                            cp.dlo[d] = a0 - lo[d];
+                            cp.slo[d] = a0 - sh[d] - (C.lo[d] - g);
+                            cp.ext[d] = a1 - a0;
+                        }
+                        if (empty) continue;
+                        cp.dst = b;
+                        cp.src = c;
+                        for (int z = 0; z < cp.ext[2]; z++)
+                            for (int y = 0; y < cp.ext[1]; y++)
+                                for (int x = 0; x < cp.ext[0]; x++) {
+                                    unsigned char &m = at(cp.dlo[0] + x, cp.dlo[1] + y, cp.dlo[2] + z);
+                                    if (m) return fail(CTU_ERR_ARG, "same-level boxes overlap under the periodic shifts");
+                                    m = 1;
+                                }
+                        const int ncell = cp.ext[0] * cp.ext[1] * cp.ext[2];
+                        const int id = (int)L.copies.size();
+                        L.copies.push_back(cp);
+                        for (int s0 = 0; s0 < ncell; s0 += NT) L.copy_t.push_back(HTile{ id, s0 });
+                    }
+        }
+        if (l == 0) {
+            for (unsigned char m : cov)
+                if (!m) return fail(CTU_ERR_ARG, "a level-0 ghost cell lies in no box (level 0 must cover the domain)");
+            continue;
+        }
+        const HierLevel &Cl = h->lev[l - 1];
+        const int Nc = N / 2;
+        int p0[3], p1[3];
+        for (int d = 0; d < 3; d++) {
+            p0[d] = floor_div(lo[d], 2);
+            p1[d] = floor_div(hi[d] - 1, 2);
+        }
+        for (int pz = p0[2]; pz <= p1[2]; pz++)
+            for (int py = p0[1]; py <= p1[1]; py++)
+                for (int px = p0[0]; px <= p1[0]; px++) {
+                    HPar P{};
+                    P.box = b;
+                    const int pu[3] = { px, py, pz };
+                    for (int d = 0; d < 3; d++) P.f0[d] = 2 * pu[d] - lo[d];
+                    for (int c8 = 0; c8 < 8; c8++) {
+                        const int x = P.f0[0] + (c8 & 1), y = P.f0[1] + ((c8 >> 1) & 1), z = P.f0[2] + ((c8 >> 2) & 1);
+                        if (x < 0 || y < 0 || z < 0 || x >= B.N[0] || y >= B.N[1] || z >= B.N[2]) continue;
+                        if (!at(x, y, z)) P.mask |= 1u << c8;
+                    }
+                    if (!P.mask) continue;
+                    for (int d = 0; d < 3; d++) P.pc[d] = wrap_h(pu[d], Nc);
+                    // the coarse boxes of the parent and its six face
+                    // neighbours (-x, +x, -y, +y, -z, +z)
+                    int ob[7];
+                    bool held_all = true, one = true;
+                    for (int t = 0; t < 7 && held_all; t++) {
+                        int q[3] = { P.pc[0], P.pc[1], P.pc[2] };
+                        if (t > 0) q[(t - 1) / 2] = wrap_h(q[(t - 1) / 2] + ((t & 1) ? -1 : 1), Nc);
+                        ob[t] = -1;
+                        for (int e = L.cb_start[b]; e < L.cb_start[b + 1] && ob[t] < 0; e++)
+                            if (holds_h(Cl.hb[L.cb_list[e]], q[0], q[1], q[2])) ob[t] = L.cb_list[e];
+                        held_all = ob[t] >= 0;
+                        one = one && held_all && ob[t] == ob[0];
+                    }
+                    if (!held_all) {
+                        P.cbox = HPAR_MISSING;
+                    } else if (one) {
+                        P.cbox = ob[0];
+                    } else {
+                        P.cbox = -1 - (int)(L.multi.size() / 7);
+                        L.multi.insert(L.multi.end(), ob, ob + 7);
+                    }
+                    L.pars.push_back(P);
+                }
+    }
+    return CTU_OK;
+}
+
 template <typename R>
 ctu_status hier_fill(ctu_hier *h, int level, void *U, const void *Uo, const void *Un, double alpha, int32_t *missing,
                      hipStream_t s)
 {
     HierLevel &L = h->lev[level];
-    if (L.fill_t.empty()) return CTU_OK;
-    const HBox *cbox = nullptr;
-    const int *cbs = nullptr, *cbl = nullptr;
-    if (level > 0) {
-        cbox = h->lev[level - 1].db;
-        cbs = L.d_cb_start;
-        cbl = L.d_cb_list;
+    // same-level copies (and, on level 0, the periodic images), then on
+    // finer levels the remaining ghosts, prolonged one coarse parent per
+    // thread; the two write disjoint cells and read no cell the other writes
+    if (!L.copy_t.empty()) {
+        hipLaunchKernelGGL((k_hcopy<R>), dim3((unsigned)L.copy_t.size()), dim3(NT), 0, s, L.db, L.d_copies,
+                           L.d_copy_t, (R *)U);
+        HIP_TRY(hipGetLastError());
     }
-    // same-level copies (and, on level 0, the periodic images); on finer
-    // levels the remaining ghosts are prolonged one coarse parent per thread
-    hipLaunchKernelGGL((k_hfill<R>), dim3((unsigned)L.fill_t.size()), dim3(NT), 0, s, L.db, L.d_fill_t,
-                       L.d_nb_start, L.d_nb_list, cbox, cbs, cbl, L.N, h->ng, (R *)U, (const R *)Uo,
-                       (const R *)(Un ? Un : Uo), alpha, (int *)missing, 0);
-    HIP_TRY(hipGetLastError());
-    if (level > 0 && !L.prol_t.empty()) {
-        hipLaunchKernelGGL((k_hprolong<R>), dim3((unsigned)L.prol_t.size()), dim3(NT), 0, s, L.db, L.d_prol_t,
-                           L.d_nb_start, L.d_nb_list, cbox, cbs, cbl, L.N, h->ng, (R *)U, (const R *)Uo,
+    if (level > 0 && !L.pars.empty()) {
+        const unsigned nb = (unsigned)((L.pars.size() + NT - 1) / NT);
+        hipLaunchKernelGGL((k_hprolong<R>), dim3(nb), dim3(NT), 0, s, L.db, L.d_pars, (int)L.pars.size(),
+                           L.d_multi, h->lev[level - 1].db, L.N, h->ng, (R *)U, (const R *)Uo,
                            (const R *)(Un ? Un : Uo), alpha, (int *)missing);
         HIP_TRY(hipGetLastError());
     }
@@ -1636,12 +1775,15 @@ ctu_status ctu_hier_create(int32_t precision, int32_t base, int32_t nlev, const 
             if (l > 0) {
                 long long fc = (long long)(B.n[0] / 2) * (B.n[1] / 2) * (B.n[2] / 2);
                 for (long long s0 = 0; s0 < fc; s0 += NT) L.avg_t.push_back(HTile{ b, (int)s0 });
-                // coarse parents of the ghosted extent (k_hprolong)
-                long long pc = 1;
-                for (int d = 0; d < 3; d++)
-                    pc *= floor_div(B.lo[d] + B.n[d] + nghost - 1, 2) - floor_div(B.lo[d] - nghost, 2) + 1;
-                for (long long s0 = 0; s0 < pc; s0 += NT) L.prol_t.push_back(HTile{ b, (int)s0 });
             }
+        }
+    }
+    // ghost-fill tables
+    for (int l = 0; l < nlev; l++) {
+        ctu_status st = build_fill_tables(h, l);
+        if (st != CTU_OK) {
+            free_hier(h);
+            return st;
         }
     }
     // children: boxes of the next finer level whose footprint meets each box
@@ -1668,11 +1810,10 @@ ctu_status ctu_hier_create(int32_t precision, int32_t base, int32_t nlev, const 
             free_hier(h);
             return st;
         }
-        if ((st = upload(L.hb, &L.db)) != CTU_OK || (st = upload(L.nb_start, &L.d_nb_start)) != CTU_OK ||
-            (st = upload(L.nb_list, &L.d_nb_list)) != CTU_OK || (st = upload(L.cb_start, &L.d_cb_start)) != CTU_OK ||
-            (st = upload(L.cb_list, &L.d_cb_list)) != CTU_OK || (st = upload(L.pb_start, &L.d_pb_start)) != CTU_OK ||
+        if ((st = upload(L.hb, &L.db)) != CTU_OK || (st = upload(L.pb_start, &L.d_pb_start)) != CTU_OK ||
             (st = upload(L.pb_list, &L.d_pb_list)) != CTU_OK || (st = upload(L.fill_t, &L.d_fill_t)) != CTU_OK ||
-            (st = upload(L.prol_t, &L.d_prol_t)) != CTU_OK ||
+            (st = upload(L.copy_t, &L.d_copy_t)) != CTU_OK || (st = upload(L.copies, &L.d_copies)) != CTU_OK ||
+            (st = upload(L.pars, &L.d_pars)) != CTU_OK || (st = upload(L.multi, &L.d_multi)) != CTU_OK ||
             (st = upload(L.avg_t, &L.d_avg_t)) != CTU_OK) {
             free_hier(h);
             return st;
