@@ -385,6 +385,17 @@ def c2_variants(args, dev, s, U64, ins, params, b, dx, gamma, samples):
     return out
 
 
+def leg_peaks():
+    """The rates this build reaches on the device (library kernels): FP32 and
+    FP64 FMA chains, and a float4 device copy of 2 GiB."""
+    from paper_1110_0740_amd import ctu
+
+    log("peaks: FMA chains and device copy")
+    return {"valu_fp32_fma_TFLOPs": ctu.measure_fma("fp32"), "valu_fp64_fma_TFLOPs": ctu.measure_fma("fp64"),
+            "hbm_copy_GBs": ctu.measure_copy(2 << 30),
+            "note": "FP32 as every kernel of this build: single-lane FMAs, no packed FP32"}
+
+
 def leg_c1(args, dev, s, samples):
     """2D 128^2 FP64, 10 CTU steps at CFL 0.4: timed as repeated steps (eager
     and graph); the L1 figure compares 10 chained steps (GPU ghosts refilled
@@ -520,8 +531,11 @@ def leg_c5(args, dev, s, samples):
     T = V[4] / V[0]
     tc = I.cooling_time_field_torch(5002, n, NG, dt0, device=dev)
     L0 = (V[4] / ((G - 1) * V[0] ** 2 * torch.sqrt(T) * tc)).reshape(-1).contiguous()
+    # the white-noise variant: t_c / dt0 log-uniform in [1e-3, 1e3], independent per cell
+    tcw = torch.from_numpy(I.cooling_time_white(5003, n, NG, dt0)).to(dev)
+    L0w = (V[4] / ((G - 1) * V[0] ** 2 * torch.sqrt(T) * tcw)).reshape(-1).contiguous()
     Tfl = 0.1 * float(T.min())
-    del V, T, tc, hyp
+    del V, T, tc, tcw, hyp
     okw = dict(recon="ppm", riemann="hlld", parabolic_mask=7, tc_phi=0.3, cooling=True, cool_beta=0.5,
                T_floor=Tfl, **coef)
     p64 = ctu.Plan(ctu.make_opts(dim=3, gamma=G, dx=dx, precision="fp64", **okw), box, NG)
@@ -538,6 +552,12 @@ def leg_c5(args, dev, s, samples):
     r32 = result(ms, zones, abz32, per, p32.get_shape()[0])
     r32["roofline"] = kernel_roofline("C5", per, zones, "f32")
     r32["max_dp_over_p"] = b.dpp.item()
+    log("C5: FP32 batched, white-noise cooling times")
+    L32w = L0w.to(torch.float32)
+    Uo32w = torch.empty_like(U32)
+    msw, perw = run_plan(p32, U32, Uo32w, params, b, K, W, s, L0=L32w)
+    r32w = result(msw, zones, abz32, perw, p32.get_shape()[0])
+    r32w["max_dp_over_p"] = b.dpp.item()
     log("C5: FP64 plain (eager)")
     Uo64 = torch.empty_like(U64)
     ms64, per64 = run_plan(p64, U64, Uo64, params, b, K, W, s, L0=L0, graph=False)
@@ -546,7 +566,10 @@ def leg_c5(args, dev, s, samples):
     L0s32 = [subbox_cells(L32, N, lo, 16) for lo in org]
     samples.add("c5_fp32", okw, dx, dt, ch, ins, [subbox(Uo32, N, lo, 16, 3) for lo in org], L0s=L0s32)
     samples.add("c5_fp64", okw, dx, dt, ch, ins, [subbox(Uo64, N, lo, 16, 3) for lo in org], L0s=L0s64)
-    return {"fp32_batched": r32, "fp64_plain": r64, "zones": zones, "coefficients": coef}
+    samples.add("c5_white_fp32", okw, dx, dt, ch, ins, [subbox(Uo32w, N, lo, 16, 3) for lo in org],
+                L0s=[subbox_cells(L32w, N, lo, 16) for lo in org])
+    return {"fp32_batched": r32, "fp32_batched_white_tc": r32w, "fp64_plain": r64, "zones": zones,
+            "coefficients": coef}
 
 
 def leg_c3(args, dev, s, samples):
@@ -862,6 +885,7 @@ def main():
     legs = set(args.legs.split(","))
     samples = Samples()
     line_legs = {}
+    peaks = leg_peaks()
     variants = {}
     c2 = timing_boxes = c2p = None
     if "c2" in legs:
@@ -883,7 +907,7 @@ def main():
         line_legs["c3_amr"] = leg_c3(args, dev, s, samples)
         torch.cuda.empty_cache()
     if c2 is None:
-        print(json.dumps({"legs": line_legs, "variants": variants}), flush=True)
+        print(json.dumps({"legs": line_legs, "variants": variants, "measured_peaks": peaks}), flush=True)
         return
     res = c2["fp32_batched"]
     K, W = args.steps, args.warmup
@@ -893,6 +917,8 @@ def main():
             res["shape"][f] == PROFILE_SHAPE[f] for f in PROFILE_SHAPE)
         roof["traffic"] = TCOUPLE_TRAFFIC_BYTES if (same and roof["kernel"] == "tcouple") else None
         roof["shape"] = res.get("shape")
+        if roof.get("achieved"):
+            roof["frac_of_measured_fma"] = roof["achieved"] / peaks["valu_fp32_fma_TFLOPs"]
     line = {
         "metric": METRIC,
         "value": res["zone_updates_per_s"],
@@ -910,8 +936,10 @@ def main():
                                "CFL 0.4, seeded smooth random modes (beta~1, Mach~1), 20 steps",
                    "zones": c2["zones"], "nghost": NG, "path": "fp32_batched"},
         "hbm_step": {"bound": "hbm", "achieved": res["hbm_alg_GBs"], "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": res["hbm_frac"], "alg_bytes_per_zone": res["alg_bytes_per_zone"]},
+                     "frac": res["hbm_frac"], "alg_bytes_per_zone": res["alg_bytes_per_zone"],
+                     "frac_of_measured_copy": res["hbm_alg_GBs"] / peaks["hbm_copy_GBs"]},
         "roofline": roof,
+        "measured_peaks": peaks,
         "paths": {"fp32_batched": res, "fp64_plain": c2["fp64_plain"]},
         "fp32_over_fp64": res["zone_updates_per_s"] / c2["fp64_plain"]["zone_updates_per_s"],
         "legs": line_legs,
@@ -937,6 +965,7 @@ def attach_l1(line, l1):
         where["c4_rmhd192_ideal_fp64"] = legs["c4_rmhd_192"]["fp64_plain"]
     if "c5_nonideal_256" in legs:
         where["c5_fp32"] = legs["c5_nonideal_256"]["fp32_batched"]
+        where["c5_white_fp32"] = legs["c5_nonideal_256"]["fp32_batched_white_tc"]
         where["c5_fp64"] = legs["c5_nonideal_256"]["fp64_plain"]
     if "c3_amr" in legs:
         for lev, rl in enumerate(legs["c3_amr"]["fp32_batched"]["levels"]):

@@ -482,6 +482,21 @@ ctu_status ctu_hier_advance(ctu_hier *hier, ctu_plan *const *plans, void *const 
 ctu_status ctu_plan_enable_timing(ctu_plan *plan, int32_t enable);
 ctu_status ctu_plan_read_timing(ctu_plan *plan, double *ms_out, int32_t *nsteps_out);
 
+/* Measurement helpers (not part of the step): the rates this build reaches
+ * on the current device, for quoting roofline fractions against measured as
+ * well as published peaks.  Both launch on the null stream and synchronise;
+ * they create two HIP events (no device allocation).
+ * ctu_measure_fma: nblocks x 256 threads, each running eight independent FMA
+ * chains for iters x 16 steps (FP32: single-lane FMAs, as every kernel of
+ * this build, which emits no packed FP32); out_dev holds nblocks * 256
+ * elements of the precision (written, values meaningless); *tflops_out =
+ * 2 FLOP per FMA over the timed launches.
+ * ctu_measure_copy: a float4 device-to-device copy of `bytes` (a multiple of
+ * 16) from src_dev to dst_dev, ten timed launches; *gbs_out = bytes read plus
+ * bytes written per second, in GB/s. */
+ctu_status ctu_measure_fma(int32_t precision, int32_t nblocks, int32_t iters, void *out_dev, double *tflops_out);
+ctu_status ctu_measure_copy(const void *src_dev, void *dst_dev, int64_t bytes, double *gbs_out);
+
 const char *ctu_last_error(void);
 
 #ifdef __cplusplus

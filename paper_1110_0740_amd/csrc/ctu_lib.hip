@@ -1931,3 +1931,104 @@ ctu_status ctu_hier_next_dt(ctu_hier *h, const double *rate_dev, const double *d
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Measurement helpers: the rates this build can reach on the device, timed
+// with HIP events (the roofline fractions are quoted against them beside the
+// published peaks).
+// ---------------------------------------------------------------------------
+
+namespace {
+
+// eight independent FMA chains per lane, 16 steps per iteration; the chains
+// converge to c / (1 - b) and their sum is stored so that none is removed
+template <typename R>
+__global__ __launch_bounds__(NT) void k_fma_peak(R *out, int iters, R b, R c)
+{
+    R a0 = R(threadIdx.x) * R(1e-3), a1 = a0 + R(1), a2 = a0 + R(2), a3 = a0 + R(3), a4 = a0 + R(4),
+      a5 = a0 + R(5), a6 = a0 + R(6), a7 = a0 + R(7);
+    for (int it = 0; it < iters; it++) {
+#pragma unroll
+        for (int u = 0; u < 16; u++) {
+            a0 = fma(a0, b, c);
+            a1 = fma(a1, b, c);
+            a2 = fma(a2, b, c);
+            a3 = fma(a3, b, c);
+            a4 = fma(a4, b, c);
+            a5 = fma(a5, b, c);
+            a6 = fma(a6, b, c);
+            a7 = fma(a7, b, c);
+        }
+    }
+    out[(size_t)blockIdx.x * NT + threadIdx.x] = ((a0 + a1) + (a2 + a3)) + ((a4 + a5) + (a6 + a7));
+}
+
+__global__ __launch_bounds__(NT) void k_copy_peak(const float4 *src, float4 *dst, long long n)
+{
+    for (long long k = (long long)blockIdx.x * NT + threadIdx.x; k < n; k += (long long)gridDim.x * NT) dst[k] = src[k];
+}
+
+// milliseconds of `reps` launches of f on the current device's null stream
+template <typename F> ctu_status time_launches(F f, int reps, double *ms)
+{
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(CTU_ERR_HIP, "hipEventCreate failed");
+    }
+    f();  // warm-up
+    hipError_t e = hipEventRecord(e0, nullptr);
+    for (int r = 0; r < reps && e == hipSuccess; r++) {
+        f();
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipEventRecord(e1, nullptr);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float t = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (e != hipSuccess) return fail(CTU_ERR_HIP, std::string("peak measurement: ") + hipGetErrorString(e));
+    *ms = t;
+    return CTU_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+ctu_status ctu_measure_fma(int32_t precision, int32_t nblocks, int32_t iters, void *out_dev, double *tflops_out)
+{
+    if ((precision != CTU_FP32 && precision != CTU_FP64) || nblocks < 1 || iters < 1 || !out_dev || !tflops_out)
+        return fail(CTU_ERR_ARG, "precision FP32 or FP64, nblocks >= 1, iters >= 1, out and tflops_out required");
+    const int reps = 5;
+    double ms = 0.0;
+    ctu_status st;
+    if (precision == CTU_FP32)
+        st = time_launches([&] { hipLaunchKernelGGL(k_fma_peak<float>, dim3(nblocks), dim3(NT), 0, nullptr,
+                                                    (float *)out_dev, iters, 0.999f, 1e-3f); }, reps, &ms);
+    else
+        st = time_launches([&] { hipLaunchKernelGGL(k_fma_peak<double>, dim3(nblocks), dim3(NT), 0, nullptr,
+                                                    (double *)out_dev, iters, 0.999, 1e-3); }, reps, &ms);
+    if (st != CTU_OK) return st;
+    const double flop = 2.0 * 8.0 * 16.0 * (double)iters * (double)nblocks * NT * reps;
+    *tflops_out = flop / (ms * 1e-3) / 1e12;
+    return CTU_OK;
+}
+
+ctu_status ctu_measure_copy(const void *src_dev, void *dst_dev, int64_t bytes, double *gbs_out)
+{
+    if (!src_dev || !dst_dev || bytes < 16 || (bytes & 15) || !gbs_out)
+        return fail(CTU_ERR_ARG, "src, dst and gbs_out required; bytes a positive multiple of 16");
+    const int reps = 10;
+    const long long n = bytes / 16;
+    double ms = 0.0;
+    ctu_status st = time_launches([&] { hipLaunchKernelGGL(k_copy_peak, dim3(256 * 16), dim3(NT), 0, nullptr,
+                                                           (const float4 *)src_dev, (float4 *)dst_dev, n); }, reps, &ms);
+    if (st != CTU_OK) return st;
+    *gbs_out = 2.0 * (double)bytes * reps / (ms * 1e-3) / 1e9;
+    return CTU_OK;
+}
+
+}  // extern "C"

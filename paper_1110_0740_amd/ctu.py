@@ -33,7 +33,7 @@ SYMBOLS = [
     "ctu_hier_advance", "ctu_hier_leaf_mask", "ctu_hier_tag", "ctu_hier_next_dt", "ctu_plan_set_leaf_mask",
     "ctu_plan_set_shape", "ctu_plan_get_shape", "ctu_plan_autotune", "ctu_tune_cache_clear",
     "ctu_plan_create_ex", "ctu_plan_set_workspace", "ctu_plan_device", "ctu_step_static",
-    "ctu_static_scratch_bytes",
+    "ctu_static_scratch_bytes", "ctu_measure_fma", "ctu_measure_copy",
 ]
 PLAN_CALLER_WORKSPACE = 1
 PLAN_LEVEL_DT = 2
@@ -107,6 +107,10 @@ def lib() -> C.CDLL:
         L.ctu_step_static.argtypes = [_vp] + [_vp] * 8 + [_vp]
         L.ctu_static_scratch_bytes.restype = C.c_int64
         L.ctu_static_scratch_bytes.argtypes = []
+        L.ctu_measure_fma.restype = C.c_int32
+        L.ctu_measure_fma.argtypes = [C.c_int32, C.c_int32, C.c_int32, _vp, C.POINTER(C.c_double)]
+        L.ctu_measure_copy.restype = C.c_int32
+        L.ctu_measure_copy.argtypes = [_vp, _vp, C.c_int64, C.POINTER(C.c_double)]
         L.ctu_plan_destroy.argtypes = [_vp]
         L.ctu_plan_state_elems.restype = C.c_int64
         L.ctu_plan_state_elems.argtypes = [_vp]
@@ -455,6 +459,32 @@ class Plan:
 
 def tune_cache_clear():
     _check(lib().ctu_tune_cache_clear())
+
+
+def measure_fma(precision: str = "fp32", nblocks: int = 4096, iters: int = 256) -> float:
+    """TFLOP/s of the library's FMA-chain kernel on the current device
+    (ctu_measure_fma); the output buffer is a torch tensor."""
+    import torch
+
+    prec = {"fp64": FP64, "fp32": FP32}[precision]
+    out = torch.empty(int(nblocks) * 256, dtype=torch.float32 if precision == "fp32" else torch.float64,
+                      device="cuda")
+    t = C.c_double()
+    _check(lib().ctu_measure_fma(prec, int(nblocks), int(iters), _ptr(out), C.byref(t)))
+    return t.value
+
+
+def measure_copy(nbytes: int = 2 << 30) -> float:
+    """GB/s (read + write) of the library's float4 copy kernel over two
+    torch buffers of `nbytes` (ctu_measure_copy)."""
+    import torch
+
+    n = int(nbytes) // 16 * 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    g = C.c_double()
+    _check(lib().ctu_measure_copy(_ptr(src), _ptr(dst), n * 4, C.byref(g)))
+    return g.value
 
 
 class Hier:

@@ -431,6 +431,33 @@ def mhd3d_fields_torch(n: int = 256, ng: int = 4, seed: int = 2000, device="cuda
     return V, dict(dim=3, gamma=5.0 / 3.0, dx=dx, box=box, ng=ng)
 
 
+def splitmix64_uniform(seed: int, counters: np.ndarray) -> np.ndarray:
+    """The (c + 1)-th uniform draw of SplitMix64(seed) for every counter c
+    (vectorised: the state after c + 1 steps is seed + (c + 1) gamma)."""
+    with np.errstate(over="ignore"):
+        z = np.uint64(seed & MASK64) + (counters.astype(np.uint64) + np.uint64(1)) * np.uint64(0x9E3779B97F4A7C15)
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+        z = z ^ (z >> np.uint64(31))
+    return (z >> np.uint64(11)).astype(np.float64) * (1.0 / (1 << 53))
+
+
+def cooling_time_white(seed: int, n: int, ng: int, dt0: float, box: Box | None = None, level_n: int | None = None):
+    """White-noise cooling times on a ghosted box of the periodic level of
+    level_n cells per side (default: the n^3 box itself): t_c = dt0 *
+    10^(3 (2u - 1)) in [1e-3, 1e3] dt0, u uniform and independent per cell,
+    drawn by SplitMix64 at the cell's periodic index (so ghosts repeat
+    their images).  [NZ, NY, NX] float64."""
+    N = level_n if level_n is not None else n
+    if box is None:
+        box = Box((0, 0, 0), (n, n, n))
+    idx = [np.arange(box.lo[d] - ng, box.lo[d] + box.n[d] + ng) % N for d in range(3)]
+    K, J, Iq = np.meshgrid(idx[2], idx[1], idx[0], indexing="ij")
+    c = (K.astype(np.int64) * N + J) * N + Iq
+    u = splitmix64_uniform(seed, c)
+    return dt0 * 10.0 ** (3.0 * (2.0 * u - 1.0))
+
+
 def cooling_time_field_torch(seed: int, n: int, ng: int, dt0: float, device="cuda"):
     """:func:`cooling_time_field` on the ghosted n^3 periodic box, with torch
     on `device` (float64, [NZ, NY, NX])."""

@@ -73,3 +73,20 @@ def test_cooling_time_torch_matches_numpy():
     b = I.cooling_time_field_torch(5002, n, ng, 0.25, device="cpu").numpy()
     assert np.allclose(a, b, rtol=1e-12, atol=0)
     assert a.min() >= 0.25e-3 * (1 - 1e-12) and a.max() <= 0.25e3 * (1 + 1e-12)
+
+
+def test_white_cooling_times_follow_splitmix64_and_periodicity():
+    """the vectorised draw is the SplitMix64 sequence; the cooling times span
+    [1e-3, 1e3] dt0 and the ghosts repeat their periodic images"""
+    rng = I.SplitMix64(77)
+    seq = [rng.uniform() for _ in range(20)]
+    assert np.array_equal(I.splitmix64_uniform(77, np.arange(20)), np.array(seq))
+    n, ng = 10, 4
+    tc = I.cooling_time_white(5003, n, ng, 2.0)
+    assert tc.min() >= 2e-3 and tc.max() <= 2e3 and tc.min() < 2e-2 and tc.max() > 2e2
+    W = tc[None].copy()
+    I.fill_periodic(W, ng, 3)
+    assert np.array_equal(W[0], tc)
+    # a sub-box sees the same cells as the whole box
+    sub = I.cooling_time_white(5003, n, ng, 2.0, box=I.Box((2, 3, 1), (4, 5, 6)), level_n=n)
+    assert np.array_equal(sub, tc[1:1 + 6 + 2 * ng, 3:3 + 5 + 2 * ng, 2:2 + 4 + 2 * ng])
