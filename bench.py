@@ -754,6 +754,9 @@ def leg_c3(args, dev, s, samples):
                         reflux=tn[lev].reflux or None) for lev, L in enumerate(hn.levels)]
     Ua = [u.to(torch.float32) for u in U64n]
     Ub = [u.clone() for u in Ua]
+    # the level plans take their tuned launch shapes, as the batched plans do
+    cyc_shapes = [p.autotune(Ua[lev], Ub[lev], paramsn[lev], reps=5, stream=s)[0] if not args.no_autotune
+                  else p.get_shape()[0] for lev, p in enumerate(plans_n)]
     hier = ctu.Hier("fp32", hn.base, [[(B.lo, B.n, ob) for B, ob in zip(L, offsn[lev])]
                                       for lev, L in enumerate(hn.levels)], NG)
     rate_l = torch.zeros(nlev, dtype=torch.float64, device=dev)
@@ -766,7 +769,7 @@ def leg_c3(args, dev, s, samples):
     cyc_zones = sum(int(np.prod(B.n)) << lev for lev, L in enumerate(hn.levels) for B in L)
     nsteps = sum(1 << lev for lev in range(nlev))
     cycle = {"ms_per_cycle": msc, "zone_updates_per_cycle": cyc_zones, "zone_updates_per_s": cyc_zones / (msc * 1e-3),
-             "patches": sum(len(L) for L in hn.levels), "level_steps_per_cycle": nsteps}
+             "patches": sum(len(L) for L in hn.levels), "level_steps_per_cycle": nsteps, "shapes": cyc_shapes}
     return {"patches": npatch, "zones": zones, "levels": [len(L) for L in h.levels], "register_slots": nslots,
             "fp32_batched": r32, "fp64_plain_per_patch": r64,
             "batched_fp32_over_plain_fp64": ms64 / ms32 if ms64 else None,

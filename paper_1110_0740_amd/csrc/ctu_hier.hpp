@@ -102,27 +102,15 @@ __global__ __launch_bounds__(NT) void k_hcopy(const HBox *box, const HCopy *cp, 
     for (int q = 0; q < NV; q++) U[dp + q * D.cells] = U[sp + q * S.cells];
 }
 
-// time-interpolated state of interior cell (ci, cj, ck) of coarse box cb
-template <typename R>
-__device__ __forceinline__ void coarse_at(const HBox &cb, int ci, int cj, int ck, int ng, const R *Uo, const R *Un,
-                                          R alpha, R *u)
-{
-    const long long p = hidx(cb, ci, cj, ck, ng);
-    if (alpha == R(0)) {
-#pragma unroll
-        for (int q = 0; q < NV; q++) u[q] = Uo[p + q * cb.cells];
-    } else {
-#pragma unroll
-        for (int q = 0; q < NV; q++) u[q] = (R(1) - alpha) * Uo[p + q * cb.cells] + alpha * Un[p + q * cb.cells];
-    }
-}
-
 // Eq. prolong for the ghost cells no same-level box holds, one thread per
-// listed coarse parent: the parent's time-interpolated state (Eq. intalpha)
-// and the MC slopes of its six face neighbours are formed once and give each
-// masked child u0 + sum_d (-+1/4) slope_d.  (One thread per parent and
-// variable, with fewer lines per wave, ran 1.6x slower: each thread re-reads
-// the parent's and the box's records.)
+// listed coarse parent: the parent's time-interpolated value (Eq. intalpha)
+// and the MC slopes of its six face neighbours give each masked child
+// u0 + sum_d (-+1/4) slope_d.  The nine variables are taken one after the
+// other (the loop is kept rolled), so that a wave has the 7-cell stencil of
+// one variable plane in flight rather than of all nine, which the L2 cannot
+// hold for the parents of a box's x-ghost slabs (two to a row).  (One thread
+// per parent and variable ran slower: each thread re-reads the parent's and
+// the box's records.)
 template <typename R>
 __global__ __launch_bounds__(NT) void k_hprolong(const HBox *box, const HPar *par, int npar, const int *multi,
                                                  const HBox *cbox, int N, int ng, R *U, const R *Uo, const R *Un,
@@ -135,58 +123,50 @@ __global__ __launch_bounds__(NT) void k_hprolong(const HBox *box, const HPar *pa
     const int Nc = N / 2, pi = P.pc[0], pj = P.pc[1], pk = P.pc[2];
     const R alpha = R(alpha_d);
     const bool ok = P.cbox != HPAR_MISSING;
-    R u0[NV], sl[3][NV];
-    if (P.cbox >= 0) {
-        const HBox C = cbox[P.cbox];
-        coarse_at(C, pi, pj, pk, ng, Uo, Un, alpha, u0);
+    // element offsets (variable 0) and variable strides of the parent and of
+    // its -x, +x, -y, +y, -z, +z neighbours in their coarse boxes (one box,
+    // or a row of the multi table), found once for the nine variables
+    long long base[7];
+    long long cl[7];
+    if (ok) {
+        const int *m = (P.cbox >= 0) ? nullptr : multi + 7 * (-1 - P.cbox);
 #pragma unroll
-        for (int d = 0; d < 3; d++) {
-            R up[NV], dn[NV];
-            const int di = (d == 0), dj = (d == 1), dk = (d == 2);
-            coarse_at(C, wrapi(pi + di, Nc), wrapi(pj + dj, Nc), wrapi(pk + dk, Nc), ng, Uo, Un, alpha, up);
-            coarse_at(C, wrapi(pi - di, Nc), wrapi(pj - dj, Nc), wrapi(pk - dk, Nc), ng, Uo, Un, alpha, dn);
-#pragma unroll
-            for (int q = 0; q < NV; q++) sl[d][q] = mc_slope(up[q] - u0[q], u0[q] - dn[q]);
-        }
-    } else if (ok) {
-        // the coarse boxes of the parent and of its -x, +x, -y, +y, -z, +z
-        // neighbours, a row of the multi table
-        const int *ob = multi + 7 * (-1 - P.cbox);
-        coarse_at(cbox[ob[0]], pi, pj, pk, ng, Uo, Un, alpha, u0);
-#pragma unroll
-        for (int d = 0; d < 3; d++) {
-            R up[NV], dn[NV];
-            const int di = (d == 0), dj = (d == 1), dk = (d == 2);
-            coarse_at(cbox[ob[2 + 2 * d]], wrapi(pi + di, Nc), wrapi(pj + dj, Nc), wrapi(pk + dk, Nc), ng, Uo, Un, alpha,
-                      up);
-            coarse_at(cbox[ob[1 + 2 * d]], wrapi(pi - di, Nc), wrapi(pj - dj, Nc), wrapi(pk - dk, Nc), ng, Uo, Un, alpha,
-                      dn);
-#pragma unroll
-            for (int q = 0; q < NV; q++) sl[d][q] = mc_slope(up[q] - u0[q], u0[q] - dn[q]);
+        for (int t = 0; t < 7; t++) {
+            int c[3] = { pi, pj, pk };
+            if (t > 0) c[(t - 1) / 2] = wrapi(c[(t - 1) / 2] + ((t & 1) ? -1 : 1), Nc);
+            const HBox C = cbox[m ? m[t] : P.cbox];
+            base[t] = hidx(C, c[0], c[1], c[2], ng);
+            cl[t] = C.cells;
         }
     }
-    for (int c8 = 0; c8 < 8; c8++) {
-        if (!(P.mask & (1u << c8))) continue;
-        const long long li =
-            ((long long)(P.f0[2] + ((c8 >> 2) & 1)) * b.N[1] + (P.f0[1] + ((c8 >> 1) & 1))) * b.N[0] + P.f0[0] + (c8 & 1);
-        R *dst = U + b.off + li;
-        R out[NV];
+    if (!ok && missing) atomicAdd(missing, __popc(P.mask));
+    auto val = [&](int t, int q) -> R {
+        const long long p = base[t] + (long long)q * cl[t];
+        return (alpha == R(0)) ? Uo[p] : (R(1) - alpha) * Uo[p] + alpha * Un[p];
+    };
+#pragma unroll 1
+    for (int q = 0; q < NV; q++) {
+        R u0 = R(0), sl[3] = { R(0), R(0), R(0) };
         if (ok) {
+            u0 = val(0, q);
 #pragma unroll
-            for (int q = 0; q < NV; q++) out[q] = u0[q];
-#pragma unroll
-            for (int d = 0; d < 3; d++) {
-                const R off = ((c8 >> d) & 1) ? R(0.25) : R(-0.25);
-#pragma unroll
-                for (int q = 0; q < NV; q++) out[q] += off * sl[d][q];
-            }
-        } else {
-#pragma unroll
-            for (int q = 0; q < NV; q++) out[q] = R(NAN);
-            if (missing) atomicAdd(missing, 1);
+            for (int d = 0; d < 3; d++) sl[d] = mc_slope(val(2 + 2 * d, q) - u0, u0 - val(1 + 2 * d, q));
         }
+        for (int c8 = 0; c8 < 8; c8++) {
+            if (!(P.mask & (1u << c8))) continue;
+            const long long li = ((long long)(P.f0[2] + ((c8 >> 2) & 1)) * b.N[1] + (P.f0[1] + ((c8 >> 1) & 1))) *
+                                     b.N[0] +
+                                 P.f0[0] + (c8 & 1);
+            R out;
+            if (ok) {
+                out = u0;
 #pragma unroll
-        for (int q = 0; q < NV; q++) dst[q * b.cells] = out[q];
+                for (int d = 0; d < 3; d++) out += (((c8 >> d) & 1) ? R(0.25) : R(-0.25)) * sl[d];
+            } else {
+                out = R(NAN);
+            }
+            U[b.off + li + (long long)q * b.cells] = out;
+        }
     }
 }
 
