@@ -42,8 +42,9 @@ NG = 4
 # Algorithmic FLOP per interior zone (add, mul, div, sqrt, transcendental;
 # FMA = 2) of what each kernel computes, from the op-counting build of the
 # FP64 oracle (profiles/oracle_opcount.md, `python oracle/opcount.py`):
-# prim = primitive recovery, tcouple = the t^n Godunov (and parabolic) fluxes
-# with their increments and, with parabolic terms, the half-step state; for
+# prim = primitive recovery, tcouple = the t^n Godunov fluxes with their
+# increments and, with parabolic terms, the half-step state; pdiv / pflux =
+# the parabolic fluxes Pi^n (with their divergence) and Pi^{n+1/2}; for
 # the relativistic workload also the sweeps (MUSCL-Hancock predictor and
 # coupling, time-centred solves, a third each, and the update in the last
 # one).  The characteristic-tracing sweeps are not listed: the oracle's
@@ -52,7 +53,7 @@ NG = 4
 # are the relativistic inversions, whose oracle form is a bisection.
 ALG_FLOP = {"C1": {"prim": 20.0, "tcouple": 943.0}, "C2": {"prim": 20.0, "tcouple": 1354.0},
             "C4": {"tcouple": 1696.0, "sweep_x": 1190.0, "sweep_y": 1190.0, "sweep_z": 1351.0},
-            "C5": {"prim": 20.0, "tcouple": 2056.0}}
+            "C5": {"prim": 20.0, "tcouple": 1520.0, "pdiv": 536.0, "pflux": 594.0}}
 # HBM bytes per launch of the FP32 256^3 t^n kernel, FETCH_SIZE x 2.0 +
 # WRITE_SIZE x 1.0 (KiB x 1024): a plain 1 GiB device copy (bench.py
 # --copy-calibration) reads back as 524,308 KiB of FETCH_SIZE and 1,048,576

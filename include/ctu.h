@@ -232,8 +232,9 @@ int32_t ctu_plan_device(const ctu_plan *plan);
  * offset + 9*NX*NY*NZ.  Bytes of device workspace the plan's option set
  * needs (held by the plan, or to be supplied by the caller): V^n and the
  * three corner-coupling increments T_d (9 values per ghosted cell each; in
- * the state's element type), with parabolic terms V^{n+1/2} and one rate
- * per cell, with the MT corner coupling three predictor-flux fields, with
+ * the state's element type), with parabolic terms V^{n+1/2}, one rate per
+ * cell and 8 parabolic face-flux values per face (one face per direction and
+ * ghosted cell), with the MT corner coupling three predictor-flux fields, with
  * the App. B hybrid one flag byte per cell, each field 256-byte aligned. */
 int64_t ctu_plan_state_elems(const ctu_plan *plan);
 int64_t ctu_plan_workspace_bytes(const ctu_plan *plan);
@@ -476,7 +477,8 @@ ctu_status ctu_hier_advance(ctu_hier *hier, ctu_plan *const *plans, void *const 
  * recorded.  The first enable creates the events (a profiling setup call).  ctu_plan_read_timing synchronises on the recorded events and
  * writes the total milliseconds per stage into ms_out[CTU_NSTAGE] and the
  * number of recorded steps into nsteps_out.  Stages: 0 primitive recovery,
- * 1 the t^n fluxes and transverse increments (with the half step), 2-4
+ * 1 the t^n fluxes and transverse increments (with the half step), 2 and 3
+ * the parabolic face fluxes of V^n and of V^{n+1/2} (parabolic runs), 4
  * unused, 5-7 direction sweeps x/y/z. */
 #define CTU_NSTAGE 8
 ctu_status ctu_plan_enable_timing(ctu_plan *plan, int32_t enable);

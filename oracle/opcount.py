@@ -18,6 +18,10 @@ work of the oracle's box does not enter:
   5 half-step state V^{n+1/2}  per ghosted cell   -> 1 per zone (parabolic)
   6 half-step parabolic flux   per face           -> dim per zone (parabolic)
   7 update, sources, rate      per zone           -> 1 per zone
+With parabolic terms the t^n stage also evaluates Pi^n; the step is counted
+a second time on the same fields with the parabolic terms and cooling off,
+and the difference of the two t^n stages is listed as Pi^n (the GPU computes
+it in a kernel of its own, k_pdiv; Pi^{n+1/2} likewise in k_pflux).
 FLOPs are additions / subtractions, multiplications, divisions, square roots
 and transcendental calls (exp, log, pow, cbrt), each one (a fused
 multiply-add is two); comparisons and min / max / abs are listed apart.
@@ -113,7 +117,7 @@ def workload(name):
         n = (64, 64)
         V, meta = I.mhd2d_fields(n=128, ng=NG, seed=1000, box=I.Box((0, 0, 0), (64, 64, 1)))
         o = O.make_opts(dim=2, recon="lin_mc", riemann="hlld", gamma=meta["gamma"], dx=meta["dx"])
-        return o, V, None, n, 2, False, 0.4, 1.0
+        return o, V, None, n, 2, None, 0.4, 1.0
     if name in ("C2", "C5"):
         seed = 2000 if name == "C2" else 5000
         n = (32, 32, 32)
@@ -127,13 +131,14 @@ def workload(name):
                       **coef)
             L0 = V[4] / ((meta["gamma"] - 1) * V[0] ** 2 * np.sqrt(T) * 1e-3)
         o = O.make_opts(dim=3, gamma=meta["gamma"], dx=meta["dx"], **kw)
-        return o, V, L0, n, 3, name == "C5", 0.4, 1.0
+        o_hyp = O.make_opts(dim=3, gamma=meta["gamma"], dx=meta["dx"], recon="ppm", riemann="hlld")
+        return o, V, L0, n, 3, (o_hyp if name == "C5" else None), 0.4, 1.0
     if name == "C4":
         n = (32, 32, 32)
         V, meta = I.rmhd3d_fields(n=192, ng=NG, seed=4000, box=I.Box((80, 80, 80), n))
         o = O.make_opts(dim=3, physics="rmhd", predictor="mh", recon="lin_mc", riemann="hll", gamma=meta["gamma"],
                         dx=meta["dx"])
-        return o, V, None, n, 3, False, 0.3, 1.0
+        return o, V, None, n, 3, None, 0.3, 1.0
     raise KeyError(name)
 
 
@@ -144,6 +149,8 @@ DESC = {"C1": "2D ideal MHD 128^2, MC-linear characteristic + HLLD + GLM (FP64)"
 STAGES = ["prim recovery", "t^n fluxes", "predict+couple", "final solves", "V^{n+1/2}", "Pi^{n+1/2}",
           "update+sources"]
 KERNELS = {"prim": [0], "tcouple": [1, 4], "sweeps": [2, 3, 5, 6]}
+# parabolic runs: row 7 = the t^n stage without parabolic terms, row 8 = Pi^n
+KERNELS_PAR = {"prim": [0], "tcouple": [7, 4], "pdiv": [8], "pflux": [5], "sweeps": [2, 3, 6]}
 
 
 def main():
@@ -155,7 +162,8 @@ def main():
              "docstring). FLOP = add + mul + div + sqrt + transcendental; FMA counts 2.", ""]
     result = {}
     for name in ("C1", "C2", "C4", "C5"):
-        o, V, L0, n, dim, par, cfl, _ = workload(name)
+        o, V, L0, n, dim, o_hyp, cfl, _ = workload(name)
+        par = o_hyp is not None
         U = O.prim2cons(o, V)
         dt = cfl / O.cfl_rate(o, U, NG)
         ch = cfl * o.dx[0] / dt
@@ -163,9 +171,14 @@ def main():
             ch = min(ch, 1.0)
         rows = counted_step(o, U, L0, dt, ch)
         pz = per_zone(rows, n, dim, par)
+        kernels = KERNELS
+        if par:
+            tn_hyp = per_zone(counted_step(o_hyp, U, None, dt, ch), n, dim, False)[1]
+            pz = np.vstack([pz, tn_hyp, pz[1] - tn_hyp])
+            kernels = KERNELS_PAR
         side = rows[9] / float(np.prod(n))
         ninv = rows[11][0] / float(np.prod(n))
-        kflops = {k: sum(flops(pz[s]) for s in v) for k, v in KERNELS.items()}
+        kflops = {k: sum(flops(pz[s]) for s in v) for k, v in kernels.items()}
         total = sum(kflops.values())
         result[name] = (pz, kflops, total, side)
         lines.append(f"## {name}: {DESC[name]}")
@@ -176,6 +189,9 @@ def main():
             if s in (4, 5) and not par:
                 continue
             lines.append(f"| {STAGES[s]} | " + " | ".join(f"{x:.1f}" for x in pz[s]) + f" | {flops(pz[s]):.1f} |")
+        if par:
+            for s, lab in ((7, "(t^n fluxes without parabolic terms)"), (8, "(of which Pi^n)")):
+                lines.append(f"| {lab} | " + " | ".join(f"{x:.1f}" for x in pz[s]) + f" | {flops(pz[s]):.1f} |")
         lines.append("")
         lines.append("FLOP per zone by kernel: " + ", ".join(f"{k} {v:.0f}" for k, v in kflops.items()) +
                      f"; step {total:.0f}.")

@@ -13,6 +13,7 @@ struct Combo {
     int phys, pred, rk, rs;
     int shk;   // App. B shock flags in use
     int fast;  // options equal the fast variant's fixed set (see variant_opts)
+    int par;   // ... the par variant's: the fast set with parabolic terms or cooling
 };
 
 // supported (physics, predictor, reconstruction, solver) combinations
@@ -33,6 +34,9 @@ hipError_t launch_mtflux_f32(int D, const Combo &c, int nblocks, const MtArgs<fl
 hipError_t launch_mtflux_f64(int D, const Combo &c, int nblocks, const MtArgs<double> &a, hipStream_t s);
 hipError_t launch_tcouple_f32(int dim, int par, const Combo &c, int nblocks, const TArgs<float> &a, hipStream_t s);
 hipError_t launch_tcouple_f64(int dim, int par, const Combo &c, int nblocks, const TArgs<double> &a, hipStream_t s);
+// div != 0: k_pdiv (Pi^n divergence), else k_pflux (Pi^{n+1/2} face slots)
+hipError_t launch_pflux_f32(int dim, int div, int nblocks, const PArgs<float> &a, hipStream_t s);
+hipError_t launch_pflux_f64(int dim, int div, int nblocks, const PArgs<double> &a, hipStream_t s);
 
 template <typename R> inline hipError_t launch_sweep(int D, const Combo &c, int nb, const SweepArgs<R> &a, hipStream_t s);
 template <> inline hipError_t launch_sweep<float>(int D, const Combo &c, int nb, const SweepArgs<float> &a, hipStream_t s)
@@ -58,15 +62,14 @@ template <> inline hipError_t launch_sweep<double>(int D, const Combo &c, int nb
     template <int D, int PHYS, int PRED, int RK, int RS>                                                         \
     static hipError_t sweep_one(const Combo &c, int nb, const SweepArgs<R> &a, hipStream_t s)                   \
     {                                                                                                            \
-        /* Rusanov, HLLC and Roe have no hybrid-flag variant */                                                  \
-        if constexpr (RS == RS_RUSANOV || RS == RS_HLLC || RS == RS_ROE) {                                       \
-            if (c.fast) return sweep_one2<D, PHYS, PRED, RK, RS, VAR_FAST>(nb, a, s);                            \
-            return sweep_one2<D, PHYS, PRED, RK, RS, VAR_GENERIC>(nb, a, s);                                     \
-        } else {                                                                                                 \
+        /* Rusanov, HLLC and Roe have no hybrid-flag variant; parabolic terms  \
+           and cooling belong to the MHD module */                                                               \
+        if constexpr (RS != RS_RUSANOV && RS != RS_HLLC && RS != RS_ROE)                                         \
             if (a.flag) return sweep_one2<D, PHYS, PRED, RK, RS, VAR_SHOCK>(nb, a, s);                           \
-            if (c.fast) return sweep_one2<D, PHYS, PRED, RK, RS, VAR_FAST>(nb, a, s);                            \
-            return sweep_one2<D, PHYS, PRED, RK, RS, VAR_GENERIC>(nb, a, s);                                     \
-        }                                                                                                        \
+        if (c.fast) return sweep_one2<D, PHYS, PRED, RK, RS, VAR_FAST>(nb, a, s);                                \
+        if constexpr (PHYS == PHYS_MHD)                                                                          \
+            if (c.par) return sweep_one2<D, PHYS, PRED, RK, RS, VAR_PAR>(nb, a, s);                              \
+        return sweep_one2<D, PHYS, PRED, RK, RS, VAR_GENERIC>(nb, a, s);                                         \
     }                                                                                                            \
     template <int D>                                                                                             \
     static hipError_t sweep_dir(const Combo &c, int nb, const SweepArgs<R> &a, hipStream_t s)                   \
@@ -117,6 +120,20 @@ template <> inline hipError_t launch_sweep<double>(int D, const Combo &c, int nb
         if (D == 1) return sweep_dir<1>(c, nb, a, s);                                                            \
         return sweep_dir<2>(c, nb, a, s);                                                                        \
     }                                                                                                            \
+    /* MHD t^n kernel: the fixed-option variants wherever the option set is   \
+       the fast or the par one (the kernel reads GLM and hyperbolic_off only) */ \
+    template <int DIM, int RS, int PAR>                                                                          \
+    static void tc_mhd(const Combo &c, int nb, const TArgs<R> &a, hipStream_t s)                                \
+    {                                                                                                            \
+        if (c.fast || c.par) {                                                                                   \
+            if constexpr (PAR)                                                                                   \
+                hipLaunchKernelGGL((k_tcouple<DIM, PHYS_MHD, RS, 1, VAR_PAR, R>), dim3(nb), dim3(NT), 0, s, a);  \
+            else                                                                                                 \
+                hipLaunchKernelGGL((k_tcouple<DIM, PHYS_MHD, RS, 0, VAR_FAST, R>), dim3(nb), dim3(NT), 0, s, a); \
+        } else {                                                                                                 \
+            hipLaunchKernelGGL((k_tcouple<DIM, PHYS_MHD, RS, PAR, VAR_GENERIC, R>), dim3(nb), dim3(NT), 0, s, a); \
+        }                                                                                                        \
+    }                                                                                                            \
     template <int DIM, int PAR>                                                                                  \
     static hipError_t tc_one(const Combo &c, int nb, const TArgs<R> &a, hipStream_t s)                          \
     {                                                                                                            \
@@ -137,28 +154,18 @@ template <> inline hipError_t launch_sweep<double>(int D, const Combo &c, int nb
             hipLaunchKernelGGL((k_tcouple<DIM, PHYS_RMHD_TM, RS_HLLD, 0, VAR_GENERIC, R>), dim3(nb), dim3(NT), 0, s, a); \
         else if (c.phys == PHYS_RMHD_TM)                                                                         \
             hipLaunchKernelGGL((k_tcouple<DIM, PHYS_RMHD_TM, RS_HLL, 0, VAR_GENERIC, R>), dim3(nb), dim3(NT), 0, s, a); \
-        else if (c.rs == RS_RUSANOV && c.fast)                                                                   \
-            hipLaunchKernelGGL((k_tcouple<DIM, PHYS_MHD, RS_RUSANOV, 0, VAR_FAST, R>), dim3(nb), dim3(NT), 0, s, a); \
-        else if (c.rs == RS_RUSANOV)                                                                             \
-            hipLaunchKernelGGL((k_tcouple<DIM, PHYS_MHD, RS_RUSANOV, PAR, VAR_GENERIC, R>), dim3(nb), dim3(NT), 0, s, a); \
-        else if (c.rs == RS_HLLC && c.fast)                                                                      \
-            hipLaunchKernelGGL((k_tcouple<DIM, PHYS_MHD, RS_HLLC, 0, VAR_FAST, R>), dim3(nb), dim3(NT), 0, s, a); \
-        else if (c.rs == RS_HLLC)                                                                                \
-            hipLaunchKernelGGL((k_tcouple<DIM, PHYS_MHD, RS_HLLC, PAR, VAR_GENERIC, R>), dim3(nb), dim3(NT), 0, s, a); \
-        else if (c.rs == RS_ROE && c.fast)                                                                       \
-            hipLaunchKernelGGL((k_tcouple<DIM, PHYS_MHD, RS_ROE, 0, VAR_FAST, R>), dim3(nb), dim3(NT), 0, s, a); \
-        else if (c.rs == RS_ROE)                                                                                 \
-            hipLaunchKernelGGL((k_tcouple<DIM, PHYS_MHD, RS_ROE, PAR, VAR_GENERIC, R>), dim3(nb), dim3(NT), 0, s, a); \
         else if (c.rs == RS_HLLD && a.flag)                                                                      \
             hipLaunchKernelGGL((k_tcouple<DIM, PHYS_MHD, RS_HLLD, PAR, VAR_SHOCK, R>), dim3(nb), dim3(NT), 0, s, a); \
-        else if (c.fast && c.rs == RS_HLLD)                                                                      \
-            hipLaunchKernelGGL((k_tcouple<DIM, PHYS_MHD, RS_HLLD, 0, VAR_FAST, R>), dim3(nb), dim3(NT), 0, s, a); \
-        else if (c.fast)                                                                                         \
-            hipLaunchKernelGGL((k_tcouple<DIM, PHYS_MHD, RS_HLL, 0, VAR_FAST, R>), dim3(nb), dim3(NT), 0, s, a); \
+        else if (c.rs == RS_RUSANOV)                                                                             \
+            tc_mhd<DIM, RS_RUSANOV, PAR>(c, nb, a, s);                                                           \
+        else if (c.rs == RS_HLLC)                                                                                \
+            tc_mhd<DIM, RS_HLLC, PAR>(c, nb, a, s);                                                              \
+        else if (c.rs == RS_ROE)                                                                                 \
+            tc_mhd<DIM, RS_ROE, PAR>(c, nb, a, s);                                                               \
         else if (c.rs == RS_HLLD)                                                                                \
-            hipLaunchKernelGGL((k_tcouple<DIM, PHYS_MHD, RS_HLLD, PAR, VAR_GENERIC, R>), dim3(nb), dim3(NT), 0, s, a); \
+            tc_mhd<DIM, RS_HLLD, PAR>(c, nb, a, s);                                                              \
         else                                                                                                     \
-            hipLaunchKernelGGL((k_tcouple<DIM, PHYS_MHD, RS_HLL, PAR, VAR_GENERIC, R>), dim3(nb), dim3(NT), 0, s, a); \
+            tc_mhd<DIM, RS_HLL, PAR>(c, nb, a, s);                                                               \
         return hipGetLastError();                                                                                \
     }                                                                                                            \
     hipError_t launch_tcouple_##SUFFIX(int dim, int par, const Combo &c, int nb, const TArgs<R> &a,            \
@@ -167,6 +174,15 @@ template <> inline hipError_t launch_sweep<double>(int D, const Combo &c, int nb
         if (nb <= 0) return hipSuccess;                                                                          \
         if (dim == 2) return par ? tc_one<2, 1>(c, nb, a, s) : tc_one<2, 0>(c, nb, a, s);                        \
         return par ? tc_one<3, 1>(c, nb, a, s) : tc_one<3, 0>(c, nb, a, s);                                      \
+    }                                                                                                            \
+    hipError_t launch_pflux_##SUFFIX(int dim, int div, int nb, const PArgs<R> &a, hipStream_t s)                \
+    {                                                                                                            \
+        if (nb <= 0) return hipSuccess;                                                                          \
+        if (dim == 2 && div) hipLaunchKernelGGL((k_pdiv<2, R>), dim3(nb), dim3(NT), 0, s, a);                    \
+        else if (dim == 2) hipLaunchKernelGGL((k_pflux<2, R>), dim3(nb), dim3(NT), 0, s, a);                     \
+        else if (div) hipLaunchKernelGGL((k_pdiv<3, R>), dim3(nb), dim3(NT), 0, s, a);                           \
+        else hipLaunchKernelGGL((k_pflux<3, R>), dim3(nb), dim3(NT), 0, s, a);                                   \
+        return hipGetLastError();                                                                                \
     }                                                                                                            \
     }
 

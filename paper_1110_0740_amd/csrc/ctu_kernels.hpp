@@ -5,11 +5,14 @@
 //   k_cons2prim  V = V(U) on every ghosted cell                       (a1)
 //   k_shock_hll, k_shock_mm
 //                App. B zone flags (shock-adaptive runs only)
-//   k_tcouple    first-order fluxes R(V_j, V_{j+1}) at t^n and the
-//                parabolic fluxes Pi^n on every face of the region
-//                [g-1, g+n], differenced into the per-cell increments T_d
-//                of Eq. transv; with parabolic terms also the cell-centred
-//                V^{n+1/2}                                   (a2, a3, a5, a7)
+//   k_pdiv       parabolic runs: the parabolic fluxes Pi^n of V^n on
+//                every face of the region [g-1, g+n], differenced per cell (a3)
+//   k_tcouple    first-order fluxes R(V_j, V_{j+1}) at t^n on those
+//                faces, differenced into the per-cell increments T_d of
+//                Eq. transv (plus the Pi^n divergence); with parabolic
+//                terms also the cell-centred V^{n+1/2}       (a2, a3, a5, a7)
+//   k_pflux      parabolic runs: Pi^{n+1/2} of V^{n+1/2} on the faces
+//                g .. g+n of the sweeps                                (a8)
 //   k_mtflux<D>, k_mtT
 //                instead of k_tcouple with the MT corner coupling: the
 //                transverse fluxes between normal-predictor states and their
@@ -22,6 +25,8 @@
 // Work is described by tables of tiles (box, range) so that boxes of any
 // size and level run in one launch per kernel.
 #pragma once
+#include <type_traits>
+
 #include "ctu_device.hpp"
 
 namespace ctu {
@@ -203,21 +208,24 @@ __global__ __launch_bounds__(NT) void k_prim2cons(const KBox *boxes, const KTile
 
 // ---------------------------------------------------------------------------
 // Kernel variants of the t^n kernel and the sweeps: generic (every option
-// read at run time), shock (App. B flags in use), and fast: the common option
+// read at run time), shock (App. B flags in use), fast: the common option
 // set (face-value reference states, GLM on, hyperbolic fluxes on, no
 // parabolic terms, no cooling) fixed at compile time, so that the code of the
 // other options folds away (about half the instructions and registers of the
-// generic sweep).
+// generic sweep), and par: the same fixed set with parabolic terms and
+// cooling read at run time (non-ideal runs).
 // ---------------------------------------------------------------------------
-constexpr int VAR_GENERIC = 0, VAR_SHOCK = 1, VAR_FAST = 2;
+constexpr int VAR_GENERIC = 0, VAR_SHOCK = 1, VAR_FAST = 2, VAR_PAR = 3;
 
 template <int VAR> __device__ __forceinline__ KOpts variant_opts(const KOpts &in)
 {
     KOpts o = in;
-    if constexpr (VAR == VAR_FAST) {
+    if constexpr (VAR == VAR_FAST || VAR == VAR_PAR) {
         o.wref = WREF_FACE;
         o.glm = 1;
         o.hyp_off = 0;
+    }
+    if constexpr (VAR == VAR_FAST) {
         o.parab = 0;
         o.cooling = 0;
     }
@@ -289,56 +297,110 @@ __global__ __launch_bounds__(NT) void k_shock_mm(const KBox *boxes, const KTile 
 }
 
 // ---------------------------------------------------------------------------
-// Parabolic face flux (Sec. 2.1.1, Sec. 3.1, App. A) on the D-face between
-// cells A = c - e_D and B = c, from primitive point values Vf of the box.
-// Face coefficients use the average of the conserved variables of A and B;
-// transverse derivatives use the four-point average.
+// Parabolic face fluxes (Sec. 2.1.1, Sec. 3.1, App. A).
+//
+// Two kernels evaluate them from a primitive state.  On the D-face between
+// cells A = c - e_D and B = c the face coefficients use the average of the
+// states of A and B (the velocity density-weighted), gradients along D the
+// two-point difference and the transverse gradients the four-point average
+// of App. A.  The saturation of the conduction flux (Eq. tc_flux) is
+// upwinded by the sign of the classical flux's normal component with the
+// face's Riemann states:
+//  * Pi^n (k_pdiv, from V^n): those states are the cells' own, so the kernel
+//    saturates and differences the fluxes into the per-cell divergence that
+//    the t^n kernel adds;
+//  * Pi^{n+1/2} (k_pflux, from V^{n+1/2}): the states are the final face
+//    states of the sweeps, so the classical flux is stored as its normal
+//    component and magnitude in eight slots per face and the sweep
+//    saturates (parab_face).
+// A block owns TX x TY in-plane cells (3D: x, y; 2D: x) and marches along
+// the last axis over a chunk of LM planes, with three planes of the eight
+// staged fields (rho, v, B, T = p / rho) and a one-cell in-plane halo in LDS.
 // ---------------------------------------------------------------------------
 
-template <int D, typename R>
-__device__ __forceinline__ void parab_flux(const R *Vf, const KBox &bx, int i, int j, int k, const KOpts &o, R pL,
-                                           R pR, R rL, R rR, R *Pi)
+constexpr int NPF = 8;  // slots per face
+constexpr int PF_M = 0;   // viscous momentum flux, three components
+constexpr int PF_BT = 3;  // resistive flux of the transverse field B_t
+constexpr int PF_BB = 4;  // ... and of the binormal field B_b
+constexpr int PF_E = 5;   // viscous and resistive energy flux
+constexpr int PF_FN = 6;  // classical conduction flux: normal component
+constexpr int PF_FM = 7;  // ... and magnitude
+
+template <int DIM> struct PTile {
+    static constexpr int TX = (DIM == 3) ? 32 : NT;
+    static constexpr int TY = (DIM == 3) ? 8 : 1;
+    static constexpr int HX = TX + 2, HY = (DIM == 3) ? TY + 2 : 1, HP = HX * HY;
+    static constexpr int LM = 16;  // planes per block along the marching axis
+};
+
+template <typename R> struct PArgs {
+    const KBox *boxes;
+    const KTile *tiles;  // (box, x offset, y offset, marching offset) from g-1+s
+    const R *V;          // primitive state (workspace)
+    R *PF;               // face slots (workspace): NPF * DIM planes per cell
+    KOpts o;
+};
+
+// the energy slot plus the conduction flux of normal component Fn and
+// magnitude Fm, saturated (Eq. tc_flux) with the pressure upwinded by the
+// sign of Fn (Eq. sat_flux)
+template <typename R>
+__device__ __forceinline__ R pf_energy(R E, R Fn, R Fm, const KOpts &o, R pL, R pR, R rL, R rR)
+{
+    if (o.parab & PB_TC) {
+        if (o.phi > 0.0 && Fm > R(0)) {
+            R pu = (Fn < R(0)) ? pL : pR;
+            R q = R(5.0 * o.phi) * pu * sqrt(pu) / sqrt(R(0.5) * (rL + rR));
+            Fn = q / (Fm + q) * Fn;
+        }
+        E += Fn;
+    }
+    return E;
+}
+
+// slots of the D-face below the lane's cell from the three staged planes
+// (P[0], P[1], P[2] = planes m-1, m, m+1, field f at f * HP); l is the
+// lane's in-plane slot
+template <int DIM, int D, typename R>
+__device__ __forceinline__ void pflux_face(const R *const *P, int l, const KBox &bx, const KOpts &o, R *out)
 {
     constexpr int n = Ax<D>::n, t = Ax<D>::t, b = Ax<D>::b;
-    int di, dj, dk;
-    unit<D>(di, dj, dk);
-    const int cs = (int)bx.cells;
-    const int cB = cidx(bx, i, j, k);
-    const int cA = cidx(bx, i - di, j - dj, k - dk);
-    auto fv = [&](int f, int c) -> R {
-        if (f < 3) return Vf[(MX1 + f) * cs + c];
-        if (f < 6) return Vf[(BX1 + f - 3) * cs + c];
-        return Vf[PRS * cs + c] / Vf[RHO * cs + c];
-    };
-    R rA = Vf[RHO * cs + cA], rB = Vf[RHO * cs + cB];
-    R irs = R(1) / (rA + rB);
-    R rhof = R(0.5) * (rA + rB);
+    constexpr int HP = PTile<DIM>::HP, HX = PTile<DIM>::HX;
+    // plane and in-plane offsets of the unit step along axis e
+    auto dm_of = [](int e) { return e == DIM - 1 ? 1 : 0; };
+    auto dl_of = [](int e) { return e == DIM - 1 ? 0 : (e == 0 ? 1 : HX); };
+    // field f of the cell at (dm, dl) from the lane's cell
+    auto val = [&](int f, int dm, int dl) -> R { return P[1 + dm][f * HP + l + dl]; };
+    const int aM = -dm_of(D), aL = -dl_of(D);  // cell A
+    const R rA = val(0, aM, aL), rB = val(0, 0, 0);
+    const R irs = R(1) / (rA + rB);
+    const R rhof = R(0.5) * (rA + rB);
     R vf[3], Bf[3];
 #pragma unroll
     for (int c = 0; c < 3; c++) {
-        vf[c] = (rA * Vf[(MX1 + c) * cs + cA] + rB * Vf[(MX1 + c) * cs + cB]) * irs;
-        Bf[c] = R(0.5) * (Vf[(BX1 + c) * cs + cA] + Vf[(BX1 + c) * cs + cB]);
+        vf[c] = (rA * val(1 + c, aM, aL) + rB * val(1 + c, 0, 0)) * irs;
+        Bf[c] = R(0.5) * (val(4 + c, aM, aL) + val(4 + c, 0, 0));
     }
     // gradients of (v_x, v_y, v_z, B_x, B_y, B_z, T) at the face
     R g[7][3];
 #pragma unroll
     for (int f = 0; f < 7; f++) {
-        g[f][D] = (fv(f, cB) - fv(f, cA)) / R(bx.dx[D]);
+        g[f][D] = (val(1 + f, 0, 0) - val(1 + f, aM, aL)) / R(bx.dx[D]);
 #pragma unroll
         for (int e = 0; e < 3; e++) {
             if (e == D) continue;
-            if (e >= o.dim) {
+            if (e >= DIM) {
                 g[f][e] = R(0);
                 continue;
             }
-            int ei = (e == 0), ej = (e == 1), ek = (e == 2);
-            R up = fv(f, cidx(bx, i + ei, j + ej, k + ek)) + fv(f, cidx(bx, i - di + ei, j - dj + ej, k - dk + ek));
-            R dn = fv(f, cidx(bx, i - ei, j - ej, k - ek)) + fv(f, cidx(bx, i - di - ei, j - dj - ej, k - dk - ek));
+            const int em = dm_of(e), el = dl_of(e);
+            R up = val(1 + f, em, el) + val(1 + f, aM + em, aL + el);
+            R dn = val(1 + f, -em, -el) + val(1 + f, aM - em, aL - el);
             g[f][e] = (up - dn) / (R(4) * R(bx.dx[e]));
         }
     }
 #pragma unroll
-    for (int q = 0; q < NV; q++) Pi[q] = R(0);
+    for (int q = 0; q < NPF; q++) out[q] = R(0);
     if (o.parab & PB_VISC) {
         R divv = g[0][0] + g[1][1] + g[2][2];
         R mu = rhof * R(o.nu);
@@ -346,9 +408,9 @@ __device__ __forceinline__ void parab_flux(const R *Vf, const KBox &bx, int i, i
 #pragma unroll
         for (int c = 0; c < 3; c++) {
             tau[c] = mu * (g[c][n] + g[n][c] - (c == n ? R(2.0 / 3.0) * divv : R(0)));
-            Pi[MX1 + c] += tau[c];
+            out[PF_M + c] = tau[c];
         }
-        Pi[ENG] += vf[0] * tau[0] + vf[1] * tau[1] + vf[2] * tau[2];
+        out[PF_E] += vf[0] * tau[0] + vf[1] * tau[1] + vf[2] * tau[2];
     }
     if (o.parab & PB_RES) {
         R J[3];
@@ -356,9 +418,9 @@ __device__ __forceinline__ void parab_flux(const R *Vf, const KBox &bx, int i, i
         J[1] = g[3][2] - g[5][0];
         J[2] = g[4][0] - g[3][1];
         R eta = R(o.eta);
-        Pi[BX1 + t] += eta * J[b];
-        Pi[BX1 + b] -= eta * J[t];
-        Pi[ENG] -= eta * (J[t] * Bf[b] - J[b] * Bf[t]);
+        out[PF_BT] = eta * J[b];
+        out[PF_BB] = -(eta * J[t]);
+        out[PF_E] -= eta * (J[t] * Bf[b] - J[b] * Bf[t]);
     }
     if (o.parab & PB_TC) {
         R B2 = Bf[0] * Bf[0] + Bf[1] * Bf[1] + Bf[2] * Bf[2];
@@ -372,15 +434,276 @@ __device__ __forceinline__ void parab_flux(const R *Vf, const KBox &bx, int i, i
         R Fc[3];
 #pragma unroll
         for (int c = 0; c < 3; c++) Fc[c] = R(o.kpar) * bh[c] * bg + R(o.kperp) * (g[6][c] - bh[c] * bg);
-        R Fm = sqrt(Fc[0] * Fc[0] + Fc[1] * Fc[1] + Fc[2] * Fc[2]);
-        R Fn = Fc[n];
-        if (o.phi > 0.0 && Fm > R(0)) {
-            R pu = (Fc[n] < R(0)) ? pL : pR;  // Eq. sat_flux: upwind by sign of t_n
-            R q = R(5.0 * o.phi) * pu * sqrt(pu) / sqrt(R(0.5) * (rL + rR));
-            Fn = q / (Fm + q) * Fc[n];
-        }
-        Pi[ENG] += Fn;
+        out[PF_FN] = Fc[n];
+        out[PF_FM] = sqrt(Fc[0] * Fc[0] + Fc[1] * Fc[1] + Fc[2] * Fc[2]);
     }
+}
+
+// stage plane m of V (rho, v, B, T = p / rho) over the tile's cells and a
+// one-cell in-plane halo into S (field f at f * HP), cells of the load range
+// [lo, hi] only
+template <int DIM, typename R>
+__device__ __forceinline__ void pf_stage(R *S, const R *Vb, const KBox &bx, const int *lo, const int *hi, int x0,
+                                         int y0, int m)
+{
+    using PT = PTile<DIM>;
+    constexpr int AM = DIM - 1;
+    if (m < lo[AM] || m > hi[AM]) return;
+    const int cs = (int)bx.cells;
+    for (int h = threadIdx.x; h < PT::HP; h += NT) {
+        const int hx = h % PT::HX, hy = h / PT::HX;
+        const int xx = x0 - 1 + hx, yy = y0 - 1 + hy;
+        if (xx < lo[0] || xx > hi[0]) continue;
+        if (DIM == 3 && (yy < lo[1] || yy > hi[1])) continue;
+        const int c = (DIM == 3) ? cidx(bx, xx, yy, m) : cidx(bx, xx, m, 0);
+        const R rho = Vb[RHO * cs + c];
+        R *d = S + h;
+        d[0] = rho;
+#pragma unroll
+        for (int q = 0; q < 3; q++) {
+            d[(1 + q) * PT::HP] = Vb[(MX1 + q) * cs + c];
+            d[(4 + q) * PT::HP] = Vb[(BX1 + q) * cs + c];
+        }
+        d[7 * PT::HP] = Vb[PRS * cs + c] / rho;
+    }
+}
+
+// Pi^{n+1/2} face slots of the sweeps (all eight, conduction unsaturated):
+// faces below cells g .. g+n along D at positions g .. g+n-1 across it,
+// reading cells g-1 .. g+n, where V^{n+1/2} is defined
+template <int DIM, typename R>
+__global__ __launch_bounds__(NT) void k_pflux(PArgs<R> a)
+{
+    using PT = PTile<DIM>;
+    constexpr int AM = DIM - 1;  // marching axis
+    __shared__ R S[3][8 * PT::HP];
+    const int tid = threadIdx.x;
+    const KTile tl = a.tiles[blockIdx.x];
+    const KBox bx = a.boxes[tl.box];
+    const KOpts &o = a.o;
+    const int cs = (int)bx.cells;
+    const R *Vb = a.V + bx.woff;
+    R *Pb = a.PF + (bx.woff / NV) * (NPF * DIM);
+    // load range [lo, hi] per axis (x, y, marching in 3D; x, marching in 2D)
+    int lo[3] = { 0, 0, 0 }, hi[3] = { 0, 0, 0 };
+#pragma unroll
+    for (int e = 0; e < DIM; e++) {
+        lo[e] = bx.g[e] - 1;
+        hi[e] = bx.g[e] + bx.n[e];
+    }
+    const int x0 = lo[0] + 1 + tl.a, y0 = (DIM == 3) ? lo[1] + 1 + tl.b : 0;
+    const int tx = tid % PT::TX, ty = tid / PT::TX;
+    const int x = x0 + tx, y = y0 + ty;
+    const int l = (DIM == 3) ? (ty + 1) * PT::HX + tx + 1 : tx + 1;
+    // the faces of this lane's position (per plane, the marching bounds below)
+    const bool inx = x <= hi[0] - 1, iny = DIM == 2 || y <= hi[1] - 1;
+    const bool fx = x <= hi[0] && iny;
+    const bool fy = DIM == 3 && inx && y <= hi[1];
+    const bool fm = inx && iny;
+    const int m0 = lo[AM] + 1 + tl.c, m1 = min(m0 + PT::LM - 1, hi[AM]);
+
+    int r0 = 0, r1 = 1, r2 = 2;  // ring slots of planes m-1, m, m+1
+    pf_stage<DIM>(&S[r0][0], Vb, bx, lo, hi, x0, y0, m0 - 1);
+    pf_stage<DIM>(&S[r1][0], Vb, bx, lo, hi, x0, y0, m0);
+    for (int m = m0; m <= m1; m++) {
+        pf_stage<DIM>(&S[r2][0], Vb, bx, lo, hi, x0, y0, m + 1);
+        __syncthreads();
+        const R *P[3] = { &S[r0][0], &S[r1][0], &S[r2][0] };
+        const int c = (DIM == 3) ? cidx(bx, x, y, m) : cidx(bx, x, m, 0);
+        R out[NPF];
+        const bool inm = m <= hi[AM] - 1;  // the in-plane faces' marching bound
+        auto face = [&](auto Dc) {
+            constexpr int D = decltype(Dc)::value;
+            pflux_face<DIM, D>(P, l, bx, o, out);
+            R *dst = Pb + D * NPF * cs + c;
+#pragma unroll
+            for (int q = 0; q < NPF; q++) dst[q * cs] = out[q];
+        };
+        if (fx && inm) face(std::integral_constant<int, 0>());
+        if constexpr (DIM == 3)
+            if (fy && inm) face(std::integral_constant<int, 1>());
+        if (fm) face(std::integral_constant<int, AM>());
+        __syncthreads();
+        const int rt = r0;
+        r0 = r1;
+        r1 = r2;
+        r2 = rt;
+    }
+}
+
+// (Pi_{D,+} - Pi_{D,-}) * idx of the saturated slots Fl (face below) and Fh
+// (face above), added into the nine-component P
+template <int D, typename R> __device__ __forceinline__ void pdiv_add(const R *Fl, const R *Fh, R idx, R *P)
+{
+    constexpr int t = Ax<D>::t, b = Ax<D>::b;
+#pragma unroll
+    for (int q = 0; q < 3; q++) P[MX1 + q] += (Fh[PF_M + q] - Fl[PF_M + q]) * idx;
+    P[BX1 + t] += (Fh[PF_BT] - Fl[PF_BT]) * idx;
+    P[BX1 + b] += (Fh[PF_BB] - Fl[PF_BB]) * idx;
+    P[ENG] += (Fh[PF_E] - Fl[PF_E]) * idx;
+}
+
+// k_pdiv: the divergence P = sum_d (Pi_{d,+} - Pi_{d,-}) / dx_d of Pi^n on
+// the cells of the t^n region [g-1, g+n], the conduction flux saturated with
+// the two cells' own states (the t^n Riemann inputs).  Stored per cell as the
+// seven components MX1 .. BX3 (planes 0 .. 6 of the box's face slots).
+// The tiles overlap by one column (and row): every lane solves the low faces
+// of its cell and the lanes of all but the last column (and row) difference
+// them with their neighbours' (3D: x from the next lane of the wave by a
+// cross-lane shuffle, y through LDS; 2D: x through LDS); the marching faces
+// are carried from plane to plane, so each cell is finished one plane later.
+template <int DIM, typename R>
+__global__ __launch_bounds__(NT) void k_pdiv(PArgs<R> a)
+{
+    using PT = PTile<DIM>;
+    constexpr int AM = DIM - 1;
+    constexpr int NS = PF_E + 1;  // saturated slots
+    static_assert(DIM == 2 || (PT::TX <= 64 && 64 % PT::TX == 0), "a tile row must lie within one wave");
+    __shared__ R S[3][8 * PT::HP];
+    __shared__ R Fy[(DIM == 3) ? NS : 1][(DIM == 3) ? NT : 1];
+    __shared__ R Fx2[(DIM == 2) ? NS : 1][(DIM == 2) ? NT : 1];
+    const int tid = threadIdx.x;
+    const KTile tl = a.tiles[blockIdx.x];
+    const KBox bx = a.boxes[tl.box];
+    const KOpts &o = a.o;
+    const int cs = (int)bx.cells;
+    const R *Vb = a.V + bx.woff;
+    R *Pb = a.PF + (bx.woff / NV) * (NPF * DIM);
+    int lo[3] = { 0, 0, 0 }, hi[3] = { 0, 0, 0 };
+#pragma unroll
+    for (int e = 0; e < DIM; e++) {
+        lo[e] = bx.g[e] - 2;
+        hi[e] = bx.g[e] + bx.n[e] + 1;
+    }
+    const int x0 = lo[0] + 1 + tl.a, y0 = (DIM == 3) ? lo[1] + 1 + tl.b : 0;
+    const int tx = tid % PT::TX, ty = tid / PT::TX;
+    const int x = x0 + tx, y = y0 + ty;
+    const int l = (DIM == 3) ? (ty + 1) * PT::HX + tx + 1 : tx + 1;
+    const bool iny = DIM == 2 || y <= hi[1] - 1;
+    const bool fx = x <= hi[0] && iny;
+    const bool fy = DIM == 3 && x <= hi[0] - 1 && y <= hi[1];
+    const bool fm = x <= hi[0] - 1 && iny;
+    const bool own = fm && tx < PT::TX - 1 && (DIM == 2 || ty < PT::TY - 1);
+    const int m0 = lo[AM] + 1 + tl.c, m1 = min(m0 + PT::LM - 1, hi[AM] - 1);
+    const int sM = (DIM == 3) ? bx.N[0] * bx.N[1] : bx.N[0];
+    const R ix = R(1.0 / bx.dx[0]), iy = R(1.0 / bx.dx[1]), iz = R(1.0 / bx.dx[2]);
+
+    int r0 = 0, r1 = 1, r2 = 2;  // ring slots of planes m-1, m, m+1
+    pf_stage<DIM>(&S[r0][0], Vb, bx, lo, hi, x0, y0, m0 - 1);
+    pf_stage<DIM>(&S[r1][0], Vb, bx, lo, hi, x0, y0, m0);
+    R Fm_prev[NS], Pin[NV], Fx[NS];
+#pragma unroll
+    for (int q = 0; q < NS; q++) Fx[q] = R(0);
+    for (int m = m0; m <= m1 + 1; m++) {
+        pf_stage<DIM>(&S[r2][0], Vb, bx, lo, hi, x0, y0, m + 1);
+        __syncthreads();
+        const R *P[3] = { &S[r0][0], &S[r1][0], &S[r2][0] };
+        const int c = (DIM == 3) ? cidx(bx, x, y, m) : cidx(bx, x, m, 0);
+        R out[NPF];
+        // the D-face below the lane's cell, saturated with the states of its
+        // two cells
+        auto face = [&](auto Dc) {
+            constexpr int D = decltype(Dc)::value;
+            pflux_face<DIM, D>(P, l, bx, o, out);
+            const int sD = (D == 0) ? 1 : (D == 1 ? bx.N[0] : bx.N[0] * bx.N[1]);
+            const R rA = P[(D == AM) ? 0 : 1][l - ((D == AM) ? 0 : (D == 0 ? 1 : PT::HX))];
+            const R rB = P[1][l];
+            out[PF_E] = pf_energy(out[PF_E], out[PF_FN], out[PF_FM], o, Vb[PRS * cs + c - sD], Vb[PRS * cs + c], rA, rB);
+        };
+        if (m <= m1) {
+            if (fx) {
+                face(std::integral_constant<int, 0>());
+#pragma unroll
+                for (int q = 0; q < NS; q++) {
+                    Fx[q] = out[q];
+                    if constexpr (DIM == 2) Fx2[q][tid] = out[q];
+                }
+            }
+            if constexpr (DIM == 3) {
+                if (fy) {
+                    face(std::integral_constant<int, 1>());
+#pragma unroll
+                    for (int q = 0; q < NS; q++) Fy[q][tid] = out[q];
+                }
+            }
+        }
+        R Fm[NS];
+        if (fm) {
+            face(std::integral_constant<int, AM>());
+#pragma unroll
+            for (int q = 0; q < NS; q++) Fm[q] = out[q];
+        }
+        // 3D: the x-face above the lane's cell is the next lane's (same row,
+        // same wave for the lanes that use it)
+        R Fxh[NS];
+        if constexpr (DIM == 3) {
+#pragma unroll
+            for (int q = 0; q < NS; q++) Fxh[q] = __shfl_down(Fx[q], 1);
+        }
+        __syncthreads();
+        if (own) {
+            // finish cell (x, y, m-1): its high marching face is Fm
+            if (m > m0) {
+                R Pc[NV];
+#pragma unroll
+                for (int q = 0; q < NV; q++) Pc[q] = Pin[q];
+                pdiv_add<AM>(Fm_prev, Fm, (DIM == 3) ? iz : iy, Pc);
+#pragma unroll
+                for (int q = 0; q < 7; q++) Pb[q * cs + c - sM] = Pc[MX1 + q];
+            }
+            // in-plane part of this plane's cell
+            if (m <= m1) {
+#pragma unroll
+                for (int q = 0; q < NV; q++) Pin[q] = R(0);
+                if constexpr (DIM == 2) {
+#pragma unroll
+                    for (int q = 0; q < NS; q++) Fxh[q] = Fx2[q][tid + 1];
+                }
+                pdiv_add<0>(Fx, Fxh, ix, Pin);
+                if constexpr (DIM == 3) {
+                    R Fl[NS], Fh[NS];
+#pragma unroll
+                    for (int q = 0; q < NS; q++) {
+                        Fl[q] = Fy[q][tid];
+                        Fh[q] = Fy[q][tid + PT::TX];
+                    }
+                    pdiv_add<1>(Fl, Fh, iy, Pin);
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < NS; q++) Fm_prev[q] = Fm[q];
+        }
+        const int rt = r0;
+        r0 = r1;
+        r1 = r2;
+        r2 = rt;
+    }
+}
+
+// Pi on the D-face below cell c from its slots (Pf: the box's slots), the
+// saturated conduction flux upwinded with the face states (pL, rL), (pR, rR)
+template <int D, typename R>
+__device__ __forceinline__ void parab_face(const R *Pf, int cs, int c, const KOpts &o, R pL, R pR, R rL, R rR, R *Pi)
+{
+    constexpr int t = Ax<D>::t, b = Ax<D>::b;
+    const R *f = Pf + D * NPF * cs + c;
+#pragma unroll
+    for (int q = 0; q < NV; q++) Pi[q] = R(0);
+#pragma unroll
+    for (int q = 0; q < 3; q++) Pi[MX1 + q] = f[(PF_M + q) * cs];
+    Pi[BX1 + t] = f[PF_BT * cs];
+    Pi[BX1 + b] = f[PF_BB * cs];
+    const bool tc = (o.parab & PB_TC) != 0;
+    Pi[ENG] = pf_energy(f[PF_E * cs], tc ? f[PF_FN * cs] : R(0), tc ? f[PF_FM * cs] : R(0), o, pL, pR, rL, rR);
+}
+
+
+// x^y for x > 0: in FP32 as 2^(y log2 x) with the hardware log2 and exp2
+// (the FP32 path's approximate-transcendental convention), in FP64 pow
+template <typename R> __device__ __forceinline__ R powp(R x, R y)
+{
+    if constexpr (sizeof(R) == 4) return __builtin_amdgcn_exp2f(y * __builtin_amdgcn_logf(x));
+    else return pow(x, y);
 }
 
 template <typename R> __device__ __forceinline__ R diff_coeff(const KOpts &o, R rho, R gam)
@@ -397,15 +720,17 @@ template <typename R> __device__ __forceinline__ R diff_coeff(const KOpts &o, R 
 //
 // A block owns 256 in-plane positions of the region [g-1, g+n] (x, y in 3D;
 // x in 2D) and marches along the last axis over a chunk of its planes.  For
-// each plane it solves the first-order Riemann problems R(V_j, V_{j+1})
-// (and, with parabolic terms, evaluates Pi^n) on the low faces of its
-// positions plus the faces above its last ones, hands them over through
-// LDS, and forms per cell the increments L_d = -(G_{d,+} - G_{d,-})/dx_d of
-// G = F - Pi and Lp_d = (Pi_{d,+} - Pi_{d,-})/dx_d.  The marching-axis faces
-// of one plane are the high faces of the previous one, so each cell is
-// finished one plane later.  Outputs, per cell:
-//   T_d = sum_{d' != d} L_{d'} + Lp_d     (the Eq. transv increment of sweep d)
-//   V^{n+1/2} = V(U^n + dt/2 sum_d L_d)   (parabolic runs only)
+// each plane it solves the first-order Riemann problems R(V_j, V_{j+1}) on
+// the low faces of its positions plus the faces above its last ones, hands
+// them over through LDS, and forms per cell the increments
+// L_d = -(F_{d,+} - F_{d,-})/dx_d.  The marching-axis faces of one plane are
+// the high faces of the previous one, so each cell is finished one plane
+// later.  With parabolic terms the cell also takes the divergence
+// P = sum_d (Pi_{d,+} - Pi_{d,-})/dx_d of the Pi^n face slots.  Outputs,
+// per cell:
+//   T_d = sum_{d' != d} L_{d'} + P   (the Eq. transv increment of sweep d:
+//                                     sum_{d' != d} (L_{d'} + Lp_{d'}) + Lp_d)
+//   V^{n+1/2} = V(U^n + dt/2 (sum_d L_d + P))   (parabolic runs only)
 //
 // Two in-plane layouts, chosen per tile on the host:
 //  * tile (b >= 0): a TX x TY rectangle at (a, b); the TY faces right of it
@@ -452,6 +777,7 @@ template <typename R> struct TArgs {
     const R *V;       // V^n (workspace)
     R *T[3];          // transverse increments (workspace)
     R *Vh;            // V^{n+1/2} (workspace) or null
+    const R *PF;      // divergence of Pi^n per cell, 7 planes (workspace) or null
     const unsigned char *flag;  // App. B zone flags (workspace) or null
     const double *params;
     KOpts o;
@@ -465,16 +791,16 @@ template <typename R> __device__ __forceinline__ void ld_cell(const Blk<R> &bV, 
     for (int q = 0; q < NV; q++) V[q] = bV.ld(q, c);
 }
 
-// one face: G = F - Pi (and Pi separately) on the D-face below cell (i,j,k),
+// one face: the first-order flux G = F on the D-face below cell (i,j,k),
 // from states already in registers: VL of the cell below the face, VR of
 // cell (i,j,k).  Both are copied (the solver overwrites B_n) through an
 // empty register barrier: a cell's state is shared by its three faces, and
 // without the barrier the compiler would share and contract their
 // arithmetic differently from a face solved alone, so the same face would
 // round differently under another launch shape
-template <int D, int PHYS, int RS, int PAR, int SHK, typename R>
-__device__ __forceinline__ void tface_s(const R *VL_in, const R *VR_in, const R *Vb, const KBox &bx, int i, int j,
-                                        int k, const KOpts &o, R gam, R ch, R *G, R *Pi, const unsigned char *fb)
+template <int D, int PHYS, int RS, int SHK, typename R>
+__device__ __forceinline__ void tface_s(const R *VL_in, const R *VR_in, const KBox &bx, int i, int j, int k,
+                                        const KOpts &o, R gam, R ch, R *G, const unsigned char *fb)
 {
     bool hl = false;
     if constexpr (SHK) {
@@ -490,7 +816,6 @@ __device__ __forceinline__ void tface_s(const R *VL_in, const R *VR_in, const R 
         asm volatile("" : "+v"(VL[q]));
         asm volatile("" : "+v"(VR[q]));
     }
-    R pL = VL[PRS], pR = VR[PRS], rL = VL[RHO], rR = VR[RHO];
     if (!o.hyp_off) {
         R sm;
         if (SHK && hl) riemann<D, PHYS, RS_HLL>(VL, VR, G, sm, gam, ch, o.glm, o.xspeeds);
@@ -499,25 +824,22 @@ __device__ __forceinline__ void tface_s(const R *VL_in, const R *VR_in, const R 
 #pragma unroll
         for (int q = 0; q < NV; q++) G[q] = R(0);
     }
-    if constexpr (PAR) {
-        parab_flux<D>(Vb, bx, i, j, k, o, pL, pR, rL, rR, Pi);
-#pragma unroll
-        for (int q = 0; q < NV; q++) G[q] -= Pi[q];
-    }
 }
 
+#ifndef CTU_TC_WAVES_PAR_F32
+#define CTU_TC_WAVES_PAR_F32 1
+#endif
+template <int PAR, typename R> constexpr int tc_waves() { return (PAR && sizeof(R) == 4) ? CTU_TC_WAVES_PAR_F32 : 1; }
+
 template <int DIM, int PHYS, int RS, int PAR, int VAR, typename R>
-__global__ __launch_bounds__(NT) void k_tcouple(TArgs<R> a)
+__global__ __launch_bounds__(NT, (tc_waves<PAR, R>())) void k_tcouple(TArgs<R> a)
 {
     constexpr int SHK = (VAR == VAR_SHOCK);
     constexpr int TX = TTile<DIM>::TX, TY = TTile<DIM>::TY;
     constexpr int GXS = TTile<DIM>::GXS, GYS = TTile<DIM>::GYS;
     constexpr int AM = DIM - 1;                 // marching axis
-    constexpr int NPX = PAR ? NV : 1;           // Pi planes kept only with parabolic terms
     __shared__ R Gx[NV][GXS];
-    __shared__ R Px[NPX][GXS];
     __shared__ R Gy[(DIM == 3) ? NV : 1][GYS];
-    __shared__ R Py[(DIM == 3) ? NPX : 1][GYS];
 
     const int tid = threadIdx.x;
     // lane in the wave that solves the extra faces; consecutive blocks go to
@@ -532,6 +854,7 @@ __global__ __launch_bounds__(NT) void k_tcouple(TArgs<R> a)
     const R hdt = R(0.5 * box_dt(bx, a.params));
     const int cs = (int)bx.cells;
     const R *Vb = a.V + bx.woff;
+    const R *Pf = PAR ? a.PF + (bx.woff / NV) * (NPF * DIM) : nullptr;
     const Blk<R> bV(Vb, bx.cells);
     const unsigned char *fb = SHK ? a.flag + bx.woff / NV : nullptr;
     const Blk<R> bT0(a.T[0] + bx.woff, bx.cells), bT1(a.T[1] + bx.woff, bx.cells), bT2(DIM == 3 ? a.T[2] + bx.woff : Vb, bx.cells);
@@ -607,15 +930,27 @@ __global__ __launch_bounds__(NT) void k_tcouple(TArgs<R> a)
     // loaded once and carried from plane to plane
     R Vc[NV], Vp[NV];
     if (inplane) ld_cell(bV, cidx(bx, i, (DIM == 3) ? j : m0 - 1, (DIM == 3) ? m0 - 1 : 0), Vp);
-    R Gm_prev[NV], Pm_prev[NV], Lx_prev[NV], Ly_prev[NV], Px_prev[NV], Py_prev[NV];
+    R Gm_prev[NV], Lx_prev[NV], Ly_prev[NV];
     for (int m = m0; m <= m1 + 1; m++) {
         const int cj = (DIM == 3) ? j : m, ck = (DIM == 3) ? m : 0;
+        // parabolic runs: U^n and P of the cell this plane finishes, loaded
+        // ahead of the face solves that hide their latency
+        R Upre[NV], Ppre[7];
+        if constexpr (PAR) {
+            if (inplane && m > m0) {
+                const int pc = cidx(bx, i, (DIM == 3) ? j : m - 1, (DIM == 3) ? m - 1 : 0);
+#pragma unroll
+                for (int q = 0; q < NV; q++) Upre[q] = Blk<R>(a.U + bx.uoff, bx.cells).ld(q, pc);
+#pragma unroll
+                for (int q = 0; q < 7; q++) Ppre[q] = Pf[q * cs + pc];
+            }
+        }
         // in FP32 every state this plane's faces read is loaded together, so
         // that one wait covers the three loads; in FP64 the two neighbour
         // states are loaded at their faces (held across the marching face
         // they would take the registers of the second wave per SIMD)
         constexpr bool GROUP = sizeof(R) == 4;
-        constexpr bool GROUP_E = GROUP && !PAR && !SHK && RS != RS_ROE;
+        constexpr bool GROUP_E = GROUP && !SHK && RS != RS_ROE;
         R VLx[NV], VLy[NV], VLe[NV], VRe[NV];
         if (inplane || (m <= m1 && (xf || yf))) ld_cell(bV, cidx(bx, i, cj, ck), Vc);
         if constexpr (GROUP) {
@@ -623,8 +958,8 @@ __global__ __launch_bounds__(NT) void k_tcouple(TArgs<R> a)
             if constexpr (DIM == 3)
                 if (m <= m1 && yf) ld_cell(bV, cidx(bx, i, j - 1, ck), VLy);
             // and the two states of the lane's extra face, where the registers
-            // they take keep three waves per SIMD (not with parabolic terms,
-            // shock flags or the Roe solver)
+            // they take keep three waves per SIMD (not with shock flags or the
+            // Roe solver)
             if constexpr (GROUP_E) {
                 if (m <= m1 && ed == 0) {
                     const int ej2 = (DIM == 3) ? ej : m;
@@ -639,28 +974,22 @@ __global__ __launch_bounds__(NT) void k_tcouple(TArgs<R> a)
         // ---- faces of this plane: the marching face below each region cell,
         // and the in-plane low faces of every position whose face borders the
         // region ----
-        R Gm[NV], Pm[NV];
-        if (inplane) tface_s<AM, PHYS, RS, PAR, SHK>(Vp, Vc, Vb, bx, i, cj, ck, o, gam, ch, Gm, Pm, fb);
+        R Gm[NV];
+        if (inplane) tface_s<AM, PHYS, RS, SHK>(Vp, Vc, bx, i, cj, ck, o, gam, ch, Gm, fb);
         if (m <= m1) {
-            R G[NV], P[NV];
+            R G[NV];
             if (xf) {
                 if constexpr (!GROUP) ld_cell(bV, cidx(bx, i - 1, cj, ck), VLx);
-                tface_s<0, PHYS, RS, PAR, SHK>(VLx, Vc, Vb, bx, i, cj, ck, o, gam, ch, G, P, fb);
+                tface_s<0, PHYS, RS, SHK>(VLx, Vc, bx, i, cj, ck, o, gam, ch, G, fb);
 #pragma unroll
-                for (int q = 0; q < NV; q++) {
-                    Gx[q][lx] = G[q];
-                    if (PAR) Px[q][lx] = P[q];
-                }
+                for (int q = 0; q < NV; q++) Gx[q][lx] = G[q];
             }
             if constexpr (DIM == 3) {
                 if (yf) {
                     if constexpr (!GROUP) ld_cell(bV, cidx(bx, i, j - 1, ck), VLy);
-                    tface_s<1, PHYS, RS, PAR, SHK>(VLy, Vc, Vb, bx, i, cj, ck, o, gam, ch, G, P, fb);
+                    tface_s<1, PHYS, RS, SHK>(VLy, Vc, bx, i, cj, ck, o, gam, ch, G, fb);
 #pragma unroll
-                    for (int q = 0; q < NV; q++) {
-                        Gy[q][ly] = G[q];
-                        if (PAR) Py[q][ly] = P[q];
-                    }
+                    for (int q = 0; q < NV; q++) Gy[q][ly] = G[q];
                 }
             }
             // the extra faces
@@ -670,23 +999,17 @@ __global__ __launch_bounds__(NT) void k_tcouple(TArgs<R> a)
                     ld_cell(bV, cidx(bx, ei - 1, ej2, ck), VLe);
                     ld_cell(bV, cidx(bx, ei, ej2, ck), VRe);
                 }
-                tface_s<0, PHYS, RS, PAR, SHK>(VLe, VRe, Vb, bx, ei, ej2, ck, o, gam, ch, G, P, fb);
+                tface_s<0, PHYS, RS, SHK>(VLe, VRe, bx, ei, ej2, ck, o, gam, ch, G, fb);
 #pragma unroll
-                for (int q = 0; q < NV; q++) {
-                    Gx[q][es] = G[q];
-                    if (PAR) Px[q][es] = P[q];
-                }
+                for (int q = 0; q < NV; q++) Gx[q][es] = G[q];
             } else if (DIM == 3 && ed == 1) {
                 if constexpr (!GROUP_E) {
                     ld_cell(bV, cidx(bx, ei, ej - 1, m), VLe);
                     ld_cell(bV, cidx(bx, ei, ej, m), VRe);
                 }
-                tface_s<(DIM == 3 ? 1 : 0), PHYS, RS, PAR, SHK>(VLe, VRe, Vb, bx, ei, ej, m, o, gam, ch, G, P, fb);
+                tface_s<(DIM == 3 ? 1 : 0), PHYS, RS, SHK>(VLe, VRe, bx, ei, ej, m, o, gam, ch, G, fb);
 #pragma unroll
-                for (int q = 0; q < NV; q++) {
-                    Gy[q][es] = G[q];
-                    if (PAR) Py[q][es] = P[q];
-                }
+                for (int q = 0; q < NV; q++) Gy[q][es] = G[q];
             }
         }
         __syncthreads();
@@ -696,26 +1019,40 @@ __global__ __launch_bounds__(NT) void k_tcouple(TArgs<R> a)
                 const int pj = (DIM == 3) ? j : m - 1, pk = (DIM == 3) ? m - 1 : 0;
                 const int c = cidx(bx, i, pj, pk);
                 const R im = (DIM == 3) ? iz : iy;
+                // parabolic runs: the divergence P of Pi^n (k_pdiv), which
+                // enters every T_d and the half step in full (Eq. transv: the
+                // bracket's sum over d' != d of L_H plus the sum of L_P over
+                // all d)
+                R Pd[NV];
+                if constexpr (PAR) {
+                    Pd[RHO] = R(0);
+                    Pd[PSI] = R(0);
+#pragma unroll
+                    for (int q = 0; q < 7; q++) Pd[MX1 + q] = Ppre[q];
+                }
+                auto addp = [&](R x, int q) -> R {
+                    if constexpr (PAR) return x + Pd[q];
+                    else return x;
+                };
                 R Lm[NV], S[NV];
 #pragma unroll
                 for (int q = 0; q < NV; q++) {
                     Lm[q] = -(Gm[q] - Gm_prev[q]) * im;
-                    R Lpm = PAR ? (Pm[q] - Pm_prev[q]) * im : R(0);
                     if constexpr (DIM == 3) {
-                        bT0.st(q, c, Ly_prev[q] + Lm[q] + (PAR ? Px_prev[q] : R(0)));
-                        bT1.st(q, c, Lx_prev[q] + Lm[q] + (PAR ? Py_prev[q] : R(0)));
-                        bT2.st(q, c, Lx_prev[q] + Ly_prev[q] + Lpm);
-                        S[q] = Lx_prev[q] + Ly_prev[q] + Lm[q];
+                        bT0.st(q, c, addp(Ly_prev[q] + Lm[q], q));
+                        bT1.st(q, c, addp(Lx_prev[q] + Lm[q], q));
+                        bT2.st(q, c, addp(Lx_prev[q] + Ly_prev[q], q));
+                        S[q] = addp(Lx_prev[q] + Ly_prev[q] + Lm[q], q);
                     } else {
-                        bT0.st(q, c, Lm[q] + (PAR ? Px_prev[q] : R(0)));
-                        bT1.st(q, c, Lx_prev[q] + Lpm);
-                        S[q] = Lx_prev[q] + Lm[q];
+                        bT0.st(q, c, addp(Lm[q], q));
+                        bT1.st(q, c, addp(Lx_prev[q], q));
+                        S[q] = addp(Lx_prev[q] + Lm[q], q);
                     }
                 }
                 if constexpr (PAR) {
                     R u[NV], v[NV];
 #pragma unroll
-                    for (int q = 0; q < NV; q++) u[q] = Blk<R>(a.U + bx.uoff, bx.cells).ld(q, c) + hdt * S[q];
+                    for (int q = 0; q < NV; q++) u[q] = Upre[q] + hdt * S[q];
                     c2p<PHYS_MHD>(u, v, gam);
 #pragma unroll
                     for (int q = 0; q < NV; q++) Blk<R>(a.Vh + bx.woff, bx.cells).st(q, c, v[q]);
@@ -726,17 +1063,12 @@ __global__ __launch_bounds__(NT) void k_tcouple(TArgs<R> a)
 #pragma unroll
                 for (int q = 0; q < NV; q++) {
                     Lx_prev[q] = -(Gx[q][lx + 1] - Gx[q][lx]) * ix;
-                    if (PAR) Px_prev[q] = (Px[q][lx + 1] - Px[q][lx]) * ix;
-                    if constexpr (DIM == 3) {
-                        Ly_prev[q] = -(Gy[q][ly + sy] - Gy[q][ly]) * iy;
-                        if (PAR) Py_prev[q] = (Py[q][ly + sy] - Py[q][ly]) * iy;
-                    }
+                    if constexpr (DIM == 3) Ly_prev[q] = -(Gy[q][ly + sy] - Gy[q][ly]) * iy;
                 }
             }
 #pragma unroll
             for (int q = 0; q < NV; q++) {
                 Gm_prev[q] = Gm[q];
-                if (PAR) Pm_prev[q] = Pm[q];
                 Vp[q] = Vc[q];
             }
         }
@@ -933,6 +1265,7 @@ template <typename R> struct SweepArgs {
     const R *V;       // V^n (workspace)
     const R *T[3];    // transverse increments of Eq. transv (workspace)
     const R *Vh;      // V^{n+1/2} (workspace) or null
+    const R *PF;      // parabolic face slots of V^{n+1/2} (workspace) or null
     R *lam;           // per-cell rate accumulator (workspace, parabolic only)
     const R *L0;      // cooling coefficient (caller layout / 9) or null
     const unsigned char *leaf;  // cells entering max |dp/p| (caller layout / 9) or null = all
@@ -949,16 +1282,26 @@ template <typename R> struct SweepArgs {
 // Waves per SIMD the sweep is compiled for: the register budget is 512 /
 // waves VGPRs.  FP32 fits two waves without spills; FP64 spills some of its
 // doubled state at two waves, which measures faster on MI355X than one
-// spill-free wave (13.5 vs 17.1 ms for a 256^3 step).
+// spill-free wave (13.5 vs 17.1 ms for a 256^3 step).  The FP32 par variant
+// (non-ideal runs) needs ~180 registers: three waves with a few dozen bytes
+// of spills measure 12 % faster than two waves on the x and y sweeps.
 #ifndef CTU_SWEEP_WAVES_F32
 #define CTU_SWEEP_WAVES_F32 2
 #endif
 #ifndef CTU_SWEEP_WAVES_F64
 #define CTU_SWEEP_WAVES_F64 2
 #endif
+#ifndef CTU_SWEEP_WAVES_PAR_F32
+#define CTU_SWEEP_WAVES_PAR_F32 3
+#endif
+template <int VAR, typename R> constexpr int sweep_waves()
+{
+    if constexpr (sizeof(R) == 8) return CTU_SWEEP_WAVES_F64;
+    else return VAR == VAR_PAR ? CTU_SWEEP_WAVES_PAR_F32 : CTU_SWEEP_WAVES_F32;
+}
 
 template <int D, int PHYS, int PRED, int RK, int RS, int VAR, typename R>
-__global__ __launch_bounds__(NT, (sizeof(R) == 4 ? CTU_SWEEP_WAVES_F32 : CTU_SWEEP_WAVES_F64)) void k_sweep(
+__global__ __launch_bounds__(NT, (sweep_waves<VAR, R>())) void k_sweep(
     SweepArgs<R> a)
 {
     constexpr int SHK = (VAR == VAR_SHOCK);
@@ -1014,6 +1357,14 @@ __global__ __launch_bounds__(NT, (sizeof(R) == 4 ? CTU_SWEEP_WAVES_F32 : CTU_SWE
     const Blk<R> bT(a.T[D] + bx.woff, bx.cells);
     const unsigned char *fb = SHK ? a.flag + bx.woff / NV : nullptr;
     double rate_loc = 0.0, dpp_loc = 0.0;
+    // last sweep: the cooling exponent 1 - beta and the floor's T^(1-beta);
+    // the diffusive rate factor sum_d 2 / dx_d^2 of Eq. Ca
+    const R com = R(1) - R(o.cool_beta);
+    const R cxf = (a.last && o.cooling) ? powp(R(o.T_floor), com) : R(0);
+    double rdx2 = 0.0;
+#pragma unroll
+    for (int e = 0; e < 3; e++)
+        if (e < dim) rdx2 += 2.0 / (bx.dx[e] * bx.dx[e]);
 
     for (int base = 0; base < items; base += NT) {
         const int kit = base + tid;
@@ -1109,7 +1460,7 @@ __global__ __launch_bounds__(NT, (sizeof(R) == 4 ? CTU_SWEEP_WAVES_F32 : CTU_SWE
             }
             if (o.parab) {
                 R Pi[NV];
-                parab_flux<D>(a.Vh + bx.woff, bx, ci, cj, ck, o, pL, pR, rL, rR, Pi);
+                parab_face<D>(a.PF + (bx.woff / NV) * (NPF * dim), cs, c, o, pL, pR, rL, rR, Pi);
 #pragma unroll
                 for (int q = 0; q < NV; q++) F[q] -= Pi[q];
             }
@@ -1170,11 +1521,9 @@ __global__ __launch_bounds__(NT, (sizeof(R) == 4 ? CTU_SWEEP_WAVES_F32 : CTU_SWE
                     c2p<PHYS_MHD>(u, v, gam);
                     R T = v[PRS] / v[RHO];
                     if (T > R(o.T_floor)) {
-                        R om = R(1) - R(o.cool_beta);
-                        R x = pow(T, om) - om * (gam - R(1)) * v[RHO] * a.L0[bx.uoff / NV + cu] * dt;
-                        R xf = pow(R(o.T_floor), om);
-                        x = fmax(x, xf);
-                        R pn = v[RHO] * pow(x, R(1) / om);
+                        R x = powp(T, com) - com * (gam - R(1)) * v[RHO] * a.L0[bx.uoff / NV + cu] * dt;
+                        x = fmax(x, cxf);
+                        R pn = v[RHO] * powp(x, R(1) / com);
                         u[ENG] += (pn - v[PRS]) / (gam - R(1));
                         if (!a.leaf || a.leaf[bx.uoff / NV + cu])
                             dpp_loc = fmax(dpp_loc, (double)(fabs(pn - v[PRS]) / v[PRS]));
@@ -1183,10 +1532,7 @@ __global__ __launch_bounds__(NT, (sizeof(R) == 4 ? CTU_SWEEP_WAVES_F32 : CTU_SWE
                 double r = (double)lamt;
                 if (o.parab) {
                     R rho_h = a.Vh[bx.woff + RHO * cs + cu];
-                    R Dc = diff_coeff(o, rho_h, gam);
-#pragma unroll
-                    for (int e = 0; e < 3; e++)
-                        if (e < dim) r += 2.0 * (double)Dc / (bx.dx[e] * bx.dx[e]);
+                    r += (double)diff_coeff(o, rho_h, gam) * rdx2;
                 }
                 rate_loc = fmax(rate_loc, r);
             } else if (!o.parab) {

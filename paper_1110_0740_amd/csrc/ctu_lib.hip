@@ -115,9 +115,11 @@ struct ctu_plan {
     int64_t ws_cells = 0;  // sum of ghosted cells
     TileSet t_cells, t_tc, t_sweep[3], t_cfl;
     TileSet t_mt[3];  // MT corner coupling: 4 x 64 face tiles per direction
+    TileSet t_pf, t_pd;  // parabolic fluxes: k_pflux / k_pdiv tiles (in-plane tiles by marching chunks)
     // workspace fields: V^n, the transverse increments T_d, V^{n+1/2}, rate
     void *wsV = nullptr, *wsT[3] = { nullptr, nullptr, nullptr };
     void *wsVh = nullptr, *wsLam = nullptr;
+    void *wsPF = nullptr;  // parabolic face slots (NPF per face, dim faces per cell)
     void *wsF[3] = { nullptr, nullptr, nullptr };  // MT corner coupling: predictor fluxes per direction
     unsigned char *wsFlag = nullptr;  // App. B zone flags (one byte per cell) or null
     int64_t ws_bytes = 0;      // bytes of the workspace block the option set needs
@@ -159,7 +161,7 @@ void free_plan(ctu_plan *p)
     if (p->graph) (void)hipGraphDestroy(p->graph);
     void *ptrs[] = { p->dboxes, p->dregs, p->drface, p->t_cells.d, p->t_tc.d, p->t_sweep[0].d, p->t_sweep[1].d,
                      p->t_sweep[2].d, p->t_cfl.d, p->ws_block, p->drefl, p->dcell_start, p->t_mt[0].d, p->t_mt[1].d,
-                     p->t_mt[2].d };
+                     p->t_mt[2].d, p->t_pf.d, p->t_pd.d };
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
     delete p;
@@ -361,6 +363,20 @@ void add_mt_tiles(TileSet &ts, int b, const KBox &bx, int D, int dim)
     }
 }
 
+// Parabolic flux tiles: TX x TY in-plane cells by LM planes.  k_pflux: the
+// n + 1 face cells g .. g+n per axis, tiles side by side; k_pdiv: the n + 2
+// region cells g-1 .. g+n, tiles overlapping by one column (and row).
+void add_pf_tiles(TileSet &ts, int b, const KBox &bx, int dim, bool div)
+{
+    const int TX = (dim == 3) ? PTile<3>::TX : PTile<2>::TX, TY = (dim == 3) ? PTile<3>::TY : PTile<2>::TY;
+    const int LM = (dim == 3) ? PTile<3>::LM : PTile<2>::LM;
+    const int k = div ? 2 : 1, sx = div ? TX - 1 : TX, sy = (div && dim == 3) ? TY - 1 : TY;
+    const int ex = bx.n[0] + k, ey = (dim == 3) ? bx.n[1] + k : 1, em = bx.n[dim - 1] + k;
+    for (int m0 = 0; m0 < em; m0 += LM)
+        for (int y0 = 0; y0 < ey; y0 += sy)
+            for (int x0 = 0; x0 < ex; x0 += sx) ts.h.push_back({ b, x0, y0, m0 });
+}
+
 ctu_status build_tables(ctu_plan *p)
 {
     const int dim = p->opts.dim;
@@ -371,9 +387,15 @@ ctu_status build_tables(ctu_plan *p)
         add_linear_tiles(p->t_cfl, b, (long long)bx.n[0] * bx.n[1] * bx.n[2]);
         if (mt)
             for (int D = 0; D < dim; D++) add_mt_tiles(p->t_mt[D], b, bx, D, dim);
+        if (p->opts.parabolic_mask) {
+            add_pf_tiles(p->t_pf, b, bx, dim, false);
+            add_pf_tiles(p->t_pd, b, bx, dim, true);
+        }
     }
+    xcd_order(p->t_pf.h);
+    xcd_order(p->t_pd.h);
     ctu_status st;
-    TileSet *all[] = { &p->t_cells, &p->t_cfl, &p->t_mt[0], &p->t_mt[1], &p->t_mt[2] };
+    TileSet *all[] = { &p->t_cells, &p->t_cfl, &p->t_mt[0], &p->t_mt[1], &p->t_mt[2], &p->t_pf, &p->t_pd };
     for (TileSet *ts : all)
         if (!ts->h.empty() && (st = upload(ts->h, &ts->d)) != CTU_OK) return st;
     if ((st = reserve_shape_tables(p)) != CTU_OK) return st;
@@ -382,8 +404,9 @@ ctu_status build_tables(ctu_plan *p)
 
 // Workspace fields of the option set, in block order, each starting on a
 // 256-byte boundary: V^n (9 per cell), T_d per direction, with parabolic
-// terms V^{n+1/2} and the per-cell rate, with the MT coupling the predictor
-// fluxes per direction, with the App. B hybrid one flag byte per cell.
+// terms V^{n+1/2}, the per-cell rate and the face slots (NPF per face, one
+// face per direction and cell), with the MT coupling the predictor fluxes
+// per direction, with the App. B hybrid one flag byte per cell.
 // With base == null only the size is computed.
 int64_t carve_ws(ctu_plan *p, char *base)
 {
@@ -399,6 +422,7 @@ int64_t carve_ws(ctu_plan *p, char *base)
     if (p->opts.parabolic_mask) {
         take(base ? &p->wsVh : &dummy, f9);
         take(base ? &p->wsLam : &dummy, p->ws_cells * p->esize);
+        take(base ? &p->wsPF : &dummy, (int64_t)NPF * p->opts.dim * p->ws_cells * p->esize);
     }
     if (p->opts.corner == CTU_CORNER_MT)
         for (int d = 0; d < p->opts.dim; d++) take(base ? &p->wsF[d] : &dummy, f9);
@@ -441,6 +465,22 @@ struct StageTimer {
         if (ev) (void)hipEventRecord(ev[1], s);
     }
 };
+
+// the parabolic fluxes over the plan's boxes: div = 1, k_pdiv on V^n (the
+// Pi^n divergence per cell of the t^n region); div = 0, k_pflux on
+// V^{n+1/2} (the sweeps' face slots).  Both write the wsPF field.
+template <typename R> hipError_t launch_pflux(ctu_plan *p, const R *V, int div, hipStream_t s)
+{
+    PArgs<R> pa;
+    const TileSet &ts = div ? p->t_pd : p->t_pf;
+    pa.boxes = p->dboxes;
+    pa.tiles = ts.d;
+    pa.V = V;
+    pa.PF = (R *)p->wsPF;
+    pa.o = p->ko;
+    if constexpr (sizeof(R) == 4) return launch_pflux_f32(p->opts.dim, div, (int)ts.n(), pa, s);
+    else return launch_pflux_f64(p->opts.dim, div, (int)ts.n(), pa, s);
+}
 
 template <typename R>
 ctu_status enqueue_step(ctu_plan *p, const void *U_in, void *U_out, const double *params, const void *L0, double *reg,
@@ -495,6 +535,10 @@ ctu_status enqueue_step(ctu_plan *p, const void *U_in, void *U_out, const double
         else hipLaunchKernelGGL((k_mtT<2, R>), dim3(p->t_cells.n()), dim3(NT), 0, s, ma);
         HIP_TRY(hipGetLastError());
     } else {
+        if (par) {
+            StageTimer tm(p, 2, s);
+            HIP_TRY(launch_pflux(p, (const R *)p->wsV, 1, s));
+        }
         StageTimer tm(p, 1, s);
         TArgs<R> ta;
         ta.boxes = p->dboxes;
@@ -503,6 +547,7 @@ ctu_status enqueue_step(ctu_plan *p, const void *U_in, void *U_out, const double
         ta.V = (const R *)p->wsV;
         for (int d = 0; d < 3; d++) ta.T[d] = (R *)p->wsT[d];
         ta.Vh = (R *)p->wsVh;
+        ta.PF = (const R *)p->wsPF;
         ta.flag = p->wsFlag;
         ta.params = params;
         ta.o = p->ko;
@@ -514,6 +559,10 @@ ctu_status enqueue_step(ctu_plan *p, const void *U_in, void *U_out, const double
             e = launch_tcouple_f64(dim, par ? 1 : 0, p->combo, p->t_tc.n(), ta, s);
         if (e != hipSuccess) return fail(CTU_ERR_HIP, std::string("t^n kernel launch: ") + hipGetErrorString(e));
     }
+    if (par) {
+        StageTimer tm(p, 3, s);
+        HIP_TRY(launch_pflux(p, (const R *)p->wsVh, 0, s));
+    }
     SweepArgs<R> a;
     a.boxes = p->dboxes;
     a.regs = p->dregs;
@@ -523,6 +572,7 @@ ctu_status enqueue_step(ctu_plan *p, const void *U_in, void *U_out, const double
     a.V = (const R *)p->wsV;
     for (int d = 0; d < 3; d++) a.T[d] = (const R *)p->wsT[d];
     a.Vh = (const R *)p->wsVh;
+    a.PF = (const R *)p->wsPF;
     a.lam = (R *)p->wsLam;
     a.L0 = (const R *)L0;
     a.leaf = p->leaf;
@@ -650,7 +700,9 @@ static ctu_status create_plan(int32_t dev, uint32_t flags, const ctu_opts *opts,
     c.rk = (o.recon == CTU_PPM) ? RK_PPM : (o.recon == CTU_WENO3 ? RK_WENO : RK_LIN);
     c.rs = o.riemann;
     c.shk = o.shock_eps > 0.0 ? 1 : 0;
-    c.fast = (o.wref == CTU_WREF_FACE && o.glm && !o.hyperbolic_off && !o.parabolic_mask && !o.cooling && !c.shk) ? 1 : 0;
+    const bool fixed = o.wref == CTU_WREF_FACE && o.glm && !o.hyperbolic_off && !c.shk;
+    c.fast = (fixed && !o.parabolic_mask && !o.cooling) ? 1 : 0;
+    c.par = (fixed && (o.parabolic_mask || o.cooling)) ? 1 : 0;
     if ((o.riemann == CTU_RUSANOV || o.riemann == CTU_HLLC || o.riemann == CTU_ROE) && c.shk)
         return fail(CTU_ERR_UNSUPPORTED, "the shock-adaptive hybrid (HLL on flagged faces) needs HLLD or HLL");
     if (o.physics == CTU_RMHD && o.riemann == CTU_ROE)

@@ -39,7 +39,7 @@ PLAN_CALLER_WORKSPACE = 1
 PLAN_LEVEL_DT = 2
 TC_LAYOUT = {"auto": 0, "tiles": 1, "flat": 2}
 NSTAGE = 8
-STAGES = ["prim", "tcouple", "unused2", "unused3", "unused4", "sweep_x", "sweep_y", "sweep_z"]
+STAGES = ["prim", "tcouple", "pdiv", "pflux", "unused4", "sweep_x", "sweep_y", "sweep_z"]
 
 
 class CtuOpts(C.Structure):
