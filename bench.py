@@ -38,6 +38,10 @@ sys.path.insert(0, ROOT)
 
 METRIC = "zone-updates/sec per CTU step (FP32 batched vs FP64 plain) + achieved HBM GB/s"
 NG = 4
+# the AMR legs' ghost width: the PPM CTU stencil's minimum (the plan refuses
+# fewer); on 16-32 cell patches a fourth layer would add ~30 % more ghost
+# cells to fill and to recover
+NG_AMR = 3
 
 # Algorithmic FLOP per interior zone (add, mul, div, sqrt, transcendental;
 # FMA = 2) of what each kernel computes, from the op-counting build of the
@@ -251,7 +255,7 @@ def subbox_cells(T, N, lo, m):
     return np.ascontiguousarray(v.cpu().numpy().astype(np.float64))
 
 
-def parity_norms(pairs, ch, physics, dim):
+def parity_norms(pairs, ch, physics, dim, ng=NG):
     """(max over variables of sum|got - ref| / S_q, max over variables of
     max|got - ref| / M_q) over the interiors of (got, ref) sub-box pairs:
     S_q = sum|ref_q|, M_q = max|ref_q|; psi against c_h |B| / 3; for RMHD
@@ -261,8 +265,8 @@ def parity_norms(pairs, ch, physics, dim):
 
     def inner(a):
         if dim == 2:
-            return a[:, :, NG:-NG, NG:-NG].reshape(9, -1)
-        return a[:, NG:-NG, NG:-NG, NG:-NG].reshape(9, -1)
+            return a[:, :, ng:-ng, ng:-ng].reshape(9, -1)
+        return a[:, ng:-ng, ng:-ng, ng:-ng].reshape(9, -1)
 
     g = np.concatenate([inner(a) for a, _ in pairs], axis=1)
     r = np.concatenate([inner(b) for _, b in pairs], axis=1)
@@ -289,9 +293,9 @@ class Samples:
     def __init__(self):
         self.items = {}
 
-    def add(self, leg, okw, dx, dt, ch, ins, outs, L0s=None, physics="mhd", dim=3, chain=None):
+    def add(self, leg, okw, dx, dt, ch, ins, outs, L0s=None, physics="mhd", dim=3, chain=None, ng=NG):
         self.items[leg] = dict(okw=okw, dx=dx, dt=dt, ch=ch, ins=ins, outs=outs, L0s=L0s, physics=physics, dim=dim,
-                               chain=chain)
+                               chain=chain, ng=ng)
 
 
 # ---------------------------------------------------------------------------
@@ -575,7 +579,7 @@ def leg_c5(args, dev, s, samples):
 
 def leg_c3(args, dev, s, samples):
     """AMR: 3 levels, ratio 2, 64 / 442 / 951 patches of 16-32 cells around
-    eight density blobs (1,457 patches, 17.4 M zones; 4 ghosts, fields at
+    eight density blobs (1,457 patches, 17.4 M zones; 3 ghosts, fields at
     each level's resolution).  One AMR batch step = one CTU step of every
     patch of every level, each by its level's step dt0 / 2^l, with FP64 flux
     registers on the coarse-fine faces, plus the consuming reflux of the two
@@ -604,11 +608,11 @@ def leg_c3(args, dev, s, samples):
             o, off = 0, []
             for B in L:
                 off.append(o)
-                o += 9 * int(np.prod([x + 2 * NG for x in B.n]))
-            V = I.amr_level_fields_torch(h, lev, NG, device=dev)
+                o += 9 * int(np.prod([x + 2 * NG_AMR for x in B.n]))
+            V = I.amr_level_fields_torch(h, lev, NG_AMR, device=dev)
             assert V.numel() == o
             tmp = ctu.Plan(ctu.make_opts(dim=3, gamma=5.0 / 3.0, dx=h.dx(0), precision="fp64", **okw),
-                           [(B.lo, B.n, lev, ob) for B, ob in zip(L, off)], NG)
+                           [(B.lo, B.n, lev, ob) for B, ob in zip(L, off)], NG_AMR)
             U = torch.empty_like(V)
             tmp.prim_to_cons(V, U)
             U64.append(U)
@@ -621,10 +625,10 @@ def leg_c3(args, dev, s, samples):
 
     log("C3: configured hierarchy (1,457 patches)")
     h = I.amr_hierarchy()
-    tables, nslots = amr.build_tables(h.levels, h.base, NG)
+    tables, nslots = amr.build_tables(h.levels, h.base, NG_AMR)
     nlev = len(h.levels)
     zones_l = [int(sum(int(np.prod(B.n)) for B in L)) for L in h.levels]
-    ghost_l = [int(sum(int(np.prod([x + 2 * NG for x in B.n])) for B in L)) for L in h.levels]
+    ghost_l = [int(sum(int(np.prod([x + 2 * NG_AMR for x in B.n])) for B in L)) for L in h.levels]
     zones = sum(zones_l)
     npatch = sum(len(L) for L in h.levels)
     U64, offs, V64 = level_states(h, keep_prim=True)
@@ -637,7 +641,7 @@ def leg_c3(args, dev, s, samples):
     plans, Uin, Uout, shapes = [], [], [], []
     for lev, L in enumerate(h.levels):
         p = ctu.Plan(ctu.make_opts(dim=3, gamma=5.0 / 3.0, dx=h.dx(0), precision="fp32", **okw),
-                     [(B.lo, B.n, lev, ob) for B, ob in zip(L, offs[lev])], NG, regfaces=tables[lev].regfaces,
+                     [(B.lo, B.n, lev, ob) for B, ob in zip(L, offs[lev])], NG_AMR, regfaces=tables[lev].regfaces,
                      reflux=tables[lev].reflux or None)
         plans.append(p)
         Uin.append(U64[lev].to(torch.float32))
@@ -667,7 +671,7 @@ def leg_c3(args, dev, s, samples):
     for lev in range(nlev):
         for bi in rng.choice(len(h.levels[lev]), size=3, replace=False):
             B = h.levels[lev][int(bi)]
-            shp = (9,) + tuple(x + 2 * NG for x in reversed(B.n))
+            shp = (9,) + tuple(x + 2 * NG_AMR for x in reversed(B.n))
             o = offs[lev][int(bi)]
             cnt = int(np.prod(shp))
             sample.append((lev, V64[lev][o:o + cnt].cpu().numpy().reshape(shp),
@@ -699,7 +703,7 @@ def leg_c3(args, dev, s, samples):
     allb = [(B.lo, B.n, lev, lbase[lev] + ob) for lev, L in enumerate(h.levels) for B, ob in zip(L, offs[lev])]
     regs = [(bbase[lev] + bb, d, f, tlo, tn, sl) for lev in range(nlev) for (bb, d, f, tlo, tn, sl) in tables[lev].regfaces]
     refl = [(bbase[lev] + cb, loc, d, sg, cs, fs) for lev in range(nlev) for (cb, loc, d, sg, cs, fs) in tables[lev].reflux]
-    one = ctu.Plan(ctu.make_opts(dim=3, gamma=5.0 / 3.0, dx=h.dx(0), precision="fp32", **okw), allb, NG,
+    one = ctu.Plan(ctu.make_opts(dim=3, gamma=5.0 / 3.0, dx=h.dx(0), precision="fp32", **okw), allb, NG_AMR,
                    regfaces=regs, reflux=refl, level_dt=True)
     p0 = params[0]
     shape1 = one.autotune(Ucat, Uocat, p0, reps=5, stream=s)[0] if not args.no_autotune else one.get_shape()[0]
@@ -734,7 +738,7 @@ def leg_c3(args, dev, s, samples):
     for lev in range(nlev):
         ins = [x for (l, x, _) in sample if l == lev]
         outs_ = [y for (l, _, y) in sample if l == lev]
-        samples.add(f"c3_level{lev}_fp32", okw, h.dx(lev), dt0 / (1 << lev), ch, ins, outs_)
+        samples.add(f"c3_level{lev}_fp32", okw, h.dx(lev), dt0 / (1 << lev), ch, ins, outs_, ng=NG_AMR)
     del one, Uin, Uout, Ucat, Uocat
     torch.cuda.synchronize()
     # FP64 plain, one plan per patch
@@ -746,12 +750,12 @@ def leg_c3(args, dev, s, samples):
     # the subcycled level cycle on the nested hierarchy
     log("C3: subcycled level cycle (nested hierarchy)")
     hn = I.amr_hierarchy(nest=3)
-    tn, nsn = amr.build_tables(hn.levels, hn.base, NG)
+    tn, nsn = amr.build_tables(hn.levels, hn.base, NG_AMR)
     U64n, offsn, _ = level_states(hn)
     paramsn = [torch.tensor([dt0 / (1 << lev), ch], dtype=torch.float64, device=dev) for lev in range(nlev)]
     regn = torch.zeros(9 * nsn, dtype=torch.float64, device=dev)
     plans_n = [ctu.Plan(ctu.make_opts(dim=3, gamma=5.0 / 3.0, dx=hn.dx(0), precision="fp32", **okw),
-                        [(B.lo, B.n, lev, ob) for B, ob in zip(L, offsn[lev])], NG, regfaces=tn[lev].regfaces,
+                        [(B.lo, B.n, lev, ob) for B, ob in zip(L, offsn[lev])], NG_AMR, regfaces=tn[lev].regfaces,
                         reflux=tn[lev].reflux or None) for lev, L in enumerate(hn.levels)]
     Ua = [u.to(torch.float32) for u in U64n]
     Ub = [u.clone() for u in Ua]
@@ -759,7 +763,7 @@ def leg_c3(args, dev, s, samples):
     cyc_shapes = [p.autotune(Ua[lev], Ub[lev], paramsn[lev], reps=5, stream=s)[0] if not args.no_autotune
                   else p.get_shape()[0] for lev, p in enumerate(plans_n)]
     hier = ctu.Hier("fp32", hn.base, [[(B.lo, B.n, ob) for B, ob in zip(L, offsn[lev])]
-                                      for lev, L in enumerate(hn.levels)], NG)
+                                      for lev, L in enumerate(hn.levels)], NG_AMR)
     rate_l = torch.zeros(nlev, dtype=torch.float64, device=dev)
     fails_acc = torch.zeros(5, dtype=torch.int32, device=dev)
     missing = torch.zeros(1, dtype=torch.int32, device=dev)
@@ -788,7 +792,7 @@ def c3_per_patch(h, U64, params, offs, okw, zones, ghost_l, npatch, b, s, K, W):
     for lev, L in enumerate(h.levels):
         go = ctu.make_opts(dim=3, gamma=5.0 / 3.0, dx=h.dx(0), precision="fp64", **okw)
         for B, ob in zip(L, offs[lev]):
-            pplans.append((lev, ctu.Plan(go, [(B.lo, B.n, lev, ob)], NG)))
+            pplans.append((lev, ctu.Plan(go, [(B.lo, B.n, lev, ob)], NG_AMR)))
     Uo64 = [torch.empty_like(u) for u in U64]
     torch.cuda.synchronize()
 
@@ -864,10 +868,10 @@ def cpu_baseline(timing_boxes, c2_params, samples):
             o = O.make_opts(dim=3, gamma=gam, dx=it["dx"], **it["okw"])
             for k, (Vi, Ug) in enumerate(zip(it["ins"], it["outs"])):
                 L0 = it["L0s"][k] if it["L0s"] else None
-                ref, _, _, f = O.step(o, O.prim2cons(o, Vi), NG, it["dt"], it["ch"], L0=L0)
+                ref, _, _, f = O.step(o, O.prim2cons(o, Vi), it["ng"], it["dt"], it["ch"], L0=L0)
                 pairs.append((Ug, ref))
             ch_last = it["ch"]
-        e, c = parity_norms(pairs, ch_last, it["physics"], it["dim"])
+        e, c = parity_norms(pairs, ch_last, it["physics"], it["dim"], it["ng"])
         l1[leg] = {"l1_rel": e, "cell_rel": c, "subboxes": len(pairs)}
     return base, l1
 

@@ -1,7 +1,8 @@
 """GPU parity of the batched AMR step on the configured hierarchy: 3 levels,
 ratio 2, 64 / 442 / 951 boxes of 16-32 cells around eight density blobs
 (1,457 patches, 17.4 M zones), one plan per level, FP64 flux registers and
-refluxing (Sec. 4, Eq. fluxcorr, Eq. addreflux), as the benchmark runs it.
+refluxing (Sec. 4, Eq. fluxcorr, Eq. addreflux), as the benchmark runs it
+(3 ghost cells, the PPM stencil's minimum).
 
 The oracle recomputes 36 seeded patches (12 per level, boxes with reflux
 entries among them): their updated states, every register slot of their
@@ -18,7 +19,7 @@ from tests.gpu_common import DEV, assert_parity
 
 pytestmark = pytest.mark.gpu
 
-NG = 4
+NG = 3
 GAMMA = 5.0 / 3.0
 PER_LEVEL = 12
 

@@ -16,6 +16,8 @@ pytestmark = pytest.mark.gpu
 
 NG = 4
 GAMMA = 5.0 / 3.0
+# ghost widths: 4, and 3 (the PPM stencil's minimum, which the AMR benchmark runs)
+NGS = [3, 4]
 
 
 def hierarchy():
@@ -23,7 +25,7 @@ def hierarchy():
                            p2=(0.5, 1.0), nest=3)
 
 
-def level_states(h, perturb=0.0, seed=0):
+def level_states(h, perturb=0.0, seed=0, ng=NG):
     """conserved ghosted states per level (FP64 numpy) and element offsets"""
     rng = np.random.default_rng(seed)
     U, offs = [], []
@@ -31,7 +33,7 @@ def level_states(h, perturb=0.0, seed=0):
         o = O.make_opts(dim=3, gamma=GAMMA, dx=h.dx(lev))
         Ul, ol, pos = [], [], 0
         for B in L:
-            V = I.amr_fields(h, B, NG)
+            V = I.amr_fields(h, B, ng)
             if perturb:
                 V = V * (1.0 + perturb * rng.standard_normal(V.shape))
             u = O.prim2cons(o, V)
@@ -56,25 +58,26 @@ def unpack(t, Ul):
     return out
 
 
-def make_hier(h, offs, precision):
+def make_hier(h, offs, precision, ng=NG):
     levels = [[(B.lo, B.n, off) for B, off in zip(L, offs[lev])] for lev, L in enumerate(h.levels)]
-    return ctu.Hier(precision, h.base, levels, NG)
+    return ctu.Hier(precision, h.base, levels, ng)
 
 
+@pytest.mark.parametrize("ng", NGS)
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
-def test_ghost_fill_matches_oracle(precision):
+def test_ghost_fill_matches_oracle(precision, ng):
     h = hierarchy()
-    U, offs = level_states(h)
-    U2, _ = level_states(h, perturb=0.05, seed=1)
+    U, offs = level_states(h, ng=ng)
+    U2, _ = level_states(h, perturb=0.05, seed=1, ng=ng)
     dtype = torch.float64 if precision == "fp64" else torch.float32
-    hier = make_hier(h, offs, precision)
+    hier = make_hier(h, offs, precision, ng)
     missing = torch.zeros(1, dtype=torch.int32, device=DEV)
     for lev in range(len(h.levels)):
         N = h.base << lev
         for alpha in ((0.0,) if lev == 0 else (0.0, 0.5)):
             ref = [u.copy() for u in U[lev]]
             coarse = None if lev == 0 else (h.levels[lev - 1], U[lev - 1], U2[lev - 1], alpha)
-            AC.fill_ghosts(h.levels[lev], ref, N, NG, coarse)
+            AC.fill_ghosts(h.levels[lev], ref, N, ng, coarse)
             Ud = pack(U[lev], dtype)
             if lev == 0:
                 hier.fill_ghosts(0, Ud, missing=missing)
@@ -115,18 +118,18 @@ def test_average_down_matches_oracle(precision):
                 assert np.abs(g - r).max() <= 2e-7 * np.abs(r).max()
 
 
-def run_gpu_cycle(h, U, offs, precision, dt0, ch, ncycles=1):
+def run_gpu_cycle(h, U, offs, precision, dt0, ch, ncycles=1, ng=NG):
     dtype = torch.float64 if precision == "fp64" else torch.float32
     nlev = len(h.levels)
-    tables, nslots = amr.build_tables(h.levels, h.base, NG)
+    tables, nslots = amr.build_tables(h.levels, h.base, ng)
     plans = []
     for lev, L in enumerate(h.levels):
         go = ctu.make_opts(dim=3, recon="ppm", riemann="hlld", gamma=GAMMA, dx=h.dx(0), precision=precision)
-        p = ctu.Plan(go, [(B.lo, B.n, lev, off) for B, off in zip(L, offs[lev])], NG, regfaces=tables[lev].regfaces)
+        p = ctu.Plan(go, [(B.lo, B.n, lev, off) for B, off in zip(L, offs[lev])], ng, regfaces=tables[lev].regfaces)
         if tables[lev].reflux:
             p.set_reflux(tables[lev].reflux)
         plans.append(p)
-    hier = make_hier(h, offs, precision)
+    hier = make_hier(h, offs, precision, ng)
     Ua = [pack(U[lev], dtype) for lev in range(nlev)]
     Ub = [torch.zeros_like(t) for t in Ua]
     cur = [0] * nlev
@@ -146,34 +149,36 @@ def oracle_opts(h):
     return lambda lev: O.make_opts(dim=3, recon="ppm", riemann="hlld", gamma=GAMMA, dx=h.dx(lev))
 
 
+@pytest.mark.parametrize("ng", NGS)
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
-def test_subcycled_cycle_matches_oracle(precision, tol):
+def test_subcycled_cycle_matches_oracle(precision, tol, ng):
     h = hierarchy()
-    U, offs = level_states(h)
+    U, offs = level_states(h, ng=ng)
     dt0 = 0.2 / h.base
     ch = 0.4 * h.dx(0)[0] / dt0 * 0.5
-    ref = AC.cycle(h.levels, U, h.base, NG, oracle_opts(h), dt0, ch)
-    got, fails, missing, reg = run_gpu_cycle(h, U, offs, precision, dt0, ch)
+    ref = AC.cycle(h.levels, U, h.base, ng, oracle_opts(h), dt0, ch)
+    got, fails, missing, reg = run_gpu_cycle(h, U, offs, precision, dt0, ch, ng=ng)
     assert fails == [0] * 5 and missing == 0
     for lev in range(len(h.levels)):
         for b in range(len(h.levels[lev])):
-            assert_parity(got[lev][b], ref[lev][b], NG, 3, ch, tol, what=(lev, b))
+            assert_parity(got[lev][b], ref[lev][b], ng, 3, ch, tol, what=(lev, b))
 
 
-def test_gpu_cycle_conserves_and_consumes_registers():
+@pytest.mark.parametrize("ng", NGS)
+def test_gpu_cycle_conserves_and_consumes_registers(ng):
     """FP64, two cycles: the composite totals of every conserved variable but
     psi are unchanged to round-off, and the registers the refluxes read are
     cleared after each use."""
     h = hierarchy()
-    U, offs = level_states(h)
+    U, offs = level_states(h, ng=ng)
     dt0 = 0.2 / h.base
     ch = 0.4 * h.dx(0)[0] / dt0 * 0.5
-    before = AC.totals(h.levels, U, h.base, NG)
-    got, fails, missing, reg = run_gpu_cycle(h, U, offs, "fp64", dt0, ch, ncycles=2)
-    after = AC.totals(h.levels, got, h.base, NG)
+    before = AC.totals(h.levels, U, h.base, ng)
+    got, fails, missing, reg = run_gpu_cycle(h, U, offs, "fp64", dt0, ch, ncycles=2, ng=ng)
+    after = AC.totals(h.levels, got, h.base, ng)
     scale = np.abs(before).max()
     assert np.max(np.abs(after[:8] - before[:8])) <= 2e-13 * scale, after - before
-    tables, _ = amr.build_tables(h.levels, h.base, NG)
+    tables, _ = amr.build_tables(h.levels, h.base, ng)
     r = reg.cpu().numpy().reshape(-1, 9)
     read = sorted({s for T in tables for e in T.reflux for s in [e[4]] + list(e[5])})
     assert np.all(r[read] == 0.0)
