@@ -296,6 +296,14 @@ __global__ __launch_bounds__(NT) void k_shock_mm(const KBox *boxes, const KTile 
     if (mm) fb[c] |= FLAG_MINMOD;
 }
 
+// A vector store reads its data registers after issue, and the compiler
+// waits for the store to complete before an instruction overwrites them.
+// Values stored from short-lived temporaries make the next instructions that
+// reuse those registers wait for the stores; keep(v) marks the registers of
+// stored values as still in use at a later point (the next store of the same
+// values), so that no other value takes them in between.
+template <typename R> __device__ __forceinline__ void keep(const R &v) { asm volatile("" ::"v"(v)); }
+
 // ---------------------------------------------------------------------------
 // Parabolic face fluxes (Sec. 2.1.1, Sec. 3.1, App. A).
 //
@@ -931,6 +939,15 @@ __global__ __launch_bounds__(NT, (tc_waves<PAR, R>())) void k_tcouple(TArgs<R> a
     R Vc[NV], Vp[NV];
     if (inplane) ld_cell(bV, cidx(bx, i, (DIM == 3) ? j : m0 - 1, (DIM == 3) ? m0 - 1 : 0), Vp);
     R Gm_prev[NV], Lx_prev[NV], Ly_prev[NV];
+    // the stored T_d and V^{n+1/2} values of the last finished cell, held
+    // until the next cell's stores (see keep): FP32 parabolic runs, whose
+    // two waves per SIMD leave the registers (6 % faster there; in the
+    // three-wave kernels the extra registers cost a wave)
+    constexpr bool KEEPT = PAR && sizeof(R) == 4;
+    constexpr int NKT = KEEPT ? (DIM + (PAR ? 1 : 0)) * NV : 1;
+    R Tk[NKT];
+#pragma unroll
+    for (int q = 0; q < NKT; q++) Tk[q] = R(0);
     for (int m = m0; m <= m1 + 1; m++) {
         const int cj = (DIM == 3) ? j : m, ck = (DIM == 3) ? m : 0;
         // parabolic runs: U^n and P of the cell this plane finishes, loaded
@@ -1034,20 +1051,33 @@ __global__ __launch_bounds__(NT, (tc_waves<PAR, R>())) void k_tcouple(TArgs<R> a
                     if constexpr (PAR) return x + Pd[q];
                     else return x;
                 };
+                if constexpr (KEEPT) {
+#pragma unroll
+                    for (int q = 0; q < NKT; q++) keep(Tk[q]);
+                }
                 R Lm[NV], S[NV];
 #pragma unroll
                 for (int q = 0; q < NV; q++) {
                     Lm[q] = -(Gm[q] - Gm_prev[q]) * im;
+                    R t0, t1, t2 = R(0);
                     if constexpr (DIM == 3) {
-                        bT0.st(q, c, addp(Ly_prev[q] + Lm[q], q));
-                        bT1.st(q, c, addp(Lx_prev[q] + Lm[q], q));
-                        bT2.st(q, c, addp(Lx_prev[q] + Ly_prev[q], q));
+                        t0 = addp(Ly_prev[q] + Lm[q], q);
+                        t1 = addp(Lx_prev[q] + Lm[q], q);
+                        t2 = addp(Lx_prev[q] + Ly_prev[q], q);
                         S[q] = addp(Lx_prev[q] + Ly_prev[q] + Lm[q], q);
                     } else {
-                        bT0.st(q, c, addp(Lm[q], q));
-                        bT1.st(q, c, addp(Lx_prev[q], q));
+                        t0 = addp(Lm[q], q);
+                        t1 = addp(Lx_prev[q], q);
                         S[q] = addp(Lx_prev[q] + Lm[q], q);
                     }
+                    if constexpr (KEEPT) {
+                        Tk[q] = t0;
+                        Tk[NV + q] = t1;
+                        if constexpr (DIM == 3) Tk[2 * NV + q] = t2;
+                    }
+                    bT0.st(q, c, t0);
+                    bT1.st(q, c, t1);
+                    if constexpr (DIM == 3) bT2.st(q, c, t2);
                 }
                 if constexpr (PAR) {
                     R u[NV], v[NV];
@@ -1055,7 +1085,10 @@ __global__ __launch_bounds__(NT, (tc_waves<PAR, R>())) void k_tcouple(TArgs<R> a
                     for (int q = 0; q < NV; q++) u[q] = Upre[q] + hdt * S[q];
                     c2p<PHYS_MHD>(u, v, gam);
 #pragma unroll
-                    for (int q = 0; q < NV; q++) Blk<R>(a.Vh + bx.woff, bx.cells).st(q, c, v[q]);
+                    for (int q = 0; q < NV; q++) {
+                        if constexpr (KEEPT) Tk[DIM * NV + q] = v[q];
+                        Blk<R>(a.Vh + bx.woff, bx.cells).st(q, c, v[q]);
+                    }
                 }
             }
             // ---- in-plane increments of this plane, kept for one plane ----
