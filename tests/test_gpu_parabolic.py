@@ -1,0 +1,65 @@
+"""GPU parity of the parabolic fluxes (Sec. 2.1.1, Sec. 3.1, App. A) through
+the C ABI, against the FP64 oracle: each term on its own (viscosity,
+resistivity, classical and saturated conduction), all terms in 2D on a box
+that spans several tiles of the parabolic kernels, the generic option variant
+(cell reference states), and the parabolic operator alone (hyperbolic fluxes
+off).  Coefficients are a few times the non-ideal workload's largest, so that
+the parabolic increments are ~1e-3 of the state: a wrong term moves the result
+by far more than the tolerances."""
+import pytest
+
+from paper_1110_0740_amd import inputs as I
+from tests.test_gpu_parity import TOL32, TOL64, _compare_one_step
+
+pytestmark = pytest.mark.gpu
+
+COEF = dict(nu=2e-2, eta=1.5e-2, kappa_par=3e-2, kappa_perp=4e-3)
+BOX3 = (13, 11, 9)  # ragged against the 32 x 8 tiles and 16-plane chunks
+
+
+def _fields3(seed):
+    return I.mhd3d_fields(n=16, ng=4, seed=seed, box=I.Box((0, 0, 0), BOX3), level_n=16, v_rms=0.5)
+
+
+@pytest.mark.parametrize("mask,phi", [(1, 0.0), (2, 0.0), (4, 0.0), (4, 0.3)],
+                         ids=["viscosity", "resistivity", "conduction", "saturated_conduction"])
+def test_single_parabolic_terms_fp64(mask, phi):
+    print(f"parabolic term mask {mask} phi {phi}: {BOX3}", flush=True)
+    V, meta = _fields3(5100 + mask)
+    e, _, _ = _compare_one_step(V, meta, "fp64", TOL64, BOX3, recon="ppm", riemann="hlld", parabolic_mask=mask,
+                                tc_phi=phi, **COEF)
+    print(f"L1 {e.max():.2e}")
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", TOL64), ("fp32", TOL32)])
+def test_parabolic_2d_across_tiles(precision, tol):
+    """2D, 300 x 20: the 256-wide rows of k_pflux and the 255-wide rows of
+    k_pdiv's overlapping tiles each need two tiles per row."""
+    n2 = (300, 20)
+    print(f"parabolic 2D {precision}: {n2}", flush=True)
+    V, meta = I.mhd2d_fields(n=384, ng=4, seed=5200, box=I.Box((0, 0, 0), (n2[0], n2[1], 1)))
+    e, _, _ = _compare_one_step(V, meta, precision, tol, n2, recon="ppm", riemann="hlld", parabolic_mask=7,
+                                tc_phi=0.3, **COEF)
+    print(f"L1 {e.max():.2e}")
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", TOL64), ("fp32", TOL32)])
+def test_parabolic_generic_variant(precision, tol):
+    """Cell reference states select the generic sweep and t^n kernels, which
+    read the parabolic options at run time."""
+    print(f"parabolic generic variant {precision}: {BOX3}", flush=True)
+    V, meta = _fields3(5300)
+    e, _, _ = _compare_one_step(V, meta, precision, tol, BOX3, recon="ppm", riemann="hlld", wref="cell",
+                                parabolic_mask=7, tc_phi=0.3, **COEF)
+    print(f"L1 {e.max():.2e}")
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", TOL64), ("fp32", TOL32)])
+def test_parabolic_operator_alone(precision, tol):
+    """Hyperbolic fluxes off: the step is the unsplit parabolic update with
+    the half-step state of Eq. transv."""
+    print(f"parabolic operator alone {precision}: {BOX3}", flush=True)
+    V, meta = _fields3(5400)
+    e, _, _ = _compare_one_step(V, meta, precision, tol, BOX3, recon="ppm", riemann="hlld", hyperbolic_off=True,
+                                parabolic_mask=7, tc_phi=0.3, **COEF)
+    print(f"L1 {e.max():.2e}")
