@@ -837,7 +837,15 @@ __device__ __forceinline__ void tface_s(const R *VL_in, const R *VR_in, const KB
 #ifndef CTU_TC_WAVES_PAR_F32
 #define CTU_TC_WAVES_PAR_F32 1
 #endif
-template <int PAR, typename R> constexpr int tc_waves() { return (PAR && sizeof(R) == 4) ? CTU_TC_WAVES_PAR_F32 : 1; }
+// the FP64 parabolic kernel at two waves (12 bytes of spills, without the
+// U^n / P prefetch) runs 15 % faster than at one wave with it
+#ifndef CTU_TC_WAVES_PAR_F64
+#define CTU_TC_WAVES_PAR_F64 2
+#endif
+template <int PAR, typename R> constexpr int tc_waves()
+{
+    return PAR ? (sizeof(R) == 4 ? CTU_TC_WAVES_PAR_F32 : CTU_TC_WAVES_PAR_F64) : 1;
+}
 
 template <int DIM, int PHYS, int RS, int PAR, int VAR, typename R>
 __global__ __launch_bounds__(NT, (tc_waves<PAR, R>())) void k_tcouple(TArgs<R> a)
@@ -944,16 +952,20 @@ __global__ __launch_bounds__(NT, (tc_waves<PAR, R>())) void k_tcouple(TArgs<R> a
     // two waves per SIMD leave the registers (6 % faster there; in the
     // three-wave kernels the extra registers cost a wave)
     constexpr bool KEEPT = PAR && sizeof(R) == 4;
+    // FP32 parabolic runs load U^n and P of the cell to finish ahead of the
+    // plane's face solves; FP64 loads them where they are used (the held
+    // registers would cost its second wave per SIMD)
+    constexpr bool PRE = PAR && sizeof(R) == 4;
     constexpr int NKT = KEEPT ? (DIM + (PAR ? 1 : 0)) * NV : 1;
     R Tk[NKT];
 #pragma unroll
     for (int q = 0; q < NKT; q++) Tk[q] = R(0);
     for (int m = m0; m <= m1 + 1; m++) {
         const int cj = (DIM == 3) ? j : m, ck = (DIM == 3) ? m : 0;
-        // parabolic runs: U^n and P of the cell this plane finishes, loaded
-        // ahead of the face solves that hide their latency
+        // U^n and P of the cell this plane finishes, loaded ahead of the face
+        // solves that hide their latency (PRE)
         R Upre[NV], Ppre[7];
-        if constexpr (PAR) {
+        if constexpr (PRE) {
             if (inplane && m > m0) {
                 const int pc = cidx(bx, i, (DIM == 3) ? j : m - 1, (DIM == 3) ? m - 1 : 0);
 #pragma unroll
@@ -1045,7 +1057,7 @@ __global__ __launch_bounds__(NT, (tc_waves<PAR, R>())) void k_tcouple(TArgs<R> a
                     Pd[RHO] = R(0);
                     Pd[PSI] = R(0);
 #pragma unroll
-                    for (int q = 0; q < 7; q++) Pd[MX1 + q] = Ppre[q];
+                    for (int q = 0; q < 7; q++) Pd[MX1 + q] = PRE ? Ppre[q] : Pf[q * cs + c];
                 }
                 auto addp = [&](R x, int q) -> R {
                     if constexpr (PAR) return x + Pd[q];
@@ -1082,7 +1094,7 @@ __global__ __launch_bounds__(NT, (tc_waves<PAR, R>())) void k_tcouple(TArgs<R> a
                 if constexpr (PAR) {
                     R u[NV], v[NV];
 #pragma unroll
-                    for (int q = 0; q < NV; q++) u[q] = Upre[q] + hdt * S[q];
+                    for (int q = 0; q < NV; q++) u[q] = (PRE ? Upre[q] : Blk<R>(a.U + bx.uoff, bx.cells).ld(q, c)) + hdt * S[q];
                     c2p<PHYS_MHD>(u, v, gam);
 #pragma unroll
                     for (int q = 0; q < NV; q++) {
