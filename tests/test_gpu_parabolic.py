@@ -107,3 +107,14 @@ def test_parabolic_several_boxes_one_plan(precision, tol):
         pos += U.size
         e, c = assert_parity(got, ref, ng, 3, ch, tol)
         print(f"L1 {e.max():.2e} cell {c.max():.2e}")
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", TOL64), ("fp32", TOL32)])
+def test_parabolic_with_shock_flags(precision, tol):
+    """With the App. B zone flags the t^n kernel and the sweeps run their
+    shock-flag variants, which read the parabolic options at run time."""
+    print(f"parabolic with shock flags {precision}: {BOX3}", flush=True)
+    V, meta = _fields3(5600)
+    e, _, _ = _compare_one_step(V, meta, precision, tol, BOX3, recon="ppm", riemann="hlld", shock_eps=0.05,
+                                parabolic_mask=7, tc_phi=0.3, **COEF)
+    print(f"L1 {e.max():.2e}")
