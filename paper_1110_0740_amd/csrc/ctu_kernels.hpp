@@ -322,7 +322,7 @@ template <typename R> __device__ __forceinline__ void keep(const R &v) { asm vol
 //    component and magnitude in eight slots per face and the sweep
 //    saturates (parab_face).
 // A block owns TX x TY in-plane cells (3D: x, y; 2D: x) and marches along
-// the last axis over a chunk of LM planes, with three planes of the eight
+// the last axis over a chunk of planes, with three planes of the eight
 // staged fields (rho, v, B, T = p / rho) and a one-cell in-plane halo in LDS.
 // ---------------------------------------------------------------------------
 
@@ -338,7 +338,9 @@ template <int DIM> struct PTile {
     static constexpr int TX = (DIM == 3) ? 32 : NT;
     static constexpr int TY = (DIM == 3) ? 8 : 1;
     static constexpr int HX = TX + 2, HY = (DIM == 3) ? TY + 2 : 1, HP = HX * HY;
-    static constexpr int LM = 16;  // planes per block along the marching axis
+    // planes per block along the marching axis (measured at 256^3: k_pflux
+    // 0.76 / 0.82 / 0.88 ms with 4 / 8 / 16, k_pdiv 0.77 / 0.73 / 0.73)
+    static constexpr int LM_FLUX = 4, LM_DIV = 8;
 };
 
 template <typename R> struct PArgs {
@@ -508,7 +510,7 @@ __global__ __launch_bounds__(NT) void k_pflux(PArgs<R> a)
     const bool fx = x <= hi[0] && iny;
     const bool fy = DIM == 3 && inx && y <= hi[1];
     const bool fm = inx && iny;
-    const int m0 = lo[AM] + 1 + tl.c, m1 = min(m0 + PT::LM - 1, hi[AM]);
+    const int m0 = lo[AM] + 1 + tl.c, m1 = min(m0 + PT::LM_FLUX - 1, hi[AM]);
 
     int r0 = 0, r1 = 1, r2 = 2;  // ring slots of planes m-1, m, m+1
     pf_stage<DIM>(&S[r0][0], Vb, bx, lo, hi, x0, y0, m0 - 1);
@@ -592,7 +594,7 @@ __global__ __launch_bounds__(NT) void k_pdiv(PArgs<R> a)
     const bool fy = DIM == 3 && x <= hi[0] - 1 && y <= hi[1];
     const bool fm = x <= hi[0] - 1 && iny;
     const bool own = fm && tx < PT::TX - 1 && (DIM == 2 || ty < PT::TY - 1);
-    const int m0 = lo[AM] + 1 + tl.c, m1 = min(m0 + PT::LM - 1, hi[AM] - 1);
+    const int m0 = lo[AM] + 1 + tl.c, m1 = min(m0 + PT::LM_DIV - 1, hi[AM] - 1);
     const int sM = (DIM == 3) ? bx.N[0] * bx.N[1] : bx.N[0];
     const R ix = R(1.0 / bx.dx[0]), iy = R(1.0 / bx.dx[1]), iz = R(1.0 / bx.dx[2]);
 

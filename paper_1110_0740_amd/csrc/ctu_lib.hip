@@ -369,7 +369,8 @@ void add_mt_tiles(TileSet &ts, int b, const KBox &bx, int D, int dim)
 void add_pf_tiles(TileSet &ts, int b, const KBox &bx, int dim, bool div)
 {
     const int TX = (dim == 3) ? PTile<3>::TX : PTile<2>::TX, TY = (dim == 3) ? PTile<3>::TY : PTile<2>::TY;
-    const int LM = (dim == 3) ? PTile<3>::LM : PTile<2>::LM;
+    const int LM = div ? ((dim == 3) ? PTile<3>::LM_DIV : PTile<2>::LM_DIV)
+                       : ((dim == 3) ? PTile<3>::LM_FLUX : PTile<2>::LM_FLUX);
     const int k = div ? 2 : 1, sx = div ? TX - 1 : TX, sy = (div && dim == 3) ? TY - 1 : TY;
     const int ex = bx.n[0] + k, ey = (dim == 3) ? bx.n[1] + k : 1, em = bx.n[dim - 1] + k;
     for (int m0 = 0; m0 < em; m0 += LM)
