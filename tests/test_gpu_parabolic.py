@@ -118,3 +118,15 @@ def test_parabolic_with_shock_flags(precision, tol):
     e, _, _ = _compare_one_step(V, meta, precision, tol, BOX3, recon="ppm", riemann="hlld", shock_eps=0.05,
                                 parabolic_mask=7, tc_phi=0.3, **COEF)
     print(f"L1 {e.max():.2e}")
+
+
+@pytest.mark.parametrize("ext", [(3, 2, 5), (1, 4, 2), (5, 1, 1)])
+@pytest.mark.parametrize("precision,tol", [("fp64", TOL64), ("fp32", TOL32)])
+def test_parabolic_tiny_boxes(precision, tol, ext):
+    """Boxes of one to five cells per axis: the parabolic kernels' regions are
+    smaller than one tile and one chunk in every direction."""
+    print(f"parabolic tiny box {precision}: {ext}", flush=True)
+    V, meta = I.mhd3d_fields(n=16, ng=4, seed=5700 + sum(ext), box=I.Box((0, 0, 0), ext), level_n=16, v_rms=0.5)
+    e, _, _ = _compare_one_step(V, meta, precision, tol, ext, recon="ppm", riemann="hlld", parabolic_mask=7,
+                                tc_phi=0.3, **COEF)
+    print(f"L1 {e.max():.2e}")
