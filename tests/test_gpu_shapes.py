@@ -210,8 +210,9 @@ def test_failure_counts_do_not_depend_on_segments(precision):
 def test_segments_with_parabolic_terms_and_cooling(precision):
     """With viscosity, resistivity, conduction and cooling the sweeps also
     carry the per-cell signal rate between directions and reduce the cooling
-    change: 1, 2, 3 and 8 y / z segments give bitwise the same state, rate
-    and dp/p on a ragged box."""
+    change: 1, 2, 3 and 8 y / z segments, both t^n layouts and t^n chunks of
+    1, 5 and 16 planes give bitwise the same state, rate and dp/p on a ragged
+    box."""
     from tests.gpu_common import GpuStepper, gpu_opts, single_box_plan
     n, ng = (17, 14, 19), 4
     V, meta = I.mhd3d_fields(n=n[0], ng=ng, seed=5000, box=I.Box((0, 0, 0), n), level_n=32)
@@ -229,8 +230,13 @@ def test_segments_with_parabolic_terms_and_cooling(precision):
     plan = single_box_plan(go, n, ng)
     st = GpuStepper(plan, U.shape, precision)
     ref = None
-    for S in (0, 2, 3, 8):
-        plan.set_shape(yz_segments=S)
+    # y / z segments, then the t^n layouts and chunk lengths (the t^n kernel
+    # adds the Pi^n divergence per cell, whatever the layout)
+    shapes = [dict(yz_segments=S) for S in (0, 2, 3, 8)]
+    shapes += [dict(tc_layout="flat"), dict(tc_layout="tiles", tc_chunk=1), dict(tc_layout="tiles", tc_chunk=16),
+               dict(tc_layout="flat", tc_chunk=5, x_pencils=3, xcd_order=0)]
+    for S in shapes:
+        plan.set_shape(**S)
         out, rate, dpp, fails = st.step(U, 0.5 * dt, 1.0, L0=L0)
         assert fails == [0] * 5 and dpp > 0.0
         if ref is None:
