@@ -973,21 +973,38 @@ __device__ __forceinline__ void riemann(R *VL, R *VR, R *F, R &smax, R gam, R ch
 // Limiters and reconstruction (Sec. 3.2), on undivided differences.
 // ---------------------------------------------------------------------------
 
-// minmod: the argument of smaller magnitude when both share a sign, else 0
-// (selects rather than sign arithmetic, same value)
+// minmod: the argument of smaller magnitude when both share a sign, else 0.
+// In FP32 it is the median of (a, b, 0), one v_med3_f32; in FP64 selects
+// (same value up to the sign of a zero result).
 template <typename R> __device__ __forceinline__ R minmod(R a, R b)
 {
-    R m = (fabs(a) < fabs(b)) ? a : b;
-    return (a * b > R(0)) ? m : R(0);
+    if constexpr (sizeof(R) == 4) {
+        return __builtin_amdgcn_fmed3f(a, b, 0.0f);
+    } else {
+        R m = (fabs(a) < fabs(b)) ? a : b;
+        return (a * b > R(0)) ? m : R(0);
+    }
 }
 
 // monotonised central limiter minmod((dp + dm)/2, 2 minmod(dp, dm)): for
-// differences of one sign, that sign times min(|dp + dm|/2, 2|dp|, 2|dm|)
+// differences of one sign, that sign times min(|dp + dm|/2, 2|dp|, 2|dm|).
+// FP32 nests the medians (minmod of three = minmod(x, minmod(y, z)), and
+// doubling is exact): two v_med3_f32 in place of the sign test and selects.
 template <typename R> __device__ __forceinline__ R lim_mc(R dp, R dm)
 {
     R c = R(0.5) * (dp + dm);
-    R m = fmin(fmin(fabs(c), R(2) * fabs(dp)), R(2) * fabs(dm));
-    return (dp * dm > R(0)) ? copysign(m, c) : R(0);
+    if constexpr (sizeof(R) == 4) {
+        return __builtin_amdgcn_fmed3f(c, 2.0f * __builtin_amdgcn_fmed3f(dp, dm, 0.0f), 0.0f);
+    } else {
+        R m = fmin(fmin(fabs(c), R(2) * fabs(dp)), R(2) * fabs(dm));
+        return (dp * dm > R(0)) ? copysign(m, c) : R(0);
+    }
+}
+
+// lim_mc(dp, dm) / 2 in FP32: the same medians on halved arguments
+__device__ __forceinline__ float lim_mc_half(float dp, float dm)
+{
+    return __builtin_amdgcn_fmed3f(0.25f * (dp + dm), __builtin_amdgcn_fmed3f(dp, dm, 0.0f), 0.0f);
 }
 
 template <typename R> __device__ __forceinline__ R limiter(int lim, R dp, R dm)
@@ -1012,12 +1029,29 @@ __device__ __forceinline__ void recon_offsets(const R *d, int lim, R dxr, R &dm,
         dp = R(0.5) * s;
         dm = -dp;
     } else if constexpr (RK == RK_PPM) {
-        R s0 = lim_mc(d[2], d[1]);
-        R sp = lim_mc(d[3], d[2]);
-        R sm = lim_mc(d[1], d[0]);
-        R P = R(0.5) * d[2] - (sp - s0) * R(1.0 / 6.0);   // Eq. ppm1, w_+ - w_0
-        R M = -R(0.5) * d[1] + (sm - s0) * R(1.0 / 6.0);  // w_- - w_0
-        if (P * M > R(0)) {                               // Eq. ppm_parabolic_lim
+        R P, M;
+        if constexpr (sizeof(R) == 4) {
+            // half slopes lim_mc / 2 = med3((dp + dm)/4, minmod(dp, dm), 0) and
+            // 1/3 in place of 1/6: power-of-two scalings, so the same bits
+            R s0 = lim_mc_half(d[2], d[1]);
+            R sp = lim_mc_half(d[3], d[2]);
+            R sm = lim_mc_half(d[1], d[0]);
+            P = 0.5f * d[2] - (sp - s0) * (1.0f / 3.0f);
+            M = -0.5f * d[1] + (sm - s0) * (1.0f / 3.0f);
+        } else {
+            R s0 = lim_mc(d[2], d[1]);
+            R sp = lim_mc(d[3], d[2]);
+            R sm = lim_mc(d[1], d[0]);
+            P = R(0.5) * d[2] - (sp - s0) * R(1.0 / 6.0);   // Eq. ppm1, w_+ - w_0
+            M = -R(0.5) * d[1] + (sm - s0) * R(1.0 / 6.0);  // w_- - w_0
+        }
+        if constexpr (sizeof(R) == 4) {
+            // Eq. ppm_parabolic_lim as medians: where P and M share a sign, -2M
+            // and -2P have the other one and the median is 0; otherwise it is
+            // the smaller in magnitude of P and -2M (of M and -2P)
+            dp = __builtin_amdgcn_fmed3f(P, -2.0f * M, 0.0f);
+            dm = __builtin_amdgcn_fmed3f(M, -2.0f * P, 0.0f);
+        } else if (P * M > R(0)) {                        // Eq. ppm_parabolic_lim
             dp = R(0);
             dm = R(0);
         } else {

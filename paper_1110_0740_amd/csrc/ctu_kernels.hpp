@@ -1462,15 +1462,18 @@ __global__ __launch_bounds__(NT, (sweep_waves<VAR, R>())) void k_sweep(
                 for (int q = 0; q < NV; q++) U0[q] = bU.ld(q, c);
                 fl |= predict_mh<D, PHYS>(Vs, U0, o, gam, dtdx, ch, Vm, Vp, mm ? LIM_MINMOD : o.limiter);
             }
-            R Up[NV];
+            // ---- corner coupling (Eq. transv) ----
+            // the T_d loads issue together, ahead of the conversions
+            R Up[NV], tr[NV];
+#pragma unroll
+            for (int q = 0; q < NV; q++) tr[q] = bT.ld(q, c);
             p2c<PHYS>(Vm, Um, gam);
             p2c<PHYS>(Vp, Up, gam);
-            // ---- corner coupling (Eq. transv) ----
 #pragma unroll
             for (int q = 0; q < NV; q++) {
-                R tr = hdt * bT.ld(q, c);
-                Um[q] += tr;
-                Up[q] += tr;
+                tr[q] *= hdt;
+                Um[q] += tr[q];
+                Up[q] += tr[q];
             }
 #pragma unroll
             for (int q = 0; q < NV; q++) sP[q][tid] = Up[q];

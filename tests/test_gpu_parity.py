@@ -143,6 +143,16 @@ def test_scheme_variants_fp64(recon, riemann, wref):
     _compare_one_step(V, meta, "fp64", TOL64, (40, 40), recon=recon, riemann=riemann, wref=wref)
 
 
+@pytest.mark.parametrize("recon,riemann,wref", [
+    ("lin_minmod", "hll", "face"), ("lin_mc", "hlld", "cw84"), ("ppm", "hlld", "cell"), ("ppm", "hll", "face")])
+def test_scheme_variants_fp32(recon, riemann, wref):
+    """The FP32 limiters are medians (minmod, MC and the PPM constraints of
+    Sec. 3.2): the values of the FP64 selects, so parity at the FP32
+    tolerance on each limiter and reference state."""
+    V, meta = I.mhd2d_fields(n=40, ng=4, seed=1003)
+    _compare_one_step(V, meta, "fp32", TOL32, (40, 40), recon=recon, riemann=riemann, wref=wref)
+
+
 @pytest.mark.parametrize("riemann", ["hlld", "hll"])
 def test_mhd_muscl_hancock_fp64(riemann):
     V, meta = I.mhd3d_fields(n=16, ng=4, seed=2002)
