@@ -974,8 +974,11 @@ __device__ __forceinline__ void riemann(R *VL, R *VR, R *F, R &smax, R gam, R ch
 // ---------------------------------------------------------------------------
 
 // minmod: the argument of smaller magnitude when both share a sign, else 0.
-// In FP32 it is the median of (a, b, 0), one v_med3_f32; in FP64 selects
-// (same value up to the sign of a zero result).
+// In FP32 it is the median of (a, b, 0), one v_med3_f32; in FP64 selects.
+// The two agree up to the sign of a zero result, except where the sign
+// product a * b of the select form would underflow (|a b| below the FP32
+// normal range): there the select form gives 0 and the median the exact
+// smaller argument.
 template <typename R> __device__ __forceinline__ R minmod(R a, R b)
 {
     if constexpr (sizeof(R) == 4) {
