@@ -1039,8 +1039,8 @@ __device__ __forceinline__ void recon_offsets(const R *d, int lim, R dxr, R &dm,
             R s0 = lim_mc_half(d[2], d[1]);
             R sp = lim_mc_half(d[3], d[2]);
             R sm = lim_mc_half(d[1], d[0]);
-            P = 0.5f * d[2] - (sp - s0) * (1.0f / 3.0f);
-            M = -0.5f * d[1] + (sm - s0) * (1.0f / 3.0f);
+            P = 0.5f * d[2] - (sp - s0) * (1.0f / 3.0f);   // Eq. ppm1, w_+ - w_0
+            M = -0.5f * d[1] + (sm - s0) * (1.0f / 3.0f);  // w_- - w_0
         } else {
             R s0 = lim_mc(d[2], d[1]);
             R sp = lim_mc(d[3], d[2]);
