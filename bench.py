@@ -333,7 +333,7 @@ def leg_c2(args, dev, s, samples):
     log("C2: FP32 batched (autotune, graph)")
     p32 = ctu.Plan(ctu.make_opts(dim=3, gamma=gamma, dx=dx, precision="fp32", **okw), box, NG)
     U32 = U64.to(torch.float32)
-    Uo32 = torch.empty_like(U32)
+    Uo32 = torch.zeros_like(U32)
     if args.shape:
         f = args.shape.split(",")
         p32.set_shape(tc_layout=f[0], tc_chunk=int(f[1]), x_pencils=int(f[2]), xcd_order=int(f[3]),
@@ -346,7 +346,7 @@ def leg_c2(args, dev, s, samples):
     r32["flat_boxes"] = flat
     # FP64 plain: default shape, eager launches
     log("C2: FP64 plain (eager)")
-    Uo64 = torch.empty_like(U64)
+    Uo64 = torch.zeros_like(U64)
     ms64, per64 = run_plan(p64, U64, Uo64, params, b, K, W, s, graph=False)
     r64 = result(ms64, zones, ghost_bytes(n, 8), per64)
     samples.add("c2_fp32", okw, dx, dt, ch, ins, [subbox(Uo32, N, lo, 16, 3) for lo in org])
@@ -379,7 +379,7 @@ def c2_variants(args, dev, s, U64, ins, params, b, dx, gamma, samples):
         log(f"C2 variant {name}")
         p = ctu.Plan(ctu.make_opts(dim=3, recon="ppm", gamma=gamma, dx=dx, precision="fp32", **kw), box, NG)
         U32 = U64.to(torch.float32)
-        Uo = torch.empty_like(U32)
+        Uo = torch.zeros_like(U32)
         if not args.no_autotune:
             p.autotune(U32, Uo, params, reps=3, stream=s)
         ms, _ = run_plan(p, U32, Uo, params, b, K, W, s, stages=False)
@@ -488,7 +488,7 @@ def leg_c4(args, dev, s, samples):
         params = torch.tensor([dt, ch], dtype=torch.float64, device=dev)
         p = ctu.Plan(ctu.make_opts(precision="fp32", **kw), box, NG)
         U32 = U64.to(torch.float32)
-        Uo = torch.empty_like(U32)
+        Uo = torch.zeros_like(U32)
         if not args.no_autotune:
             p.autotune(U32, Uo, params, reps=3, stream=s)
         ms, per = run_plan(p, U32, Uo, params, b, K, W, s, stages=main)
@@ -499,7 +499,7 @@ def leg_c4(args, dev, s, samples):
             r["roofline"] = kernel_roofline("C4", per, zones, "f32")
             out["fp32_batched"] = r
             log("C4: FP64 plain (eager)")
-            Uo64 = torch.empty_like(U64)
+            Uo64 = torch.zeros_like(U64)
             ms64, per64 = run_plan(p64, U64, Uo64, params, b, K, W, s, graph=False)
             out["fp64_plain"] = result(ms64, zones, ghost_bytes(n, 8), per64)
             samples.add(f"c4_{name}_fp64", okw, meta["dx"], dt, ch, ins, [subbox(Uo64, N, lo, 12, 3) for lo in org],
@@ -549,7 +549,7 @@ def leg_c5(args, dev, s, samples):
     log("C5: FP32 batched (autotune, graph)")
     p32 = ctu.Plan(ctu.make_opts(dim=3, gamma=G, dx=dx, precision="fp32", **okw), box, NG)
     U32, L32 = U64.to(torch.float32), L0.to(torch.float32)
-    Uo32 = torch.empty_like(U32)
+    Uo32 = torch.zeros_like(U32)
     if not args.no_autotune:
         p32.autotune(U32, Uo32, params, L0=L32, reps=5, stream=s)
     ms, per = run_plan(p32, U32, Uo32, params, b, K, W, s, L0=L32)
@@ -559,12 +559,12 @@ def leg_c5(args, dev, s, samples):
     r32["max_dp_over_p"] = b.dpp.item()
     log("C5: FP32 batched, white-noise cooling times")
     L32w = L0w.to(torch.float32)
-    Uo32w = torch.empty_like(U32)
+    Uo32w = torch.zeros_like(U32)
     msw, perw = run_plan(p32, U32, Uo32w, params, b, K, W, s, L0=L32w)
     r32w = result(msw, zones, abz32, perw, p32.get_shape()[0])
     r32w["max_dp_over_p"] = b.dpp.item()
     log("C5: FP64 plain (eager)")
-    Uo64 = torch.empty_like(U64)
+    Uo64 = torch.zeros_like(U64)
     ms64, per64 = run_plan(p64, U64, Uo64, params, b, K, W, s, L0=L0, graph=False)
     r64 = result(ms64, zones, ghost_bytes(n, 8) + 8 * ((n + 2 * NG) / n) ** 3, per64)
     L0s64 = [subbox_cells(L0, N, lo, 16) for lo in org]
@@ -793,7 +793,7 @@ def c3_per_patch(h, U64, params, offs, okw, zones, ghost_l, npatch, b, s, K, W):
         go = ctu.make_opts(dim=3, gamma=5.0 / 3.0, dx=h.dx(0), precision="fp64", **okw)
         for B, ob in zip(L, offs[lev]):
             pplans.append((lev, ctu.Plan(go, [(B.lo, B.n, lev, ob)], NG_AMR)))
-    Uo64 = [torch.empty_like(u) for u in U64]
+    Uo64 = [torch.zeros_like(u) for u in U64]
     torch.cuda.synchronize()
 
     def amr_step64():
