@@ -1446,6 +1446,16 @@ __global__ __launch_bounds__(NT, (sweep_waves<VAR, R>())) void k_sweep(
             for (int l = l0; l < l1; l++)
 #pragma unroll
                 for (int q = 0; q < NV; q++) Vs[l][q] = bV.ld(q, c + (l - 2) * sD);
+            // T_d of the item's cell (Eq. transv): in the FP32 fixed-option PPM
+            // and MUSCL-Hancock sweeps loaded with the stencil, so that the
+            // predictor covers its latency (their waves per SIMD stay as they
+            // are); elsewhere just before the corner coupling
+            constexpr bool TPRE = sizeof(R) == 4 && VAR == VAR_FAST && (RK == RK_PPM || PRED == PRED_MH);
+            R tr[NV];
+            if constexpr (TPRE) {
+#pragma unroll
+                for (int q = 0; q < NV; q++) tr[q] = bT.ld(q, c);
+            }
             R Vm[NV], Vp[NV];
             Wc = w_guess<PHYS>(Vs[2], gam);
             // App. B: MinMod linear reconstruction near a flagged zone
@@ -1464,9 +1474,11 @@ __global__ __launch_bounds__(NT, (sweep_waves<VAR, R>())) void k_sweep(
             }
             // ---- corner coupling (Eq. transv) ----
             // the T_d loads issue together, ahead of the conversions
-            R Up[NV], tr[NV];
+            R Up[NV];
+            if constexpr (!TPRE) {
 #pragma unroll
-            for (int q = 0; q < NV; q++) tr[q] = bT.ld(q, c);
+                for (int q = 0; q < NV; q++) tr[q] = bT.ld(q, c);
+            }
             p2c<PHYS>(Vm, Um, gam);
             p2c<PHYS>(Vp, Up, gam);
 #pragma unroll
