@@ -60,10 +60,10 @@ ALG_FLOP = {"C1": {"prim": 20.0, "tcouple": 943.0}, "C2": {"prim": 20.0, "tcoupl
             "C5": {"prim": 20.0, "tcouple": 1520.0, "pdiv": 536.0, "pflux": 594.0}}
 # HBM bytes per launch of the FP32 256^3 t^n kernel, FETCH_SIZE x 2.0 +
 # WRITE_SIZE x 1.0 (KiB x 1024): a plain 1 GiB device copy (bench.py
-# --copy-calibration) reads back as 524,309 KiB of FETCH_SIZE and 1,048,576
+# --copy-calibration) reads back as 524,308 KiB of FETCH_SIZE and 1,048,576
 # KiB of WRITE_SIZE, hence the factors (profiles/c2_mhd3d_256_ppm_hlld.md).
 # None once the kernel has changed since the counters were taken.
-TCOUPLE_TRAFFIC_BYTES = (530383 * 2 + 2086532) * 1024
+TCOUPLE_TRAFFIC_BYTES = (530399 * 2 + 2085694) * 1024
 # the launch shape those counters were taken with (bench.py --shape tiles,4,16,1,2)
 PROFILE_SHAPE = {"tc_layout": "tiles", "tc_chunk": 4, "xcd_order": 1}
 # Step parameters of the workloads (dt and c_h; C1's ten chained steps; C5's
